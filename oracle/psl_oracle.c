@@ -1,0 +1,865 @@
+/*
+ * psl_oracle.c -- sequential CPU reference presolver (TEST INFRASTRUCTURE).
+ *
+ * Not part of the product: only tests, the smoke check and the benchmark's
+ * CPU-baseline leg load this. It is deliberately plain and slow. Build with
+ * -O2 -ffp-contract=off (no fused multiply-add, no fast-math).
+ *
+ * What it computes follows the paper (Cederberg & Boyd, "GPU-Accelerated
+ * Presolving for Linear Programming"):
+ *   - LP form: eq. (1), section 2.1.
+ *   - Reductions with a postsolve record each: section 2.1, "Reductions" and
+ *     "Postsolver"; fixing stores only index and value.
+ *   - Bound tightening from min/max activities, repeated in rounds until a
+ *     round tightens nothing or a round cap is hit: section 3.1, "Bound
+ *     tightening" (worked example x1 + 2 x2 <= 4, x >= 0 => x1 <= 4, x2 <= 2).
+ *   - Inactive flags instead of physical removal; activities recomputed on
+ *     demand; row and column sizes maintained: section 3.2, "Internal data
+ *     structures".
+ *   - Parallel rows by a two-level hash on pattern and coefficients, verified
+ *     against a leader (first equality of the group, else first inequality):
+ *     section 3.2, "Parallel rows".
+ *   - Emission of a reduced LP of the same form and primal recovery:
+ *     section 3.3.
+ *
+ * Readings where the paper is silent (they define the round semantics that
+ * the GPU library must reproduce bit for bit):
+ *   R-Jacobi  every test in a round reads the bounds as they were at the start
+ *             of the round; tightenings are combined by max/min (the paper's
+ *             in-place atomic updates are order dependent).
+ *   R-Sum     every sum of a row (activities, fixed-column constants) and the
+ *             objective offset is the canonical pairwise tree: leaves are the
+ *             row's CSR positions 0..len-1 padded with +0 to the next power of
+ *             two, each node is fl(left + right); terms equal to zero are +0.
+ *   R-Bound   implied bounds from residual activities with infinite-bound
+ *             counts (formulas in propagate_row below).
+ *   R-Tol     tol(s) = feas_tol * max(1, |s|); candidate bound qualifies if it
+ *             improves by more than min_improve * max(1, |bound|) (any strict
+ *             improvement for a row with one active column).
+ *   R-Hash    parallel-row key over the row's stored entries (pattern and
+ *             coefficients normalised by the first stored coefficient), mixed
+ *             with the SplitMix64 finaliser (Steele, Lea & Flood 2014).
+ *   R-Order   records ordered by (round, phase, index, side).
+ */
+#include "psl_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { RES_REDUCED = 0, RES_UNCHANGED = 1, RES_INFEASIBLE = 2, RES_UNBOUNDED = 3 };
+
+/* record types; fields (unused ints are -1, unused doubles 0):
+ *  FIX_COL        j; v = {value, c_j}
+ *  EMPTY_COL      j; v = {value, c_j}
+ *  EMPTY_ROW      i; v = {activity, lhs, rhs}
+ *  REDUNDANT_ROW  i; v = {min activity or -inf, max activity or +inf, lhs, rhs}
+ *  SINGLETON_ROW  i, j = the active column; v = {a_ij, lhs, rhs}
+ *  BOUND_CHANGE   j, side (0 lower, 1 upper), k = source row;
+ *                 v = {old bound, new bound, a_kj}
+ *  PARALLEL_ROW   i = removed row, k = leader; v = {lambda, lhs_i, rhs_i}
+ *  LEADER_SIDES   i = leader, j = row giving lhs, k = row giving rhs;
+ *                 v = {old lhs, old rhs, new lhs, new rhs}
+ */
+enum {
+    REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
+    REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8
+};
+
+/* classes of the reduced problem's rows and columns (listed, not applied) */
+enum { RCLS_OTHER = 0, RCLS_SINGLETON = 1, RCLS_DOUBLETON_EQ = 2, RCLS_DOUBLETON_INEQ = 3 };
+enum { CCLS_OTHER = 0, CCLS_SINGLETON_FREE = 1, CCLS_SINGLETON = 2, CCLS_DOUBLETON = 3 };
+
+struct or_handle {
+    int32_t m, n;
+    int64_t nnz;
+    int32_t *rp, *ci;
+    double *va;
+    double *lhs, *rhs, *lb, *ub, *c, off;
+    or_settings s;
+
+    uint8_t *row_on, *col_on;
+    int32_t *col_len;
+
+    or_record *rec;
+    int64_t nrec, caprec;
+
+    int32_t result, round;
+    char err[256];
+
+    /* reduced problem */
+    int32_t rm, rn;
+    int64_t rnnz;
+    double roff;
+    int32_t *r_rp, *r_ci, *r_cp, *r_ri, *r_rowmap, *r_colmap;
+    double *r_va, *r_cva, *r_lhs, *r_rhs, *r_lb, *r_ub, *r_c;
+    uint8_t *r_rcls, *r_ccls;
+};
+
+/* ------------------------------------------------------------------------- */
+/* small helpers                                                              */
+/* ------------------------------------------------------------------------- */
+
+static double pos0(double x) { return x == 0.0 ? 0.0 : x; } /* -0 -> +0 */
+static double mx1(double x) { double a = fabs(x); return a > 1.0 ? a : 1.0; }
+static double tol_of(const or_settings *s, double x) { return s->feas_tol * mx1(x); }
+
+static void *xcalloc(size_t n, size_t sz) {
+    void *p = calloc(n ? n : 1, sz);
+    if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    return p;
+}
+
+static void push(or_handle *h, int type, int side, int32_t i, int32_t j, int32_t k,
+                 double v0, double v1, double v2, double v3) {
+    if (h->nrec == h->caprec) {
+        h->caprec = h->caprec ? 2 * h->caprec : 1024;
+        h->rec = (or_record *)realloc(h->rec, (size_t)h->caprec * sizeof(or_record));
+        if (!h->rec) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    }
+    or_record *r = &h->rec[h->nrec++];
+    memset(r, 0, sizeof *r);
+    r->type = (uint8_t)type;
+    r->side = (uint8_t)side;
+    r->round = (uint16_t)h->round;
+    r->i = i; r->j = j; r->k = k;
+    r->v[0] = v0; r->v[1] = v1; r->v[2] = v2; r->v[3] = v3;
+}
+
+/* ------------------------------------------------------------------------- */
+/* canonical pairwise sum (reading R-Sum)                                     */
+/* ------------------------------------------------------------------------- */
+
+/* Sum of the aligned block [lo, lo+size) of the padded leaf sequence. */
+static double pw_block(const double *x, int64_t len, int64_t lo, int64_t size) {
+    if (lo >= len) return 0.0;            /* an all-padding block sums to +0 */
+    if (size == 1) return x[lo];
+    int64_t h = size / 2;
+    double left = pw_block(x, len, lo, h);
+    double right = pw_block(x, len, lo + h, h);
+    return left + right;
+}
+
+double or_pairwise_sum(const double *x, int64_t len) {
+    if (len <= 0) return 0.0;
+    int64_t p = 1;
+    while (p < len) p <<= 1;
+    return pw_block(x, len, 0, p);
+}
+
+/* ------------------------------------------------------------------------- */
+/* parallel-row key (reading R-Hash)                                          */
+/* ------------------------------------------------------------------------- */
+
+/* SplitMix64 output function for state x (Steele, Lea & Flood 2014). */
+static uint64_t splitmix(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* keep sign, exponent and the top 32 mantissa bits, rounded to nearest */
+static uint64_t quantize(double v) {
+    uint64_t b;
+    memcpy(&b, &v, 8);
+    uint64_t sign = b >> 63;
+    uint64_t mag = b & 0x7FFFFFFFFFFFFFFFULL;
+    uint64_t q = (mag + (1ULL << 19)) >> 20;
+    return q | (sign << 63);
+}
+
+uint64_t or_row_key(const int32_t *cols, const double *vals, int64_t len) {
+    /* level 1: sparsity pattern; level 2: normalised coefficients */
+    uint64_t h1 = (uint64_t)len;
+    uint64_t h2 = 0;
+    for (int64_t k = 0; k < len; ++k) {
+        uint64_t cj = splitmix((uint64_t)(uint32_t)cols[k]);
+        double v = vals[k] / vals[0];
+        h1 += cj;
+        h2 += splitmix(cj ^ quantize(v));
+    }
+    return (splitmix(h1) ^ h2) | 1ULL;
+}
+
+/* ------------------------------------------------------------------------- */
+/* validation and ingest                                                      */
+/* ------------------------------------------------------------------------- */
+
+static int fail(or_handle *h, const char *msg) {
+    snprintf(h->err, sizeof h->err, "%s", msg);
+    return 1;
+}
+
+static double canon_inf(double v, double inf_value) {
+    if (v >= inf_value) return INFINITY;
+    if (v <= -inf_value) return -INFINITY;
+    return pos0(v);
+}
+
+static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s) {
+    if (s->max_rounds < 1 || s->max_outer < 1 ||
+        (int64_t)s->max_outer * (s->max_rounds + 1) + 1 > 65535)
+        return fail(h, "invalid round limits");
+    if (!(s->feas_tol >= 0) || !(s->fix_tol >= 0) || !(s->min_improve >= 0) ||
+        !(s->par_tol >= 0) || !(s->inf_value > 0) || !(s->coef_tol >= 0))
+        return fail(h, "invalid tolerance");
+    if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return fail(h, "negative size");
+    int32_t m = lp->m, n = lp->n;
+    if (m > 0 && (!lp->row_ptr || !lp->lhs || !lp->rhs)) return fail(h, "null row array");
+    if (n > 0 && (!lp->lb || !lp->ub || !lp->c)) return fail(h, "null column array");
+    if (lp->nnz > 0 && (!lp->col_idx || !lp->val)) return fail(h, "null matrix array");
+    if (m > 0 && (lp->row_ptr[0] != 0 || lp->row_ptr[m] != lp->nnz)) return fail(h, "bad row_ptr ends");
+    if (m == 0 && lp->nnz != 0) return fail(h, "entries without rows");
+    for (int32_t i = 0; i < m; ++i) {
+        if (lp->row_ptr[i + 1] < lp->row_ptr[i]) return fail(h, "row_ptr decreasing");
+        for (int64_t k = lp->row_ptr[i]; k < lp->row_ptr[i + 1]; ++k) {
+            int32_t j = lp->col_idx[k];
+            if (j < 0 || j >= n) return fail(h, "column index out of range");
+            if (k > lp->row_ptr[i] && j <= lp->col_idx[k - 1]) return fail(h, "columns not strictly ascending");
+            double a = lp->val[k];
+            if (!isfinite(a) || a == 0.0) return fail(h, "coefficient zero or not finite");
+        }
+    }
+    for (int32_t i = 0; i < m; ++i) {
+        if (isnan(lp->lhs[i]) || isnan(lp->rhs[i])) return fail(h, "NaN side");
+        if (lp->lhs[i] == INFINITY || lp->rhs[i] == -INFINITY) return fail(h, "side infinite on the wrong end");
+        if (lp->lhs[i] >= s->inf_value || lp->rhs[i] <= -s->inf_value) return fail(h, "side infinite on the wrong end");
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        if (isnan(lp->lb[j]) || isnan(lp->ub[j])) return fail(h, "NaN bound");
+        if (lp->lb[j] >= s->inf_value || lp->ub[j] <= -s->inf_value) return fail(h, "bound infinite on the wrong end");
+        if (!isfinite(lp->c[j])) return fail(h, "cost not finite");
+    }
+    if (!isfinite(lp->obj_offset)) return fail(h, "offset not finite");
+
+    h->m = m; h->n = n; h->nnz = lp->nnz; h->s = *s;
+    h->rp = (int32_t *)xcalloc((size_t)m + 1, sizeof(int32_t));
+    h->ci = (int32_t *)xcalloc((size_t)lp->nnz, sizeof(int32_t));
+    h->va = (double *)xcalloc((size_t)lp->nnz, sizeof(double));
+    h->lhs = (double *)xcalloc((size_t)m, sizeof(double));
+    h->rhs = (double *)xcalloc((size_t)m, sizeof(double));
+    h->lb = (double *)xcalloc((size_t)n, sizeof(double));
+    h->ub = (double *)xcalloc((size_t)n, sizeof(double));
+    h->c = (double *)xcalloc((size_t)n, sizeof(double));
+    if (m > 0) memcpy(h->rp, lp->row_ptr, ((size_t)m + 1) * sizeof(int32_t));
+    if (lp->nnz > 0) {
+        memcpy(h->ci, lp->col_idx, (size_t)lp->nnz * sizeof(int32_t));
+        memcpy(h->va, lp->val, (size_t)lp->nnz * sizeof(double));
+    }
+    for (int32_t i = 0; i < m; ++i) {
+        h->lhs[i] = canon_inf(lp->lhs[i], s->inf_value);
+        h->rhs[i] = canon_inf(lp->rhs[i], s->inf_value);
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        h->lb[j] = canon_inf(lp->lb[j], s->inf_value);
+        h->ub[j] = canon_inf(lp->ub[j], s->inf_value);
+        h->c[j] = pos0(lp->c[j]);
+    }
+    h->off = pos0(lp->obj_offset);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* activities (section 3.1): min/max activity with infinite-bound counts      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t L;            /* active (not removed) columns in the row      */
+    int32_t ninf_min, ninf_max;
+    double minact, maxact; /* pairwise sums of the finite contributions */
+} row_stats;
+
+/* contribution of coefficient a on [lo, up] to the min (which=0) / max (1)
+ * activity; returns 1 when the bound used is infinite */
+static int contribution(double a, double lo, double up, int which, double *out) {
+    double b = (a > 0) == (which == 0) ? lo : up;
+    if (isinf(b)) { *out = 0.0; return 1; }
+    *out = pos0(a * b);
+    return 0;
+}
+
+static void compute_stats(const or_handle *h, int32_t i, const double *lb, const double *ub,
+                          double *tmin, double *tmax, row_stats *st) {
+    int64_t s0 = h->rp[i], len = h->rp[i + 1] - h->rp[i];
+    st->L = 0; st->ninf_min = 0; st->ninf_max = 0;
+    for (int64_t t = 0; t < len; ++t) {
+        int32_t j = h->ci[s0 + t];
+        double a = h->va[s0 + t];
+        if (h->col_on[j]) st->L++;
+        st->ninf_min += contribution(a, lb[j], ub[j], 0, &tmin[t]);
+        st->ninf_max += contribution(a, lb[j], ub[j], 1, &tmax[t]);
+    }
+    st->minact = or_pairwise_sum(tmin, len);
+    st->maxact = or_pairwise_sum(tmax, len);
+}
+
+/* ------------------------------------------------------------------------- */
+/* one propagation round (reading R-Jacobi)                                   */
+/* ------------------------------------------------------------------------- */
+
+enum { DEC_KEEP = 0, DEC_EMPTY = 1, DEC_REDUNDANT = 2, DEC_SINGLETON = 3 };
+
+typedef struct {
+    double *lb_s, *ub_s;       /* snapshot                         */
+    double *lb_n, *ub_n;       /* best qualifying candidates       */
+    int32_t *src_lb, *src_ub;  /* lowest row giving the final value */
+    double *tmin, *tmax;       /* per-row scratch                  */
+    uint8_t *dec;
+    row_stats *st;
+} round_ws;
+
+/* Implied bounds of row i on each of its active columns, from the residual
+ * activity with the column's own contribution taken out. Returns 1 when the
+ * row (with one active column) is fully captured by the candidates it gave. */
+static int propagate_row(or_handle *h, int32_t i, const row_stats *st, round_ws *w) {
+    const or_settings *s = &h->s;
+    int64_t s0 = h->rp[i], len = h->rp[i + 1] - h->rp[i];
+    double lhs = h->lhs[i], rhs = h->rhs[i];
+    int single = st->L == 1;
+    int captured = 1;
+    for (int64_t t = 0; t < len; ++t) {
+        int32_t j = h->ci[s0 + t];
+        if (!h->col_on[j]) continue;
+        double a = h->va[s0 + t];
+        if (fabs(a) < s->coef_tol) { captured = 0; continue; }
+        double cmin, cmax;
+        int imin = contribution(a, w->lb_s[j], w->ub_s[j], 0, &cmin);
+        int imax = contribution(a, w->lb_s[j], w->ub_s[j], 1, &cmax);
+
+        /* residual min activity: every other column at its min contribution */
+        int have_rmin = 0, have_rmax = 0;
+        double rmin = 0, rmax = 0;
+        if (st->ninf_min == 0) { rmin = st->minact - cmin; have_rmin = 1; }
+        else if (st->ninf_min == 1 && imin) { rmin = st->minact; have_rmin = 1; }
+        if (st->ninf_max == 0) { rmax = st->maxact - cmax; have_rmax = 1; }
+        else if (st->ninf_max == 1 && imax) { rmax = st->maxact; have_rmax = 1; }
+
+        for (int side = 0; side < 2; ++side) {
+            /* side 0: from rhs and the residual min; side 1: from lhs and the residual max */
+            double b = side == 0 ? rhs : lhs;
+            int have = side == 0 ? have_rmin : have_rmax;
+            if (isinf(b)) continue;
+            if (!have) { captured = 0; continue; }
+            double t_ = pos0((b - (side == 0 ? rmin : rmax)) / a);
+            if (!(fabs(t_) < s->inf_value)) { captured = 0; continue; }
+            /* a > 0: rhs gives an upper bound, lhs a lower bound; a < 0 swaps */
+            int upper = (side == 0) == (a > 0);
+            if (upper) {
+                double u = w->ub_s[j];
+                int q = isinf(u) ? 1 : (single ? t_ < u : t_ < u - s->min_improve * mx1(u));
+                if (q && t_ < w->ub_n[j]) { w->ub_n[j] = t_; w->src_ub[j] = i; }
+            } else {
+                double l = w->lb_s[j];
+                int q = isinf(l) ? 1 : (single ? t_ > l : t_ > l + s->min_improve * mx1(l));
+                if (q && t_ > w->lb_n[j]) { w->lb_n[j] = t_; w->src_lb[j] = i; }
+            }
+        }
+    }
+    return single && captured;
+}
+
+static double coef_in_row(const or_handle *h, int32_t i, int32_t j) {
+    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k)
+        if (h->ci[k] == j) return h->va[k];
+    return 0.0;
+}
+
+static void drop_row(or_handle *h, int32_t i) {
+    h->row_on[i] = 0;
+    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k)
+        if (h->col_on[h->ci[k]]) h->col_len[h->ci[k]]--;
+}
+
+/* returns 1 if anything changed; sets h->result on infeasible / unbounded */
+static int run_round(or_handle *h, round_ws *w) {
+    const or_settings *s = &h->s;
+    int32_t m = h->m, n = h->n;
+    int64_t nrec0 = h->nrec;
+    int infeasible = 0, unbounded = 0;
+
+    for (int32_t j = 0; j < n; ++j) {
+        w->lb_s[j] = w->lb_n[j] = h->lb[j];
+        w->ub_s[j] = w->ub_n[j] = h->ub[j];
+        w->src_lb[j] = w->src_ub[j] = -1;
+    }
+
+    /* rows: statistics, decisions, propagation (all from the snapshot) */
+    for (int32_t i = 0; i < m; ++i) {
+        w->dec[i] = DEC_KEEP;
+        if (!h->row_on[i]) continue;
+        row_stats *st = &w->st[i];
+        compute_stats(h, i, w->lb_s, w->ub_s, w->tmin, w->tmax, st);
+        double lhs = h->lhs[i], rhs = h->rhs[i];
+        int lo_ok = isinf(lhs) || (st->ninf_min == 0 && st->minact >= lhs - tol_of(s, lhs));
+        int up_ok = isinf(rhs) || (st->ninf_max == 0 && st->maxact <= rhs + tol_of(s, rhs));
+        if (st->L == 0) {
+            /* all columns removed: the activity is a constant */
+            if (lo_ok && up_ok) w->dec[i] = DEC_EMPTY;
+            else infeasible = 1;
+            continue;
+        }
+        if (lo_ok && up_ok) { w->dec[i] = DEC_REDUNDANT; continue; }
+        if ((st->ninf_min == 0 && !isinf(rhs) && st->minact > rhs + tol_of(s, rhs)) ||
+            (st->ninf_max == 0 && !isinf(lhs) && st->maxact < lhs - tol_of(s, lhs))) {
+            infeasible = 1;
+            propagate_row(h, i, st, w);
+            continue;
+        }
+        if (propagate_row(h, i, st, w)) w->dec[i] = DEC_SINGLETON;
+    }
+
+    /* row records, ascending row index */
+    for (int32_t i = 0; i < m; ++i) {
+        if (w->dec[i] == DEC_KEEP) continue;
+        const row_stats *st = &w->st[i];
+        if (w->dec[i] == DEC_EMPTY) {
+            push(h, REC_EMPTY_ROW, 0, i, -1, -1, st->minact, h->lhs[i], h->rhs[i], 0);
+        } else if (w->dec[i] == DEC_REDUNDANT) {
+            push(h, REC_REDUNDANT_ROW, 0, i, -1, -1,
+                 st->ninf_min ? -INFINITY : st->minact, st->ninf_max ? INFINITY : st->maxact,
+                 h->lhs[i], h->rhs[i]);
+        } else {
+            int32_t jj = -1;
+            double a = 0;
+            for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k)
+                if (h->col_on[h->ci[k]]) { jj = h->ci[k]; a = h->va[k]; }
+            push(h, REC_SINGLETON_ROW, 0, i, jj, -1, a, h->lhs[i], h->rhs[i], 0);
+        }
+        drop_row(h, i);
+    }
+
+    /* columns: bound changes, fixings, empty columns; ascending column index */
+    for (int32_t j = 0; j < n; ++j) {
+        if (!h->col_on[j]) continue;
+        double lo = w->lb_n[j], up = w->ub_n[j];
+        if (lo != w->lb_s[j])
+            push(h, REC_BOUND_CHANGE, 0, -1, j, w->src_lb[j], w->lb_s[j], lo,
+                 coef_in_row(h, w->src_lb[j], j), 0);
+        if (up != w->ub_s[j])
+            push(h, REC_BOUND_CHANGE, 1, -1, j, w->src_ub[j], w->ub_s[j], up,
+                 coef_in_row(h, w->src_ub[j], j), 0);
+        if (!isinf(lo) && !isinf(up) && lo > up + tol_of(s, up)) infeasible = 1;
+        if (!isinf(lo) && !isinf(up) && up - lo <= s->fix_tol * mx1(lo)) {
+            push(h, REC_FIX_COL, 0, -1, j, -1, lo, h->c[j], 0, 0);
+            h->lb[j] = h->ub[j] = lo;
+            h->col_on[j] = 0;
+        } else if (h->col_len[j] == 0) {
+            double cj = h->c[j], v;
+            if (cj > 0) v = lo;
+            else if (cj < 0) v = up;
+            else v = lo > 0 ? lo : (up < 0 ? up : 0.0);
+            if (isinf(v)) {
+                unbounded = 1;
+                h->lb[j] = lo; h->ub[j] = up;
+            } else {
+                push(h, REC_EMPTY_COL, 0, -1, j, -1, v, cj, 0, 0);
+                h->lb[j] = h->ub[j] = v;
+                h->col_on[j] = 0;
+            }
+        } else {
+            h->lb[j] = lo;
+            h->ub[j] = up;
+        }
+    }
+
+    if (infeasible) h->result = RES_INFEASIBLE;
+    else if (unbounded) h->result = RES_UNBOUNDED;
+    return h->nrec != nrec0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* parallel rows (section 3.2)                                                */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { uint64_t key; int32_t row; } keyrow;
+
+static int cmp_keyrow(const void *a, const void *b) {
+    const keyrow *x = (const keyrow *)a, *y = (const keyrow *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return (x->row > y->row) - (x->row < y->row);
+}
+
+static int active_len(const or_handle *h, int32_t i) {
+    int L = 0;
+    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k) L += h->col_on[h->ci[k]];
+    return L;
+}
+
+/* same stored pattern and coefficients proportional within par_tol */
+static int rows_parallel(const or_handle *h, int32_t r, int32_t l) {
+    int64_t lr = h->rp[r + 1] - h->rp[r], ll = h->rp[l + 1] - h->rp[l];
+    if (lr != ll) return 0;
+    const int32_t *cr = h->ci + h->rp[r], *cl = h->ci + h->rp[l];
+    const double *vr = h->va + h->rp[r], *vl = h->va + h->rp[l];
+    for (int64_t t = 0; t < lr; ++t) {
+        if (cr[t] != cl[t]) return 0;
+        double a = vr[t] / vr[0], b = vl[t] / vl[0];
+        double scale = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+        if (!(fabs(a - b) <= h->s.par_tol * scale)) return 0;
+    }
+    return 1;
+}
+
+/* returns 1 if any row was merged */
+static int parallel_rows(or_handle *h) {
+    const or_settings *s = &h->s;
+    int32_t m = h->m;
+    keyrow *kr = (keyrow *)xcalloc((size_t)m, sizeof(keyrow));
+    int32_t nk = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        if (!h->row_on[i] || active_len(h, i) < 2) continue;
+        kr[nk].key = or_row_key(h->ci + h->rp[i], h->va + h->rp[i], h->rp[i + 1] - h->rp[i]);
+        kr[nk].row = i;
+        nk++;
+    }
+    qsort(kr, (size_t)nk, sizeof(keyrow), cmp_keyrow);
+
+    int32_t *leader_of = (int32_t *)xcalloc((size_t)m, sizeof(int32_t));
+    double *lam = (double *)xcalloc((size_t)m, sizeof(double));
+    double *new_l = (double *)xcalloc((size_t)m, sizeof(double));
+    double *new_u = (double *)xcalloc((size_t)m, sizeof(double));
+    int32_t *src_l = (int32_t *)xcalloc((size_t)m, sizeof(int32_t));
+    int32_t *src_u = (int32_t *)xcalloc((size_t)m, sizeof(int32_t));
+    uint8_t *is_leader = (uint8_t *)xcalloc((size_t)m, 1);
+    for (int32_t i = 0; i < m; ++i) leader_of[i] = -1;
+
+    for (int32_t g0 = 0; g0 < nk;) {
+        int32_t g1 = g0 + 1;
+        while (g1 < nk && kr[g1].key == kr[g0].key) g1++;
+        if (g1 - g0 >= 2) {
+            /* leader: the first equality row of the group, else the first row */
+            int32_t L = -1;
+            for (int32_t t = g0; t < g1 && L < 0; ++t)
+                if (h->lhs[kr[t].row] == h->rhs[kr[t].row]) L = kr[t].row;
+            if (L < 0) L = kr[g0].row;
+            /* members in ascending row order; the leader's own sides first */
+            double lo = h->lhs[L], up = h->rhs[L];
+            int32_t sl = L, su = L;
+            int any = 0;
+            for (int32_t t = g0; t < g1; ++t) {
+                int32_t r = kr[t].row;
+                if (r == L || !rows_parallel(h, r, L)) continue;
+                double la = h->va[h->rp[r]] / h->va[h->rp[L]];
+                double ml, mu;
+                if (la > 0) { ml = h->lhs[r] / la; mu = h->rhs[r] / la; }
+                else { ml = h->rhs[r] / la; mu = h->lhs[r] / la; }
+                ml = pos0(ml); mu = pos0(mu);
+                if (ml > lo || (ml == lo && r < sl)) { lo = ml; sl = r; }
+                if (mu < up || (mu == up && r < su)) { up = mu; su = r; }
+                leader_of[r] = L;
+                lam[r] = la;
+                any = 1;
+            }
+            if (any) {
+                is_leader[L] = 1;
+                new_l[L] = lo; new_u[L] = up;
+                src_l[L] = sl; src_u[L] = su;
+            }
+        }
+        g0 = g1;
+    }
+
+    int merged = 0, infeasible = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        if (leader_of[i] >= 0) {
+            push(h, REC_PARALLEL_ROW, 0, i, -1, leader_of[i], lam[i], h->lhs[i], h->rhs[i], 0);
+            drop_row(h, i);
+            merged = 1;
+        } else if (is_leader[i]) {
+            double lo = new_l[i], up = new_u[i];
+            if (!isinf(lo) && !isinf(up) && lo > up) {
+                if (lo > up + tol_of(s, up)) infeasible = 1;
+                else lo = up;
+            }
+            if (lo != h->lhs[i] || up != h->rhs[i]) {
+                push(h, REC_LEADER_SIDES, 0, i, src_l[i], src_u[i], h->lhs[i], h->rhs[i], lo, up);
+                h->lhs[i] = lo;
+                h->rhs[i] = up;
+            }
+        }
+    }
+    if (infeasible) h->result = RES_INFEASIBLE;
+    free(kr); free(leader_of); free(lam); free(new_l); free(new_u);
+    free(src_l); free(src_u); free(is_leader);
+    return merged;
+}
+
+/* ------------------------------------------------------------------------- */
+/* reduced problem (section 3.3)                                              */
+/* ------------------------------------------------------------------------- */
+
+static void compact(or_handle *h) {
+    int32_t m = h->m, n = h->n;
+    int32_t *nr = (int32_t *)xcalloc((size_t)m, sizeof(int32_t));
+    int32_t *nc = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    int32_t rm = 0, rn = 0;
+    for (int32_t i = 0; i < m; ++i) nr[i] = h->row_on[i] ? rm++ : -1;
+    for (int32_t j = 0; j < n; ++j) nc[j] = h->col_on[j] ? rn++ : -1;
+    int64_t rnnz = 0;
+    for (int32_t i = 0; i < m; ++i)
+        if (h->row_on[i])
+            for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k) rnnz += h->col_on[h->ci[k]];
+
+    h->rm = rm; h->rn = rn; h->rnnz = rnnz;
+    h->r_rp = (int32_t *)xcalloc((size_t)rm + 1, sizeof(int32_t));
+    h->r_ci = (int32_t *)xcalloc((size_t)rnnz, sizeof(int32_t));
+    h->r_va = (double *)xcalloc((size_t)rnnz, sizeof(double));
+    h->r_cp = (int32_t *)xcalloc((size_t)rn + 1, sizeof(int32_t));
+    h->r_ri = (int32_t *)xcalloc((size_t)rnnz, sizeof(int32_t));
+    h->r_cva = (double *)xcalloc((size_t)rnnz, sizeof(double));
+    h->r_lhs = (double *)xcalloc((size_t)rm, sizeof(double));
+    h->r_rhs = (double *)xcalloc((size_t)rm, sizeof(double));
+    h->r_lb = (double *)xcalloc((size_t)rn, sizeof(double));
+    h->r_ub = (double *)xcalloc((size_t)rn, sizeof(double));
+    h->r_c = (double *)xcalloc((size_t)rn, sizeof(double));
+    h->r_rowmap = (int32_t *)xcalloc((size_t)rm, sizeof(int32_t));
+    h->r_colmap = (int32_t *)xcalloc((size_t)rn, sizeof(int32_t));
+    h->r_rcls = (uint8_t *)xcalloc((size_t)rm, 1);
+    h->r_ccls = (uint8_t *)xcalloc((size_t)rn, 1);
+
+    int64_t maxlen = 0;
+    for (int32_t i = 0; i < m; ++i)
+        if (h->rp[i + 1] - h->rp[i] > maxlen) maxlen = h->rp[i + 1] - h->rp[i];
+    double *tmp = (double *)xcalloc((size_t)maxlen, sizeof(double));
+
+    int64_t pos = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        if (!h->row_on[i]) continue;
+        int32_t ri = nr[i];
+        h->r_rowmap[ri] = i;
+        int64_t s0 = h->rp[i], len = h->rp[i + 1] - h->rp[i];
+        for (int64_t t = 0; t < len; ++t) {
+            int32_t j = h->ci[s0 + t];
+            if (h->col_on[j]) {
+                h->r_ci[pos] = nc[j];
+                h->r_va[pos] = h->va[s0 + t];
+                pos++;
+                tmp[t] = 0.0;
+            } else {
+                tmp[t] = pos0(h->va[s0 + t] * h->lb[j]);
+            }
+        }
+        h->r_rp[ri + 1] = (int32_t)pos;
+        /* sides shifted by the removed columns' constant contribution */
+        double k = or_pairwise_sum(tmp, len);
+        h->r_lhs[ri] = isinf(h->lhs[i]) ? h->lhs[i] : pos0(h->lhs[i] - k);
+        h->r_rhs[ri] = isinf(h->rhs[i]) ? h->rhs[i] : pos0(h->rhs[i] - k);
+        int32_t L = h->r_rp[ri + 1] - h->r_rp[ri];
+        h->r_rcls[ri] = L == 1 ? RCLS_SINGLETON
+                      : L == 2 ? (h->r_lhs[ri] == h->r_rhs[ri] ? RCLS_DOUBLETON_EQ : RCLS_DOUBLETON_INEQ)
+                      : RCLS_OTHER;
+    }
+    free(tmp);
+
+    /* objective offset: removed columns' cost terms, pairwise over j */
+    double *terms = (double *)xcalloc((size_t)n, sizeof(double));
+    for (int32_t j = 0; j < n; ++j) {
+        if (h->col_on[j]) {
+            terms[j] = 0.0;
+            int32_t rj = nc[j];
+            h->r_colmap[rj] = j;
+            h->r_lb[rj] = h->lb[j];
+            h->r_ub[rj] = h->ub[j];
+            h->r_c[rj] = h->c[j];
+        } else {
+            terms[j] = pos0(h->c[j] * h->lb[j]);
+        }
+    }
+    h->roff = pos0(h->off + or_pairwise_sum(terms, n));
+    free(terms);
+
+    /* CSC of the reduced matrix: stable counting transpose */
+    for (int64_t p = 0; p < rnnz; ++p) h->r_cp[h->r_ci[p] + 1]++;
+    for (int32_t j = 0; j < rn; ++j) h->r_cp[j + 1] += h->r_cp[j];
+    int32_t *cur = (int32_t *)xcalloc((size_t)rn + 1, sizeof(int32_t));
+    memcpy(cur, h->r_cp, ((size_t)rn + 1) * sizeof(int32_t));
+    for (int32_t ri = 0; ri < rm; ++ri)
+        for (int64_t p = h->r_rp[ri]; p < h->r_rp[ri + 1]; ++p) {
+            int32_t cj = h->r_ci[p];
+            h->r_ri[cur[cj]] = ri;
+            h->r_cva[cur[cj]] = h->r_va[p];
+            cur[cj]++;
+        }
+    free(cur);
+    for (int32_t rj = 0; rj < rn; ++rj) {
+        int32_t len = h->r_cp[rj + 1] - h->r_cp[rj];
+        int free_col = isinf(h->r_lb[rj]) && isinf(h->r_ub[rj]);
+        h->r_ccls[rj] = len == 1 ? (free_col ? CCLS_SINGLETON_FREE : CCLS_SINGLETON)
+                      : len == 2 ? CCLS_DOUBLETON : CCLS_OTHER;
+    }
+    free(nr);
+    free(nc);
+}
+
+/* ------------------------------------------------------------------------- */
+/* driver                                                                     */
+/* ------------------------------------------------------------------------- */
+
+int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
+    or_handle *h = (or_handle *)xcalloc(1, sizeof(or_handle));
+    *out = h;
+    h->result = RES_UNCHANGED;
+    if (!lp || !s) return fail(h, "null argument");
+    if (validate_and_copy(h, lp, s)) return 1;
+    int32_t m = h->m, n = h->n;
+
+    h->row_on = (uint8_t *)xcalloc((size_t)m, 1);
+    h->col_on = (uint8_t *)xcalloc((size_t)n, 1);
+    h->col_len = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    for (int32_t i = 0; i < m; ++i) h->row_on[i] = 1;
+    for (int32_t j = 0; j < n; ++j) h->col_on[j] = 1;
+    for (int64_t k = 0; k < h->nnz; ++k) h->col_len[h->ci[k]]++;
+
+    /* round 0: input fixings and crossed bounds / sides */
+    h->round = 0;
+    int infeasible = 0;
+    for (int32_t i = 0; i < m; ++i)
+        if (!isinf(h->lhs[i]) && !isinf(h->rhs[i]) && h->lhs[i] > h->rhs[i] + tol_of(s, h->rhs[i]))
+            infeasible = 1;
+    for (int32_t j = 0; j < n; ++j) {
+        double lo = h->lb[j], up = h->ub[j];
+        if (isinf(lo) || isinf(up)) continue;
+        if (lo > up + tol_of(s, up)) infeasible = 1;
+        if (up - lo <= s->fix_tol * mx1(lo)) {
+            push(h, REC_FIX_COL, 0, -1, j, -1, lo, h->c[j], 0, 0);
+            h->ub[j] = lo;
+            h->col_on[j] = 0;
+        }
+    }
+    if (infeasible) { h->result = RES_INFEASIBLE; return 0; }
+
+    int64_t maxlen = 0;
+    for (int32_t i = 0; i < m; ++i)
+        if (h->rp[i + 1] - h->rp[i] > maxlen) maxlen = h->rp[i + 1] - h->rp[i];
+    round_ws w;
+    w.lb_s = (double *)xcalloc((size_t)n, sizeof(double));
+    w.ub_s = (double *)xcalloc((size_t)n, sizeof(double));
+    w.lb_n = (double *)xcalloc((size_t)n, sizeof(double));
+    w.ub_n = (double *)xcalloc((size_t)n, sizeof(double));
+    w.src_lb = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    w.src_ub = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    w.tmin = (double *)xcalloc((size_t)maxlen, sizeof(double));
+    w.tmax = (double *)xcalloc((size_t)maxlen, sizeof(double));
+    w.dec = (uint8_t *)xcalloc((size_t)m, 1);
+    w.st = (row_stats *)xcalloc((size_t)m, sizeof(row_stats));
+
+    int stop = 0;
+    for (int outer = 0; outer < s->max_outer && !stop; ++outer) {
+        for (int r = 0; r < s->max_rounds; ++r) {
+            h->round++;
+            int changed = run_round(h, &w);
+            if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
+            if (!changed) break;
+        }
+        if (stop || !s->enable_parallel_rows) break;
+        h->round++;
+        int merged = parallel_rows(h);
+        if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
+        if (!merged) break;
+    }
+    free(w.lb_s); free(w.ub_s); free(w.lb_n); free(w.ub_n);
+    free(w.src_lb); free(w.src_ub); free(w.tmin); free(w.tmax); free(w.dec); free(w.st);
+
+    if (h->result < RES_INFEASIBLE) {
+        h->result = h->nrec ? RES_REDUCED : RES_UNCHANGED;
+        compact(h);
+    }
+    return 0;
+}
+
+/* Round-1 activities of every row from the input bounds (all columns active);
+ * exposed for the pin tests. */
+int or_activities(const or_lp *lp, double *minact, double *maxact,
+                  int32_t *ninf_min, int32_t *ninf_max) {
+    or_handle h;
+    memset(&h, 0, sizeof h);
+    h.m = lp->m; h.n = lp->n;
+    h.rp = (int32_t *)lp->row_ptr; h.ci = (int32_t *)lp->col_idx; h.va = (double *)lp->val;
+    h.col_on = (uint8_t *)xcalloc((size_t)lp->n, 1);
+    for (int32_t j = 0; j < lp->n; ++j) h.col_on[j] = 1;
+    int64_t maxlen = 0;
+    for (int32_t i = 0; i < lp->m; ++i)
+        if (lp->row_ptr[i + 1] - lp->row_ptr[i] > maxlen) maxlen = lp->row_ptr[i + 1] - lp->row_ptr[i];
+    double *tmin = (double *)xcalloc((size_t)maxlen, sizeof(double));
+    double *tmax = (double *)xcalloc((size_t)maxlen, sizeof(double));
+    for (int32_t i = 0; i < lp->m; ++i) {
+        row_stats st;
+        compute_stats(&h, i, lp->lb, lp->ub, tmin, tmax, &st);
+        minact[i] = st.minact; maxact[i] = st.maxact;
+        ninf_min[i] = st.ninf_min; ninf_max[i] = st.ninf_max;
+    }
+    free(tmin); free(tmax); free(h.col_on);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* postsolve (primal): kept columns from the reduced solution, removed ones   */
+/* from their FIX_COL / EMPTY_COL records; every other record on the hot path */
+/* keeps the feasible set and leaves x unchanged.                             */
+/* ------------------------------------------------------------------------- */
+
+int or_postsolve(const or_handle *h, const double *x_red, double *x) {
+    if (h->result >= RES_INFEASIBLE) return 1;
+    for (int32_t j = 0; j < h->n; ++j) x[j] = 0.0;
+    for (int32_t rj = 0; rj < h->rn; ++rj) x[h->r_colmap[rj]] = x_red[rj];
+    for (int64_t t = h->nrec - 1; t >= 0; --t) {
+        const or_record *r = &h->rec[t];
+        if (r->type == REC_FIX_COL || r->type == REC_EMPTY_COL) x[r->j] = r->v[0];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* accessors                                                                  */
+/* ------------------------------------------------------------------------- */
+
+void or_free(or_handle *h) {
+    if (!h) return;
+    free(h->rp); free(h->ci); free(h->va); free(h->lhs); free(h->rhs);
+    free(h->lb); free(h->ub); free(h->c); free(h->row_on); free(h->col_on);
+    free(h->col_len); free(h->rec);
+    free(h->r_rp); free(h->r_ci); free(h->r_va); free(h->r_cp); free(h->r_ri); free(h->r_cva);
+    free(h->r_lhs); free(h->r_rhs); free(h->r_lb); free(h->r_ub); free(h->r_c);
+    free(h->r_rowmap); free(h->r_colmap); free(h->r_rcls); free(h->r_ccls);
+    free(h);
+}
+
+const char *or_error(const or_handle *h) { return h ? h->err : "null handle"; }
+int32_t or_result(const or_handle *h) { return h->result; }
+int32_t or_rounds(const or_handle *h) { return h->round; }
+int64_t or_num_records(const or_handle *h) { return h->nrec; }
+const or_record *or_records(const or_handle *h) { return h->rec; }
+
+void or_reduced_dims(const or_handle *h, int32_t *m, int32_t *n, int64_t *nnz, double *obj_offset) {
+    *m = h->rm; *n = h->rn; *nnz = h->rnnz; *obj_offset = h->roff;
+}
+
+void or_reduced_copy(const or_handle *h, int32_t *row_ptr, int32_t *col_idx, double *val,
+                     int32_t *col_ptr, int32_t *row_idx, double *cval,
+                     double *lhs, double *rhs, double *lb, double *ub, double *c,
+                     int32_t *row_map, int32_t *col_map,
+                     uint8_t *row_class, uint8_t *col_class) {
+    memcpy(row_ptr, h->r_rp, ((size_t)h->rm + 1) * sizeof(int32_t));
+    memcpy(col_ptr, h->r_cp, ((size_t)h->rn + 1) * sizeof(int32_t));
+    if (h->rnnz) {
+        memcpy(col_idx, h->r_ci, (size_t)h->rnnz * sizeof(int32_t));
+        memcpy(val, h->r_va, (size_t)h->rnnz * sizeof(double));
+        memcpy(row_idx, h->r_ri, (size_t)h->rnnz * sizeof(int32_t));
+        memcpy(cval, h->r_cva, (size_t)h->rnnz * sizeof(double));
+    }
+    if (h->rm) {
+        memcpy(lhs, h->r_lhs, (size_t)h->rm * sizeof(double));
+        memcpy(rhs, h->r_rhs, (size_t)h->rm * sizeof(double));
+        memcpy(row_map, h->r_rowmap, (size_t)h->rm * sizeof(int32_t));
+        memcpy(row_class, h->r_rcls, (size_t)h->rm);
+    }
+    if (h->rn) {
+        memcpy(lb, h->r_lb, (size_t)h->rn * sizeof(double));
+        memcpy(ub, h->r_ub, (size_t)h->rn * sizeof(double));
+        memcpy(c, h->r_c, (size_t)h->rn * sizeof(double));
+        memcpy(col_map, h->r_colmap, (size_t)h->rn * sizeof(int32_t));
+        memcpy(col_class, h->r_ccls, (size_t)h->rn);
+    }
+}
