@@ -1,0 +1,204 @@
+/*
+ * psl.h -- C-ABI of libpsl, a GPU (MI355X, gfx950) presolve sweep for linear
+ * programs of the form of eq. (1) in section 2.1 of Cederberg & Boyd,
+ * "GPU-Accelerated Presolving for Linear Programming":
+ *
+ *     minimize c'x + obj_offset   s.t.   lhs <= A x <= rhs,   lb <= x <= ub.
+ *
+ * One call to psl_presolve_run performs, in rounds, the reductions of
+ * sections 3.1 and 3.2 of that paper that are data parallel over rows and
+ * columns (activities, bound tightening, empty / redundant / singleton rows,
+ * fixed and empty columns, parallel rows), then emits a reduced LP of the same
+ * form (section 3.3) and a stream of postsolve records (section 2.1,
+ * "Postsolver"). All of it runs in the library's HIP kernels; postsolve runs on
+ * the host, as in section 3.3.
+ *
+ * Conventions for every function:
+ *   - The return value is a psl_status. On any status other than PSL_OK the
+ *     out-parameters are left untouched and psl_last_error() describes the
+ *     failure (per handle; NULL handle -> the last create error of the thread).
+ *   - Infeasible or unbounded problems are results (psl_result), not errors.
+ *   - Arrays are plain pointers with explicit sizes. Where a struct carries a
+ *     psl_mem field, PSL_MEM_HOST means host memory and PSL_MEM_DEVICE means
+ *     memory of the device named in psl_settings.device.
+ *   - All device work is ordered on psl_settings.stream (a hipStream_t, or
+ *     NULL for the default stream). Calls return after that work is complete
+ *     unless stated otherwise.
+ *   - Infinity: a side or bound whose magnitude is >= inf_value (default 1e20),
+ *     or +-INFINITY, is infinite.
+ *   - One handle must not be used from two threads at once.
+ */
+#ifndef PSL_H
+#define PSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSL_OK = 0,
+    PSL_ERR_INVALID = 1,     /* malformed input, bad argument or settings      */
+    PSL_ERR_OOM = 2,         /* device or host allocation failed               */
+    PSL_ERR_DEVICE = 3,      /* a HIP call failed                              */
+    PSL_ERR_STATE = 4,       /* call not valid in the handle's current state   */
+    PSL_ERR_CAPACITY = 5,    /* a size limit of the library was exceeded       */
+    PSL_ERR_UNSUPPORTED = 6  /* feature not provided (e.g. dual postsolve)     */
+} psl_status;
+
+typedef enum {
+    PSL_RES_REDUCED = 0,                 /* at least one reduction applied      */
+    PSL_RES_UNCHANGED = 1,               /* no reduction found                  */
+    PSL_RES_INFEASIBLE = 2,              /* a row or column is infeasible       */
+    PSL_RES_UNBOUNDED_OR_INFEASIBLE = 3  /* an empty column with a cost that
+                                            points to an infinite bound         */
+} psl_result;
+
+typedef enum { PSL_MEM_HOST = 0, PSL_MEM_DEVICE = 1 } psl_mem;
+
+/* The input LP, eq. (1). CSR with int32 indices: row_ptr[m+1] (row_ptr[0] = 0,
+ * non-decreasing, row_ptr[m] = nnz), col_idx[nnz] strictly ascending within
+ * each row and in [0, n), val[nnz] finite and non-zero. lhs/rhs[m], lb/ub/c[n].
+ * lhs must not be +inf, rhs not -inf; lb not +inf, ub not -inf; no NaN.
+ * nnz < 2^31. The library copies everything at create/reload: the caller
+ * keeps ownership of these arrays and may free them once the call returns. */
+typedef struct {
+    int32_t m, n;
+    int64_t nnz;
+    psl_mem mem;
+    const int32_t *row_ptr, *col_idx;
+    const double *val;
+    const double *lhs, *rhs, *lb, *ub, *c;
+    double obj_offset;
+} psl_lp;
+
+/* Settings. The tolerances are part of the round semantics: changing them
+ * changes which reductions fire. Defaults from psl_settings_default():
+ *   max_rounds 16, max_outer 4, enable_parallel_rows 1,
+ *   feas_tol 1e-9, fix_tol 1e-9, min_improve 1e-7, par_tol 1e-9,
+ *   inf_value 1e20, coef_tol 1e-9, bin thresholds from the tuner (NULL),
+ *   device 0, stream NULL.
+ * bin_thresholds (optional, n_bins = 2): row lengths up to which a row is
+ * swept by one 64-lane wavefront, and above which it is split over several
+ * workgroups. They change only the speed, never a result. */
+typedef struct {
+    int32_t max_rounds;            /* propagation rounds per outer cycle        */
+    int32_t max_outer;             /* outer cycles (rounds, then parallel rows) */
+    int32_t enable_parallel_rows;
+    double feas_tol;               /* tol(s) = feas_tol * max(1, |s|)           */
+    double fix_tol;                /* fix when ub - lb <= fix_tol*max(1,|lb|)   */
+    double min_improve;            /* accept a bound if it improves by more
+                                      than min_improve * max(1, |bound|)        */
+    double par_tol;                /* parallel-row coefficient tolerance        */
+    double inf_value;
+    double coef_tol;               /* |a| below this gives no implied bound     */
+    const int32_t *bin_thresholds;
+    int32_t n_bins;
+    int32_t device;
+    void *stream;                  /* hipStream_t or NULL                       */
+} psl_settings;
+
+/* Postsolve record: 48 bytes, emitted in the order (round, phase, index,
+ * side). Unused integer fields are -1, unused doubles 0.
+ *   type 1 FIX_COL        j; v = {value, c_j}
+ *   type 2 EMPTY_COL      j; v = {value, c_j}
+ *   type 3 EMPTY_ROW      i; v = {activity, lhs, rhs}
+ *   type 4 REDUNDANT_ROW  i; v = {min activity or -inf, max activity or +inf,
+ *                                 lhs, rhs}
+ *   type 5 SINGLETON_ROW  i, j = its active column; v = {a_ij, lhs, rhs}
+ *   type 6 BOUND_CHANGE   j, side (0 lower, 1 upper), k = source row;
+ *                         v = {old bound, new bound, a_kj}
+ *   type 7 PARALLEL_ROW   i = removed row, k = leader; v = {lambda, lhs, rhs}
+ *   type 8 LEADER_SIDES   i = leader, j = row giving lhs, k = row giving rhs;
+ *                         v = {old lhs, old rhs, new lhs, new rhs}
+ * round 0 holds input fixings; each propagation round and each parallel-row
+ * pass has its own round number. */
+typedef struct {
+    uint8_t type, side;
+    uint16_t round;
+    int32_t i, j, k;
+    double v[4];
+} psl_record;
+
+typedef struct {
+    int32_t rounds;                /* last round number used                    */
+    int32_t outer_cycles;
+    int64_t records;
+    int64_t nnz_in, nnz_out;
+    int32_t m_out, n_out;
+    /* device time per phase (ms), measured with HIP events on the stream */
+    double ms_ingest, ms_sweep, ms_decide, ms_parallel, ms_compact, ms_total;
+    int64_t sweep_launches;        /* launches of the row-sweep kernel          */
+    double sweep_bytes;            /* algorithmic bytes of those launches       */
+} psl_stats;
+
+/* The reduced problem. DEVICE pointers owned by the handle, valid until the
+ * next psl_presolve_run / psl_presolve_reload or psl_presolve_free.
+ * row_map / col_map give the original index of each kept row / column.
+ * row_class: 0 other, 1 singleton, 2 doubleton equality, 3 doubleton
+ * inequality. col_class: 0 other, 1 free singleton, 2 singleton, 3 doubleton.
+ * Rows and columns of these classes are detected and listed, not eliminated. */
+typedef struct {
+    int32_t m, n;
+    int64_t nnz;
+    const int32_t *row_ptr, *col_idx;
+    const double *val;
+    const int32_t *col_ptr, *row_idx;
+    const double *cval;
+    const double *lhs, *rhs, *lb, *ub, *c;
+    double obj_offset;
+    const int32_t *row_map, *col_map;
+    const uint8_t *row_class, *col_class;
+} psl_reduced_view;
+
+typedef struct psl_presolver psl_presolver;
+
+/* Fill *s with the defaults listed above. */
+void psl_settings_default(psl_settings *s);
+
+/* Validate and copy the LP to the device (section 3.2, "Internal data
+ * structures": A is kept with its transpose; sizes and flags are the state).
+ * Settings are copied. Errors: PSL_ERR_INVALID for malformed input (the
+ * checks listed at psl_lp) or settings, PSL_ERR_OOM, PSL_ERR_DEVICE. */
+psl_status psl_presolve_create(const psl_lp *lp, const psl_settings *s, psl_presolver **out);
+
+/* Replace the handle's LP with another one of the same m, n and nnz, reusing
+ * its device memory (no allocation). Same checks as create. */
+psl_status psl_presolve_reload(psl_presolver *p, const psl_lp *lp);
+
+/* Run the sweep: rounds of activities + bound tightening + row/column
+ * reductions (section 3.1, "Bound tightening"), parallel rows (section 3.2),
+ * then compaction. Writes the outcome to *res and, if stats is non-NULL,
+ * statistics. Errors: PSL_ERR_STATE if already run since create/reload,
+ * PSL_ERR_DEVICE, PSL_ERR_OOM. */
+psl_status psl_presolve_run(psl_presolver *p, psl_result *res, psl_stats *stats);
+
+/* View of the reduced problem (device pointers). PSL_ERR_STATE unless the
+ * last run gave PSL_RES_REDUCED or PSL_RES_UNCHANGED. */
+psl_status psl_reduced_problem(const psl_presolver *p, psl_reduced_view *out);
+
+/* Number of postsolve records of the last run, and a copy of them into the
+ * HOST array out[cap] (cap >= count, else PSL_ERR_CAPACITY). */
+psl_status psl_records(const psl_presolver *p, int64_t *count, psl_record *out, int64_t cap);
+
+/* Postsolve on the host (section 3.3): map a HOST solution x_red of the
+ * reduced problem to x[n] of the original. Kept columns come from x_red,
+ * removed columns from their FIX_COL / EMPTY_COL records; the other record
+ * types keep the feasible set and leave x unchanged. y_red / z_red (dual
+ * values) must be NULL: dual postsolve is not provided (PSL_ERR_UNSUPPORTED),
+ * and y, z are then not written. */
+psl_status psl_postsolve(psl_presolver *p, const double *x_red, const double *y_red,
+                         const double *z_red, double *x, double *y, double *z);
+
+void psl_presolve_free(psl_presolver *p);
+
+/* Message of the last failure on p (or of the last failed create when p is
+ * NULL). Never NULL. */
+const char *psl_last_error(const psl_presolver *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSL_H */

@@ -1,0 +1,125 @@
+// compact.hip -- emission of the reduced LP (section 3.3): kept rows x kept
+// columns in their original order, sides shifted by the removed columns'
+// constant contribution (canonical pairwise sum over the row, computed by the
+// sweep in compaction mode), the removed columns' cost terms folded into the
+// objective offset, and both the CSR and the transposed copy.
+//
+// Output positions come from exclusive scans of keep flags over the CSR
+// positions and over the transposed copy's positions, so the kept entries keep
+// their order in both layouts.
+#include "psl_kern.h"
+#include "sweep.h"
+
+namespace psl {
+
+__global__ void k_cmp_flags(Dev d, CompactScratch c) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i < d.m; i += stride) c.row_new[i] = d.row_on[i];
+  for (int64_t j = t0; j < d.n; j += stride) {
+    double2 b = d.bnd[j];
+    bool kept = b.x != b.y;
+    c.col_new[j] = kept;
+    c.terms[j] = kept ? 0.0 : pos0(d.c[j] * b.x);
+  }
+  for (int64_t p = t0; p <= d.nnz; p += stride) {
+    int ef = 0, qf = 0;
+    if (p < d.nnz) {
+      int row = c.rowid1[p + 1];
+      double2 b = d.bnd[d.ci[p]];
+      ef = d.row_on[row] && b.x != b.y;
+      double2 bq = d.bnd[c.colid[p]];
+      qf = d.row_on[d.ri[p]] && bq.x != bq.y;
+    }
+    c.eflag[p] = ef;
+    c.qflag[p] = qf;
+  }
+}
+
+__global__ void k_cmp_offset(const double* sum, double off, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = pos0(off + sum[0]);
+}
+
+__global__ void k_cmp_gather(Dev d, CompactScratch c, Reduced r) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < d.nnz; p += stride) {
+    int pe = c.eflag[p];
+    if (c.eflag[p + 1] != pe) {  // kept
+      r.col_idx[pe] = c.col_new[d.ci[p]];
+      r.val[pe] = d.va[p];
+    }
+    int pq = c.qflag[p];
+    if (c.qflag[p + 1] != pq) {
+      r.row_idx[pq] = c.row_new[d.ri[p]];
+      r.cval[pq] = d.cva[p];
+    }
+  }
+}
+
+__global__ void k_cmp_fill(Dev d, CompactScratch c, Reduced r) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t m = d.m, n = d.n;
+  if (t == 0) {
+    r.row_ptr[c.totals[0]] = c.totals[2];
+    r.col_ptr[c.totals[1]] = c.totals[2];
+  }
+  if (t < m) {
+    int i = (int)t;
+    if (!d.row_on[i]) return;
+    int ri = c.row_new[i];
+    double k = d.row_out[i].v0;  // constant of the removed columns
+    double l = d.lhs[i], u = d.rhs[i];
+    double nl = is_inf(l) ? l : pos0(l - k);
+    double nu = is_inf(u) ? u : pos0(u - k);
+    int p0 = c.eflag[d.rp[i]], p1 = c.eflag[d.rp[i + 1]];
+    int len = p1 - p0;
+    r.row_map[ri] = i;
+    r.lhs[ri] = nl;
+    r.rhs[ri] = nu;
+    r.row_ptr[ri] = p0;
+    r.row_class[ri] = len == 1 ? 1 : len == 2 ? (nl == nu ? 2 : 3) : 0;
+    return;
+  }
+  if (t >= m + n) return;
+  int j = (int)(t - m);
+  double2 b = d.bnd[j];
+  if (b.x == b.y) return;
+  int rj = c.col_new[j];
+  int q0 = c.qflag[d.cp[j]], q1 = c.qflag[d.cp[j + 1]];
+  int len = q1 - q0;
+  r.col_map[rj] = j;
+  r.lb[rj] = b.x;
+  r.ub[rj] = b.y;
+  r.c[rj] = d.c[j];
+  r.col_ptr[rj] = q0;
+  bool fr = is_inf(b.x) && is_inf(b.y);
+  r.col_class[rj] = len == 1 ? (fr ? 1 : 2) : len == 2 ? 3 : 0;
+}
+
+void compact_flags(const Dev& d, const CompactScratch& c, hipStream_t s) {
+  int64_t t = d.nnz + 1;
+  if (d.m > t) t = d.m;
+  if (d.n > t) t = d.n;
+  int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_cmp_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c);
+  scan_excl(c.row_new, c.row_new, d.m, c.totals + 0, c.ws, s);
+  scan_excl(c.col_new, c.col_new, d.n, c.totals + 1, c.ws, s);
+  scan_excl(c.eflag, c.eflag, d.nnz + 1, c.totals + 2, c.ws, s);
+  scan_excl(c.qflag, c.qflag, d.nnz + 1, c.totals + 3, c.ws, s);
+}
+
+void compact_write(const Dev& d, const CompactScratch& c, const Reduced& r, double obj_offset, hipStream_t s) {
+  pairwise_sum(c.terms, d.n, c.pws, c.pws + 1, s);
+  hipLaunchKernelGGL(k_cmp_offset, dim3(1), dim3(64), 0, s, (const double*)c.pws, obj_offset, c.offset);
+  if (d.nnz > 0) {
+    int64_t blocks = (d.nnz + PSL_BLOCK - 1) / PSL_BLOCK;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_cmp_gather, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c, r);
+  }
+  int64_t t = (int64_t)d.m + d.n;
+  if (t < 1) t = 1;
+  hipLaunchKernelGGL(k_cmp_fill, dim3((unsigned)((t + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d, c, r);
+}
+
+}  // namespace psl

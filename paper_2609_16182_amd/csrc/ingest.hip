@@ -1,0 +1,269 @@
+// ingest.hip -- validation, canonicalisation, the transposed copy of A, row
+// binning and the input fixings ("round 0").
+//
+// The paper keeps A together with its transpose (section 3.2, "Internal data
+// structures"). The transpose is built here by a stable radix sort of the CSR
+// positions by column, so the rows of every column come out ascending.
+#include "psl_kern.h"
+#include "sweep.h"
+
+namespace psl {
+
+enum : int32_t {
+  ERR_ROWPTR = 1, ERR_COLIDX = 2, ERR_COEF = 4, ERR_SIDE = 8, ERR_BOUND = 16, ERR_COST = 32
+};
+
+__device__ __forceinline__ void report(const Dev& d, int32_t bit, int64_t pos) {
+  atomicOr(&d.flags->error, bit);
+  atomicMin((long long*)&d.flags->error_pos, (long long)pos);
+}
+
+__device__ __forceinline__ double canon_inf(double v, double inf_value) {
+  if (v >= inf_value) return __builtin_huge_val();
+  if (v <= -inf_value) return -__builtin_huge_val();
+  return pos0(v);
+}
+
+__global__ void k_check_rows(Dev d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.m) return;
+  int32_t a = d.rp[i], b = d.rp[i + 1];
+  if ((i == 0 && a != 0) || a < 0 || b < a || (int64_t)b > d.nnz || (i == d.m - 1 && (int64_t)b != d.nnz))
+    report(d, ERR_ROWPTR, i);
+  double l = d.lhs[i], r = d.rhs[i];
+  double iv = d.cfg.inf_value;
+  if (__builtin_isnan(l) || __builtin_isnan(r) || l >= iv || r <= -iv) report(d, ERR_SIDE, i);
+  d.lhs[i] = canon_inf(l, iv);
+  d.rhs[i] = canon_inf(r, iv);
+}
+
+__global__ void k_check_cols(Dev d, const double* lb_in, const double* ub_in, double* c_mut) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d.n) return;
+  double l = lb_in[j], u = ub_in[j], c = c_mut[j];
+  double iv = d.cfg.inf_value;
+  if (__builtin_isnan(l) || __builtin_isnan(u) || l >= iv || u <= -iv) report(d, ERR_BOUND, j);
+  if (!__builtin_isfinite(c)) report(d, ERR_COST, j);
+  d.bnd[j] = make_double2(canon_inf(l, iv), canon_inf(u, iv));
+  c_mut[j] = pos0(c);
+}
+
+// rowid1[e] counts the rows ending at position e; its exclusive scan then
+// gives, at index p + 1, the row holding CSR position p.
+__global__ void k_row_ends(Dev d, int32_t* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.m) return;
+  atomicAdd(&cnt[d.rp[i + 1]], 1);
+}
+
+__global__ void k_check_entries(Dev d, const int32_t* rowid1) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < d.nnz; p += (int64_t)gridDim.x * blockDim.x) {
+    int row = rowid1[p + 1];
+    int j = d.ci[p];
+    if (j < 0 || j >= d.n || (p > d.rp[row] && d.ci[p - 1] >= j)) report(d, ERR_COLIDX, p);
+    double a = d.va[p];
+    if (!__builtin_isfinite(a) || a == 0.0) report(d, ERR_COEF, p);
+  }
+}
+
+void launch_check_rows(const Dev& d, hipStream_t s) {
+  if (d.m == 0) return;
+  hipLaunchKernelGGL(k_check_rows, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d);
+}
+
+void check_cols(const Dev& d, const double* lb_in, const double* ub_in, double* c_mut, hipStream_t s) {
+  if (d.n == 0) return;
+  hipLaunchKernelGGL(k_check_cols, dim3((d.n + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, lb_in, ub_in,
+                     c_mut);
+}
+
+void build_rowid(const Dev& d, IngestScratch& sc, hipStream_t s) {
+  fill_i32(sc.rowid1, 0, d.nnz + 1, s);
+  if (d.m > 0)
+    hipLaunchKernelGGL(k_row_ends, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, sc.rowid1);
+  scan_excl(sc.rowid1, sc.rowid1, d.nnz + 1, nullptr, sc.ws, s);
+}
+
+void launch_check_entries(const Dev& d, const int32_t* rowid1, hipStream_t s) {
+  if (d.nnz == 0) return;
+  int64_t blocks = (d.nnz + PSL_BLOCK - 1) / PSL_BLOCK;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_check_entries, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, rowid1);
+}
+
+// ---------------------------------------------------------------------------
+// transposed copy
+// ---------------------------------------------------------------------------
+__global__ void k_csc_gather(Dev d, const int32_t* perm, const int32_t* rowid1, int32_t* ri, double* cva) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < d.nnz; q += (int64_t)gridDim.x * blockDim.x) {
+    int p = perm ? perm[q] : (int)q;
+    ri[q] = rowid1[p + 1];
+    cva[q] = d.va[p];
+  }
+}
+
+// cp[j] = first position of column j in the column-sorted keys
+__global__ void k_col_ptr(Dev d, const uint32_t* keys, int32_t* cp) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > d.n) return;
+  int64_t lo = 0, hi = d.nnz;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < j) lo = mid + 1;
+    else hi = mid;
+  }
+  cp[j] = (int32_t)lo;
+}
+
+__global__ void k_col_len(Dev d, const int32_t* cp, int32_t* col_len) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d.n) return;
+  col_len[j] = cp[j + 1] - cp[j];
+}
+
+// Returns the column of every position of the transposed copy (the sorted
+// keys), which compaction uses.
+const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, int32_t* col_len, IngestScratch& sc,
+                          hipStream_t s) {
+  int bits = 0;
+  while (bits < 31 && ((int64_t)1 << bits) < (int64_t)d.n) ++bits;
+  const uint32_t* kin = (const uint32_t*)d.ci;
+  const int32_t* vin = nullptr;
+  uint32_t* kb[2] = {sc.k0, sc.k1};
+  int32_t* vb[2] = {sc.v0, sc.v1};
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    int b = bits - shift < 8 ? bits - shift : 8;
+    radix_pass(kin, vin, kb[cur], vb[cur], d.nnz, shift, b, sc.ws, s);
+    kin = kb[cur];
+    vin = vb[cur];
+    cur ^= 1;
+  }
+  if (d.nnz > 0) {
+    int64_t blocks = (d.nnz + PSL_BLOCK - 1) / PSL_BLOCK;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_csc_gather, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, vin, sc.rowid1, ri, cva);
+  }
+  hipLaunchKernelGGL(k_col_ptr, dim3((d.n + 1 + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, kin, cp);
+  if (d.n > 0)
+    hipLaunchKernelGGL(k_col_len, dim3((d.n + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d,
+                       (const int32_t*)cp, col_len);
+  return kin;
+}
+
+// ---------------------------------------------------------------------------
+// row bins by CSR length
+// ---------------------------------------------------------------------------
+__global__ void k_bin_keys(Dev d, int32_t t_wave, int32_t t_block, uint32_t* keys, int32_t* counts) {
+  __shared__ int c[NBINS];
+  if (threadIdx.x < NBINS) c[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.m) {
+    int len = d.rp[i + 1] - d.rp[i];
+    uint32_t b = len <= 4 ? BIN_G4 : len <= 16 ? BIN_G16 : len <= t_wave ? BIN_WAVE : len <= t_block ? BIN_BLOCK : BIN_DENSE;
+    keys[i] = b;
+    atomicAdd(&c[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < NBINS && c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], c[threadIdx.x]);
+}
+
+void build_bins(const Dev& d, const int32_t* thresholds, int32_t* bin_rows, int32_t* counts, IngestScratch& sc,
+                hipStream_t s) {
+  fill_i32(counts, 0, NBINS, s);
+  if (d.m == 0) return;
+  hipLaunchKernelGGL(k_bin_keys, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, thresholds[0],
+                     thresholds[1], sc.k0, counts);
+  radix_pass(sc.k0, nullptr, sc.k1, bin_rows, d.m, 0, 3, sc.ws, s);
+}
+
+// ---------------------------------------------------------------------------
+// state initialisation and round 0 (input fixings, crossed bounds / sides)
+// ---------------------------------------------------------------------------
+__global__ void k_init_state(Dev d) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < d.m) {
+    d.row_on[t] = 1;
+    d.row_code[t] = RC_KEEP;
+  }
+  if (t < d.n) {
+    double2 b = d.bnd[t];
+    d.bkey[2 * t] = dkey(b.x);
+    d.bkey[2 * t + 1] = dkey(b.y);
+    d.src[2 * t] = 0x7FFFFFFF;
+    d.src[2 * t + 1] = 0x7FFFFFFF;
+    d.col_code[t] = 0;
+  }
+  if (t == 0) {
+    Flags f;
+    f.infeasible = f.unbounded = f.error = f.merged = 0;
+    f.cand_count = f.round_total = f.vlist_count = f.pad = 0;
+    f.error_pos = 0x7FFFFFFFFFFFFFFFLL;
+    *d.flags = f;
+  }
+}
+
+void launch_init_state(const Dev& d, hipStream_t s) {
+  int64_t t = d.m > d.n ? d.m : d.n;
+  if (t < 1) t = 1;
+  hipLaunchKernelGGL(k_init_state, dim3((unsigned)((t + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d);
+}
+
+__global__ void k_round0_count(Dev d) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t m = d.m, n = d.n;
+  if (t < m) {
+    d.cnt[t] = 0;
+    double l = d.lhs[t], r = d.rhs[t];
+    if (!is_inf(l) && !is_inf(r) && l > r + tol_of(d.cfg, r)) atomicOr(&d.flags->infeasible, 1);
+    return;
+  }
+  if (t >= m + n) return;
+  int j = (int)(t - m);
+  double2 b = d.bnd[j];
+  int k = 0;
+  if (!is_inf(b.x) && !is_inf(b.y)) {
+    if (b.x > b.y + tol_of(d.cfg, b.y)) atomicOr(&d.flags->infeasible, 1);
+    if (b.y - b.x <= d.cfg.fix_tol * mx1(b.x)) k = 1;
+  }
+  d.cnt[t] = k;
+}
+
+__global__ void k_round0_emit(Dev d, int64_t base) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t m = d.m, n = d.n;
+  if (t < m || t >= m + n) return;
+  int j = (int)(t - m);
+  double2 b = d.bnd[j];
+  if (is_inf(b.x) || is_inf(b.y) || !(b.y - b.x <= d.cfg.fix_tol * mx1(b.x))) return;
+  Record r;
+  r.type = REC_FIX_COL;
+  r.side = 0;
+  r.round = 0;
+  r.i = -1;
+  r.j = j;
+  r.k = -1;
+  r.v[0] = b.x;
+  r.v[1] = d.c[j];
+  r.v[2] = 0.0;
+  r.v[3] = 0.0;
+  d.rec[base + d.off[t]] = r;
+  d.bnd[j] = make_double2(b.x, b.x);
+  d.bkey[2 * (int64_t)j + 1] = dkey(b.x);
+}
+
+void launch_round0_count(const Dev& d, hipStream_t s) {
+  int64_t t = (int64_t)d.m + d.n;
+  if (t == 0) return;
+  hipLaunchKernelGGL(k_round0_count, dim3((unsigned)((t + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d);
+}
+
+void launch_round0_emit(const Dev& d, int64_t base, hipStream_t s) {
+  int64_t t = (int64_t)d.m + d.n;
+  if (t == 0) return;
+  hipLaunchKernelGGL(k_round0_emit, dim3((unsigned)((t + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d,
+                     base);
+}
+
+}  // namespace psl

@@ -1,0 +1,392 @@
+// parallel.hip -- parallel rows (section 3.2, "Parallel rows").
+//
+// Two rows are parallel when a_i = lambda a_k. Every active row with at least
+// two active columns is hashed independently (two levels: the stored sparsity
+// pattern, then the coefficients normalised by the row's first stored
+// coefficient and quantised), the keys go into an open-addressing table, and
+// each row of a key group is checked against the group's leader: the lowest
+// equality row of the group, else its lowest row. Verified rows are removed
+// and the leader's sides become the intersection of the mapped sides; the row
+// giving each final side is the lowest such row.
+#include "psl_kern.h"
+#include "sweep.h"
+
+namespace psl {
+
+__device__ __forceinline__ void hash_terms(const Dev& d, int64_t p, bool v, double a0, unsigned long long& h1,
+                                           unsigned long long& h2, bool& act) {
+  h1 = h2 = 0;
+  act = false;
+  if (!v) return;
+  int j = d.ci[p];
+  double a = d.va[p];
+  double2 b = d.bnd[j];
+  act = b.x != b.y;
+  unsigned long long cj = splitmix((unsigned long long)(uint32_t)j);
+  h1 = cj;
+  h2 = splitmix(cj ^ quantize(a / a0));
+}
+
+__device__ __forceinline__ unsigned long long row_key(int len, unsigned long long s1, unsigned long long s2) {
+  return (splitmix((unsigned long long)len + s1) ^ s2) | 1ULL;
+}
+
+__device__ __forceinline__ void par_insert(const Dev& d, const ParScratch& P, int row, unsigned long long key) {
+  unsigned long long mask = (unsigned long long)P.cap - 1;
+  unsigned long long h = splitmix(key) & mask;
+  for (int64_t probe = 0; probe < P.cap; ++probe) {
+    unsigned long long old = atomicCAS(&P.table[h].key, 0ULL, key);
+    if (old == 0ULL || old == key) break;
+    h = (h + 1) & mask;
+  }
+  bool eq = d.lhs[row] == d.rhs[row];
+  atomicMin(&P.table[h].leader, (eq ? 0u : 0x80000000u) | (unsigned)row);
+  atomicAdd(&P.table[h].count, 1u);
+  P.slot[row] = (int)h;
+}
+
+__global__ void k_par_reset(Dev d, ParScratch P) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P.cap; t += stride) {
+    HashSlot z;
+    z.key = 0;
+    z.leader = 0xFFFFFFFFu;
+    z.count = 0;
+    P.table[t] = z;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += stride) {
+    P.slot[i] = -1;
+    P.lead[i] = -1;
+    P.is_leader[i] = 0;
+    P.side_key[2 * i] = dkey(d.lhs[i]);
+    P.side_key[2 * i + 1] = dkey(d.rhs[i]);
+    P.side_src[2 * i] = 0x7FFFFFFF;
+    P.side_src[2 * i + 1] = 0x7FFFFFFF;
+  }
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 3 * (int64_t)d.ndense; k += stride)
+    P.hacc[k] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.flags->vlist_count = 0;
+    d.flags->merged = 0;
+  }
+}
+
+// G-lane groups, one pass (rows of at most G entries)
+template <int G>
+__device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, int bin, int lblock) {
+  int gid = lblock * (PSL_BLOCK / G) + (int)(threadIdx.x / G);
+  int count = d.bin_off[bin + 1] - d.bin_off[bin];
+  bool vr = gid < count;
+  int row = vr ? d.bin_rows[d.bin_off[bin] + gid] : 0;
+  int gl = threadIdx.x & (G - 1);
+  int64_t s0 = 0;
+  int len = 0;
+  bool on = false;
+  if (vr) {
+    s0 = d.rp[row];
+    len = d.rp[row + 1] - (int)s0;
+    on = d.row_on[row] != 0;
+  }
+  double a0 = on && len > 0 ? d.va[s0] : 1.0;
+  unsigned long long h1, h2;
+  bool act;
+  hash_terms(d, s0 + gl, on && gl < len, a0, h1, h2, act);
+  h1 = group_sum_u64<G>(h1);
+  h2 = group_sum_u64<G>(h2);
+  int L = __popcll(__ballot(act) & group_mask<G>());
+  if (vr && on && gl == 0 && L >= 2) par_insert(d, P, row, row_key(len, h1, h2));
+}
+
+// one wavefront per row, any length
+__device__ __forceinline__ void hash_wave_row(const Dev& d, const ParScratch& P, int row) {
+  int lane = lane_id();
+  int64_t s0 = d.rp[row];
+  int len = d.rp[row + 1] - (int)s0;
+  if (!d.row_on[row] || len < 2) return;
+  double a0 = d.va[s0];
+  unsigned long long s1 = 0, s2 = 0;
+  int L = 0;
+  for (int q0 = 0; q0 < len; q0 += PSL_WAVE) {
+    int q = q0 + lane;
+    unsigned long long h1, h2;
+    bool act;
+    hash_terms(d, s0 + q, q < len, a0, h1, h2, act);
+    s1 += h1;
+    s2 += h2;
+    L += __popcll(__ballot(act));
+  }
+  s1 = group_sum_u64<PSL_WAVE>(s1);
+  s2 = group_sum_u64<PSL_WAVE>(s2);
+  if (lane == 0 && L >= 2) par_insert(d, P, row, row_key(len, s1, s2));
+}
+
+// dense rows: one workgroup per chunk, accumulated with 64-bit atomic adds
+__device__ __forceinline__ void hash_dense_chunk(const Dev& d, const ParScratch& P, int chunk, int chunk_len) {
+  DenseChunk ch = d.dchunk[chunk];
+  int row = ch.row;
+  if (!d.row_on[row]) return;
+  int64_t s0 = d.rp[row];
+  int len = d.rp[row + 1] - (int)s0;
+  double a0 = d.va[s0];
+  unsigned long long s1 = 0, s2 = 0;
+  int L = 0;
+  int end = min(len, ch.first + chunk_len);
+  for (int q0 = ch.first; q0 < end; q0 += PSL_BLOCK) {
+    int q = q0 + (int)threadIdx.x;
+    unsigned long long h1, h2;
+    bool act;
+    hash_terms(d, s0 + q, q < end, a0, h1, h2, act);
+    s1 += h1;
+    s2 += h2;
+    L += act ? 1 : 0;
+  }
+  s1 = group_sum_u64<PSL_WAVE>(s1);
+  s2 = group_sum_u64<PSL_WAVE>(s2);
+  unsigned long long l64 = group_sum_u64<PSL_WAVE>((unsigned long long)L);
+  if (lane_id() == 0) {
+    atomicAdd(&P.hacc[3 * (int64_t)ch.drow], s1);
+    atomicAdd(&P.hacc[3 * (int64_t)ch.drow + 1], s2);
+    atomicAdd(&P.hacc[3 * (int64_t)ch.drow + 2], l64);
+  }
+}
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_par_hash(Dev d, ParScratch P, SweepGrid g, int chunk_len) {
+  int b = blockIdx.x;
+  if (b < g.nb[0]) {
+    hash_groups<4>(d, P, BIN_G4, b);
+    return;
+  }
+  b -= g.nb[0];
+  if (b < g.nb[1]) {
+    hash_groups<16>(d, P, BIN_G16, b);
+    return;
+  }
+  b -= g.nb[1];
+  if (b < g.nb[2]) {
+    int wid = b * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6);
+    if (wid < d.bin_off[BIN_WAVE + 1] - d.bin_off[BIN_WAVE]) hash_wave_row(d, P, d.bin_rows[d.bin_off[BIN_WAVE] + wid]);
+    return;
+  }
+  b -= g.nb[2];
+  if (b < g.nb[3]) {
+    // workgroup-length rows: four rows per workgroup, one per wavefront
+    int wid = b * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6);
+    if (wid < d.bin_off[BIN_BLOCK + 1] - d.bin_off[BIN_BLOCK])
+      hash_wave_row(d, P, d.bin_rows[d.bin_off[BIN_BLOCK] + wid]);
+    return;
+  }
+  b -= g.nb[3];
+  if (b < g.nb[4]) hash_dense_chunk(d, P, b, chunk_len);
+}
+
+__global__ void k_par_dense_insert(Dev d, ParScratch P) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.ndense) return;
+  int row = d.drow[k].row;
+  if (!d.row_on[row]) return;
+  int len = d.rp[row + 1] - d.rp[row];
+  if ((int64_t)P.hacc[3 * (int64_t)k + 2] >= 2)
+    par_insert(d, P, row, row_key(len, P.hacc[3 * (int64_t)k], P.hacc[3 * (int64_t)k + 1]));
+}
+
+// rows of a key group (other than its leader) go to the verify list
+__global__ void k_par_vlist(Dev d, ParScratch P) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool pred = false;
+  if (i < d.m) {
+    int s = P.slot[i];
+    if (s >= 0) {
+      HashSlot h = P.table[s];
+      pred = h.count >= 2 && (int)(h.leader & 0x7FFFFFFFu) != (int)i;
+    }
+  }
+  unsigned long long mask = __ballot(pred);
+  if (mask == 0) return;
+  int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(&d.flags->vlist_count, (int)__popcll(mask));
+  base = __shfl(base, leader, PSL_WAVE);
+  if (pred) P.vlist[base + __popcll(mask & lanemask_lt())] = (int)i;
+}
+
+__device__ __forceinline__ void mapped_sides(const Dev& d, int r, int L, double& lam, double& ml, double& mu) {
+  lam = d.va[d.rp[r]] / d.va[d.rp[L]];
+  double lr = d.lhs[r], rr = d.rhs[r];
+  if (lam > 0) {
+    ml = lr / lam;
+    mu = rr / lam;
+  } else {
+    ml = rr / lam;
+    mu = lr / lam;
+  }
+  ml = pos0(ml);
+  mu = pos0(mu);
+}
+
+// one wavefront per listed row: same stored pattern, proportional coefficients
+__global__ void __launch_bounds__(PSL_BLOCK) k_par_verify(Dev d, ParScratch P) {
+  int nv = d.flags->vlist_count;
+  int lane = lane_id();
+  int wstride = gridDim.x * (PSL_BLOCK / PSL_WAVE);
+  for (int k = blockIdx.x * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6); k < nv; k += wstride) {
+    int r = P.vlist[k];
+    int L = (int)(P.table[P.slot[r]].leader & 0x7FFFFFFFu);
+    int64_t sr = d.rp[r], sl = d.rp[L];
+    int len = d.rp[r + 1] - (int)sr;
+    bool ok = len == d.rp[L + 1] - (int)sl;
+    if (ok) {
+      double r0 = d.va[sr], l0 = d.va[sl];
+      for (int q0 = 0; q0 < len && ok; q0 += PSL_WAVE) {
+        int q = q0 + lane;
+        bool bad = false;
+        if (q < len) {
+          if (d.ci[sr + q] != d.ci[sl + q]) {
+            bad = true;
+          } else {
+            double a = d.va[sr + q] / r0, b = d.va[sl + q] / l0;
+            double scale = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+            bad = !(fabs(a - b) <= d.cfg.par_tol * scale);
+          }
+        }
+        ok = __ballot(bad) == 0;
+      }
+    }
+    if (ok && lane == 0) {
+      double lam, ml, mu;
+      mapped_sides(d, r, L, lam, ml, mu);
+      P.lead[r] = L;
+      P.is_leader[L] = 1;
+      atomicMax(&P.side_key[2 * (int64_t)L], dkey(ml));
+      atomicMin(&P.side_key[2 * (int64_t)L + 1], dkey(mu));
+    }
+  }
+}
+
+// lowest row giving each final side of a leader (the leader counts itself)
+__global__ void k_par_src(Dev d, ParScratch P) {
+  int nv = d.flags->vlist_count;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nv; k += gridDim.x * blockDim.x) {
+    int r = P.vlist[k];
+    int L = P.lead[r];
+    if (L < 0) continue;
+    double lam, ml, mu;
+    mapped_sides(d, r, L, lam, ml, mu);
+    double lo = dunkey(P.side_key[2 * (int64_t)L]);
+    double up = dunkey(P.side_key[2 * (int64_t)L + 1]);
+    if (ml == lo) atomicMin(&P.side_src[2 * (int64_t)L], r);
+    if (mu == up) atomicMin(&P.side_src[2 * (int64_t)L + 1], r);
+    if (d.lhs[L] == lo) atomicMin(&P.side_src[2 * (int64_t)L], L);
+    if (d.rhs[L] == up) atomicMin(&P.side_src[2 * (int64_t)L + 1], L);
+  }
+}
+
+__device__ __forceinline__ bool leader_sides(const Dev& d, const ParScratch& P, int i, double& lo, double& up,
+                                             bool& infeasible) {
+  lo = dunkey(P.side_key[2 * (int64_t)i]);
+  up = dunkey(P.side_key[2 * (int64_t)i + 1]);
+  infeasible = false;
+  if (!is_inf(lo) && !is_inf(up) && lo > up) {
+    if (lo > up + tol_of(d.cfg, up)) infeasible = true;
+    else lo = up;
+  }
+  return lo != d.lhs[i] || up != d.rhs[i];
+}
+
+__global__ void k_par_count(Dev d, ParScratch P) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.m) return;
+  int k = 0;
+  if (P.lead[i] >= 0) {
+    k = 1;
+    d.flags->merged = 1;
+  } else if (P.is_leader[i]) {
+    double lo, up;
+    bool inf;
+    if (leader_sides(d, P, (int)i, lo, up, inf)) k = 1;
+    if (inf) atomicOr(&d.flags->infeasible, 1);
+  }
+  d.cnt[i] = k;
+}
+
+__global__ void k_par_emit(Dev d, ParScratch P, int64_t base, int round) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.m) return;
+  int i = (int)t;
+  Record r;
+  r.side = 0;
+  r.round = (uint16_t)round;
+  if (P.lead[i] >= 0) {
+    int L = P.lead[i];
+    double lam, ml, mu;
+    mapped_sides(d, i, L, lam, ml, mu);
+    r.type = REC_PARALLEL_ROW;
+    r.i = i;
+    r.j = -1;
+    r.k = L;
+    r.v[0] = lam;
+    r.v[1] = d.lhs[i];
+    r.v[2] = d.rhs[i];
+    r.v[3] = 0.0;
+    d.rec[base + d.off[t]] = r;
+    d.row_on[i] = 0;
+    for (int64_t p = d.rp[i]; p < d.rp[i + 1]; ++p) {
+      int j = d.ci[p];
+      double2 b = d.bnd[j];
+      if (b.x != b.y) atomicSub(&d.col_len[j], 1);
+    }
+  } else if (P.is_leader[i]) {
+    double lo, up;
+    bool inf;
+    if (!leader_sides(d, P, i, lo, up, inf)) return;
+    r.type = REC_LEADER_SIDES;
+    r.i = i;
+    r.j = P.side_src[2 * (int64_t)i];
+    r.k = P.side_src[2 * (int64_t)i + 1];
+    r.v[0] = d.lhs[i];
+    r.v[1] = d.rhs[i];
+    r.v[2] = lo;
+    r.v[3] = up;
+    d.rec[base + d.off[t]] = r;
+    d.lhs[i] = lo;
+    d.rhs[i] = up;
+  }
+}
+
+// ---------------------------------------------------------------------------
+void launch_par_reset(const Dev& d, const ParScratch& p, hipStream_t s) {
+  int64_t t = p.cap > d.m ? p.cap : d.m;
+  int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_par_reset, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, p);
+}
+
+void launch_par_hash(const Dev& d, const ParScratch& p, const SweepGrid& g, hipStream_t s) {
+  SweepGrid h = g;
+  // workgroup-length rows are hashed four per workgroup
+  int nblk = d.bin_off[BIN_BLOCK + 1] - d.bin_off[BIN_BLOCK];
+  h.nb[3] = (nblk + 3) / 4;
+  int total = h.nb[0] + h.nb[1] + h.nb[2] + h.nb[3] + h.nb[4];
+  if (total > 0)
+    hipLaunchKernelGGL(k_par_hash, dim3(total), dim3(PSL_BLOCK), 0, s, d, p, h, dense_chunk_size());
+  if (d.ndense > 0)
+    hipLaunchKernelGGL(k_par_dense_insert, dim3((d.ndense + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);
+  if (d.m > 0) hipLaunchKernelGGL(k_par_vlist, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);
+}
+
+void launch_par_verify(const Dev& d, const ParScratch& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_par_verify, dim3(2048), dim3(PSL_BLOCK), 0, s, d, p);
+  hipLaunchKernelGGL(k_par_src, dim3(1024), dim3(PSL_BLOCK), 0, s, d, p);
+}
+
+void launch_par_count(const Dev& d, const ParScratch& p, hipStream_t s) {
+  if (d.m == 0) return;
+  hipLaunchKernelGGL(k_par_count, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);
+}
+
+void launch_par_emit(const Dev& d, const ParScratch& p, int64_t base, int round, hipStream_t s) {
+  if (d.m == 0) return;
+  hipLaunchKernelGGL(k_par_emit, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p, base, round);
+}
+
+}  // namespace psl

@@ -1,0 +1,235 @@
+// primitives.hip -- device-wide scan, stable radix pass, fill and canonical
+// pairwise array sum. Plain reduce-then-scan; every result is independent of
+// scheduling (integer sums, and pairwise trees over aligned power-of-two
+// blocks).
+#include "psl_kern.h"
+
+namespace psl {
+
+#define SCAN_ITEMS 8
+#define SCAN_TILE (PSL_BLOCK * SCAN_ITEMS)
+
+// exclusive scan of one int per thread across the 256-thread block
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+  __shared__ int wsum[PSL_BLOCK / PSL_WAVE];
+  int lane = lane_id(), w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < PSL_WAVE; o <<= 1) {
+    int y = __shfl_up(x, o, PSL_WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == PSL_WAVE - 1) wsum[w] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < PSL_BLOCK / PSL_WAVE; ++k) {
+    int s = wsum[k];
+    if (k < w) pre += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_scan_tile_sums(const int32_t* in, int64_t n, int32_t* sums) {
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k)
+    if (base + k < n) s += in[base + k];
+  int tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_scan_tile_apply(const int32_t* in, int32_t* out, int64_t n,
+                                                               const int32_t* tile_off, int32_t* total) {
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0;
+    s += v[k];
+  }
+  int tot;
+  int pre = block_excl_scan(s, &tot);
+  int off = tile_off ? tile_off[blockIdx.x] : 0;
+  int run = off + pre;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
+}
+
+__global__ void k_fill_i32(int32_t* out, int32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = v;
+}
+
+size_t scan_ws_ints(int64_t n) {
+  int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (nb <= 1) return 0;
+  return (size_t)nb + scan_ws_ints(nb);
+}
+
+void fill_i32(int32_t* out, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + PSL_BLOCK - 1) / PSL_BLOCK;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, out, v, n);
+}
+
+void scan_excl(const int32_t* in, int32_t* out, int64_t n, int32_t* total, int32_t* ws, hipStream_t s) {
+  if (n <= 0) {
+    if (total) fill_i32(total, 0, 1, s);
+    return;
+  }
+  int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (nb == 1) {
+    hipLaunchKernelGGL(k_scan_tile_apply, dim3(1), dim3(PSL_BLOCK), 0, s, in, out, n, (const int32_t*)nullptr, total);
+    return;
+  }
+  int32_t* sums = ws;
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nb), dim3(PSL_BLOCK), 0, s, in, n, sums);
+  scan_excl(sums, sums, nb, nullptr, ws + nb, s);
+  hipLaunchKernelGGL(k_scan_tile_apply, dim3((unsigned)nb), dim3(PSL_BLOCK), 0, s, in, out, n,
+                     (const int32_t*)sums, total);
+}
+
+// ---------------------------------------------------------------------------
+// stable radix pass
+// ---------------------------------------------------------------------------
+
+#define RX_ROUNDS 8
+#define RX_TILE (PSL_BLOCK * RX_ROUNDS)
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_rx_count(const uint32_t* keys, int64_t n, int shift, uint32_t mask,
+                                                        int32_t* hist, int ntiles) {
+  __shared__ int c[256];
+  int t = threadIdx.x;
+  c[t] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RX_TILE;
+  for (int r = 0; r < RX_ROUNDS; ++r) {
+    int64_t idx = base + r * PSL_BLOCK + t;
+    if (idx < n) atomicAdd(&c[(keys[idx] >> shift) & mask], 1);
+  }
+  __syncthreads();
+  if ((uint32_t)t <= mask) hist[(int64_t)t * ntiles + blockIdx.x] = c[t];
+}
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_rx_scatter(const uint32_t* kin, const int32_t* vin, uint32_t* kout,
+                                                          int32_t* vout, int64_t n, int shift, uint32_t mask,
+                                                          const int32_t* hoff, int ntiles) {
+  __shared__ int tile_cnt[256];
+  __shared__ int wcnt[PSL_BLOCK / PSL_WAVE][256];
+  int t = threadIdx.x, w = t >> 6;
+  tile_cnt[t] = 0;
+#pragma unroll
+  for (int k = 0; k < PSL_BLOCK / PSL_WAVE; ++k) wcnt[k][t] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RX_TILE;
+  for (int r = 0; r < RX_ROUNDS; ++r) {
+    int64_t idx = base + r * PSL_BLOCK + t;
+    bool valid = idx < n;
+    uint32_t key = valid ? kin[idx] : 0u;
+    int32_t val = valid ? (vin ? vin[idx] : (int32_t)idx) : 0;
+    uint32_t d = (key >> shift) & mask;
+    // lanes of this wave holding the same digit
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (d >> b) & 1u;
+      unsigned long long bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    int rank = __popcll(peers & lanemask_lt());
+    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    int pos = 0;
+    if (valid) {
+      int before = tile_cnt[d];
+      for (int k = 0; k < w; ++k) before += wcnt[k][d];
+      pos = hoff[(int64_t)d * ntiles + blockIdx.x] + before + rank;
+    }
+    __syncthreads();
+    {
+      int sum = 0;
+#pragma unroll
+      for (int k = 0; k < PSL_BLOCK / PSL_WAVE; ++k) {
+        sum += wcnt[k][t];
+        wcnt[k][t] = 0;
+      }
+      tile_cnt[t] += sum;
+    }
+    __syncthreads();
+    if (valid) {
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+  }
+}
+
+size_t radix_ws_ints(int64_t n) {
+  int64_t ntiles = (n + RX_TILE - 1) / RX_TILE;
+  if (ntiles < 1) ntiles = 1;
+  return (size_t)(256 * ntiles) + scan_ws_ints(256 * ntiles);
+}
+
+void radix_pass(const uint32_t* keys_in, const int32_t* vals_in, uint32_t* keys_out, int32_t* vals_out,
+                int64_t n, int shift, int bits, int32_t* ws, hipStream_t s) {
+  if (n <= 0) return;
+  int ntiles = (int)((n + RX_TILE - 1) / RX_TILE);
+  uint32_t mask = (1u << bits) - 1u;
+  int32_t* hist = ws;
+  int32_t* sws = ws + 256 * (int64_t)ntiles;
+  hipLaunchKernelGGL(k_rx_count, dim3(ntiles), dim3(PSL_BLOCK), 0, s, keys_in, n, shift, mask, hist, ntiles);
+  scan_excl(hist, hist, (int64_t)(mask + 1) * ntiles, nullptr, sws, s);
+  hipLaunchKernelGGL(k_rx_scatter, dim3(ntiles), dim3(PSL_BLOCK), 0, s, keys_in, vals_in, keys_out, vals_out, n,
+                     shift, mask, (const int32_t*)hist, ntiles);
+}
+
+// ---------------------------------------------------------------------------
+// canonical pairwise sum of an array
+// ---------------------------------------------------------------------------
+
+#define PW_TILE 2048
+
+// Each block sums the aligned chunk [2048 b, 2048 b + 2048): eight contiguous
+// leaves per thread (tree of 8), a butterfly over the wave (tree of 64 such
+// groups), then the four wave sums as (w0 + w1) + (w2 + w3).
+__global__ void __launch_bounds__(PSL_BLOCK) k_pw_chunks(const double* x, int64_t n, double* out) {
+  __shared__ double ws[PSL_BLOCK / PSL_WAVE];
+  int64_t base = (int64_t)blockIdx.x * PW_TILE + (int64_t)threadIdx.x * 8;
+  double v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = base + k < n ? x[base + k] : 0.0;
+  double s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  s = group_sum<PSL_WAVE>(s);
+  if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+size_t pairwise_ws_doubles(int64_t n) {
+  int64_t nb = (n + PW_TILE - 1) / PW_TILE;
+  if (nb <= 1) return 1;
+  return (size_t)nb + pairwise_ws_doubles(nb);
+}
+
+void pairwise_sum(const double* x, int64_t n, double* out, double* ws, hipStream_t s) {
+  int64_t nb = (n + PW_TILE - 1) / PW_TILE;
+  if (nb <= 1) {
+    hipLaunchKernelGGL(k_pw_chunks, dim3(1), dim3(PSL_BLOCK), 0, s, x, n, out);
+    return;
+  }
+  hipLaunchKernelGGL(k_pw_chunks, dim3((unsigned)nb), dim3(PSL_BLOCK), 0, s, x, n, ws);
+  pairwise_sum(ws, nb, out, ws + nb, s);
+}
+
+}  // namespace psl

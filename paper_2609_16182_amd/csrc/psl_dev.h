@@ -1,0 +1,231 @@
+// psl_dev.h -- device state and device helpers of libpsl (gfx950, wave64).
+//
+// Layout in HBM (one presolver handle):
+//   CSR   rp[m+1] i32, ci[N] i32, va[N] f64              (input, read-only)
+//   CSC   cp[n+1] i32, ri[N] i32, cva[N] f64             (built at ingest)
+//   rows  lhs/rhs[m] f64, row_on[m] u8, row_code[m] u8, row_out[m] 16 B
+//   cols  bnd[n] double2 (lb, ub), bkey[2n] i64 (order-mapped accumulators of
+//         the round's best lb / ub), src[2n] i32, col_len[n] i32, c[n] f64
+//   bins  bin_rows[m] i32 (rows grouped by CSR length, ascending within a bin)
+// A column is removed exactly when lb == ub: a fixed column keeps lb = ub = v,
+// and every active column has ub - lb > fix_tol * max(1, |lb|) >= 0 once a
+// round has run, so the sweep learns a column's state from its bounds alone.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PSL_BLOCK 256
+#define PSL_WAVE 64
+
+namespace psl {
+
+enum : uint8_t {
+  REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
+  REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8
+};
+
+// row decision codes written by the sweep for the current round
+enum : uint8_t { RC_KEEP = 0, RC_EMPTY = 1, RC_REDUNDANT = 2, RC_SINGLETON = 3 };
+
+// column decision bits of a round
+enum : uint8_t {
+  CC_LB = 1, CC_UB = 2, CC_FIX = 4, CC_EMPTY = 8, CC_UNBOUNDED = 16, CC_INFEAS = 32
+};
+
+// row length bins: 4 lanes, 16 lanes, one wave, one workgroup, many workgroups
+enum { BIN_G4 = 0, BIN_G16 = 1, BIN_WAVE = 2, BIN_BLOCK = 3, BIN_DENSE = 4, NBINS = 5 };
+
+struct Record {
+  uint8_t type, side;
+  uint16_t round;
+  int32_t i, j, k;
+  double v[4];
+};
+static_assert(sizeof(Record) == 48, "record layout");
+
+struct RowOut {      // what the sweep leaves for a removed row's record
+  double v0, v1;     // (activity, -) / (min act, max act) / (a_ij, -)
+  int32_t j, pad;
+};
+
+struct Cand {        // a candidate bound that may be the round's final value
+  int32_t js;        // 2*j + side (side 1 = upper)
+  int32_t row;
+  double t;
+};
+
+struct DenseChunk {  // one workgroup-sized slice of a dense row
+  int32_t row, first;  // row index, first CSR position (relative to row start)
+  int32_t drow, pad;   // index of the dense row
+};
+
+struct DensePart {   // partial statistics of one chunk
+  double smin, smax;
+  int32_t nmin, nmax, L, pad;
+};
+
+struct DenseRow {    // per dense row
+  int32_t row, chunk0, nchunk, pad;
+  double minact, maxact;
+  int32_t nmin, nmax, L, keep;
+};
+
+struct Flags {
+  int32_t infeasible, unbounded, error, merged;
+  int32_t cand_count, round_total, vlist_count, pad;
+  int64_t error_pos;
+};
+
+struct Cfg {
+  double feas_tol, fix_tol, min_improve, par_tol, inf_value, coef_tol;
+};
+
+struct HashSlot {
+  unsigned long long key;
+  unsigned int leader;   // (inequality << 31) | row, minimised
+  unsigned int count;
+};
+
+struct Dev {
+  int32_t m, n;
+  int64_t nnz;
+  const int32_t *rp, *ci;
+  const double *va;
+  const int32_t *cp, *ri;
+  const double *cva;
+  double *lhs, *rhs;
+  double2 *bnd;
+  long long *bkey;
+  int32_t *src;
+  const double *c;
+  int32_t *col_len;
+  uint8_t *row_on, *row_code, *col_code;
+  RowOut *row_out;
+  Cand *cand;
+  Flags *flags;
+  int32_t *cnt, *off;
+  Record *rec;
+  const int32_t *bin_rows;
+  int32_t bin_off[NBINS + 1];
+  const DenseChunk *dchunk;
+  DensePart *dpart;
+  DenseRow *drow;
+  int32_t ndense, nchunks;
+  Cfg cfg;
+};
+
+// ---------------------------------------------------------------------------
+// scalar helpers (IEEE double; the library is built with -ffp-contract=off)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double pos0(double x) { return x == 0.0 ? 0.0 : x; }
+__device__ __forceinline__ double mx1(double x) {
+  double a = fabs(x);
+  return a > 1.0 ? a : 1.0;
+}
+__device__ __forceinline__ bool is_inf(double x) { return __builtin_isinf(x); }
+__device__ __forceinline__ double tol_of(const Cfg& c, double x) { return c.feas_tol * mx1(x); }
+
+// order-preserving map double <-> int64 (an involution); -0 never occurs
+__device__ __forceinline__ long long dkey(double x) {
+  long long b = __double_as_longlong(x);
+  return b >= 0 ? b : (b ^ 0x7FFFFFFFFFFFFFFFLL);
+}
+__device__ __forceinline__ double dunkey(long long k) {
+  return __longlong_as_double(k >= 0 ? k : (k ^ 0x7FFFFFFFFFFFFFFFLL));
+}
+
+// contribution of coefficient a on [lb, ub] to the min / max activity
+__device__ __forceinline__ void contrib(double a, double lb, double ub, double& tmin,
+                                       bool& imin, double& tmax, bool& imax) {
+  double bmin = a > 0 ? lb : ub;
+  double bmax = a > 0 ? ub : lb;
+  imin = is_inf(bmin);
+  imax = is_inf(bmax);
+  tmin = imin ? 0.0 : pos0(a * bmin);
+  tmax = imax ? 0.0 : pos0(a * bmax);
+}
+
+// ---------------------------------------------------------------------------
+// wave helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (PSL_WAVE - 1); }
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ double shfl_xor_d(double x, int m) {
+  return __shfl_xor(x, m, PSL_WAVE);
+}
+
+// Sum over aligned groups of G lanes by a butterfly. fl(a + b) is
+// commutative, so both partners compute the same node and after log2(G)
+// steps every lane of the group holds the pairwise tree over its G lanes.
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+#pragma unroll
+  for (int s = 1; s < G; s <<= 1) x = x + shfl_xor_d(x, s);
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ unsigned long long group_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int s = 1; s < G; s <<= 1) {
+    unsigned lo = (unsigned)x, hi = (unsigned)(x >> 32);
+    lo = __shfl_xor(lo, s, PSL_WAVE);
+    hi = __shfl_xor(hi, s, PSL_WAVE);
+    x += ((unsigned long long)hi << 32) | lo;
+  }
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ unsigned long long group_mask() {
+  if (G == 64) return ~0ull;
+  return ((1ull << G) - 1) << (lane_id() & ~(G - 1));
+}
+
+// Pairwise tree over v[0..n) padded with +0 to the next power of two,
+// in place (used for pass and chunk sums held in LDS).
+__device__ __forceinline__ double tree_inplace(double* v, int n) {
+  if (n <= 0) return 0.0;
+  int p = 1;
+  while (p < n) p <<= 1;
+  for (int w = 1; w < p; w <<= 1)
+    for (int i = 0; i + w < n; i += 2 * w) v[i] = v[i] + v[i + w];
+  return v[0];
+}
+
+// Wave-aggregated append of one 16-byte candidate per lane with pred set.
+// Must be reached by all lanes of the wave.
+__device__ __forceinline__ void wave_append(bool pred, const Cand& e, Cand* list, int32_t* counter) {
+  unsigned long long mask = __ballot(pred);
+  if (mask == 0) return;
+  int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, (int)__popcll(mask));
+  base = __shfl(base, leader, PSL_WAVE);
+  if (pred) list[base + __popcll(mask & lanemask_lt())] = e;
+}
+
+// SplitMix64 output function for state x (Steele, Lea & Flood 2014).
+__device__ __forceinline__ unsigned long long splitmix(unsigned long long x) {
+  unsigned long long z = x + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// sign, exponent and top 32 mantissa bits, rounded to nearest
+__device__ __forceinline__ unsigned long long quantize(double v) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  unsigned long long sign = b >> 63;
+  unsigned long long mag = b & 0x7FFFFFFFFFFFFFFFULL;
+  return ((mag + (1ULL << 19)) >> 20) | (sign << 63);
+}
+
+}  // namespace psl

@@ -1,0 +1,89 @@
+// sweep.h -- launchers of the per-round kernels (sweep.hip), the parallel-row
+// pass (parallel.hip), ingest (ingest.hip) and compaction (compact.hip).
+#pragma once
+#include "psl_dev.h"
+
+namespace psl {
+
+enum { MODE_ROUND = 0, MODE_COMPACT = 1 };
+
+struct SweepGrid {
+  int nb[NBINS];  // workgroups per bin in the fused sweep launch
+};
+
+// sweep.hip
+void launch_sweep(const Dev& d, const SweepGrid& g, int mode, hipStream_t s);
+void launch_dense(const Dev& d, int mode, hipStream_t s);
+void launch_src(const Dev& d, hipStream_t s);
+void launch_count(const Dev& d, hipStream_t s);
+void launch_emit(const Dev& d, int64_t base, int round, hipStream_t s);
+int dense_chunk_size();
+int dense_max_chunks();
+int wave_max_len();
+int block_max_len();
+
+// ingest.hip
+struct IngestScratch {
+  int32_t* rowid1;   // [nnz+1]: rowid1[p+1] = row of CSR position p
+  uint32_t* k0;      // [nnz]
+  uint32_t* k1;      // [nnz]
+  int32_t* v0;       // [nnz]
+  int32_t* v1;       // [nnz]
+  int32_t* ws;       // scan / radix workspace
+};
+void launch_check_rows(const Dev& d, hipStream_t s);
+void check_cols(const Dev& d, const double* lb_in, const double* ub_in, double* c_mut, hipStream_t s);
+void launch_check_entries(const Dev& d, const int32_t* rowid1, hipStream_t s);
+void build_rowid(const Dev& d, IngestScratch& sc, hipStream_t s);
+const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, int32_t* col_len, IngestScratch& sc,
+                          hipStream_t s);
+// bins: writes bin_rows and per-bin counts (device counts[NBINS])
+void build_bins(const Dev& d, const int32_t* thresholds, int32_t* bin_rows, int32_t* counts, IngestScratch& sc,
+                hipStream_t s);
+void launch_round0_count(const Dev& d, hipStream_t s);
+void launch_round0_emit(const Dev& d, int64_t base, hipStream_t s);
+void launch_init_state(const Dev& d, hipStream_t s);
+
+// parallel.hip
+struct ParScratch {
+  HashSlot* table;
+  int64_t cap;        // power of two
+  int32_t* slot;      // [m] slot of a candidate row, -1 otherwise
+  int32_t* lead;      // [m] leader of a merged row, -1 otherwise
+  long long* side_key;// [2m] merged (lhs, rhs) keys of a leader
+  int32_t* side_src;  // [2m]
+  uint8_t* is_leader; // [m]
+  int32_t* vlist;     // [m] rows to verify
+  unsigned long long* hacc;  // [3m] dense-row hash accumulators (h1, h2, L)
+};
+void launch_par_reset(const Dev& d, const ParScratch& p, hipStream_t s);
+void launch_par_hash(const Dev& d, const ParScratch& p, const SweepGrid& g, hipStream_t s);
+void launch_par_verify(const Dev& d, const ParScratch& p, hipStream_t s);
+void launch_par_count(const Dev& d, const ParScratch& p, hipStream_t s);
+void launch_par_emit(const Dev& d, const ParScratch& p, int64_t base, int round, hipStream_t s);
+
+// compact.hip
+struct Reduced {
+  int32_t *row_ptr, *col_idx, *col_ptr, *row_idx, *row_map, *col_map;
+  double *val, *cval, *lhs, *rhs, *lb, *ub, *c;
+  uint8_t *row_class, *col_class;
+};
+struct CompactScratch {
+  int32_t* row_new;       // [m]     kept flags -> new row ids
+  int32_t* col_new;       // [n]     kept flags -> new column ids
+  double* terms;          // [n]     cost terms of removed columns
+  double* pws;            // pairwise-sum workspace; pws[0] = the sum
+  int32_t* totals;        // [4]     m', n', nnz' (CSR), nnz' (transposed)
+  double* offset;         // [1]     reduced objective offset
+  int32_t* ws;            // scan workspace
+  int32_t* eflag;         // [nnz+1] CSR keep flags -> output positions
+  int32_t* qflag;         // [nnz+1] transposed keep flags -> output positions
+  const int32_t* rowid1;  // row of CSR position p at index p + 1
+  const uint32_t* colid;  // column of each position of the transposed copy
+};
+// flags and scans (totals written to c.totals)
+void compact_flags(const Dev& d, const CompactScratch& c, hipStream_t s);
+// offset, gather of both layouts, vectors, maps and classes
+void compact_write(const Dev& d, const CompactScratch& c, const Reduced& r, double obj_offset, hipStream_t s);
+
+}  // namespace psl

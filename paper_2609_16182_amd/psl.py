@@ -1,0 +1,311 @@
+"""Thin ctypes binding of libpsl (include/psl.h): argument marshalling only.
+
+Every presolve step runs in the library's HIP kernels. PyTorch, when used,
+only provides device memory and the stream. Loading fails loudly when
+libpsl.so has not been built (python -m paper_2609_16182_amd.build).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpsl.so")
+
+PSL_OK, PSL_ERR_INVALID, PSL_ERR_OOM, PSL_ERR_DEVICE, PSL_ERR_STATE, PSL_ERR_CAPACITY, PSL_ERR_UNSUPPORTED = range(7)
+STATUS_NAMES = ["OK", "INVALID", "OOM", "DEVICE", "STATE", "CAPACITY", "UNSUPPORTED"]
+RESULT_NAMES = {0: "REDUCED", 1: "UNCHANGED", 2: "INFEASIBLE", 3: "UNBOUNDED_OR_INFEASIBLE"}
+PSL_MEM_HOST, PSL_MEM_DEVICE = 0, 1
+
+RECORD_DTYPE = np.dtype([
+    ("type", "u1"), ("side", "u1"), ("round", "<u2"),
+    ("i", "<i4"), ("j", "<i4"), ("k", "<i4"), ("v", "<f8", (4,)),
+])
+REC_NAMES = {1: "FIX_COL", 2: "EMPTY_COL", 3: "EMPTY_ROW", 4: "REDUNDANT_ROW",
+             5: "SINGLETON_ROW", 6: "BOUND_CHANGE", 7: "PARALLEL_ROW", 8: "LEADER_SIDES"}
+
+
+class psl_lp(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("nnz", C.c_int64), ("mem", C.c_int),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("lhs", C.c_void_p), ("rhs", C.c_void_p), ("lb", C.c_void_p), ("ub", C.c_void_p),
+                ("c", C.c_void_p), ("obj_offset", C.c_double)]
+
+
+class psl_settings(C.Structure):
+    _fields_ = [("max_rounds", C.c_int32), ("max_outer", C.c_int32), ("enable_parallel_rows", C.c_int32),
+                ("feas_tol", C.c_double), ("fix_tol", C.c_double), ("min_improve", C.c_double),
+                ("par_tol", C.c_double), ("inf_value", C.c_double), ("coef_tol", C.c_double),
+                ("bin_thresholds", C.c_void_p), ("n_bins", C.c_int32), ("device", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class psl_stats(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("outer_cycles", C.c_int32), ("records", C.c_int64),
+                ("nnz_in", C.c_int64), ("nnz_out", C.c_int64), ("m_out", C.c_int32), ("n_out", C.c_int32),
+                ("ms_ingest", C.c_double), ("ms_sweep", C.c_double), ("ms_decide", C.c_double),
+                ("ms_parallel", C.c_double), ("ms_compact", C.c_double), ("ms_total", C.c_double),
+                ("sweep_launches", C.c_int64), ("sweep_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class psl_reduced_view(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("col_ptr", C.c_void_p), ("row_idx", C.c_void_p), ("cval", C.c_void_p),
+                ("lhs", C.c_void_p), ("rhs", C.c_void_p), ("lb", C.c_void_p), ("ub", C.c_void_p),
+                ("c", C.c_void_p), ("obj_offset", C.c_double),
+                ("row_map", C.c_void_p), ("col_map", C.c_void_p),
+                ("row_class", C.c_void_p), ("col_class", C.c_void_p)]
+
+
+class PslError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_hip = None
+
+
+def load(path=None):
+    """Load libpsl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2609_16182_amd.build`")
+    lib = C.CDLL(path)
+    lib.psl_settings_default.argtypes = [C.POINTER(psl_settings)]
+    lib.psl_settings_default.restype = None
+    lib.psl_presolve_create.argtypes = [C.POINTER(psl_lp), C.POINTER(psl_settings), C.POINTER(C.c_void_p)]
+    lib.psl_presolve_reload.argtypes = [C.c_void_p, C.POINTER(psl_lp)]
+    lib.psl_presolve_run.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(psl_stats)]
+    lib.psl_reduced_problem.argtypes = [C.c_void_p, C.POINTER(psl_reduced_view)]
+    lib.psl_records.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_void_p, C.c_int64]
+    lib.psl_postsolve.argtypes = [C.c_void_p] + [C.c_void_p] * 6
+    lib.psl_presolve_free.argtypes = [C.c_void_p]
+    lib.psl_presolve_free.restype = None
+    lib.psl_last_error.argtypes = [C.c_void_p]
+    lib.psl_last_error.restype = C.c_char_p
+    for f in ("psl_presolve_create", "psl_presolve_reload", "psl_presolve_run", "psl_reduced_problem",
+              "psl_records", "psl_postsolve"):
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _hiprt():
+    """HIP runtime (already loaded by libpsl) for device-to-host copies."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    return _hip
+
+
+def _check(st, h=None):
+    if st != PSL_OK:
+        raise PslError(st, load().psl_last_error(h).decode())
+
+
+# ---------------------------------------------------------------------------
+# the C-ABI, one Python function per entry point
+# ---------------------------------------------------------------------------
+
+def psl_settings_default():
+    s = psl_settings()
+    load().psl_settings_default(C.byref(s))
+    return s
+
+
+def psl_presolve_create(lp: psl_lp, settings: psl_settings):
+    h = C.c_void_p()
+    _check(load().psl_presolve_create(C.byref(lp), C.byref(settings), C.byref(h)))
+    return h
+
+
+def psl_presolve_reload(h, lp: psl_lp):
+    _check(load().psl_presolve_reload(h, C.byref(lp)), h)
+
+
+def psl_presolve_run(h):
+    res = C.c_int()
+    st = psl_stats()
+    _check(load().psl_presolve_run(h, C.byref(res), C.byref(st)), h)
+    return res.value, st
+
+
+def psl_reduced_problem(h):
+    v = psl_reduced_view()
+    _check(load().psl_reduced_problem(h, C.byref(v)), h)
+    return v
+
+
+def psl_records(h):
+    cnt = C.c_int64()
+    _check(load().psl_records(h, C.byref(cnt), None, 0), h)
+    out = np.zeros(cnt.value, RECORD_DTYPE)
+    if cnt.value:
+        _check(load().psl_records(h, C.byref(cnt), out.ctypes.data, cnt.value), h)
+    return out
+
+
+def psl_postsolve(h, x_red, n):
+    x_red = np.ascontiguousarray(x_red, np.float64)
+    x = np.zeros(n)
+    _check(load().psl_postsolve(h, x_red.ctypes.data if x_red.size else None, None, None,
+                                x.ctypes.data if n else None, None, None), h)
+    return x
+
+
+def psl_presolve_free(h):
+    if h:
+        load().psl_presolve_free(h)
+
+
+def psl_last_error(h=None):
+    return load().psl_last_error(h).decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+_LP_KEYS = ("row_ptr", "col_idx", "val", "lhs", "rhs", "lb", "ub", "c")
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def make_lp(lp, keep):
+    """psl_lp from a dict of numpy arrays (host) or torch CUDA tensors (device)."""
+    arrs = {}
+    dev = None
+    for k in _LP_KEYS:
+        a = lp[k]
+        if _is_torch(a):
+            d = a.is_cuda
+            want = {"row_ptr": "int32", "col_idx": "int32"}.get(k, "float64")
+            if str(a.dtype).split(".")[-1] != want or not a.is_contiguous():
+                raise ValueError(f"{k}: needs a contiguous {want} tensor")
+        else:
+            d = False
+            a = np.ascontiguousarray(a, np.int32 if k in ("row_ptr", "col_idx") else np.float64)
+        if dev is None:
+            dev = d
+        elif dev != d:
+            raise ValueError("all arrays must be on the host or all on the device")
+        arrs[k] = a
+    keep.append(arrs)
+
+    def ptr(a):
+        if _is_torch(a):
+            return a.data_ptr() if a.numel() else None
+        return a.ctypes.data if a.size else None
+
+    m, n = int(lp["m"]), int(lp["n"])
+    nnz = int(lp.get("nnz", int(arrs["row_ptr"][-1]) if m else 0))
+    return psl_lp(m, n, nnz, PSL_MEM_DEVICE if dev else PSL_MEM_HOST,
+                  *[ptr(arrs[k]) for k in _LP_KEYS], float(lp.get("obj_offset", 0.0)))
+
+
+def make_settings(stream=None, **kw):
+    s = psl_settings_default()
+    for k, v in kw.items():
+        if k == "bin_thresholds":
+            arr = (C.c_int32 * 2)(*v)
+            s.bin_thresholds = C.cast(arr, C.c_void_p)
+            s.n_bins = 2
+            s._thr = arr
+        else:
+            setattr(s, k, v)
+    if stream is not None:
+        s.stream = stream
+    return s
+
+
+def _d2h(ptr, count, dtype):
+    out = np.zeros(count, dtype)
+    if count:
+        st = _hiprt().hipMemcpy(out.ctypes.data, ptr, out.nbytes, 2)  # hipMemcpyDeviceToHost
+        if st != 0:
+            raise PslError(PSL_ERR_DEVICE, f"hipMemcpy failed ({st})")
+    return out
+
+
+class Presolver:
+    """One presolve handle: create (copies the LP to the device), run, read."""
+
+    def __init__(self, lp, stream=None, **settings):
+        self._keep = []
+        self.n = int(lp["n"])
+        self.settings = make_settings(stream=stream, **settings)
+        self.h = psl_presolve_create(make_lp(lp, self._keep), self.settings)
+        self._keep.clear()
+
+    def reload(self, lp):
+        keep = []
+        psl_presolve_reload(self.h, make_lp(lp, keep))
+
+    def run(self):
+        res, st = psl_presolve_run(self.h)
+        self.result = res
+        self.result_name = RESULT_NAMES[res]
+        self.stats = st.as_dict()
+        return self.result_name
+
+    def records(self):
+        return psl_records(self.h)
+
+    def view(self):
+        return psl_reduced_problem(self.h)
+
+    def reduced(self):
+        """Copy of the reduced problem on the host (numpy)."""
+        v = self.view()
+        m, n, nnz = v.m, v.n, v.nnz
+        return dict(
+            m=m, n=n, nnz=nnz, obj_offset=v.obj_offset,
+            row_ptr=_d2h(v.row_ptr, m + 1, np.int32), col_idx=_d2h(v.col_idx, nnz, np.int32),
+            val=_d2h(v.val, nnz, np.float64), col_ptr=_d2h(v.col_ptr, n + 1, np.int32),
+            row_idx=_d2h(v.row_idx, nnz, np.int32), cval=_d2h(v.cval, nnz, np.float64),
+            lhs=_d2h(v.lhs, m, np.float64), rhs=_d2h(v.rhs, m, np.float64),
+            lb=_d2h(v.lb, n, np.float64), ub=_d2h(v.ub, n, np.float64), c=_d2h(v.c, n, np.float64),
+            row_map=_d2h(v.row_map, m, np.int32), col_map=_d2h(v.col_map, n, np.int32),
+            row_class=_d2h(v.row_class, m, np.uint8), col_class=_d2h(v.col_class, n, np.uint8))
+
+    def postsolve(self, x_red):
+        return psl_postsolve(self.h, x_red, self.n)
+
+    def close(self):
+        if getattr(self, "h", None):
+            psl_presolve_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def presolve(lp, **settings):
+    """Create, run and collect everything on the host; returns a dict."""
+    p = Presolver(lp, **settings)
+    try:
+        name = p.run()
+        out = {"result_name": name, "records": p.records(), "stats": p.stats}
+        out["reduced"] = p.reduced() if name in ("REDUCED", "UNCHANGED") else None
+        return out, p
+    except Exception:
+        p.close()
+        raise

@@ -1,0 +1,180 @@
+"""GPU library vs CPU oracle, bit for bit (result, records, reduced problem).
+
+Runs through the C-ABI (ctypes binding). Sizes are chosen so the oracle
+finishes in seconds while spanning many workgroups and every row bin,
+including ragged tails and forced multi-workgroup (dense) rows.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_16182_amd import lpgen
+from tests.lp_utils import load_golden, make
+from tests.parity_util import assert_same
+
+pytestmark = pytest.mark.gpu
+
+psl = pytest.importorskip("paper_2609_16182_amd.psl")
+
+INF = np.inf
+
+
+def run_both(lp, **settings):
+    ref = O.presolve(lp, **{k: v for k, v in settings.items() if k in O.DEFAULTS})
+    got, p = psl.presolve(lp, **settings)
+    p.close()
+    return got, ref
+
+
+@pytest.mark.parametrize("seed", range(0, 120))
+def test_tiny(seed):
+    lp = lpgen.tiny(seed, finite_bounds=seed % 3 == 0)
+    got, ref = run_both(lp)
+    assert_same(got, ref, f"tiny {seed}")
+
+
+def test_worked_example_and_parallel_golden():
+    for name in ("worked_example_propagation.json", "parallel_rows_merge.json"):
+        _, lp = load_golden(name)
+        got, ref = run_both(lp)
+        assert_same(got, ref, name)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_single_small(seed):
+    lp = lpgen.single_small(seed=seed)
+    got, ref = run_both(lp)
+    assert got["result_name"] == "REDUCED"
+    assert_same(got, ref, f"small {seed}")
+
+
+@pytest.mark.parametrize("scale", [0.003, 0.02])
+def test_power_law_scaled(scale):
+    lp = lpgen.power_law(scale=scale)
+    got, ref = run_both(lp)
+    assert_same(got, ref, f"power-law {scale}")
+
+
+def test_large_scaled_with_chains():
+    lp = lpgen.large(scale=0.0005)
+    got, ref = run_both(lp)
+    assert ref.rounds >= 5
+    assert_same(got, ref, "large")
+
+
+@pytest.mark.parametrize("thr", [(16, 16), (64, 256), (1024, 16384), (4096, 65536)])
+def test_bins_do_not_change_results(thr):
+    """Every bin threshold (wavefront / workgroup / multi-workgroup rows)
+    gives the same bytes: the sums are canonical pairwise trees."""
+    lp = lpgen.large(scale=0.0005)
+    got, ref = run_both(lp, bin_thresholds=thr)
+    assert_same(got, ref, f"thresholds {thr}")
+    lp = lpgen.power_law(scale=0.01, seed=9)
+    got, ref = run_both(lp, bin_thresholds=thr)
+    assert_same(got, ref, f"power-law thresholds {thr}")
+
+
+def test_settings_variants():
+    lp = lpgen.single_small(seed=4)
+    for kw in (dict(max_rounds=1), dict(max_rounds=3, max_outer=1), dict(enable_parallel_rows=0),
+               dict(min_improve=0.0), dict(fix_tol=1e-6, feas_tol=1e-6)):
+        got, ref = run_both(lp, **kw)
+        assert_same(got, ref, str(kw))
+
+
+def test_edge_cases():
+    cases = {
+        "no rows": make(0, 3, [], [], [], [0, -1, 0], [1, 1, INF], [1.0, 0.0, 1.0]),
+        "no columns": make(2, 0, [[], []], [-1.0, -INF], [1.0, INF], [], [], []),
+        "nothing": make(0, 0, [], [], [], [], [], []),
+        "all fixed": make(2, 2, [[(0, 1.0), (1, 2.0)], [(1, 1.0)]], [-INF, 0.0], [10.0, 5.0], [1, 2], [1, 2], [1, 1]),
+        "infeasible empty row": make(1, 1, [[]], [1.0], [2.0], [0], [1], [0]),
+        "infeasible bounds": make(1, 2, [[(0, 1.0)]], [-INF], [3.0], [2, 0], [1, 1], [0, 0]),
+        "unbounded": make(1, 2, [[(0, 1.0)]], [-INF], [3.0], [0, 0], [INF, INF], [1, -1]),
+        "infeasible row": make(1, 2, [[(0, 1.0), (1, 1.0)]], [5.0], [INF], [0, 0], [1, 1], [0, 0]),
+        "free row": make(1, 2, [[(0, 1.0), (1, 1.0)]], [-INF], [INF], [-INF, 0], [INF, 1], [0, 1]),
+        "huge sides": make(1, 2, [[(0, 1.0), (1, 1.0)]], [-1e25], [1e21], [0, 0], [INF, 1], [1, 1]),
+    }
+    for name, lp in cases.items():
+        got, ref = run_both(lp)
+        assert_same(got, ref, name)
+
+
+def test_invalid_input_rejected_on_device():
+    good = make(2, 3, [[(0, 1.0), (2, 1.0)], [(1, 2.0)]], [-INF, 0.0], [4.0, 1.0], [0, 0, 0], [1, 1, 1], [0, 0, 0])
+    bad = []
+    b = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in good.items()}
+    b["col_idx"] = np.array([2, 0, 1], np.int32)
+    bad.append(b)
+    b = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in good.items()}
+    b["col_idx"] = np.array([0, 3, 1], np.int32)
+    bad.append(b)
+    b = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in good.items()}
+    b["val"] = np.array([1.0, 0.0, 2.0])
+    bad.append(b)
+    b = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in good.items()}
+    b["lb"] = np.array([0.0, np.nan, 0.0])
+    bad.append(b)
+    b = {k: (v.copy() if hasattr(v, "copy") else v) for k, v in good.items()}
+    b["row_ptr"] = np.array([0, 3, 2], np.int32)
+    bad.append(b)
+    for k, lp in enumerate(bad):
+        with pytest.raises(psl.PslError) as ei:
+            psl.Presolver(lp)
+        assert ei.value.status == psl.PSL_ERR_INVALID, k
+    p = psl.Presolver(good)
+    p.run()
+    p.close()
+
+
+def test_device_resident_input_and_reload():
+    torch = pytest.importorskip("torch")
+    lp1 = lpgen.single_small(seed=7)
+    lp2 = lpgen.make_lp(2000, 3000, seed=8, row_len=(4, 8))
+    # same shape for reload
+    lp2 = {**lp2}
+    ref1 = O.presolve(lp1)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(lp1[k])).cuda() for k in
+           ("row_ptr", "col_idx", "val", "lhs", "rhs", "lb", "ub", "c")}
+    dev.update(m=lp1["m"], n=lp1["n"])
+    p = psl.Presolver(dev, stream=torch.cuda.current_stream().cuda_stream)
+    p.run()
+    got = {"result_name": p.result_name, "records": p.records(), "reduced": p.reduced()}
+    assert_same(got, ref1, "device input")
+    # reload the same handle with another LP of the same shape
+    if lpgen.nnz(lp2) == lpgen.nnz(lp1):
+        p.reload(lp2)
+        p.run()
+        got2 = {"result_name": p.result_name, "records": p.records(), "reduced": p.reduced()}
+        assert_same(got2, O.presolve(lp2), "reload")
+    p.reload(lp1)
+    p.run()
+    got3 = {"result_name": p.result_name, "records": p.records(), "reduced": p.reduced()}
+    assert_same(got3, ref1, "reload same")
+    p.close()
+
+
+def test_postsolve_matches_oracle():
+    lp = lpgen.single_small(seed=11)
+    ref = O.presolve(lp)
+    got, p = psl.presolve(lp)
+    rng = np.random.default_rng(0)
+    xr = rng.normal(size=got["reduced"]["n"])
+    assert np.array_equal(p.postsolve(xr), ref.postsolve(xr))
+    x = np.zeros(lp["n"])
+    st = psl.load().psl_postsolve(p.h, xr.ctypes.data, xr.ctypes.data, None, x.ctypes.data, None, None)
+    assert st == psl.PSL_ERR_UNSUPPORTED  # dual postsolve is not provided
+    p.close()
+
+
+def test_repeat_is_deterministic():
+    lp = lpgen.power_law(scale=0.01, seed=3)
+    outs = []
+    for _ in range(3):
+        got, p = psl.presolve(lp)
+        p.close()
+        outs.append(got)
+    for g in outs[1:]:
+        assert np.array_equal(g["records"].view(np.uint8), outs[0]["records"].view(np.uint8))
+        for k in ("val", "lb", "ub", "lhs", "rhs"):
+            assert np.array_equal(g["reduced"][k].view(np.uint64), outs[0]["reduced"][k].view(np.uint64))
