@@ -62,7 +62,7 @@ typedef enum { PSL_MEM_HOST = 0, PSL_MEM_DEVICE = 1 } psl_mem;
  * non-decreasing, row_ptr[m] = nnz), col_idx[nnz] strictly ascending within
  * each row and in [0, n), val[nnz] finite and non-zero. lhs/rhs[m], lb/ub/c[n].
  * lhs must not be +inf, rhs not -inf; lb not +inf, ub not -inf; no NaN.
- * nnz < 2^31. The library copies everything at create/reload: the caller
+ * nnz < 2^30. The library copies everything at create/reload: the caller
  * keeps ownership of these arrays and may free them once the call returns. */
 typedef struct {
     int32_t m, n;
@@ -80,9 +80,10 @@ typedef struct {
  *   feas_tol 1e-9, fix_tol 1e-9, min_improve 1e-7, par_tol 1e-9,
  *   inf_value 1e20, coef_tol 1e-9, bin thresholds from the tuner (NULL),
  *   device 0, stream NULL.
- * bin_thresholds (optional, n_bins = 2): row lengths up to which a row is
- * swept by one 64-lane wavefront, and above which it is split over several
- * workgroups. They change only the speed, never a result. */
+ * bin_thresholds (optional, n_bins = 2): [0] the longest row swept by one
+ * 64-lane wavefront (16..512, default 512); [1] positions per workgroup chunk
+ * of longer rows (a power of two >= 2048, default 2048). They change only the
+ * speed, never a result. */
 typedef struct {
     int32_t max_rounds;            /* propagation rounds per outer cycle        */
     int32_t max_outer;             /* outer cycles (rounds, then parallel rows) */
@@ -132,6 +133,8 @@ typedef struct {
     double ms_ingest, ms_sweep, ms_decide, ms_parallel, ms_compact, ms_total;
     int64_t sweep_launches;        /* launches of the row-sweep kernel          */
     double sweep_bytes;            /* algorithmic bytes of those launches       */
+    double ms_long;                /* long-row chunk statistics (before each
+                                      sweep launch)                             */
 } psl_stats;
 
 /* The reduced problem. DEVICE pointers owned by the handle, valid until the

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -46,10 +47,14 @@ struct psl_presolver {
   const uint32_t* colid = nullptr;
   int32_t* bin_counts_dev = nullptr;
   int32_t bin_counts[NBINS] = {0};
-  int32_t thresholds[2] = {1024, 16384};
+  int32_t thresholds[2] = {512, PASS_LEN};  // longest wavefront row, chunk positions
   SweepGrid grid{};
-  int64_t chunk_cap = 0, dense_cap = 0;
-  DenseChunk* dchunk = nullptr;
+  int64_t chunk_cap = 0, long_cap = 0, cand_cap = 0;
+  int32_t* cand_cnt = nullptr;
+  BinEnt *bins_a = nullptr, *bins_b = nullptr;
+  LongChunk *chunks_a = nullptr, *chunks_b = nullptr;
+  int32_t* rebin_dev = nullptr;  // [NBINS+1] new offsets, then 3 totals
+  int64_t act_rows = 0, act_nnz = 0;
 
   // records
   Record* rec = nullptr;
@@ -70,6 +75,7 @@ struct psl_presolver {
   double* hoff = nullptr;
 
   int state = 0;  // 0 loaded, 1 ran
+  int sweep_mode = MODE_ROUND;  // PSL_SWEEP_SPLIT=1: three launches by register class
   psl_result result = PSL_RES_UNCHANGED;
   psl_stats stats{};
   double ms_ingest = 0.0;
@@ -140,14 +146,16 @@ static std::string check_settings(const psl_settings* s) {
   if (s->bin_thresholds) {
     if (s->n_bins != 2) return "bin_thresholds needs n_bins = 2";
     int a = s->bin_thresholds[0], b = s->bin_thresholds[1];
-    if (a < 16 || a > wave_max_len() || b < a || b > block_max_len()) return "bin thresholds out of range";
+    if (a < 16 || a > 512) return "bin_thresholds[0] (longest wavefront row) must be in [16, 512]";
+    if (b < PASS_LEN || b > PASS_LEN * long_max_passes() || (b & (b - 1)) != 0)
+      return "bin_thresholds[1] (chunk positions) must be a power of two >= 2048";
   }
   return "";
 }
 
 static std::string check_lp_shape(const psl_lp* lp) {
   if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return "negative size";
-  if (lp->nnz >= ((int64_t)1 << 31) - 2) return "nnz must be below 2^31";
+  if (lp->nnz >= ((int64_t)1 << 30)) return "nnz must be below 2^30";
   if (lp->m == 0 && lp->nnz != 0) return "entries without rows";
   if (lp->m > 0 && (!lp->row_ptr || !lp->lhs || !lp->rhs)) return "null row array";
   if (lp->n > 0 && (!lp->lb || !lp->ub || !lp->c)) return "null column array";
@@ -160,7 +168,7 @@ static std::string check_lp_shape(const psl_lp* lp) {
 static psl_status setup_arena(psl_presolver* p) {
   int64_t m = p->m, n = p->n, N = p->nnz;
   Dev& d = p->d;
-  int32_t *rp, *ci, *cp, *ri, *col_len, *src, *cnt, *off, *bin_rows;
+  int32_t *rp, *ci, *cp, *ri, *col_len, *src, *cnt, *off;
   double *va, *cva, *lhs, *rhs;
   double2* bnd;
   long long* bkey;
@@ -185,11 +193,18 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(row_code, m);
   ALLOC(col_code, n);
   ALLOC(row_out, m);
-  ALLOC(cand, 2 * N + 64);
+  // candidate regions: short and wavefront bins reserve at most 8 entries per
+  // row plus 8 per position (their regions are sized for the bin's longest
+  // row); long rows reserve 2 per position
+  p->cand_cap = 8 * m + 10 * N + 8 * PASS_LEN;
+  ALLOC(cand, p->cand_cap);
+  ALLOC(p->cand_cnt, std::max<int64_t>(1, m + N / PASS_LEN + 16));
   ALLOC(flags, 1);
   ALLOC(cnt, m + n + 1);
   ALLOC(off, m + n + 1);
-  ALLOC(bin_rows, m);
+  ALLOC(p->bins_a, m);
+  ALLOC(p->bins_b, m);
+  ALLOC(p->rebin_dev, 16);
   ALLOC(p->bin_counts_dev, NBINS);
   ALLOC(p->lb_in, n);
   ALLOC(p->ub_in, n);
@@ -205,14 +220,15 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->ws, wsn);
   p->isc.ws = p->ws;
 
-  // dense rows: rows longer than 4096 can be dense (threshold >= 16 * 256)
-  p->dense_cap = N / 4096 + 1;
-  p->chunk_cap = N / dense_chunk_size() + p->dense_cap + 1;
-  ALLOC(p->dchunk, p->chunk_cap);
-  DensePart* dpart;
-  DenseRow* drow;
-  ALLOC(dpart, p->chunk_cap);
-  ALLOC(drow, p->dense_cap);
+  // long rows are longer than the wavefront threshold; chunks of >= 2048
+  p->long_cap = N / ((int64_t)p->thresholds[0] + 1) + 1;
+  p->chunk_cap = N / PASS_LEN + p->long_cap + 1;
+  ALLOC(p->chunks_a, p->chunk_cap);
+  ALLOC(p->chunks_b, p->chunk_cap);
+  LongPart* lpart;
+  LongRow* lrow;
+  ALLOC(lpart, p->chunk_cap);
+  ALLOC(lrow, p->long_cap);
 
   p->rec_cap = 2 * m + 4 * n + 1024;
   ALLOC(p->rec, p->rec_cap);
@@ -228,7 +244,7 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->par.side_src, 2 * m);
   ALLOC(p->par.is_leader, m);
   ALLOC(p->par.vlist, m);
-  ALLOC(p->par.hacc, 3 * p->dense_cap);
+  ALLOC(p->par.hacc, 3 * p->long_cap);
 
   // compaction
   ALLOC(p->cmp.row_new, m + 1);
@@ -260,7 +276,7 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(r.col_class, n);
 
   HIPCHK(p, hipHostMalloc((void**)&p->hflags, sizeof(Flags), hipHostMallocDefault));
-  HIPCHK(p, hipHostMalloc((void**)&p->htot, 4 * sizeof(int32_t) + 16, hipHostMallocDefault));
+  HIPCHK(p, hipHostMalloc((void**)&p->htot, 64 * sizeof(int32_t), hipHostMallocDefault));
   HIPCHK(p, hipHostMalloc((void**)&p->hoff, sizeof(double), hipHostMallocDefault));
   for (auto& e : p->ev) HIPCHK(p, hipEventCreate(&e));
 
@@ -285,15 +301,16 @@ static psl_status setup_arena(psl_presolver* p) {
   d.col_code = col_code;
   d.row_out = row_out;
   d.cand = cand;
+  d.cand_cnt = p->cand_cnt;
   d.flags = flags;
   d.cnt = cnt;
   d.off = off;
   d.rec = p->rec;
-  d.bin_rows = bin_rows;
-  d.dchunk = p->dchunk;
-  d.dpart = dpart;
-  d.drow = drow;
-  d.ndense = 0;
+  d.bins = p->bins_a;
+  d.lchunk = p->chunks_a;
+  d.lpart = lpart;
+  d.lrow = lrow;
+  d.nlong = 0;
   d.nchunks = 0;
   const psl_settings& s = p->s;
   d.cfg = Cfg{s.feas_tol, s.fix_tol, s.min_improve, s.par_tol, s.inf_value, s.coef_tol};
@@ -303,6 +320,49 @@ static psl_status setup_arena(psl_presolver* p) {
 static psl_status read_flags(psl_presolver* p) {
   HIPCHK(p, hipMemcpyAsync(p->hflags, p->d.flags, sizeof(Flags), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
+  return PSL_OK;
+}
+
+// flags plus the number of row records of the last scan (rows removed)
+static psl_status read_round(psl_presolver* p, int64_t rows_total, int32_t* rows_removed) {
+  HIPCHK(p, hipMemcpyAsync(p->hflags, p->d.flags, sizeof(Flags), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipMemcpyAsync(p->htot + 32, p->d.off + rows_total, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  *rows_removed = p->htot[32];
+  return PSL_OK;
+}
+
+// workgroups per bin from the current bin offsets and chunk count
+static void set_grid(psl_presolver* p) {
+  const Dev& d = p->d;
+  auto cnt = [&](int b) { return d.bin_off[b + 1] - d.bin_off[b]; };
+  p->grid.nb[BIN_G4] = (cnt(BIN_G4) + 63) / 64;
+  p->grid.nb[BIN_G16] = (cnt(BIN_G16) + 15) / 16;
+  p->grid.nb[BIN_W1] = (cnt(BIN_W1) + 3) / 4;
+  p->grid.nb[BIN_W4] = (cnt(BIN_W4) + 3) / 4;
+  p->grid.nb[BIN_W8] = (cnt(BIN_W8) + 3) / 4;
+  p->grid.nb[BIN_LONG] = d.nchunks;
+  p->grid.long_base = 0;
+  for (int b = 0; b < BIN_LONG; ++b) p->grid.long_base += (int64_t)p->grid.nb[b] * cand_region(b);
+}
+
+// drop removed rows from the bin lists and chunks (double-buffered)
+static psl_status do_rebin(psl_presolver* p) {
+  Dev& d = p->d;
+  BinEnt* bout = d.bins == p->bins_a ? p->bins_b : p->bins_a;
+  LongChunk* cout = d.lchunk == p->chunks_a ? p->chunks_b : p->chunks_a;
+  // scratch: cnt / off (free after the round's emission) and v0 (free between
+  // ingest and compaction; k0 / k1 hold the transposed copy's column ids)
+  rebin(d, bout, cout, d.cnt, d.off, p->isc.v0, p->rebin_dev, p->rebin_dev + NBINS + 1, p->ws, p->stream);
+  HIPCHK(p, hipMemcpyAsync(p->htot, p->rebin_dev, (NBINS + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  for (int b = 0; b <= NBINS; ++b) d.bin_off[b] = p->htot[b];
+  p->act_rows = p->htot[NBINS + 1];
+  p->act_nnz = p->htot[NBINS + 2];
+  d.nchunks = p->htot[NBINS + 3];
+  d.bins = bout;
+  d.lchunk = cout;
+  set_grid(p);
   return PSL_OK;
 }
 
@@ -352,7 +412,9 @@ static psl_status ingest(psl_presolver* p, const psl_lp* lp) {
   if (p->hflags->error) return fail(p, PSL_ERR_INVALID, error_message(p->hflags->error, p->hflags->error_pos));
 
   // bins (before the transpose: both use k0/k1)
-  build_bins(d, p->thresholds, (int32_t*)d.bin_rows, p->bin_counts_dev, p->isc, st);
+  d.bins = p->bins_a;
+  d.lchunk = p->chunks_a;
+  build_bins(d, p->thresholds, p->bins_a, p->bin_counts_dev, p->isc, st);
   HIPCHK(p, hipMemcpyAsync(p->htot, p->bin_counts_dev, NBINS * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(p, hipStreamSynchronize(st));
   int off = 0;
@@ -363,36 +425,22 @@ static psl_status ingest(psl_presolver* p, const psl_lp* lp) {
   }
   d.bin_off[NBINS] = off;
 
-  // dense rows: chunk table built on the host from the (few) dense rows
-  int ndense = p->bin_counts[BIN_DENSE];
-  std::vector<int32_t> drows(ndense);
-  std::vector<DenseChunk> chunks;
-  std::vector<DenseRow> drs(ndense);
-  if (ndense > 0) {
-    if (ndense > p->dense_cap) return fail(p, PSL_ERR_CAPACITY, "too many dense rows");
-    HIPCHK(p, hipMemcpy(drows.data(), d.bin_rows + d.bin_off[BIN_DENSE], ndense * 4, hipMemcpyDeviceToHost));
-    std::vector<int32_t> rph(m + 1);
-    HIPCHK(p, hipMemcpy(rph.data(), d.rp, (m + 1) * 4, hipMemcpyDeviceToHost));
-    int CH = dense_chunk_size();
-    for (int k = 0; k < ndense; ++k) {
-      int row = drows[k];
-      int len = rph[row + 1] - rph[row];
-      int nch = (len + CH - 1) / CH;
-      if (nch > dense_max_chunks()) return fail(p, PSL_ERR_CAPACITY, "row longer than the dense-row limit");
-      drs[k] = DenseRow{row, (int32_t)chunks.size(), nch, 0, 0.0, 0.0, 0, 0, 0, 0};
-      for (int c = 0; c < nch; ++c) chunks.push_back(DenseChunk{row, c * CH, k, 0});
-    }
-    if ((int64_t)chunks.size() > p->chunk_cap) return fail(p, PSL_ERR_CAPACITY, "too many dense chunks");
-    HIPCHK(p, hipMemcpyAsync(p->dchunk, chunks.data(), chunks.size() * sizeof(DenseChunk), hipMemcpyHostToDevice, st));
-    HIPCHK(p, hipMemcpyAsync(d.drow, drs.data(), ndense * sizeof(DenseRow), hipMemcpyHostToDevice, st));
-  }
-  d.ndense = ndense;
-  d.nchunks = (int32_t)chunks.size();
-  p->grid.nb[BIN_G4] = (p->bin_counts[BIN_G4] + 63) / 64;
-  p->grid.nb[BIN_G16] = (p->bin_counts[BIN_G16] + 15) / 16;
-  p->grid.nb[BIN_WAVE] = (p->bin_counts[BIN_WAVE] + 3) / 4;
-  p->grid.nb[BIN_BLOCK] = p->bin_counts[BIN_BLOCK];
-  p->grid.nb[BIN_DENSE] = d.nchunks;
+  // long rows: chunk table built on the device
+  int nlong = p->bin_counts[BIN_LONG];
+  if (nlong > p->long_cap) return fail(p, PSL_ERR_CAPACITY, "too many long rows");
+  d.nlong = nlong;
+  build_long_chunks(d, p->thresholds[1] / PASS_LEN, p->chunks_a, d.cnt, d.off, p->bin_counts_dev, p->ws, st);
+  HIPCHK(p, hipMemcpyAsync(p->htot, p->bin_counts_dev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  s0 = read_flags(p);
+  if (s0 != PSL_OK) return s0;
+  if (p->hflags->error & 64) return fail(p, PSL_ERR_CAPACITY, "a row is longer than 2^26 entries");
+  if (p->htot[0] > p->chunk_cap) return fail(p, PSL_ERR_CAPACITY, "too many long-row chunks");
+  d.nchunks = p->htot[0];
+  set_grid(p);
+  if (p->grid.long_base + (int64_t)p->htot[1] > p->cand_cap)
+    return fail(p, PSL_ERR_CAPACITY, "candidate buffer too small for the row bins");
+  p->act_rows = m;
+  p->act_nnz = N;
 
   p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.col_len, p->isc, st);
   p->cmp.colid = p->colid;
@@ -432,6 +480,7 @@ extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* 
     p->thresholds[1] = s->bin_thresholds[1];
   }
   p->stream = (hipStream_t)s->stream;
+  if (const char* e = std::getenv("PSL_SWEEP_SPLIT")) p->sweep_mode = std::atoi(e) ? 2 : MODE_ROUND;
   p->m = lp->m;
   p->n = lp->n;
   p->nnz = lp->nnz;
@@ -509,8 +558,7 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
   p->rec_count += p->hflags->round_total;
   int round = 0;
   bool infeasible = p->hflags->infeasible != 0, unbounded = false;
-  int64_t act_rows = m, act_nnz = p->nnz;
-  double sweep_ms = 0.0, decide_ms = 0.0, par_ms = 0.0;
+  double sweep_ms = 0.0, decide_ms = 0.0, par_ms = 0.0, long_ms = 0.0;
 
   bool stop = infeasible;
   int outer = 0;
@@ -520,22 +568,29 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
       e = ensure_capacity(p, m + 3 * n + 16);
       if (e != PSL_OK) return e;
       HIPCHK(p, hipEventRecord(p->ev[4], st));
-      launch_sweep(d, p->grid, MODE_ROUND, st);
+      launch_long_stats(d, MODE_ROUND, st);
+      HIPCHK(p, hipEventRecord(p->ev[7], st));
+      launch_sweep(d, p->grid, p->sweep_mode, st);
       HIPCHK(p, hipEventRecord(p->ev[5], st));
-      launch_dense(d, MODE_ROUND, st);
-      launch_src(d, st);
+      launch_src(d, p->grid, st);
       launch_count(d, st);
       scan_excl(d.cnt, d.off, m + n, &d.flags->round_total, p->ws, st);
       launch_emit(d, p->rec_count, round, st);
       HIPCHK(p, hipEventRecord(p->ev[6], st));
-      e = read_flags(p);
+      int32_t removed = 0;
+      e = read_round(p, m, &removed);
       if (e != PSL_OK) return e;
-      sweep_ms += elapsed(p, 4, 5);
+      long_ms += elapsed(p, 4, 7);
+      sweep_ms += elapsed(p, 7, 5);
       decide_ms += elapsed(p, 5, 6);
       S.sweep_launches += 1;
-      S.sweep_bytes += 12.0 * act_nnz + 24.0 * act_rows + 2.0 * m + 16.0 * n;
-      (void)act_rows;
+      S.sweep_bytes += 12.0 * p->act_nnz + 24.0 * p->act_rows + 16.0 * n;
       p->rec_count += p->hflags->round_total;
+      // keep the sweep on live rows once a sixteenth of them went
+      if (removed > 0 && (int64_t)removed * 16 >= p->act_rows) {
+        e = do_rebin(p);
+        if (e != PSL_OK) return e;
+      }
       if (p->hflags->infeasible) infeasible = true;
       if (p->hflags->unbounded) unbounded = true;
       if (infeasible || unbounded) {
@@ -555,6 +610,7 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
     launch_par_count(d, p->par, st);
     scan_excl(d.cnt, d.off, m, &d.flags->round_total, p->ws, st);
     launch_par_emit(d, p->par, p->rec_count, round, st);
+    launch_par_drop(d, p->par, st);
     HIPCHK(p, hipEventRecord(p->ev[5], st));
     e = read_flags(p);
     if (e != PSL_OK) return e;
@@ -577,8 +633,8 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
   double cmp_ms = 0.0;
   if (result == PSL_RES_REDUCED || result == PSL_RES_UNCHANGED) {
     HIPCHK(p, hipEventRecord(p->ev[4], st));
+    launch_long_stats(d, MODE_COMPACT, st);
     launch_sweep(d, p->grid, MODE_COMPACT, st);
-    launch_dense(d, MODE_COMPACT, st);
     compact_flags(d, p->cmp, st);
     compact_write(d, p->cmp, p->red, p->obj_offset, st);
     HIPCHK(p, hipEventRecord(p->ev[5], st));
@@ -603,6 +659,7 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
   S.n_out = p->red_n;
   S.ms_ingest = p->ms_ingest;
   S.ms_sweep = sweep_ms;
+  S.ms_long = long_ms;
   S.ms_decide = decide_ms;
   S.ms_parallel = par_ms;
   S.ms_compact = cmp_ms;

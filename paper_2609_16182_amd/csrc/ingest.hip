@@ -152,16 +152,17 @@ const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, i
 }
 
 // ---------------------------------------------------------------------------
-// row bins by CSR length
+// row bins by CSR length, and the chunk table of long rows
 // ---------------------------------------------------------------------------
-__global__ void k_bin_keys(Dev d, int32_t t_wave, int32_t t_block, uint32_t* keys, int32_t* counts) {
+__global__ void k_bin_keys(Dev d, int32_t t_long, uint32_t* keys, int32_t* counts) {
   __shared__ int c[NBINS];
   if (threadIdx.x < NBINS) c[threadIdx.x] = 0;
   __syncthreads();
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < d.m) {
     int len = d.rp[i + 1] - d.rp[i];
-    uint32_t b = len <= 4 ? BIN_G4 : len <= 16 ? BIN_G16 : len <= t_wave ? BIN_WAVE : len <= t_block ? BIN_BLOCK : BIN_DENSE;
+    uint32_t b = len <= 4 ? BIN_G4 : len <= 16 ? BIN_G16 : len > t_long ? BIN_LONG
+               : len <= 64 ? BIN_W1 : len <= 256 ? BIN_W4 : BIN_W8;
     keys[i] = b;
     atomicAdd(&c[b], 1);
   }
@@ -169,13 +170,112 @@ __global__ void k_bin_keys(Dev d, int32_t t_wave, int32_t t_block, uint32_t* key
   if (threadIdx.x < NBINS && c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], c[threadIdx.x]);
 }
 
-void build_bins(const Dev& d, const int32_t* thresholds, int32_t* bin_rows, int32_t* counts, IngestScratch& sc,
+__global__ void k_bin_fill(Dev d, const int32_t* rows, BinEnt* bins) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.m) return;
+  int row = rows[k];
+  int a = d.rp[row], b = d.rp[row + 1];
+  bins[k] = BinEnt{row, a, b - a, 0};
+}
+
+void build_bins(const Dev& d, const int32_t* thresholds, BinEnt* bins, int32_t* counts, IngestScratch& sc,
                 hipStream_t s) {
   fill_i32(counts, 0, NBINS, s);
   if (d.m == 0) return;
-  hipLaunchKernelGGL(k_bin_keys, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, thresholds[0],
-                     thresholds[1], sc.k0, counts);
-  radix_pass(sc.k0, nullptr, sc.k1, bin_rows, d.m, 0, 3, sc.ws, s);
+  unsigned blocks = (unsigned)((d.m + PSL_BLOCK - 1) / PSL_BLOCK);
+  hipLaunchKernelGGL(k_bin_keys, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, thresholds[0], sc.k0, counts);
+  radix_pass(sc.k0, nullptr, sc.k1, sc.v0, d.m, 0, 3, sc.ws, s);
+  hipLaunchKernelGGL(k_bin_fill, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)sc.v0, bins);
+}
+
+// ---------------------------------------------------------------------------
+// filtering of the bin lists and the chunk list down to the active rows
+// ---------------------------------------------------------------------------
+__global__ void k_rebin_flags(Dev d, int32_t nent, int32_t* keep, int32_t* keep_len, int32_t nch, int32_t* ckeep) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= nent; k += stride) {
+    int f = 0, l = 0;
+    if (k < nent) {
+      BinEnt be = d.bins[k];
+      f = d.row_on[be.row] != 0;
+      l = f ? be.len : 0;
+    }
+    keep[k] = f;
+    keep_len[k] = l;
+  }
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nch; c += stride)
+    ckeep[c] = c < nch ? (d.row_on[d.lchunk[c].row] != 0) : 0;
+}
+
+__global__ void k_rebin_scatter(Dev d, int32_t nent, const int32_t* pos, BinEnt* out, int32_t nch, const int32_t* cpos,
+                                LongChunk* cout, int32_t* new_off) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t k = t0; k < nent; k += stride)
+    if (pos[k + 1] != pos[k]) out[pos[k]] = d.bins[k];
+  for (int64_t c = t0; c < nch; c += stride)
+    if (cpos[c + 1] != cpos[c]) cout[cpos[c]] = d.lchunk[c];
+  if (t0 <= NBINS) new_off[t0] = pos[d.bin_off[t0]];
+}
+
+void rebin(const Dev& d, BinEnt* bins_out, LongChunk* chunks_out, int32_t* keep, int32_t* keep_len, int32_t* ckeep,
+           int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s) {
+  int32_t nent = d.bin_off[NBINS];
+  int64_t t = nent + 1 > d.nchunks + 1 ? nent + 1 : d.nchunks + 1;
+  int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_rebin_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, nent, keep, keep_len,
+                     d.nchunks, ckeep);
+  scan_excl(keep, keep, nent + 1, totals + 0, ws, s);
+  scan_excl(keep_len, keep_len, nent + 1, totals + 1, ws, s);
+  scan_excl(ckeep, ckeep, d.nchunks + 1, totals + 2, ws, s);
+  hipLaunchKernelGGL(k_rebin_scatter, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, nent, (const int32_t*)keep,
+                     bins_out, d.nchunks, (const int32_t*)ckeep, chunks_out, new_off);
+}
+
+// passes per chunk: the requested size, doubled until the row has at most
+// LONG_MAX_CHUNKS chunks (chunk sizes stay powers of two times PASS_LEN)
+__global__ void k_long_count(Dev d, int npass0, int32_t* cnt, int32_t* cnt2) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.nlong) return;
+  BinEnt be = d.bins[d.bin_off[BIN_LONG] + k];
+  int row = be.row;
+  int64_t len = be.len;
+  int64_t np = npass0;
+  while ((len + np * PASS_LEN - 1) / (np * PASS_LEN) > LONG_MAX_CHUNKS) np *= 2;
+  if (np > LONG_MAX_PASSES) {
+    atomicOr(&d.flags->error, 64);  // row too long for the chunk table
+    np = LONG_MAX_PASSES;
+  }
+  int nch = (int)((len + np * PASS_LEN - 1) / (np * PASS_LEN));
+  d.lrow[k] = LongRow{row, 0, nch, (int32_t)np};
+  cnt[k] = nch;
+  cnt2[k] = 2 * (int)len;  // candidate entries of the row's chunks
+}
+
+__global__ void k_long_fill(Dev d, const int32_t* off, const int32_t* uoff, LongChunk* chunks) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.nlong) return;
+  LongRow lr = d.lrow[k];
+  lr.chunk0 = off[k];
+  d.lrow[k] = lr;
+  for (int c = 0; c < lr.nchunk; ++c)
+    chunks[lr.chunk0 + c] = LongChunk{lr.row, c * lr.npass * PASS_LEN, k, lr.npass,
+                                      uoff[k] + 2 * c * lr.npass * PASS_LEN, lr.chunk0 + c};
+}
+
+void build_long_chunks(const Dev& d, int npass0, LongChunk* chunks, int32_t* cnt, int32_t* cnt2, int32_t* totals,
+                       int32_t* ws, hipStream_t s) {
+  if (d.nlong == 0) {
+    fill_i32(totals, 0, 2, s);
+    return;
+  }
+  unsigned blocks = (unsigned)((d.nlong + PSL_BLOCK - 1) / PSL_BLOCK);
+  hipLaunchKernelGGL(k_long_count, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, npass0, cnt, cnt2);
+  scan_excl(cnt, cnt, d.nlong, totals, ws, s);
+  scan_excl(cnt2, cnt2, d.nlong, totals + 1, ws, s);
+  hipLaunchKernelGGL(k_long_fill, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)cnt, (const int32_t*)cnt2,
+                     chunks);
 }
 
 // ---------------------------------------------------------------------------

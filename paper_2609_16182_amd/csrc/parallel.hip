@@ -63,7 +63,7 @@ __global__ void k_par_reset(Dev d, ParScratch P) {
     P.side_src[2 * i] = 0x7FFFFFFF;
     P.side_src[2 * i + 1] = 0x7FFFFFFF;
   }
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 3 * (int64_t)d.ndense; k += stride)
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 3 * (int64_t)d.nlong; k += stride)
     P.hacc[k] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.flags->vlist_count = 0;
@@ -71,22 +71,24 @@ __global__ void k_par_reset(Dev d, ParScratch P) {
   }
 }
 
-// G-lane groups, one pass (rows of at most G entries)
+// G-lane groups, rows of at most G entries, one position per lane
 template <int G>
 __device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, int bin, int lblock) {
   int gid = lblock * (PSL_BLOCK / G) + (int)(threadIdx.x / G);
   int count = d.bin_off[bin + 1] - d.bin_off[bin];
   bool vr = gid < count;
-  int row = vr ? d.bin_rows[d.bin_off[bin] + gid] : 0;
-  int gl = threadIdx.x & (G - 1);
+  int row = 0;
   int64_t s0 = 0;
   int len = 0;
   bool on = false;
   if (vr) {
-    s0 = d.rp[row];
-    len = d.rp[row + 1] - (int)s0;
+    BinEnt be = d.bins[d.bin_off[bin] + gid];
+    row = be.row;
+    s0 = be.start;
+    len = be.len;
     on = d.row_on[row] != 0;
   }
+  int gl = threadIdx.x & (G - 1);
   double a0 = on && len > 0 ? d.va[s0] : 1.0;
   unsigned long long h1, h2;
   bool act;
@@ -97,7 +99,7 @@ __device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, i
   if (vr && on && gl == 0 && L >= 2) par_insert(d, P, row, row_key(len, h1, h2));
 }
 
-// one wavefront per row, any length
+// one wavefront per row (rows of at most 512 entries)
 __device__ __forceinline__ void hash_wave_row(const Dev& d, const ParScratch& P, int row) {
   int lane = lane_id();
   int64_t s0 = d.rp[row];
@@ -120,9 +122,10 @@ __device__ __forceinline__ void hash_wave_row(const Dev& d, const ParScratch& P,
   if (lane == 0 && L >= 2) par_insert(d, P, row, row_key(len, s1, s2));
 }
 
-// dense rows: one workgroup per chunk, accumulated with 64-bit atomic adds
-__device__ __forceinline__ void hash_dense_chunk(const Dev& d, const ParScratch& P, int chunk, int chunk_len) {
-  DenseChunk ch = d.dchunk[chunk];
+// long rows: one workgroup per chunk, accumulated with 64-bit atomic adds
+// (the key is a sum modulo 2^64, so the order does not matter)
+__device__ __forceinline__ void hash_long_chunk(const Dev& d, const ParScratch& P, int chunk) {
+  LongChunk ch = d.lchunk[chunk];
   int row = ch.row;
   if (!d.row_on[row]) return;
   int64_t s0 = d.rp[row];
@@ -130,7 +133,7 @@ __device__ __forceinline__ void hash_dense_chunk(const Dev& d, const ParScratch&
   double a0 = d.va[s0];
   unsigned long long s1 = 0, s2 = 0;
   int L = 0;
-  int end = min(len, ch.first + chunk_len);
+  int end = min(len, ch.first + ch.npass * PASS_LEN);
   for (int q0 = ch.first; q0 < end; q0 += PSL_BLOCK) {
     int q = q0 + (int)threadIdx.x;
     unsigned long long h1, h2;
@@ -144,45 +147,39 @@ __device__ __forceinline__ void hash_dense_chunk(const Dev& d, const ParScratch&
   s2 = group_sum_u64<PSL_WAVE>(s2);
   unsigned long long l64 = group_sum_u64<PSL_WAVE>((unsigned long long)L);
   if (lane_id() == 0) {
-    atomicAdd(&P.hacc[3 * (int64_t)ch.drow], s1);
-    atomicAdd(&P.hacc[3 * (int64_t)ch.drow + 1], s2);
-    atomicAdd(&P.hacc[3 * (int64_t)ch.drow + 2], l64);
+    atomicAdd(&P.hacc[3 * (int64_t)ch.lrow], s1);
+    atomicAdd(&P.hacc[3 * (int64_t)ch.lrow + 1], s2);
+    atomicAdd(&P.hacc[3 * (int64_t)ch.lrow + 2], l64);
   }
 }
 
-__global__ void __launch_bounds__(PSL_BLOCK) k_par_hash(Dev d, ParScratch P, SweepGrid g, int chunk_len) {
+__global__ void __launch_bounds__(PSL_BLOCK) k_par_hash(Dev d, ParScratch P, SweepGrid g) {
   int b = blockIdx.x;
-  if (b < g.nb[0]) {
+  if (b < g.nb[BIN_G4]) {
     hash_groups<4>(d, P, BIN_G4, b);
     return;
   }
-  b -= g.nb[0];
-  if (b < g.nb[1]) {
+  b -= g.nb[BIN_G4];
+  if (b < g.nb[BIN_G16]) {
     hash_groups<16>(d, P, BIN_G16, b);
     return;
   }
-  b -= g.nb[1];
-  if (b < g.nb[2]) {
+  b -= g.nb[BIN_G16];
+  // the three wavefront bins are consecutive in the bin list
+  int nw = g.nb[BIN_W1] + g.nb[BIN_W4] + g.nb[BIN_W8];
+  if (b < nw) {
     int wid = b * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6);
-    if (wid < d.bin_off[BIN_WAVE + 1] - d.bin_off[BIN_WAVE]) hash_wave_row(d, P, d.bin_rows[d.bin_off[BIN_WAVE] + wid]);
+    if (wid < d.bin_off[BIN_W8 + 1] - d.bin_off[BIN_W1]) hash_wave_row(d, P, d.bins[d.bin_off[BIN_W1] + wid].row);
     return;
   }
-  b -= g.nb[2];
-  if (b < g.nb[3]) {
-    // workgroup-length rows: four rows per workgroup, one per wavefront
-    int wid = b * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6);
-    if (wid < d.bin_off[BIN_BLOCK + 1] - d.bin_off[BIN_BLOCK])
-      hash_wave_row(d, P, d.bin_rows[d.bin_off[BIN_BLOCK] + wid]);
-    return;
-  }
-  b -= g.nb[3];
-  if (b < g.nb[4]) hash_dense_chunk(d, P, b, chunk_len);
+  b -= nw;
+  if (b < g.nb[BIN_LONG]) hash_long_chunk(d, P, b);
 }
 
-__global__ void k_par_dense_insert(Dev d, ParScratch P) {
+__global__ void k_par_long_insert(Dev d, ParScratch P) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d.ndense) return;
-  int row = d.drow[k].row;
+  if (k >= d.nlong) return;
+  int row = d.lrow[k].row;
   if (!d.row_on[row]) return;
   int len = d.rp[row + 1] - d.rp[row];
   if ((int64_t)P.hacc[3 * (int64_t)k + 2] >= 2)
@@ -329,11 +326,6 @@ __global__ void k_par_emit(Dev d, ParScratch P, int64_t base, int round) {
     r.v[3] = 0.0;
     d.rec[base + d.off[t]] = r;
     d.row_on[i] = 0;
-    for (int64_t p = d.rp[i]; p < d.rp[i + 1]; ++p) {
-      int j = d.ci[p];
-      double2 b = d.bnd[j];
-      if (b.x != b.y) atomicSub(&d.col_len[j], 1);
-    }
   } else if (P.is_leader[i]) {
     double lo, up;
     bool inf;
@@ -361,17 +353,32 @@ void launch_par_reset(const Dev& d, const ParScratch& p, hipStream_t s) {
   hipLaunchKernelGGL(k_par_reset, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, p);
 }
 
+// column lengths lose the merged rows: one wavefront per listed row
+__global__ void __launch_bounds__(PSL_BLOCK) k_par_drop(Dev d, ParScratch P) {
+  int nv = d.flags->vlist_count;
+  int wstride = gridDim.x * (PSL_BLOCK / PSL_WAVE);
+  for (int k = blockIdx.x * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6); k < nv; k += wstride) {
+    int r = P.vlist[k];
+    if (P.lead[r] < 0) continue;
+    for (int p = d.rp[r] + lane_id(); p < d.rp[r + 1]; p += PSL_WAVE) {
+      int j = d.ci[p];
+      double2 b = d.bnd[j];
+      if (b.x != b.y) atomicSub(&d.col_len[j], 1);
+    }
+  }
+}
+
 void launch_par_hash(const Dev& d, const ParScratch& p, const SweepGrid& g, hipStream_t s) {
-  SweepGrid h = g;
-  // workgroup-length rows are hashed four per workgroup
-  int nblk = d.bin_off[BIN_BLOCK + 1] - d.bin_off[BIN_BLOCK];
-  h.nb[3] = (nblk + 3) / 4;
-  int total = h.nb[0] + h.nb[1] + h.nb[2] + h.nb[3] + h.nb[4];
-  if (total > 0)
-    hipLaunchKernelGGL(k_par_hash, dim3(total), dim3(PSL_BLOCK), 0, s, d, p, h, dense_chunk_size());
-  if (d.ndense > 0)
-    hipLaunchKernelGGL(k_par_dense_insert, dim3((d.ndense + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);
+  int total = 0;
+  for (int b = 0; b < NBINS; ++b) total += g.nb[b];
+  if (total > 0) hipLaunchKernelGGL(k_par_hash, dim3(total), dim3(PSL_BLOCK), 0, s, d, p, g);
+  if (d.nlong > 0)
+    hipLaunchKernelGGL(k_par_long_insert, dim3((d.nlong + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);
   if (d.m > 0) hipLaunchKernelGGL(k_par_vlist, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);
+}
+
+void launch_par_drop(const Dev& d, const ParScratch& p, hipStream_t s) {
+  hipLaunchKernelGGL(k_par_drop, dim3(1024), dim3(PSL_BLOCK), 0, s, d, p);
 }
 
 void launch_par_verify(const Dev& d, const ParScratch& p, hipStream_t s) {

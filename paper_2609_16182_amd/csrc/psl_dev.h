@@ -6,7 +6,8 @@
 //   rows  lhs/rhs[m] f64, row_on[m] u8, row_code[m] u8, row_out[m] 16 B
 //   cols  bnd[n] double2 (lb, ub), bkey[2n] i64 (order-mapped accumulators of
 //         the round's best lb / ub), src[2n] i32, col_len[n] i32, c[n] f64
-//   bins  bin_rows[m] i32 (rows grouped by CSR length, ascending within a bin)
+//   bins  bins[m] {row, start, len} (active rows grouped by CSR length,
+//         ascending within a bin; filtered as rows are removed)
 // A column is removed exactly when lb == ub: a fixed column keeps lb = ub = v,
 // and every active column has ub - lb > fix_tol * max(1, |lb|) >= 0 once a
 // round has run, so the sweep learns a column's state from its bounds alone.
@@ -32,8 +33,14 @@ enum : uint8_t {
   CC_LB = 1, CC_UB = 2, CC_FIX = 4, CC_EMPTY = 8, CC_UNBOUNDED = 16, CC_INFEAS = 32
 };
 
-// row length bins: 4 lanes, 16 lanes, one wave, one workgroup, many workgroups
-enum { BIN_G4 = 0, BIN_G16 = 1, BIN_WAVE = 2, BIN_BLOCK = 3, BIN_DENSE = 4, NBINS = 5 };
+// row length bins: rows of <= 4 / <= 16 entries by 4- / 16-lane groups, rows
+// of <= 64 / <= 256 / <= 512 entries by one wavefront (1 / 4 / 8 contiguous
+// positions per lane), longer rows split into workgroup chunks
+enum { BIN_G4 = 0, BIN_G16 = 1, BIN_W1 = 2, BIN_W4 = 3, BIN_W8 = 4, BIN_LONG = 5, NBINS = 6 };
+
+#define PASS_LEN 2048      // positions per workgroup pass (256 lanes x 8)
+#define LONG_MAX_CHUNKS 512
+#define LONG_MAX_PASSES 64   // rows up to 512 chunks x 64 passes x 2048 positions
 
 struct Record {
   uint8_t type, side;
@@ -54,20 +61,28 @@ struct Cand {        // a candidate bound that may be the round's final value
   double t;
 };
 
-struct DenseChunk {  // one workgroup-sized slice of a dense row
+struct LongChunk {   // one workgroup's slice of a long row: npass passes of PASS_LEN
   int32_t row, first;  // row index, first CSR position (relative to row start)
-  int32_t drow, pad;   // index of the dense row
+  int32_t lrow, npass; // index of the long row, passes per chunk
+  int32_t cand_off;    // start of its candidate region (after the other bins')
+  int32_t id;          // index of its partial statistics (stable under filtering)
 };
 
-struct DensePart {   // partial statistics of one chunk
+struct BinEnt {      // one row of a bin list
+  int32_t row, start, len, pad;
+};
+
+// Candidate regions: every sweep workgroup appends to its own region of the
+// candidate buffer (an LDS counter, no global atomics). A region holds two
+// candidates per position the workgroup can visit.
+
+struct LongPart {    // partial statistics of one chunk (an aligned subtree)
   double smin, smax;
   int32_t nmin, nmax, L, pad;
 };
 
-struct DenseRow {    // per dense row
-  int32_t row, chunk0, nchunk, pad;
-  double minact, maxact;
-  int32_t nmin, nmax, L, keep;
+struct LongRow {     // per long row
+  int32_t row, chunk0, nchunk, npass;
 };
 
 struct Flags {
@@ -102,15 +117,16 @@ struct Dev {
   uint8_t *row_on, *row_code, *col_code;
   RowOut *row_out;
   Cand *cand;
+  int32_t *cand_cnt;   // candidates written per sweep workgroup
   Flags *flags;
   int32_t *cnt, *off;
   Record *rec;
-  const int32_t *bin_rows;
+  const BinEnt *bins;
   int32_t bin_off[NBINS + 1];
-  const DenseChunk *dchunk;
-  DensePart *dpart;
-  DenseRow *drow;
-  int32_t ndense, nchunks;
+  const LongChunk *lchunk;
+  LongPart *lpart;
+  LongRow *lrow;
+  int32_t nlong, nchunks;
   Cfg cfg;
 };
 
@@ -200,8 +216,8 @@ __device__ __forceinline__ double tree_inplace(double* v, int n) {
   return v[0];
 }
 
-// Wave-aggregated append of one 16-byte candidate per lane with pred set.
-// Must be reached by all lanes of the wave.
+// Wave-aggregated append of one 16-byte candidate per lane with pred set;
+// counter may live in LDS. Must be reached by all lanes of the wave.
 __device__ __forceinline__ void wave_append(bool pred, const Cand& e, Cand* list, int32_t* counter) {
   unsigned long long mask = __ballot(pred);
   if (mask == 0) return;
@@ -210,6 +226,12 @@ __device__ __forceinline__ void wave_append(bool pred, const Cand& e, Cand* list
   if (lane_id() == leader) base = atomicAdd(counter, (int)__popcll(mask));
   base = __shfl(base, leader, PSL_WAVE);
   if (pred) list[base + __popcll(mask & lanemask_lt())] = e;
+}
+
+// candidate-region sizes (entries) of the sweep bins, per workgroup
+__host__ __device__ __forceinline__ int64_t cand_region(int bin) {
+  // 2 candidates x (rows per workgroup x longest row of the bin)
+  return bin == 0 ? 2 * 64 * 4 : bin == 1 ? 2 * 16 * 16 : bin == 2 ? 2 * 4 * 64 : bin == 3 ? 2 * 4 * 256 : 2 * 4 * 512;
 }
 
 // SplitMix64 output function for state x (Steele, Lea & Flood 2014).

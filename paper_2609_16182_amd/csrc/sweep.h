@@ -8,19 +8,28 @@ namespace psl {
 enum { MODE_ROUND = 0, MODE_COMPACT = 1 };
 
 struct SweepGrid {
-  int nb[NBINS];  // workgroups per bin in the fused sweep launch
+  int nb[NBINS];        // workgroups per bin in the fused sweep launch
+  int64_t long_base;    // candidate entries before the long-row regions
 };
 
+// candidate region start of sweep workgroup b (non-long bins)
+__host__ __device__ __forceinline__ int64_t cand_region_start(const SweepGrid& g, int b, int& bin) {
+  int64_t off = 0;
+  for (bin = 0; bin < BIN_LONG; ++bin) {
+    if (b < g.nb[bin]) return off + (int64_t)b * cand_region(bin);
+    b -= g.nb[bin];
+    off += (int64_t)g.nb[bin] * cand_region(bin);
+  }
+  return -1;  // a long-row chunk: region from its chunk record
+}
+
 // sweep.hip
+void launch_long_stats(const Dev& d, int mode, hipStream_t s);
 void launch_sweep(const Dev& d, const SweepGrid& g, int mode, hipStream_t s);
-void launch_dense(const Dev& d, int mode, hipStream_t s);
-void launch_src(const Dev& d, hipStream_t s);
+void launch_src(const Dev& d, const SweepGrid& g, hipStream_t s);
 void launch_count(const Dev& d, hipStream_t s);
 void launch_emit(const Dev& d, int64_t base, int round, hipStream_t s);
-int dense_chunk_size();
-int dense_max_chunks();
-int wave_max_len();
-int block_max_len();
+int long_max_passes();
 
 // ingest.hip
 struct IngestScratch {
@@ -37,9 +46,17 @@ void launch_check_entries(const Dev& d, const int32_t* rowid1, hipStream_t s);
 void build_rowid(const Dev& d, IngestScratch& sc, hipStream_t s);
 const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, int32_t* col_len, IngestScratch& sc,
                           hipStream_t s);
-// bins: writes bin_rows and per-bin counts (device counts[NBINS])
-void build_bins(const Dev& d, const int32_t* thresholds, int32_t* bin_rows, int32_t* counts, IngestScratch& sc,
+// bins: writes the bin lists and per-bin counts (device counts[NBINS])
+void build_bins(const Dev& d, const int32_t* thresholds, BinEnt* bins, int32_t* counts, IngestScratch& sc,
                 hipStream_t s);
+// keep only active rows in the bin lists and chunk list: new_off[0..NBINS],
+// totals = {kept rows, their nonzeros, kept chunks} (device)
+void rebin(const Dev& d, BinEnt* bins_out, LongChunk* chunks_out, int32_t* keep, int32_t* keep_len, int32_t* ckeep,
+           int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s);
+// chunk table of the long rows (d.nlong set); total chunks to *total (device)
+// totals[0] = chunks, totals[1] = candidate units of all chunks
+void build_long_chunks(const Dev& d, int npass0, LongChunk* chunks, int32_t* cnt, int32_t* cnt2, int32_t* totals,
+                       int32_t* ws, hipStream_t s);
 void launch_round0_count(const Dev& d, hipStream_t s);
 void launch_round0_emit(const Dev& d, int64_t base, hipStream_t s);
 void launch_init_state(const Dev& d, hipStream_t s);
@@ -54,13 +71,14 @@ struct ParScratch {
   int32_t* side_src;  // [2m]
   uint8_t* is_leader; // [m]
   int32_t* vlist;     // [m] rows to verify
-  unsigned long long* hacc;  // [3m] dense-row hash accumulators (h1, h2, L)
+  unsigned long long* hacc;  // [3 * long rows] hash accumulators (h1, h2, L)
 };
 void launch_par_reset(const Dev& d, const ParScratch& p, hipStream_t s);
 void launch_par_hash(const Dev& d, const ParScratch& p, const SweepGrid& g, hipStream_t s);
 void launch_par_verify(const Dev& d, const ParScratch& p, hipStream_t s);
 void launch_par_count(const Dev& d, const ParScratch& p, hipStream_t s);
 void launch_par_emit(const Dev& d, const ParScratch& p, int64_t base, int round, hipStream_t s);
+void launch_par_drop(const Dev& d, const ParScratch& p, hipStream_t s);
 
 // compact.hip
 struct Reduced {

@@ -6,33 +6,34 @@
 // atomic max/min on order-mapped int64 keys; the source row of a final bound
 // is the lowest row whose candidate equals it (resolved from a candidate list
 // after the sweep). Activities are canonical pairwise trees over the row's CSR
-// positions, so every lane grouping below gives the same bits.
+// positions (leaves padded with +0 to a power of two), so every aligned
+// power-of-two grouping of positions -- C contiguous positions per lane, a
+// butterfly over G lanes, four wavefronts, chunk partials -- gives the same
+// bits, whatever bin a row falls in.
 //
-// Rows are binned by CSR length at ingest. One kernel launch sweeps all bins:
-//   bin 0: 4-lane groups (16 rows per wavefront), one pass
-//   bin 1: 16-lane groups (4 rows per wavefront), one pass
-//   bin 2: one wavefront per row, passes of 64 positions
-//   bin 3: one 256-lane workgroup per row, passes of 256 positions
-//   bin 4: dense rows, 8192-position chunks per workgroup (partials here,
-//          combined by k_dense_finish, propagated by k_dense_prop)
+// Bins (by CSR length; rows are listed per bin, ascending):
+//   G4  <= 4     4-lane groups, 1 position per lane
+//   G16 <= 16    16-lane groups, 1 position per lane
+//   W1  <= 64    one wavefront, 1 position per lane
+//   W4  <= 256   one wavefront, 4 contiguous positions per lane
+//   W8  <= 512   one wavefront, 8 contiguous positions per lane
+//   LONG         chunks of npass * 2048 positions, one workgroup each:
+//                k_long_stats writes chunk partials, then k_sweep combines
+//                them in tree order and propagates chunk by chunk.
+// Each row is handled in one pass with its elements kept in registers.
 #include "psl_kern.h"
 #include "sweep.h"
 
 namespace psl {
 
-#define WAVE_MAXP 64      // passes per wavefront row   (bin 2 rows <= 4096)
-#define BLOCK_MAXP 256    // passes per workgroup row   (bin 3 rows <= 65536)
-#define DENSE_CHUNK 8192  // positions per dense chunk  (power of two)
-#define DENSE_MAXCH 2048  // chunks per dense row
 
-struct Elem {
+struct El {
   int j;
-  double a, lb, ub, tmin, tmax;
-  bool v, act, imin, imax;
+  double a, lb, ub;
+  bool v;
 };
 
-template <int MODE>
-__device__ __forceinline__ void load_elem(const Dev& d, int64_t p, bool v, Elem& e) {
+__device__ __forceinline__ void load_el(const Dev& d, int64_t p, bool v, El& e) {
   e.v = v;
   e.j = 0;
   e.a = 0.0;
@@ -45,20 +46,66 @@ __device__ __forceinline__ void load_elem(const Dev& d, int64_t p, bool v, Elem&
     e.lb = b.x;
     e.ub = b.y;
   }
-  e.act = v && (e.lb != e.ub);
+}
+
+__device__ __forceinline__ bool el_active(const El& e) { return e.v && e.lb != e.ub; }
+
+// activity terms of one element and its packed counts
+// (bit 0: infinite min contribution, bit 10: infinite max, bit 20: active)
+template <int MODE>
+__device__ __forceinline__ void el_terms(const El& e, double& tmin, double& tmax, int& cnt) {
+  tmin = tmax = 0.0;
+  cnt = 0;
+  if (!e.v) return;
+  bool act = e.lb != e.ub;
   if (MODE == MODE_ROUND) {
-    if (v) {
-      contrib(e.a, e.lb, e.ub, e.tmin, e.imin, e.tmax, e.imax);
-    } else {
-      e.tmin = e.tmax = 0.0;
-      e.imin = e.imax = false;
-    }
+    bool imin, imax;
+    contrib(e.a, e.lb, e.ub, tmin, imin, tmax, imax);
+    cnt = (imin ? 1 : 0) | (imax ? 1 << 10 : 0) | (act ? 1 << 20 : 0);
   } else {
-    // compaction: the constant of the removed columns, kept-entry count
-    e.imin = e.imax = false;
-    e.tmin = (v && !e.act) ? pos0(e.a * e.lb) : 0.0;
-    e.tmax = 0.0;
+    // compaction: constant of the removed columns; active-entry count
+    tmin = act ? 0.0 : pos0(e.a * e.lb);
+    cnt = act ? 1 << 20 : 0;
   }
+}
+
+__device__ __forceinline__ int cnt_min(int c) { return c & 1023; }
+__device__ __forceinline__ int cnt_max(int c) { return (c >> 10) & 1023; }
+__device__ __forceinline__ int cnt_act(int c) { return c >> 20; }
+
+template <int G>
+__device__ __forceinline__ int group_sum_int(int x) {
+#pragma unroll
+  for (int s = 1; s < G; s <<= 1) x += __shfl_xor(x, s, PSL_WAVE);
+  return x;
+}
+
+// pairwise tree over C values held in registers (C a power of two)
+template <int C>
+__device__ __forceinline__ double lane_tree(double (&x)[C]) {
+#pragma unroll
+  for (int w = 1; w < C; w <<= 1)
+#pragma unroll
+    for (int i = 0; i < C; i += 2 * w) x[i] = x[i] + x[i + w];
+  return x[0];
+}
+
+// load C contiguous positions [base, base + C) of a row and reduce them
+template <int C, int MODE>
+__device__ __forceinline__ void lane_stats(const Dev& d, int64_t s0, int len, int base, El (&e)[C], double& smin,
+                                           double& smax, int& cnt) {
+  double a[C], b[C];
+  cnt = 0;
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    int q = base + k;
+    load_el(d, s0 + q, q < len, e[k]);
+    int c;
+    el_terms<MODE>(e[k], a[k], b[k], c);
+    cnt += c;
+  }
+  smin = lane_tree<C>(a);
+  smax = lane_tree<C>(b);
 }
 
 struct RowDec {
@@ -88,14 +135,19 @@ __device__ __forceinline__ RowDec decide_row(const Cfg& c, double lhs, double rh
   return r;
 }
 
+struct RowStat {
+  double minact, maxact;
+  int nmin, nmax;
+};
+
 // Implied bounds of one active entry from the residual activity (the row's
 // activity with the entry's own contribution taken out). Side 0 uses rhs and
 // the residual min, side 1 lhs and the residual max; a > 0 turns side 0 into an
-// upper bound, a < 0 into a lower bound. cap = false when the entry (in a row
-// with one active column) yields a side that is not turned into a bound.
-__device__ __forceinline__ void prop_elem(const Cfg& c, bool on, const Elem& e, double lhs, double rhs,
-                                          double minact, double maxact, int nmin, int nmax, bool single,
-                                          bool& cap, bool& hlo, double& tlo, bool& hup, double& tup) {
+// upper bound, a < 0 into a lower bound. cap = false when a finite side yields
+// no bound (it matters for rows with one active column, which are removed only
+// when every finite side became a bound).
+__device__ __forceinline__ void prop_el(const Cfg& c, bool on, const El& e, double lhs, double rhs, const RowStat& st,
+                                        bool single, bool& cap, bool& hlo, double& tlo, bool& hup, double& tup) {
   cap = true;
   hlo = hup = false;
   tlo = tup = 0.0;
@@ -104,20 +156,23 @@ __device__ __forceinline__ void prop_elem(const Cfg& c, bool on, const Elem& e, 
     cap = false;
     return;
   }
+  double tmin, tmax;
+  bool imin, imax;
+  contrib(e.a, e.lb, e.ub, tmin, imin, tmax, imax);
   bool hmin = false, hmax = false;
   double rmin = 0.0, rmax = 0.0;
-  if (nmin == 0) {
-    rmin = minact - e.tmin;
+  if (st.nmin == 0) {
+    rmin = st.minact - tmin;
     hmin = true;
-  } else if (nmin == 1 && e.imin) {
-    rmin = minact;
+  } else if (st.nmin == 1 && imin) {
+    rmin = st.minact;
     hmin = true;
   }
-  if (nmax == 0) {
-    rmax = maxact - e.tmax;
+  if (st.nmax == 0) {
+    rmax = st.maxact - tmax;
     hmax = true;
-  } else if (nmax == 1 && e.imax) {
-    rmax = maxact;
+  } else if (st.nmax == 1 && imax) {
+    rmax = st.maxact;
     hmax = true;
   }
 #pragma unroll
@@ -153,16 +208,21 @@ __device__ __forceinline__ void prop_elem(const Cfg& c, bool on, const Elem& e, 
   }
 }
 
+struct CandSink {  // this workgroup's candidate region and its LDS counter
+  Cand* list;
+  int32_t* counter;
+};
+
 // Fold qualifying candidates into the round's accumulators. A candidate that
-// is not better than the value read is not the final one unless equal, so
+// is not better than the value read cannot be the final one unless equal, so
 // only candidates <= (>=) the current value go to the source list.
 // Must be reached by every lane of the wavefront.
-__device__ __forceinline__ void commit_cands(const Dev& d, int row, int j, bool hlo, double tlo, bool hup,
-                                             double tup) {
+__device__ __forceinline__ void commit_cands(const Dev& d, const CandSink& sk, int row, int j, bool hlo, double tlo,
+                                             bool hup, double tup) {
   bool alo = false, aup = false;
   if (hlo) {
     long long* k = &d.bkey[2 * (int64_t)j];
-    double cur = dunkey(__atomic_load_n(k, __ATOMIC_RELAXED));
+    double cur = dunkey(*k);  // may be stale (larger): only costs an extra atomic
     if (tlo >= cur) {
       alo = true;
       if (tlo > cur) atomicMax(k, dkey(tlo));
@@ -170,60 +230,129 @@ __device__ __forceinline__ void commit_cands(const Dev& d, int row, int j, bool 
   }
   if (hup) {
     long long* k = &d.bkey[2 * (int64_t)j + 1];
-    double cur = dunkey(__atomic_load_n(k, __ATOMIC_RELAXED));
+    double cur = dunkey(*k);
     if (tup <= cur) {
       aup = true;
       if (tup < cur) atomicMin(k, dkey(tup));
     }
   }
-  wave_append(alo, Cand{2 * j, row, tlo}, d.cand, &d.flags->cand_count);
-  wave_append(aup, Cand{2 * j + 1, row, tup}, d.cand, &d.flags->cand_count);
+  wave_append(alo, Cand{2 * j, row, tlo}, sk.list, sk.counter);
+  wave_append(aup, Cand{2 * j + 1, row, tup}, sk.list, sk.counter);
 }
 
-__device__ __forceinline__ RowOut row_out_of(uint8_t code, double minact, double maxact, int nmin, int nmax) {
+__device__ __forceinline__ RowOut row_out_of(uint8_t code, const RowStat& st) {
   RowOut o;
   o.j = -1;
   o.pad = 0;
   if (code == RC_EMPTY) {
-    o.v0 = minact;
+    o.v0 = st.minact;
     o.v1 = 0.0;
   } else {
-    o.v0 = nmin ? -__builtin_huge_val() : minact;
-    o.v1 = nmax ? __builtin_huge_val() : maxact;
+    o.v0 = st.nmin ? -__builtin_huge_val() : st.minact;
+    o.v1 = st.nmax ? __builtin_huge_val() : st.maxact;
   }
   return o;
 }
 
+// propagate the C register-held elements of a lane; tracks the one active
+// element of a row with L == 1 and whether some entry left a side unbounded
+template <int C>
+__device__ __forceinline__ void lane_prop(const Dev& d, const CandSink& sk, int row, bool prop, const El (&e)[C],
+                                          double lhs, double rhs,
+                                          const RowStat& st, bool single, bool& uncap, bool& mine, int& aj,
+                                          double& aa) {
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    bool act = prop && el_active(e[k]);
+    bool cap, hlo, hup;
+    double tlo, tup;
+    prop_el(d.cfg, act, e[k], lhs, rhs, st, single, cap, hlo, tlo, hup, tup);
+    commit_cands(d, sk, row, e[k].j, hlo, tlo, hup, tup);
+    if (act && !cap) uncap = true;
+    if (act) {
+      mine = true;
+      aj = e[k].j;
+      aa = e[k].a;
+    }
+  }
+}
+
+// the same, loading each element as it goes (two at a time), so that wide
+// lanes do not keep C elements live
+template <int C>
+__device__ __forceinline__ void lane_prop_stream(const Dev& d, const CandSink& sk, int row, bool prop, int64_t s0,
+                                                 int len, int base, double lhs, double rhs, const RowStat& st,
+                                                 bool single, bool& uncap, bool& mine, int& aj, double& aa) {
+#pragma unroll 2
+  for (int k = 0; k < C; ++k) {
+    El e;
+    load_el(d, s0 + base + k, prop && base + k < len, e);
+    bool act = el_active(e);
+    bool cap, hlo, hup;
+    double tlo, tup;
+    prop_el(d.cfg, act, e, lhs, rhs, st, single, cap, hlo, tlo, hup, tup);
+    commit_cands(d, sk, row, e.j, hlo, tlo, hup, tup);
+    if (act && !cap) uncap = true;
+    if (act) {
+      mine = true;
+      aj = e.j;
+      aa = e.a;
+    }
+  }
+}
+
+template <int C>
+__device__ __forceinline__ void lane_drop_stream(const Dev& d, bool on, int64_t s0, int len, int base) {
+#pragma unroll 2
+  for (int k = 0; k < C; ++k) {
+    El e;
+    load_el(d, s0 + base + k, on && base + k < len, e);
+    if (el_active(e)) atomicSub(&d.col_len[e.j], 1);
+  }
+}
+
+template <int C>
+__device__ __forceinline__ void lane_drop(const Dev& d, const El (&e)[C]) {
+#pragma unroll
+  for (int k = 0; k < C; ++k)
+    if (el_active(e[k])) atomicSub(&d.col_len[e[k].j], 1);
+}
+
 // ---------------------------------------------------------------------------
-// bins 0 and 1: G-lane groups, a row in one pass
+// rows of at most G*C entries: one G-lane group per row, C positions per lane
 // ---------------------------------------------------------------------------
-template <int G, int MODE>
-__device__ __forceinline__ void sweep_groups(const Dev& d, int bin, int lblock) {
+template <int G, int C, int MODE>
+__device__ __forceinline__ void sweep_rows(const Dev& d, const CandSink& sk, int bin, int lblock) {
   const int per_block = PSL_BLOCK / G;
   int gid = lblock * per_block + (int)(threadIdx.x / G);
   int count = d.bin_off[bin + 1] - d.bin_off[bin];
   bool vr = gid < count;
-  int row = vr ? d.bin_rows[d.bin_off[bin] + gid] : 0;
-  int gl = threadIdx.x & (G - 1);
+  int row = 0;
   int64_t s0 = 0;
   int len = 0;
   bool on = false;
   if (vr) {
-    s0 = d.rp[row];
-    len = d.rp[row + 1] - (int)s0;
+    BinEnt be = d.bins[d.bin_off[bin] + gid];
+    row = be.row;
+    s0 = be.start;
+    len = be.len;
     on = d.row_on[row] != 0;
   }
-  Elem e;
-  load_elem<MODE>(d, s0 + gl, on && gl < len, e);
-  double minact = group_sum<G>(e.tmin);
-  double maxact = group_sum<G>(e.tmax);
-  unsigned long long gm = group_mask<G>();
-  int nmin = __popcll(__ballot(e.v && e.imin) & gm);
-  int nmax = __popcll(__ballot(e.v && e.imax) & gm);
-  int L = __popcll(__ballot(e.act) & gm);
+  int gl = threadIdx.x & (G - 1);
+  El e[C];
+  double smin, smax;
+  int cnt;
+  lane_stats<C, MODE>(d, s0, on ? len : 0, gl * C, e, smin, smax, cnt);
+  RowStat st;
+  st.minact = group_sum<G>(smin);
+  st.maxact = group_sum<G>(smax);
+  cnt = group_sum_int<G>(cnt);
+  st.nmin = cnt_min(cnt);
+  st.nmax = cnt_max(cnt);
+  int L = cnt_act(cnt);
   if (MODE == MODE_COMPACT) {
     if (vr && gl == 0) {
-      d.row_out[row].v0 = minact;
+      d.row_out[row].v0 = st.minact;
       d.row_out[row].j = on ? L : 0;
     }
     return;
@@ -234,13 +363,15 @@ __device__ __forceinline__ void sweep_groups(const Dev& d, int bin, int lblock) 
     lhs = d.lhs[row];
     rhs = d.rhs[row];
   }
-  RowDec dec = decide_row(d.cfg, lhs, rhs, L, nmin, nmax, minact, maxact);
+  RowDec dec = decide_row(d.cfg, lhs, rhs, L, st.nmin, st.nmax, st.minact, st.maxact);
   bool prop = live && dec.prop;
-  bool cap, hlo, hup;
-  double tlo, tup;
-  prop_elem(d.cfg, prop && e.act, e, lhs, rhs, minact, maxact, nmin, nmax, dec.single, cap, hlo, tlo, hup, tup);
-  commit_cands(d, row, e.j, hlo, tlo, hup, tup);
-  bool captured = (__ballot(prop && e.act && !cap) & gm) == 0;
+  bool uncap = false, mine = false;
+  int aj = 0;
+  double aa = 0.0;
+  if (C == 1) lane_prop<C>(d, sk, row, prop, e, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
+  else  // reload (L1/L2 hits) instead of keeping C elements live through the sums
+    lane_prop_stream<C>(d, sk, row, prop, s0, len, gl * C, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
+  bool captured = (__ballot(uncap) & group_mask<G>()) == 0;
   uint8_t code = RC_KEEP;
   if (live) {
     code = dec.code;
@@ -248,417 +379,263 @@ __device__ __forceinline__ void sweep_groups(const Dev& d, int bin, int lblock) 
     if (dec.infeasible && gl == 0) atomicOr(&d.flags->infeasible, 1);
   }
   if (vr && gl == 0) d.row_code[row] = code;
-  if (live && gl == 0 && (code == RC_EMPTY || code == RC_REDUNDANT))
-    d.row_out[row] = row_out_of(code, minact, maxact, nmin, nmax);
-  if (live && code == RC_SINGLETON && e.act) d.row_out[row] = RowOut{e.a, 0.0, e.j, 0};
-  if (live && code != RC_KEEP && e.act) atomicSub(&d.col_len[e.j], 1);
-}
-
-// ---------------------------------------------------------------------------
-// bin 2: one wavefront per row, passes of 64 positions
-// ---------------------------------------------------------------------------
-template <int MODE>
-__device__ __forceinline__ void sweep_wave(const Dev& d, int lblock, double* lds) {
-  const int bin = BIN_WAVE;
-  int w = threadIdx.x >> 6, lane = lane_id();
-  int wid = lblock * (PSL_BLOCK / PSL_WAVE) + w;
-  int count = d.bin_off[bin + 1] - d.bin_off[bin];
-  if (wid >= count) return;  // whole wavefront
-  double* ps = lds + w * 2 * WAVE_MAXP;
-  int row = d.bin_rows[d.bin_off[bin] + wid];
-  int64_t s0 = d.rp[row];
-  int len = d.rp[row + 1] - (int)s0;
-  bool on = d.row_on[row] != 0;
-  int np = on ? (len + PSL_WAVE - 1) / PSL_WAVE : 0;
-  int nmin = 0, nmax = 0, L = 0;
-  for (int p = 0; p < np; ++p) {
-    int q = p * PSL_WAVE + lane;
-    Elem e;
-    load_elem<MODE>(d, s0 + q, q < len, e);
-    double a = group_sum<PSL_WAVE>(e.tmin);
-    double b = group_sum<PSL_WAVE>(e.tmax);
-    if (lane == 0) {
-      ps[p] = a;
-      ps[WAVE_MAXP + p] = b;
-    }
-    nmin += __popcll(__ballot(e.v && e.imin));
-    nmax += __popcll(__ballot(e.v && e.imax));
-    L += __popcll(__ballot(e.act));
-  }
-  double minact = 0.0, maxact = 0.0;
-  if (lane == 0) {
-    minact = tree_inplace(ps, np);
-    maxact = tree_inplace(ps + WAVE_MAXP, np);
-  }
-  minact = __shfl(minact, 0, PSL_WAVE);
-  maxact = __shfl(maxact, 0, PSL_WAVE);
-  if (MODE == MODE_COMPACT) {
-    if (lane == 0) {
-      d.row_out[row].v0 = minact;
-      d.row_out[row].j = on ? L : 0;
-    }
-    return;
-  }
-  if (!on) {
-    if (lane == 0) d.row_code[row] = RC_KEEP;
-    return;
-  }
-  double lhs = d.lhs[row], rhs = d.rhs[row];
-  RowDec dec = decide_row(d.cfg, lhs, rhs, L, nmin, nmax, minact, maxact);
-  bool uncap = false, mine = false;
-  int aj = 0;
-  double aa = 0.0;
-  if (dec.prop) {
-    for (int p = 0; p < np; ++p) {
-      int q = p * PSL_WAVE + lane;
-      Elem e;
-      load_elem<MODE>(d, s0 + q, q < len, e);
-      bool cap, hlo, hup;
-      double tlo, tup;
-      prop_elem(d.cfg, e.act, e, lhs, rhs, minact, maxact, nmin, nmax, dec.single, cap, hlo, tlo, hup, tup);
-      commit_cands(d, row, e.j, hlo, tlo, hup, tup);
-      uncap |= __ballot(e.act && !cap) != 0;
-      if (e.act) {
-        mine = true;
-        aj = e.j;
-        aa = e.a;
-      }
-    }
-  }
-  uint8_t code = dec.code;
-  if (dec.prop && dec.single && !dec.infeasible && !uncap) code = RC_SINGLETON;
-  if (lane == 0) {
-    d.row_code[row] = code;
-    if (dec.infeasible) atomicOr(&d.flags->infeasible, 1);
-    if (code == RC_EMPTY || code == RC_REDUNDANT) d.row_out[row] = row_out_of(code, minact, maxact, nmin, nmax);
-  }
+  if (live && gl == 0 && (code == RC_EMPTY || code == RC_REDUNDANT)) d.row_out[row] = row_out_of(code, st);
   if (code == RC_SINGLETON && mine) {
     d.row_out[row] = RowOut{aa, 0.0, aj, 0};
     atomicSub(&d.col_len[aj], 1);
   }
   if (code == RC_REDUNDANT) {
-    for (int p = 0; p < np; ++p) {
-      int q = p * PSL_WAVE + lane;
-      if (q < len) {
-        int j = d.ci[s0 + q];
-        double2 b = d.bnd[j];
-        if (b.x != b.y) atomicSub(&d.col_len[j], 1);
-      }
-    }
+    if (C == 1) lane_drop<C>(d, e);
+    else lane_drop_stream<C>(d, live, s0, len, gl * C);
   }
 }
 
 // ---------------------------------------------------------------------------
-// workgroup-wide pass sums (bins 3 and 4)
+// long rows: workgroup passes of 2048 positions (8 contiguous per thread)
 // ---------------------------------------------------------------------------
 
-// Sum of 256 consecutive positions: wavefront butterflies, then
-// (w0 + w1) + (w2 + w3). Returns the pass sums in every thread via LDS.
-__device__ __forceinline__ void block_pass_sum(double a, double b, double* wl, double& sa, double& sb) {
-  int w = threadIdx.x >> 6;
+// sums of one pass: (w0 + w1) + (w2 + w3) over the wavefront butterflies
+template <int MODE>
+__device__ __forceinline__ void pass_stats(const Dev& d, int64_t s0, int len, int base, El (&e)[8], double* wl,
+                                           int* il, double& psmin, double& psmax, int& nmin, int& nmax, int& L) {
+  double a, b;
+  int c;
+  lane_stats<8, MODE>(d, s0, len, base + (int)threadIdx.x * 8, e, a, b, c);
   a = group_sum<PSL_WAVE>(a);
   b = group_sum<PSL_WAVE>(b);
+  c = group_sum_int<PSL_WAVE>(c);
+  int w = threadIdx.x >> 6;
   if (lane_id() == 0) {
     wl[w] = a;
     wl[4 + w] = b;
+    il[w] = c;
   }
   __syncthreads();
-  sa = (wl[0] + wl[1]) + (wl[2] + wl[3]);
-  sb = (wl[4] + wl[5]) + (wl[6] + wl[7]);
-  __syncthreads();
-}
-
-__device__ __forceinline__ int block_count(bool pred, int* il) {
-  int c = __popcll(__ballot(pred));
-  int w = threadIdx.x >> 6;
-  if (lane_id() == 0) il[w] = c;
-  __syncthreads();
-  int s = il[0] + il[1] + il[2] + il[3];
-  __syncthreads();
-  return s;
-}
-
-// stats over positions [first, first + 256*np) of the row, pass by pass
-template <int MODE>
-__device__ __forceinline__ void block_stats(const Dev& d, int64_t s0, int len, int first, int np, double* ps,
-                                            int psmax, double* wl, int* il, double& minact, double& maxact,
-                                            int& nmin, int& nmax, int& L) {
+  psmin = (wl[0] + wl[1]) + (wl[2] + wl[3]);
+  psmax = (wl[4] + wl[5]) + (wl[6] + wl[7]);
   nmin = nmax = L = 0;
-  for (int p = 0; p < np; ++p) {
-    int q = first + p * PSL_BLOCK + (int)threadIdx.x;
-    Elem e;
-    load_elem<MODE>(d, s0 + q, q < len, e);
-    double sa, sb;
-    block_pass_sum(e.tmin, e.tmax, wl, sa, sb);
-    if (threadIdx.x == 0) {
-      ps[p] = sa;
-      ps[psmax + p] = sb;
-    }
-    nmin += block_count(e.v && e.imin, il);
-    nmax += block_count(e.v && e.imax, il);
-    L += block_count(e.act, il);
-  }
-  if (threadIdx.x == 0) {
-    wl[0] = tree_inplace(ps, np);
-    wl[1] = tree_inplace(ps + psmax, np);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    nmin += cnt_min(il[k]);
+    nmax += cnt_max(il[k]);
+    L += cnt_act(il[k]);
   }
   __syncthreads();
-  minact = wl[0];
-  maxact = wl[1];
-  __syncthreads();
 }
 
-// propagation / removal bookkeeping over positions [first, first+256*np)
+// partial statistics of one chunk (its passes combined in tree order)
 template <int MODE>
-__device__ __forceinline__ void block_apply(const Dev& d, int row, int64_t s0, int len, int first, int np,
-                                            const RowDec& dec, double lhs, double rhs, double minact,
-                                            double maxact, int nmin, int nmax, bool& uncap_any, bool& mine,
-                                            int& aj, double& aa, int* il) {
-  uncap_any = false;
-  mine = false;
-  aj = 0;
-  aa = 0.0;
-  if (dec.prop) {
-    bool unc = false;
-    for (int p = 0; p < np; ++p) {
-      int q = first + p * PSL_BLOCK + (int)threadIdx.x;
-      Elem e;
-      load_elem<MODE>(d, s0 + q, q < len, e);
-      bool cap, hlo, hup;
-      double tlo, tup;
-      prop_elem(d.cfg, e.act, e, lhs, rhs, minact, maxact, nmin, nmax, dec.single, cap, hlo, tlo, hup, tup);
-      commit_cands(d, row, e.j, hlo, tlo, hup, tup);
-      unc |= e.act && !cap;
-      if (e.act) {
-        mine = true;
-        aj = e.j;
-        aa = e.a;
-      }
-    }
-    uncap_any = block_count(unc, il) > 0;
-  } else if (dec.code == RC_REDUNDANT) {
-    for (int p = 0; p < np; ++p) {
-      int q = first + p * PSL_BLOCK + (int)threadIdx.x;
-      if (q < len) {
-        int j = d.ci[s0 + q];
-        double2 b = d.bnd[j];
-        if (b.x != b.y) atomicSub(&d.col_len[j], 1);
-      }
-    }
-  }
-}
-
-// bin 3: one workgroup per row
-template <int MODE>
-__device__ __forceinline__ void sweep_block(const Dev& d, int lblock, double* lds) {
-  const int bin = BIN_BLOCK;
-  double* ps = lds;
-  double* wl = lds + 2 * BLOCK_MAXP;
-  int* il = (int*)(wl + 8);
-  int row = d.bin_rows[d.bin_off[bin] + lblock];
-  int64_t s0 = d.rp[row];
-  int len = d.rp[row + 1] - (int)s0;
-  bool on = d.row_on[row] != 0;
-  int np = on ? (len + PSL_BLOCK - 1) / PSL_BLOCK : 0;
-  double minact, maxact;
-  int nmin, nmax, L;
-  block_stats<MODE>(d, s0, len, 0, np, ps, BLOCK_MAXP, wl, il, minact, maxact, nmin, nmax, L);
-  if (MODE == MODE_COMPACT) {
-    if (threadIdx.x == 0) {
-      d.row_out[row].v0 = minact;
-      d.row_out[row].j = on ? L : 0;
-    }
-    return;
-  }
-  if (!on) {
-    if (threadIdx.x == 0) d.row_code[row] = RC_KEEP;
-    return;
-  }
-  double lhs = d.lhs[row], rhs = d.rhs[row];
-  RowDec dec = decide_row(d.cfg, lhs, rhs, L, nmin, nmax, minact, maxact);
-  bool uncap, mine;
-  int aj;
-  double aa;
-  block_apply<MODE>(d, row, s0, len, 0, np, dec, lhs, rhs, minact, maxact, nmin, nmax, uncap, mine, aj, aa, il);
-  uint8_t code = dec.code;
-  if (dec.prop && dec.single && !dec.infeasible && !uncap) code = RC_SINGLETON;
-  if (threadIdx.x == 0) {
-    d.row_code[row] = code;
-    if (dec.infeasible) atomicOr(&d.flags->infeasible, 1);
-    if (code == RC_EMPTY || code == RC_REDUNDANT) d.row_out[row] = row_out_of(code, minact, maxact, nmin, nmax);
-  }
-  if (code == RC_SINGLETON && mine) {
-    d.row_out[row] = RowOut{aa, 0.0, aj, 0};
-    atomicSub(&d.col_len[aj], 1);
-  }
-}
-
-// bin 4 (first launch): partial statistics of one dense chunk
-template <int MODE>
-__device__ __forceinline__ void sweep_dense_part(const Dev& d, int chunk, double* lds) {
-  double* ps = lds;
-  const int cmax = DENSE_CHUNK / PSL_BLOCK;
-  double* wl = lds + 2 * cmax;
-  int* il = (int*)(wl + 8);
-  DenseChunk ch = d.dchunk[chunk];
-  int row = ch.row;
-  int64_t s0 = d.rp[row];
-  int len = d.rp[row + 1] - (int)s0;
-  bool on = d.row_on[row] != 0;
-  int rem = len - ch.first;
-  int np = on ? min(cmax, (rem + PSL_BLOCK - 1) / PSL_BLOCK) : 0;
-  double smin, smax;
-  int nmin, nmax, L;
-  block_stats<MODE>(d, s0, len, ch.first, np, ps, cmax, wl, il, smin, smax, nmin, nmax, L);
-  if (threadIdx.x == 0) {
-    DensePart pt;
-    pt.smin = smin;
-    pt.smax = smax;
-    pt.nmin = nmin;
-    pt.nmax = nmax;
-    pt.L = L;
-    pt.pad = 0;
-    d.dpart[chunk] = pt;
-  }
-}
-
-template <int MODE>
-__global__ void __launch_bounds__(PSL_BLOCK) k_sweep(Dev d, SweepGrid g) {
-  __shared__ double lds[2 * BLOCK_MAXP + 16];
-  int b = blockIdx.x;
-  if (b < g.nb[0]) {
-    sweep_groups<4, MODE>(d, BIN_G4, b);
-    return;
-  }
-  b -= g.nb[0];
-  if (b < g.nb[1]) {
-    sweep_groups<16, MODE>(d, BIN_G16, b);
-    return;
-  }
-  b -= g.nb[1];
-  if (b < g.nb[2]) {
-    sweep_wave<MODE>(d, b, lds);
-    return;
-  }
-  b -= g.nb[2];
-  if (b < g.nb[3]) {
-    sweep_block<MODE>(d, b, lds);
-    return;
-  }
-  b -= g.nb[3];
-  if (b < g.nb[4]) sweep_dense_part<MODE>(d, b, lds);
-}
-
-// combine the chunk partials of each dense row in tree order, then decide
-template <int MODE>
-__global__ void __launch_bounds__(PSL_BLOCK) k_dense_finish(Dev d) {
-  __shared__ double ps[2 * DENSE_MAXCH];
-  __shared__ int cnt[3];
-  DenseRow& dr = d.drow[blockIdx.x];
-  int row = dr.row;
-  int nch = dr.nchunk;
-  if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  int a = 0, b = 0, l = 0;
-  for (int k = threadIdx.x; k < nch; k += PSL_BLOCK) {
-    DensePart pt = d.dpart[dr.chunk0 + k];
-    ps[k] = pt.smin;
-    ps[DENSE_MAXCH + k] = pt.smax;
-    a += pt.nmin;
-    b += pt.nmax;
-    l += pt.L;
-  }
-  atomicAdd(&cnt[0], a);
-  atomicAdd(&cnt[1], b);
-  atomicAdd(&cnt[2], l);
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  // chunk offsets of kept entries (used by compaction's gather)
-  if (MODE == MODE_COMPACT) {
-    int run = 0;
-    for (int k = 0; k < nch; ++k) {
-      int lk = d.dpart[dr.chunk0 + k].L;
-      d.dpart[dr.chunk0 + k].pad = run;
-      run += lk;
-    }
-  }
-  bool on = d.row_on[row] != 0;
-  double minact = tree_inplace(ps, nch);
-  double maxact = tree_inplace(ps + DENSE_MAXCH, nch);
-  int nmin = cnt[0], nmax = cnt[1], L = cnt[2];
-  if (MODE == MODE_COMPACT) {
-    d.row_out[row].v0 = minact;
-    d.row_out[row].j = on ? L : 0;
-    return;
-  }
-  dr.minact = minact;
-  dr.maxact = maxact;
-  dr.nmin = nmin;
-  dr.nmax = nmax;
-  dr.L = L;
-  if (!on) {
-    dr.keep = 0;
-    d.row_code[row] = RC_KEEP;
-    return;
-  }
-  RowDec dec = decide_row(d.cfg, d.lhs[row], d.rhs[row], L, nmin, nmax, minact, maxact);
-  dr.keep = dec.code == RC_KEEP ? (dec.infeasible ? 3 : 1) : (dec.code == RC_REDUNDANT ? 2 : 0);
-  d.row_code[row] = dec.code;
-  if (dec.infeasible) atomicOr(&d.flags->infeasible, 1);
-  if (dec.code == RC_EMPTY || dec.code == RC_REDUNDANT)
-    d.row_out[row] = row_out_of(dec.code, minact, maxact, nmin, nmax);
-}
-
-// propagation (or removal bookkeeping) over one dense chunk
-__global__ void __launch_bounds__(PSL_BLOCK) k_dense_prop(Dev d) {
+__global__ void __launch_bounds__(PSL_BLOCK) k_long_stats(Dev d) {
+  __shared__ double ps[2 * LONG_MAX_PASSES];
+  __shared__ double wl[8];
   __shared__ int il[4];
-  DenseChunk ch = d.dchunk[blockIdx.x];
-  const DenseRow& dr = d.drow[ch.drow];
-  if (!d.row_on[ch.row]) return;
+  LongChunk ch = d.lchunk[blockIdx.x];
   int row = ch.row;
+  if (!d.row_on[row]) return;
   int64_t s0 = d.rp[row];
   int len = d.rp[row + 1] - (int)s0;
-  int rem = len - ch.first;
-  int np = min(DENSE_CHUNK / PSL_BLOCK, (rem + PSL_BLOCK - 1) / PSL_BLOCK);
-  RowDec dec;
-  dec.code = dr.keep == 2 ? RC_REDUNDANT : (dr.keep == 0 ? RC_EMPTY : RC_KEEP);
-  dec.infeasible = dr.keep == 3;
-  dec.prop = dr.keep == 1 || dr.keep == 3;
-  dec.single = dr.L == 1;
-  double lhs = d.lhs[row], rhs = d.rhs[row];
-  bool uncap, mine;
-  int aj;
-  double aa;
-  block_apply<MODE_ROUND>(d, row, s0, len, ch.first, np, dec, lhs, rhs, dr.minact, dr.maxact, dr.nmin, dr.nmax,
-                          uncap, mine, aj, aa, il);
-  // a dense row with one active column: the chunk holding it decides
-  if (dec.prop && dec.single && !dec.infeasible && mine) {
-    bool cap, hlo, hup;
-    double tlo, tup;
-    Elem e;
-    e.a = aa;
-    e.j = aj;
-    double2 bb = d.bnd[aj];
-    e.lb = bb.x;
-    e.ub = bb.y;
-    e.v = e.act = true;
-    contrib(e.a, e.lb, e.ub, e.tmin, e.imin, e.tmax, e.imax);
-    prop_elem(d.cfg, true, e, lhs, rhs, dr.minact, dr.maxact, dr.nmin, dr.nmax, true, cap, hlo, tlo, hup, tup);
-    if (cap) {
-      d.row_code[row] = RC_SINGLETON;
-      d.row_out[row] = RowOut{aa, 0.0, aj, 0};
-      atomicSub(&d.col_len[aj], 1);
+  int tmin = 0, tmax = 0, tl = 0;
+  int np = ch.npass;
+  for (int p = 0; p < np; ++p) {
+    El e[8];
+    double a, b;
+    int x, y, z;
+    pass_stats<MODE>(d, s0, len, ch.first + p * PASS_LEN, e, wl, il, a, b, x, y, z);
+    if (threadIdx.x == 0) {
+      ps[p] = a;
+      ps[LONG_MAX_PASSES + p] = b;
     }
+    tmin += x;
+    tmax += y;
+    tl += z;
+  }
+  if (threadIdx.x == 0) {
+    LongPart pt;
+    pt.smin = tree_inplace(ps, np);
+    pt.smax = tree_inplace(ps + LONG_MAX_PASSES, np);
+    pt.nmin = tmin;
+    pt.nmax = tmax;
+    pt.L = tl;
+    pt.pad = 0;
+    d.lpart[ch.id] = pt;
+  }
+}
+
+// row totals from the chunk partials: one wavefront, 8 chunks per lane
+__device__ __forceinline__ void long_totals(const Dev& d, const LongRow& lr, RowStat& st, int& L) {
+  double a[8], b[8];
+  int n0 = 0, n1 = 0, n2 = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    int c = lane_id() * 8 + k;
+    a[k] = b[k] = 0.0;
+    if (c < lr.nchunk) {
+      LongPart pt = d.lpart[lr.chunk0 + c];
+      a[k] = pt.smin;
+      b[k] = pt.smax;
+      n0 += pt.nmin;
+      n1 += pt.nmax;
+      n2 += pt.L;
+    }
+  }
+  st.minact = group_sum<PSL_WAVE>(lane_tree<8>(a));
+  st.maxact = group_sum<PSL_WAVE>(lane_tree<8>(b));
+  st.nmin = group_sum_int<PSL_WAVE>(n0);
+  st.nmax = group_sum_int<PSL_WAVE>(n1);
+  L = group_sum_int<PSL_WAVE>(n2);
+}
+
+// decisions and propagation over one chunk of a long row
+__device__ __forceinline__ void sweep_long_chunk(const Dev& d, const CandSink& sk, int chunk, double* lds) {
+  LongChunk ch = d.lchunk[chunk];
+  int row = ch.row;
+  if (!d.row_on[row]) {
+    if (ch.first == 0 && threadIdx.x == 0) d.row_code[row] = RC_KEEP;
+    return;
+  }
+  LongRow lr = d.lrow[ch.lrow];
+  int* li = (int*)(lds + 2);
+  if (threadIdx.x < PSL_WAVE) {
+    RowStat st;
+    int L;
+    long_totals(d, lr, st, L);
+    if (threadIdx.x == 0) {
+      lds[0] = st.minact;
+      lds[1] = st.maxact;
+      li[0] = st.nmin;
+      li[1] = st.nmax;
+      li[2] = L;
+    }
+  }
+  __syncthreads();
+  RowStat st;
+  st.minact = lds[0];
+  st.maxact = lds[1];
+  st.nmin = li[0];
+  st.nmax = li[1];
+  int L = li[2];
+  int64_t s0 = d.rp[row];
+  int len = d.rp[row + 1] - (int)s0;
+  double lhs = d.lhs[row], rhs = d.rhs[row];
+  RowDec dec = decide_row(d.cfg, lhs, rhs, L, st.nmin, st.nmax, st.minact, st.maxact);
+  bool uncap = false, mine = false;
+  int aj = 0;
+  double aa = 0.0;
+  for (int p = 0; p < ch.npass; ++p) {
+    int base = ch.first + p * PASS_LEN + (int)threadIdx.x * 8;
+    if (dec.prop) lane_prop_stream<8>(d, sk, row, true, s0, len, base, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
+    else if (dec.code == RC_REDUNDANT) lane_drop_stream<8>(d, true, s0, len, base);
+  }
+  if (dec.prop && dec.single && !dec.infeasible) {
+    // the one active entry decides whether its row becomes bounds
+    if (mine) {
+      if (!uncap) {
+        d.row_code[row] = RC_SINGLETON;
+        d.row_out[row] = RowOut{aa, 0.0, aj, 0};
+        atomicSub(&d.col_len[aj], 1);
+      } else {
+        d.row_code[row] = RC_KEEP;
+      }
+    }
+  } else if (ch.first == 0 && threadIdx.x == 0) {
+    d.row_code[row] = dec.code;
+    if (dec.infeasible) atomicOr(&d.flags->infeasible, 1);
+    if (dec.code == RC_EMPTY || dec.code == RC_REDUNDANT) d.row_out[row] = row_out_of(dec.code, st);
+  }
+}
+
+__device__ __forceinline__ int long_first_block(const SweepGrid& g) {
+  int b = 0;
+  for (int k = 0; k < BIN_LONG; ++k) b += g.nb[k];
+  return b;
+}
+
+// Three launches per sweep, by register need: (0) 4/16/64-lane group bins
+// with one position per lane, (1) wavefront bins with 4 or 8 positions per
+// lane, (2) long-row chunks. Workgroups keep one global numbering across the
+// launches (candidate regions and counts are indexed by it).
+enum { KIND_SHORT = 0, KIND_WIDE = 1, KIND_LONG = 2, KIND_ALL = 3 };
+
+template <int MODE, int KIND>
+__global__ void __launch_bounds__(PSL_BLOCK) k_sweep(Dev d, SweepGrid g, int base) {
+  __shared__ double lds[8];
+  __shared__ int32_t lcount;
+  if (threadIdx.x == 0) lcount = 0;
+  __syncthreads();
+  int gb = blockIdx.x + base;  // global workgroup number
+  int b = gb;
+  int bin;
+  int64_t start = cand_region_start(g, b, bin);
+  int lfb = long_first_block(g);
+  if (MODE == MODE_ROUND && (KIND == KIND_LONG || (KIND == KIND_ALL && b >= lfb)))
+    start = g.long_base + (int64_t)d.lchunk[b - lfb].cand_off;
+  CandSink sk{d.cand + (start < 0 ? 0 : start), &lcount};
+  if (KIND == KIND_ALL) {
+    if (b < g.nb[BIN_G4]) {
+      sweep_rows<4, 1, MODE>(d, sk, BIN_G4, b);
+    } else if ((b -= g.nb[BIN_G4]) < g.nb[BIN_G16]) {
+      sweep_rows<16, 1, MODE>(d, sk, BIN_G16, b);
+    } else if ((b -= g.nb[BIN_G16]) < g.nb[BIN_W1]) {
+      sweep_rows<64, 1, MODE>(d, sk, BIN_W1, b);
+    } else if ((b -= g.nb[BIN_W1]) < g.nb[BIN_W4]) {
+      sweep_rows<64, 4, MODE>(d, sk, BIN_W4, b);
+    } else if ((b -= g.nb[BIN_W4]) < g.nb[BIN_W8]) {
+      sweep_rows<64, 8, MODE>(d, sk, BIN_W8, b);
+    } else if (MODE == MODE_ROUND) {
+      sweep_long_chunk(d, sk, gb - lfb, lds);
+    }
+  } else if (KIND == KIND_SHORT) {
+    if (b < g.nb[BIN_G4]) {
+      sweep_rows<4, 1, MODE>(d, sk, BIN_G4, b);
+    } else if ((b -= g.nb[BIN_G4]) < g.nb[BIN_G16]) {
+      sweep_rows<16, 1, MODE>(d, sk, BIN_G16, b);
+    } else {
+      b -= g.nb[BIN_G16];
+      sweep_rows<64, 1, MODE>(d, sk, BIN_W1, b);
+    }
+  } else if (KIND == KIND_WIDE) {
+    b -= g.nb[BIN_G4] + g.nb[BIN_G16] + g.nb[BIN_W1];
+    if (b < g.nb[BIN_W4]) sweep_rows<64, 4, MODE>(d, sk, BIN_W4, b);
+    else sweep_rows<64, 8, MODE>(d, sk, BIN_W8, b - g.nb[BIN_W4]);
+  } else if (MODE == MODE_ROUND) {
+    sweep_long_chunk(d, sk, b - lfb, lds);
+  }
+  if (MODE == MODE_ROUND) {
+    __syncthreads();
+    if (threadIdx.x == 0) d.cand_cnt[gb] = lcount;
+  }
+}
+
+// compaction: a long row's constant and active length from its partials
+__global__ void __launch_bounds__(PSL_BLOCK) k_long_finish_compact(Dev d) {
+  int k = blockIdx.x * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6);
+  if (k >= d.nlong) return;
+  LongRow lr = d.lrow[k];
+  bool on = d.row_on[lr.row] != 0;
+  RowStat st;
+  int L = 0;
+  if (on) long_totals(d, lr, st, L);
+  else st.minact = 0.0;
+  if (lane_id() == 0) {
+    d.row_out[lr.row].v0 = st.minact;
+    d.row_out[lr.row].j = on ? L : 0;
   }
 }
 
 // ---------------------------------------------------------------------------
 // source rows of the final bounds
 // ---------------------------------------------------------------------------
-__global__ void k_src(Dev d) {
-  int n = d.flags->cand_count;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    Cand c = d.cand[i];
+// one workgroup per sweep workgroup: its candidate region
+__global__ void __launch_bounds__(PSL_BLOCK) k_src(Dev d, SweepGrid g) {
+  int b = blockIdx.x;
+  int n = d.cand_cnt[b];
+  if (n == 0) return;
+  int bin;
+  int64_t start = cand_region_start(g, b, bin);
+  if (start < 0) start = g.long_base + (int64_t)d.lchunk[b - long_first_block(g)].cand_off;
+  const Cand* list = d.cand + start;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    Cand c = list[i];
     if (c.t == dunkey(d.bkey[c.js])) atomicMin(&d.src[c.js], c.row);
   }
 }
@@ -674,7 +651,6 @@ __device__ __forceinline__ double empty_value(double c, double lo, double up) {
 
 __global__ void k_count(Dev d) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) d.flags->cand_count = 0;
   int64_t m = d.m, n = d.n;
   if (t < m) {
     d.cnt[t] = d.row_code[t] != RC_KEEP;
@@ -761,6 +737,7 @@ __global__ void k_emit(Dev d, int64_t base, int round) {
     else if (code == RC_REDUNDANT) *r = mkrec(REC_REDUNDANT_ROW, 0, round, i, -1, -1, o.v0, o.v1, d.lhs[i], d.rhs[i]);
     else *r = mkrec(REC_SINGLETON_ROW, 0, round, i, o.j, -1, o.v0, d.lhs[i], d.rhs[i], 0.0);
     d.row_on[i] = 0;
+    d.row_code[i] = RC_KEEP;
     return;
   }
   if (t >= m + n) return;
@@ -798,25 +775,41 @@ __global__ void k_emit(Dev d, int64_t base, int round) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+void launch_long_stats(const Dev& d, int mode, hipStream_t s) {
+  if (d.nchunks == 0) return;
+  if (mode == MODE_ROUND) hipLaunchKernelGGL(k_long_stats<MODE_ROUND>, dim3(d.nchunks), dim3(PSL_BLOCK), 0, s, d);
+  else hipLaunchKernelGGL(k_long_stats<MODE_COMPACT>, dim3(d.nchunks), dim3(PSL_BLOCK), 0, s, d);
+}
+
 void launch_sweep(const Dev& d, const SweepGrid& g, int mode, hipStream_t s) {
-  int total = g.nb[0] + g.nb[1] + g.nb[2] + g.nb[3] + g.nb[4];
-  if (total > 0) {
-    if (mode == MODE_ROUND) hipLaunchKernelGGL(k_sweep<MODE_ROUND>, dim3(total), dim3(PSL_BLOCK), 0, s, d, g);
-    else hipLaunchKernelGGL(k_sweep<MODE_COMPACT>, dim3(total), dim3(PSL_BLOCK), 0, s, d, g);
-  }
-}
-
-void launch_dense(const Dev& d, int mode, hipStream_t s) {
-  if (d.ndense == 0) return;
+  int n_short = g.nb[BIN_G4] + g.nb[BIN_G16] + g.nb[BIN_W1];
+  int n_wide = g.nb[BIN_W4] + g.nb[BIN_W8];
+  int n_long = g.nb[BIN_LONG];
   if (mode == MODE_ROUND) {
-    hipLaunchKernelGGL(k_dense_finish<MODE_ROUND>, dim3(d.ndense), dim3(PSL_BLOCK), 0, s, d);
-    hipLaunchKernelGGL(k_dense_prop, dim3(d.nchunks), dim3(PSL_BLOCK), 0, s, d);
+    int total = n_short + n_wide + n_long;
+    if (total) hipLaunchKernelGGL((k_sweep<MODE_ROUND, KIND_ALL>), dim3(total), dim3(PSL_BLOCK), 0, s, d, g, 0);
+  } else if (mode == 2) {
+    if (n_short) hipLaunchKernelGGL((k_sweep<MODE_ROUND, KIND_SHORT>), dim3(n_short), dim3(PSL_BLOCK), 0, s, d, g, 0);
+    if (n_wide)
+      hipLaunchKernelGGL((k_sweep<MODE_ROUND, KIND_WIDE>), dim3(n_wide), dim3(PSL_BLOCK), 0, s, d, g, n_short);
+    if (n_long)
+      hipLaunchKernelGGL((k_sweep<MODE_ROUND, KIND_LONG>), dim3(n_long), dim3(PSL_BLOCK), 0, s, d, g,
+                         n_short + n_wide);
   } else {
-    hipLaunchKernelGGL(k_dense_finish<MODE_COMPACT>, dim3(d.ndense), dim3(PSL_BLOCK), 0, s, d);
+    if (n_short)
+      hipLaunchKernelGGL((k_sweep<MODE_COMPACT, KIND_SHORT>), dim3(n_short), dim3(PSL_BLOCK), 0, s, d, g, 0);
+    if (n_wide)
+      hipLaunchKernelGGL((k_sweep<MODE_COMPACT, KIND_WIDE>), dim3(n_wide), dim3(PSL_BLOCK), 0, s, d, g, n_short);
+    if (d.nlong > 0)
+      hipLaunchKernelGGL(k_long_finish_compact, dim3((d.nlong + 3) / 4), dim3(PSL_BLOCK), 0, s, d);
   }
 }
 
-void launch_src(const Dev& d, hipStream_t s) { hipLaunchKernelGGL(k_src, dim3(1024), dim3(PSL_BLOCK), 0, s, d); }
+void launch_src(const Dev& d, const SweepGrid& g, hipStream_t s) {
+  int total = 0;
+  for (int b = 0; b < NBINS; ++b) total += g.nb[b];
+  if (total > 0) hipLaunchKernelGGL(k_src, dim3(total), dim3(PSL_BLOCK), 0, s, d, g);
+}
 
 void launch_count(const Dev& d, hipStream_t s) {
   int64_t t = (int64_t)d.m + d.n;
@@ -832,9 +825,6 @@ void launch_emit(const Dev& d, int64_t base, int round, hipStream_t s) {
   hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, base, round);
 }
 
-int dense_chunk_size() { return DENSE_CHUNK; }
-int dense_max_chunks() { return DENSE_MAXCH; }
-int wave_max_len() { return WAVE_MAXP * PSL_WAVE; }
-int block_max_len() { return BLOCK_MAXP * PSL_BLOCK; }
+int long_max_passes() { return LONG_MAX_PASSES; }
 
 }  // namespace psl

@@ -80,11 +80,13 @@ def _fill_columns(rng, lengths, n, draw):
     cols = draw(rng, len(row_of))
     key = row_of * n + cols
     key.sort()
-    while True:
+    for it in range(10_000):
         dup = np.flatnonzero(key[1:] == key[:-1]) + 1
         if len(dup) == 0:
             break
-        key[dup] = row_of[dup] * n + draw(rng, len(dup))
+        # after many redraws from a skewed law, finish with uniform redraws
+        new = draw(rng, len(dup)) if it < 48 else rng.integers(0, n, size=len(dup))
+        key[dup] = row_of[dup] * n + new
         key.sort()
     return (key % n).astype(np.int32)
 
@@ -144,7 +146,7 @@ def make_lp(m, n, *, seed, row_len=(4, 8), col_dist="uniform", zipf_cap=None,
         z = rng.zipf(row_len[1], size=n_plain).astype(np.int64)
         lengths = 2 + z
         cap = zipf_cap if zipf_cap is not None else n_rand
-        np.minimum(lengths, min(cap, n_rand), out=lengths)
+        np.minimum(lengths, min(cap, max(2, n_rand // 4)), out=lengths)
     else:
         lengths = rng.integers(row_len[0], row_len[1] + 1, size=n_plain).astype(np.int64)
 
