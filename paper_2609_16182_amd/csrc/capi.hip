@@ -31,6 +31,14 @@ struct Timer {
 
 }  // namespace
 
+struct View {
+  BinEnt* bins = nullptr;
+  LongChunk* chunks = nullptr;
+  int32_t off[NBINS + 1] = {0};
+  int32_t nchunks = 0;
+  int64_t rows = 0, nnz = 0;
+};
+
 struct psl_presolver {
   Dev d{};
   psl_settings s{};
@@ -51,10 +59,13 @@ struct psl_presolver {
   SweepGrid grid{};
   int64_t chunk_cap = 0, long_cap = 0, cand_cap = 0;
   int32_t* cand_cnt = nullptr;
-  BinEnt *bins_a = nullptr, *bins_b = nullptr;
-  LongChunk *chunks_a = nullptr, *chunks_b = nullptr;
+  // bin views: the master lists hold the active rows (filtered after
+  // removals); a selection holds the active rows touched by a column change
+  // since they were last swept
+  BinEnt *bins_a = nullptr, *bins_b = nullptr, *bins_s = nullptr;
+  LongChunk *chunks_a = nullptr, *chunks_b = nullptr, *chunks_s = nullptr;
   int32_t* rebin_dev = nullptr;  // [NBINS+1] new offsets, then 3 totals
-  int64_t act_rows = 0, act_nnz = 0;
+  View master, cur;
 
   // records
   Record* rec = nullptr;
@@ -198,12 +209,15 @@ static psl_status setup_arena(psl_presolver* p) {
   // row); long rows reserve 2 per position
   p->cand_cap = 8 * m + 10 * N + 8 * PASS_LEN;
   ALLOC(cand, p->cand_cap);
-  ALLOC(p->cand_cnt, std::max<int64_t>(1, m + N / PASS_LEN + 16));
+  // one count per sweep workgroup: at most m/4 + NBINS for the row bins plus
+  // one per long-row chunk
+  ALLOC(p->cand_cnt, m / 4 + NBINS + (N / PASS_LEN + N / 512 + 2) + 64);
   ALLOC(flags, 1);
   ALLOC(cnt, m + n + 1);
   ALLOC(off, m + n + 1);
   ALLOC(p->bins_a, m);
   ALLOC(p->bins_b, m);
+  ALLOC(p->bins_s, m);
   ALLOC(p->rebin_dev, 16);
   ALLOC(p->bin_counts_dev, NBINS);
   ALLOC(p->lb_in, n);
@@ -225,6 +239,9 @@ static psl_status setup_arena(psl_presolver* p) {
   p->chunk_cap = N / PASS_LEN + p->long_cap + 1;
   ALLOC(p->chunks_a, p->chunk_cap);
   ALLOC(p->chunks_b, p->chunk_cap);
+  ALLOC(p->chunks_s, p->chunk_cap);
+  uint8_t* dirty;
+  ALLOC(dirty, m);
   LongPart* lpart;
   LongRow* lrow;
   ALLOC(lpart, p->chunk_cap);
@@ -308,12 +325,20 @@ static psl_status setup_arena(psl_presolver* p) {
   d.rec = p->rec;
   d.bins = p->bins_a;
   d.lchunk = p->chunks_a;
+  d.dirty = dirty;
   d.lpart = lpart;
   d.lrow = lrow;
   d.nlong = 0;
   d.nchunks = 0;
   const psl_settings& s = p->s;
   d.cfg = Cfg{s.feas_tol, s.fix_tol, s.min_improve, s.par_tol, s.inf_value, s.coef_tol};
+  // every device array the kernels index must exist (allocations are >= 64 B
+  // even for empty problems); colid is set once the transposed copy exists
+  const void* ptrs[] = {d.rp, d.ci, d.va, d.cp, d.ri, d.cva, d.lhs, d.rhs, d.bnd, d.bkey, d.src, d.c,
+                        d.col_len, d.row_on, d.row_code, d.col_code, d.dirty, d.row_out, d.cand, d.cand_cnt,
+                        d.flags, d.cnt, d.off, d.rec, d.bins, d.lchunk, d.lpart, d.lrow};
+  for (const void* q : ptrs)
+    if (!q) return fail(p, PSL_ERR_DEVICE, "internal: a device array was not set up");
   return PSL_OK;
 }
 
@@ -346,23 +371,35 @@ static void set_grid(psl_presolver* p) {
   for (int b = 0; b < BIN_LONG; ++b) p->grid.long_base += (int64_t)p->grid.nb[b] * cand_region(b);
 }
 
-// drop removed rows from the bin lists and chunks (double-buffered)
-static psl_status do_rebin(psl_presolver* p) {
+// sweep the rows of view v from now on
+static void use_view(psl_presolver* p, const View& v) {
   Dev& d = p->d;
-  BinEnt* bout = d.bins == p->bins_a ? p->bins_b : p->bins_a;
-  LongChunk* cout = d.lchunk == p->chunks_a ? p->chunks_b : p->chunks_a;
+  d.bins = v.bins;
+  d.lchunk = v.chunks;
+  for (int b = 0; b <= NBINS; ++b) d.bin_off[b] = v.off[b];
+  d.nchunks = v.nchunks;
+  set_grid(p);
+  p->cur = v;
+}
+
+// dst = the active rows of src (only the dirty ones when dirty is set)
+static psl_status filter_view(psl_presolver* p, const View& src, BinEnt* bout, LongChunk* cout, bool dirty,
+                              View& dst) {
+  Dev& d = p->d;
   // scratch: cnt / off (free after the round's emission) and v0 (free between
   // ingest and compaction; k0 / k1 hold the transposed copy's column ids)
-  rebin(d, bout, cout, d.cnt, d.off, p->isc.v0, p->rebin_dev, p->rebin_dev + NBINS + 1, p->ws, p->stream);
+  rebin(d, src.bins, src.off, src.chunks, src.nchunks, bout, cout, dirty ? d.dirty : nullptr, d.cnt, d.off,
+        p->isc.v0, p->rebin_dev, p->rebin_dev + NBINS + 1, p->ws, p->stream);
   HIPCHK(p, hipMemcpyAsync(p->htot, p->rebin_dev, (NBINS + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
-  for (int b = 0; b <= NBINS; ++b) d.bin_off[b] = p->htot[b];
-  p->act_rows = p->htot[NBINS + 1];
-  p->act_nnz = p->htot[NBINS + 2];
-  d.nchunks = p->htot[NBINS + 3];
-  d.bins = bout;
-  d.lchunk = cout;
-  set_grid(p);
+  View v;
+  v.bins = bout;
+  v.chunks = cout;
+  for (int b = 0; b <= NBINS; ++b) v.off[b] = p->htot[b];
+  v.rows = p->htot[NBINS + 1];
+  v.nnz = p->htot[NBINS + 2];
+  v.nchunks = p->htot[NBINS + 3];
+  dst = v;
   return PSL_OK;
 }
 
@@ -436,14 +473,22 @@ static psl_status ingest(psl_presolver* p, const psl_lp* lp) {
   if (p->hflags->error & 64) return fail(p, PSL_ERR_CAPACITY, "a row is longer than 2^26 entries");
   if (p->htot[0] > p->chunk_cap) return fail(p, PSL_ERR_CAPACITY, "too many long-row chunks");
   d.nchunks = p->htot[0];
-  set_grid(p);
+  d.colid = nullptr;
+  View mv;
+  mv.bins = p->bins_a;
+  mv.chunks = p->chunks_a;
+  for (int b = 0; b <= NBINS; ++b) mv.off[b] = d.bin_off[b];
+  mv.nchunks = d.nchunks;
+  mv.rows = m;
+  mv.nnz = N;
+  p->master = mv;
+  use_view(p, mv);
   if (p->grid.long_base + (int64_t)p->htot[1] > p->cand_cap)
     return fail(p, PSL_ERR_CAPACITY, "candidate buffer too small for the row bins");
-  p->act_rows = m;
-  p->act_nnz = N;
 
   p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.col_len, p->isc, st);
   p->cmp.colid = p->colid;
+  d.colid = p->colid;
   HIPCHK(p, hipEventRecord(p->ev[1], st));
   HIPCHK(p, hipStreamSynchronize(st));
   float ms = 0;
@@ -561,6 +606,8 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
   double sweep_ms = 0.0, decide_ms = 0.0, par_ms = 0.0, long_ms = 0.0;
 
   bool stop = infeasible;
+  bool was_incremental = false;
+  use_view(p, p->master);
   int outer = 0;
   for (; outer < s.max_outer && !stop; ++outer) {
     for (int r = 0; r < s.max_rounds; ++r) {
@@ -584,13 +631,8 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
       sweep_ms += elapsed(p, 7, 5);
       decide_ms += elapsed(p, 5, 6);
       S.sweep_launches += 1;
-      S.sweep_bytes += 12.0 * p->act_nnz + 24.0 * p->act_rows + 16.0 * n;
+      S.sweep_bytes += 12.0 * p->cur.nnz + 24.0 * p->cur.rows + 16.0 * n;
       p->rec_count += p->hflags->round_total;
-      // keep the sweep on live rows once a sixteenth of them went
-      if (removed > 0 && (int64_t)removed * 16 >= p->act_rows) {
-        e = do_rebin(p);
-        if (e != PSL_OK) return e;
-      }
       if (p->hflags->infeasible) infeasible = true;
       if (p->hflags->unbounded) unbounded = true;
       if (infeasible || unbounded) {
@@ -598,7 +640,34 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
         break;
       }
       if (p->hflags->round_total == 0) break;
+      // keep the master lists on live rows once a sixteenth of them went
+      if (removed > 0 && (int64_t)removed * 16 >= p->master.rows) {
+        View nv;
+        BinEnt* bo = p->master.bins == p->bins_a ? p->bins_b : p->bins_a;
+        LongChunk* co = p->master.chunks == p->chunks_a ? p->chunks_b : p->chunks_a;
+        e = filter_view(p, p->master, bo, co, false, nv);
+        if (e != PSL_OK) return e;
+        p->master = nv;
+      }
+      // Next round: rows none of whose columns changed since they were last
+      // swept give the same statistics and no qualifying candidate, so after
+      // a round with few column changes only the touched rows are swept.
+      int64_t changed_cols = (int64_t)p->hflags->round_total - removed;
+      bool incremental = r + 1 < s.max_rounds && changed_cols * 8 < (int64_t)n;
+      if (incremental) {
+        if (!d.dirty || !d.colid) return fail(p, PSL_ERR_DEVICE, "internal: incremental state not set up");
+        mark_dirty(d, !was_incremental, st);
+        View sel;
+        e = filter_view(p, p->master, p->bins_s, p->chunks_s, true, sel);
+        if (e != PSL_OK) return e;
+        use_view(p, sel);
+      } else {
+        use_view(p, p->master);
+      }
+      was_incremental = incremental;
     }
+    use_view(p, p->master);
+    was_incremental = false;
     if (stop || !s.enable_parallel_rows) break;
     ++round;
     e = ensure_capacity(p, m + 16);
@@ -632,6 +701,7 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
 
   double cmp_ms = 0.0;
   if (result == PSL_RES_REDUCED || result == PSL_RES_UNCHANGED) {
+    use_view(p, p->master);
     HIPCHK(p, hipEventRecord(p->ev[4], st));
     launch_long_stats(d, MODE_COMPACT, st);
     launch_sweep(d, p->grid, MODE_COMPACT, st);

@@ -191,48 +191,6 @@ void build_bins(const Dev& d, const int32_t* thresholds, BinEnt* bins, int32_t* 
 // ---------------------------------------------------------------------------
 // filtering of the bin lists and the chunk list down to the active rows
 // ---------------------------------------------------------------------------
-__global__ void k_rebin_flags(Dev d, int32_t nent, int32_t* keep, int32_t* keep_len, int32_t nch, int32_t* ckeep) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= nent; k += stride) {
-    int f = 0, l = 0;
-    if (k < nent) {
-      BinEnt be = d.bins[k];
-      f = d.row_on[be.row] != 0;
-      l = f ? be.len : 0;
-    }
-    keep[k] = f;
-    keep_len[k] = l;
-  }
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nch; c += stride)
-    ckeep[c] = c < nch ? (d.row_on[d.lchunk[c].row] != 0) : 0;
-}
-
-__global__ void k_rebin_scatter(Dev d, int32_t nent, const int32_t* pos, BinEnt* out, int32_t nch, const int32_t* cpos,
-                                LongChunk* cout, int32_t* new_off) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t k = t0; k < nent; k += stride)
-    if (pos[k + 1] != pos[k]) out[pos[k]] = d.bins[k];
-  for (int64_t c = t0; c < nch; c += stride)
-    if (cpos[c + 1] != cpos[c]) cout[cpos[c]] = d.lchunk[c];
-  if (t0 <= NBINS) new_off[t0] = pos[d.bin_off[t0]];
-}
-
-void rebin(const Dev& d, BinEnt* bins_out, LongChunk* chunks_out, int32_t* keep, int32_t* keep_len, int32_t* ckeep,
-           int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s) {
-  int32_t nent = d.bin_off[NBINS];
-  int64_t t = nent + 1 > d.nchunks + 1 ? nent + 1 : d.nchunks + 1;
-  int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_rebin_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, nent, keep, keep_len,
-                     d.nchunks, ckeep);
-  scan_excl(keep, keep, nent + 1, totals + 0, ws, s);
-  scan_excl(keep_len, keep_len, nent + 1, totals + 1, ws, s);
-  scan_excl(ckeep, ckeep, d.nchunks + 1, totals + 2, ws, s);
-  hipLaunchKernelGGL(k_rebin_scatter, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, nent, (const int32_t*)keep,
-                     bins_out, d.nchunks, (const int32_t*)ckeep, chunks_out, new_off);
-}
-
 // passes per chunk: the requested size, doubled until the row has at most
 // LONG_MAX_CHUNKS chunks (chunk sizes stay powers of two times PASS_LEN)
 __global__ void k_long_count(Dev d, int npass0, int32_t* cnt, int32_t* cnt2) {
@@ -276,6 +234,93 @@ void build_long_chunks(const Dev& d, int npass0, LongChunk* chunks, int32_t* cnt
   scan_excl(cnt2, cnt2, d.nlong, totals + 1, ws, s);
   hipLaunchKernelGGL(k_long_fill, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)cnt, (const int32_t*)cnt2,
                      chunks);
+}
+
+struct BinOffsets {
+  int32_t off[NBINS + 1];
+};
+
+// keep a bin entry (and the chunks of a long row) when its row is active and,
+// with a dirty array, touched by a column change since it was last swept
+__global__ void k_rebin_flags(Dev d, const BinEnt* bins, int32_t nent, const LongChunk* chunks, int32_t nch,
+                              const uint8_t* dirty, int32_t* keep, int32_t* keep_len, int32_t* ckeep) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= nent; k += stride) {
+    int f = 0, l = 0;
+    if (k < nent) {
+      BinEnt be = bins[k];
+      f = d.row_on[be.row] != 0 && (!dirty || dirty[be.row]);
+      l = f ? be.len : 0;
+    }
+    keep[k] = f;
+    keep_len[k] = l;
+  }
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nch; c += stride) {
+    int f = 0;
+    if (c < nch) {
+      int row = chunks[c].row;
+      f = d.row_on[row] != 0 && (!dirty || dirty[row]);
+    }
+    ckeep[c] = f;
+  }
+}
+
+__global__ void k_rebin_scatter(const BinEnt* bins, int32_t nent, const int32_t* pos, BinEnt* out,
+                                const LongChunk* chunks, int32_t nch, const int32_t* cpos, LongChunk* cout,
+                                BinOffsets old, int32_t* new_off, uint8_t* dirty) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t k = t0; k < nent; k += stride)
+    if (pos[k + 1] != pos[k]) {
+      BinEnt be = bins[k];
+      out[pos[k]] = be;
+      if (dirty) dirty[be.row] = 0;  // swept now
+    }
+  for (int64_t c = t0; c < nch; c += stride)
+    if (cpos[c + 1] != cpos[c]) cout[cpos[c]] = chunks[c];
+  if (t0 <= NBINS) new_off[t0] = pos[old.off[t0]];
+}
+
+void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const LongChunk* chunks_in, int32_t nch,
+           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, int32_t* keep, int32_t* keep_len,
+           int32_t* ckeep, int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s) {
+  BinOffsets bo;
+  for (int b = 0; b <= NBINS; ++b) bo.off[b] = off_in[b];
+  int32_t nent = off_in[NBINS];
+  int64_t t = nent + 1 > nch + 1 ? nent + 1 : nch + 1;
+  int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_rebin_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, bins_in, nent, chunks_in, nch,
+                     (const uint8_t*)dirty, keep, keep_len, ckeep);
+  scan_excl(keep, keep, nent + 1, totals + 0, ws, s);
+  scan_excl(keep_len, keep_len, nent + 1, totals + 1, ws, s);
+  scan_excl(ckeep, ckeep, nch + 1, totals + 2, ws, s);
+  hipLaunchKernelGGL(k_rebin_scatter, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, bins_in, nent,
+                     (const int32_t*)keep, bins_out, chunks_in, nch, (const int32_t*)ckeep, chunks_out, bo, new_off,
+                     dirty);
+}
+
+// rows of columns whose bounds changed (or that were fixed) this round
+__global__ void k_mark(Dev d) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < d.nnz; q += stride)
+    if (d.col_code[d.colid[q]] & (CC_LB | CC_UB | CC_FIX)) d.dirty[d.ri[q]] = 1;
+}
+
+__global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void mark_dirty(const Dev& d, bool clear_first, hipStream_t s) {
+  if (clear_first && d.m > 0) {
+    int64_t b = (d.m + PSL_BLOCK - 1) / PSL_BLOCK;
+    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(PSL_BLOCK), 0, s, d.dirty, (uint8_t)0,
+                       (int64_t)d.m);
+  }
+  if (d.nnz == 0) return;
+  int64_t b = (d.nnz + PSL_BLOCK - 1) / PSL_BLOCK;
+  hipLaunchKernelGGL(k_mark, dim3((unsigned)(b > 16384 ? 16384 : b)), dim3(PSL_BLOCK), 0, s, d);
 }
 
 // ---------------------------------------------------------------------------

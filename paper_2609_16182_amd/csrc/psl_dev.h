@@ -115,6 +115,8 @@ struct Dev {
   const double *c;
   int32_t *col_len;
   uint8_t *row_on, *row_code, *col_code;
+  uint8_t *dirty;          // rows touched by a column change since last swept
+  const uint32_t *colid;   // column of each position of the transposed copy
   RowOut *row_out;
   Cand *cand;
   int32_t *cand_cnt;   // candidates written per sweep workgroup

@@ -49,10 +49,15 @@ const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, i
 // bins: writes the bin lists and per-bin counts (device counts[NBINS])
 void build_bins(const Dev& d, const int32_t* thresholds, BinEnt* bins, int32_t* counts, IngestScratch& sc,
                 hipStream_t s);
-// keep only active rows in the bin lists and chunk list: new_off[0..NBINS],
-// totals = {kept rows, their nonzeros, kept chunks} (device)
-void rebin(const Dev& d, BinEnt* bins_out, LongChunk* chunks_out, int32_t* keep, int32_t* keep_len, int32_t* ckeep,
-           int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s);
+// keep the active rows (and, with dirty != nullptr, only the dirty ones,
+// whose flags are then cleared) of a bin list and chunk list: new_off
+// [0..NBINS], totals = {kept rows, their nonzeros, kept chunks} (device)
+void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const LongChunk* chunks_in, int32_t nch,
+           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, int32_t* keep, int32_t* keep_len,
+           int32_t* ckeep, int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s);
+// mark the rows of the columns changed in the last round (optionally clearing
+// all marks first)
+void mark_dirty(const Dev& d, bool clear_first, hipStream_t s);
 // chunk table of the long rows (d.nlong set); total chunks to *total (device)
 // totals[0] = chunks, totals[1] = candidate units of all chunks
 void build_long_chunks(const Dev& d, int npass0, LongChunk* chunks, int32_t* cnt, int32_t* cnt2, int32_t* totals,
