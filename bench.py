@@ -37,9 +37,22 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the full power-law LP)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-gb", type=float, default=None,
-                    help="measured HBM bytes per sweep launch (GB), from rocprofv3 counters")
     return ap.parse_args()
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    or None when the sweep's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "powerlaw_1e6_k_sweep_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    src = b"".join(open(os.path.join(ROOT, x), "rb").read() for x in t["sources"])
+    if hashlib.sha256(src).hexdigest() != t["source_sha256"]:
+        return None
+    return t["traffic_bytes_per_launch"]
 
 
 def main():
@@ -98,7 +111,7 @@ def main():
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": args.traffic_gb,
+        "traffic": measured_traffic(),
         "kernel": "k_sweep<0> (row sweep: activities, decisions, implied bounds)",
         "launches": sweep_launches, "avg_launch_us": round(sweep_ms * 1e3 / max(1, sweep_launches), 2),
         "alg_bytes_per_launch": round(per_launch_bytes),
