@@ -201,6 +201,50 @@ void psl_presolve_free(psl_presolver *p);
  * NULL). Never NULL. */
 const char *psl_last_error(const psl_presolver *p);
 
+/* ---- Batched presolve -----------------------------------------------------
+ * k independent LPs presolved together: they are laid out as the diagonal
+ * blocks of one LP, so every kernel launch covers all of them, while each LP
+ * keeps its own round count, stopping test and outer cycles. Each LP's
+ * outcome, records and reduced problem are exactly those psl_presolve_run
+ * gives for that LP alone, with the LP's own row and column numbering. */
+typedef struct psl_batch psl_batch;
+
+/* k >= 1 LPs, all with the same mem kind, each checked as at
+ * psl_presolve_create (the message names the first invalid LP). The totals of
+ * these LPs (rows, columns, nonzeros, and k) are the batch's capacity; their
+ * total nnz must be below 2^30. Settings apply to every LP. */
+psl_status psl_batch_create(int32_t k, const psl_lp *lps, const psl_settings *s, psl_batch **out);
+
+/* Replace the LPs by k others (any shapes) whose totals fit the capacity,
+ * reusing the device memory. PSL_ERR_CAPACITY otherwise. */
+psl_status psl_batch_reload(psl_batch *b, int32_t k, const psl_lp *lps);
+
+/* Presolve every LP. res[k] (host array of the batch's k) receives each
+ * outcome; total (nullable) the batch's device times, rounds = the largest
+ * round number of any LP, records / nnz / m_out / n_out summed over LPs. */
+psl_status psl_batch_run(psl_batch *b, psl_result *res, psl_stats *total);
+
+/* Statistics of LP idx of the last run: rounds, outer_cycles, records,
+ * nnz_in, nnz_out, m_out, n_out (the times are the batch's). */
+psl_status psl_batch_stats(const psl_batch *b, int32_t idx, psl_stats *out);
+
+/* As psl_reduced_problem, for LP idx (device pointers into the batch's
+ * arrays, valid until the next run, reload or free of the batch). */
+psl_status psl_batch_reduced_problem(const psl_batch *b, int32_t idx, psl_reduced_view *out);
+
+/* As psl_records, for LP idx (LP-local indices). */
+psl_status psl_batch_records(const psl_batch *b, int32_t idx, int64_t *count, psl_record *out, int64_t cap);
+
+/* As psl_postsolve, for LP idx (x has that LP's n entries). */
+psl_status psl_batch_postsolve(psl_batch *b, int32_t idx, const double *x_red, const double *y_red,
+                               const double *z_red, double *x, double *y, double *z);
+
+void psl_batch_free(psl_batch *b);
+
+/* Message of the last failure on b (or of the last failed batch create of
+ * the thread when b is NULL). Never NULL. */
+const char *psl_batch_last_error(const psl_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

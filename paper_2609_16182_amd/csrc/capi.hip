@@ -5,6 +5,12 @@
 //
 // Control crosses to the host once per round: a 64-byte flag block (records
 // emitted, infeasible / unbounded) is read back to decide whether to go on.
+//
+// One engine serves a single LP (K = 1) and batches of K LPs laid out as the
+// blocks of one block-diagonal LP. In a batch every LP has its own state
+// machine on the host (propagating / converged / done, its round count and
+// outer cycles); the per-round readback then also holds each LP's record
+// count and flags, and LPs that stopped are filtered out of the bin lists.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,14 +45,60 @@ struct View {
   int64_t rows = 0, nnz = 0;
 };
 
+// host state of one LP of a batch
+enum : uint8_t { LP_PROP = 0, LP_WAIT = 1, LP_DONE = 2 };
+struct LpState {
+  uint8_t phase = LP_PROP;
+  bool infeasible = false, unbounded = false;
+  int32_t rounds = 0, cycles = 0;
+};
+
 struct psl_presolver {
   Dev d{};
   psl_settings s{};
   hipStream_t stream = nullptr;
   int32_t m = 0, n = 0;
   int64_t nnz = 0;
-  std::vector<void*> allocs;
+  // arena capacity (the create-time sizes; a batch reload may use less)
+  int32_t cap_m = 0, cap_n = 0, cap_K = 1;
+  int64_t cap_nnz = 0;
+
+  // batch (K > 1): device maps and per-LP arrays, pinned host mirrors
+  int32_t K = 1;
+  int32_t *row_lp = nullptr, *col_lp = nullptr, *lp_row0 = nullptr, *lp_col0 = nullptr, *lp_round = nullptr;
+  uint8_t* lp_ok = nullptr;
+  LpFlags* lpf = nullptr;
+  LpOut* lpo = nullptr;
+  LpTab* lpt = nullptr;
+  LpRed* lpr = nullptr;
+  int64_t* lp_z0 = nullptr;
+  LpDesc* descs = nullptr;
+  double *lp_off_in = nullptr, *lp_off = nullptr;
+  int32_t *h_row0 = nullptr, *h_col0 = nullptr, *h_round = nullptr;
+  int64_t* h_z0 = nullptr;
+  uint8_t* h_ok = nullptr;
+  LpFlags* h_lpf = nullptr;
+  LpOut* h_lpo = nullptr;
+  LpTab* h_lpt = nullptr;
+  LpRed* h_lpr = nullptr;
+  LpDesc* h_desc = nullptr;
+  double *h_off_in = nullptr, *h_off = nullptr;
+  std::vector<LpState> lst;
+  std::vector<psl_result> lp_result;
+  BinEnt* bins_0 = nullptr;  // the ingest bins of all rows
+  LongChunk* chunks_0 = nullptr;
+  View all;
+  // records split by LP
+  Record* rec_lp = nullptr;
+  int64_t split_cap = 0;
+  uint32_t *sk0 = nullptr, *sk1 = nullptr;
+  int32_t *sv0 = nullptr, *sv1 = nullptr, *sws = nullptr, *rec_off = nullptr;
+  std::vector<int32_t> h_rec_off;
+  std::vector<std::vector<psl_record>> lp_host_rec;
+  std::vector<uint8_t> lp_rec_valid;
+  std::vector<void*> allocs, hallocs;
   std::string err = "no error";
+  int64_t par_slots = 0;
 
   // staging and persistent scratch
   double *lb_in = nullptr, *ub_in = nullptr, *c_mut = nullptr;
@@ -176,8 +228,30 @@ static std::string check_lp_shape(const psl_lp* lp) {
   return "";
 }
 
+template <class T>
+static psl_status halloc(psl_presolver* p, T** out, size_t count) {
+  size_t bytes = count * sizeof(T);
+  if (bytes == 0) bytes = 64;
+  if (hipHostMalloc((void**)out, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    p->err = "pinned host allocation failed";
+    return PSL_ERR_OOM;
+  }
+  p->hallocs.push_back((void*)*out);
+  return PSL_OK;
+}
+
+#define HALLOC(ptr, cnt)                               \
+  do {                                                 \
+    psl_status st_ = halloc(p, &(ptr), (size_t)(cnt)); \
+    if (st_ != PSL_OK) return st_;                     \
+  } while (0)
+
+// device arena for LPs of up to cap_m rows, cap_n columns, cap_nnz entries
+// (and cap_K LPs)
 static psl_status setup_arena(psl_presolver* p) {
-  int64_t m = p->m, n = p->n, N = p->nnz;
+  int64_t m = p->cap_m, n = p->cap_n, N = p->cap_nnz, K = p->cap_K;
   Dev& d = p->d;
   int32_t *rp, *ci, *cp, *ri, *col_len, *src, *cnt, *off;
   double *va, *cva, *lhs, *rhs;
@@ -250,10 +324,11 @@ static psl_status setup_arena(psl_presolver* p) {
   p->rec_cap = 2 * m + 4 * n + 1024;
   ALLOC(p->rec, p->rec_cap);
 
-  // parallel rows
+  // parallel rows: a table of >= 2m slots (per LP in a batch)
   int64_t cap = 64;
   while (cap < 2 * m) cap <<= 1;
-  p->par.cap = cap;
+  if (K > 1) cap = 4 * m + 64 * K + 64;
+  p->par_slots = cap;
   ALLOC(p->par.table, cap);
   ALLOC(p->par.slot, m);
   ALLOC(p->par.lead, m);
@@ -262,6 +337,7 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->par.is_leader, m);
   ALLOC(p->par.vlist, m);
   ALLOC(p->par.hacc, 3 * p->long_cap);
+  p->par.lpt = nullptr;
 
   // compaction
   ALLOC(p->cmp.row_new, m + 1);
@@ -269,17 +345,22 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->cmp.terms, n);
   ALLOC(p->cmp.pws, pairwise_ws_doubles(n) + 2);
   ALLOC(p->cmp.totals, 4);
-  ALLOC(p->cmp.offset, 1);
+  ALLOC(p->cmp.offset, K);
+  ALLOC(p->lpr, K + 1);
   p->cmp.ws = p->ws;
   p->cmp.eflag = p->isc.v0;
   p->cmp.qflag = p->isc.v1;
   p->cmp.rowid1 = p->isc.rowid1;
+  p->cmp.lpr = p->lpr;
+  p->cmp.seg = nullptr;
+  p->cmp.seg_host = nullptr;
+  p->cmp.lp_off_in = nullptr;
 
   Reduced& r = p->red;
-  ALLOC(r.row_ptr, m + 1);
+  ALLOC(r.row_ptr, m + K);
   ALLOC(r.col_idx, N);
   ALLOC(r.val, N);
-  ALLOC(r.col_ptr, n + 1);
+  ALLOC(r.col_ptr, n + K);
   ALLOC(r.row_idx, N);
   ALLOC(r.cval, N);
   ALLOC(r.lhs, m);
@@ -292,14 +373,45 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(r.row_class, m);
   ALLOC(r.col_class, n);
 
-  HIPCHK(p, hipHostMalloc((void**)&p->hflags, sizeof(Flags), hipHostMallocDefault));
-  HIPCHK(p, hipHostMalloc((void**)&p->htot, 64 * sizeof(int32_t), hipHostMallocDefault));
-  HIPCHK(p, hipHostMalloc((void**)&p->hoff, sizeof(double), hipHostMallocDefault));
+  HALLOC(p->hflags, 1);
+  HALLOC(p->htot, 64);
+  HALLOC(p->hoff, 1);
+  HALLOC(p->h_lpr, K + 1);
   for (auto& e : p->ev) HIPCHK(p, hipEventCreate(&e));
 
-  d.m = (int32_t)m;
-  d.n = (int32_t)n;
-  d.nnz = N;
+  if (K > 1) {
+    ALLOC(p->row_lp, m);
+    ALLOC(p->col_lp, n);
+    ALLOC(p->lp_row0, K + 1);
+    ALLOC(p->lp_col0, K + 1);
+    ALLOC(p->lp_round, K);
+    ALLOC(p->lp_ok, K);
+    ALLOC(p->lpf, K);
+    ALLOC(p->lpo, K);
+    ALLOC(p->lpt, K);
+    ALLOC(p->lp_z0, K + 1);
+    ALLOC(p->descs, K);
+    ALLOC(p->lp_off_in, K);
+    ALLOC(p->rec_off, K + 1);
+    ALLOC(p->bins_0, m);
+    ALLOC(p->chunks_0, p->chunk_cap);
+    HALLOC(p->h_row0, K + 1);
+    HALLOC(p->h_col0, K + 1);
+    HALLOC(p->h_z0, K + 1);
+    HALLOC(p->h_round, K);
+    HALLOC(p->h_ok, K);
+    HALLOC(p->h_lpf, K);
+    HALLOC(p->h_lpo, K);
+    HALLOC(p->h_lpt, K);
+    HALLOC(p->h_desc, K);
+    HALLOC(p->h_off_in, K);
+    HALLOC(p->h_off, K);
+    p->par.lpt = p->lpt;
+    p->cmp.seg = p->lp_col0;
+    p->cmp.seg_host = p->h_col0;
+    p->cmp.lp_off_in = p->lp_off_in;
+  }
+
   d.rp = rp;
   d.ci = ci;
   d.va = va;
@@ -330,15 +442,30 @@ static psl_status setup_arena(psl_presolver* p) {
   d.lrow = lrow;
   d.nlong = 0;
   d.nchunks = 0;
+  d.K = 1;
+  d.row_lp = p->row_lp;
+  d.col_lp = p->col_lp;
+  d.lp_row0 = p->lp_row0;
+  d.lp_col0 = p->lp_col0;
+  d.lp_ok = p->lp_ok;
+  d.lp_round = p->lp_round;
+  d.lpf = p->lpf;
+  d.lpo = p->lpo;
   const psl_settings& s = p->s;
   d.cfg = Cfg{s.feas_tol, s.fix_tol, s.min_improve, s.par_tol, s.inf_value, s.coef_tol};
   // every device array the kernels index must exist (allocations are >= 64 B
   // even for empty problems); colid is set once the transposed copy exists
   const void* ptrs[] = {d.rp, d.ci, d.va, d.cp, d.ri, d.cva, d.lhs, d.rhs, d.bnd, d.bkey, d.src, d.c,
                         d.col_len, d.row_on, d.row_code, d.col_code, d.dirty, d.row_out, d.cand, d.cand_cnt,
-                        d.flags, d.cnt, d.off, d.rec, d.bins, d.lchunk, d.lpart, d.lrow};
+                        d.flags, d.cnt, d.off, d.rec, d.bins, d.lchunk, d.lpart, d.lrow, p->lpr};
   for (const void* q : ptrs)
     if (!q) return fail(p, PSL_ERR_DEVICE, "internal: a device array was not set up");
+  if (K > 1) {
+    const void* bp[] = {d.row_lp, d.col_lp, d.lp_row0, d.lp_col0, d.lp_ok, d.lp_round, d.lpf, d.lpo, p->lpt,
+                        p->lp_z0, p->descs, p->lp_off_in, p->rec_off, p->bins_0, p->chunks_0};
+    for (const void* q : bp)
+      if (!q) return fail(p, PSL_ERR_DEVICE, "internal: a batch array was not set up");
+  }
   return PSL_OK;
 }
 
@@ -403,18 +530,143 @@ static psl_status filter_view(psl_presolver* p, const View& src, BinEnt* bout, L
   return PSL_OK;
 }
 
-static std::string error_message(int32_t bits, int64_t pos) {
-  std::string what;
-  if (bits & 1) what = "row_ptr must start at 0, be non-decreasing and end at nnz";
-  else if (bits & 2) what = "column index out of range or not strictly ascending within its row";
-  else if (bits & 4) what = "coefficient zero or not finite";
-  else if (bits & 8) what = "side NaN or infinite on the wrong end";
-  else if (bits & 16) what = "bound NaN or infinite on the wrong end";
-  else what = "cost not finite";
-  return "invalid input: " + what + " (first at index " + std::to_string(pos) + ")";
+static std::string error_what(int32_t bits) {
+  if (bits & 1) return "row_ptr must start at 0, be non-decreasing and end at nnz";
+  if (bits & 2) return "column index out of range or not strictly ascending within its row";
+  if (bits & 4) return "coefficient zero or not finite";
+  if (bits & 8) return "side NaN or infinite on the wrong end";
+  if (bits & 16) return "bound NaN or infinite on the wrong end";
+  return "cost not finite";
 }
 
-// copy + validate + transpose + bins; the LP's shape equals the handle's
+static std::string error_message(const psl_presolver* p, int32_t bits, int64_t pos) {
+  if (p->K == 1) return "invalid input: " + error_what(bits) + " (first at index " + std::to_string(pos) + ")";
+  // position in the batch's rows, columns or entries -> LP and its own index
+  const int64_t* z0 = p->h_z0;
+  int k = 0;
+  int64_t local = pos;
+  auto find = [&](auto start) {
+    int lo = 0, hi = p->K - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if ((int64_t)start[mid] <= pos) lo = mid;
+      else hi = mid - 1;
+    }
+    k = lo;
+    local = pos - (int64_t)start[lo];
+  };
+  if (bits & (1 | 8)) find(p->h_row0);
+  else if (bits & (2 | 4)) find(z0);
+  else find(p->h_col0);
+  return "invalid input in LP " + std::to_string(k) + ": " + error_what(bits) + " (first at index " +
+         std::to_string(local) + ")";
+}
+
+// the LP (or union of LPs) of the handle is in d.rp .. p->c_mut; validate,
+// transpose, bin
+static psl_status ingest_rest(psl_presolver* p) {
+  Dev& d = p->d;
+  hipStream_t st = p->stream;
+  int64_t m = p->m, n = p->n, N = p->nnz;
+  launch_init_state(d, st);  // clears the flag block
+  launch_check_rows(d, st);
+  check_cols(d, p->lb_in, p->ub_in, p->c_mut, st);
+  psl_status s0 = read_flags(p);
+  if (s0 != PSL_OK) return s0;
+  if (p->hflags->error) return fail(p, PSL_ERR_INVALID, error_message(p, p->hflags->error, p->hflags->error_pos));
+
+  build_rowid(d, p->isc, st);
+  launch_check_entries(d, p->isc.rowid1, st);
+  s0 = read_flags(p);
+  if (s0 != PSL_OK) return s0;
+  if (p->hflags->error) return fail(p, PSL_ERR_INVALID, error_message(p, p->hflags->error, p->hflags->error_pos));
+
+  // bins (before the transpose: both use k0/k1); a batch keeps the bins of
+  // all its rows apart (the compaction starts from them)
+  BinEnt* bins0 = p->K > 1 ? p->bins_0 : p->bins_a;
+  LongChunk* chunks0 = p->K > 1 ? p->chunks_0 : p->chunks_a;
+  d.bins = bins0;
+  d.lchunk = chunks0;
+  build_bins(d, p->thresholds, bins0, p->bin_counts_dev, p->isc, st);
+  HIPCHK(p, hipMemcpyAsync(p->htot, p->bin_counts_dev, NBINS * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(p, hipStreamSynchronize(st));
+  int off = 0;
+  for (int b = 0; b < NBINS; ++b) {
+    p->bin_counts[b] = p->htot[b];
+    d.bin_off[b] = off;
+    off += p->htot[b];
+  }
+  d.bin_off[NBINS] = off;
+
+  // long rows: chunk table built on the device
+  int nlong = p->bin_counts[BIN_LONG];
+  if (nlong > p->long_cap) return fail(p, PSL_ERR_CAPACITY, "too many long rows");
+  d.nlong = nlong;
+  build_long_chunks(d, p->thresholds[1] / PASS_LEN, chunks0, d.cnt, d.off, p->bin_counts_dev, p->ws, st);
+  HIPCHK(p, hipMemcpyAsync(p->htot, p->bin_counts_dev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  s0 = read_flags(p);
+  if (s0 != PSL_OK) return s0;
+  if (p->hflags->error & 64) return fail(p, PSL_ERR_CAPACITY, "a row is longer than 2^26 entries");
+  if (p->htot[0] > p->chunk_cap) return fail(p, PSL_ERR_CAPACITY, "too many long-row chunks");
+  d.nchunks = p->htot[0];
+  d.colid = nullptr;
+  View mv;
+  mv.bins = bins0;
+  mv.chunks = chunks0;
+  for (int b = 0; b <= NBINS; ++b) mv.off[b] = d.bin_off[b];
+  mv.nchunks = d.nchunks;
+  mv.rows = m;
+  mv.nnz = N;
+  p->master = mv;
+  p->all = mv;
+  use_view(p, mv);
+  if (p->grid.long_base + (int64_t)p->htot[1] > p->cand_cap)
+    return fail(p, PSL_ERR_CAPACITY, "candidate buffer too small for the row bins");
+
+  p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.col_len, p->isc, st);
+  p->cmp.colid = p->colid;
+  d.colid = p->colid;
+
+  // parallel-row table: one slice of >= 2 m_k slots per LP
+  if (p->K == 1) {
+    int64_t cap = 64;
+    while (cap < 2 * m) cap <<= 1;
+    p->par.cap = cap;
+  } else {
+    int64_t base = 0;
+    for (int k = 0; k < p->K; ++k) {
+      int64_t mk = p->h_row0[k + 1] - p->h_row0[k], cap = 64;
+      while (cap < 2 * mk) cap <<= 1;
+      p->h_lpt[k] = LpTab{base, cap};
+      base += cap;
+    }
+    if (base > p->par_slots) return fail(p, PSL_ERR_DEVICE, "internal: parallel-row table too small");
+    p->par.cap = base;
+    HIPCHK(p, hipMemcpyAsync(p->lpt, p->h_lpt, p->K * sizeof(LpTab), hipMemcpyHostToDevice, st));
+  }
+  (void)n;
+  HIPCHK(p, hipEventRecord(p->ev[1], st));
+  HIPCHK(p, hipStreamSynchronize(st));
+  float ms = 0;
+  HIPCHK(p, hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+  p->ms_ingest = ms;
+  p->state = 0;
+  p->host_rec_valid = false;
+  return PSL_OK;
+}
+
+static void set_sizes(psl_presolver* p, int32_t K, int32_t m, int32_t n, int64_t nnz) {
+  p->K = K;
+  p->m = m;
+  p->n = n;
+  p->nnz = nnz;
+  p->d.K = K;
+  p->d.m = m;
+  p->d.n = n;
+  p->d.nnz = nnz;
+}
+
+// copy + validate + transpose + bins of one LP whose shape equals the handle's
 static psl_status ingest(psl_presolver* p, const psl_lp* lp) {
   Dev& d = p->d;
   hipStream_t st = p->stream;
@@ -434,69 +686,93 @@ static psl_status ingest(psl_presolver* p, const psl_lp* lp) {
   HIPCHK(p, cp(p->ub_in, lp->ub, n * 8));
   HIPCHK(p, cp(p->c_mut, lp->c, n * 8));
   p->obj_offset = lp->obj_offset == 0.0 ? 0.0 : lp->obj_offset;
+  return ingest_rest(p);
+}
 
-  launch_init_state(d, st);  // clears the flag block
-  launch_check_rows(d, st);
-  check_cols(d, p->lb_in, p->ub_in, p->c_mut, st);
+// a batch of k LPs (shapes already checked to fit): the union goes into the
+// handle's arrays, from host memory through host-side packing, from device
+// memory by the gather kernels
+static psl_status ingest_batch(psl_presolver* p, int32_t k, const psl_lp* lps) {
+  Dev& d = p->d;
+  hipStream_t st = p->stream;
+  int64_t M = 0, Nc = 0, Z = 0;
+  for (int32_t t = 0; t < k; ++t) {
+    p->h_row0[t] = (int32_t)M;
+    p->h_col0[t] = (int32_t)Nc;
+    p->h_z0[t] = Z;
+    p->h_off_in[t] = lps[t].obj_offset == 0.0 ? 0.0 : lps[t].obj_offset;
+    M += lps[t].m;
+    Nc += lps[t].n;
+    Z += lps[t].nnz;
+  }
+  p->h_row0[k] = (int32_t)M;
+  p->h_col0[k] = (int32_t)Nc;
+  p->h_z0[k] = Z;
+  set_sizes(p, k, (int32_t)M, (int32_t)Nc, Z);
+  p->obj_offset = 0.0;
+  HIPCHK(p, hipEventRecord(p->ev[0], st));
+  HIPCHK(p, hipMemcpyAsync(p->lp_row0, p->h_row0, (k + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(p, hipMemcpyAsync(p->lp_col0, p->h_col0, (k + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(p, hipMemcpyAsync(p->lp_z0, p->h_z0, (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIPCHK(p, hipMemcpyAsync(p->lp_off_in, p->h_off_in, k * sizeof(double), hipMemcpyHostToDevice, st));
+  launch_init_state(d, st);  // clears the error flags for the gather's checks
+  if (lps[0].mem == PSL_MEM_DEVICE) {
+    for (int32_t t = 0; t < k; ++t) {
+      const psl_lp& L = lps[t];
+      p->h_desc[t] = LpDesc{L.row_ptr, L.col_idx, L.val, L.lhs, L.rhs, L.lb, L.ub, L.c, L.m, L.n, L.nnz};
+    }
+    HIPCHK(p, hipMemcpyAsync(p->descs, p->h_desc, k * sizeof(LpDesc), hipMemcpyHostToDevice, st));
+    batch_gather(d, p->descs, p->lp_z0, (int32_t*)d.rp, (int32_t*)d.ci, (double*)d.va, d.lhs, d.rhs, p->lb_in,
+                 p->ub_in, p->c_mut, p->row_lp, p->col_lp, st);
+    fill_i32((int32_t*)d.rp + M, (int32_t)Z, 1, st);
+  } else {
+    // host: pack the union (row pointers and column indices shifted)
+    std::vector<int32_t> rp(M + 1), ci(Z);
+    std::vector<double> va(Z), lhs(M), rhs(M), lb(Nc), ub(Nc), c(Nc);
+    for (int32_t t = 0; t < k; ++t) {
+      const psl_lp& L = lps[t];
+      int64_t r0 = p->h_row0[t], c0 = p->h_col0[t], z0 = p->h_z0[t];
+      if (L.m > 0 && (L.row_ptr[0] != 0 || (int64_t)L.row_ptr[L.m] != L.nnz))
+        return fail(p, PSL_ERR_INVALID, "invalid input in LP " + std::to_string(t) + ": " + error_what(1));
+      for (int32_t i = 0; i < L.m; ++i) rp[r0 + i] = (int32_t)(L.row_ptr[i] + z0);
+      for (int64_t q = 0; q < L.nnz; ++q) {
+        int32_t j = L.col_idx[q];
+        if (j < 0 || j >= L.n)
+          return fail(p, PSL_ERR_INVALID, "invalid input in LP " + std::to_string(t) + ": " + error_what(2) +
+                                              " (first at index " + std::to_string(q) + ")");
+        ci[z0 + q] = (int32_t)(j + c0);
+      }
+      if (L.nnz) std::memcpy(&va[z0], L.val, L.nnz * sizeof(double));
+      if (L.m) {
+        std::memcpy(&lhs[r0], L.lhs, L.m * sizeof(double));
+        std::memcpy(&rhs[r0], L.rhs, L.m * sizeof(double));
+      }
+      if (L.n) {
+        std::memcpy(&lb[c0], L.lb, L.n * sizeof(double));
+        std::memcpy(&ub[c0], L.ub, L.n * sizeof(double));
+        std::memcpy(&c[c0], L.c, L.n * sizeof(double));
+      }
+    }
+    rp[M] = (int32_t)Z;
+    auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+      if (bytes == 0) return hipSuccess;
+      return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    HIPCHK(p, hipStreamSynchronize(st));
+    HIPCHK(p, up((void*)d.rp, rp.data(), (M + 1) * 4));
+    HIPCHK(p, up((void*)d.ci, ci.data(), Z * 4));
+    HIPCHK(p, up((void*)d.va, va.data(), Z * 8));
+    HIPCHK(p, up(d.lhs, lhs.data(), M * 8));
+    HIPCHK(p, up(d.rhs, rhs.data(), M * 8));
+    HIPCHK(p, up(p->lb_in, lb.data(), Nc * 8));
+    HIPCHK(p, up(p->ub_in, ub.data(), Nc * 8));
+    HIPCHK(p, up(p->c_mut, c.data(), Nc * 8));
+    batch_maps(d, p->row_lp, p->col_lp, st);
+  }
   psl_status s0 = read_flags(p);
   if (s0 != PSL_OK) return s0;
-  if (p->hflags->error) return fail(p, PSL_ERR_INVALID, error_message(p->hflags->error, p->hflags->error_pos));
-
-  build_rowid(d, p->isc, st);
-  launch_check_entries(d, p->isc.rowid1, st);
-  s0 = read_flags(p);
-  if (s0 != PSL_OK) return s0;
-  if (p->hflags->error) return fail(p, PSL_ERR_INVALID, error_message(p->hflags->error, p->hflags->error_pos));
-
-  // bins (before the transpose: both use k0/k1)
-  d.bins = p->bins_a;
-  d.lchunk = p->chunks_a;
-  build_bins(d, p->thresholds, p->bins_a, p->bin_counts_dev, p->isc, st);
-  HIPCHK(p, hipMemcpyAsync(p->htot, p->bin_counts_dev, NBINS * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  HIPCHK(p, hipStreamSynchronize(st));
-  int off = 0;
-  for (int b = 0; b < NBINS; ++b) {
-    p->bin_counts[b] = p->htot[b];
-    d.bin_off[b] = off;
-    off += p->htot[b];
-  }
-  d.bin_off[NBINS] = off;
-
-  // long rows: chunk table built on the device
-  int nlong = p->bin_counts[BIN_LONG];
-  if (nlong > p->long_cap) return fail(p, PSL_ERR_CAPACITY, "too many long rows");
-  d.nlong = nlong;
-  build_long_chunks(d, p->thresholds[1] / PASS_LEN, p->chunks_a, d.cnt, d.off, p->bin_counts_dev, p->ws, st);
-  HIPCHK(p, hipMemcpyAsync(p->htot, p->bin_counts_dev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  s0 = read_flags(p);
-  if (s0 != PSL_OK) return s0;
-  if (p->hflags->error & 64) return fail(p, PSL_ERR_CAPACITY, "a row is longer than 2^26 entries");
-  if (p->htot[0] > p->chunk_cap) return fail(p, PSL_ERR_CAPACITY, "too many long-row chunks");
-  d.nchunks = p->htot[0];
-  d.colid = nullptr;
-  View mv;
-  mv.bins = p->bins_a;
-  mv.chunks = p->chunks_a;
-  for (int b = 0; b <= NBINS; ++b) mv.off[b] = d.bin_off[b];
-  mv.nchunks = d.nchunks;
-  mv.rows = m;
-  mv.nnz = N;
-  p->master = mv;
-  use_view(p, mv);
-  if (p->grid.long_base + (int64_t)p->htot[1] > p->cand_cap)
-    return fail(p, PSL_ERR_CAPACITY, "candidate buffer too small for the row bins");
-
-  p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.col_len, p->isc, st);
-  p->cmp.colid = p->colid;
-  d.colid = p->colid;
-  HIPCHK(p, hipEventRecord(p->ev[1], st));
-  HIPCHK(p, hipStreamSynchronize(st));
-  float ms = 0;
-  HIPCHK(p, hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
-  p->ms_ingest = ms;
-  p->state = 0;
-  p->host_rec_valid = false;
-  return PSL_OK;
+  if (p->hflags->error) return fail(p, PSL_ERR_INVALID, error_message(p, p->hflags->error, p->hflags->error_pos));
+  return ingest_rest(p);
 }
 
 extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* s, psl_presolver** out) {
@@ -526,9 +802,11 @@ extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* 
   }
   p->stream = (hipStream_t)s->stream;
   if (const char* e = std::getenv("PSL_SWEEP_SPLIT")) p->sweep_mode = std::atoi(e) ? 2 : MODE_ROUND;
-  p->m = lp->m;
-  p->n = lp->n;
-  p->nnz = lp->nnz;
+  p->cap_m = lp->m;
+  p->cap_n = lp->n;
+  p->cap_nnz = lp->nnz;
+  p->cap_K = 1;
+  set_sizes(p, 1, lp->m, lp->n, lp->nnz);
   psl_status st = setup_arena(p);
   if (st == PSL_OK) st = ingest(p, lp);
   if (st != PSL_OK) {
@@ -544,7 +822,7 @@ extern "C" psl_status psl_presolve_reload(psl_presolver* p, const psl_lp* lp) {
   if (!p || !lp) return PSL_ERR_INVALID;
   std::string e = check_lp_shape(lp);
   if (!e.empty()) return fail(p, PSL_ERR_INVALID, e);
-  if (lp->m != p->m || lp->n != p->n || lp->nnz != p->nnz)
+  if (p->cap_K != 1 || lp->m != p->cap_m || lp->n != p->cap_n || lp->nnz != p->cap_nnz)
     return fail(p, PSL_ERR_INVALID, "reload needs the same m, n and nnz");
   if (hipSetDevice(p->s.device) != hipSuccess) return fail(p, PSL_ERR_DEVICE, "cannot select the device");
   psl_status st = ingest(p, lp);
@@ -578,41 +856,149 @@ static float elapsed(psl_presolver* p, int a, int b) {
   return ms;
 }
 
-extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_stats* stats) {
-  if (!p || !res) return PSL_ERR_INVALID;
-  if (p->state != 0) return fail(p, PSL_ERR_STATE, "run needs a fresh create or reload");
-  if (hipSetDevice(p->s.device) != hipSuccess) return fail(p, PSL_ERR_DEVICE, "cannot select the device");
+// K > 1: upload the LPs' round numbers and clear their flags before a round
+static psl_status begin_lp_round(psl_presolver* p) {
+  if (p->K == 1) return PSL_OK;
+  HIPCHK(p, hipMemcpyAsync(p->lp_round, p->h_round, p->K * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(p, hipMemsetAsync(p->lpf, 0, p->K * sizeof(LpFlags), p->stream));
+  return PSL_OK;
+}
+
+// K > 1: queue the readback of the LPs' flags (and record counts); the next
+// synchronising read completes it
+static psl_status queue_lp_read(psl_presolver* p, bool totals) {
+  if (p->K == 1) return PSL_OK;
+  if (totals) {
+    launch_lp_totals(p->d, true, p->stream);
+    HIPCHK(p, hipMemcpyAsync(p->h_lpo, p->lpo, p->K * sizeof(LpOut), hipMemcpyDeviceToHost, p->stream));
+  }
+  HIPCHK(p, hipMemcpyAsync(p->h_lpf, p->lpf, p->K * sizeof(LpFlags), hipMemcpyDeviceToHost, p->stream));
+  return PSL_OK;
+}
+
+// K > 1: LPs that stopped leave the master bin lists
+static psl_status drop_done_lps(psl_presolver* p) {
+  for (int k = 0; k < p->K; ++k) p->h_ok[k] = p->lst[k].phase != LP_DONE;
+  HIPCHK(p, hipMemcpyAsync(p->lp_ok, p->h_ok, p->K, hipMemcpyHostToDevice, p->stream));
+  View nv;
+  BinEnt* bo = p->master.bins == p->bins_a ? p->bins_b : p->bins_a;
+  LongChunk* co = p->master.chunks == p->chunks_a ? p->chunks_b : p->chunks_a;
+  psl_status e = filter_view(p, p->master, bo, co, false, nv);
+  if (e != PSL_OK) return e;
+  p->master = nv;
+  return PSL_OK;
+}
+
+// scratch of the record split (K > 1), grown to the record count
+static psl_status split_records(psl_presolver* p) {
+  int64_t cnt = p->rec_count;
+  if (cnt > p->split_cap) {
+    for (void* q : {(void*)p->rec_lp, (void*)p->sk0, (void*)p->sk1, (void*)p->sv0, (void*)p->sv1, (void*)p->sws}) {
+      auto it = std::find(p->allocs.begin(), p->allocs.end(), q);
+      if (q && it != p->allocs.end()) {
+        (void)hipFree(q);
+        p->allocs.erase(it);
+      }
+    }
+    int64_t cap = std::max<int64_t>(cnt, 1024);
+    ALLOC(p->rec_lp, cap);
+    ALLOC(p->sk0, cap);
+    ALLOC(p->sk1, cap);
+    ALLOC(p->sv0, cap);
+    ALLOC(p->sv1, cap);
+    ALLOC(p->sws, rec_split_ws_ints(cap) + 64);
+    p->split_cap = cap;
+  }
+  rec_split(p->d, p->rec, cnt, p->rec_lp, p->rec_off, p->sk0, p->sk1, p->sv0, p->sv1, p->sws, p->stream);
+  p->h_rec_off.resize(p->K + 1);
+  HIPCHK(p, hipMemcpyAsync(p->h_rec_off.data(), p->rec_off, (p->K + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  return PSL_OK;
+}
+
+// The round controller for K >= 1 LPs. Each LP's life, as for one LP alone:
+// round 0 (input fixings); then outer cycles of propagation rounds until a
+// round changes nothing or max_rounds is reached, followed by a parallel-row
+// pass, another cycle only if that pass merged rows; infeasible or unbounded
+// ends it at once. In a batch an LP that converged waits for the cycle's
+// parallel pass (sweeping its rows again changes nothing); LPs that stopped
+// are dropped from the bin lists.
+static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   Dev& d = p->d;
   hipStream_t st = p->stream;
   const psl_settings& s = p->s;
+  const int K = p->K;
+  const bool B = K > 1;
   int64_t m = p->m, n = p->n;
   psl_stats S{};
   S.nnz_in = p->nnz;
   p->rec_count = 0;
   p->host_rec_valid = false;
+  p->lp_host_rec.clear();
   p->state = 1;
+  p->lst.assign(K, LpState{});
   HIPCHK(p, hipEventRecord(p->ev[2], st));
+  if (B) {
+    for (int k = 0; k < K; ++k) {
+      p->h_ok[k] = 1;
+      p->h_round[k] = 0;
+    }
+    HIPCHK(p, hipMemcpyAsync(p->lp_ok, p->h_ok, K, hipMemcpyHostToDevice, st));
+    psl_status e0 = begin_lp_round(p);
+    if (e0 != PSL_OK) return e0;
+  }
+  auto lp_inf = [&](int k) { return B ? p->h_lpf[k].infeasible != 0 : p->hflags->infeasible != 0; };
+  auto lp_unb = [&](int k) { return B ? p->h_lpf[k].unbounded != 0 : p->hflags->unbounded != 0; };
+  auto lp_merged = [&](int k) { return B ? p->h_lpf[k].merged != 0 : p->hflags->merged != 0; };
+  auto lp_total = [&](int k) { return B ? p->h_lpo[k].total : p->hflags->round_total; };
 
   // round 0: input fixings
   launch_init_state(d, st);
   launch_round0_count(d, st);
   scan_excl(d.cnt, d.off, m + n, &d.flags->round_total, p->ws, st);
   launch_round0_emit(d, 0, st);
-  psl_status e = read_flags(p);
+  psl_status e = queue_lp_read(p, false);
+  if (e != PSL_OK) return e;
+  e = read_flags(p);
   if (e != PSL_OK) return e;
   p->rec_count += p->hflags->round_total;
   int round = 0;
-  bool infeasible = p->hflags->infeasible != 0, unbounded = false;
   double sweep_ms = 0.0, decide_ms = 0.0, par_ms = 0.0, long_ms = 0.0;
-
-  bool stop = infeasible;
-  bool was_incremental = false;
+  bool any_done = false;
+  for (int k = 0; k < K; ++k)
+    if (lp_inf(k)) {
+      p->lst[k].phase = LP_DONE;
+      p->lst[k].infeasible = true;
+      p->lst[k].cycles = 1;
+      any_done = true;
+    }
   use_view(p, p->master);
+  if (B && any_done) {
+    e = drop_done_lps(p);
+    if (e != PSL_OK) return e;
+    use_view(p, p->master);
+  }
+
+  bool was_incremental = false;
   int outer = 0;
-  for (; outer < s.max_outer && !stop; ++outer) {
+  for (; outer < s.max_outer; ++outer) {
+    int nprop = 0;
+    for (auto& L : p->lst)
+      if (L.phase == LP_PROP) {
+        L.cycles = outer + 1;
+        ++nprop;
+      }
+    if (nprop == 0) break;
     for (int r = 0; r < s.max_rounds; ++r) {
       ++round;
+      for (int k = 0; k < K; ++k)
+        if (p->lst[k].phase == LP_PROP) {
+          ++p->lst[k].rounds;
+          if (B) p->h_round[k] = p->lst[k].rounds;
+        }
       e = ensure_capacity(p, m + 3 * n + 16);
+      if (e == PSL_OK) e = begin_lp_round(p);
       if (e != PSL_OK) return e;
       HIPCHK(p, hipEventRecord(p->ev[4], st));
       launch_long_stats(d, MODE_ROUND, st);
@@ -624,6 +1010,8 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
       scan_excl(d.cnt, d.off, m + n, &d.flags->round_total, p->ws, st);
       launch_emit(d, p->rec_count, round, st);
       HIPCHK(p, hipEventRecord(p->ev[6], st));
+      e = queue_lp_read(p, true);
+      if (e != PSL_OK) return e;
       int32_t removed = 0;
       e = read_round(p, m, &removed);
       if (e != PSL_OK) return e;
@@ -633,21 +1021,39 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
       S.sweep_launches += 1;
       S.sweep_bytes += 12.0 * p->cur.nnz + 24.0 * p->cur.rows + 16.0 * n;
       p->rec_count += p->hflags->round_total;
-      if (p->hflags->infeasible) infeasible = true;
-      if (p->hflags->unbounded) unbounded = true;
-      if (infeasible || unbounded) {
-        stop = true;
-        break;
+      any_done = false;
+      nprop = 0;
+      for (int k = 0; k < K; ++k) {
+        LpState& L = p->lst[k];
+        if (L.phase != LP_PROP) continue;
+        if (lp_inf(k)) {
+          L.phase = LP_DONE;
+          L.infeasible = true;
+          any_done = true;
+        } else if (lp_unb(k)) {
+          L.phase = LP_DONE;
+          L.unbounded = true;
+          any_done = true;
+        } else if (lp_total(k) == 0) {
+          L.phase = LP_WAIT;
+        } else {
+          ++nprop;
+        }
       }
-      if (p->hflags->round_total == 0) break;
-      // keep the master lists on live rows once a sixteenth of them went
-      if (removed > 0 && (int64_t)removed * 16 >= p->master.rows) {
-        View nv;
-        BinEnt* bo = p->master.bins == p->bins_a ? p->bins_b : p->bins_a;
-        LongChunk* co = p->master.chunks == p->chunks_a ? p->chunks_b : p->chunks_a;
-        e = filter_view(p, p->master, bo, co, false, nv);
+      if (nprop == 0) break;
+      // keep the master lists on live rows once a sixteenth of them went (and
+      // on live LPs)
+      if ((removed > 0 && (int64_t)removed * 16 >= p->master.rows) || (B && any_done)) {
+        if (B) {
+          e = drop_done_lps(p);
+        } else {
+          View nv;
+          BinEnt* bo = p->master.bins == p->bins_a ? p->bins_b : p->bins_a;
+          LongChunk* co = p->master.chunks == p->chunks_a ? p->chunks_b : p->chunks_a;
+          e = filter_view(p, p->master, bo, co, false, nv);
+          p->master = nv;
+        }
         if (e != PSL_OK) return e;
-        p->master = nv;
       }
       // Next round: rows none of whose columns changed since they were last
       // swept give the same statistics and no qualifying candidate, so after
@@ -668,9 +1074,23 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
     }
     use_view(p, p->master);
     was_incremental = false;
-    if (stop || !s.enable_parallel_rows) break;
+    // the cycle's parallel-row pass, for every LP still presolving
+    int npar = 0;
+    for (auto& L : p->lst)
+      if (L.phase != LP_DONE) ++npar;
+    if (npar == 0) break;
+    if (!s.enable_parallel_rows) {
+      for (auto& L : p->lst) L.phase = LP_DONE;
+      break;
+    }
     ++round;
+    for (int k = 0; k < K; ++k)
+      if (p->lst[k].phase != LP_DONE) {
+        ++p->lst[k].rounds;
+        if (B) p->h_round[k] = p->lst[k].rounds;
+      }
     e = ensure_capacity(p, m + 16);
+    if (e == PSL_OK) e = begin_lp_round(p);
     if (e != PSL_OK) return e;
     HIPCHK(p, hipEventRecord(p->ev[4], st));
     launch_par_reset(d, p->par, st);
@@ -681,27 +1101,49 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
     launch_par_emit(d, p->par, p->rec_count, round, st);
     launch_par_drop(d, p->par, st);
     HIPCHK(p, hipEventRecord(p->ev[5], st));
-    e = read_flags(p);
+    e = queue_lp_read(p, false);
+    if (e == PSL_OK) e = read_flags(p);
     if (e != PSL_OK) return e;
     par_ms += elapsed(p, 4, 5);
     p->rec_count += p->hflags->round_total;
-    if (p->hflags->infeasible) {
-      infeasible = true;
-      stop = true;
-      break;
+    any_done = false;
+    for (int k = 0; k < K; ++k) {
+      LpState& L = p->lst[k];
+      if (L.phase == LP_DONE) continue;
+      if (lp_inf(k)) {
+        L.phase = LP_DONE;
+        L.infeasible = true;
+      } else if (lp_merged(k) && outer + 1 < s.max_outer) {
+        L.phase = LP_PROP;
+      } else {
+        L.phase = LP_DONE;
+      }
+      any_done |= L.phase == LP_DONE;
     }
-    if (!p->hflags->merged) break;
+    if (B && any_done) {
+      e = drop_done_lps(p);
+      if (e != PSL_OK) return e;
+      use_view(p, p->master);
+    }
   }
-  if (outer == s.max_outer) outer = s.max_outer;  // cap reached
 
-  psl_result result;
-  if (infeasible) result = PSL_RES_INFEASIBLE;
-  else if (unbounded) result = PSL_RES_UNBOUNDED_OR_INFEASIBLE;
-  else result = p->rec_count ? PSL_RES_REDUCED : PSL_RES_UNCHANGED;
-
+  // compaction of the LPs that ended feasible
+  bool any_feasible = false;
+  for (auto& L : p->lst) any_feasible |= !L.infeasible && !L.unbounded;
   double cmp_ms = 0.0;
-  if (result == PSL_RES_REDUCED || result == PSL_RES_UNCHANGED) {
-    use_view(p, p->master);
+  p->red_m = p->red_n = 0;
+  p->red_nnz = 0;
+  if (any_feasible) {
+    if (B) {
+      for (int k = 0; k < K; ++k) p->h_ok[k] = !p->lst[k].infeasible && !p->lst[k].unbounded;
+      HIPCHK(p, hipMemcpyAsync(p->lp_ok, p->h_ok, K, hipMemcpyHostToDevice, st));
+      View cv;
+      e = filter_view(p, p->all, p->bins_s, p->chunks_s, false, cv);
+      if (e != PSL_OK) return e;
+      use_view(p, cv);
+    } else {
+      use_view(p, p->master);
+    }
     HIPCHK(p, hipEventRecord(p->ev[4], st));
     launch_long_stats(d, MODE_COMPACT, st);
     launch_sweep(d, p->grid, MODE_COMPACT, st);
@@ -709,20 +1151,40 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
     compact_write(d, p->cmp, p->red, p->obj_offset, st);
     HIPCHK(p, hipEventRecord(p->ev[5], st));
     HIPCHK(p, hipMemcpyAsync(p->htot, p->cmp.totals, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(p, hipMemcpyAsync(p->hoff, p->cmp.offset, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(p, hipMemcpyAsync(p->h_lpr, p->lpr, (K + 1) * sizeof(LpRed), hipMemcpyDeviceToHost, st));
+    if (B) HIPCHK(p, hipMemcpyAsync(p->h_off, p->cmp.offset, K * sizeof(double), hipMemcpyDeviceToHost, st));
+    else HIPCHK(p, hipMemcpyAsync(p->hoff, p->cmp.offset, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(p, hipStreamSynchronize(st));
     cmp_ms = elapsed(p, 4, 5);
     p->red_m = p->htot[0];
     p->red_n = p->htot[1];
     p->red_nnz = p->htot[2];
-    p->red_off = *p->hoff;
+    p->red_off = B ? 0.0 : *p->hoff;
     if (p->htot[2] != p->htot[3]) return fail(p, PSL_ERR_DEVICE, "reduced CSR and transposed copy disagree");
+    for (int k = 0; k < K; ++k)
+      if (p->h_lpr[k + 1].eb - p->h_lpr[k].eb != p->h_lpr[k + 1].qb - p->h_lpr[k].qb)
+        return fail(p, PSL_ERR_DEVICE, "reduced CSR and transposed copy disagree");
+  }
+  if (B) {
+    e = split_records(p);
+    if (e != PSL_OK) return e;
   }
   HIPCHK(p, hipEventRecord(p->ev[3], st));
   HIPCHK(p, hipEventSynchronize(p->ev[3]));
-  p->result = result;
+
+  p->lp_result.resize(K);
+  for (int k = 0; k < K; ++k) {
+    const LpState& L = p->lst[k];
+    int64_t recs = B ? p->h_rec_off[k + 1] - p->h_rec_off[k] : p->rec_count;
+    p->lp_result[k] = L.infeasible ? PSL_RES_INFEASIBLE
+                      : L.unbounded ? PSL_RES_UNBOUNDED_OR_INFEASIBLE
+                      : recs ? PSL_RES_REDUCED
+                             : PSL_RES_UNCHANGED;
+  }
+  p->result = p->lp_result[0];
   S.rounds = round;
-  S.outer_cycles = std::min(outer + 1, s.max_outer);
+  S.outer_cycles = 1;
+  for (auto& L : p->lst) S.outer_cycles = std::max(S.outer_cycles, L.cycles);
   S.records = p->rec_count;
   S.nnz_out = p->red_nnz;
   S.m_out = p->red_m;
@@ -735,64 +1197,137 @@ extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_st
   S.ms_compact = cmp_ms;
   S.ms_total = elapsed(p, 2, 3);
   p->stats = S;
-  *res = result;
+  if (out) *out = S;
+  return PSL_OK;
+}
+
+extern "C" psl_status psl_presolve_run(psl_presolver* p, psl_result* res, psl_stats* stats) {
+  if (!p || !res) return PSL_ERR_INVALID;
+  if (p->state != 0) return fail(p, PSL_ERR_STATE, "run needs a fresh create or reload");
+  if (hipSetDevice(p->s.device) != hipSuccess) return fail(p, PSL_ERR_DEVICE, "cannot select the device");
+  psl_stats S{};
+  psl_status e = run_engine(p, &S);
+  if (e != PSL_OK) return e;
+  *res = p->result;
   if (stats) *stats = S;
   return PSL_OK;
 }
 
+// view of LP k's reduced problem (K = 1: the whole reduced problem)
+static psl_reduced_view reduced_view(const psl_presolver* p, int k) {
+  const LpRed& b = p->h_lpr[k];
+  const LpRed& e = p->h_lpr[k + 1];
+  psl_reduced_view v;
+  v.m = e.rb - b.rb;
+  v.n = e.cb - b.cb;
+  v.nnz = e.eb - b.eb;
+  v.row_ptr = p->red.row_ptr + b.rb + k;
+  v.col_idx = p->red.col_idx + b.eb;
+  v.val = p->red.val + b.eb;
+  v.col_ptr = p->red.col_ptr + b.cb + k;
+  v.row_idx = p->red.row_idx + b.qb;
+  v.cval = p->red.cval + b.qb;
+  v.lhs = p->red.lhs + b.rb;
+  v.rhs = p->red.rhs + b.rb;
+  v.lb = p->red.lb + b.cb;
+  v.ub = p->red.ub + b.cb;
+  v.c = p->red.c + b.cb;
+  v.obj_offset = p->K > 1 ? p->h_off[k] : p->red_off;
+  v.row_map = p->red.row_map + b.rb;
+  v.col_map = p->red.col_map + b.cb;
+  v.row_class = p->red.row_class + b.rb;
+  v.col_class = p->red.col_class + b.cb;
+  return v;
+}
+
+static bool has_reduced(const psl_presolver* p, int k) {
+  return p->state == 1 && k >= 0 && k < (int)p->lp_result.size() &&
+         (p->lp_result[k] == PSL_RES_REDUCED || p->lp_result[k] == PSL_RES_UNCHANGED);
+}
+
 extern "C" psl_status psl_reduced_problem(const psl_presolver* p, psl_reduced_view* out) {
   if (!p || !out) return PSL_ERR_INVALID;
-  if (p->state != 1 || (p->result != PSL_RES_REDUCED && p->result != PSL_RES_UNCHANGED)) {
+  if (!has_reduced(p, 0)) {
     const_cast<psl_presolver*>(p)->err = "no reduced problem: run first (and the result must not be infeasible)";
     return PSL_ERR_STATE;
   }
-  psl_reduced_view v;
-  v.m = p->red_m;
-  v.n = p->red_n;
-  v.nnz = p->red_nnz;
-  v.row_ptr = p->red.row_ptr;
-  v.col_idx = p->red.col_idx;
-  v.val = p->red.val;
-  v.col_ptr = p->red.col_ptr;
-  v.row_idx = p->red.row_idx;
-  v.cval = p->red.cval;
-  v.lhs = p->red.lhs;
-  v.rhs = p->red.rhs;
-  v.lb = p->red.lb;
-  v.ub = p->red.ub;
-  v.c = p->red.c;
-  v.obj_offset = p->red_off;
-  v.row_map = p->red.row_map;
-  v.col_map = p->red.col_map;
-  v.row_class = p->red.row_class;
-  v.col_class = p->red.col_class;
-  *out = v;
+  *out = reduced_view(p, 0);
   return PSL_OK;
 }
 
-static psl_status fetch_records(psl_presolver* p) {
-  if (p->host_rec_valid) return PSL_OK;
-  p->host_rec.resize((size_t)p->rec_count);
-  if (p->rec_count) {
-    HIPCHK(p, hipMemcpyAsync(p->host_rec.data(), p->rec, p->rec_count * sizeof(Record), hipMemcpyDeviceToHost,
-                             p->stream));
-    HIPCHK(p, hipStreamSynchronize(p->stream));
+// records of LP k on the host (K = 1: all records)
+static psl_status fetch_lp_records(psl_presolver* p, int k, const std::vector<psl_record>** out) {
+  if (p->K == 1) {
+    if (!p->host_rec_valid) {
+      p->host_rec.resize((size_t)p->rec_count);
+      if (p->rec_count) {
+        HIPCHK(p, hipMemcpyAsync(p->host_rec.data(), p->rec, p->rec_count * sizeof(Record), hipMemcpyDeviceToHost,
+                                 p->stream));
+        HIPCHK(p, hipStreamSynchronize(p->stream));
+      }
+      p->host_rec_valid = true;
+    }
+    *out = &p->host_rec;
+    return PSL_OK;
   }
-  p->host_rec_valid = true;
+  if (p->lp_host_rec.size() != (size_t)p->K) {
+    p->lp_host_rec.assign(p->K, {});
+    p->lp_rec_valid.assign(p->K, 0);
+  }
+  if (!p->lp_rec_valid[k]) {
+    int64_t a = p->h_rec_off[k], c = p->h_rec_off[k + 1] - a;
+    auto& v = p->lp_host_rec[k];
+    v.resize((size_t)c);
+    if (c) {
+      HIPCHK(p, hipMemcpyAsync(v.data(), p->rec_lp + a, c * sizeof(Record), hipMemcpyDeviceToHost, p->stream));
+      HIPCHK(p, hipStreamSynchronize(p->stream));
+    }
+    p->lp_rec_valid[k] = 1;
+  }
+  *out = &p->lp_host_rec[k];
+  return PSL_OK;
+}
+
+static psl_status records_of(psl_presolver* p, int k, int64_t* count, psl_record* out, int64_t cap) {
+  if (p->state != 1) return fail(p, PSL_ERR_STATE, "no run yet");
+  int64_t c = p->K == 1 ? p->rec_count : p->h_rec_off[k + 1] - p->h_rec_off[k];
+  if (out) {
+    if (cap < c) return fail(p, PSL_ERR_CAPACITY, "record buffer too small");
+    const std::vector<psl_record>* v = nullptr;
+    psl_status st = fetch_lp_records(p, k, &v);
+    if (st != PSL_OK) return st;
+    if (c) std::memcpy(out, v->data(), c * sizeof(psl_record));
+  }
+  *count = c;
   return PSL_OK;
 }
 
 extern "C" psl_status psl_records(const psl_presolver* cp, int64_t* count, psl_record* out, int64_t cap) {
   psl_presolver* p = const_cast<psl_presolver*>(cp);
   if (!p || !count) return PSL_ERR_INVALID;
-  if (p->state != 1) return fail(p, PSL_ERR_STATE, "no run yet");
-  if (out) {
-    if (cap < p->rec_count) return fail(p, PSL_ERR_CAPACITY, "record buffer too small");
-    psl_status st = fetch_records(p);
-    if (st != PSL_OK) return st;
-    if (p->rec_count) std::memcpy(out, p->host_rec.data(), p->rec_count * sizeof(psl_record));
+  return records_of(p, 0, count, out, cap);
+}
+
+// primal postsolve of LP k: kept columns from x_red, removed ones from their
+// FIX_COL / EMPTY_COL records; the other records keep the feasible set
+static psl_status postsolve_of(psl_presolver* p, int k, const double* x_red, const double* y_red,
+                               const double* z_red, double* x) {
+  if (y_red || z_red) return fail(p, PSL_ERR_UNSUPPORTED, "dual postsolve is not provided");
+  if (!has_reduced(p, k)) return fail(p, PSL_ERR_STATE, "no reduced problem to postsolve");
+  psl_reduced_view v = reduced_view(p, k);
+  int32_t n = p->K == 1 ? p->n : p->h_col0[k + 1] - p->h_col0[k];
+  if ((n > 0 && !x) || (v.n > 0 && !x_red)) return fail(p, PSL_ERR_INVALID, "null solution array");
+  const std::vector<psl_record>* rec = nullptr;
+  psl_status st = fetch_lp_records(p, k, &rec);
+  if (st != PSL_OK) return st;
+  std::vector<int32_t> cmap(v.n);
+  if (v.n) HIPCHK(p, hipMemcpy(cmap.data(), v.col_map, v.n * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int32_t j = 0; j < n; ++j) x[j] = 0.0;
+  for (int32_t t = 0; t < v.n; ++t) x[cmap[t]] = x_red[t];
+  for (int64_t t = (int64_t)rec->size() - 1; t >= 0; --t) {
+    const psl_record& r = (*rec)[t];
+    if (r.type == REC_FIX_COL || r.type == REC_EMPTY_COL) x[r.j] = r.v[0];
   }
-  *count = p->rec_count;
   return PSL_OK;
 }
 
@@ -801,22 +1336,7 @@ extern "C" psl_status psl_postsolve(psl_presolver* p, const double* x_red, const
   (void)y;
   (void)z;
   if (!p) return PSL_ERR_INVALID;
-  if (y_red || z_red) return fail(p, PSL_ERR_UNSUPPORTED, "dual postsolve is not provided");
-  if (p->state != 1 || (p->result != PSL_RES_REDUCED && p->result != PSL_RES_UNCHANGED))
-    return fail(p, PSL_ERR_STATE, "no reduced problem to postsolve");
-  if ((p->n > 0 && !x) || (p->red_n > 0 && !x_red)) return fail(p, PSL_ERR_INVALID, "null solution array");
-  psl_status st = fetch_records(p);
-  if (st != PSL_OK) return st;
-  std::vector<int32_t> cmap(p->red_n);
-  if (p->red_n)
-    HIPCHK(p, hipMemcpy(cmap.data(), p->red.col_map, p->red_n * sizeof(int32_t), hipMemcpyDeviceToHost));
-  for (int32_t j = 0; j < p->n; ++j) x[j] = 0.0;
-  for (int32_t k = 0; k < p->red_n; ++k) x[cmap[k]] = x_red[k];
-  for (int64_t t = p->rec_count - 1; t >= 0; --t) {
-    const psl_record& r = p->host_rec[t];
-    if (r.type == REC_FIX_COL || r.type == REC_EMPTY_COL) x[r.j] = r.v[0];
-  }
-  return PSL_OK;
+  return postsolve_of(p, 0, x_red, y_red, z_red, x);
 }
 
 extern "C" void psl_presolve_free(psl_presolver* p) {
@@ -825,9 +1345,7 @@ extern "C" void psl_presolve_free(psl_presolver* p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
   for (void* a : p->allocs) (void)hipFree(a);
-  if (p->hflags) (void)hipHostFree(p->hflags);
-  if (p->htot) (void)hipHostFree(p->htot);
-  if (p->hoff) (void)hipHostFree(p->hoff);
+  for (void* a : p->hallocs) (void)hipHostFree(a);
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
   delete p;
@@ -836,4 +1354,170 @@ extern "C" void psl_presolve_free(psl_presolver* p) {
 extern "C" const char* psl_last_error(const psl_presolver* p) {
   if (!p) return g_create_error.c_str();
   return p->err.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// batched presolve
+// ---------------------------------------------------------------------------
+struct psl_batch {
+  psl_presolver* p = nullptr;
+};
+
+namespace {
+thread_local std::string g_batch_error = "no error";
+}
+
+static std::string check_batch(int32_t k, const psl_lp* lps, int64_t& M, int64_t& Nc, int64_t& Z) {
+  M = Nc = Z = 0;
+  if (k < 1) return "a batch needs k >= 1 LPs";
+  for (int32_t t = 0; t < k; ++t) {
+    std::string e = check_lp_shape(&lps[t]);
+    if (!e.empty()) return "LP " + std::to_string(t) + ": " + e;
+    if (lps[t].mem != lps[0].mem) return "all LPs of a batch must have the same mem kind";
+    M += lps[t].m;
+    Nc += lps[t].n;
+    Z += lps[t].nnz;
+  }
+  if (Z >= ((int64_t)1 << 30)) return "total nnz of a batch must be below 2^30";
+  if (M >= ((int64_t)1 << 30) || Nc >= ((int64_t)1 << 30)) return "a batch must have below 2^30 rows and columns";
+  return "";
+}
+
+static psl_status batch_load(psl_presolver* p, int32_t k, const psl_lp* lps) {
+  if (k == 1) {
+    set_sizes(p, 1, lps[0].m, lps[0].n, lps[0].nnz);
+    return ingest(p, &lps[0]);
+  }
+  return ingest_batch(p, k, lps);
+}
+
+extern "C" psl_status psl_batch_create(int32_t k, const psl_lp* lps, const psl_settings* s, psl_batch** out) {
+  if (!lps || !out) {
+    g_batch_error = "null argument";
+    return PSL_ERR_INVALID;
+  }
+  psl_settings def;
+  psl_settings_default(&def);
+  if (!s) s = &def;
+  int64_t M, Nc, Z;
+  std::string e = check_settings(s);
+  if (e.empty()) e = check_batch(k, lps, M, Nc, Z);
+  if (!e.empty()) {
+    g_batch_error = e;
+    return PSL_ERR_INVALID;
+  }
+  if (hipSetDevice(s->device) != hipSuccess) {
+    g_batch_error = "cannot select the device";
+    return PSL_ERR_DEVICE;
+  }
+  psl_presolver* p = new psl_presolver();
+  p->s = *s;
+  p->s.bin_thresholds = nullptr;
+  if (s->bin_thresholds) {
+    p->thresholds[0] = s->bin_thresholds[0];
+    p->thresholds[1] = s->bin_thresholds[1];
+  }
+  p->stream = (hipStream_t)s->stream;
+  p->cap_m = (int32_t)M;
+  p->cap_n = (int32_t)Nc;
+  p->cap_nnz = Z;
+  p->cap_K = k;
+  psl_status st = setup_arena(p);
+  if (st == PSL_OK) st = batch_load(p, k, lps);
+  if (st != PSL_OK) {
+    g_batch_error = p->err;
+    psl_presolve_free(p);
+    return st;
+  }
+  psl_batch* b = new psl_batch();
+  b->p = p;
+  *out = b;
+  return PSL_OK;
+}
+
+extern "C" psl_status psl_batch_reload(psl_batch* b, int32_t k, const psl_lp* lps) {
+  if (!b || !lps) return PSL_ERR_INVALID;
+  psl_presolver* p = b->p;
+  int64_t M, Nc, Z;
+  std::string e = check_batch(k, lps, M, Nc, Z);
+  if (!e.empty()) return fail(p, PSL_ERR_INVALID, e);
+  if (k > p->cap_K || M > p->cap_m || Nc > p->cap_n || Z > p->cap_nnz)
+    return fail(p, PSL_ERR_CAPACITY, "the LPs exceed the batch's capacity");
+  if (hipSetDevice(p->s.device) != hipSuccess) return fail(p, PSL_ERR_DEVICE, "cannot select the device");
+  psl_status st = batch_load(p, k, lps);
+  if (st != PSL_OK) p->state = 2;
+  return st;
+}
+
+extern "C" psl_status psl_batch_run(psl_batch* b, psl_result* res, psl_stats* total) {
+  if (!b || !res) return PSL_ERR_INVALID;
+  psl_presolver* p = b->p;
+  if (p->state != 0) return fail(p, PSL_ERR_STATE, "run needs a fresh create or reload");
+  if (hipSetDevice(p->s.device) != hipSuccess) return fail(p, PSL_ERR_DEVICE, "cannot select the device");
+  psl_stats S{};
+  psl_status e = run_engine(p, &S);
+  if (e != PSL_OK) return e;
+  for (int k = 0; k < p->K; ++k) res[k] = p->lp_result[k];
+  if (total) *total = S;
+  return PSL_OK;
+}
+
+static bool batch_idx_ok(const psl_batch* b, int32_t idx) {
+  return b && idx >= 0 && idx < b->p->K;
+}
+
+extern "C" psl_status psl_batch_stats(const psl_batch* b, int32_t idx, psl_stats* out) {
+  if (!batch_idx_ok(b, idx) || !out) return PSL_ERR_INVALID;
+  psl_presolver* p = b->p;
+  if (p->state != 1) return fail(p, PSL_ERR_STATE, "no run yet");
+  psl_stats S = p->stats;
+  const LpState& L = p->lst[idx];
+  S.rounds = L.rounds;
+  S.outer_cycles = std::max(1, L.cycles);
+  S.records = p->K == 1 ? p->rec_count : p->h_rec_off[idx + 1] - p->h_rec_off[idx];
+  S.nnz_in = p->K == 1 ? p->nnz : p->h_z0[idx + 1] - p->h_z0[idx];
+  if (has_reduced(p, idx)) {
+    psl_reduced_view v = reduced_view(p, idx);
+    S.nnz_out = v.nnz;
+    S.m_out = v.m;
+    S.n_out = v.n;
+  } else {
+    S.nnz_out = 0;
+    S.m_out = S.n_out = 0;
+  }
+  *out = S;
+  return PSL_OK;
+}
+
+extern "C" psl_status psl_batch_reduced_problem(const psl_batch* b, int32_t idx, psl_reduced_view* out) {
+  if (!batch_idx_ok(b, idx) || !out) return PSL_ERR_INVALID;
+  if (!has_reduced(b->p, idx))
+    return fail(b->p, PSL_ERR_STATE, "no reduced problem: run first (and the result must not be infeasible)");
+  *out = reduced_view(b->p, idx);
+  return PSL_OK;
+}
+
+extern "C" psl_status psl_batch_records(const psl_batch* b, int32_t idx, int64_t* count, psl_record* out,
+                                        int64_t cap) {
+  if (!batch_idx_ok(b, idx) || !count) return PSL_ERR_INVALID;
+  return records_of(b->p, idx, count, out, cap);
+}
+
+extern "C" psl_status psl_batch_postsolve(psl_batch* b, int32_t idx, const double* x_red, const double* y_red,
+                                          const double* z_red, double* x, double* y, double* z) {
+  (void)y;
+  (void)z;
+  if (!batch_idx_ok(b, idx)) return PSL_ERR_INVALID;
+  return postsolve_of(b->p, idx, x_red, y_red, z_red, x);
+}
+
+extern "C" void psl_batch_free(psl_batch* b) {
+  if (!b) return;
+  psl_presolve_free(b->p);
+  delete b;
+}
+
+extern "C" const char* psl_batch_last_error(const psl_batch* b) {
+  if (!b) return g_batch_error.c_str();
+  return b->p->err.c_str();
 }

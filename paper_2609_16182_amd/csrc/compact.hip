@@ -6,7 +6,8 @@
 //
 // Output positions come from exclusive scans of keep flags over the CSR
 // positions and over the transposed copy's positions, so the kept entries keep
-// their order in both layouts.
+// their order in both layouts. In a batch the LPs are blocks of one LP, so
+// each LP's kept rows, columns and entries are contiguous in these scans.
 #include "psl_kern.h"
 #include "sweep.h"
 
@@ -40,17 +41,44 @@ __global__ void k_cmp_offset(const double* sum, double off, double* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = pos0(off + sum[0]);
 }
 
+// Batched presolve: each LP's reduced problem is numbered from 0 (its rows,
+// columns and positions start at the LP's bases in c.lpr) and its row and
+// column pointer arrays get one end entry each, at lpr.rb + k and lpr.cb + k.
+__global__ void k_cmp_lpbase(Dev d, CompactScratch c, Reduced r) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > d.K) return;
+  auto base = [&](int q) {
+    int i0 = d.K > 1 ? d.lp_row0[q] : (q ? d.m : 0);
+    int j0 = d.K > 1 ? d.lp_col0[q] : (q ? d.n : 0);
+    LpRed b;
+    b.rb = i0 < d.m ? c.row_new[i0] : c.totals[0];
+    b.cb = j0 < d.n ? c.col_new[j0] : c.totals[1];
+    b.eb = c.eflag[d.rp[i0]];
+    b.qb = c.qflag[d.cp[j0]];
+    return b;
+  };
+  LpRed b = base(k);
+  c.lpr[k] = b;
+  if (k < d.K) {
+    LpRed e = base(k + 1);
+    r.row_ptr[e.rb + k] = e.eb - b.eb;
+    r.col_ptr[e.cb + k] = e.qb - b.qb;
+  }
+}
+
 __global__ void k_cmp_gather(Dev d, CompactScratch c, Reduced r) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < d.nnz; p += stride) {
     int pe = c.eflag[p];
     if (c.eflag[p + 1] != pe) {  // kept
-      r.col_idx[pe] = c.col_new[d.ci[p]];
+      int j = d.ci[p];
+      r.col_idx[pe] = c.col_new[j] - (d.K > 1 ? c.lpr[d.col_lp[j]].cb : 0);
       r.val[pe] = d.va[p];
     }
     int pq = c.qflag[p];
     if (c.qflag[p + 1] != pq) {
-      r.row_idx[pq] = c.row_new[d.ri[p]];
+      int i = d.ri[p];
+      r.row_idx[pq] = c.row_new[i] - (d.K > 1 ? c.lpr[d.row_lp[i]].rb : 0);
       r.cval[pq] = d.cva[p];
     }
   }
@@ -59,13 +87,11 @@ __global__ void k_cmp_gather(Dev d, CompactScratch c, Reduced r) {
 __global__ void k_cmp_fill(Dev d, CompactScratch c, Reduced r) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t m = d.m, n = d.n;
-  if (t == 0) {
-    r.row_ptr[c.totals[0]] = c.totals[2];
-    r.col_ptr[c.totals[1]] = c.totals[2];
-  }
   if (t < m) {
     int i = (int)t;
     if (!d.row_on[i]) return;
+    int lp = row_lp_of(d, i);
+    LpRed b = c.lpr[lp];
     int ri = c.row_new[i];
     double k = d.row_out[i].v0;  // constant of the removed columns
     double l = d.lhs[i], u = d.rhs[i];
@@ -73,10 +99,10 @@ __global__ void k_cmp_fill(Dev d, CompactScratch c, Reduced r) {
     double nu = is_inf(u) ? u : pos0(u - k);
     int p0 = c.eflag[d.rp[i]], p1 = c.eflag[d.rp[i + 1]];
     int len = p1 - p0;
-    r.row_map[ri] = i;
+    r.row_map[ri] = i - (d.K > 1 ? d.lp_row0[lp] : 0);
     r.lhs[ri] = nl;
     r.rhs[ri] = nu;
-    r.row_ptr[ri] = p0;
+    r.row_ptr[ri + lp] = p0 - b.eb;
     r.row_class[ri] = len == 1 ? 1 : len == 2 ? (nl == nu ? 2 : 3) : 0;
     return;
   }
@@ -84,14 +110,16 @@ __global__ void k_cmp_fill(Dev d, CompactScratch c, Reduced r) {
   int j = (int)(t - m);
   double2 b = d.bnd[j];
   if (b.x == b.y) return;
+  int lp = col_lp_of(d, j);
+  LpRed cb = c.lpr[lp];
   int rj = c.col_new[j];
   int q0 = c.qflag[d.cp[j]], q1 = c.qflag[d.cp[j + 1]];
   int len = q1 - q0;
-  r.col_map[rj] = j;
+  r.col_map[rj] = j - (d.K > 1 ? d.lp_col0[lp] : 0);
   r.lb[rj] = b.x;
   r.ub[rj] = b.y;
   r.c[rj] = d.c[j];
-  r.col_ptr[rj] = q0;
+  r.col_ptr[rj + lp] = q0 - cb.qb;
   bool fr = is_inf(b.x) && is_inf(b.y);
   r.col_class[rj] = len == 1 ? (fr ? 1 : 2) : len == 2 ? 3 : 0;
 }
@@ -110,8 +138,13 @@ void compact_flags(const Dev& d, const CompactScratch& c, hipStream_t s) {
 }
 
 void compact_write(const Dev& d, const CompactScratch& c, const Reduced& r, double obj_offset, hipStream_t s) {
-  pairwise_sum(c.terms, d.n, c.pws, c.pws + 1, s);
-  hipLaunchKernelGGL(k_cmp_offset, dim3(1), dim3(64), 0, s, (const double*)c.pws, obj_offset, c.offset);
+  if (d.K == 1) {
+    pairwise_sum(c.terms, d.n, c.pws, c.pws + 1, s);
+    hipLaunchKernelGGL(k_cmp_offset, dim3(1), dim3(64), 0, s, (const double*)c.pws, obj_offset, c.offset);
+  } else {
+    segmented_pairwise_sum(c.terms, c.seg, c.seg_host, d.K, c.lp_off_in, c.offset, c.pws, s);
+  }
+  hipLaunchKernelGGL(k_cmp_lpbase, dim3((d.K + PSL_BLOCK) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, c, r);
   if (d.nnz > 0) {
     int64_t blocks = (d.nnz + PSL_BLOCK - 1) / PSL_BLOCK;
     if (blocks > 16384) blocks = 16384;

@@ -240,8 +240,9 @@ struct BinOffsets {
   int32_t off[NBINS + 1];
 };
 
-// keep a bin entry (and the chunks of a long row) when its row is active and,
-// with a dirty array, touched by a column change since it was last swept
+// keep a bin entry (and the chunks of a long row) when its row is active, its
+// LP still presolving and, with a dirty array, touched by a column change
+// since it was last swept
 __global__ void k_rebin_flags(Dev d, const BinEnt* bins, int32_t nent, const LongChunk* chunks, int32_t nch,
                               const uint8_t* dirty, int32_t* keep, int32_t* keep_len, int32_t* ckeep) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -249,7 +250,7 @@ __global__ void k_rebin_flags(Dev d, const BinEnt* bins, int32_t nent, const Lon
     int f = 0, l = 0;
     if (k < nent) {
       BinEnt be = bins[k];
-      f = d.row_on[be.row] != 0 && (!dirty || dirty[be.row]);
+      f = d.row_on[be.row] != 0 && (!dirty || dirty[be.row]) && (d.K == 1 || d.lp_ok[d.row_lp[be.row]]);
       l = f ? be.len : 0;
     }
     keep[k] = f;
@@ -259,7 +260,7 @@ __global__ void k_rebin_flags(Dev d, const BinEnt* bins, int32_t nent, const Lon
     int f = 0;
     if (c < nch) {
       int row = chunks[c].row;
-      f = d.row_on[row] != 0 && (!dirty || dirty[row]);
+      f = d.row_on[row] != 0 && (!dirty || dirty[row]) && (d.K == 1 || d.lp_ok[d.row_lp[row]]);
     }
     ckeep[c] = f;
   }
@@ -361,7 +362,7 @@ __global__ void k_round0_count(Dev d) {
   if (t < m) {
     d.cnt[t] = 0;
     double l = d.lhs[t], r = d.rhs[t];
-    if (!is_inf(l) && !is_inf(r) && l > r + tol_of(d.cfg, r)) atomicOr(&d.flags->infeasible, 1);
+    if (!is_inf(l) && !is_inf(r) && l > r + tol_of(d.cfg, r)) flag_infeasible(d, row_lp_of(d, (int)t));
     return;
   }
   if (t >= m + n) return;
@@ -369,7 +370,7 @@ __global__ void k_round0_count(Dev d) {
   double2 b = d.bnd[j];
   int k = 0;
   if (!is_inf(b.x) && !is_inf(b.y)) {
-    if (b.x > b.y + tol_of(d.cfg, b.y)) atomicOr(&d.flags->infeasible, 1);
+    if (b.x > b.y + tol_of(d.cfg, b.y)) flag_infeasible(d, col_lp_of(d, j));
     if (b.y - b.x <= d.cfg.fix_tol * mx1(b.x)) k = 1;
   }
   d.cnt[t] = k;

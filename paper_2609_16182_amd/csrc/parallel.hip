@@ -13,8 +13,10 @@
 
 namespace psl {
 
-__device__ __forceinline__ void hash_terms(const Dev& d, int64_t p, bool v, double a0, unsigned long long& h1,
-                                           unsigned long long& h2, bool& act) {
+// col0: first column of the row's LP (the pattern is hashed in the LP's own
+// column numbering, so a row's key does not depend on its place in a batch)
+__device__ __forceinline__ void hash_terms(const Dev& d, int64_t p, bool v, double a0, int col0,
+                                           unsigned long long& h1, unsigned long long& h2, bool& act) {
   h1 = h2 = 0;
   act = false;
   if (!v) return;
@@ -22,7 +24,7 @@ __device__ __forceinline__ void hash_terms(const Dev& d, int64_t p, bool v, doub
   double a = d.va[p];
   double2 b = d.bnd[j];
   act = b.x != b.y;
-  unsigned long long cj = splitmix((unsigned long long)(uint32_t)j);
+  unsigned long long cj = splitmix((unsigned long long)(uint32_t)(j - col0));
   h1 = cj;
   h2 = splitmix(cj ^ quantize(a / a0));
 }
@@ -31,18 +33,29 @@ __device__ __forceinline__ unsigned long long row_key(int len, unsigned long lon
   return (splitmix((unsigned long long)len + s1) ^ s2) | 1ULL;
 }
 
+__device__ __forceinline__ int lp_col0(const Dev& d, int row) { return d.K > 1 ? d.lp_col0[d.row_lp[row]] : 0; }
+
+// every LP has its own table (a power-of-two slice of the slot array), so key
+// groups never mix rows of different LPs
 __device__ __forceinline__ void par_insert(const Dev& d, const ParScratch& P, int row, unsigned long long key) {
-  unsigned long long mask = (unsigned long long)P.cap - 1;
+  int64_t base = 0, cap = P.cap;
+  if (d.K > 1) {
+    LpTab t = P.lpt[d.row_lp[row]];
+    base = t.base;
+    cap = t.cap;
+  }
+  HashSlot* tab = P.table + base;
+  unsigned long long mask = (unsigned long long)cap - 1;
   unsigned long long h = splitmix(key) & mask;
-  for (int64_t probe = 0; probe < P.cap; ++probe) {
-    unsigned long long old = atomicCAS(&P.table[h].key, 0ULL, key);
+  for (int64_t probe = 0; probe < cap; ++probe) {
+    unsigned long long old = atomicCAS(&tab[h].key, 0ULL, key);
     if (old == 0ULL || old == key) break;
     h = (h + 1) & mask;
   }
   bool eq = d.lhs[row] == d.rhs[row];
-  atomicMin(&P.table[h].leader, (eq ? 0u : 0x80000000u) | (unsigned)row);
-  atomicAdd(&P.table[h].count, 1u);
-  P.slot[row] = (int)h;
+  atomicMin(&tab[h].leader, (eq ? 0u : 0x80000000u) | (unsigned)row);
+  atomicAdd(&tab[h].count, 1u);
+  P.slot[row] = (int)(base + (int64_t)h);
 }
 
 __global__ void k_par_reset(Dev d, ParScratch P) {
@@ -90,9 +103,10 @@ __device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, i
   }
   int gl = threadIdx.x & (G - 1);
   double a0 = on && len > 0 ? d.va[s0] : 1.0;
+  int col0 = on ? lp_col0(d, row) : 0;
   unsigned long long h1, h2;
   bool act;
-  hash_terms(d, s0 + gl, on && gl < len, a0, h1, h2, act);
+  hash_terms(d, s0 + gl, on && gl < len, a0, col0, h1, h2, act);
   h1 = group_sum_u64<G>(h1);
   h2 = group_sum_u64<G>(h2);
   int L = __popcll(__ballot(act) & group_mask<G>());
@@ -106,13 +120,14 @@ __device__ __forceinline__ void hash_wave_row(const Dev& d, const ParScratch& P,
   int len = d.rp[row + 1] - (int)s0;
   if (!d.row_on[row] || len < 2) return;
   double a0 = d.va[s0];
+  int col0 = lp_col0(d, row);
   unsigned long long s1 = 0, s2 = 0;
   int L = 0;
   for (int q0 = 0; q0 < len; q0 += PSL_WAVE) {
     int q = q0 + lane;
     unsigned long long h1, h2;
     bool act;
-    hash_terms(d, s0 + q, q < len, a0, h1, h2, act);
+    hash_terms(d, s0 + q, q < len, a0, col0, h1, h2, act);
     s1 += h1;
     s2 += h2;
     L += __popcll(__ballot(act));
@@ -131,6 +146,7 @@ __device__ __forceinline__ void hash_long_chunk(const Dev& d, const ParScratch& 
   int64_t s0 = d.rp[row];
   int len = d.rp[row + 1] - (int)s0;
   double a0 = d.va[s0];
+  int col0 = lp_col0(d, row);
   unsigned long long s1 = 0, s2 = 0;
   int L = 0;
   int end = min(len, ch.first + ch.npass * PASS_LEN);
@@ -138,7 +154,7 @@ __device__ __forceinline__ void hash_long_chunk(const Dev& d, const ParScratch& 
     int q = q0 + (int)threadIdx.x;
     unsigned long long h1, h2;
     bool act;
-    hash_terms(d, s0 + q, q < end, a0, h1, h2, act);
+    hash_terms(d, s0 + q, q < end, a0, col0, h1, h2, act);
     s1 += h1;
     s2 += h2;
     L += act ? 1 : 0;
@@ -296,11 +312,12 @@ __global__ void k_par_count(Dev d, ParScratch P) {
   if (P.lead[i] >= 0) {
     k = 1;
     d.flags->merged = 1;
+    if (d.K > 1) d.lpf[d.row_lp[i]].merged = 1;
   } else if (P.is_leader[i]) {
     double lo, up;
     bool inf;
     if (leader_sides(d, P, (int)i, lo, up, inf)) k = 1;
-    if (inf) atomicOr(&d.flags->infeasible, 1);
+    if (inf) flag_infeasible(d, row_lp_of(d, (int)i));
   }
   d.cnt[i] = k;
 }
@@ -311,7 +328,7 @@ __global__ void k_par_emit(Dev d, ParScratch P, int64_t base, int round) {
   int i = (int)t;
   Record r;
   r.side = 0;
-  r.round = (uint16_t)round;
+  r.round = (uint16_t)round_of(d, row_lp_of(d, i), round);
   if (P.lead[i] >= 0) {
     int L = P.lead[i];
     double lam, ml, mu;

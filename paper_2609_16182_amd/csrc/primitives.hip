@@ -200,20 +200,30 @@ void radix_pass(const uint32_t* keys_in, const int32_t* vals_in, uint32_t* keys_
 
 #define PW_TILE 2048
 
-// Each block sums the aligned chunk [2048 b, 2048 b + 2048): eight contiguous
-// leaves per thread (tree of 8), a butterfly over the wave (tree of 64 such
-// groups), then the four wave sums as (w0 + w1) + (w2 + w3).
-__global__ void __launch_bounds__(PSL_BLOCK) k_pw_chunks(const double* x, int64_t n, double* out) {
+// Sum of one aligned tile x[0..2048) (elements at or beyond lim read as 0) by
+// the whole block: eight contiguous leaves per thread (tree of 8), a butterfly
+// over the wave (tree of 64 such groups), then the four wave sums as
+// (w0 + w1) + (w2 + w3). Every thread returns the sum.
+__device__ __forceinline__ double tile_sum(const double* x, int64_t lim) {
   __shared__ double ws[PSL_BLOCK / PSL_WAVE];
-  int64_t base = (int64_t)blockIdx.x * PW_TILE + (int64_t)threadIdx.x * 8;
+  int64_t base = (int64_t)threadIdx.x * 8;
   double v[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = base + k < n ? x[base + k] : 0.0;
+  for (int k = 0; k < 8; ++k) v[k] = base + k < lim ? x[base + k] : 0.0;
   double s = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
   s = group_sum<PSL_WAVE>(s);
   if (lane_id() == 0) ws[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+  double t = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+  __syncthreads();
+  return t;
+}
+
+// Each block sums the aligned chunk [2048 b, 2048 b + 2048).
+__global__ void __launch_bounds__(PSL_BLOCK) k_pw_chunks(const double* x, int64_t n, double* out) {
+  int64_t base = (int64_t)blockIdx.x * PW_TILE;
+  double t = tile_sum(x + base, n - base);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 size_t pairwise_ws_doubles(int64_t n) {
@@ -230,6 +240,40 @@ void pairwise_sum(const double* x, int64_t n, double* out, double* ws, hipStream
   }
   hipLaunchKernelGGL(k_pw_chunks, dim3((unsigned)nb), dim3(PSL_BLOCK), 0, s, x, n, ws);
   pairwise_sum(ws, nb, out, ws + nb, s);
+}
+
+// One block per segment of at most 2048 tiles: the tile sums go to LDS, then
+// one more tile tree over them (the same tree as pairwise_sum's second level).
+__global__ void __launch_bounds__(PSL_BLOCK) k_pw_segments(const double* x, const int32_t* seg, const double* off,
+                                                           double* out) {
+  __shared__ double tiles[PW_TILE];
+  int k = blockIdx.x;
+  int64_t s0 = seg[k], n = (int64_t)seg[k + 1] - s0;
+  int64_t nt = (n + PW_TILE - 1) / PW_TILE;
+  if (nt > PW_TILE) return;  // summed on its own
+  for (int64_t t = 0; t < nt; ++t) {
+    double v = tile_sum(x + s0 + t * PW_TILE, n - t * PW_TILE);
+    if (threadIdx.x == 0) tiles[t] = v;
+  }
+  __syncthreads();
+  double sum = nt <= 1 ? (nt == 1 ? tiles[0] : 0.0) : tile_sum(tiles, nt);
+  if (threadIdx.x == 0) out[k] = pos0(off[k] + sum);
+}
+
+__global__ void k_pw_finish(const double* sum, const double* off, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = pos0(off[0] + sum[0]);
+}
+
+void segmented_pairwise_sum(const double* x, const int32_t* seg_dev, const int32_t* seg_host, int K,
+                            const double* off, double* out, double* ws, hipStream_t s) {
+  if (K <= 0) return;
+  hipLaunchKernelGGL(k_pw_segments, dim3((unsigned)K), dim3(PSL_BLOCK), 0, s, x, seg_dev, off, out);
+  for (int k = 0; k < K; ++k) {
+    int64_t n = (int64_t)seg_host[k + 1] - seg_host[k];
+    if ((n + PW_TILE - 1) / PW_TILE <= PW_TILE) continue;
+    pairwise_sum(x + seg_host[k], n, ws, ws + 1, s);
+    hipLaunchKernelGGL(k_pw_finish, dim3(1), dim3(64), 0, s, (const double*)ws, off + k, out + k);
+  }
 }
 
 }  // namespace psl

@@ -85,6 +85,18 @@ struct LongRow {     // per long row
   int32_t row, chunk0, nchunk, npass;
 };
 
+// Batched presolve: K LPs form one block-diagonal LP (the rows and columns of
+// LP k are contiguous, its entries use the shifted column indices). Every LP
+// keeps its own round count and stopping state, so its records and reduced
+// problem are those of presolving it alone.
+struct LpFlags {     // per LP, cleared before every round
+  int32_t infeasible, unbounded, merged, pad;
+};
+
+struct LpOut {       // per LP records of the last round, and row records among them
+  int32_t total, rows;
+};
+
 struct Flags {
   int32_t infeasible, unbounded, error, merged;
   int32_t cand_count, round_total, vlist_count, pad;
@@ -129,8 +141,30 @@ struct Dev {
   LongPart *lpart;
   LongRow *lrow;
   int32_t nlong, nchunks;
+  // batched presolve (K LPs); with K == 1 every row and column is in LP 0
+  // and none of these arrays is read
+  int32_t K;
+  const int32_t *row_lp, *col_lp;     // LP of each row / column
+  const int32_t *lp_row0, *lp_col0;   // [K+1] first row / column of each LP
+  const uint8_t *lp_ok;               // [K] LP still presolving (its rows stay in the bins)
+  const int32_t *lp_round;            // [K] the LP's own number of the current round
+  LpFlags *lpf;                       // [K]
+  LpOut *lpo;                         // [K]
   Cfg cfg;
 };
+
+__device__ __forceinline__ int row_lp_of(const Dev& d, int i) { return d.K > 1 ? d.row_lp[i] : 0; }
+__device__ __forceinline__ int col_lp_of(const Dev& d, int j) { return d.K > 1 ? d.col_lp[j] : 0; }
+// round number written into a record of LP lp
+__device__ __forceinline__ int round_of(const Dev& d, int lp, int round) { return d.K > 1 ? d.lp_round[lp] : round; }
+__device__ __forceinline__ void flag_infeasible(const Dev& d, int lp) {
+  atomicOr(&d.flags->infeasible, 1);
+  if (d.K > 1) atomicOr(&d.lpf[lp].infeasible, 1);
+}
+__device__ __forceinline__ void flag_unbounded(const Dev& d, int lp) {
+  atomicOr(&d.flags->unbounded, 1);
+  if (d.K > 1) atomicOr(&d.lpf[lp].unbounded, 1);
+}
 
 // ---------------------------------------------------------------------------
 // scalar helpers (IEEE double; the library is built with -ffp-contract=off)

@@ -26,4 +26,11 @@ void fill_i32(int32_t* out, int32_t v, int64_t n, hipStream_t s);
 size_t pairwise_ws_doubles(int64_t n);
 void pairwise_sum(const double* x, int64_t n, double* out, double* ws, hipStream_t s);
 
+// out[k] = +0-canonical (off[k] + canonical pairwise sum of x[seg[k]..seg[k+1]))
+// for k < K; the tree of every segment starts at the segment's first element.
+// seg is given on the device and on the host; segments of more than
+// 2048 * 2048 elements are summed by pairwise_sum (ws: pairwise_ws_doubles + 1).
+void segmented_pairwise_sum(const double* x, const int32_t* seg_dev, const int32_t* seg_host, int K,
+                            const double* off, double* out, double* ws, hipStream_t s);
+
 }  // namespace psl

@@ -67,9 +67,13 @@ void launch_round0_emit(const Dev& d, int64_t base, hipStream_t s);
 void launch_init_state(const Dev& d, hipStream_t s);
 
 // parallel.hip
+struct LpTab {        // an LP's slice of the parallel-row table
+  int64_t base, cap;  // first slot, slots (a power of two)
+};
 struct ParScratch {
   HashSlot* table;
-  int64_t cap;        // power of two
+  int64_t cap;        // power of two (all slots when K > 1)
+  const LpTab* lpt;   // [K] per-LP slices (K > 1)
   int32_t* slot;      // [m] slot of a candidate row, -1 otherwise
   int32_t* lead;      // [m] leader of a merged row, -1 otherwise
   long long* side_key;// [2m] merged (lhs, rhs) keys of a leader
@@ -91,6 +95,10 @@ struct Reduced {
   double *val, *cval, *lhs, *rhs, *lb, *ub, *c;
   uint8_t *row_class, *col_class;
 };
+struct LpRed {           // bases of an LP's reduced problem in the batch's arrays
+  int32_t rb, cb;        // first reduced row / column
+  int32_t eb, qb;        // first position in the reduced CSR / transposed copy
+};
 struct CompactScratch {
   int32_t* row_new;       // [m]     kept flags -> new row ids
   int32_t* col_new;       // [n]     kept flags -> new column ids
@@ -103,10 +111,37 @@ struct CompactScratch {
   int32_t* qflag;         // [nnz+1] transposed keep flags -> output positions
   const int32_t* rowid1;  // row of CSR position p at index p + 1
   const uint32_t* colid;  // column of each position of the transposed copy
+  LpRed* lpr;             // [K+1] per-LP bases (lpr[K] = totals)
+  const int32_t* seg;     // [K+1] first column of each LP (K > 1), device
+  const int32_t* seg_host;//        the same on the host
+  const double* lp_off_in;// [K] input objective offsets (K > 1)
 };
 // flags and scans (totals written to c.totals)
 void compact_flags(const Dev& d, const CompactScratch& c, hipStream_t s);
-// offset, gather of both layouts, vectors, maps and classes
+// offset(s), gather of both layouts, vectors, maps and classes; with K > 1 the
+// offsets go to c.offset[0..K)
 void compact_write(const Dev& d, const CompactScratch& c, const Reduced& r, double obj_offset, hipStream_t s);
+
+// batch.hip
+struct LpDesc {        // one LP of a batch, as given (device pointers)
+  const int32_t *rp, *ci;
+  const double *va, *lhs, *rhs, *lb, *ub, *c;
+  int32_t m, n;
+  int64_t nnz;
+};
+// union arrays from K device-resident LPs (d.m, d.n, d.nnz, d.K, d.lp_row0,
+// d.lp_col0 set; z0[k] = first position of LP k); errors go to d.flags
+void batch_gather(const Dev& d, const LpDesc* desc, const int64_t* z0, int32_t* rp, int32_t* ci, double* va,
+                  double* lhs, double* rhs, double* lb, double* ub, double* c, int32_t* row_lp, int32_t* col_lp,
+                  hipStream_t s);
+// row -> LP and column -> LP maps from d.lp_row0 / d.lp_col0
+void batch_maps(const Dev& d, int32_t* row_lp, int32_t* col_lp, hipStream_t s);
+// d.lpo from the last scan of record counts (rows only, or rows and columns)
+void launch_lp_totals(const Dev& d, bool cols, hipStream_t s);
+// stable split of the records by LP, renumbered per LP (K > 1); scratch of
+// count entries each, ws: rec_split_ws_ints(count)
+size_t rec_split_ws_ints(int64_t count);
+void rec_split(const Dev& d, const Record* rec, int64_t count, Record* out, int32_t* rec_off, uint32_t* k0,
+               uint32_t* k1, int32_t* v0, int32_t* v1, int32_t* ws, hipStream_t s);
 
 }  // namespace psl

@@ -376,7 +376,7 @@ __device__ __forceinline__ void sweep_rows(const Dev& d, const CandSink& sk, int
   if (live) {
     code = dec.code;
     if (prop && dec.single && !dec.infeasible && captured) code = RC_SINGLETON;
-    if (dec.infeasible && gl == 0) atomicOr(&d.flags->infeasible, 1);
+    if (dec.infeasible && gl == 0) flag_infeasible(d, row_lp_of(d, row));
   }
   if (vr && gl == 0) d.row_code[row] = code;
   if (live && gl == 0 && (code == RC_EMPTY || code == RC_REDUNDANT)) d.row_out[row] = row_out_of(code, st);
@@ -539,7 +539,7 @@ __device__ __forceinline__ void sweep_long_chunk(const Dev& d, const CandSink& s
     }
   } else if (ch.first == 0 && threadIdx.x == 0) {
     d.row_code[row] = dec.code;
-    if (dec.infeasible) atomicOr(&d.flags->infeasible, 1);
+    if (dec.infeasible) flag_infeasible(d, row_lp_of(d, row));
     if (dec.code == RC_EMPTY || dec.code == RC_REDUNDANT) d.row_out[row] = row_out_of(dec.code, st);
   }
 }
@@ -692,8 +692,8 @@ __global__ void k_count(Dev d) {
   }
   d.col_code[j] = code;
   d.cnt[t] = k;
-  if (code & CC_INFEAS) atomicOr(&d.flags->infeasible, 1);
-  if (code & CC_UNBOUNDED) atomicOr(&d.flags->unbounded, 1);
+  if (code & CC_INFEAS) flag_infeasible(d, col_lp_of(d, j));
+  if (code & CC_UNBOUNDED) flag_unbounded(d, col_lp_of(d, j));
 }
 
 __device__ __forceinline__ double coef_in_row(const Dev& d, int row, int j) {
@@ -731,6 +731,7 @@ __global__ void k_emit(Dev d, int64_t base, int round) {
     uint8_t code = d.row_code[t];
     if (code == RC_KEEP) return;
     int i = (int)t;
+    round = round_of(d, row_lp_of(d, i), round);
     RowOut o = d.row_out[i];
     Record* r = d.rec + base + d.off[t];
     if (code == RC_EMPTY) *r = mkrec(REC_EMPTY_ROW, 0, round, i, -1, -1, o.v0, d.lhs[i], d.rhs[i], 0.0);
@@ -744,6 +745,7 @@ __global__ void k_emit(Dev d, int64_t base, int round) {
   int j = (int)(t - m);
   uint8_t code = d.col_code[j];
   if (code == 0) return;
+  round = round_of(d, col_lp_of(d, j), round);
   double2 b = d.bnd[j];
   double lo = dunkey(d.bkey[2 * (int64_t)j]);
   double up = dunkey(d.bkey[2 * (int64_t)j + 1]);

@@ -94,8 +94,20 @@ def load(path=None):
     lib.psl_presolve_free.restype = None
     lib.psl_last_error.argtypes = [C.c_void_p]
     lib.psl_last_error.restype = C.c_char_p
+    lib.psl_batch_create.argtypes = [C.c_int32, C.c_void_p, C.POINTER(psl_settings), C.POINTER(C.c_void_p)]
+    lib.psl_batch_reload.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+    lib.psl_batch_run.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(psl_stats)]
+    lib.psl_batch_stats.argtypes = [C.c_void_p, C.c_int32, C.POINTER(psl_stats)]
+    lib.psl_batch_reduced_problem.argtypes = [C.c_void_p, C.c_int32, C.POINTER(psl_reduced_view)]
+    lib.psl_batch_records.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_void_p, C.c_int64]
+    lib.psl_batch_postsolve.argtypes = [C.c_void_p, C.c_int32] + [C.c_void_p] * 6
+    lib.psl_batch_free.argtypes = [C.c_void_p]
+    lib.psl_batch_free.restype = None
+    lib.psl_batch_last_error.argtypes = [C.c_void_p]
+    lib.psl_batch_last_error.restype = C.c_char_p
     for f in ("psl_presolve_create", "psl_presolve_reload", "psl_presolve_run", "psl_reduced_problem",
-              "psl_records", "psl_postsolve"):
+              "psl_records", "psl_postsolve", "psl_batch_create", "psl_batch_reload", "psl_batch_run",
+              "psl_batch_stats", "psl_batch_reduced_problem", "psl_batch_records", "psl_batch_postsolve"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -114,6 +126,11 @@ def _hiprt():
 def _check(st, h=None):
     if st != PSL_OK:
         raise PslError(st, load().psl_last_error(h).decode())
+
+
+def _bcheck(st, b=None):
+    if st != PSL_OK:
+        raise PslError(st, load().psl_batch_last_error(b).decode())
 
 
 # ---------------------------------------------------------------------------
@@ -173,6 +190,63 @@ def psl_presolve_free(h):
 
 def psl_last_error(h=None):
     return load().psl_last_error(h).decode()
+
+
+def psl_batch_create(lps, settings: psl_settings):
+    arr = (psl_lp * len(lps))(*lps)
+    b = C.c_void_p()
+    _bcheck(load().psl_batch_create(len(lps), C.cast(arr, C.c_void_p), C.byref(settings), C.byref(b)))
+    return b
+
+
+def psl_batch_reload(b, lps):
+    arr = (psl_lp * len(lps))(*lps)
+    _bcheck(load().psl_batch_reload(b, len(lps), C.cast(arr, C.c_void_p)), b)
+
+
+def psl_batch_run(b, k):
+    res = (C.c_int * k)()
+    st = psl_stats()
+    _bcheck(load().psl_batch_run(b, C.cast(res, C.c_void_p), C.byref(st)), b)
+    return list(res), st
+
+
+def psl_batch_stats(b, idx):
+    st = psl_stats()
+    _bcheck(load().psl_batch_stats(b, idx, C.byref(st)), b)
+    return st
+
+
+def psl_batch_reduced_problem(b, idx):
+    v = psl_reduced_view()
+    _bcheck(load().psl_batch_reduced_problem(b, idx, C.byref(v)), b)
+    return v
+
+
+def psl_batch_records(b, idx):
+    cnt = C.c_int64()
+    _bcheck(load().psl_batch_records(b, idx, C.byref(cnt), None, 0), b)
+    out = np.zeros(cnt.value, RECORD_DTYPE)
+    if cnt.value:
+        _bcheck(load().psl_batch_records(b, idx, C.byref(cnt), out.ctypes.data, cnt.value), b)
+    return out
+
+
+def psl_batch_postsolve(b, idx, x_red, n):
+    x_red = np.ascontiguousarray(x_red, np.float64)
+    x = np.zeros(n)
+    _bcheck(load().psl_batch_postsolve(b, idx, x_red.ctypes.data if x_red.size else None, None, None,
+                                       x.ctypes.data if n else None, None, None), b)
+    return x
+
+
+def psl_batch_free(b):
+    if b:
+        load().psl_batch_free(b)
+
+
+def psl_batch_last_error(b=None):
+    return load().psl_batch_last_error(b).decode()
 
 
 # ---------------------------------------------------------------------------
@@ -242,6 +316,20 @@ def _d2h(ptr, count, dtype):
     return out
 
 
+def reduced_to_host(v):
+    """Copy of a psl_reduced_view's arrays on the host (numpy)."""
+    m, n, nnz = v.m, v.n, v.nnz
+    return dict(
+        m=m, n=n, nnz=nnz, obj_offset=v.obj_offset,
+        row_ptr=_d2h(v.row_ptr, m + 1, np.int32), col_idx=_d2h(v.col_idx, nnz, np.int32),
+        val=_d2h(v.val, nnz, np.float64), col_ptr=_d2h(v.col_ptr, n + 1, np.int32),
+        row_idx=_d2h(v.row_idx, nnz, np.int32), cval=_d2h(v.cval, nnz, np.float64),
+        lhs=_d2h(v.lhs, m, np.float64), rhs=_d2h(v.rhs, m, np.float64),
+        lb=_d2h(v.lb, n, np.float64), ub=_d2h(v.ub, n, np.float64), c=_d2h(v.c, n, np.float64),
+        row_map=_d2h(v.row_map, m, np.int32), col_map=_d2h(v.col_map, n, np.int32),
+        row_class=_d2h(v.row_class, m, np.uint8), col_class=_d2h(v.col_class, n, np.uint8))
+
+
 class Presolver:
     """One presolve handle: create (copies the LP to the device), run, read."""
 
@@ -271,17 +359,7 @@ class Presolver:
 
     def reduced(self):
         """Copy of the reduced problem on the host (numpy)."""
-        v = self.view()
-        m, n, nnz = v.m, v.n, v.nnz
-        return dict(
-            m=m, n=n, nnz=nnz, obj_offset=v.obj_offset,
-            row_ptr=_d2h(v.row_ptr, m + 1, np.int32), col_idx=_d2h(v.col_idx, nnz, np.int32),
-            val=_d2h(v.val, nnz, np.float64), col_ptr=_d2h(v.col_ptr, n + 1, np.int32),
-            row_idx=_d2h(v.row_idx, nnz, np.int32), cval=_d2h(v.cval, nnz, np.float64),
-            lhs=_d2h(v.lhs, m, np.float64), rhs=_d2h(v.rhs, m, np.float64),
-            lb=_d2h(v.lb, n, np.float64), ub=_d2h(v.ub, n, np.float64), c=_d2h(v.c, n, np.float64),
-            row_map=_d2h(v.row_map, m, np.int32), col_map=_d2h(v.col_map, n, np.int32),
-            row_class=_d2h(v.row_class, m, np.uint8), col_class=_d2h(v.col_class, n, np.uint8))
+        return reduced_to_host(self.view())
 
     def postsolve(self, x_red):
         return psl_postsolve(self.h, x_red, self.n)
@@ -309,3 +387,50 @@ def presolve(lp, **settings):
     except Exception:
         p.close()
         raise
+
+
+class Batch:
+    """A batch handle: K LPs presolved together, each with its own result."""
+
+    def __init__(self, lps, stream=None, **settings):
+        keep = []
+        self.ns = [int(lp["n"]) for lp in lps]
+        self.settings = make_settings(stream=stream, **settings)
+        self.h = psl_batch_create([make_lp(lp, keep) for lp in lps], self.settings)
+
+    def reload(self, lps):
+        keep = []
+        self.ns = [int(lp["n"]) for lp in lps]
+        psl_batch_reload(self.h, [make_lp(lp, keep) for lp in lps])
+
+    def run(self):
+        res, st = psl_batch_run(self.h, len(self.ns))
+        self.results = [RESULT_NAMES[r] for r in res]
+        self.stats = st.as_dict()
+        return self.results
+
+    def lp_stats(self, idx):
+        return psl_batch_stats(self.h, idx).as_dict()
+
+    def records(self, idx):
+        return psl_batch_records(self.h, idx)
+
+    def view(self, idx):
+        return psl_batch_reduced_problem(self.h, idx)
+
+    def reduced(self, idx):
+        return reduced_to_host(self.view(idx))
+
+    def postsolve(self, idx, x_red):
+        return psl_batch_postsolve(self.h, idx, x_red, self.ns[idx])
+
+    def close(self):
+        if getattr(self, "h", None):
+            psl_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

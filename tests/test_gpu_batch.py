@@ -1,0 +1,177 @@
+"""Batched presolve: every LP of a batch gets exactly the result it gets alone.
+
+Each LP of a batch is compared bit for bit with the CPU oracle run on that
+LP alone (result, record stream, reduced problem, offset) and with the
+single-LP GPU path (statistics, postsolve). Batches mix sizes, outcomes
+(infeasible, unbounded, unchanged), empty LPs and LPs that need several
+outer cycles, so LPs stop at different rounds while others go on.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_16182_amd import lpgen
+from tests.lp_utils import load_golden, make
+from tests.parity_util import assert_same
+
+pytestmark = pytest.mark.gpu
+
+psl = pytest.importorskip("paper_2609_16182_amd.psl")
+
+INF = np.inf
+
+
+def batch_outputs(b, k):
+    out = []
+    for idx in range(k):
+        name = b.results[idx]
+        got = {"result_name": name, "records": b.records(idx)}
+        got["reduced"] = b.reduced(idx) if name in ("REDUCED", "UNCHANGED") else None
+        out.append(got)
+    return out
+
+
+def check_batch(lps, label, **settings):
+    b = psl.Batch(lps, **settings)
+    try:
+        b.run()
+        outs = batch_outputs(b, len(lps))
+        for idx, lp in enumerate(lps):
+            ref = O.presolve(lp, **{k: v for k, v in settings.items() if k in O.DEFAULTS})
+            assert_same(outs[idx], ref, f"{label} LP {idx}")
+            st = b.lp_stats(idx)
+            assert st["records"] == len(ref.records)
+            assert st["rounds"] == ref.rounds, (label, idx, st["rounds"], ref.rounds)
+        return b, outs
+    except Exception:
+        b.close()
+        raise
+
+
+def infeasible_lp():
+    # x0 + x1 >= 5 with both in [0, 1]
+    return make(1, 2, [[(0, 1.0), (1, 1.0)]], [5.0], [INF], [0, 0], [1, 1], [1.0, 1.0])
+
+
+def unbounded_lp():
+    # column 1 appears in no row, costs -1 and has no upper bound
+    return make(1, 2, [[(0, 1.0)]], [0.0], [4.0], [0, 0], [10, INF], [1.0, -1.0])
+
+
+def empty_rows_lp():
+    return make(3, 3, [[], [(1, 2.0)], []], [-1.0, 0.0, 0.0], [1.0, 4.0, 0.0], [0, 0, -INF], [5, 5, INF],
+                [1.0, 1.0, 0.0])
+
+
+def mixed_lps():
+    lps = [lpgen.tiny(s, finite_bounds=s % 3 == 0) for s in range(16)]
+    lps += [lpgen.batch_member(i, m=100 + 37 * i) for i in range(8)]
+    lps += [lpgen.single_small(seed=5), infeasible_lp(), unbounded_lp(), empty_rows_lp()]
+    for name in ("worked_example_propagation.json", "parallel_rows_merge.json"):
+        lps.append(load_golden(name)[1])
+    return lps
+
+
+def test_batch_mixed_matches_oracle():
+    b, _ = check_batch(mixed_lps(), "mixed")
+    names = set(b.results)
+    assert {"REDUCED", "INFEASIBLE", "UNBOUNDED_OR_INFEASIBLE"} <= names
+    b.close()
+
+
+@pytest.mark.parametrize("settings", [
+    dict(enable_parallel_rows=0), dict(max_rounds=1), dict(max_outer=1), dict(max_rounds=2, max_outer=3),
+    dict(min_improve=0.0), dict(bin_thresholds=(16, 2048)),
+])
+def test_batch_settings(settings):
+    lps = [lpgen.tiny(s) for s in range(20, 30)] + [lpgen.batch_member(i, m=150 + 50 * i) for i in range(6)]
+    b, _ = check_batch(lps, f"settings {settings}", **settings)
+    b.close()
+
+
+def test_batch_of_one_and_empty_members():
+    b, _ = check_batch([lpgen.single_small(seed=2)], "k=1")
+    b.close()
+    empty = make(0, 3, [], [], [], [0, -1, 0], [1, 2, 3], [1.0, -1.0, 0.0])
+    nocols = make(2, 0, [[], []], [-1.0, 0.0], [1.0, 0.0], [], [], [])
+    nothing = make(0, 0, [], [], [], [], [], [])
+    b, _ = check_batch([empty, lpgen.tiny(3), nocols, nothing, lpgen.tiny(4), empty, nothing], "empty members")
+    b.close()
+
+
+def test_batch_cfg_members_scaled():
+    """Members drawn exactly as in the 4096-LP workload (m log-uniform in
+    [100, 20000]), 24 of them."""
+    lps = [lpgen.batch_member(i) for i in range(24)]
+    b, _ = check_batch(lps, "batch members")
+    b.close()
+
+
+def test_batch_equals_single_gpu_stats_and_postsolve():
+    lps = [lpgen.batch_member(i, m=300 + 111 * i) for i in range(5)] + [load_golden("parallel_rows_merge.json")[1]]
+    b = psl.Batch(lps)
+    b.run()
+    for idx, lp in enumerate(lps):
+        got, p = psl.presolve(lp)
+        st_b, st_s = b.lp_stats(idx), p.stats
+        for key in ("rounds", "outer_cycles", "records", "nnz_in", "nnz_out", "m_out", "n_out"):
+            assert st_b[key] == st_s[key], (idx, key, st_b[key], st_s[key])
+        red = b.reduced(idx)
+        x_red = np.random.default_rng(idx).uniform(-1, 1, red["n"])
+        assert np.array_equal(b.postsolve(idx, x_red), p.postsolve(x_red))
+        p.close()
+    b.close()
+
+
+def test_batch_device_input_and_reload():
+    torch = pytest.importorskip("torch")
+    lps = [lpgen.batch_member(i, m=200 + 50 * i) for i in range(6)] + [lpgen.tiny(7), infeasible_lp()]
+    keys = ("row_ptr", "col_idx", "val", "lhs", "rhs", "lb", "ub", "c")
+
+    def dev(lp):
+        d = {k: torch.from_numpy(np.ascontiguousarray(lp[k])).cuda() for k in keys}
+        d.update(m=lp["m"], n=lp["n"], nnz=lpgen.nnz(lp))
+        return d
+
+    b = psl.Batch([dev(lp) for lp in lps])
+    b.run()
+    outs = batch_outputs(b, len(lps))
+    for idx, lp in enumerate(lps):
+        assert_same(outs[idx], O.presolve(lp), f"device LP {idx}")
+    # reload with different, smaller LPs (host and device) and run again
+    lps2 = [lpgen.tiny(s) for s in range(40, 45)] + [lpgen.batch_member(9, m=400)]
+    for form in ("host", "device"):
+        b.reload(lps2 if form == "host" else [dev(lp) for lp in lps2])
+        b.run()
+        outs = batch_outputs(b, len(lps2))
+        for idx, lp in enumerate(lps2):
+            assert_same(outs[idx], O.presolve(lp), f"reload {form} LP {idx}")
+    with pytest.raises(psl.PslError) as e:
+        b.reload(lps + lps)
+    assert e.value.status == psl.PSL_ERR_CAPACITY
+    b.close()
+
+
+def test_batch_invalid_member_names_lp():
+    good = lpgen.tiny(1)
+    bad = dict(lpgen.tiny(2))
+    bad["col_idx"] = np.array(bad["col_idx"], np.int32).copy()
+    if len(bad["col_idx"]):
+        bad["col_idx"][0] = bad["n"] + 3
+    else:
+        pytest.skip("tiny LP without entries")
+    with pytest.raises(psl.PslError) as e:
+        psl.Batch([good, bad])
+    assert e.value.status == psl.PSL_ERR_INVALID
+    assert "LP 1" in str(e.value)
+
+
+def test_batch_deterministic():
+    lps = [lpgen.batch_member(i, m=500) for i in range(4)]
+    b = psl.Batch(lps)
+    b.run()
+    first = [b.records(i).tobytes() for i in range(4)]
+    b.reload(lps)
+    b.run()
+    assert [b.records(i).tobytes() for i in range(4)] == first
+    b.close()
