@@ -37,7 +37,122 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the full power-law LP)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-lps", type=int, default=4096, help="LPs of the batched workload (0 = skip it)")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--only-batch", action="store_true", help="run the batched workload only")
+    ap.add_argument("--batch-no-seq", action="store_true", help="skip the sequential single-LP baseline")
     return ap.parse_args()
+
+
+def _member(i):
+    from paper_2609_16182_amd import lpgen
+    return lpgen.batch_member(i)
+
+
+def _oracle_nnz(i):
+    from oracle import oracle as O
+    from paper_2609_16182_amd import lpgen
+    lp = lpgen.batch_member(i)
+    O.presolve(lp)
+    return lpgen.nnz(lp)
+
+
+def batch_leg(args, torch, psl):
+    """4096 LPs (m log-uniform in [100, 20000], n = 1.5m, U{4..10} nnz/row),
+    device-resident. A batched step = psl_batch_reload + psl_batch_run of all
+    of them; the sequential baseline = psl_presolve_reload + psl_presolve_run
+    of each LP on its own handle, one after the other on the same stream."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    K = args.batch_lps
+    t0 = time.time()
+    workers = min(16, os.cpu_count() or 1)
+    with ProcessPoolExecutor(workers) as ex:
+        lps = list(ex.map(_member, range(K), chunksize=64))
+    keys = ("row_ptr", "col_idx", "val", "lhs", "rhs", "lb", "ub", "c")
+    dev = []
+    for lp in lps:
+        d = {k: torch.from_numpy(np.ascontiguousarray(lp[k])).cuda() for k in keys}
+        d.update(m=lp["m"], n=lp["n"], nnz=int(lp["row_ptr"][-1]))
+        dev.append(d)
+    total_nnz = sum(d["nnz"] for d in dev)
+    print(f"[bench] batch of {K} LPs, {total_nnz} nnz, generated in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream().cuda_stream
+    lset = psl.LpSet(dev)
+    b = psl.Batch(lset, stream=stream)
+    b.run()
+    b.reload(lset)
+    b.run()
+    torch.cuda.synchronize()
+    ms = []
+    stats = None
+    for _ in range(args.batch_steps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        b.reload(lset)
+        b.run()
+        ms.append((time.perf_counter() - ts) * 1e3)
+        stats = b.stats
+    torch.cuda.synchronize()
+    batch_ms = float(np.median(ms))
+    bres = list(b.results)
+    brec = [b.lp_stats(i)["records"] for i in range(K)]
+    bout = [b.lp_stats(i)["nnz_out"] for i in range(K)]
+    print(f"[bench] batched step {batch_ms:.1f} ms", file=sys.stderr, flush=True)
+
+    if args.batch_no_seq:
+        b.close()
+        return {"metric": "batched LPs/s", "value": round(K / (batch_ms * 1e-3), 1), "ms_per_batch": batch_ms,
+                "device_ms": {k: round(stats[k], 3) for k in ("ms_ingest", "ms_sweep", "ms_long", "ms_decide",
+                                                             "ms_parallel", "ms_compact", "ms_total")},
+                "rounds": stats["rounds"]}
+    # sequential single-LP runs on the same stream
+    t0 = time.time()
+    hs = [psl.Presolver(d, stream=stream) for d in dev]
+    print(f"[bench] {K} single-LP handles created in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    for p in hs[:64]:
+        p.run()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for p, d in zip(hs, dev):
+        p.reload(d)
+        p.run()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - ts) * 1e3
+    same = all(p.result_name == r and p.stats["records"] == rc and p.stats["nnz_out"] == no
+               for p, r, rc, no in zip(hs, bres, brec, bout))
+    sample = list(range(0, K, max(1, K // 16)))
+    same_bytes = all(hs[i].records().tobytes() == b.records(i).tobytes() for i in sample)
+    for p in hs:
+        p.close()
+    b.close()
+    print(f"[bench] sequential {seq_ms:.1f} ms, equal outputs: {same and same_bytes}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_s = min(K, 256)
+        ts = time.perf_counter()
+        with ProcessPoolExecutor(workers) as ex:
+            nnz_s = sum(ex.map(_oracle_nnz, range(n_s), chunksize=8))
+        dt = time.perf_counter() - ts
+        cpu = {"value": round(n_s / dt, 1), "unit": "LPs/s", "cores": workers, "kind": "oracle",
+               "sample": f"the first {n_s} LPs of the batch ({nnz_s} nnz, generation included) on a pool of "
+                         f"{workers} processes"}
+    return {
+        "metric": "batched LPs/s", "lps": K, "nnz": total_nnz,
+        "value": round(K / (batch_ms * 1e-3), 1), "unit": "LPs/s",
+        "ms_per_batch": round(batch_ms, 3), "nnz_per_s": round(total_nnz / (batch_ms * 1e-3), 1),
+        "sequential": {"value": round(K / (seq_ms * 1e-3), 1), "unit": "LPs/s", "ms_total": round(seq_ms, 1)},
+        "speedup_vs_sequential": round(seq_ms / batch_ms, 2),
+        "equal_outputs": bool(same and same_bytes),
+        "device_ms": {k: round(stats[k], 3) for k in ("ms_ingest", "ms_sweep", "ms_long", "ms_decide",
+                                                     "ms_parallel", "ms_compact", "ms_total")},
+        "rounds": stats["rounds"], "sweep_launches": stats["sweep_launches"],
+        "config": {"workload": "4096 LPs, m log-uniform [100, 20000], n = 1.5m, U{4..10} nnz/row, "
+                               "small-LP planting ratios", "steps": args.batch_steps},
+        "cpu_baseline": cpu,
+    }
 
 
 def measured_traffic():
@@ -68,6 +183,9 @@ def main():
     from paper_2609_16182_amd import lpgen, psl
 
     torch.cuda.set_device(0)
+    if args.only_batch:
+        print(json.dumps(batch_leg(args, torch, psl)), flush=True)
+        return
     t0 = time.time()
     lp = lpgen.power_law(seed=1, scale=args.scale)
     nnz = lpgen.nnz(lp)
@@ -129,6 +247,8 @@ def main():
         if ref.records.shape[0] != stats["records"]:
             print("[bench] WARNING: record counts differ from the oracle", file=sys.stderr)
 
+    batch = batch_leg(args, torch, psl) if args.batch_lps > 0 else None
+
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "nnz/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -147,6 +267,7 @@ def main():
                    "ms_parallel": round(stats["ms_parallel"], 3), "ms_compact": round(stats["ms_compact"], 3),
                    "step_ms_p50": round(float(np.median(step_ms)), 3),
                    "first_run_ms": round(first["ms_total"], 3)},
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 

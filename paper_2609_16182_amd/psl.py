@@ -192,16 +192,23 @@ def psl_last_error(h=None):
     return load().psl_last_error(h).decode()
 
 
+def lp_array(lps):
+    """ctypes array of psl_lp structs (reusable across reloads)."""
+    if isinstance(lps, C.Array):
+        return lps
+    return (psl_lp * len(lps))(*lps)
+
+
 def psl_batch_create(lps, settings: psl_settings):
-    arr = (psl_lp * len(lps))(*lps)
+    arr = lp_array(lps)
     b = C.c_void_p()
-    _bcheck(load().psl_batch_create(len(lps), C.cast(arr, C.c_void_p), C.byref(settings), C.byref(b)))
+    _bcheck(load().psl_batch_create(len(arr), C.cast(arr, C.c_void_p), C.byref(settings), C.byref(b)))
     return b
 
 
 def psl_batch_reload(b, lps):
-    arr = (psl_lp * len(lps))(*lps)
-    _bcheck(load().psl_batch_reload(b, len(lps), C.cast(arr, C.c_void_p)), b)
+    arr = lp_array(lps)
+    _bcheck(load().psl_batch_reload(b, len(arr), C.cast(arr, C.c_void_p)), b)
 
 
 def psl_batch_run(b, k):
@@ -389,19 +396,32 @@ def presolve(lp, **settings):
         raise
 
 
+class LpSet:
+    """Prepared psl_lp descriptors of several LPs (arrays kept alive), for
+    repeated batch reloads without rebuilding them."""
+
+    def __init__(self, lps):
+        self._keep = []
+        self.ns = [int(lp["n"]) for lp in lps]
+        self.arr = lp_array([make_lp(lp, self._keep) for lp in lps])
+
+    def __len__(self):
+        return len(self.ns)
+
+
 class Batch:
     """A batch handle: K LPs presolved together, each with its own result."""
 
     def __init__(self, lps, stream=None, **settings):
-        keep = []
-        self.ns = [int(lp["n"]) for lp in lps]
+        lset = lps if isinstance(lps, LpSet) else LpSet(lps)
+        self.ns = list(lset.ns)
         self.settings = make_settings(stream=stream, **settings)
-        self.h = psl_batch_create([make_lp(lp, keep) for lp in lps], self.settings)
+        self.h = psl_batch_create(lset.arr, self.settings)
 
     def reload(self, lps):
-        keep = []
-        self.ns = [int(lp["n"]) for lp in lps]
-        psl_batch_reload(self.h, [make_lp(lp, keep) for lp in lps])
+        lset = lps if isinstance(lps, LpSet) else LpSet(lps)
+        self.ns = list(lset.ns)
+        psl_batch_reload(self.h, lset.arr)
 
     def run(self):
         res, st = psl_batch_run(self.h, len(self.ns))
