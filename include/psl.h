@@ -245,6 +245,101 @@ void psl_batch_free(psl_batch *b);
  * the thread when b is NULL). Never NULL. */
 const char *psl_batch_last_error(const psl_batch *b);
 
+/* ---- Serving ---------------------------------------------------------------
+ * A request loop for a stream of LPs (continuous batching). Submitted LPs wait
+ * in a FIFO queue; a free batch slot takes every waiting LP from the head of
+ * the queue that fits its capacity and whose reduced problem can be reserved
+ * in the device-memory budget, and presolves them as one batch. Several slots
+ * run at once, each with its own stream, host thread and device arena, so LPs
+ * that arrive while others are on the device start as soon as a slot and
+ * memory are free and their work overlaps on the device. Reduced problems
+ * stay on the device until released. Each request's outcome, records and
+ * reduced problem are exactly those psl_presolve_run gives for its LP alone.
+ * The server's functions may be called from any thread. */
+typedef struct psl_server psl_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;  /* device memory for the slot arenas and the
+                                 resident reduced problems                   */
+    int32_t slots;            /* batches in flight at once (>= 1)            */
+    int32_t threaded;         /* 1: each slot has a worker thread; 0: no
+                                 threads, psl_server_step runs one batch     */
+    int32_t max_batch_lps;    /* LPs per batch                               */
+    int32_t max_batch_rows, max_batch_cols;
+    int64_t max_batch_nnz;    /* also the largest LP that can be served      */
+} psl_server_config;
+
+/* Defaults: 64 GiB, 2 slots, threaded, 1024 LPs, 2.6e6 rows, 3.9e6 columns,
+ * 3e7 nonzeros per batch. */
+void psl_server_config_default(psl_server_config *c);
+
+/* Create the slots (their arenas and streams) and the result heap (the rest
+ * of the budget). settings.stream is ignored. PSL_ERR_CAPACITY if the arenas
+ * do not fit the budget. */
+psl_status psl_server_create(const psl_server_config *c, const psl_settings *s, psl_server **out);
+
+/* Queue an LP; *ticket identifies the request. The LP's arrays (host or
+ * device) are read when its batch starts: they must stay valid and unchanged
+ * until the ticket is done. PSL_ERR_CAPACITY if the LP exceeds a batch or the
+ * result heap; shape errors as at create (PSL_ERR_INVALID). */
+psl_status psl_server_submit(psl_server *sv, const psl_lp *lp, uint64_t *ticket);
+
+/* Without worker threads (threaded = 0): admit waiting LPs into a batch on
+ * slot 0 and presolve it before returning. *n_run = LPs presolved (0 when the
+ * queue was empty or the head does not fit yet). PSL_ERR_STATE if threaded. */
+psl_status psl_server_step(psl_server *sv, int32_t *n_run);
+
+/* Copy up to cap tickets completed since the last poll into tickets[], in
+ * completion order; *n_done = how many. */
+psl_status psl_server_poll(psl_server *sv, uint64_t *tickets, int32_t cap, int32_t *n_done);
+
+/* Block until the ticket is done, or until timeout_ms (< 0: no limit) has
+ * passed (then PSL_ERR_STATE). */
+psl_status psl_server_wait(psl_server *sv, uint64_t ticket, double timeout_ms);
+
+typedef struct {
+    psl_status status;        /* PSL_OK, or why this request failed          */
+    psl_result result;
+    double queue_ms;          /* submit -> its batch started                 */
+    double latency_ms;        /* submit -> reduced problem ready on device   */
+    int32_t batch_lps;        /* LPs in its batch                            */
+    int32_t slot;
+    psl_stats stats;          /* as psl_batch_stats for this LP              */
+} psl_ticket_info;
+
+/* State of a done ticket (PSL_ERR_STATE while it is queued or running). */
+psl_status psl_server_info(psl_server *sv, uint64_t ticket, psl_ticket_info *out);
+
+/* The ticket's reduced problem, resident on the device until released. */
+psl_status psl_server_reduced_problem(psl_server *sv, uint64_t ticket, psl_reduced_view *out);
+
+/* The ticket's postsolve records (host copy; LP-local indices). */
+psl_status psl_server_records(psl_server *sv, uint64_t ticket, int64_t *count, psl_record *out, int64_t cap);
+
+/* As psl_postsolve, for the ticket's LP. */
+psl_status psl_server_postsolve(psl_server *sv, uint64_t ticket, const double *x_red, const double *y_red,
+                                const double *z_red, double *x, double *y, double *z);
+
+/* Free the ticket's device memory and state. */
+psl_status psl_server_release(psl_server *sv, uint64_t ticket);
+
+/* Block until the queue is empty and no batch runs. */
+psl_status psl_server_drain(psl_server *sv);
+
+/* Device memory of the server: the slot arenas, the result heap's size, the
+ * bytes reserved in it now and at most so far. A request reserves the size
+ * of its LP's arrays (an upper bound of its reduced problem) at admission;
+ * the reservation shrinks to the reduced problem when it is ready. */
+psl_status psl_server_memory(psl_server *sv, size_t *arena_bytes, size_t *heap_bytes, size_t *heap_used,
+                             size_t *heap_peak);
+
+/* Stops the workers (waiting for running batches) and frees everything. */
+void psl_server_free(psl_server *sv);
+
+/* Message of the last failure on sv (or of the last failed server create of
+ * the thread when sv is NULL). Never NULL. */
+const char *psl_server_last_error(const psl_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-result", "-Wl,--no-undefined",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result", "-pthread", "-Wl,--no-undefined",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 

@@ -21,9 +21,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/psl.h"
-#include "psl_kern.h"
-#include "sweep.h"
+#include "engine.h"
 
 using namespace psl;
 
@@ -36,114 +34,6 @@ struct Timer {
 };
 
 }  // namespace
-
-struct View {
-  BinEnt* bins = nullptr;
-  LongChunk* chunks = nullptr;
-  int32_t off[NBINS + 1] = {0};
-  int32_t nchunks = 0;
-  int64_t rows = 0, nnz = 0;
-};
-
-// host state of one LP of a batch
-enum : uint8_t { LP_PROP = 0, LP_WAIT = 1, LP_DONE = 2 };
-struct LpState {
-  uint8_t phase = LP_PROP;
-  bool infeasible = false, unbounded = false;
-  int32_t rounds = 0, cycles = 0;
-};
-
-struct psl_presolver {
-  Dev d{};
-  psl_settings s{};
-  hipStream_t stream = nullptr;
-  int32_t m = 0, n = 0;
-  int64_t nnz = 0;
-  // arena capacity (the create-time sizes; a batch reload may use less)
-  int32_t cap_m = 0, cap_n = 0, cap_K = 1;
-  int64_t cap_nnz = 0;
-
-  // batch (K > 1): device maps and per-LP arrays, pinned host mirrors
-  int32_t K = 1;
-  int32_t *row_lp = nullptr, *col_lp = nullptr, *lp_row0 = nullptr, *lp_col0 = nullptr, *lp_round = nullptr;
-  uint8_t* lp_ok = nullptr;
-  LpFlags* lpf = nullptr;
-  LpOut* lpo = nullptr;
-  LpTab* lpt = nullptr;
-  LpRed* lpr = nullptr;
-  int64_t* lp_z0 = nullptr;
-  LpDesc* descs = nullptr;
-  double *lp_off_in = nullptr, *lp_off = nullptr;
-  int32_t *h_row0 = nullptr, *h_col0 = nullptr, *h_round = nullptr;
-  int64_t* h_z0 = nullptr;
-  uint8_t* h_ok = nullptr;
-  LpFlags* h_lpf = nullptr;
-  LpOut* h_lpo = nullptr;
-  LpTab* h_lpt = nullptr;
-  LpRed* h_lpr = nullptr;
-  LpDesc* h_desc = nullptr;
-  double *h_off_in = nullptr, *h_off = nullptr;
-  std::vector<LpState> lst;
-  std::vector<psl_result> lp_result;
-  BinEnt* bins_0 = nullptr;  // the ingest bins of all rows
-  LongChunk* chunks_0 = nullptr;
-  View all;
-  // records split by LP
-  Record* rec_lp = nullptr;
-  int64_t split_cap = 0;
-  uint32_t *sk0 = nullptr, *sk1 = nullptr;
-  int32_t *sv0 = nullptr, *sv1 = nullptr, *sws = nullptr, *rec_off = nullptr;
-  std::vector<int32_t> h_rec_off;
-  std::vector<std::vector<psl_record>> lp_host_rec;
-  std::vector<uint8_t> lp_rec_valid;
-  std::vector<void*> allocs, hallocs;
-  std::string err = "no error";
-  int64_t par_slots = 0;
-
-  // staging and persistent scratch
-  double *lb_in = nullptr, *ub_in = nullptr, *c_mut = nullptr;
-  IngestScratch isc{};
-  int32_t* ws = nullptr;
-  const uint32_t* colid = nullptr;
-  int32_t* bin_counts_dev = nullptr;
-  int32_t bin_counts[NBINS] = {0};
-  int32_t thresholds[2] = {512, PASS_LEN};  // longest wavefront row, chunk positions
-  SweepGrid grid{};
-  int64_t chunk_cap = 0, long_cap = 0, cand_cap = 0;
-  int32_t* cand_cnt = nullptr;
-  // bin views: the master lists hold the active rows (filtered after
-  // removals); a selection holds the active rows touched by a column change
-  // since they were last swept
-  BinEnt *bins_a = nullptr, *bins_b = nullptr, *bins_s = nullptr;
-  LongChunk *chunks_a = nullptr, *chunks_b = nullptr, *chunks_s = nullptr;
-  int32_t* rebin_dev = nullptr;  // [NBINS+1] new offsets, then 3 totals
-  View master, cur;
-
-  // records
-  Record* rec = nullptr;
-  int64_t rec_cap = 0, rec_count = 0;
-  std::vector<psl_record> host_rec;
-  bool host_rec_valid = false;
-
-  ParScratch par{};
-  CompactScratch cmp{};
-  Reduced red{};
-  int32_t red_m = 0, red_n = 0;
-  int64_t red_nnz = 0;
-  double red_off = 0.0;
-  double obj_offset = 0.0;
-
-  Flags* hflags = nullptr;  // pinned
-  int32_t* htot = nullptr;  // pinned [4] + offset
-  double* hoff = nullptr;
-
-  int state = 0;  // 0 loaded, 1 ran
-  int sweep_mode = MODE_ROUND;  // PSL_SWEEP_SPLIT=1: three launches by register class
-  psl_result result = PSL_RES_UNCHANGED;
-  psl_stats stats{};
-  double ms_ingest = 0.0;
-  hipEvent_t ev[8] = {nullptr};
-};
 
 #define HIPCHK(p, call)                                                              \
   do {                                                                               \
@@ -172,6 +62,7 @@ static psl_status dalloc(psl_presolver* p, T** out, size_t count) {
     return PSL_ERR_OOM;
   }
   p->allocs.push_back(ptr);
+  p->arena_bytes += bytes;
   *out = (T*)ptr;
   return PSL_OK;
 }
@@ -200,7 +91,7 @@ extern "C" void psl_settings_default(psl_settings* s) {
   s->stream = nullptr;
 }
 
-static std::string check_settings(const psl_settings* s) {
+std::string psl::check_settings(const psl_settings* s) {
   if (s->max_rounds < 1 || s->max_outer < 1 || (int64_t)s->max_outer * (s->max_rounds + 1) + 1 > 65535)
     return "invalid round limits";
   if (!(s->feas_tol >= 0) || !(s->fix_tol >= 0) || !(s->min_improve >= 0) || !(s->par_tol >= 0) ||
@@ -216,7 +107,7 @@ static std::string check_settings(const psl_settings* s) {
   return "";
 }
 
-static std::string check_lp_shape(const psl_lp* lp) {
+std::string psl::check_lp_shape(const psl_lp* lp) {
   if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return "negative size";
   if (lp->nnz >= ((int64_t)1 << 30)) return "nnz must be below 2^30";
   if (lp->m == 0 && lp->nnz != 0) return "entries without rows";
@@ -539,8 +430,11 @@ static std::string error_what(int32_t bits) {
   return "cost not finite";
 }
 
-static std::string error_message(const psl_presolver* p, int32_t bits, int64_t pos) {
-  if (p->K == 1) return "invalid input: " + error_what(bits) + " (first at index " + std::to_string(pos) + ")";
+static std::string error_message(psl_presolver* p, int32_t bits, int64_t pos) {
+  if (p->K == 1) {
+    p->err_lp = 0;
+    return "invalid input: " + error_what(bits) + " (first at index " + std::to_string(pos) + ")";
+  }
   // position in the batch's rows, columns or entries -> LP and its own index
   const int64_t* z0 = p->h_z0;
   int k = 0;
@@ -558,6 +452,7 @@ static std::string error_message(const psl_presolver* p, int32_t bits, int64_t p
   if (bits & (1 | 8)) find(p->h_row0);
   else if (bits & (2 | 4)) find(z0);
   else find(p->h_col0);
+  p->err_lp = k;
   return "invalid input in LP " + std::to_string(k) + ": " + error_what(bits) + " (first at index " +
          std::to_string(local) + ")";
 }
@@ -732,14 +627,18 @@ static psl_status ingest_batch(psl_presolver* p, int32_t k, const psl_lp* lps) {
     for (int32_t t = 0; t < k; ++t) {
       const psl_lp& L = lps[t];
       int64_t r0 = p->h_row0[t], c0 = p->h_col0[t], z0 = p->h_z0[t];
-      if (L.m > 0 && (L.row_ptr[0] != 0 || (int64_t)L.row_ptr[L.m] != L.nnz))
+      if (L.m > 0 && (L.row_ptr[0] != 0 || (int64_t)L.row_ptr[L.m] != L.nnz)) {
+        p->err_lp = t;
         return fail(p, PSL_ERR_INVALID, "invalid input in LP " + std::to_string(t) + ": " + error_what(1));
+      }
       for (int32_t i = 0; i < L.m; ++i) rp[r0 + i] = (int32_t)(L.row_ptr[i] + z0);
       for (int64_t q = 0; q < L.nnz; ++q) {
         int32_t j = L.col_idx[q];
-        if (j < 0 || j >= L.n)
+        if (j < 0 || j >= L.n) {
+          p->err_lp = t;
           return fail(p, PSL_ERR_INVALID, "invalid input in LP " + std::to_string(t) + ": " + error_what(2) +
                                               " (first at index " + std::to_string(q) + ")");
+        }
         ci[z0 + q] = (int32_t)(j + c0);
       }
       if (L.nnz) std::memcpy(&va[z0], L.val, L.nnz * sizeof(double));
@@ -1320,12 +1219,23 @@ static psl_status postsolve_of(psl_presolver* p, int k, const double* x_red, con
   const std::vector<psl_record>* rec = nullptr;
   psl_status st = fetch_lp_records(p, k, &rec);
   if (st != PSL_OK) return st;
-  std::vector<int32_t> cmap(v.n);
-  if (v.n) HIPCHK(p, hipMemcpy(cmap.data(), v.col_map, v.n * sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::string err;
+  st = postsolve_primal(rec->data(), (int64_t)rec->size(), v.col_map, n, v.n, x_red, x, &err);
+  if (st != PSL_OK) p->err = err;
+  return st;
+}
+
+psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
+                                 int32_t n_red, const double* x_red, double* x, std::string* err) {
+  std::vector<int32_t> cmap(n_red);
+  if (n_red && hipMemcpy(cmap.data(), col_map_dev, n_red * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+    *err = "HIP error copying the column map";
+    return PSL_ERR_DEVICE;
+  }
   for (int32_t j = 0; j < n; ++j) x[j] = 0.0;
-  for (int32_t t = 0; t < v.n; ++t) x[cmap[t]] = x_red[t];
-  for (int64_t t = (int64_t)rec->size() - 1; t >= 0; --t) {
-    const psl_record& r = (*rec)[t];
+  for (int32_t t = 0; t < n_red; ++t) x[cmap[t]] = x_red[t];
+  for (int64_t t = count - 1; t >= 0; --t) {
+    const psl_record& r = rec[t];
     if (r.type == REC_FIX_COL || r.type == REC_EMPTY_COL) x[r.j] = r.v[0];
   }
   return PSL_OK;
@@ -1367,7 +1277,7 @@ namespace {
 thread_local std::string g_batch_error = "no error";
 }
 
-static std::string check_batch(int32_t k, const psl_lp* lps, int64_t& M, int64_t& Nc, int64_t& Z) {
+std::string psl::check_batch(int32_t k, const psl_lp* lps, int64_t& M, int64_t& Nc, int64_t& Z) {
   M = Nc = Z = 0;
   if (k < 1) return "a batch needs k >= 1 LPs";
   for (int32_t t = 0; t < k; ++t) {
@@ -1384,6 +1294,7 @@ static std::string check_batch(int32_t k, const psl_lp* lps, int64_t& M, int64_t
 }
 
 static psl_status batch_load(psl_presolver* p, int32_t k, const psl_lp* lps) {
+  p->err_lp = -1;
   if (k == 1) {
     set_sizes(p, 1, lps[0].m, lps[0].n, lps[0].nnz);
     return ingest(p, &lps[0]);
@@ -1466,10 +1377,7 @@ static bool batch_idx_ok(const psl_batch* b, int32_t idx) {
   return b && idx >= 0 && idx < b->p->K;
 }
 
-extern "C" psl_status psl_batch_stats(const psl_batch* b, int32_t idx, psl_stats* out) {
-  if (!batch_idx_ok(b, idx) || !out) return PSL_ERR_INVALID;
-  psl_presolver* p = b->p;
-  if (p->state != 1) return fail(p, PSL_ERR_STATE, "no run yet");
+void psl::engine_lp_stats(const psl_presolver* p, int idx, psl_stats* out) {
   psl_stats S = p->stats;
   const LpState& L = p->lst[idx];
   S.rounds = L.rounds;
@@ -1486,6 +1394,12 @@ extern "C" psl_status psl_batch_stats(const psl_batch* b, int32_t idx, psl_stats
     S.m_out = S.n_out = 0;
   }
   *out = S;
+}
+
+extern "C" psl_status psl_batch_stats(const psl_batch* b, int32_t idx, psl_stats* out) {
+  if (!batch_idx_ok(b, idx) || !out) return PSL_ERR_INVALID;
+  if (b->p->state != 1) return fail(b->p, PSL_ERR_STATE, "no run yet");
+  engine_lp_stats(b->p, idx, out);
   return PSL_OK;
 }
 
@@ -1521,3 +1435,64 @@ extern "C" const char* psl_batch_last_error(const psl_batch* b) {
   if (!b) return g_batch_error.c_str();
   return b->p->err.c_str();
 }
+
+// ---------------------------------------------------------------------------
+// engine interface for the server
+// ---------------------------------------------------------------------------
+psl_presolver* psl::engine_new(const psl_settings* s, int32_t cap_m, int32_t cap_n, int64_t cap_nnz, int32_t cap_K,
+                               psl_status* st, std::string* err) {
+  psl_presolver* p = new psl_presolver();
+  p->s = *s;
+  p->s.bin_thresholds = nullptr;
+  if (s->bin_thresholds) {
+    p->thresholds[0] = s->bin_thresholds[0];
+    p->thresholds[1] = s->bin_thresholds[1];
+  }
+  p->stream = (hipStream_t)s->stream;
+  p->cap_m = cap_m;
+  p->cap_n = cap_n;
+  p->cap_nnz = cap_nnz;
+  p->cap_K = cap_K;
+  p->state = 2;  // nothing loaded
+  *st = setup_arena(p);
+  if (*st != PSL_OK) {
+    *err = p->err;
+    psl_presolve_free(p);
+    return nullptr;
+  }
+  return p;
+}
+
+void psl::engine_free(psl_presolver* p) { psl_presolve_free(p); }
+
+psl_status psl::engine_load(psl_presolver* p, int32_t k, const psl_lp* lps) {
+  psl_status st = batch_load(p, k, lps);
+  if (st != PSL_OK) p->state = 2;
+  return st;
+}
+
+psl_status psl::engine_run(psl_presolver* p, psl_stats* out) {
+  if (p->state != 0) return fail(p, PSL_ERR_STATE, "run needs a fresh load");
+  return run_engine(p, out);
+}
+
+psl_result psl::engine_result(const psl_presolver* p, int k) { return p->lp_result[k]; }
+
+bool psl::engine_has_reduced(const psl_presolver* p, int k) { return has_reduced(p, k); }
+
+psl_reduced_view psl::engine_view(const psl_presolver* p, int k) { return reduced_view(p, k); }
+
+int64_t psl::engine_records(const psl_presolver* p, int k, const void** dev) {
+  if (p->K == 1) {
+    *dev = p->rec;
+    return p->rec_count;
+  }
+  *dev = p->rec_lp + p->h_rec_off[k];
+  return p->h_rec_off[k + 1] - p->h_rec_off[k];
+}
+
+const std::string& psl::engine_error(const psl_presolver* p) { return p->err; }
+
+int32_t psl::engine_error_lp(const psl_presolver* p) { return p->err_lp; }
+
+size_t psl::engine_arena_bytes(const psl_presolver* p) { return p->arena_bytes; }

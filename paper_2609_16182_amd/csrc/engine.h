@@ -1,0 +1,170 @@
+// engine.h -- the presolve engine behind libpsl's C-ABI: the device arena,
+// the views of the row bins and the round controller's state, for one LP or a
+// batch of LPs. Shared by the presolve / batch entry points and the server.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/psl.h"
+#include "psl_kern.h"
+#include "sweep.h"
+
+using psl::BinEnt;
+using psl::CompactScratch;
+using psl::Flags;
+using psl::IngestScratch;
+using psl::LongChunk;
+using psl::LpDesc;
+using psl::LpFlags;
+using psl::LpOut;
+using psl::LpRed;
+using psl::LpTab;
+using psl::MODE_ROUND;
+using psl::NBINS;
+using psl::ParScratch;
+using psl::Record;
+using psl::Reduced;
+using psl::SweepGrid;
+
+struct View {
+  BinEnt* bins = nullptr;
+  LongChunk* chunks = nullptr;
+  int32_t off[NBINS + 1] = {0};
+  int32_t nchunks = 0;
+  int64_t rows = 0, nnz = 0;
+};
+
+// host state of one LP of a batch
+enum : uint8_t { LP_PROP = 0, LP_WAIT = 1, LP_DONE = 2 };
+struct LpState {
+  uint8_t phase = LP_PROP;
+  bool infeasible = false, unbounded = false;
+  int32_t rounds = 0, cycles = 0;
+};
+
+struct psl_presolver {
+  using Dev = psl::Dev;
+  Dev d{};
+  psl_settings s{};
+  hipStream_t stream = nullptr;
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0;
+  // arena capacity (the create-time sizes; a batch reload may use less)
+  int32_t cap_m = 0, cap_n = 0, cap_K = 1;
+  int64_t cap_nnz = 0;
+
+  // batch (K > 1): device maps and per-LP arrays, pinned host mirrors
+  int32_t K = 1;
+  int32_t *row_lp = nullptr, *col_lp = nullptr, *lp_row0 = nullptr, *lp_col0 = nullptr, *lp_round = nullptr;
+  uint8_t* lp_ok = nullptr;
+  LpFlags* lpf = nullptr;
+  LpOut* lpo = nullptr;
+  LpTab* lpt = nullptr;
+  LpRed* lpr = nullptr;
+  int64_t* lp_z0 = nullptr;
+  LpDesc* descs = nullptr;
+  double *lp_off_in = nullptr, *lp_off = nullptr;
+  int32_t *h_row0 = nullptr, *h_col0 = nullptr, *h_round = nullptr;
+  int64_t* h_z0 = nullptr;
+  uint8_t* h_ok = nullptr;
+  LpFlags* h_lpf = nullptr;
+  LpOut* h_lpo = nullptr;
+  LpTab* h_lpt = nullptr;
+  LpRed* h_lpr = nullptr;
+  LpDesc* h_desc = nullptr;
+  double *h_off_in = nullptr, *h_off = nullptr;
+  std::vector<LpState> lst;
+  std::vector<psl_result> lp_result;
+  BinEnt* bins_0 = nullptr;  // the ingest bins of all rows
+  LongChunk* chunks_0 = nullptr;
+  View all;
+  // records split by LP
+  Record* rec_lp = nullptr;
+  int64_t split_cap = 0;
+  uint32_t *sk0 = nullptr, *sk1 = nullptr;
+  int32_t *sv0 = nullptr, *sv1 = nullptr, *sws = nullptr, *rec_off = nullptr;
+  std::vector<int32_t> h_rec_off;
+  std::vector<std::vector<psl_record>> lp_host_rec;
+  std::vector<uint8_t> lp_rec_valid;
+  std::vector<void*> allocs, hallocs;
+  size_t arena_bytes = 0;   // device bytes allocated by the handle
+  std::string err = "no error";
+  int32_t err_lp = -1;      // LP of a batch that failed validation, else -1
+  int64_t par_slots = 0;
+
+  // staging and persistent scratch
+  double *lb_in = nullptr, *ub_in = nullptr, *c_mut = nullptr;
+  IngestScratch isc{};
+  int32_t* ws = nullptr;
+  const uint32_t* colid = nullptr;
+  int32_t* bin_counts_dev = nullptr;
+  int32_t bin_counts[NBINS] = {0};
+  int32_t thresholds[2] = {512, PASS_LEN};  // longest wavefront row, chunk positions
+  SweepGrid grid{};
+  int64_t chunk_cap = 0, long_cap = 0, cand_cap = 0;
+  int32_t* cand_cnt = nullptr;
+  // bin views: the master lists hold the active rows (filtered after
+  // removals); a selection holds the active rows touched by a column change
+  // since they were last swept
+  BinEnt *bins_a = nullptr, *bins_b = nullptr, *bins_s = nullptr;
+  LongChunk *chunks_a = nullptr, *chunks_b = nullptr, *chunks_s = nullptr;
+  int32_t* rebin_dev = nullptr;  // [NBINS+1] new offsets, then 3 totals
+  View master, cur;
+
+  // records
+  Record* rec = nullptr;
+  int64_t rec_cap = 0, rec_count = 0;
+  std::vector<psl_record> host_rec;
+  bool host_rec_valid = false;
+
+  ParScratch par{};
+  CompactScratch cmp{};
+  Reduced red{};
+  int32_t red_m = 0, red_n = 0;
+  int64_t red_nnz = 0;
+  double red_off = 0.0;
+  double obj_offset = 0.0;
+
+  Flags* hflags = nullptr;  // pinned
+  int32_t* htot = nullptr;  // pinned [4] + offset
+  double* hoff = nullptr;
+
+  int state = 0;  // 0 loaded, 1 ran
+  int sweep_mode = MODE_ROUND;  // PSL_SWEEP_SPLIT=1: three launches by register class
+  psl_result result = PSL_RES_UNCHANGED;
+  psl_stats stats{};
+  double ms_ingest = 0.0;
+  hipEvent_t ev[8] = {nullptr};
+};
+
+namespace psl {
+
+std::string check_settings(const psl_settings* s);
+std::string check_lp_shape(const psl_lp* lp);
+// k LPs of one batch: shapes checked, totals returned
+std::string check_batch(int32_t k, const psl_lp* lps, int64_t& M, int64_t& Nc, int64_t& Z);
+// an engine with room for LPs of these total sizes (no LP loaded yet); on
+// failure returns nullptr and sets *st and *err
+psl_presolver* engine_new(const psl_settings* s, int32_t cap_m, int32_t cap_n, int64_t cap_nnz, int32_t cap_K,
+                          psl_status* st, std::string* err);
+void engine_free(psl_presolver* p);
+// load k LPs (totals within the capacity) and run them
+psl_status engine_load(psl_presolver* p, int32_t k, const psl_lp* lps);
+psl_status engine_run(psl_presolver* p, psl_stats* out);
+psl_result engine_result(const psl_presolver* p, int k);
+bool engine_has_reduced(const psl_presolver* p, int k);
+psl_reduced_view engine_view(const psl_presolver* p, int k);
+// LP k's records of the last run: count, and their device address
+int64_t engine_records(const psl_presolver* p, int k, const void** dev);
+const std::string& engine_error(const psl_presolver* p);
+int32_t engine_error_lp(const psl_presolver* p);
+// per-LP statistics of the last run (as psl_batch_stats)
+void engine_lp_stats(const psl_presolver* p, int k, psl_stats* out);
+// primal postsolve on the host from records and the reduced column map
+psl_status postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
+                            int32_t n_red, const double* x_red, double* x, std::string* err);
+size_t engine_arena_bytes(const psl_presolver* p);
+
+}  // namespace psl

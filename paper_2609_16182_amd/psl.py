@@ -63,6 +63,17 @@ class psl_reduced_view(C.Structure):
                 ("row_class", C.c_void_p), ("col_class", C.c_void_p)]
 
 
+class psl_server_config(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("slots", C.c_int32), ("threaded", C.c_int32),
+                ("max_batch_lps", C.c_int32), ("max_batch_rows", C.c_int32), ("max_batch_cols", C.c_int32),
+                ("max_batch_nnz", C.c_int64)]
+
+
+class psl_ticket_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("result", C.c_int), ("queue_ms", C.c_double), ("latency_ms", C.c_double),
+                ("batch_lps", C.c_int32), ("slot", C.c_int32), ("stats", psl_stats)]
+
+
 class PslError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
@@ -105,9 +116,31 @@ def load(path=None):
     lib.psl_batch_free.restype = None
     lib.psl_batch_last_error.argtypes = [C.c_void_p]
     lib.psl_batch_last_error.restype = C.c_char_p
+    lib.psl_server_config_default.argtypes = [C.POINTER(psl_server_config)]
+    lib.psl_server_config_default.restype = None
+    lib.psl_server_create.argtypes = [C.POINTER(psl_server_config), C.POINTER(psl_settings), C.POINTER(C.c_void_p)]
+    lib.psl_server_submit.argtypes = [C.c_void_p, C.POINTER(psl_lp), C.POINTER(C.c_uint64)]
+    lib.psl_server_step.argtypes = [C.c_void_p, C.POINTER(C.c_int32)]
+    lib.psl_server_poll.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
+    lib.psl_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_double]
+    lib.psl_server_info.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(psl_ticket_info)]
+    lib.psl_server_reduced_problem.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(psl_reduced_view)]
+    lib.psl_server_records.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int64), C.c_void_p, C.c_int64]
+    lib.psl_server_postsolve.argtypes = [C.c_void_p, C.c_uint64] + [C.c_void_p] * 6
+    lib.psl_server_release.argtypes = [C.c_void_p, C.c_uint64]
+    lib.psl_server_drain.argtypes = [C.c_void_p]
+    lib.psl_server_memory.argtypes = [C.c_void_p] + [C.POINTER(C.c_size_t)] * 4
+    lib.psl_server_memory.restype = C.c_int
+    lib.psl_server_free.argtypes = [C.c_void_p]
+    lib.psl_server_free.restype = None
+    lib.psl_server_last_error.argtypes = [C.c_void_p]
+    lib.psl_server_last_error.restype = C.c_char_p
     for f in ("psl_presolve_create", "psl_presolve_reload", "psl_presolve_run", "psl_reduced_problem",
               "psl_records", "psl_postsolve", "psl_batch_create", "psl_batch_reload", "psl_batch_run",
-              "psl_batch_stats", "psl_batch_reduced_problem", "psl_batch_records", "psl_batch_postsolve"):
+              "psl_batch_stats", "psl_batch_reduced_problem", "psl_batch_records", "psl_batch_postsolve",
+              "psl_server_create", "psl_server_submit", "psl_server_step", "psl_server_poll", "psl_server_wait",
+              "psl_server_info", "psl_server_reduced_problem", "psl_server_records", "psl_server_postsolve",
+              "psl_server_release", "psl_server_drain"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -131,6 +164,11 @@ def _check(st, h=None):
 def _bcheck(st, b=None):
     if st != PSL_OK:
         raise PslError(st, load().psl_batch_last_error(b).decode())
+
+
+def _scheck(st, sv=None):
+    if st != PSL_OK:
+        raise PslError(st, load().psl_server_last_error(sv).decode())
 
 
 # ---------------------------------------------------------------------------
@@ -254,6 +292,102 @@ def psl_batch_free(b):
 
 def psl_batch_last_error(b=None):
     return load().psl_batch_last_error(b).decode()
+
+
+def psl_server_config_default():
+    c = psl_server_config()
+    load().psl_server_config_default(C.byref(c))
+    return c
+
+
+def psl_server_create(cfg: psl_server_config, settings: psl_settings):
+    sv = C.c_void_p()
+    _scheck(load().psl_server_create(C.byref(cfg), C.byref(settings), C.byref(sv)))
+    return sv
+
+
+def psl_server_submit(sv, lp: psl_lp):
+    t = C.c_uint64()
+    _scheck(load().psl_server_submit(sv, C.byref(lp), C.byref(t)), sv)
+    return t.value
+
+
+def psl_server_step(sv):
+    n = C.c_int32()
+    _scheck(load().psl_server_step(sv, C.byref(n)), sv)
+    return n.value
+
+
+def psl_server_poll(sv, cap=1024):
+    arr = (C.c_uint64 * cap)()
+    n = C.c_int32()
+    _scheck(load().psl_server_poll(sv, C.cast(arr, C.c_void_p), cap, C.byref(n)), sv)
+    return list(arr[:n.value])
+
+
+def psl_server_wait(sv, ticket, timeout_ms=-1.0):
+    _scheck(load().psl_server_wait(sv, ticket, float(timeout_ms)), sv)
+
+
+def psl_server_info(sv, ticket):
+    i = psl_ticket_info()
+    _scheck(load().psl_server_info(sv, ticket, C.byref(i)), sv)
+    return i
+
+
+def psl_server_reduced_problem(sv, ticket):
+    v = psl_reduced_view()
+    _scheck(load().psl_server_reduced_problem(sv, ticket, C.byref(v)), sv)
+    return v
+
+
+def psl_server_records(sv, ticket):
+    cnt = C.c_int64()
+    _scheck(load().psl_server_records(sv, ticket, C.byref(cnt), None, 0), sv)
+    out = np.zeros(cnt.value, RECORD_DTYPE)
+    if cnt.value:
+        _scheck(load().psl_server_records(sv, ticket, C.byref(cnt), out.ctypes.data, cnt.value), sv)
+    return out
+
+
+def psl_server_postsolve(sv, ticket, x_red, n):
+    x_red = np.ascontiguousarray(x_red, np.float64)
+    x = np.zeros(n)
+    _scheck(load().psl_server_postsolve(sv, ticket, x_red.ctypes.data if x_red.size else None, None, None,
+                                        x.ctypes.data if n else None, None, None), sv)
+    return x
+
+
+def psl_server_release(sv, ticket):
+    _scheck(load().psl_server_release(sv, ticket), sv)
+
+
+def psl_server_drain(sv):
+    _scheck(load().psl_server_drain(sv), sv)
+
+
+def psl_server_memory(sv):
+    v = [C.c_size_t() for _ in range(4)]
+    _scheck(load().psl_server_memory(sv, *[C.byref(x) for x in v]), sv)
+    return dict(zip(("arena_bytes", "heap_bytes", "heap_used", "heap_peak"), [x.value for x in v]))
+
+
+def reduced_footprint(m, n, nnz):
+    """Bytes a request reserves in the server's result heap (its LP's sizes)."""
+    def a(x):
+        return (x + 255) // 256 * 256
+    sizes = [(m + 1) * 4, nnz * 4, nnz * 8, (n + 1) * 4, nnz * 4, nnz * 8, m * 8, m * 8, n * 8, n * 8, n * 8,
+             m * 4, n * 4, m, n]
+    return sum(a(x) for x in sizes)
+
+
+def psl_server_free(sv):
+    if sv:
+        load().psl_server_free(sv)
+
+
+def psl_server_last_error(sv=None):
+    return load().psl_server_last_error(sv).decode()
 
 
 # ---------------------------------------------------------------------------
@@ -448,6 +582,77 @@ class Batch:
         if getattr(self, "h", None):
             psl_batch_free(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching presolve server (psl_server_*). The arrays of a
+    submitted LP are kept alive here until its ticket is released."""
+
+    def __init__(self, stream=None, **config):
+        settings = {k: config.pop(k) for k in list(config) if k in {f for f, _ in psl_settings._fields_}}
+        self.cfg = psl_server_config_default()
+        for k, v in config.items():
+            setattr(self.cfg, k, v)
+        self.settings = make_settings(**settings)
+        self.h = psl_server_create(self.cfg, self.settings)
+        self._keep = {}
+        self._n = {}
+
+    def submit(self, lp):
+        keep = []
+        t = psl_server_submit(self.h, make_lp(lp, keep))
+        self._keep[t] = keep
+        self._n[t] = int(lp["n"])
+        return t
+
+    def step(self):
+        return psl_server_step(self.h)
+
+    def poll(self, cap=1024):
+        return psl_server_poll(self.h, cap)
+
+    def wait(self, ticket, timeout_ms=-1.0):
+        psl_server_wait(self.h, ticket, timeout_ms)
+
+    def info(self, ticket):
+        i = psl_server_info(self.h, ticket)
+        return {"status": i.status, "result_name": RESULT_NAMES.get(i.result, i.result), "queue_ms": i.queue_ms,
+                "latency_ms": i.latency_ms, "batch_lps": i.batch_lps, "slot": i.slot, "stats": i.stats.as_dict()}
+
+    def records(self, ticket):
+        return psl_server_records(self.h, ticket)
+
+    def view(self, ticket):
+        return psl_server_reduced_problem(self.h, ticket)
+
+    def reduced(self, ticket):
+        return reduced_to_host(self.view(ticket))
+
+    def postsolve(self, ticket, x_red):
+        return psl_server_postsolve(self.h, ticket, x_red, self._n[ticket])
+
+    def release(self, ticket):
+        psl_server_release(self.h, ticket)
+        self._keep.pop(ticket, None)
+        self._n.pop(ticket, None)
+
+    def drain(self):
+        psl_server_drain(self.h)
+
+    def memory(self):
+        return psl_server_memory(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            psl_server_free(self.h)
+            self.h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

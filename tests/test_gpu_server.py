@@ -1,0 +1,156 @@
+"""Serving: every request's result is the same alone and in the mix.
+
+LPs are submitted from another thread at random moments while batches are
+on the device, so they land in batches of varying composition on both
+slots; each ticket's outcome, records and reduced problem are compared bit
+for bit with the CPU oracle run on that LP alone. Also: manual stepping,
+admission by the result-heap budget (the queue head waits for releases),
+invalid LPs failing alone, device-resident inputs, postsolve.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2609_16182_amd import lpgen
+from tests.lp_utils import make
+from tests.parity_util import assert_same
+
+pytestmark = pytest.mark.gpu
+
+psl = pytest.importorskip("paper_2609_16182_amd.psl")
+
+INF = np.inf
+SMALL = dict(hbm_budget_bytes=6 << 30, max_batch_lps=16, max_batch_rows=60_000, max_batch_cols=90_000,
+             max_batch_nnz=600_000)
+
+
+def got_of(sv, t):
+    info = sv.info(t)
+    assert info["status"] == psl.PSL_OK, info
+    name = info["result_name"]
+    out = {"result_name": name, "records": sv.records(t)}
+    out["reduced"] = sv.reduced(t) if name in ("REDUCED", "UNCHANGED") else None
+    return out, info
+
+
+def mix_lps():
+    lps = [lpgen.tiny(s, finite_bounds=s % 3 == 0) for s in range(24)]
+    lps += [lpgen.batch_member(i, m=200 + 173 * i) for i in range(12)]
+    lps += [lpgen.single_small(seed=11)]
+    lps.append(make(1, 2, [[(0, 1.0), (1, 1.0)]], [5.0], [INF], [0, 0], [1, 1], [1.0, 1.0]))  # infeasible
+    lps.append(make(1, 2, [[(0, 1.0)]], [0.0], [4.0], [0, 0], [10, INF], [1.0, -1.0]))      # unbounded
+    rng = np.random.default_rng(5)
+    order = rng.permutation(len(lps))
+    return [lps[i] for i in order]
+
+
+def test_server_mix_equals_alone():
+    lps = mix_lps()
+    sv = psl.Server(**SMALL)
+    tickets = [None] * len(lps)
+    rng = np.random.default_rng(1)
+    delays = rng.exponential(0.002, len(lps))
+
+    def producer():
+        for i, lp in enumerate(lps):
+            time.sleep(delays[i])
+            tickets[i] = sv.submit(lp)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    sv.drain()
+    batch_sizes, slots = [], set()
+    for i, lp in enumerate(lps):
+        sv.wait(tickets[i], 60_000)
+        got, info = got_of(sv, tickets[i])
+        assert_same(got, O.presolve(lp), f"ticket {i}")
+        assert info["latency_ms"] >= info["queue_ms"] >= 0
+        batch_sizes.append(info["batch_lps"])
+        slots.add(info["slot"])
+        if got["reduced"] is not None:
+            x_red = np.random.default_rng(i).uniform(-1, 1, got["reduced"]["n"])
+            x = sv.postsolve(tickets[i], x_red)
+            p = psl.Presolver(lp)
+            p.run()
+            assert np.array_equal(x, p.postsolve(x_red))
+            p.close()
+        sv.release(tickets[i])
+    assert max(batch_sizes) > 1, batch_sizes  # LPs were presolved together
+    assert len(set(sv.poll())) == len(lps)
+    sv.close()
+
+
+def test_server_manual_steps_and_invalid_member():
+    lps = [lpgen.batch_member(i, m=300 + 50 * i) for i in range(5)]
+    bad = dict(lpgen.tiny(2))
+    bad["col_idx"] = np.array(bad["col_idx"], np.int32).copy()
+    bad["col_idx"][-1] = bad["n"] + 5
+    lps.insert(2, bad)
+    sv = psl.Server(slots=1, threaded=0, **SMALL)
+    ts = [sv.submit(lp) for lp in lps]
+    with pytest.raises(psl.PslError):
+        sv.info(ts[0])  # not done yet
+    n = sv.step()
+    assert n == len(lps)
+    for i, (t, lp) in enumerate(zip(ts, lps)):
+        info = sv.info(t)
+        if i == 2:
+            assert info["status"] == psl.PSL_ERR_INVALID
+            continue
+        got, _ = got_of(sv, t)
+        assert_same(got, O.presolve(lp), f"manual {i}")
+    assert sv.step() == 0
+    sv.close()
+
+
+def test_server_admission_waits_for_memory():
+    lps = [lpgen.batch_member(20 + i, m=4000) for i in range(8)]
+    foot = max(psl.reduced_footprint(lp["m"], lp["n"], lpgen.nnz(lp)) for lp in lps)
+    probe = psl.Server(slots=1, **SMALL)
+    arena = probe.memory()["arena_bytes"]
+    probe.close()
+    # a result heap that holds two reservations at a time, not three
+    sv = psl.Server(slots=1, **{**SMALL, "hbm_budget_bytes": arena + int(2.5 * foot)})
+    heap = sv.memory()["heap_bytes"]
+    assert 2 * foot <= heap < 3 * foot
+    ts = [sv.submit(lp) for lp in lps]
+    left = set(ts)
+    deadline = time.time() + 120
+    while left and time.time() < deadline:
+        for t in sv.poll():
+            idx = ts.index(t)
+            got, info = got_of(sv, t)
+            assert info["batch_lps"] <= 2, info
+            assert_same(got, O.presolve(lps[idx]), f"budget {idx}")
+            sv.release(t)
+            left.discard(t)
+        time.sleep(0.001)
+    assert not left, "not every request completed"
+    mem = sv.memory()
+    assert mem["heap_peak"] <= heap and mem["heap_used"] == 0
+    with pytest.raises(psl.PslError) as e:
+        sv.submit(lpgen.batch_member(99, m=20000))  # its reservation can never fit the heap
+    assert e.value.status == psl.PSL_ERR_CAPACITY
+    sv.close()
+
+
+def test_server_device_inputs():
+    torch = pytest.importorskip("torch")
+    lps = [lpgen.batch_member(i, m=500 + 90 * i) for i in range(6)] + [lpgen.tiny(9)]
+    keys = ("row_ptr", "col_idx", "val", "lhs", "rhs", "lb", "ub", "c")
+    sv = psl.Server(**SMALL)
+    ts = []
+    for lp in lps:
+        d = {k: torch.from_numpy(np.ascontiguousarray(lp[k])).cuda() for k in keys}
+        d.update(m=lp["m"], n=lp["n"], nnz=lpgen.nnz(lp))
+        ts.append(sv.submit(d))
+    sv.drain()
+    for t, lp in zip(ts, lps):
+        got, _ = got_of(sv, t)
+        assert_same(got, O.presolve(lp), "device")
+        sv.release(t)
+    sv.close()
