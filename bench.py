@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--only-batch", action="store_true", help="run the batched workload only")
     ap.add_argument("--batch-no-seq", action="store_true", help="skip the sequential single-LP baseline")
+    ap.add_argument("--serve-pool", type=int, default=64, help="LPs in the serving pool (0 = skip serving)")
+    ap.add_argument("--serve-rates", default="50,200,1000")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--only-serving", action="store_true", help="run the serving workload only")
     return ap.parse_args()
 
 
@@ -55,6 +59,91 @@ def _oracle_nnz(i):
     lp = lpgen.batch_member(i)
     O.presolve(lp)
     return lpgen.nnz(lp)
+
+
+def _serving_member(i):
+    from paper_2609_16182_amd import lpgen
+    return lpgen.serving_member(i)
+
+
+def _replay(psl, sv, pool, rate, seconds, seed):
+    """Submit pool LPs at Poisson arrivals of `rate`/s for `seconds`, release
+    each result once done; returns per-request latencies and the span."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, int(rate * seconds * 1.5) + 16))
+    arrivals = arrivals[arrivals < seconds]
+    picks = rng.integers(0, len(pool), len(arrivals))
+    lat, qms, bsz, arr_of = [], [], [], {}
+    t0 = time.perf_counter()
+    k = 0
+    last_done = t0
+    pending = 0
+    while k < len(arrivals) or pending:
+        now = time.perf_counter() - t0
+        while k < len(arrivals) and arrivals[k] <= now:
+            t = sv.submit(pool[picks[k]])
+            arr_of[t] = arrivals[k]
+            k += 1
+            pending += 1
+        for t in sv.poll():
+            info = sv.info(t)
+            if arr_of[t] >= 0.1 * seconds:  # warm-up arrivals are not counted
+                lat.append(info["latency_ms"])
+                qms.append(info["queue_ms"])
+                bsz.append(info["batch_lps"])
+            sv.release(t)
+            pending -= 1
+            last_done = time.perf_counter()
+        if now > seconds + 120:
+            raise RuntimeError("serving run did not drain")
+        time.sleep(0.0002)
+    span = last_done - t0
+    lat = np.array(lat)
+    return {"rate": rate, "requests": int(len(arrivals)), "lps_per_s": round(len(arrivals) / span, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_queue_ms": round(float(np.mean(qms)), 3), "mean_batch_lps": round(float(np.mean(bsz)), 2)}
+
+
+def serving_leg(args, torch, psl):
+    """Poisson arrivals of LPs from a device-resident pool (m log-uniform in
+    [1e3, 1e6], n = 1.5m, U{4..20} nnz/row); latency = submit -> reduced LP
+    ready on the device. The continuous-batching server (2 slots) is compared
+    with a one-LP-per-launch FIFO server (1 slot, batches of 1) at each rate."""
+    from concurrent.futures import ProcessPoolExecutor
+
+    t0 = time.time()
+    workers = min(16, os.cpu_count() or 1)
+    with ProcessPoolExecutor(workers) as ex:
+        lps = list(ex.map(_serving_member, range(args.serve_pool)))
+    keys = ("row_ptr", "col_idx", "val", "lhs", "rhs", "lb", "ub", "c")
+    pool = []
+    for lp in lps:
+        d = {k: torch.from_numpy(np.ascontiguousarray(lp[k])).cuda() for k in keys}
+        d.update(m=lp["m"], n=lp["n"], nnz=int(lp["row_ptr"][-1]))
+        pool.append(d)
+    del lps
+    torch.cuda.synchronize()
+    pool_nnz = [d["nnz"] for d in pool]
+    print(f"[bench] serving pool of {len(pool)} LPs (mean nnz {np.mean(pool_nnz):.0f}, max {max(pool_nnz)}) "
+          f"in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    out = {"metric": "serving LPs/s and latency", "pool": len(pool), "mean_nnz": round(float(np.mean(pool_nnz))),
+           "seconds_per_rate": args.serve_seconds, "batched": [], "fifo_one_lp_per_launch": []}
+    for kind, cfg in (("batched", dict(slots=2)), ("fifo_one_lp_per_launch", dict(slots=1, max_batch_lps=1))):
+        sv = psl.Server(**cfg)
+        for lp in pool[:2]:  # warm up
+            sv.wait(sv.submit(lp))
+        for t in sv.poll():
+            sv.release(t)
+        for i, rate in enumerate(rates):
+            r = _replay(psl, sv, pool, rate, args.serve_seconds, seed=100 + i)
+            out[kind].append(r)
+            print(f"[bench] serving {kind} rate {rate}: {r}", file=sys.stderr, flush=True)
+        sv.close()
+    out["config"] = {"workload": "Poisson arrivals over a pool of LPs with m log-uniform in [1e3, 1e6], n = 1.5m, "
+                                 "U{4..20} nnz/row, small-LP planting ratios; inputs device-resident",
+                     "rates": rates}
+    return out
 
 
 def batch_leg(args, torch, psl):
@@ -186,6 +275,9 @@ def main():
     if args.only_batch:
         print(json.dumps(batch_leg(args, torch, psl)), flush=True)
         return
+    if args.only_serving:
+        print(json.dumps(serving_leg(args, torch, psl)), flush=True)
+        return
     t0 = time.time()
     lp = lpgen.power_law(seed=1, scale=args.scale)
     nnz = lpgen.nnz(lp)
@@ -248,6 +340,7 @@ def main():
             print("[bench] WARNING: record counts differ from the oracle", file=sys.stderr)
 
     batch = batch_leg(args, torch, psl) if args.batch_lps > 0 else None
+    serving = serving_leg(args, torch, psl) if args.serve_pool > 0 else None
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "nnz/s", "n_gpus": 1,
@@ -268,6 +361,7 @@ def main():
                    "step_ms_p50": round(float(np.median(step_ms)), 3),
                    "first_run_ms": round(first["ms_total"], 3)},
         "batch": batch,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
