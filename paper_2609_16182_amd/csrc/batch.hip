@@ -6,7 +6,7 @@
 // problems are renumbered per LP), and their own round counts and stopping
 // state (kept on the host), so every LP gets the result of presolving it
 // alone. These kernels load the union, map rows and columns to their LPs,
-// count each LP's records of a round, and split the record stream by LP.
+// and split the record stream by LP.
 #include <utility>
 
 #include "psl_kern.h"
@@ -118,20 +118,6 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_lp_maps(Dev d, int32_t* row_lp, i
   }
 }
 
-// records of each LP in the round just emitted, from the exclusive scan of the
-// per-row (and, with cols, per-column) record counts over [0, limit)
-__global__ void k_lp_totals(Dev d, int cols) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d.K) return;
-  int64_t limit = cols ? (int64_t)d.m + d.n : d.m;
-  int32_t tot = d.flags->round_total;
-  auto at = [&](int64_t x) { return x < limit ? d.off[x] : tot; };
-  int rows = at(d.lp_row0[k + 1]) - at(d.lp_row0[k]);
-  int all = rows;
-  if (cols) all += at((int64_t)d.m + d.lp_col0[k + 1]) - at((int64_t)d.m + d.lp_col0[k]);
-  d.lpo[k] = LpOut{all, rows};
-}
-
 // LP of each record: its row for row records, its column for column records
 __global__ void k_rec_keys(Dev d, const Record* rec, int64_t count, uint32_t* keys) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,10 +187,6 @@ void batch_gather(const Dev& d, const LpDesc* desc, const int64_t* z0, int32_t* 
 void batch_maps(const Dev& d, int32_t* row_lp, int32_t* col_lp, hipStream_t s) {
   int64_t span = (int64_t)d.m + d.n;
   if (span > 0) hipLaunchKernelGGL(k_lp_maps, dim3(tiles(span)), dim3(PSL_BLOCK), 0, s, d, row_lp, col_lp);
-}
-
-void launch_lp_totals(const Dev& d, bool cols, hipStream_t s) {
-  hipLaunchKernelGGL(k_lp_totals, dim3((d.K + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, cols ? 1 : 0);
 }
 
 size_t rec_split_ws_ints(int64_t count) { return radix_ws_ints(count); }

@@ -207,6 +207,10 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->chunks_s, p->chunk_cap);
   uint8_t* dirty;
   ALLOC(dirty, m);
+  ALLOC(d.touch, n);
+  ALLOC(d.rinf, m);
+  ALLOC(d.dense_cols, N / 4096 + 2);
+  ALLOC(d.n_dense, 1);
   LongPart* lpart;
   LongRow* lrow;
   ALLOC(lpart, p->chunk_cap);
@@ -329,6 +333,7 @@ static psl_status setup_arena(psl_presolver* p) {
   d.bins = p->bins_a;
   d.lchunk = p->chunks_a;
   d.dirty = dirty;
+  d.rowid1 = p->isc.rowid1;
   d.lpart = lpart;
   d.lrow = lrow;
   d.nlong = 0;
@@ -348,7 +353,8 @@ static psl_status setup_arena(psl_presolver* p) {
   // even for empty problems); colid is set once the transposed copy exists
   const void* ptrs[] = {d.rp, d.ci, d.va, d.cp, d.ri, d.cva, d.lhs, d.rhs, d.bnd, d.bkey, d.src, d.c,
                         d.col_len, d.row_on, d.row_code, d.col_code, d.dirty, d.row_out, d.cand, d.cand_cnt,
-                        d.flags, d.cnt, d.off, d.rec, d.bins, d.lchunk, d.lpart, d.lrow, p->lpr};
+                        d.flags, d.cnt, d.off, d.rec, d.bins, d.lchunk, d.lpart, d.lrow, p->lpr,
+                        d.dense_cols, d.n_dense, d.touch, d.rinf};
   for (const void* q : ptrs)
     if (!q) return fail(p, PSL_ERR_DEVICE, "internal: a device array was not set up");
   if (K > 1) {
@@ -366,12 +372,11 @@ static psl_status read_flags(psl_presolver* p) {
   return PSL_OK;
 }
 
-// flags plus the number of row records of the last scan (rows removed)
-static psl_status read_round(psl_presolver* p, int64_t rows_total, int32_t* rows_removed) {
-  HIPCHK(p, hipMemcpyAsync(p->hflags, p->d.flags, sizeof(Flags), hipMemcpyDeviceToHost, p->stream));
-  HIPCHK(p, hipMemcpyAsync(p->htot + 32, p->d.off + rows_total, sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
-  HIPCHK(p, hipStreamSynchronize(p->stream));
-  *rows_removed = p->htot[32];
+// flags of a round, with the number of rows it removed
+static psl_status read_round(psl_presolver* p, int32_t* rows_removed) {
+  psl_status e = read_flags(p);
+  if (e != PSL_OK) return e;
+  *rows_removed = p->hflags->rows_removed;
   return PSL_OK;
 }
 
@@ -402,11 +407,11 @@ static void use_view(psl_presolver* p, const View& v) {
 
 // dst = the active rows of src (only the dirty ones when dirty is set)
 static psl_status filter_view(psl_presolver* p, const View& src, BinEnt* bout, LongChunk* cout, bool dirty,
-                              View& dst) {
+                              View& dst, bool inert = false) {
   Dev& d = p->d;
   // scratch: cnt / off (free after the round's emission) and v0 (free between
   // ingest and compaction; k0 / k1 hold the transposed copy's column ids)
-  rebin(d, src.bins, src.off, src.chunks, src.nchunks, bout, cout, dirty ? d.dirty : nullptr, d.cnt, d.off,
+  rebin(d, src.bins, src.off, src.chunks, src.nchunks, bout, cout, dirty ? d.dirty : nullptr, inert, d.cnt, d.off,
         p->isc.v0, p->rebin_dev, p->rebin_dev + NBINS + 1, p->ws, p->stream);
   HIPCHK(p, hipMemcpyAsync(p->htot, p->rebin_dev, (NBINS + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
@@ -521,6 +526,7 @@ static psl_status ingest_rest(psl_presolver* p) {
   p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.col_len, p->isc, st);
   p->cmp.colid = p->colid;
   d.colid = p->colid;
+  list_dense_cols(d, st);
 
   // parallel-row table: one slice of >= 2 m_k slots per LP
   if (p->K == 1) {
@@ -701,6 +707,7 @@ extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* 
   }
   p->stream = (hipStream_t)s->stream;
   if (const char* e = std::getenv("PSL_SWEEP_SPLIT")) p->sweep_mode = std::atoi(e) ? 2 : MODE_ROUND;
+  if (const char* e = std::getenv("PSL_TRACE")) p->trace = std::atoi(e) != 0;
   p->cap_m = lp->m;
   p->cap_n = lp->n;
   p->cap_nnz = lp->nnz;
@@ -760,6 +767,7 @@ static psl_status begin_lp_round(psl_presolver* p) {
   if (p->K == 1) return PSL_OK;
   HIPCHK(p, hipMemcpyAsync(p->lp_round, p->h_round, p->K * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
   HIPCHK(p, hipMemsetAsync(p->lpf, 0, p->K * sizeof(LpFlags), p->stream));
+  HIPCHK(p, hipMemsetAsync(p->lpo, 0, p->K * sizeof(LpOut), p->stream));
   return PSL_OK;
 }
 
@@ -767,10 +775,7 @@ static psl_status begin_lp_round(psl_presolver* p) {
 // synchronising read completes it
 static psl_status queue_lp_read(psl_presolver* p, bool totals) {
   if (p->K == 1) return PSL_OK;
-  if (totals) {
-    launch_lp_totals(p->d, true, p->stream);
-    HIPCHK(p, hipMemcpyAsync(p->h_lpo, p->lpo, p->K * sizeof(LpOut), hipMemcpyDeviceToHost, p->stream));
-  }
+  if (totals) HIPCHK(p, hipMemcpyAsync(p->h_lpo, p->lpo, p->K * sizeof(LpOut), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipMemcpyAsync(p->h_lpf, p->lpf, p->K * sizeof(LpFlags), hipMemcpyDeviceToHost, p->stream));
   return PSL_OK;
 }
@@ -905,14 +910,12 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       launch_sweep(d, p->grid, p->sweep_mode, st);
       HIPCHK(p, hipEventRecord(p->ev[5], st));
       launch_src(d, p->grid, st);
-      launch_count(d, st);
-      scan_excl(d.cnt, d.off, m + n, &d.flags->round_total, p->ws, st);
-      launch_emit(d, p->rec_count, round, st);
+      launch_decide(d, p->rec_count, round, d.cnt, d.off, p->ws, st);
       HIPCHK(p, hipEventRecord(p->ev[6], st));
       e = queue_lp_read(p, true);
       if (e != PSL_OK) return e;
       int32_t removed = 0;
-      e = read_round(p, m, &removed);
+      e = read_round(p, &removed);
       if (e != PSL_OK) return e;
       long_ms += elapsed(p, 4, 7);
       sweep_ms += elapsed(p, 7, 5);
@@ -939,6 +942,10 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
           ++nprop;
         }
       }
+      if (p->trace)
+        std::fprintf(stderr, "[psl] round %d: swept rows %lld nnz %lld, records %d, rows removed %d, "
+                     "LPs propagating %d\n", round, (long long)p->cur.rows, (long long)p->cur.nnz,
+                     p->hflags->round_total, removed, nprop);
       if (nprop == 0) break;
       // keep the master lists on live rows once a sixteenth of them went (and
       // on live LPs)
@@ -954,21 +961,25 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
         }
         if (e != PSL_OK) return e;
       }
-      // Next round: rows none of whose columns changed since they were last
+      // Next round. Rows none of whose columns changed since they were last
       // swept give the same statistics and no qualifying candidate, so after
-      // a round with few column changes only the touched rows are swept.
+      // a round with few column changes only the touched rows are swept; and
+      // inert rows (their infinite-contribution counts, kept current as
+      // bounds become finite, rule out every outcome) are never swept.
+      // The counts are kept by decrements while few bounds become finite in a
+      // round. After a round with many, no decrement is made and the next
+      // round skips no row: it sweeps, and so recounts, every row one of whose
+      // bounds became finite (they are dirty), while the counts of the rows it
+      // does not sweep are still exact; after it the counts are exact again.
       int64_t changed_cols = (int64_t)p->hflags->round_total - removed;
       bool incremental = r + 1 < s.max_rounds && changed_cols * 8 < (int64_t)n;
-      if (incremental) {
-        if (!d.dirty || !d.colid) return fail(p, PSL_ERR_DEVICE, "internal: incremental state not set up");
-        mark_dirty(d, !was_incremental, st);
-        View sel;
-        e = filter_view(p, p->master, p->bins_s, p->chunks_s, true, sel);
-        if (e != PSL_OK) return e;
-        use_view(p, sel);
-      } else {
-        use_view(p, p->master);
-      }
+      bool counts = (int64_t)p->hflags->fin_cols * 16 < (int64_t)n;
+      if (!d.dirty || !d.colid) return fail(p, PSL_ERR_DEVICE, "internal: incremental state not set up");
+      mark_dirty(d, !was_incremental, incremental, counts, st);
+      View sel;
+      e = filter_view(p, p->master, p->bins_s, p->chunks_s, incremental, sel, counts);
+      if (e != PSL_OK) return e;
+      use_view(p, sel);
       was_incremental = incremental;
     }
     use_view(p, p->master);
@@ -1329,6 +1340,7 @@ extern "C" psl_status psl_batch_create(int32_t k, const psl_lp* lps, const psl_s
     p->thresholds[1] = s->bin_thresholds[1];
   }
   p->stream = (hipStream_t)s->stream;
+  if (const char* e = std::getenv("PSL_TRACE")) p->trace = std::atoi(e) != 0;
   p->cap_m = (int32_t)M;
   p->cap_n = (int32_t)Nc;
   p->cap_nnz = Z;

@@ -132,7 +132,8 @@ struct psl_presolver {
   double* hoff = nullptr;
 
   int state = 0;  // 0 loaded, 1 ran
-  int sweep_mode = MODE_ROUND;  // PSL_SWEEP_SPLIT=1: three launches by register class
+  int sweep_mode = MODE_ROUND;
+  bool trace = false;  // PSL_TRACE=1: one line per round on stderr  // PSL_SWEEP_SPLIT=1: three launches by register class
   psl_result result = PSL_RES_UNCHANGED;
   psl_stats stats{};
   double ms_ingest = 0.0;

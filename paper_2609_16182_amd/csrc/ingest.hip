@@ -241,16 +241,21 @@ struct BinOffsets {
 };
 
 // keep a bin entry (and the chunks of a long row) when its row is active, its
-// LP still presolving and, with a dirty array, touched by a column change
-// since it was last swept
+// LP still presolving, with a dirty array touched by a column change since it
+// was last swept, and with inert set not inert
+__device__ __forceinline__ bool keep_row(const Dev& d, int row, const uint8_t* dirty, bool inert) {
+  return d.row_on[row] != 0 && (!dirty || dirty[row]) && (d.K == 1 || d.lp_ok[d.row_lp[row]]) &&
+         (!inert || !row_inert(d.rinf[row], d.lhs[row], d.rhs[row]));
+}
+
 __global__ void k_rebin_flags(Dev d, const BinEnt* bins, int32_t nent, const LongChunk* chunks, int32_t nch,
-                              const uint8_t* dirty, int32_t* keep, int32_t* keep_len, int32_t* ckeep) {
+                              const uint8_t* dirty, int inert, int32_t* keep, int32_t* keep_len, int32_t* ckeep) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= nent; k += stride) {
     int f = 0, l = 0;
     if (k < nent) {
       BinEnt be = bins[k];
-      f = d.row_on[be.row] != 0 && (!dirty || dirty[be.row]) && (d.K == 1 || d.lp_ok[d.row_lp[be.row]]);
+      f = keep_row(d, be.row, dirty, inert != 0);
       l = f ? be.len : 0;
     }
     keep[k] = f;
@@ -260,7 +265,7 @@ __global__ void k_rebin_flags(Dev d, const BinEnt* bins, int32_t nent, const Lon
     int f = 0;
     if (c < nch) {
       int row = chunks[c].row;
-      f = d.row_on[row] != 0 && (!dirty || dirty[row]) && (d.K == 1 || d.lp_ok[d.row_lp[row]]);
+      f = keep_row(d, row, dirty, inert != 0);
     }
     ckeep[c] = f;
   }
@@ -283,7 +288,7 @@ __global__ void k_rebin_scatter(const BinEnt* bins, int32_t nent, const int32_t*
 }
 
 void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const LongChunk* chunks_in, int32_t nch,
-           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, int32_t* keep, int32_t* keep_len,
+           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, int32_t* keep, int32_t* keep_len,
            int32_t* ckeep, int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s) {
   BinOffsets bo;
   for (int b = 0; b <= NBINS; ++b) bo.off[b] = off_in[b];
@@ -292,7 +297,7 @@ void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const Lon
   int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_rebin_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, bins_in, nent, chunks_in, nch,
-                     (const uint8_t*)dirty, keep, keep_len, ckeep);
+                     (const uint8_t*)dirty, inert ? 1 : 0, keep, keep_len, ckeep);
   scan_excl(keep, keep, nent + 1, totals + 0, ws, s);
   scan_excl(keep_len, keep_len, nent + 1, totals + 1, ws, s);
   scan_excl(ckeep, ckeep, nch + 1, totals + 2, ws, s);
@@ -301,11 +306,92 @@ void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const Lon
                      dirty);
 }
 
-// rows of columns whose bounds changed (or that were fixed) this round
-__global__ void k_mark(Dev d) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < d.nnz; q += stride)
-    if (d.col_code[d.colid[q]] & (CC_LB | CC_UB | CC_FIX)) d.dirty[d.ri[q]] = 1;
+// Rows of the columns whose bounds changed (or that were fixed) this round,
+// from the transposed copy; their infinite-contribution counts follow the
+// bounds that became finite. One wavefront per 64 columns walks the entries of
+// its changed columns; columns of more than MARK_DENSE entries (listed once
+// at ingest) are walked by every workgroup of a second launch.
+#define MARK_DENSE 4096
+#define MARK_MASK (CC_LB | CC_UB | CC_FIX)
+
+// One entry (q, row i) of a changed column: mark the row (when the next
+// round sweeps dirty rows only), and (with count) lower its infinite-
+// contribution counts when the column's lb / ub became finite.
+__device__ __forceinline__ void mark_entry(const Dev& d, int64_t q, int code, bool mark, bool count) {
+  int i = d.ri[q];
+  if (mark) d.dirty[i] = 1;
+  if (count && (code & (CC_LBFIN | CC_UBFIN))) {
+    bool pos = d.cva[q] > 0;
+    bool lbf = (code & CC_LBFIN) != 0, ubf = (code & CC_UBFIN) != 0;
+    if ((lbf && pos) || (ubf && !pos)) atomicSub(&d.rinf[i].x, 1);  // min contribution now finite
+    if ((lbf && !pos) || (ubf && pos)) atomicSub(&d.rinf[i].y, 1);  // max contribution now finite
+  }
+}
+
+// columns the marking pass walks: changed ones when rows are marked, those
+// with a bound that became finite when counts are kept
+__device__ __forceinline__ bool mark_col(int code, int mode) {
+  return ((mode & 1) && (code & MARK_MASK)) || ((mode & 2) && (code & (CC_LBFIN | CC_UBFIN)));
+}
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_mark_sparse(Dev d, int mode) {
+  int64_t j = (int64_t)blockIdx.x * PSL_BLOCK + threadIdx.x;
+  bool ch = false;
+  int q0 = 0, q1 = 0, code = 0;
+  if (j < d.n) code = d.col_code[j];
+  if (mark_col(code, mode)) {
+    q0 = d.cp[j];
+    q1 = d.cp[j + 1];
+    ch = q1 - q0 <= MARK_DENSE;
+  }
+  unsigned long long mask = __ballot(ch);
+  int lane = lane_id();
+  while (mask) {
+    int l = __ffsll((long long)mask) - 1;
+    mask &= mask - 1;
+    int a = __shfl(q0, l, PSL_WAVE), b = __shfl(q1, l, PSL_WAVE), cl = __shfl(code, l, PSL_WAVE);
+    for (int q = a + lane; q < b; q += PSL_WAVE) mark_entry(d, q, cl, mode & 1, mode & 2);
+  }
+}
+
+// every workgroup lists the changed dense columns (in slices of 1024, checked
+// in parallel) and walks a grid-strided share of their entries
+__global__ void __launch_bounds__(PSL_BLOCK) k_mark_dense(Dev d, int mode) {
+  __shared__ int32_t list[1024];
+  __shared__ int32_t cnt;
+  int nd = *d.n_dense;
+  for (int k0 = 0; k0 < nd; k0 += 1024) {
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int k = k0 + threadIdx.x; k < nd && k < k0 + 1024; k += PSL_BLOCK) {
+      int j = d.dense_cols[k];
+      if (mark_col(d.col_code[j], mode)) list[atomicAdd(&cnt, 1)] = j;
+    }
+    __syncthreads();
+    int nc = cnt;
+    for (int c = 0; c < nc; ++c) {
+      int j = list[c];
+      int code = d.col_code[j];
+      int64_t q1 = d.cp[j + 1];
+      for (int64_t q = d.cp[j] + (int64_t)blockIdx.x * PSL_BLOCK + threadIdx.x; q < q1;
+           q += (int64_t)gridDim.x * PSL_BLOCK)
+        mark_entry(d, q, code, mode & 1, mode & 2);
+    }
+    __syncthreads();
+  }
+}
+
+// the columns of more than MARK_DENSE entries (order irrelevant)
+__global__ void k_dense_cols(Dev d) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d.n) return;
+  if (d.cp[j + 1] - d.cp[j] > MARK_DENSE) d.dense_cols[atomicAdd(d.n_dense, 1)] = (int32_t)j;
+}
+
+void list_dense_cols(const Dev& d, hipStream_t s) {
+  fill_i32(d.n_dense, 0, 1, s);
+  if (d.n > 0)
+    hipLaunchKernelGGL(k_dense_cols, dim3((unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d);
 }
 
 __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
@@ -313,15 +399,17 @@ __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
     p[i] = v;
 }
 
-void mark_dirty(const Dev& d, bool clear_first, hipStream_t s) {
-  if (clear_first && d.m > 0) {
+void mark_dirty(const Dev& d, bool clear_first, bool mark, bool count, hipStream_t s) {
+  if (mark && clear_first && d.m > 0) {
     int64_t b = (d.m + PSL_BLOCK - 1) / PSL_BLOCK;
     hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(PSL_BLOCK), 0, s, d.dirty, (uint8_t)0,
                        (int64_t)d.m);
   }
-  if (d.nnz == 0) return;
-  int64_t b = (d.nnz + PSL_BLOCK - 1) / PSL_BLOCK;
-  hipLaunchKernelGGL(k_mark, dim3((unsigned)(b > 16384 ? 16384 : b)), dim3(PSL_BLOCK), 0, s, d);
+  int mode = (mark ? 1 : 0) | (count ? 2 : 0);
+  if (d.nnz == 0 || d.n == 0 || mode == 0) return;
+  hipLaunchKernelGGL(k_mark_sparse, dim3((unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d,
+                     mode);
+  hipLaunchKernelGGL(k_mark_dense, dim3(1024), dim3(PSL_BLOCK), 0, s, d, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -335,6 +423,7 @@ __global__ void k_init_state(Dev d) {
   }
   if (t < d.n) {
     double2 b = d.bnd[t];
+    d.touch[t] = 1;  // the first round decides every column
     d.bkey[2 * t] = dkey(b.x);
     d.bkey[2 * t + 1] = dkey(b.y);
     d.src[2 * t] = 0x7FFFFFFF;
@@ -344,7 +433,8 @@ __global__ void k_init_state(Dev d) {
   if (t == 0) {
     Flags f;
     f.infeasible = f.unbounded = f.error = f.merged = 0;
-    f.cand_count = f.round_total = f.vlist_count = f.pad = 0;
+    f.cand_count = f.round_total = f.vlist_count = f.rows_removed = 0;
+    f.fin_cols = f.pad2 = 0;
     f.error_pos = 0x7FFFFFFFFFFFFFFFLL;
     *d.flags = f;
   }

@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_drop(Dev d, ParScratch P) {
     for (int p = d.rp[r] + lane_id(); p < d.rp[r + 1]; p += PSL_WAVE) {
       int j = d.ci[p];
       double2 b = d.bnd[j];
-      if (b.x != b.y) atomicSub(&d.col_len[j], 1);
+      if (b.x != b.y) drop_col(d, j);
     }
   }
 }

@@ -9,30 +9,6 @@ namespace psl {
 #define SCAN_ITEMS 8
 #define SCAN_TILE (PSL_BLOCK * SCAN_ITEMS)
 
-// exclusive scan of one int per thread across the 256-thread block
-__device__ __forceinline__ int block_excl_scan(int v, int* total) {
-  __shared__ int wsum[PSL_BLOCK / PSL_WAVE];
-  int lane = lane_id(), w = threadIdx.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < PSL_WAVE; o <<= 1) {
-    int y = __shfl_up(x, o, PSL_WAVE);
-    if (lane >= o) x += y;
-  }
-  if (lane == PSL_WAVE - 1) wsum[w] = x;
-  __syncthreads();
-  int pre = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < PSL_BLOCK / PSL_WAVE; ++k) {
-    int s = wsum[k];
-    if (k < w) pre += s;
-    tot += s;
-  }
-  __syncthreads();
-  *total = tot;
-  return pre + x - v;
-}
-
 __global__ void __launch_bounds__(PSL_BLOCK) k_scan_tile_sums(const int32_t* in, int64_t n, int32_t* sums) {
   int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int s = 0;

@@ -30,7 +30,8 @@ enum : uint8_t { RC_KEEP = 0, RC_EMPTY = 1, RC_REDUNDANT = 2, RC_SINGLETON = 3 }
 
 // column decision bits of a round
 enum : uint8_t {
-  CC_LB = 1, CC_UB = 2, CC_FIX = 4, CC_EMPTY = 8, CC_UNBOUNDED = 16, CC_INFEAS = 32
+  CC_LB = 1, CC_UB = 2, CC_FIX = 4, CC_EMPTY = 8, CC_UNBOUNDED = 16, CC_INFEAS = 32,
+  CC_LBFIN = 64, CC_UBFIN = 128  // set at emission: lb (ub) went from infinite to finite
 };
 
 // row length bins: rows of <= 4 / <= 16 entries by 4- / 16-lane groups, rows
@@ -57,7 +58,7 @@ struct RowOut {      // what the sweep leaves for a removed row's record
 
 struct Cand {        // a candidate bound that may be the round's final value
   int32_t js;        // 2*j + side (side 1 = upper)
-  int32_t row;
+  int32_t pos;       // CSR position of the entry (its row and coefficient)
   double t;
 };
 
@@ -93,13 +94,14 @@ struct LpFlags {     // per LP, cleared before every round
   int32_t infeasible, unbounded, merged, pad;
 };
 
-struct LpOut {       // per LP records of the last round, and row records among them
-  int32_t total, rows;
+struct LpOut {       // per LP: nonzero when the last round gave it records (cleared per round)
+  int32_t total, pad;
 };
 
 struct Flags {
   int32_t infeasible, unbounded, error, merged;
-  int32_t cand_count, round_total, vlist_count, pad;
+  int32_t cand_count, round_total, vlist_count, rows_removed;
+  int32_t fin_cols, pad2;  // columns of the round with a bound that became finite
   int64_t error_pos;
 };
 
@@ -128,6 +130,12 @@ struct Dev {
   int32_t *col_len;
   uint8_t *row_on, *row_code, *col_code;
   uint8_t *dirty;          // rows touched by a column change since last swept
+  const int32_t *rowid1;   // row of CSR position p at index p + 1 (built at ingest)
+  int2 *rinf;              // per row: infinite min / max contributions at its last
+                           // sweep, lowered as bounds of its columns become finite
+  int32_t *dense_cols;     // columns of more than 4096 entries (listed at ingest)
+  int32_t *n_dense;
+  uint8_t *touch;          // columns whose decision may change this round
   const uint32_t *colid;   // column of each position of the transposed copy
   RowOut *row_out;
   Cand *cand;
@@ -157,6 +165,12 @@ __device__ __forceinline__ int row_lp_of(const Dev& d, int i) { return d.K > 1 ?
 __device__ __forceinline__ int col_lp_of(const Dev& d, int j) { return d.K > 1 ? d.col_lp[j] : 0; }
 // round number written into a record of LP lp
 __device__ __forceinline__ int round_of(const Dev& d, int lp, int round) { return d.K > 1 ? d.lp_round[lp] : round; }
+// a row removal takes column j out of that row; a column left in no row is
+// decided this round
+__device__ __forceinline__ void drop_col(const Dev& d, int j) {
+  if (atomicSub(&d.col_len[j], 1) == 1) d.touch[j] = 1;
+}
+
 __device__ __forceinline__ void flag_infeasible(const Dev& d, int lp) {
   atomicOr(&d.flags->infeasible, 1);
   if (d.K > 1) atomicOr(&d.lpf[lp].infeasible, 1);
@@ -176,6 +190,17 @@ __device__ __forceinline__ double mx1(double x) {
   return a > 1.0 ? a : 1.0;
 }
 __device__ __forceinline__ bool is_inf(double x) { return __builtin_isinf(x); }
+
+// A row whose every finite side has at least two infinite contributions on
+// the side's residual, and that cannot be redundant, gives no candidate, no
+// removal and no infeasibility: sweeping it changes nothing.
+__device__ __forceinline__ bool row_inert(int2 c, double lhs, double rhs) {
+  bool lo_inf = is_inf(lhs), up_inf = is_inf(rhs);
+  bool prop = (!up_inf && c.x <= 1) || (!lo_inf && c.y <= 1);
+  bool redundant_possible = (lo_inf || c.x == 0) && (up_inf || c.y == 0);
+  return !prop && !redundant_possible;
+}
+
 __device__ __forceinline__ double tol_of(const Cfg& c, double x) { return c.feas_tol * mx1(x); }
 
 // order-preserving map double <-> int64 (an involution); -0 never occurs
@@ -285,5 +310,30 @@ __device__ __forceinline__ unsigned long long quantize(double v) {
   unsigned long long mag = b & 0x7FFFFFFFFFFFFFFFULL;
   return ((mag + (1ULL << 19)) >> 20) | (sign << 63);
 }
+
+// exclusive scan of one int per thread across the 256-thread block
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+  __shared__ int wsum[PSL_BLOCK / PSL_WAVE];
+  int lane = lane_id(), w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < PSL_WAVE; o <<= 1) {
+    int y = __shfl_up(x, o, PSL_WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == PSL_WAVE - 1) wsum[w] = x;
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < PSL_BLOCK / PSL_WAVE; ++k) {
+    int s = wsum[k];
+    if (k < w) pre += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
 
 }  // namespace psl

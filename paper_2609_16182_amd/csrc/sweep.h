@@ -27,8 +27,10 @@ __host__ __device__ __forceinline__ int64_t cand_region_start(const SweepGrid& g
 void launch_long_stats(const Dev& d, int mode, hipStream_t s);
 void launch_sweep(const Dev& d, const SweepGrid& g, int mode, hipStream_t s);
 void launch_src(const Dev& d, const SweepGrid& g, hipStream_t s);
-void launch_count(const Dev& d, hipStream_t s);
-void launch_emit(const Dev& d, int64_t base, int round, hipStream_t s);
+// decisions, counts and records of a round (tile_sum / tile_off: one int per
+// 2048 rows and columns, ws: scan workspace)
+void launch_decide(const Dev& d, int64_t base, int round, int32_t* tile_sum, int32_t* tile_off, int32_t* ws,
+                   hipStream_t s);
 int long_max_passes();
 
 // ingest.hip
@@ -50,14 +52,18 @@ const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, i
 void build_bins(const Dev& d, const int32_t* thresholds, BinEnt* bins, int32_t* counts, IngestScratch& sc,
                 hipStream_t s);
 // keep the active rows (and, with dirty != nullptr, only the dirty ones,
-// whose flags are then cleared) of a bin list and chunk list: new_off
-// [0..NBINS], totals = {kept rows, their nonzeros, kept chunks} (device)
+// whose flags are then cleared; with inert, only rows that are not inert) of
+// a bin list and chunk list: new_off [0..NBINS], totals = {kept rows, their
+// nonzeros, kept chunks} (device)
 void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const LongChunk* chunks_in, int32_t nch,
-           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, int32_t* keep, int32_t* keep_len,
+           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, int32_t* keep, int32_t* keep_len,
            int32_t* ckeep, int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s);
-// mark the rows of the columns changed in the last round (optionally clearing
-// all marks first)
-void mark_dirty(const Dev& d, bool clear_first, hipStream_t s);
+// after a round: with count, lower the infinite-contribution counts of the
+// rows of columns whose bounds became finite; with mark, mark the rows of the
+// changed columns dirty (clearing all marks first with clear_first)
+void mark_dirty(const Dev& d, bool clear_first, bool mark, bool count, hipStream_t s);
+// d.dense_cols / d.n_dense from the transposed copy (after build_csc)
+void list_dense_cols(const Dev& d, hipStream_t s);
 // chunk table of the long rows (d.nlong set); total chunks to *total (device)
 // totals[0] = chunks, totals[1] = candidate units of all chunks
 void build_long_chunks(const Dev& d, int npass0, LongChunk* chunks, int32_t* cnt, int32_t* cnt2, int32_t* totals,
@@ -136,8 +142,6 @@ void batch_gather(const Dev& d, const LpDesc* desc, const int64_t* z0, int32_t* 
                   hipStream_t s);
 // row -> LP and column -> LP maps from d.lp_row0 / d.lp_col0
 void batch_maps(const Dev& d, int32_t* row_lp, int32_t* col_lp, hipStream_t s);
-// d.lpo from the last scan of record counts (rows only, or rows and columns)
-void launch_lp_totals(const Dev& d, bool cols, hipStream_t s);
 // stable split of the records by LP, renumbered per LP (K > 1); scratch of
 // count entries each, ws: rec_split_ws_ints(count)
 size_t rec_split_ws_ints(int64_t count);

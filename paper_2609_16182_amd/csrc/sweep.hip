@@ -130,7 +130,12 @@ __device__ __forceinline__ RowDec decide_row(const Cfg& c, double lhs, double rh
   if ((nmin == 0 && !is_inf(rhs) && minact > rhs + tol_of(c, rhs)) ||
       (nmax == 0 && !is_inf(lhs) && maxact < lhs - tol_of(c, lhs)))
     r.infeasible = true;
-  r.prop = true;
+  // A side gives an entry a bound only when the residual activity on that side
+  // is finite, i.e. with at most one infinite contribution (the entry's own);
+  // with none on either side the row yields no candidate and is not re-read.
+  // (A row with one active column has at most one infinite contribution per
+  // side, so it always propagates on its finite sides.)
+  r.prop = (!is_inf(rhs) && nmin <= 1) || (!is_inf(lhs) && nmax <= 1);
   r.single = (L == 1);
   return r;
 }
@@ -217,7 +222,7 @@ struct CandSink {  // this workgroup's candidate region and its LDS counter
 // is not better than the value read cannot be the final one unless equal, so
 // only candidates <= (>=) the current value go to the source list.
 // Must be reached by every lane of the wavefront.
-__device__ __forceinline__ void commit_cands(const Dev& d, const CandSink& sk, int row, int j, bool hlo, double tlo,
+__device__ __forceinline__ void commit_cands(const Dev& d, const CandSink& sk, int pos, int j, bool hlo, double tlo,
                                              bool hup, double tup) {
   bool alo = false, aup = false;
   if (hlo) {
@@ -236,8 +241,8 @@ __device__ __forceinline__ void commit_cands(const Dev& d, const CandSink& sk, i
       if (tup < cur) atomicMin(k, dkey(tup));
     }
   }
-  wave_append(alo, Cand{2 * j, row, tlo}, sk.list, sk.counter);
-  wave_append(aup, Cand{2 * j + 1, row, tup}, sk.list, sk.counter);
+  wave_append(alo, Cand{2 * j, pos, tlo}, sk.list, sk.counter);
+  wave_append(aup, Cand{2 * j + 1, pos, tup}, sk.list, sk.counter);
 }
 
 __device__ __forceinline__ RowOut row_out_of(uint8_t code, const RowStat& st) {
@@ -257,7 +262,7 @@ __device__ __forceinline__ RowOut row_out_of(uint8_t code, const RowStat& st) {
 // propagate the C register-held elements of a lane; tracks the one active
 // element of a row with L == 1 and whether some entry left a side unbounded
 template <int C>
-__device__ __forceinline__ void lane_prop(const Dev& d, const CandSink& sk, int row, bool prop, const El (&e)[C],
+__device__ __forceinline__ void lane_prop(const Dev& d, const CandSink& sk, int64_t p0, bool prop, const El (&e)[C],
                                           double lhs, double rhs,
                                           const RowStat& st, bool single, bool& uncap, bool& mine, int& aj,
                                           double& aa) {
@@ -267,7 +272,7 @@ __device__ __forceinline__ void lane_prop(const Dev& d, const CandSink& sk, int 
     bool cap, hlo, hup;
     double tlo, tup;
     prop_el(d.cfg, act, e[k], lhs, rhs, st, single, cap, hlo, tlo, hup, tup);
-    commit_cands(d, sk, row, e[k].j, hlo, tlo, hup, tup);
+    commit_cands(d, sk, (int)(p0 + k), e[k].j, hlo, tlo, hup, tup);
     if (act && !cap) uncap = true;
     if (act) {
       mine = true;
@@ -291,7 +296,7 @@ __device__ __forceinline__ void lane_prop_stream(const Dev& d, const CandSink& s
     bool cap, hlo, hup;
     double tlo, tup;
     prop_el(d.cfg, act, e, lhs, rhs, st, single, cap, hlo, tlo, hup, tup);
-    commit_cands(d, sk, row, e.j, hlo, tlo, hup, tup);
+    commit_cands(d, sk, (int)(s0 + base + k), e.j, hlo, tlo, hup, tup);
     if (act && !cap) uncap = true;
     if (act) {
       mine = true;
@@ -307,7 +312,7 @@ __device__ __forceinline__ void lane_drop_stream(const Dev& d, bool on, int64_t 
   for (int k = 0; k < C; ++k) {
     El e;
     load_el(d, s0 + base + k, on && base + k < len, e);
-    if (el_active(e)) atomicSub(&d.col_len[e.j], 1);
+    if (el_active(e)) drop_col(d, e.j);
   }
 }
 
@@ -315,7 +320,7 @@ template <int C>
 __device__ __forceinline__ void lane_drop(const Dev& d, const El (&e)[C]) {
 #pragma unroll
   for (int k = 0; k < C; ++k)
-    if (el_active(e[k])) atomicSub(&d.col_len[e[k].j], 1);
+    if (el_active(e[k])) drop_col(d, e[k].j);
 }
 
 // ---------------------------------------------------------------------------
@@ -362,13 +367,14 @@ __device__ __forceinline__ void sweep_rows(const Dev& d, const CandSink& sk, int
   if (live) {
     lhs = d.lhs[row];
     rhs = d.rhs[row];
+    if (gl == 0) d.rinf[row] = make_int2(st.nmin, st.nmax);
   }
   RowDec dec = decide_row(d.cfg, lhs, rhs, L, st.nmin, st.nmax, st.minact, st.maxact);
   bool prop = live && dec.prop;
   bool uncap = false, mine = false;
   int aj = 0;
   double aa = 0.0;
-  if (C == 1) lane_prop<C>(d, sk, row, prop, e, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
+  if (C == 1) lane_prop<C>(d, sk, s0 + gl * C, prop, e, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
   else  // reload (L1/L2 hits) instead of keeping C elements live through the sums
     lane_prop_stream<C>(d, sk, row, prop, s0, len, gl * C, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
   bool captured = (__ballot(uncap) & group_mask<G>()) == 0;
@@ -382,7 +388,7 @@ __device__ __forceinline__ void sweep_rows(const Dev& d, const CandSink& sk, int
   if (live && gl == 0 && (code == RC_EMPTY || code == RC_REDUNDANT)) d.row_out[row] = row_out_of(code, st);
   if (code == RC_SINGLETON && mine) {
     d.row_out[row] = RowOut{aa, 0.0, aj, 0};
-    atomicSub(&d.col_len[aj], 1);
+    drop_col(d, aj);
   }
   if (code == RC_REDUNDANT) {
     if (C == 1) lane_drop<C>(d, e);
@@ -518,6 +524,7 @@ __device__ __forceinline__ void sweep_long_chunk(const Dev& d, const CandSink& s
   int len = d.rp[row + 1] - (int)s0;
   double lhs = d.lhs[row], rhs = d.rhs[row];
   RowDec dec = decide_row(d.cfg, lhs, rhs, L, st.nmin, st.nmax, st.minact, st.maxact);
+  if (ch.first == 0 && threadIdx.x == 0) d.rinf[row] = make_int2(st.nmin, st.nmax);
   bool uncap = false, mine = false;
   int aj = 0;
   double aa = 0.0;
@@ -532,7 +539,7 @@ __device__ __forceinline__ void sweep_long_chunk(const Dev& d, const CandSink& s
       if (!uncap) {
         d.row_code[row] = RC_SINGLETON;
         d.row_out[row] = RowOut{aa, 0.0, aj, 0};
-        atomicSub(&d.col_len[aj], 1);
+        drop_col(d, aj);
       } else {
         d.row_code[row] = RC_KEEP;
       }
@@ -636,7 +643,8 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_src(Dev d, SweepGrid g) {
   const Cand* list = d.cand + start;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     Cand c = list[i];
-    if (c.t == dunkey(d.bkey[c.js])) atomicMin(&d.src[c.js], c.row);
+    d.touch[c.js >> 1] = 1;
+    if (c.t == dunkey(d.bkey[c.js])) atomicMin(&d.src[c.js], c.pos);
   }
 }
 
@@ -649,25 +657,15 @@ __device__ __forceinline__ double empty_value(double c, double lo, double up) {
   return lo > 0 ? lo : (up < 0 ? up : 0.0);
 }
 
-__global__ void k_count(Dev d) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t m = d.m, n = d.n;
-  if (t < m) {
-    d.cnt[t] = d.row_code[t] != RC_KEEP;
-    return;
-  }
-  if (t >= m + n) return;
-  int j = (int)(t - m);
+// decision of an active or removed column from the round's accumulators:
+// code bits, and the number of records it gives
+__device__ __forceinline__ uint8_t col_decide(const Dev& d, int j, int& k) {
+  k = 0;
   double2 b = d.bnd[j];
-  if (b.x == b.y) {
-    d.col_code[j] = 0;
-    d.cnt[t] = 0;
-    return;
-  }
+  if (b.x == b.y) return 0;
   double lo = dunkey(d.bkey[2 * (int64_t)j]);
   double up = dunkey(d.bkey[2 * (int64_t)j + 1]);
   uint8_t code = 0;
-  int k = 0;
   if (lo != b.x) {
     code |= CC_LB;
     ++k;
@@ -690,22 +688,56 @@ __global__ void k_count(Dev d) {
       ++k;
     }
   }
-  d.col_code[j] = code;
-  d.cnt[t] = k;
   if (code & CC_INFEAS) flag_infeasible(d, col_lp_of(d, j));
   if (code & CC_UNBOUNDED) flag_unbounded(d, col_lp_of(d, j));
+  return code;
 }
 
-__device__ __forceinline__ double coef_in_row(const Dev& d, int row, int j) {
-  if (row < 0 || row >= d.m) return __builtin_nan("");  // never taken: a changed bound has a source row
-  int lo = d.rp[row], hi = d.rp[row + 1] - 1;
-  if (hi < lo) return __builtin_nan("");
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (d.ci[mid] < j) lo = mid + 1;
-    else hi = mid;
+// records of index t of the round's index space (rows, then columns), from
+// the codes written by the sweep and by k_decide_count
+__device__ __forceinline__ int rec_count_of(const Dev& d, int64_t t) {
+  if (t < d.m) return d.row_code[t] != RC_KEEP;
+  uint8_t code = d.col_code[t - d.m];
+  return (code & CC_LB ? 1 : 0) + (code & CC_UB ? 1 : 0) + (code & (CC_FIX | CC_EMPTY) ? 1 : 0);
+}
+
+// one index per thread: the record stores of a wavefront stay contiguous and
+// the column decisions' loads overlap across lanes
+#define DEC_ITEMS 1
+#define DEC_TILE (PSL_BLOCK * DEC_ITEMS)
+
+// Column decisions of the touched columns (untouched ones cannot change: an
+// active column with unchanged bounds and rows is neither fixed nor empty),
+// and the record count of each tile of DEC_TILE indices.
+__global__ void __launch_bounds__(PSL_BLOCK) k_decide_count(Dev d, int32_t* tile_sum) {
+  int64_t m = d.m, span = m + d.n;
+  int64_t t0 = (int64_t)blockIdx.x * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < DEC_ITEMS; ++k) {
+    int64_t t = t0 + k;
+    if (t >= span) break;
+    if (t < m) {
+      c += d.row_code[t] != RC_KEEP;
+      continue;
+    }
+    int j = (int)(t - m);
+    if (!d.touch[j]) {
+      if (d.col_code[j]) d.col_code[j] = 0;
+      continue;
+    }
+    d.touch[j] = 0;
+    int kk;
+    d.col_code[j] = col_decide(d, j, kk);
+    c += kk;
   }
-  return d.va[lo];
+  int tot;
+  block_excl_scan(c, &tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    d.flags->rows_removed = 0;
+    d.flags->fin_cols = 0;
+  }
 }
 
 __device__ __forceinline__ Record mkrec(uint8_t type, uint8_t side, int round, int i, int j, int k, double v0,
@@ -724,39 +756,36 @@ __device__ __forceinline__ Record mkrec(uint8_t type, uint8_t side, int round, i
   return r;
 }
 
-__global__ void k_emit(Dev d, int64_t base, int round) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t m = d.m, n = d.n;
-  if (t < m) {
-    uint8_t code = d.row_code[t];
-    if (code == RC_KEEP) return;
-    int i = (int)t;
-    round = round_of(d, row_lp_of(d, i), round);
-    RowOut o = d.row_out[i];
-    Record* r = d.rec + base + d.off[t];
-    if (code == RC_EMPTY) *r = mkrec(REC_EMPTY_ROW, 0, round, i, -1, -1, o.v0, d.lhs[i], d.rhs[i], 0.0);
-    else if (code == RC_REDUNDANT) *r = mkrec(REC_REDUNDANT_ROW, 0, round, i, -1, -1, o.v0, o.v1, d.lhs[i], d.rhs[i]);
-    else *r = mkrec(REC_SINGLETON_ROW, 0, round, i, o.j, -1, o.v0, d.lhs[i], d.rhs[i], 0.0);
-    d.row_on[i] = 0;
-    d.row_code[i] = RC_KEEP;
-    return;
-  }
-  if (t >= m + n) return;
-  int j = (int)(t - m);
+__device__ __forceinline__ void emit_row(const Dev& d, int i, int round, Record* r) {
+  uint8_t code = d.row_code[i];
+  RowOut o = d.row_out[i];
+  if (code == RC_EMPTY) *r = mkrec(REC_EMPTY_ROW, 0, round, i, -1, -1, o.v0, d.lhs[i], d.rhs[i], 0.0);
+  else if (code == RC_REDUNDANT) *r = mkrec(REC_REDUNDANT_ROW, 0, round, i, -1, -1, o.v0, o.v1, d.lhs[i], d.rhs[i]);
+  else *r = mkrec(REC_SINGLETON_ROW, 0, round, i, o.j, -1, o.v0, d.lhs[i], d.rhs[i], 0.0);
+  d.row_on[i] = 0;
+  d.row_code[i] = RC_KEEP;
+}
+
+// returns 1 when a bound of the column became finite
+__device__ __forceinline__ int emit_col(const Dev& d, int j, int round, Record* r) {
   uint8_t code = d.col_code[j];
-  if (code == 0) return;
-  round = round_of(d, col_lp_of(d, j), round);
   double2 b = d.bnd[j];
   double lo = dunkey(d.bkey[2 * (int64_t)j]);
   double up = dunkey(d.bkey[2 * (int64_t)j + 1]);
-  Record* r = d.rec + base + d.off[t];
+  // the source of a changed bound is the CSR position of the lowest row's
+  // candidate equal to it (positions of one column ascend with the row); a
+  // changed bound always has one
   if (code & CC_LB) {
-    int s = d.src[2 * (int64_t)j];
-    *r++ = mkrec(REC_BOUND_CHANGE, 0, round, -1, j, s, b.x, lo, coef_in_row(d, s, j), 0.0);
+    int q = d.src[2 * (int64_t)j];
+    bool ok = q >= 0 && q < d.nnz;
+    *r++ = mkrec(REC_BOUND_CHANGE, 0, round, -1, j, ok ? d.rowid1[q + 1] : -1, b.x, lo,
+                 ok ? d.va[q] : __builtin_nan(""), 0.0);
   }
   if (code & CC_UB) {
-    int s = d.src[2 * (int64_t)j + 1];
-    *r++ = mkrec(REC_BOUND_CHANGE, 1, round, -1, j, s, b.y, up, coef_in_row(d, s, j), 0.0);
+    int q = d.src[2 * (int64_t)j + 1];
+    bool ok = q >= 0 && q < d.nnz;
+    *r++ = mkrec(REC_BOUND_CHANGE, 1, round, -1, j, ok ? d.rowid1[q + 1] : -1, b.y, up,
+                 ok ? d.va[q] : __builtin_nan(""), 0.0);
   }
   double nlo = lo, nup = up;
   if (code & CC_FIX) {
@@ -767,11 +796,63 @@ __global__ void k_emit(Dev d, int64_t base, int round) {
     *r++ = mkrec(REC_EMPTY_COL, 0, round, -1, j, -1, v, d.c[j], 0.0, 0.0);
     nlo = nup = v;
   }
+  // bounds that became finite lower the infinite-contribution counts of
+  // the column's rows (applied by the marking pass)
+  uint8_t fin = (is_inf(b.x) && !is_inf(nlo) ? CC_LBFIN : 0) | (is_inf(b.y) && !is_inf(nup) ? CC_UBFIN : 0);
+  if (fin) d.col_code[j] = code | fin;
   d.bnd[j] = make_double2(nlo, nup);
   d.bkey[2 * (int64_t)j] = dkey(nlo);
   d.bkey[2 * (int64_t)j + 1] = dkey(nup);
   d.src[2 * (int64_t)j] = 0x7FFFFFFF;
   d.src[2 * (int64_t)j + 1] = 0x7FFFFFFF;
+  return fin ? 1 : 0;
+}
+
+// Records of the round in index order: each tile's offset comes from the
+// scanned tile sums, positions inside the tile from a block scan of the
+// counts. Also counts the removed rows and (batches) marks the LPs that
+// changed.
+__global__ void __launch_bounds__(PSL_BLOCK) k_decide_emit(Dev d, const int32_t* tile_off, int64_t base, int round) {
+  int64_t m = d.m, span = m + d.n;
+  int64_t t0 = (int64_t)blockIdx.x * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
+  int cnt[DEC_ITEMS];
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < DEC_ITEMS; ++k) {
+    int64_t t = t0 + k;
+    cnt[k] = t < span ? rec_count_of(d, t) : 0;
+    c += cnt[k];
+  }
+  int tot;
+  int pre = block_excl_scan(c, &tot);
+  if (tot == 0) return;
+  // removed rows of the tile: one atomic per workgroup
+  int nrow = 0;
+#pragma unroll
+  for (int k = 0; k < DEC_ITEMS; ++k) nrow += (t0 + k < m) ? cnt[k] : 0;
+  int rtot;
+  block_excl_scan(nrow, &rtot);
+  if (rtot && threadIdx.x == 0) atomicAdd(&d.flags->rows_removed, rtot);
+  Record* r = d.rec + base + tile_off[blockIdx.x] + pre;
+  int fin = 0;
+#pragma unroll
+  for (int k = 0; k < DEC_ITEMS; ++k) {
+    if (!cnt[k]) continue;
+    int64_t t = t0 + k;
+    int lp;
+    if (t < m) {
+      lp = row_lp_of(d, (int)t);
+      emit_row(d, (int)t, round_of(d, lp, round), r);
+    } else {
+      lp = col_lp_of(d, (int)(t - m));
+      fin += emit_col(d, (int)(t - m), round_of(d, lp, round), r);
+    }
+    if (d.K > 1) d.lpo[lp].total = 1;  // the LP changed this round
+    r += cnt[k];
+  }
+  int ftot;
+  block_excl_scan(fin, &ftot);
+  if (ftot && threadIdx.x == 0) atomicAdd(&d.flags->fin_cols, ftot);
 }
 
 // ---------------------------------------------------------------------------
@@ -813,18 +894,21 @@ void launch_src(const Dev& d, const SweepGrid& g, hipStream_t s) {
   if (total > 0) hipLaunchKernelGGL(k_src, dim3(total), dim3(PSL_BLOCK), 0, s, d, g);
 }
 
-void launch_count(const Dev& d, hipStream_t s) {
-  int64_t t = (int64_t)d.m + d.n;
-  unsigned blocks = (unsigned)((t + PSL_BLOCK - 1) / PSL_BLOCK);
-  if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(k_count, dim3(blocks), dim3(PSL_BLOCK), 0, s, d);
-}
-
-void launch_emit(const Dev& d, int64_t base, int round, hipStream_t s) {
-  int64_t t = (int64_t)d.m + d.n;
-  if (t == 0) return;
-  unsigned blocks = (unsigned)((t + PSL_BLOCK - 1) / PSL_BLOCK);
-  hipLaunchKernelGGL(k_emit, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, base, round);
+// the round's decisions and records: counts per tile, scan, emission; the
+// record total goes to d.flags->round_total
+void launch_decide(const Dev& d, int64_t base, int round, int32_t* tile_sum, int32_t* tile_off, int32_t* ws,
+                   hipStream_t s) {
+  int64_t span = (int64_t)d.m + d.n;
+  int64_t tiles = (span + DEC_TILE - 1) / DEC_TILE;
+  if (tiles == 0) {
+    fill_i32(&d.flags->round_total, 0, 1, s);
+    fill_i32(&d.flags->rows_removed, 0, 1, s);
+    return;
+  }
+  hipLaunchKernelGGL(k_decide_count, dim3((unsigned)tiles), dim3(PSL_BLOCK), 0, s, d, tile_sum);
+  scan_excl(tile_sum, tile_off, tiles, &d.flags->round_total, ws, s);
+  hipLaunchKernelGGL(k_decide_emit, dim3((unsigned)tiles), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)tile_off, base,
+                     round);
 }
 
 int long_max_passes() { return LONG_MAX_PASSES; }

@@ -33,3 +33,75 @@ def test_power_law_full_size():
     x0 = lp["x0"][r["col_map"]]
     sc = np.maximum(1.0, np.abs(x0))
     assert np.all(x0 >= r["lb"] - 1e-9 * sc) and np.all(x0 <= r["ub"] + 1e-9 * sc)
+
+
+def _load_digests(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated (tests/golden/make_digests.py)")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.timeout(900)
+def test_large_full_size_digest():
+    """The large LP (m = 1e7, n = 1.5e7, ~9.7e7 nnz with 20 dense rows of 1e6
+    entries and 20 dense columns of 1e5, planted chains): outcome, record
+    stream and reduced problem equal the oracle's bit for bit, compared
+    through SHA-256 digests written by tests/golden/make_digests.py (the oracle
+    needs minutes at this size)."""
+    from tests.golden.digest import digest_of
+    ref = _load_digests("large_1e7_digest.json")
+    t0 = time.time()
+    lp = lpgen.large(seed=2, scale=1.0)
+    print(f"generated nnz={lpgen.nnz(lp)} in {time.time() - t0:.1f}s", flush=True)
+    assert (lp["m"], lp["n"], lpgen.nnz(lp)) == (ref["m"], ref["n"], ref["nnz"])
+    got, p = psl.presolve(lp)
+    print(f"gpu stats {got['stats']}", flush=True)
+    p.close()
+    assert got["stats"]["rounds"] == ref["rounds"]
+    dg = digest_of(got["result_name"], got["records"], got["reduced"])
+    for key in ("result_name", "records", "records_sha256"):
+        assert dg[key] == ref[key], key
+    for key, v in ref["reduced"].items():
+        assert dg["reduced"][key] == v, key
+    # the chains need at least 5 Jacobi rounds
+    assert ref["rounds"] >= 5
+    r = got["reduced"]
+    x0 = lp["x0"][r["col_map"]]
+    sc = np.maximum(1.0, np.abs(x0))
+    assert np.all(x0 >= r["lb"] - 1e-9 * sc) and np.all(x0 <= r["ub"] + 1e-9 * sc)
+
+
+@pytest.mark.timeout(600)
+def test_batch_4096_digests():
+    """All 4096 LPs of the batched workload, presolved in one batch from
+    device-resident inputs, in the benchmark's launch configuration: each
+    LP's result equals the oracle's (digests by tests/golden/make_digests.py)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import os
+
+    import torch
+    from tests.golden.digest import lp_digest
+    ref = _load_digests("batch_4096_digests.json")
+    with ProcessPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        lps = list(ex.map(lpgen.batch_member, range(4096), chunksize=64))
+    keys = ("row_ptr", "col_idx", "val", "lhs", "rhs", "lb", "ub", "c")
+    dev = []
+    for lp in lps:
+        d = {k: torch.from_numpy(np.ascontiguousarray(lp[k])).cuda() for k in keys}
+        d.update(m=lp["m"], n=lp["n"], nnz=lpgen.nnz(lp))
+        dev.append(d)
+    torch.cuda.synchronize()
+    b = psl.Batch(dev)
+    b.run()
+    bad = []
+    for i in range(4096):
+        name = b.results[i]
+        red = b.reduced(i) if name in ("REDUCED", "UNCHANGED") else None
+        if lp_digest(name, b.records(i), red) != ref["digests"][i] or b.lp_stats(i)["rounds"] != ref["rounds"][i]:
+            bad.append(i)
+    b.close()
+    assert not bad, f"{len(bad)} LPs differ, first {bad[:10]}"
