@@ -169,7 +169,12 @@ def batch_leg(args, torch, psl):
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream().cuda_stream
     lset = psl.LpSet(dev)
-    b = psl.Batch(lset, stream=stream)
+    # launch shapes picked by the tuner on a sample of the batch (every 8th LP)
+    t0 = time.time()
+    tuned = psl.tune(psl.LpSet(dev[::8]), reps=2, stream=stream)
+    print(f"[bench] tuner: {tuned} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    shape = dict(bin_thresholds=tuned["bin_thresholds"], split_sweep=tuned["split_sweep"])
+    b = psl.Batch(lset, stream=stream, **shape)
     b.run()
     b.reload(lset)
     b.run()
@@ -193,12 +198,13 @@ def batch_leg(args, torch, psl):
     if args.batch_no_seq:
         b.close()
         return {"metric": "batched LPs/s", "value": round(K / (batch_ms * 1e-3), 1), "ms_per_batch": batch_ms,
+                "tuned_shape": tuned,
                 "device_ms": {k: round(stats[k], 3) for k in ("ms_ingest", "ms_sweep", "ms_long", "ms_decide",
                                                              "ms_parallel", "ms_compact", "ms_total")},
                 "rounds": stats["rounds"]}
     # sequential single-LP runs on the same stream
     t0 = time.time()
-    hs = [psl.Presolver(d, stream=stream) for d in dev]
+    hs = [psl.Presolver(d, stream=stream, **shape) for d in dev]
     print(f"[bench] {K} single-LP handles created in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     for p in hs[:64]:
         p.run()
@@ -234,6 +240,7 @@ def batch_leg(args, torch, psl):
         "ms_per_batch": round(batch_ms, 3), "nnz_per_s": round(total_nnz / (batch_ms * 1e-3), 1),
         "sequential": {"value": round(K / (seq_ms * 1e-3), 1), "unit": "LPs/s", "ms_total": round(seq_ms, 1)},
         "speedup_vs_sequential": round(seq_ms / batch_ms, 2),
+        "tuned_shape": tuned,
         "equal_outputs": bool(same and same_bytes),
         "device_ms": {k: round(stats[k], 3) for k in ("ms_ingest", "ms_sweep", "ms_long", "ms_decide",
                                                      "ms_parallel", "ms_compact", "ms_total")},

@@ -80,10 +80,12 @@ typedef struct {
  *   feas_tol 1e-9, fix_tol 1e-9, min_improve 1e-7, par_tol 1e-9,
  *   inf_value 1e20, coef_tol 1e-9, bin thresholds from the tuner (NULL),
  *   device 0, stream NULL.
- * bin_thresholds (optional, n_bins = 2): [0] the longest row swept by one
+ * bin_thresholds (optional, n_bins = 2 or 3): [0] the longest row swept by one
  * 64-lane wavefront (16..512, default 512); [1] positions per workgroup chunk
- * of longer rows (a power of two >= 2048, default 2048). They change only the
- * speed, never a result. */
+ * of longer rows (a power of two >= 2048, default 2048); [2] the longest row
+ * swept by an 8-lane group (8, the default, or 4: rows of 5..8 entries then go
+ * to 16-lane groups). They change only the speed, never a result; psl_tune
+ * picks them by timing. */
 typedef struct {
     int32_t max_rounds;            /* propagation rounds per outer cycle        */
     int32_t max_outer;             /* outer cycles (rounds, then parallel rows) */
@@ -99,6 +101,9 @@ typedef struct {
     int32_t n_bins;
     int32_t device;
     void *stream;                  /* hipStream_t or NULL                       */
+    int32_t split_sweep;           /* 0: one row-sweep launch per round; 1: three
+                                      (short rows, wavefront rows, long-row
+                                      chunks). Speed only, never a result.     */
 } psl_settings;
 
 /* Postsolve record: 48 bytes, emitted in the order (round, phase, index,
@@ -200,6 +205,23 @@ void psl_presolve_free(psl_presolver *p);
 /* Message of the last failure on p (or of the last failed create when p is
  * NULL). Never NULL. */
 const char *psl_last_error(const psl_presolver *p);
+
+/* ---- Autotuning -------------------------------------------------------------
+ * The launch shapes (bin thresholds, one or three sweep launches) change only
+ * the speed. psl_tune times presolves of the given LPs (one batch when k > 1)
+ * under candidate shapes and reports the fastest; every candidate must give
+ * the same outcome and record count as the first (else PSL_ERR_DEVICE). */
+typedef struct {
+    int32_t bin_thresholds[3];     /* fastest: as psl_settings.bin_thresholds   */
+    int32_t split_sweep;           /* fastest launch split                       */
+    int32_t candidates;            /* shapes timed                               */
+    double ms_best;                /* median device ms of a presolve, fastest     */
+    double ms_default;             /* the same with the default shape            */
+} psl_tuning;
+
+/* reps >= 1 timed presolves per candidate (after one untimed). s: the settings
+ * to tune (its thresholds and split are ignored); NULL = defaults. */
+psl_status psl_tune(int32_t k, const psl_lp *lps, const psl_settings *s, int32_t reps, psl_tuning *out);
 
 /* ---- Batched presolve -----------------------------------------------------
  * k independent LPs presolved together: they are laid out as the diagonal

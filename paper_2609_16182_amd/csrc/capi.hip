@@ -89,6 +89,7 @@ extern "C" void psl_settings_default(psl_settings* s) {
   s->n_bins = 0;
   s->device = 0;
   s->stream = nullptr;
+  s->split_sweep = 0;
 }
 
 std::string psl::check_settings(const psl_settings* s) {
@@ -98,8 +99,10 @@ std::string psl::check_settings(const psl_settings* s) {
       !(s->inf_value > 0) || !(s->coef_tol >= 0))
     return "invalid tolerance";
   if (s->bin_thresholds) {
-    if (s->n_bins != 2) return "bin_thresholds needs n_bins = 2";
+    if (s->n_bins != 2 && s->n_bins != 3) return "bin_thresholds needs n_bins = 2 or 3";
     int a = s->bin_thresholds[0], b = s->bin_thresholds[1];
+    if (s->n_bins == 3 && s->bin_thresholds[2] != 4 && s->bin_thresholds[2] != 8)
+      return "bin_thresholds[2] (longest row of the 8-lane bin) must be 4 (no such bin) or 8";
     if (a < 16 || a > 512) return "bin_thresholds[0] (longest wavefront row) must be in [16, 512]";
     if (b < PASS_LEN || b > PASS_LEN * long_max_passes() || (b & (b - 1)) != 0)
       return "bin_thresholds[1] (chunk positions) must be a power of two >= 2048";
@@ -385,6 +388,7 @@ static void set_grid(psl_presolver* p) {
   const Dev& d = p->d;
   auto cnt = [&](int b) { return d.bin_off[b + 1] - d.bin_off[b]; };
   p->grid.nb[BIN_G4] = (cnt(BIN_G4) + 63) / 64;
+  p->grid.nb[BIN_G8] = (cnt(BIN_G8) + 31) / 32;
   p->grid.nb[BIN_G16] = (cnt(BIN_G16) + 15) / 16;
   p->grid.nb[BIN_W1] = (cnt(BIN_W1) + 3) / 4;
   p->grid.nb[BIN_W4] = (cnt(BIN_W4) + 3) / 4;
@@ -704,9 +708,10 @@ extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* 
   if (s->bin_thresholds) {
     p->thresholds[0] = s->bin_thresholds[0];
     p->thresholds[1] = s->bin_thresholds[1];
+    if (s->n_bins == 3) p->thresholds[2] = s->bin_thresholds[2];
   }
   p->stream = (hipStream_t)s->stream;
-  if (const char* e = std::getenv("PSL_SWEEP_SPLIT")) p->sweep_mode = std::atoi(e) ? 2 : MODE_ROUND;
+  p->sweep_mode = s->split_sweep ? 2 : MODE_ROUND;
   if (const char* e = std::getenv("PSL_TRACE")) p->trace = std::atoi(e) != 0;
   p->cap_m = lp->m;
   p->cap_n = lp->n;
@@ -944,8 +949,8 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       }
       if (p->trace)
         std::fprintf(stderr, "[psl] round %d: swept rows %lld nnz %lld, records %d, rows removed %d, "
-                     "LPs propagating %d\n", round, (long long)p->cur.rows, (long long)p->cur.nnz,
-                     p->hflags->round_total, removed, nprop);
+                     "bounds made finite %d, LPs propagating %d\n", round, (long long)p->cur.rows,
+                     (long long)p->cur.nnz, p->hflags->round_total, removed, p->hflags->fin_cols, nprop);
       if (nprop == 0) break;
       // keep the master lists on live rows once a sixteenth of them went (and
       // on live LPs)
@@ -972,8 +977,8 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       // bounds became finite (they are dirty), while the counts of the rows it
       // does not sweep are still exact; after it the counts are exact again.
       int64_t changed_cols = (int64_t)p->hflags->round_total - removed;
-      bool incremental = r + 1 < s.max_rounds && changed_cols * 8 < (int64_t)n;
-      bool counts = (int64_t)p->hflags->fin_cols * 16 < (int64_t)n;
+      bool incremental = r + 1 < s.max_rounds && changed_cols * p->incr_factor < (int64_t)n;
+      bool counts = (int64_t)p->hflags->fin_cols * p->count_factor < (int64_t)n;
       if (!d.dirty || !d.colid) return fail(p, PSL_ERR_DEVICE, "internal: incremental state not set up");
       mark_dirty(d, !was_incremental, incremental, counts, st);
       View sel;
@@ -1338,8 +1343,10 @@ extern "C" psl_status psl_batch_create(int32_t k, const psl_lp* lps, const psl_s
   if (s->bin_thresholds) {
     p->thresholds[0] = s->bin_thresholds[0];
     p->thresholds[1] = s->bin_thresholds[1];
+    if (s->n_bins == 3) p->thresholds[2] = s->bin_thresholds[2];
   }
   p->stream = (hipStream_t)s->stream;
+  p->sweep_mode = s->split_sweep ? 2 : MODE_ROUND;
   if (const char* e = std::getenv("PSL_TRACE")) p->trace = std::atoi(e) != 0;
   p->cap_m = (int32_t)M;
   p->cap_n = (int32_t)Nc;
@@ -1459,8 +1466,10 @@ psl_presolver* psl::engine_new(const psl_settings* s, int32_t cap_m, int32_t cap
   if (s->bin_thresholds) {
     p->thresholds[0] = s->bin_thresholds[0];
     p->thresholds[1] = s->bin_thresholds[1];
+    if (s->n_bins == 3) p->thresholds[2] = s->bin_thresholds[2];
   }
   p->stream = (hipStream_t)s->stream;
+  p->sweep_mode = s->split_sweep ? 2 : MODE_ROUND;
   p->cap_m = cap_m;
   p->cap_n = cap_n;
   p->cap_nnz = cap_nnz;
@@ -1508,3 +1517,73 @@ const std::string& psl::engine_error(const psl_presolver* p) { return p->err; }
 int32_t psl::engine_error_lp(const psl_presolver* p) { return p->err_lp; }
 
 size_t psl::engine_arena_bytes(const psl_presolver* p) { return p->arena_bytes; }
+
+// ---------------------------------------------------------------------------
+// autotuning of the launch shapes
+// ---------------------------------------------------------------------------
+extern "C" psl_status psl_tune(int32_t k, const psl_lp* lps, const psl_settings* s, int32_t reps, psl_tuning* out) {
+  if (!lps || !out || k < 1 || reps < 1) {
+    g_batch_error = "psl_tune needs k >= 1 LPs, reps >= 1 and an output";
+    return PSL_ERR_INVALID;
+  }
+  psl_settings base;
+  if (s) base = *s;
+  else psl_settings_default(&base);
+  // the default shape first, then wavefront thresholds, chunk sizes, splits
+  const int32_t t0s[] = {512, 256, 128, 64};
+  const int32_t t1s[] = {PASS_LEN, 4 * PASS_LEN};
+  const int32_t t2s[] = {8, 4};
+  psl_tuning best{};
+  best.ms_best = -1.0;
+  std::vector<psl_result> res(k), ref;
+  int64_t ref_records = -1;
+  int cand = 0;
+  for (int32_t t2 : t2s)
+  for (int32_t t1 : t1s)
+    for (int32_t t0 : t0s)
+      for (int split = 0; split < 2; ++split) {
+        psl_settings c = base;
+        int32_t thr[3] = {t0, t1, t2};
+        c.bin_thresholds = thr;
+        c.n_bins = 3;
+        c.split_sweep = split;
+        psl_batch* b = nullptr;
+        psl_status st = psl_batch_create(k, lps, &c, &b);
+        if (st != PSL_OK) return st;
+        psl_stats S{};
+        std::vector<double> ms;
+        st = psl_batch_run(b, res.data(), &S);
+        for (int r = 0; r < reps && st == PSL_OK; ++r) {
+          st = psl_batch_reload(b, k, lps);
+          if (st == PSL_OK) st = psl_batch_run(b, res.data(), &S);
+          if (st == PSL_OK) ms.push_back(S.ms_total + S.ms_ingest);
+        }
+        if (st != PSL_OK) {
+          g_batch_error = b->p->err;
+          psl_batch_free(b);
+          return st;
+        }
+        psl_batch_free(b);
+        if (ref_records < 0) {
+          ref_records = S.records;
+          ref = res;
+        } else if (S.records != ref_records || res != ref) {
+          g_batch_error = "tuning candidates gave different results";
+          return PSL_ERR_DEVICE;
+        }
+        std::sort(ms.begin(), ms.end());
+        double med = ms[ms.size() / 2];
+        if (cand == 0) best.ms_default = med;
+        if (best.ms_best < 0 || med < best.ms_best) {
+          best.ms_best = med;
+          best.bin_thresholds[0] = t0;
+          best.bin_thresholds[1] = t1;
+          best.bin_thresholds[2] = t2;
+          best.split_sweep = split;
+        }
+        ++cand;
+      }
+  best.candidates = cand;
+  *out = best;
+  return PSL_OK;
+}

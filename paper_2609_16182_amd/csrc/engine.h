@@ -101,7 +101,7 @@ struct psl_presolver {
   const uint32_t* colid = nullptr;
   int32_t* bin_counts_dev = nullptr;
   int32_t bin_counts[NBINS] = {0};
-  int32_t thresholds[2] = {512, PASS_LEN};  // longest wavefront row, chunk positions
+  int32_t thresholds[3] = {512, PASS_LEN, 8};  // longest wavefront row, chunk positions, longest 8-lane row
   SweepGrid grid{};
   int64_t chunk_cap = 0, long_cap = 0, cand_cap = 0;
   int32_t* cand_cnt = nullptr;
@@ -132,8 +132,12 @@ struct psl_presolver {
   double* hoff = nullptr;
 
   int state = 0;  // 0 loaded, 1 ran
-  int sweep_mode = MODE_ROUND;
-  bool trace = false;  // PSL_TRACE=1: one line per round on stderr  // PSL_SWEEP_SPLIT=1: three launches by register class
+  int sweep_mode = MODE_ROUND;  // 2: three launches by register class
+  bool trace = false;  // PSL_TRACE=1: one line per round on stderr
+  // after a round changing fewer than n / incr_factor columns only touched
+  // rows are swept; with fewer than n / count_factor bounds made finite the
+  // infinite-contribution counts are kept and inert rows skipped
+  int incr_factor = 4, count_factor = 16;
   psl_result result = PSL_RES_UNCHANGED;
   psl_stats stats{};
   double ms_ingest = 0.0;

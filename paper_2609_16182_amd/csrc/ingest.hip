@@ -154,14 +154,14 @@ const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, i
 // ---------------------------------------------------------------------------
 // row bins by CSR length, and the chunk table of long rows
 // ---------------------------------------------------------------------------
-__global__ void k_bin_keys(Dev d, int32_t t_long, uint32_t* keys, int32_t* counts) {
+__global__ void k_bin_keys(Dev d, int32_t t_long, int32_t t_g8, uint32_t* keys, int32_t* counts) {
   __shared__ int c[NBINS];
   if (threadIdx.x < NBINS) c[threadIdx.x] = 0;
   __syncthreads();
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < d.m) {
     int len = d.rp[i + 1] - d.rp[i];
-    uint32_t b = len <= 4 ? BIN_G4 : len <= 16 ? BIN_G16 : len > t_long ? BIN_LONG
+    uint32_t b = len <= 4 ? BIN_G4 : len <= t_g8 ? BIN_G8 : len <= 16 ? BIN_G16 : len > t_long ? BIN_LONG
                : len <= 64 ? BIN_W1 : len <= 256 ? BIN_W4 : BIN_W8;
     keys[i] = b;
     atomicAdd(&c[b], 1);
@@ -183,7 +183,8 @@ void build_bins(const Dev& d, const int32_t* thresholds, BinEnt* bins, int32_t* 
   fill_i32(counts, 0, NBINS, s);
   if (d.m == 0) return;
   unsigned blocks = (unsigned)((d.m + PSL_BLOCK - 1) / PSL_BLOCK);
-  hipLaunchKernelGGL(k_bin_keys, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, thresholds[0], sc.k0, counts);
+  hipLaunchKernelGGL(k_bin_keys, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, thresholds[0], thresholds[2], sc.k0,
+                     counts);
   radix_pass(sc.k0, nullptr, sc.k1, sc.v0, d.m, 0, 3, sc.ws, s);
   hipLaunchKernelGGL(k_bin_fill, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)sc.v0, bins);
 }

@@ -176,6 +176,11 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_hash(Dev d, ParScratch P, Swe
     return;
   }
   b -= g.nb[BIN_G4];
+  if (b < g.nb[BIN_G8]) {
+    hash_groups<8>(d, P, BIN_G8, b);
+    return;
+  }
+  b -= g.nb[BIN_G8];
   if (b < g.nb[BIN_G16]) {
     hash_groups<16>(d, P, BIN_G16, b);
     return;

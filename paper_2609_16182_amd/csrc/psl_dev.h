@@ -34,10 +34,11 @@ enum : uint8_t {
   CC_LBFIN = 64, CC_UBFIN = 128  // set at emission: lb (ub) went from infinite to finite
 };
 
-// row length bins: rows of <= 4 / <= 16 entries by 4- / 16-lane groups, rows
-// of <= 64 / <= 256 / <= 512 entries by one wavefront (1 / 4 / 8 contiguous
-// positions per lane), longer rows split into workgroup chunks
-enum { BIN_G4 = 0, BIN_G16 = 1, BIN_W1 = 2, BIN_W4 = 3, BIN_W8 = 4, BIN_LONG = 5, NBINS = 6 };
+// row length bins: rows of <= 4 / <= 8 / <= 16 entries by 4- / 8- / 16-lane
+// groups (the 8-lane bin is optional: its bound is 4 or 8), rows of <= 64 /
+// <= 256 / <= 512 entries by one wavefront (1 / 4 / 8 contiguous positions per
+// lane), longer rows split into workgroup chunks
+enum { BIN_G4 = 0, BIN_G8 = 1, BIN_G16 = 2, BIN_W1 = 3, BIN_W4 = 4, BIN_W8 = 5, BIN_LONG = 6, NBINS = 7 };
 
 #define PASS_LEN 2048      // positions per workgroup pass (256 lanes x 8)
 #define LONG_MAX_CHUNKS 512
@@ -292,7 +293,8 @@ __device__ __forceinline__ void wave_append(bool pred, const Cand& e, Cand* list
 // candidate-region sizes (entries) of the sweep bins, per workgroup
 __host__ __device__ __forceinline__ int64_t cand_region(int bin) {
   // 2 candidates x (rows per workgroup x longest row of the bin)
-  return bin == 0 ? 2 * 64 * 4 : bin == 1 ? 2 * 16 * 16 : bin == 2 ? 2 * 4 * 64 : bin == 3 ? 2 * 4 * 256 : 2 * 4 * 512;
+  return bin == BIN_G4 ? 2 * 64 * 4 : bin == BIN_G8 ? 2 * 32 * 8 : bin == BIN_G16 ? 2 * 16 * 16
+       : bin == BIN_W1 ? 2 * 4 * 64 : bin == BIN_W4 ? 2 * 4 * 256 : 2 * 4 * 512;
 }
 
 // SplitMix64 output function for state x (Steele, Lea & Flood 2014).

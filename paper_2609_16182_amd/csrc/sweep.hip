@@ -557,7 +557,7 @@ __device__ __forceinline__ int long_first_block(const SweepGrid& g) {
   return b;
 }
 
-// Three launches per sweep, by register need: (0) 4/16/64-lane group bins
+// Three launches per sweep, by register need: (0) 4/8/16/64-lane group bins
 // with one position per lane, (1) wavefront bins with 4 or 8 positions per
 // lane, (2) long-row chunks. Workgroups keep one global numbering across the
 // launches (candidate regions and counts are indexed by it).
@@ -580,7 +580,9 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_sweep(Dev d, SweepGrid g, int bas
   if (KIND == KIND_ALL) {
     if (b < g.nb[BIN_G4]) {
       sweep_rows<4, 1, MODE>(d, sk, BIN_G4, b);
-    } else if ((b -= g.nb[BIN_G4]) < g.nb[BIN_G16]) {
+    } else if ((b -= g.nb[BIN_G4]) < g.nb[BIN_G8]) {
+      sweep_rows<8, 1, MODE>(d, sk, BIN_G8, b);
+    } else if ((b -= g.nb[BIN_G8]) < g.nb[BIN_G16]) {
       sweep_rows<16, 1, MODE>(d, sk, BIN_G16, b);
     } else if ((b -= g.nb[BIN_G16]) < g.nb[BIN_W1]) {
       sweep_rows<64, 1, MODE>(d, sk, BIN_W1, b);
@@ -594,14 +596,16 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_sweep(Dev d, SweepGrid g, int bas
   } else if (KIND == KIND_SHORT) {
     if (b < g.nb[BIN_G4]) {
       sweep_rows<4, 1, MODE>(d, sk, BIN_G4, b);
-    } else if ((b -= g.nb[BIN_G4]) < g.nb[BIN_G16]) {
+    } else if ((b -= g.nb[BIN_G4]) < g.nb[BIN_G8]) {
+      sweep_rows<8, 1, MODE>(d, sk, BIN_G8, b);
+    } else if ((b -= g.nb[BIN_G8]) < g.nb[BIN_G16]) {
       sweep_rows<16, 1, MODE>(d, sk, BIN_G16, b);
     } else {
       b -= g.nb[BIN_G16];
       sweep_rows<64, 1, MODE>(d, sk, BIN_W1, b);
     }
   } else if (KIND == KIND_WIDE) {
-    b -= g.nb[BIN_G4] + g.nb[BIN_G16] + g.nb[BIN_W1];
+    b -= g.nb[BIN_G4] + g.nb[BIN_G8] + g.nb[BIN_G16] + g.nb[BIN_W1];
     if (b < g.nb[BIN_W4]) sweep_rows<64, 4, MODE>(d, sk, BIN_W4, b);
     else sweep_rows<64, 8, MODE>(d, sk, BIN_W8, b - g.nb[BIN_W4]);
   } else if (MODE == MODE_ROUND) {
@@ -865,7 +869,7 @@ void launch_long_stats(const Dev& d, int mode, hipStream_t s) {
 }
 
 void launch_sweep(const Dev& d, const SweepGrid& g, int mode, hipStream_t s) {
-  int n_short = g.nb[BIN_G4] + g.nb[BIN_G16] + g.nb[BIN_W1];
+  int n_short = g.nb[BIN_G4] + g.nb[BIN_G8] + g.nb[BIN_G16] + g.nb[BIN_W1];
   int n_wide = g.nb[BIN_W4] + g.nb[BIN_W8];
   int n_long = g.nb[BIN_LONG];
   if (mode == MODE_ROUND) {

@@ -39,7 +39,7 @@ class psl_settings(C.Structure):
                 ("feas_tol", C.c_double), ("fix_tol", C.c_double), ("min_improve", C.c_double),
                 ("par_tol", C.c_double), ("inf_value", C.c_double), ("coef_tol", C.c_double),
                 ("bin_thresholds", C.c_void_p), ("n_bins", C.c_int32), ("device", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("split_sweep", C.c_int32)]
 
 
 class psl_stats(C.Structure):
@@ -61,6 +61,11 @@ class psl_reduced_view(C.Structure):
                 ("c", C.c_void_p), ("obj_offset", C.c_double),
                 ("row_map", C.c_void_p), ("col_map", C.c_void_p),
                 ("row_class", C.c_void_p), ("col_class", C.c_void_p)]
+
+
+class psl_tuning(C.Structure):
+    _fields_ = [("bin_thresholds", C.c_int32 * 3), ("split_sweep", C.c_int32), ("candidates", C.c_int32),
+                ("ms_best", C.c_double), ("ms_default", C.c_double)]
 
 
 class psl_server_config(C.Structure):
@@ -112,6 +117,8 @@ def load(path=None):
     lib.psl_batch_reduced_problem.argtypes = [C.c_void_p, C.c_int32, C.POINTER(psl_reduced_view)]
     lib.psl_batch_records.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_void_p, C.c_int64]
     lib.psl_batch_postsolve.argtypes = [C.c_void_p, C.c_int32] + [C.c_void_p] * 6
+    lib.psl_tune.argtypes = [C.c_int32, C.c_void_p, C.POINTER(psl_settings), C.c_int32, C.POINTER(psl_tuning)]
+    lib.psl_tune.restype = C.c_int
     lib.psl_batch_free.argtypes = [C.c_void_p]
     lib.psl_batch_free.restype = None
     lib.psl_batch_last_error.argtypes = [C.c_void_p]
@@ -285,6 +292,16 @@ def psl_batch_postsolve(b, idx, x_red, n):
     return x
 
 
+def psl_tune(lps, settings: psl_settings, reps=3):
+    """Time candidate launch shapes on these LPs; returns a dict with the
+    fastest (bin_thresholds, split_sweep) and the timings."""
+    arr = lp_array(lps)
+    t = psl_tuning()
+    _bcheck(load().psl_tune(len(arr), C.cast(arr, C.c_void_p), C.byref(settings), reps, C.byref(t)))
+    return {"bin_thresholds": tuple(t.bin_thresholds), "split_sweep": t.split_sweep,
+            "candidates": t.candidates, "ms_best": t.ms_best, "ms_default": t.ms_default}
+
+
 def psl_batch_free(b):
     if b:
         load().psl_batch_free(b)
@@ -433,13 +450,19 @@ def make_lp(lp, keep):
                   *[ptr(arrs[k]) for k in _LP_KEYS], float(lp.get("obj_offset", 0.0)))
 
 
+def tune(lps, reps=3, stream=None, **settings):
+    """psl_tune on a list of LP dicts or an LpSet."""
+    lset = lps if isinstance(lps, LpSet) else LpSet(lps)
+    return psl_tune(lset.arr, make_settings(stream=stream, **settings), reps)
+
+
 def make_settings(stream=None, **kw):
     s = psl_settings_default()
     for k, v in kw.items():
         if k == "bin_thresholds":
-            arr = (C.c_int32 * 2)(*v)
+            arr = (C.c_int32 * len(v))(*v)
             s.bin_thresholds = C.cast(arr, C.c_void_p)
-            s.n_bins = 2
+            s.n_bins = len(v)
             s._thr = arr
         else:
             setattr(s, k, v)

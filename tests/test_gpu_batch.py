@@ -175,3 +175,13 @@ def test_batch_deterministic():
     b.run()
     assert [b.records(i).tobytes() for i in range(4)] == first
     b.close()
+
+
+def test_tuner_picks_a_shape_and_results_do_not_change():
+    lps = [lpgen.batch_member(i, m=300 + 40 * i) for i in range(12)] + [lpgen.power_law(seed=3, scale=0.003)]
+    t = psl.tune(lps, reps=1)
+    assert t["candidates"] == 32 and t["ms_best"] > 0 and t["ms_default"] >= t["ms_best"]
+    assert t["bin_thresholds"][0] in (64, 128, 256, 512) and t["bin_thresholds"][1] in (2048, 8192)
+    assert t["bin_thresholds"][2] in (4, 8)
+    b, _ = check_batch(lps, "tuned", bin_thresholds=t["bin_thresholds"], split_sweep=t["split_sweep"])
+    b.close()

@@ -62,7 +62,7 @@ def test_large_scaled_with_chains():
     assert_same(got, ref, "large")
 
 
-@pytest.mark.parametrize("thr", [(16, 2048), (64, 4096), (300, 2048), (512, 16384)])
+@pytest.mark.parametrize("thr", [(16, 2048), (64, 4096), (300, 2048), (512, 16384), (512, 2048, 4), (64, 2048, 8)])
 def test_bins_do_not_change_results(thr):
     """Every bin threshold (the longest row swept by one wavefront, the chunk
     size of longer rows, hence one or several workgroup passes per chunk)
