@@ -387,12 +387,10 @@ static psl_status read_round(psl_presolver* p, int32_t* rows_removed) {
 static void set_grid(psl_presolver* p) {
   const Dev& d = p->d;
   auto cnt = [&](int b) { return d.bin_off[b + 1] - d.bin_off[b]; };
-  p->grid.nb[BIN_G4] = (cnt(BIN_G4) + 63) / 64;
-  p->grid.nb[BIN_G8] = (cnt(BIN_G8) + 31) / 32;
-  p->grid.nb[BIN_G16] = (cnt(BIN_G16) + 15) / 16;
-  p->grid.nb[BIN_W1] = (cnt(BIN_W1) + 3) / 4;
-  p->grid.nb[BIN_W4] = (cnt(BIN_W4) + 3) / 4;
-  p->grid.nb[BIN_W8] = (cnt(BIN_W8) + 3) / 4;
+  for (int b = 0; b < BIN_LONG; ++b) {
+    int per_wg = bin_rows(b) * bin_rep(b);  // rows one workgroup sweeps
+    p->grid.nb[b] = (cnt(b) + per_wg - 1) / per_wg;
+  }
   p->grid.nb[BIN_LONG] = d.nchunks;
   p->grid.long_base = 0;
   for (int b = 0; b < BIN_LONG; ++b) p->grid.long_base += (int64_t)p->grid.nb[b] * cand_region(b);
@@ -415,7 +413,7 @@ static psl_status filter_view(psl_presolver* p, const View& src, BinEnt* bout, L
   Dev& d = p->d;
   // scratch: cnt / off (free after the round's emission) and v0 (free between
   // ingest and compaction; k0 / k1 hold the transposed copy's column ids)
-  rebin(d, src.bins, src.off, src.chunks, src.nchunks, bout, cout, dirty ? d.dirty : nullptr, inert, d.cnt, d.off,
+  rebin(d, src.bins, src.off, src.chunks, src.nchunks, bout, cout, dirty ? d.dirty : nullptr, inert, d.cnt,
         p->isc.v0, p->rebin_dev, p->rebin_dev + NBINS + 1, p->ws, p->stream);
   HIPCHK(p, hipMemcpyAsync(p->htot, p->rebin_dev, (NBINS + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));

@@ -250,17 +250,13 @@ __device__ __forceinline__ bool keep_row(const Dev& d, int row, const uint8_t* d
 }
 
 __global__ void k_rebin_flags(Dev d, const BinEnt* bins, int32_t nent, const LongChunk* chunks, int32_t nch,
-                              const uint8_t* dirty, int inert, int32_t* keep, int32_t* keep_len, int32_t* ckeep) {
+                              const uint8_t* dirty, int inert, int32_t* keep, int32_t* ckeep, int32_t* totals) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) totals[1] = 0;  // kept nonzeros, summed by the scatter
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= nent; k += stride) {
-    int f = 0, l = 0;
-    if (k < nent) {
-      BinEnt be = bins[k];
-      f = keep_row(d, be.row, dirty, inert != 0);
-      l = f ? be.len : 0;
-    }
+    int f = 0;
+    if (k < nent) f = keep_row(d, bins[k].row, dirty, inert != 0);
     keep[k] = f;
-    keep_len[k] = l;
   }
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nch; c += stride) {
     int f = 0;
@@ -272,25 +268,31 @@ __global__ void k_rebin_flags(Dev d, const BinEnt* bins, int32_t nent, const Lon
   }
 }
 
-__global__ void k_rebin_scatter(const BinEnt* bins, int32_t nent, const int32_t* pos, BinEnt* out,
-                                const LongChunk* chunks, int32_t nch, const int32_t* cpos, LongChunk* cout,
-                                BinOffsets old, int32_t* new_off, uint8_t* dirty) {
+__global__ void __launch_bounds__(PSL_BLOCK) k_rebin_scatter(const BinEnt* bins, int32_t nent, const int32_t* pos,
+                                                             BinEnt* out, const LongChunk* chunks, int32_t nch,
+                                                             const int32_t* cpos, LongChunk* cout, BinOffsets old,
+                                                             int32_t* new_off, uint8_t* dirty, int32_t* totals) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int len = 0;
   for (int64_t k = t0; k < nent; k += stride)
     if (pos[k + 1] != pos[k]) {
       BinEnt be = bins[k];
       out[pos[k]] = be;
+      len += be.len;
       if (dirty) dirty[be.row] = 0;  // swept now
     }
   for (int64_t c = t0; c < nch; c += stride)
     if (cpos[c + 1] != cpos[c]) cout[cpos[c]] = chunks[c];
   if (t0 <= NBINS) new_off[t0] = pos[old.off[t0]];
+  int tot;
+  block_excl_scan(len, &tot);
+  if (tot && threadIdx.x == 0) atomicAdd(&totals[1], tot);
 }
 
 void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const LongChunk* chunks_in, int32_t nch,
-           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, int32_t* keep, int32_t* keep_len,
-           int32_t* ckeep, int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s) {
+           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, int32_t* keep, int32_t* ckeep,
+           int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s) {
   BinOffsets bo;
   for (int b = 0; b <= NBINS; ++b) bo.off[b] = off_in[b];
   int32_t nent = off_in[NBINS];
@@ -298,13 +300,12 @@ void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const Lon
   int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_rebin_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, bins_in, nent, chunks_in, nch,
-                     (const uint8_t*)dirty, inert ? 1 : 0, keep, keep_len, ckeep);
+                     (const uint8_t*)dirty, inert ? 1 : 0, keep, ckeep, totals);
   scan_excl(keep, keep, nent + 1, totals + 0, ws, s);
-  scan_excl(keep_len, keep_len, nent + 1, totals + 1, ws, s);
   scan_excl(ckeep, ckeep, nch + 1, totals + 2, ws, s);
   hipLaunchKernelGGL(k_rebin_scatter, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, bins_in, nent,
                      (const int32_t*)keep, bins_out, chunks_in, nch, (const int32_t*)ckeep, chunks_out, bo, new_off,
-                     dirty);
+                     dirty, totals);
 }
 
 // Rows of the columns whose bounds changed (or that were fixed) this round,

@@ -169,31 +169,32 @@ __device__ __forceinline__ void hash_long_chunk(const Dev& d, const ParScratch& 
   }
 }
 
+// the wavefront rows of a row block (four per workgroup)
+__device__ __forceinline__ void hash_wave_block(const Dev& d, const ParScratch& P, int bin, int vb) {
+  int wid = vb * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6);
+  if (wid < d.bin_off[bin + 1] - d.bin_off[bin]) hash_wave_row(d, P, d.bins[d.bin_off[bin] + wid].row);
+}
+
+// one workgroup per workgroup of the sweep's grid (the same row blocks)
 __global__ void __launch_bounds__(PSL_BLOCK) k_par_hash(Dev d, ParScratch P, SweepGrid g) {
   int b = blockIdx.x;
-  if (b < g.nb[BIN_G4]) {
-    hash_groups<4>(d, P, BIN_G4, b);
+  for (int bin = 0; bin < BIN_LONG; ++bin) {
+    if (b >= g.nb[bin]) {
+      b -= g.nb[bin];
+      continue;
+    }
+    int rep = bin_rep(bin);
+    int count = d.bin_off[bin + 1] - d.bin_off[bin];
+    for (int k = 0; k < rep; ++k) {
+      int vb = b * rep + k;
+      if (vb * bin_rows(bin) >= count) break;
+      if (bin == BIN_G4) hash_groups<4>(d, P, bin, vb);
+      else if (bin == BIN_G8) hash_groups<8>(d, P, bin, vb);
+      else if (bin == BIN_G16) hash_groups<16>(d, P, bin, vb);
+      else hash_wave_block(d, P, bin, vb);
+    }
     return;
   }
-  b -= g.nb[BIN_G4];
-  if (b < g.nb[BIN_G8]) {
-    hash_groups<8>(d, P, BIN_G8, b);
-    return;
-  }
-  b -= g.nb[BIN_G8];
-  if (b < g.nb[BIN_G16]) {
-    hash_groups<16>(d, P, BIN_G16, b);
-    return;
-  }
-  b -= g.nb[BIN_G16];
-  // the three wavefront bins are consecutive in the bin list
-  int nw = g.nb[BIN_W1] + g.nb[BIN_W4] + g.nb[BIN_W8];
-  if (b < nw) {
-    int wid = b * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6);
-    if (wid < d.bin_off[BIN_W8 + 1] - d.bin_off[BIN_W1]) hash_wave_row(d, P, d.bins[d.bin_off[BIN_W1] + wid].row);
-    return;
-  }
-  b -= nw;
   if (b < g.nb[BIN_LONG]) hash_long_chunk(d, P, b);
 }
 

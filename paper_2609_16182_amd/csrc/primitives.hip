@@ -60,16 +60,43 @@ void fill_i32(int32_t* out, int32_t v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, out, v, n);
 }
 
+// Up to SCAN_ONE_MAX ints: one workgroup walks the array in tiles of
+// SCAN_TILE, carrying the running total (one launch instead of three).
+#define SCAN_ONE_MAX (8 * SCAN_TILE)
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_scan_one(const int32_t* in, int32_t* out, int64_t n, int32_t* total) {
+  int carry = 0;
+  for (int64_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
+    int64_t base = t0 + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      v[k] = base + k < n ? in[base + k] : 0;
+      s += v[k];
+    }
+    int tot;
+    int run = carry + block_excl_scan(s, &tot);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      if (base + k < n) out[base + k] = run;
+      run += v[k];
+    }
+    carry += tot;
+  }
+  if (total && threadIdx.x == 0) *total = carry;
+}
+
 void scan_excl(const int32_t* in, int32_t* out, int64_t n, int32_t* total, int32_t* ws, hipStream_t s) {
   if (n <= 0) {
     if (total) fill_i32(total, 0, 1, s);
     return;
   }
-  int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-  if (nb == 1) {
-    hipLaunchKernelGGL(k_scan_tile_apply, dim3(1), dim3(PSL_BLOCK), 0, s, in, out, n, (const int32_t*)nullptr, total);
+  if (n <= SCAN_ONE_MAX) {
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(PSL_BLOCK), 0, s, in, out, n, total);
     return;
   }
+  int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   int32_t* sums = ws;
   hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nb), dim3(PSL_BLOCK), 0, s, in, n, sums);
   scan_excl(sums, sums, nb, nullptr, ws + nb, s);

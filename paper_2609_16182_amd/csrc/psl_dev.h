@@ -291,10 +291,21 @@ __device__ __forceinline__ void wave_append(bool pred, const Cand& e, Cand* list
 }
 
 // candidate-region sizes (entries) of the sweep bins, per workgroup
+// Row blocks (of 256 threads' rows) one workgroup of a bin sweeps in turn:
+// short rows give a wavefront little work, so their workgroups take several.
+__host__ __device__ __forceinline__ int bin_rep(int bin) {
+  return bin <= BIN_G16 ? 4 : bin == BIN_W1 ? 2 : 1;
+}
+
+// rows of a row block of the bin
+__host__ __device__ __forceinline__ int bin_rows(int bin) {
+  return bin == BIN_G4 ? 64 : bin == BIN_G8 ? 32 : bin == BIN_G16 ? 16 : 4;
+}
+
 __host__ __device__ __forceinline__ int64_t cand_region(int bin) {
   // 2 candidates x (rows per workgroup x longest row of the bin)
-  return bin == BIN_G4 ? 2 * 64 * 4 : bin == BIN_G8 ? 2 * 32 * 8 : bin == BIN_G16 ? 2 * 16 * 16
-       : bin == BIN_W1 ? 2 * 4 * 64 : bin == BIN_W4 ? 2 * 4 * 256 : 2 * 4 * 512;
+  int len = bin == BIN_G4 ? 4 : bin == BIN_G8 ? 8 : bin == BIN_G16 ? 16 : bin == BIN_W1 ? 64 : bin == BIN_W4 ? 256 : 512;
+  return 2 * (int64_t)bin_rep(bin) * bin_rows(bin) * len;
 }
 
 // SplitMix64 output function for state x (Steele, Lea & Flood 2014).

@@ -56,8 +56,8 @@ void build_bins(const Dev& d, const int32_t* thresholds, BinEnt* bins, int32_t* 
 // a bin list and chunk list: new_off [0..NBINS], totals = {kept rows, their
 // nonzeros, kept chunks} (device)
 void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const LongChunk* chunks_in, int32_t nch,
-           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, int32_t* keep, int32_t* keep_len,
-           int32_t* ckeep, int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s);
+           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, int32_t* keep, int32_t* ckeep,
+           int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s);
 // after a round: with count, lower the infinite-contribution counts of the
 // rows of columns whose bounds became finite; with mark, mark the rows of the
 // changed columns dirty (clearing all marks first with clear_first)

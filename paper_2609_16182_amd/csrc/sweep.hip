@@ -327,9 +327,9 @@ __device__ __forceinline__ void lane_drop(const Dev& d, const El (&e)[C]) {
 // rows of at most G*C entries: one G-lane group per row, C positions per lane
 // ---------------------------------------------------------------------------
 template <int G, int C, int MODE>
-__device__ __forceinline__ void sweep_rows(const Dev& d, const CandSink& sk, int bin, int lblock) {
+__device__ __forceinline__ void sweep_row_block(const Dev& d, const CandSink& sk, int bin, int vblock) {
   const int per_block = PSL_BLOCK / G;
-  int gid = lblock * per_block + (int)(threadIdx.x / G);
+  int gid = vblock * per_block + (int)(threadIdx.x / G);
   int count = d.bin_off[bin + 1] - d.bin_off[bin];
   bool vr = gid < count;
   int row = 0;
@@ -393,6 +393,18 @@ __device__ __forceinline__ void sweep_rows(const Dev& d, const CandSink& sk, int
   if (code == RC_REDUNDANT) {
     if (C == 1) lane_drop<C>(d, e);
     else lane_drop_stream<C>(d, live, s0, len, gl * C);
+  }
+}
+
+// the workgroup's row blocks of the bin, one after the other
+template <int G, int C, int MODE>
+__device__ __forceinline__ void sweep_rows(const Dev& d, const CandSink& sk, int bin, int lblock) {
+  const int rep = bin_rep(bin);
+  int count = d.bin_off[bin + 1] - d.bin_off[bin];
+  for (int k = 0; k < rep; ++k) {
+    int vb = lblock * rep + k;
+    if (vb * (PSL_BLOCK / G) >= count) break;  // uniform over the workgroup
+    sweep_row_block<G, C, MODE>(d, sk, bin, vb);
   }
 }
 
