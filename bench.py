@@ -35,7 +35,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the full power-law LP)")
+    ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the full-size LP)")
+    ap.add_argument("--workload", choices=("powerlaw", "large"), default="powerlaw",
+                    help="single-LP workload: the power-law LP (default) or the large LP")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-lps", type=int, default=4096, help="LPs of the batched workload (0 = skip it)")
     ap.add_argument("--batch-steps", type=int, default=3)
@@ -286,7 +288,8 @@ def main():
         print(json.dumps(serving_leg(args, torch, psl)), flush=True)
         return
     t0 = time.time()
-    lp = lpgen.power_law(seed=1, scale=args.scale)
+    lp = (lpgen.power_law(seed=1, scale=args.scale) if args.workload == "powerlaw"
+          else lpgen.large(seed=2, scale=args.scale))
     nnz = lpgen.nnz(lp)
     print(f"[bench] workload m={lp['m']} n={lp['n']} nnz={nnz} generated in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
@@ -328,7 +331,7 @@ def main():
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(),
+        "traffic": measured_traffic() if args.workload == "powerlaw" and args.scale == 1.0 else None,
         "kernel": "k_sweep<0> (row sweep: activities, decisions, implied bounds)",
         "launches": sweep_launches, "avg_launch_us": round(sweep_ms * 1e3 / max(1, sweep_launches), 2),
         "alg_bytes_per_launch": round(per_launch_bytes),
@@ -355,8 +358,11 @@ def main():
         "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "power-law LP: m=1e6, n=1.5e6, rows 2+Zipf(2) capped 1e5, "
-                               "power-law columns, planted 2% singleton/doubleton/duplicate rows",
+        "config": {"workload": ("power-law LP: m=1e6, n=1.5e6, rows 2+Zipf(2) capped 1e5, "
+                                "power-law columns, planted 2% singleton/doubleton/duplicate rows")
+                   if args.workload == "powerlaw" else
+                   ("large LP: m=1e7, n=1.5e7, rows U{3..12}, 20 dense rows of 1e6, 20 dense columns of 1e5, "
+                    "1% planted reductions with 8-row propagation chains"),
                    "m": lp["m"], "n": lp["n"], "nnz": nnz, "scale": args.scale,
                    "parallelism": "single GPU"},
         "roofline": roofline,
