@@ -208,6 +208,8 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->chunks_a, p->chunk_cap);
   ALLOC(p->chunks_b, p->chunk_cap);
   ALLOC(p->chunks_s, p->chunk_cap);
+  ALLOC(p->rb_keep, rebin_flag_bytes(m, p->chunk_cap));
+  ALLOC(p->rb_tiles, (m + p->chunk_cap) / 1024 + 8);
   uint8_t* dirty;
   ALLOC(dirty, m);
   ALLOC(d.touch, n);
@@ -407,25 +409,37 @@ static void use_view(psl_presolver* p, const View& v) {
   p->cur = v;
 }
 
+// the view described by a selection's device totals (bin offsets, rows,
+// nonzeros, chunks)
+static View view_of(BinEnt* bins, LongChunk* chunks, const int32_t* tot) {
+  View v;
+  v.bins = bins;
+  v.chunks = chunks;
+  for (int b = 0; b <= NBINS; ++b) v.off[b] = tot[b];
+  v.rows = tot[NBINS + 1];
+  v.nnz = tot[NBINS + 2];
+  v.nchunks = tot[NBINS + 3];
+  return v;
+}
+
 // dst = the active rows of src (only the dirty ones when dirty is set)
 static psl_status filter_view(psl_presolver* p, const View& src, BinEnt* bout, LongChunk* cout, bool dirty,
                               View& dst, bool inert = false) {
   Dev& d = p->d;
-  // scratch: cnt / off (free after the round's emission) and v0 (free between
-  // ingest and compaction; k0 / k1 hold the transposed copy's column ids)
-  rebin(d, src.bins, src.off, src.chunks, src.nchunks, bout, cout, dirty ? d.dirty : nullptr, inert, d.cnt,
-        p->isc.v0, p->rebin_dev, p->rebin_dev + NBINS + 1, p->ws, p->stream);
+  rebin(d, src.bins, src.off, src.chunks, src.nchunks, bout, cout, dirty ? d.dirty : nullptr, inert, nullptr,
+        p->rb_keep, p->rb_tiles, p->rebin_dev, p->rebin_dev + NBINS + 1, p->ws, p->stream);
   HIPCHK(p, hipMemcpyAsync(p->htot, p->rebin_dev, (NBINS + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
-  View v;
-  v.bins = bout;
-  v.chunks = cout;
-  for (int b = 0; b <= NBINS; ++b) v.off[b] = p->htot[b];
-  v.rows = p->htot[NBINS + 1];
-  v.nnz = p->htot[NBINS + 2];
-  v.nchunks = p->htot[NBINS + 3];
-  dst = v;
+  dst = view_of(bout, cout, p->htot);
   return PSL_OK;
+}
+
+// queue the next round's selection from src with the mode the device decided
+// (d.flags->mode); read with the round's flags
+static void queue_selection(psl_presolver* p, const View& src) {
+  Dev& d = p->d;
+  rebin(d, src.bins, src.off, src.chunks, src.nchunks, p->bins_s, p->chunks_s, nullptr, false, &d.flags->mode,
+        p->rb_keep, p->rb_tiles, d.flags->sel, d.flags->sel + NBINS + 1, p->ws, p->stream);
 }
 
 static std::string error_what(int32_t bits) {
@@ -525,7 +539,8 @@ static psl_status ingest_rest(psl_presolver* p) {
   if (p->grid.long_base + (int64_t)p->htot[1] > p->cand_cap)
     return fail(p, PSL_ERR_CAPACITY, "candidate buffer too small for the row bins");
 
-  p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.col_len, p->isc, st);
+  // the reduced problem's value array is free until compaction
+  p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.col_len, p->isc, p->red.val, st);
   p->cmp.colid = p->colid;
   d.colid = p->colid;
   list_dense_cols(d, st);
@@ -915,6 +930,23 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       launch_src(d, p->grid, st);
       launch_decide(d, p->rec_count, round, d.cnt, d.off, p->ws, st);
       HIPCHK(p, hipEventRecord(p->ev[6], st));
+      // The next round's selection is queued before the round's one read.
+      // Rows none of whose columns changed since they were last swept give
+      // the same statistics and no qualifying candidate, so after a round
+      // with few column changes only the touched rows are swept; and inert
+      // rows (their infinite-contribution counts, kept current as bounds
+      // become finite, rule out every outcome) are never swept. The counts
+      // are kept by decrements while few bounds become finite in a round.
+      // After a round with many, no decrement is made and the next round
+      // skips no row: it sweeps, and so recounts, every row one of whose
+      // bounds became finite (they are dirty), while the counts of the rows
+      // it does not sweep are still exact; after it the counts are exact
+      // again. The device takes these decisions from the round's totals
+      // (d.flags->mode); an LP that stopped has left lp_ok already. When the
+      // rounds end here the selection is not used.
+      if (!d.dirty || !d.colid) return fail(p, PSL_ERR_DEVICE, "internal: incremental state not set up");
+      mark_dirty(d, !was_incremental, r + 1 < s.max_rounds, p->incr_factor, p->count_factor, st);
+      queue_selection(p, p->master);
       e = queue_lp_read(p, true);
       if (e != PSL_OK) return e;
       int32_t removed = 0;
@@ -950,6 +982,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
                      "bounds made finite %d, LPs propagating %d\n", round, (long long)p->cur.rows,
                      (long long)p->cur.nnz, p->hflags->round_total, removed, p->hflags->fin_cols, nprop);
       if (nprop == 0) break;
+      View sel = view_of(p->bins_s, p->chunks_s, p->hflags->sel);
       // keep the master lists on live rows once a sixteenth of them went (and
       // on live LPs)
       if ((removed > 0 && (int64_t)removed * 16 >= p->master.rows) || (B && any_done)) {
@@ -964,26 +997,8 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
         }
         if (e != PSL_OK) return e;
       }
-      // Next round. Rows none of whose columns changed since they were last
-      // swept give the same statistics and no qualifying candidate, so after
-      // a round with few column changes only the touched rows are swept; and
-      // inert rows (their infinite-contribution counts, kept current as
-      // bounds become finite, rule out every outcome) are never swept.
-      // The counts are kept by decrements while few bounds become finite in a
-      // round. After a round with many, no decrement is made and the next
-      // round skips no row: it sweeps, and so recounts, every row one of whose
-      // bounds became finite (they are dirty), while the counts of the rows it
-      // does not sweep are still exact; after it the counts are exact again.
-      int64_t changed_cols = (int64_t)p->hflags->round_total - removed;
-      bool incremental = r + 1 < s.max_rounds && changed_cols * p->incr_factor < (int64_t)n;
-      bool counts = (int64_t)p->hflags->fin_cols * p->count_factor < (int64_t)n;
-      if (!d.dirty || !d.colid) return fail(p, PSL_ERR_DEVICE, "internal: incremental state not set up");
-      mark_dirty(d, !was_incremental, incremental, counts, st);
-      View sel;
-      e = filter_view(p, p->master, p->bins_s, p->chunks_s, incremental, sel, counts);
-      if (e != PSL_OK) return e;
       use_view(p, sel);
-      was_incremental = incremental;
+      was_incremental = (p->hflags->mode & 1) != 0;
     }
     use_view(p, p->master);
     was_incremental = false;

@@ -109,6 +109,8 @@ struct psl_presolver {
   // removals); a selection holds the active rows touched by a column change
   // since they were last swept
   BinEnt *bins_a = nullptr, *bins_b = nullptr, *bins_s = nullptr;
+  uint8_t* rb_keep = nullptr;     // keep decisions of the bin-list filter
+  int32_t* rb_tiles = nullptr;    // its tile counts / offsets
   LongChunk *chunks_a = nullptr, *chunks_b = nullptr, *chunks_s = nullptr;
   int32_t* rebin_dev = nullptr;  // [NBINS+1] new offsets, then 3 totals
   View master, cur;

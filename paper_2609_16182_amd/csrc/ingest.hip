@@ -102,17 +102,18 @@ __global__ void k_csc_gather(Dev d, const int32_t* perm, const int32_t* rowid1, 
   }
 }
 
-// cp[j] = first position of column j in the column-sorted keys
+// cp from the column-sorted keys: position q starts every column in
+// (keys[q-1], keys[q]] (keys[-1] = -1, keys[nnz] = n), so empty columns get
+// the next column's start
 __global__ void k_col_ptr(Dev d, const uint32_t* keys, int32_t* cp) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > d.n) return;
-  int64_t lo = 0, hi = d.nnz;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)keys[mid] < j) lo = mid + 1;
-    else hi = mid;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= d.nnz; q += (int64_t)gridDim.x * blockDim.x) {
+    int64_t prev = q > 0 ? (int64_t)keys[q - 1] : -1;
+    int64_t cur = q < d.nnz ? (int64_t)keys[q] : (int64_t)d.n;
+    // keys were validated (< n); clamped all the same so no store leaves cp
+    prev = prev < (int64_t)d.n ? prev : (int64_t)d.n;
+    cur = cur < (int64_t)d.n ? cur : (int64_t)d.n;
+    for (int64_t j = prev + 1; j <= cur; ++j) cp[j] = (int32_t)q;
   }
-  cp[j] = (int32_t)lo;
 }
 
 __global__ void k_col_len(Dev d, const int32_t* cp, int32_t* col_len) {
@@ -121,30 +122,49 @@ __global__ void k_col_len(Dev d, const int32_t* cp, int32_t* col_len) {
   col_len[j] = cp[j + 1] - cp[j];
 }
 
+// Stable transpose by LSD radix passes over the column index (at most 8 bits
+// a pass, the bits split evenly), moving row and value with each key; the
+// last pass writes the transposed copy itself. vtmp: nnz doubles of scratch.
 // Returns the column of every position of the transposed copy (the sorted
 // keys), which compaction uses.
 const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, int32_t* col_len, IngestScratch& sc,
-                          hipStream_t s) {
+                          double* vtmp, hipStream_t s) {
   int bits = 0;
   while (bits < 31 && ((int64_t)1 << bits) < (int64_t)d.n) ++bits;
+  int passes = (bits + 7) / 8;
   const uint32_t* kin = (const uint32_t*)d.ci;
-  const int32_t* vin = nullptr;
-  uint32_t* kb[2] = {sc.k0, sc.k1};
-  int32_t* vb[2] = {sc.v0, sc.v1};
-  int cur = 0;
-  for (int shift = 0; shift < bits; shift += 8) {
-    int b = bits - shift < 8 ? bits - shift : 8;
-    radix_pass(kin, vin, kb[cur], vb[cur], d.nnz, shift, b, sc.ws, s);
-    kin = kb[cur];
-    vin = vb[cur];
-    cur ^= 1;
+  if (passes == 0) {
+    // at most one column: the transposed copy is the CSR order
+    if (d.nnz > 0) {
+      int64_t blocks = (d.nnz + PSL_BLOCK - 1) / PSL_BLOCK;
+      if (blocks > 16384) blocks = 16384;
+      hipLaunchKernelGGL(k_csc_gather, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)nullptr,
+                         sc.rowid1, ri, cva);
+    }
+  } else {
+    int per = (bits + passes - 1) / passes;
+    const int32_t* rin = nullptr;
+    const double* vin = d.va;
+    uint32_t* kb[2] = {sc.k0, sc.k1};
+    int32_t* rb[2] = {sc.v0, sc.v1};
+    for (int pass = 0, shift = 0; pass < passes; ++pass, shift += per) {
+      int b = bits - shift < per ? bits - shift : per;
+      bool last = pass == passes - 1;
+      // the values end in cva after an odd number of hops from it
+      double* vout = ((passes - 1 - pass) % 2 == 0) ? cva : vtmp;
+      int32_t* rout = last ? ri : rb[pass & 1];
+      uint32_t* kout = kb[pass & 1];
+      radix_pass_payload(kin, rin, sc.rowid1, vin, kout, rout, vout, d.nnz, shift, b, sc.ws, s);
+      kin = kout;
+      rin = rout;
+      vin = vout;
+    }
   }
-  if (d.nnz > 0) {
-    int64_t blocks = (d.nnz + PSL_BLOCK - 1) / PSL_BLOCK;
+  {
+    int64_t blocks = (d.nnz + 1 + PSL_BLOCK - 1) / PSL_BLOCK;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_csc_gather, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, vin, sc.rowid1, ri, cva);
+    hipLaunchKernelGGL(k_col_ptr, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, kin, cp);
   }
-  hipLaunchKernelGGL(k_col_ptr, dim3((d.n + 1 + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, kin, cp);
   if (d.n > 0)
     hipLaunchKernelGGL(k_col_len, dim3((d.n + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d,
                        (const int32_t*)cp, col_len);
@@ -241,71 +261,174 @@ struct BinOffsets {
   int32_t off[NBINS + 1];
 };
 
+// The filter works in tiles of RB_TILE items (RB_ITEMS per thread, striped so
+// the loads coalesce): the entry tiles of the bin list, then the tiles of the
+// chunk list. A first launch takes the keep decisions (one byte per item) and
+// counts each tile's kept items, a scan of the tile counts gives each tile's
+// output offset, and a second launch writes the kept items in input order.
+// The decisions are taken once: the second launch clears dirty flags, which
+// the chunks of a long row would otherwise read after its entry cleared them.
+#define RB_ITEMS 4
+#define RB_TILE (PSL_BLOCK * RB_ITEMS)
+
+size_t rebin_flag_bytes(int64_t nent, int64_t nch) { return (size_t)(nent + nch + 2 * RB_TILE); }
+
+struct RebinArgs {
+  const BinEnt* bins;
+  int32_t nent;
+  const LongChunk* chunks;
+  int32_t nch;
+  uint8_t* dirty;        // dirty flags (used when the mode asks for them)
+  int use_dirty, inert;  // filter mode, unless mode != nullptr
+  const int32_t* mode;   // device: bit 0 = dirty rows only, bit 1 = skip inert rows
+  uint8_t* keep;         // [T * RB_TILE] keep decisions
+};
+
+__device__ __forceinline__ void rebin_mode(const RebinArgs& a, const uint8_t*& dirty, bool& inert) {
+  int md = a.mode ? *a.mode : ((a.use_dirty ? 1 : 0) | (a.inert ? 2 : 0));
+  dirty = (md & 1) ? a.dirty : nullptr;
+  inert = (md & 2) != 0;
+}
+
 // keep a bin entry (and the chunks of a long row) when its row is active, its
 // LP still presolving, with a dirty array touched by a column change since it
-// was last swept, and with inert set not inert
-__device__ __forceinline__ bool keep_row(const Dev& d, int row, const uint8_t* dirty, bool inert) {
-  return d.row_on[row] != 0 && (!dirty || dirty[row]) && (d.K == 1 || d.lp_ok[d.row_lp[row]]) &&
-         (!inert || !row_inert(d.rinf[row], d.lhs[row], d.rhs[row]));
+// was last swept, and with inert set not inert; no short-circuit loads, so the
+// loads of a thread's items are in flight together
+__device__ __forceinline__ bool keep_row_flat(const Dev& d, int row, const uint8_t* dirty, bool inert) {
+  bool on = d.row_on[row] != 0;
+  bool dt = dirty ? dirty[row] != 0 : true;
+  bool lp = d.K == 1 ? true : d.lp_ok[d.row_lp[row]] != 0;
+  bool live = true;
+  if (inert) live = !row_inert(d.rinf[row], d.lhs[row], d.rhs[row]);
+  return on && dt && lp && live;
 }
 
-__global__ void k_rebin_flags(Dev d, const BinEnt* bins, int32_t nent, const LongChunk* chunks, int32_t nch,
-                              const uint8_t* dirty, int inert, int32_t* keep, int32_t* ckeep, int32_t* totals) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) totals[1] = 0;  // kept nonzeros, summed by the scatter
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= nent; k += stride) {
-    int f = 0;
-    if (k < nent) f = keep_row(d, bins[k].row, dirty, inert != 0);
-    keep[k] = f;
-  }
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= nch; c += stride) {
-    int f = 0;
-    if (c < nch) {
-      int row = chunks[c].row;
-      f = keep_row(d, row, dirty, inert != 0);
+__global__ void __launch_bounds__(PSL_BLOCK) k_rebin_count(Dev d, RebinArgs a, int te, int T, int32_t* tile_sum,
+                                                           int32_t* totals) {
+  int c = 0;
+  int tile = blockIdx.x;
+  if (tile < T) {
+    const uint8_t* dirty;
+    bool inert;
+    rebin_mode(a, dirty, inert);
+    bool ct = tile >= te;
+    int64_t base = (int64_t)(ct ? tile - te : tile) * RB_TILE + threadIdx.x;
+    int64_t lim = ct ? a.nch : a.nent;
+    int rows[RB_ITEMS];
+#pragma unroll
+    for (int k = 0; k < RB_ITEMS; ++k) {
+      int64_t idx = base + (int64_t)k * PSL_BLOCK;
+      rows[k] = idx < lim ? (ct ? a.chunks[idx].row : a.bins[idx].row) : -1;
     }
-    ckeep[c] = f;
+#pragma unroll
+    for (int k = 0; k < RB_ITEMS; ++k) {
+      bool f = keep_row_flat(d, rows[k] >= 0 ? rows[k] : 0, dirty, inert) & (rows[k] >= 0);
+      a.keep[(int64_t)tile * RB_TILE + k * PSL_BLOCK + threadIdx.x] = f ? 1 : 0;
+      c += f;
+    }
+  }
+  int tot;
+  block_excl_scan(c, &tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    tile_sum[T] = 0;
+    totals[1] = 0;  // kept nonzeros, summed by the scatter
   }
 }
 
-__global__ void __launch_bounds__(PSL_BLOCK) k_rebin_scatter(const BinEnt* bins, int32_t nent, const int32_t* pos,
-                                                             BinEnt* out, const LongChunk* chunks, int32_t nch,
-                                                             const int32_t* cpos, LongChunk* cout, BinOffsets old,
-                                                             int32_t* new_off, uint8_t* dirty, int32_t* totals) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// tile_off: exclusive scan of the tile counts (T + 1 entries)
+__global__ void __launch_bounds__(PSL_BLOCK) k_rebin_scatter(RebinArgs a, int te, int T, const int32_t* tile_off,
+                                                             BinEnt* out, LongChunk* cout, BinOffsets old,
+                                                             int32_t* new_off, int32_t* totals) {
+  __shared__ int wcnt[RB_ITEMS][PSL_BLOCK / PSL_WAVE];
+  int w = threadIdx.x >> 6;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    totals[0] = tile_off[te];
+    totals[2] = tile_off[T] - tile_off[te];
+  }
+  if (blockIdx.x == 0 && threadIdx.x <= NBINS && old.off[threadIdx.x] == a.nent)
+    new_off[threadIdx.x] = tile_off[te];
+  int tile = blockIdx.x;
+  if (tile >= T) return;
+  bool ct = tile >= te;
+  int64_t base_idx = (int64_t)(ct ? tile - te : tile) * RB_TILE + threadIdx.x;
+  bool f[RB_ITEMS];
+  int pre[RB_ITEMS];
+#pragma unroll
+  for (int k = 0; k < RB_ITEMS; ++k) {
+    f[k] = a.keep[(int64_t)tile * RB_TILE + k * PSL_BLOCK + threadIdx.x] != 0;
+    unsigned long long bal = __ballot(f[k]);
+    pre[k] = __popcll(bal & lanemask_lt());
+    if (lane_id() == 0) wcnt[k][w] = __popcll(bal);
+  }
+  __syncthreads();
+  // exclusive prefix of item (k, thread) in index order (k-major)
+  int run = 0;
+#pragma unroll
+  for (int k = 0; k < RB_ITEMS; ++k) {
+    int row_tot = 0, before = 0;
+#pragma unroll
+    for (int v = 0; v < PSL_BLOCK / PSL_WAVE; ++v) {
+      int c = wcnt[k][v];
+      row_tot += c;
+      if (v < w) before += c;
+    }
+    pre[k] += run + before;
+    run += row_tot;
+  }
+  int64_t base = (int64_t)tile_off[tile] - (ct ? tile_off[te] : 0);
+  const uint8_t* dirty;
+  bool inert;
+  rebin_mode(a, dirty, inert);
   int len = 0;
-  for (int64_t k = t0; k < nent; k += stride)
-    if (pos[k + 1] != pos[k]) {
-      BinEnt be = bins[k];
-      out[pos[k]] = be;
-      len += be.len;
-      if (dirty) dirty[be.row] = 0;  // swept now
+#pragma unroll
+  for (int k = 0; k < RB_ITEMS; ++k) {
+    int64_t idx = base_idx + (int64_t)k * PSL_BLOCK;
+    int64_t pos = base + pre[k];
+    if (!ct) {
+      if (idx < a.nent) {
+#pragma unroll
+        for (int b = 0; b <= NBINS; ++b)
+          if (old.off[b] == idx) new_off[b] = (int32_t)pos;
+      }
+      if (f[k]) {
+        BinEnt be = a.bins[idx];
+        out[pos] = be;
+        len += be.len;
+        if (dirty) a.dirty[be.row] = 0;  // swept now
+      }
+    } else if (f[k]) {
+      cout[pos] = a.chunks[idx];
     }
-  for (int64_t c = t0; c < nch; c += stride)
-    if (cpos[c + 1] != cpos[c]) cout[cpos[c]] = chunks[c];
-  if (t0 <= NBINS) new_off[t0] = pos[old.off[t0]];
+  }
   int tot;
   block_excl_scan(len, &tot);
   if (tot && threadIdx.x == 0) atomicAdd(&totals[1], tot);
 }
 
 void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const LongChunk* chunks_in, int32_t nch,
-           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, int32_t* keep, int32_t* ckeep,
-           int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s) {
+           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, const int32_t* mode,
+           uint8_t* keep, int32_t* tile_sum, int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s) {
   BinOffsets bo;
   for (int b = 0; b <= NBINS; ++b) bo.off[b] = off_in[b];
-  int32_t nent = off_in[NBINS];
-  int64_t t = nent + 1 > nch + 1 ? nent + 1 : nch + 1;
-  int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_rebin_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, bins_in, nent, chunks_in, nch,
-                     (const uint8_t*)dirty, inert ? 1 : 0, keep, ckeep, totals);
-  scan_excl(keep, keep, nent + 1, totals + 0, ws, s);
-  scan_excl(ckeep, ckeep, nch + 1, totals + 2, ws, s);
-  hipLaunchKernelGGL(k_rebin_scatter, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, bins_in, nent,
-                     (const int32_t*)keep, bins_out, chunks_in, nch, (const int32_t*)ckeep, chunks_out, bo, new_off,
-                     dirty, totals);
+  RebinArgs a;
+  a.bins = bins_in;
+  a.nent = off_in[NBINS];
+  a.chunks = chunks_in;
+  a.nch = nch;
+  a.dirty = mode ? d.dirty : dirty;
+  a.use_dirty = dirty != nullptr;
+  a.inert = inert ? 1 : 0;
+  a.mode = mode;
+  a.keep = keep;
+  int te = (int)(((int64_t)a.nent + RB_TILE - 1) / RB_TILE);
+  int tc = (int)(((int64_t)nch + RB_TILE - 1) / RB_TILE);
+  int T = te + tc;
+  unsigned grid = (unsigned)(T > 0 ? T : 1);
+  hipLaunchKernelGGL(k_rebin_count, dim3(grid), dim3(PSL_BLOCK), 0, s, d, a, te, T, tile_sum, totals);
+  scan_excl(tile_sum, tile_sum, (int64_t)T + 1, nullptr, ws, s);
+  hipLaunchKernelGGL(k_rebin_scatter, dim3(grid), dim3(PSL_BLOCK), 0, s, a, te, T, (const int32_t*)tile_sum,
+                     bins_out, chunks_out, bo, new_off, totals);
 }
 
 // Rows of the columns whose bounds changed (or that were fixed) this round,
@@ -336,7 +459,24 @@ __device__ __forceinline__ bool mark_col(int code, int mode) {
   return ((mode & 1) && (code & MARK_MASK)) || ((mode & 2) && (code & (CC_LBFIN | CC_UBFIN)));
 }
 
-__global__ void __launch_bounds__(PSL_BLOCK) k_mark_sparse(Dev d, int mode) {
+// The next round's selection mode from this round's totals (bit 0: sweep only
+// the rows touched by a change, when few columns changed and allow is set;
+// bit 1: keep the infinite-contribution counts, when few bounds became finite)
+struct RoundMode {
+  int allow, incr_factor, count_factor;
+};
+
+__device__ __forceinline__ int round_mode(const Dev& d, const RoundMode& rm) {
+  int64_t changed = (int64_t)d.flags->round_total - d.flags->rows_removed;
+  bool incr = rm.allow && changed * rm.incr_factor < (int64_t)d.n;
+  bool counts = (int64_t)d.flags->fin_cols * rm.count_factor < (int64_t)d.n;
+  return (incr ? 1 : 0) | (counts ? 2 : 0);
+}
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_mark_sparse(Dev d, RoundMode rm) {
+  int mode = round_mode(d, rm);
+  if (blockIdx.x == 0 && threadIdx.x == 0) d.flags->mode = mode;
+  if (mode == 0) return;
   int64_t j = (int64_t)blockIdx.x * PSL_BLOCK + threadIdx.x;
   bool ch = false;
   int q0 = 0, q1 = 0, code = 0;
@@ -358,9 +498,11 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_mark_sparse(Dev d, int mode) {
 
 // every workgroup lists the changed dense columns (in slices of 1024, checked
 // in parallel) and walks a grid-strided share of their entries
-__global__ void __launch_bounds__(PSL_BLOCK) k_mark_dense(Dev d, int mode) {
+__global__ void __launch_bounds__(PSL_BLOCK) k_mark_dense(Dev d, RoundMode rm) {
   __shared__ int32_t list[1024];
   __shared__ int32_t cnt;
+  int mode = round_mode(d, rm);
+  if (mode == 0) return;
   int nd = *d.n_dense;
   for (int k0 = 0; k0 < nd; k0 += 1024) {
     if (threadIdx.x == 0) cnt = 0;
@@ -401,17 +543,17 @@ __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
     p[i] = v;
 }
 
-void mark_dirty(const Dev& d, bool clear_first, bool mark, bool count, hipStream_t s) {
-  if (mark && clear_first && d.m > 0) {
+void mark_dirty(const Dev& d, bool clear_first, bool allow_incremental, int incr_factor, int count_factor,
+                hipStream_t s) {
+  if (clear_first && d.m > 0) {
     int64_t b = (d.m + PSL_BLOCK - 1) / PSL_BLOCK;
     hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(PSL_BLOCK), 0, s, d.dirty, (uint8_t)0,
                        (int64_t)d.m);
   }
-  int mode = (mark ? 1 : 0) | (count ? 2 : 0);
-  if (d.nnz == 0 || d.n == 0 || mode == 0) return;
-  hipLaunchKernelGGL(k_mark_sparse, dim3((unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d,
-                     mode);
-  hipLaunchKernelGGL(k_mark_dense, dim3(1024), dim3(PSL_BLOCK), 0, s, d, mode);
+  RoundMode rm{allow_incremental ? 1 : 0, incr_factor, count_factor};
+  unsigned blocks = (unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK);
+  hipLaunchKernelGGL(k_mark_sparse, dim3(blocks > 0 ? blocks : 1), dim3(PSL_BLOCK), 0, s, d, rm);
+  if (d.nnz > 0 && d.n > 0) hipLaunchKernelGGL(k_mark_dense, dim3(1024), dim3(PSL_BLOCK), 0, s, d, rm);
 }
 
 // ---------------------------------------------------------------------------
@@ -436,7 +578,7 @@ __global__ void k_init_state(Dev d) {
     Flags f;
     f.infeasible = f.unbounded = f.error = f.merged = 0;
     f.cand_count = f.round_total = f.vlist_count = f.rows_removed = 0;
-    f.fin_cols = f.pad2 = 0;
+    f.fin_cols = f.mode = 0;
     f.error_pos = 0x7FFFFFFFFFFFFFFFLL;
     *d.flags = f;
   }

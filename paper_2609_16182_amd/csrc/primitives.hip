@@ -60,31 +60,45 @@ void fill_i32(int32_t* out, int32_t v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, out, v, n);
 }
 
-// Up to SCAN_ONE_MAX ints: one workgroup walks the array in tiles of
-// SCAN_TILE, carrying the running total (one launch instead of three).
-#define SCAN_ONE_MAX (8 * SCAN_TILE)
+// Up to SCAN_ONE_MAX ints: one workgroup stages the array in LDS with
+// coalesced loads, each thread scans a contiguous run of it, and one block
+// scan joins the runs (one launch and one trip to memory instead of three
+// launches).
+#define SCAN_ONE_MAX 12288
 
 __global__ void __launch_bounds__(PSL_BLOCK) k_scan_one(const int32_t* in, int32_t* out, int64_t n, int32_t* total) {
-  int carry = 0;
-  for (int64_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
-    int64_t base = t0 + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int v[SCAN_ITEMS];
-    int s = 0;
+  __shared__ int32_t buf[SCAN_ONE_MAX];
+  int nn = (int)n;
+  {
+    // every load in flight at once
+    int v[SCAN_ONE_MAX / PSL_BLOCK];
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-      v[k] = base + k < n ? in[base + k] : 0;
-      s += v[k];
+    for (int i = 0; i < SCAN_ONE_MAX / PSL_BLOCK; ++i) {
+      int k = i * PSL_BLOCK + threadIdx.x;
+      v[i] = k < nn ? in[k] : 0;
     }
-    int tot;
-    int run = carry + block_excl_scan(s, &tot);
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-      if (base + k < n) out[base + k] = run;
-      run += v[k];
+    for (int i = 0; i < SCAN_ONE_MAX / PSL_BLOCK; ++i) {
+      int k = i * PSL_BLOCK + threadIdx.x;
+      if (k < nn) buf[k] = v[i];
     }
-    carry += tot;
   }
-  if (total && threadIdx.x == 0) *total = carry;
+  __syncthreads();
+  int per = (nn + PSL_BLOCK - 1) / PSL_BLOCK;
+  int b0 = threadIdx.x * per;
+  int b1 = b0 + per < nn ? b0 + per : nn;
+  int s = 0;
+  for (int k = b0; k < b1; ++k) s += buf[k];
+  int tot;
+  int run = block_excl_scan(s, &tot);
+  for (int k = b0; k < b1; ++k) {
+    int v = buf[k];
+    buf[k] = run;
+    run += v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nn; k += PSL_BLOCK) out[k] = buf[k];
+  if (total && threadIdx.x == 0) *total = tot;
 }
 
 void scan_excl(const int32_t* in, int32_t* out, int64_t n, int32_t* total, int32_t* ws, hipStream_t s) {
@@ -195,6 +209,116 @@ void radix_pass(const uint32_t* keys_in, const int32_t* vals_in, uint32_t* keys_
   scan_excl(hist, hist, (int64_t)(mask + 1) * ntiles, nullptr, sws, s);
   hipLaunchKernelGGL(k_rx_scatter, dim3(ntiles), dim3(PSL_BLOCK), 0, s, keys_in, vals_in, keys_out, vals_out, n,
                      shift, mask, (const int32_t*)hist, ntiles);
+}
+
+// Stable pass with a (row, value) payload, staged through LDS: each tile is
+// ordered by digit in LDS first, so consecutive threads store consecutive
+// positions of a digit's run (coalesced) instead of one scattered store per
+// item. With rows_in == nullptr the payload of item p is (rowid1[p + 1],
+// vals_in[p]) (the CSR itself).
+__global__ void __launch_bounds__(PSL_BLOCK) k_tx_scatter(const uint32_t* kin, const int32_t* rin,
+                                                          const int32_t* rowid1, const double* vin, uint32_t* kout,
+                                                          int32_t* rout, double* vout, int64_t n, int shift,
+                                                          uint32_t mask, const int32_t* hoff, int ntiles) {
+  __shared__ int start[256];   // tile-local start of each digit's run
+  __shared__ int gbase[256];   // global start of the tile's run of each digit
+  __shared__ int run[256];     // items of each digit placed so far
+  __shared__ int wcnt[PSL_BLOCK / PSL_WAVE][256];
+  __shared__ uint32_t sk[RX_TILE];
+  __shared__ int32_t sr[RX_TILE];
+  __shared__ double sv[RX_TILE];
+  int t = threadIdx.x, w = t >> 6;
+  int64_t base = (int64_t)blockIdx.x * RX_TILE;
+  int cnt = (int)(n - base < RX_TILE ? n - base : RX_TILE);
+  uint32_t key[RX_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RX_ROUNDS; ++r) {
+    int64_t idx = base + r * PSL_BLOCK + t;
+    key[r] = idx < n ? kin[idx] : 0u;
+  }
+  start[t] = 0;
+  run[t] = 0;
+  gbase[t] = (uint32_t)t <= mask ? hoff[(int64_t)t * ntiles + blockIdx.x] : 0;
+#pragma unroll
+  for (int k = 0; k < PSL_BLOCK / PSL_WAVE; ++k) wcnt[k][t] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RX_ROUNDS; ++r)
+    if (r * PSL_BLOCK + t < cnt) atomicAdd(&start[(key[r] >> shift) & mask], 1);
+  __syncthreads();
+  {
+    int h = start[t], tot;
+    int e = block_excl_scan(h, &tot);
+    start[t] = e;
+  }
+  __syncthreads();
+  int slot[RX_ROUNDS];
+#pragma unroll
+  for (int r = 0; r < RX_ROUNDS; ++r) {
+    bool valid = r * PSL_BLOCK + t < cnt;
+    uint32_t d = (key[r] >> shift) & mask;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (d >> b) & 1u;
+      unsigned long long bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    int rank = __popcll(peers & lanemask_lt());
+    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    slot[r] = -1;
+    if (valid) {
+      int before = start[d] + run[d];
+      for (int k = 0; k < w; ++k) before += wcnt[k][d];
+      slot[r] = before + rank;
+    }
+    __syncthreads();
+    {
+      int sum = 0;
+#pragma unroll
+      for (int k = 0; k < PSL_BLOCK / PSL_WAVE; ++k) {
+        sum += wcnt[k][t];
+        wcnt[k][t] = 0;
+      }
+      run[t] += sum;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < RX_ROUNDS; ++r) {
+    if (slot[r] < 0) continue;
+    int64_t idx = base + r * PSL_BLOCK + t;
+    sk[slot[r]] = key[r];
+    sr[slot[r]] = rin ? rin[idx] : rowid1[idx + 1];
+    sv[slot[r]] = vin[idx];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RX_ROUNDS; ++r) {
+    int sl = r * PSL_BLOCK + t;
+    if (sl >= cnt) continue;
+    uint32_t k = sk[sl];
+    uint32_t d = (k >> shift) & mask;
+    int64_t g = (int64_t)gbase[d] + (sl - start[d]);
+    kout[g] = k;
+    rout[g] = sr[sl];
+    vout[g] = sv[sl];
+  }
+}
+
+void radix_pass_payload(const uint32_t* keys_in, const int32_t* rows_in, const int32_t* rowid1,
+                        const double* vals_in, uint32_t* keys_out, int32_t* rows_out, double* vals_out, int64_t n,
+                        int shift, int bits, int32_t* ws, hipStream_t s) {
+  if (n <= 0) return;
+  int ntiles = (int)((n + RX_TILE - 1) / RX_TILE);
+  uint32_t mask = (1u << bits) - 1u;
+  int32_t* hist = ws;
+  int32_t* sws = ws + 256 * (int64_t)ntiles;
+  hipLaunchKernelGGL(k_rx_count, dim3(ntiles), dim3(PSL_BLOCK), 0, s, keys_in, n, shift, mask, hist, ntiles);
+  scan_excl(hist, hist, (int64_t)(mask + 1) * ntiles, nullptr, sws, s);
+  hipLaunchKernelGGL(k_tx_scatter, dim3(ntiles), dim3(PSL_BLOCK), 0, s, keys_in, rows_in, rowid1, vals_in, keys_out,
+                     rows_out, vals_out, n, shift, mask, (const int32_t*)hist, ntiles);
 }
 
 // ---------------------------------------------------------------------------

@@ -102,8 +102,12 @@ struct LpOut {       // per LP: nonzero when the last round gave it records (cle
 struct Flags {
   int32_t infeasible, unbounded, error, merged;
   int32_t cand_count, round_total, vlist_count, rows_removed;
-  int32_t fin_cols, pad2;  // columns of the round with a bound that became finite
+  int32_t fin_cols;        // columns of the round with a bound that became finite
+  int32_t mode;            // the next round's selection mode (bit 0: touched rows
+                           // only, bit 1: inert rows skipped), set after a round
   int64_t error_pos;
+  int32_t sel[NBINS + 4];  // the next round's selection: bin offsets [0..NBINS],
+                           // rows, their nonzeros, long-row chunks
 };
 
 struct Cfg {
@@ -155,7 +159,8 @@ struct Dev {
   int32_t K;
   const int32_t *row_lp, *col_lp;     // LP of each row / column
   const int32_t *lp_row0, *lp_col0;   // [K+1] first row / column of each LP
-  const uint8_t *lp_ok;               // [K] LP still presolving (its rows stay in the bins)
+  uint8_t *lp_ok;                     // [K] LP still presolving (its rows stay in the bins;
+                                      // cleared here when the LP stops)
   const int32_t *lp_round;            // [K] the LP's own number of the current round
   LpFlags *lpf;                       // [K]
   LpOut *lpo;                         // [K]
@@ -172,13 +177,20 @@ __device__ __forceinline__ void drop_col(const Dev& d, int j) {
   if (atomicSub(&d.col_len[j], 1) == 1) d.touch[j] = 1;
 }
 
+// an LP that stops leaves the next selection at once
 __device__ __forceinline__ void flag_infeasible(const Dev& d, int lp) {
   atomicOr(&d.flags->infeasible, 1);
-  if (d.K > 1) atomicOr(&d.lpf[lp].infeasible, 1);
+  if (d.K > 1) {
+    atomicOr(&d.lpf[lp].infeasible, 1);
+    d.lp_ok[lp] = 0;
+  }
 }
 __device__ __forceinline__ void flag_unbounded(const Dev& d, int lp) {
   atomicOr(&d.flags->unbounded, 1);
-  if (d.K > 1) atomicOr(&d.lpf[lp].unbounded, 1);
+  if (d.K > 1) {
+    atomicOr(&d.lpf[lp].unbounded, 1);
+    d.lp_ok[lp] = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------

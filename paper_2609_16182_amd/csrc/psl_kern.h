@@ -19,6 +19,13 @@ size_t radix_ws_ints(int64_t n);
 void radix_pass(const uint32_t* keys_in, const int32_t* vals_in, uint32_t* keys_out, int32_t* vals_out,
                 int64_t n, int shift, int bits, int32_t* ws, hipStream_t s);
 
+// The same pass moving a payload of a row index and a value with each key;
+// rows_in == nullptr takes row rowid1[p + 1] for item p. Buffers must not
+// alias. ws: radix_ws_ints(n).
+void radix_pass_payload(const uint32_t* keys_in, const int32_t* rows_in, const int32_t* rowid1,
+                        const double* vals_in, uint32_t* keys_out, int32_t* rows_out, double* vals_out, int64_t n,
+                        int shift, int bits, int32_t* ws, hipStream_t s);
+
 // out[i] = v (32-bit words)
 void fill_i32(int32_t* out, int32_t v, int64_t n, hipStream_t s);
 
