@@ -485,6 +485,9 @@ static psl_status ingest_rest(psl_presolver* p) {
   hipStream_t st = p->stream;
   int64_t m = p->m, n = p->n, N = p->nnz;
   launch_init_state(d, st);  // clears the flag block
+  // the sweep's loads read position 0 for lanes without an entry: with no
+  // entries it must still hold a valid column
+  if (N == 0) fill_i32((int32_t*)d.ci, 0, 1, st);
   launch_check_rows(d, st);
   check_cols(d, p->lb_in, p->ub_in, p->c_mut, st);
   psl_status s0 = read_flags(p);

@@ -15,18 +15,44 @@ namespace psl {
 
 // col0: first column of the row's LP (the pattern is hashed in the LP's own
 // column numbering, so a row's key does not depend on its place in a batch)
-__device__ __forceinline__ void hash_terms(const Dev& d, int64_t p, bool v, double a0, int col0,
-                                           unsigned long long& h1, unsigned long long& h2, bool& act) {
-  h1 = h2 = 0;
-  act = false;
-  if (!v) return;
-  int j = d.ci[p];
-  double a = d.va[p];
-  double2 b = d.bnd[j];
-  act = b.x != b.y;
+__device__ __forceinline__ void hash_el(int j, double a, double2 b, bool v, double a0, int col0,
+                                        unsigned long long& h1, unsigned long long& h2, bool& act) {
   unsigned long long cj = splitmix((unsigned long long)(uint32_t)(j - col0));
-  h1 = cj;
-  h2 = splitmix(cj ^ quantize(a / a0));
+  h1 = v ? cj : 0ULL;
+  h2 = v ? splitmix(cj ^ quantize(a / a0)) : 0ULL;
+  act = v && b.x != b.y;
+}
+
+// Hash terms of the positions q = q0 + u * STRIDE + lane (u < U, valid when
+// q < end) of a row starting at s0 (which is a valid position: the row has
+// entries), added to s1 / s2, active ones counted in L. All loads are issued
+// before any is used.
+template <int U, int STRIDE>
+__device__ __forceinline__ void hash_batch(const Dev& d, int64_t s0, int q0, int lane, int end, double a0, int col0,
+                                           unsigned long long& s1, unsigned long long& s2, int& L) {
+  int j[U];
+  double a[U];
+  bool v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    int q = q0 + u * STRIDE + lane;
+    v[u] = q < end;
+    int64_t p = v[u] ? s0 + q : s0;
+    j[u] = d.ci[p];
+    a[u] = d.va[p];
+  }
+  double2 b[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) b[u] = d.bnd[j[u]];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    unsigned long long h1, h2;
+    bool act;
+    hash_el(j[u], a[u], b[u], v[u], a0, col0, h1, h2, act);
+    s1 += h1;
+    s2 += h2;
+    L += act ? 1 : 0;
+  }
 }
 
 __device__ __forceinline__ unsigned long long row_key(int len, unsigned long long s1, unsigned long long s2) {
@@ -84,29 +110,30 @@ __global__ void k_par_reset(Dev d, ParScratch P) {
   }
 }
 
-// G-lane groups, rows of at most G entries, one position per lane
+// G-lane groups, rows of at most G entries, one position per lane (a lane
+// without a row reads the bin's first entry, which exists, and position 0
+// or the row's first position, so that no load is conditional)
 template <int G>
 __device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, int bin, int lblock) {
   int gid = lblock * (PSL_BLOCK / G) + (int)(threadIdx.x / G);
   int count = d.bin_off[bin + 1] - d.bin_off[bin];
   bool vr = gid < count;
-  int row = 0;
-  int64_t s0 = 0;
-  int len = 0;
-  bool on = false;
-  if (vr) {
-    BinEnt be = d.bins[d.bin_off[bin] + gid];
-    row = be.row;
-    s0 = be.start;
-    len = be.len;
-    on = d.row_on[row] != 0;
-  }
+  BinEnt be = d.bins[d.bin_off[bin] + (vr ? gid : 0)];
+  int row = be.row;
+  int64_t s0 = be.start;
+  int len = vr ? be.len : 0;
   int gl = threadIdx.x & (G - 1);
-  double a0 = on && len > 0 ? d.va[s0] : 1.0;
-  int col0 = on ? lp_col0(d, row) : 0;
+  int64_t p0 = len > 0 ? s0 : 0;
+  int64_t p = gl < len ? s0 + gl : p0;
+  bool on = vr && d.row_on[row] != 0;
+  double a0 = d.va[p0];
+  int j = d.ci[p];
+  double a = d.va[p];
+  double2 bb = d.bnd[j];
+  int col0 = lp_col0(d, row);
   unsigned long long h1, h2;
   bool act;
-  hash_terms(d, s0 + gl, on && gl < len, a0, col0, h1, h2, act);
+  hash_el(j, a, bb, on && gl < len, len > 0 ? a0 : 1.0, col0, h1, h2, act);
   h1 = group_sum_u64<G>(h1);
   h2 = group_sum_u64<G>(h2);
   int L = __popcll(__ballot(act) & group_mask<G>());
@@ -123,17 +150,10 @@ __device__ __forceinline__ void hash_wave_row(const Dev& d, const ParScratch& P,
   int col0 = lp_col0(d, row);
   unsigned long long s1 = 0, s2 = 0;
   int L = 0;
-  for (int q0 = 0; q0 < len; q0 += PSL_WAVE) {
-    int q = q0 + lane;
-    unsigned long long h1, h2;
-    bool act;
-    hash_terms(d, s0 + q, q < len, a0, col0, h1, h2, act);
-    s1 += h1;
-    s2 += h2;
-    L += __popcll(__ballot(act));
-  }
+  for (int q0 = 0; q0 < len; q0 += 4 * PSL_WAVE) hash_batch<4, PSL_WAVE>(d, s0, q0, lane, len, a0, col0, s1, s2, L);
   s1 = group_sum_u64<PSL_WAVE>(s1);
   s2 = group_sum_u64<PSL_WAVE>(s2);
+  L = (int)group_sum_u64<PSL_WAVE>((unsigned long long)L);
   if (lane == 0 && L >= 2) par_insert(d, P, row, row_key(len, s1, s2));
 }
 
@@ -150,15 +170,8 @@ __device__ __forceinline__ void hash_long_chunk(const Dev& d, const ParScratch& 
   unsigned long long s1 = 0, s2 = 0;
   int L = 0;
   int end = min(len, ch.first + ch.npass * PASS_LEN);
-  for (int q0 = ch.first; q0 < end; q0 += PSL_BLOCK) {
-    int q = q0 + (int)threadIdx.x;
-    unsigned long long h1, h2;
-    bool act;
-    hash_terms(d, s0 + q, q < end, a0, col0, h1, h2, act);
-    s1 += h1;
-    s2 += h2;
-    L += act ? 1 : 0;
-  }
+  for (int q0 = ch.first; q0 < end; q0 += 4 * PSL_BLOCK)
+    hash_batch<4, PSL_BLOCK>(d, s0, q0, (int)threadIdx.x, end, a0, col0, s1, s2, L);
   s1 = group_sum_u64<PSL_WAVE>(s1);
   s2 = group_sum_u64<PSL_WAVE>(s2);
   unsigned long long l64 = group_sum_u64<PSL_WAVE>((unsigned long long)L);

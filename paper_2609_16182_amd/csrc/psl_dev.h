@@ -336,9 +336,10 @@ __device__ __forceinline__ unsigned long long quantize(double v) {
   return ((mag + (1ULL << 19)) >> 20) | (sign << 63);
 }
 
-// exclusive scan of one int per thread across the 256-thread block
-__device__ __forceinline__ int block_excl_scan(int v, int* total) {
-  __shared__ int wsum[PSL_BLOCK / PSL_WAVE];
+// exclusive scan of one int per thread across a block of NT threads
+template <int NT>
+__device__ __forceinline__ int block_excl_scan_n(int v, int* total) {
+  __shared__ int wsum[NT / PSL_WAVE];
   int lane = lane_id(), w = threadIdx.x >> 6;
   int x = v;
 #pragma unroll
@@ -350,7 +351,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int* total) {
   __syncthreads();
   int pre = 0, tot = 0;
 #pragma unroll
-  for (int k = 0; k < PSL_BLOCK / PSL_WAVE; ++k) {
+  for (int k = 0; k < NT / PSL_WAVE; ++k) {
     int s = wsum[k];
     if (k < w) pre += s;
     tot += s;
@@ -359,6 +360,9 @@ __device__ __forceinline__ int block_excl_scan(int v, int* total) {
   *total = tot;
   return pre + x - v;
 }
+
+// the same across the 256-thread block
+__device__ __forceinline__ int block_excl_scan(int v, int* total) { return block_excl_scan_n<PSL_BLOCK>(v, total); }
 
 
 }  // namespace psl

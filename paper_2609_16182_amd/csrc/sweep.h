@@ -28,7 +28,7 @@ void launch_long_stats(const Dev& d, int mode, hipStream_t s);
 void launch_sweep(const Dev& d, const SweepGrid& g, int mode, hipStream_t s);
 void launch_src(const Dev& d, const SweepGrid& g, hipStream_t s);
 // decisions, counts and records of a round (tile_sum / tile_off: one int per
-// 2048 rows and columns, ws: scan workspace)
+// 1024 rows and columns, ws: scan workspace)
 void launch_decide(const Dev& d, int64_t base, int round, int32_t* tile_sum, int32_t* tile_off, int32_t* ws,
                    hipStream_t s);
 int long_max_passes();

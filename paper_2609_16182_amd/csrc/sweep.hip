@@ -33,18 +33,40 @@ struct El {
   bool v;
 };
 
-__device__ __forceinline__ void load_el(const Dev& d, int64_t p, bool v, El& e) {
-  e.v = v;
-  e.j = 0;
-  e.a = 0.0;
-  e.lb = 0.0;
-  e.ub = 0.0;
-  if (v) {
-    e.j = d.ci[p];
-    e.a = d.va[p];
-    double2 b = d.bnd[e.j];
-    e.lb = b.x;
-    e.ub = b.y;
+// Elements at positions s0 + base + k (k < C) of a row, valid when on and
+// base + k < len. All loads are issued before any is used, without branches
+// between them (an invalid element reads position 0, which exists whenever
+// the matrix has an entry), so a lane has C gathers in flight at once.
+template <int C>
+__device__ __forceinline__ void load_els(const Dev& d, int64_t s0, int len, int base, bool on, El (&e)[C]) {
+  int j[C];
+  double a[C];
+  double2 b[C];
+  bool v[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    v[k] = on && base + k < len;
+    j[k] = 0;
+    a[k] = 0.0;
+    b[k] = make_double2(0.0, 0.0);
+  }
+  if (d.nnz > 0) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      int64_t p = v[k] ? s0 + base + k : 0;
+      j[k] = d.ci[p];
+      a[k] = d.va[p];
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) b[k] = d.bnd[j[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    e[k].v = v[k];
+    e[k].j = v[k] ? j[k] : 0;
+    e[k].a = v[k] ? a[k] : 0.0;
+    e[k].lb = v[k] ? b[k].x : 0.0;
+    e[k].ub = v[k] ? b[k].y : 0.0;
   }
 }
 
@@ -52,12 +74,13 @@ __device__ __forceinline__ bool el_active(const El& e) { return e.v && e.lb != e
 
 // activity terms of one element and its packed counts
 // (bit 0: infinite min contribution, bit 10: infinite max, bit 20: active)
+// (straight-line: an invalid element holds a = lb = ub = 0 and so gives +0
+// terms and no counts)
 template <int MODE>
 __device__ __forceinline__ void el_terms(const El& e, double& tmin, double& tmax, int& cnt) {
   tmin = tmax = 0.0;
   cnt = 0;
-  if (!e.v) return;
-  bool act = e.lb != e.ub;
+  bool act = e.v && e.lb != e.ub;
   if (MODE == MODE_ROUND) {
     bool imin, imax;
     contrib(e.a, e.lb, e.ub, tmin, imin, tmax, imax);
@@ -96,10 +119,9 @@ __device__ __forceinline__ void lane_stats(const Dev& d, int64_t s0, int len, in
                                            double& smax, int& cnt) {
   double a[C], b[C];
   cnt = 0;
+  load_els<C>(d, s0, len, base, true, e);
 #pragma unroll
   for (int k = 0; k < C; ++k) {
-    int q = base + k;
-    load_el(d, s0 + q, q < len, e[k]);
     int c;
     el_terms<MODE>(e[k], a[k], b[k], c);
     cnt += c;
@@ -282,37 +304,46 @@ __device__ __forceinline__ void lane_prop(const Dev& d, const CandSink& sk, int6
   }
 }
 
-// the same, loading each element as it goes (two at a time), so that wide
-// lanes do not keep C elements live
+// the same, loading the elements again in groups of (at most) four, so that
+// wide lanes do not keep C elements live while each group's gathers are in
+// flight together
+#define STREAM_GROUP 4
 template <int C>
 __device__ __forceinline__ void lane_prop_stream(const Dev& d, const CandSink& sk, int row, bool prop, int64_t s0,
                                                  int len, int base, double lhs, double rhs, const RowStat& st,
                                                  bool single, bool& uncap, bool& mine, int& aj, double& aa) {
-#pragma unroll 2
-  for (int k = 0; k < C; ++k) {
-    El e;
-    load_el(d, s0 + base + k, prop && base + k < len, e);
-    bool act = el_active(e);
-    bool cap, hlo, hup;
-    double tlo, tup;
-    prop_el(d.cfg, act, e, lhs, rhs, st, single, cap, hlo, tlo, hup, tup);
-    commit_cands(d, sk, (int)(s0 + base + k), e.j, hlo, tlo, hup, tup);
-    if (act && !cap) uncap = true;
-    if (act) {
-      mine = true;
-      aj = e.j;
-      aa = e.a;
+  constexpr int GS = C < STREAM_GROUP ? C : STREAM_GROUP;
+#pragma unroll 1
+  for (int g = 0; g < C; g += GS) {
+    El e[GS];
+    load_els<GS>(d, s0, len, base + g, prop, e);
+#pragma unroll
+    for (int k = 0; k < GS; ++k) {
+      bool act = el_active(e[k]);
+      bool cap, hlo, hup;
+      double tlo, tup;
+      prop_el(d.cfg, act, e[k], lhs, rhs, st, single, cap, hlo, tlo, hup, tup);
+      commit_cands(d, sk, (int)(s0 + base + g + k), e[k].j, hlo, tlo, hup, tup);
+      if (act && !cap) uncap = true;
+      if (act) {
+        mine = true;
+        aj = e[k].j;
+        aa = e[k].a;
+      }
     }
   }
 }
 
 template <int C>
 __device__ __forceinline__ void lane_drop_stream(const Dev& d, bool on, int64_t s0, int len, int base) {
-#pragma unroll 2
-  for (int k = 0; k < C; ++k) {
-    El e;
-    load_el(d, s0 + base + k, on && base + k < len, e);
-    if (el_active(e)) drop_col(d, e.j);
+  constexpr int GS = C < STREAM_GROUP ? C : STREAM_GROUP;
+#pragma unroll 1
+  for (int g = 0; g < C; g += GS) {
+    El e[GS];
+    load_els<GS>(d, s0, len, base + g, on, e);
+#pragma unroll
+    for (int k = 0; k < GS; ++k)
+      if (el_active(e[k])) drop_col(d, e[k].j);
   }
 }
 
@@ -326,28 +357,65 @@ __device__ __forceinline__ void lane_drop(const Dev& d, const El (&e)[C]) {
 // ---------------------------------------------------------------------------
 // rows of at most G*C entries: one G-lane group per row, C positions per lane
 // ---------------------------------------------------------------------------
-template <int G, int C, int MODE>
-__device__ __forceinline__ void sweep_row_block(const Dev& d, const CandSink& sk, int bin, int vblock) {
+
+// what a lane reads of its row in a row block
+template <int C>
+struct RowIn {
+  bool vr, on;   // the lane's group has a row; the row is active
+  int row, len;
+  int64_t s0;
+  double lhs, rhs;
+  El e[C];
+};
+
+// First level of a row block's loads: the bin entry of the lane's row. A
+// lane without a row reads the bin's first entry (the workgroup exists
+// because the bin has one), so no load of the row block is conditional.
+template <int G, int C>
+__device__ __forceinline__ void row_entry(const Dev& d, int bin, int vblock, RowIn<C>& in) {
   const int per_block = PSL_BLOCK / G;
   int gid = vblock * per_block + (int)(threadIdx.x / G);
   int count = d.bin_off[bin + 1] - d.bin_off[bin];
-  bool vr = gid < count;
-  int row = 0;
-  int64_t s0 = 0;
-  int len = 0;
-  bool on = false;
-  if (vr) {
-    BinEnt be = d.bins[d.bin_off[bin] + gid];
-    row = be.row;
-    s0 = be.start;
-    len = be.len;
-    on = d.row_on[row] != 0;
-  }
+  in.vr = gid < count;
+  BinEnt be = d.bins[d.bin_off[bin] + (in.vr ? gid : 0)];
+  in.row = be.row;
+  in.s0 = be.start;
+  in.len = in.vr ? be.len : 0;
+}
+
+// Second level: the row's flag and sides and the lane's positions (columns
+// and coefficients); the third level, the bounds, is issued by load_els or
+// by the caller.
+template <int G, int C>
+__device__ __forceinline__ void row_data(const Dev& d, RowIn<C>& in) {
+  in.on = in.vr && d.row_on[in.row] != 0;
+  in.lhs = d.lhs[in.row];
+  in.rhs = d.rhs[in.row];
+}
+
+// statistics, decisions, candidates and removals of the row block's rows
+// from the loaded inputs (elements of inactive rows are cleared here)
+template <int G, int C, int MODE>
+__device__ __forceinline__ void row_block(const Dev& d, const CandSink& sk, RowIn<C>& in) {
+  const bool vr = in.vr, on = in.on;
+  const int row = in.row, len = in.len;
+  const int64_t s0 = in.s0;
   int gl = threadIdx.x & (G - 1);
-  El e[C];
+  El(&e)[C] = in.e;
   double smin, smax;
-  int cnt;
-  lane_stats<C, MODE>(d, s0, on ? len : 0, gl * C, e, smin, smax, cnt);
+  int cnt = 0;
+  {
+    double a[C], b[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      if (!on) e[k] = El{0, 0.0, 0.0, 0.0, false};
+      int c;
+      el_terms<MODE>(e[k], a[k], b[k], c);
+      cnt += c;
+    }
+    smin = lane_tree<C>(a);
+    smax = lane_tree<C>(b);
+  }
   RowStat st;
   st.minact = group_sum<G>(smin);
   st.maxact = group_sum<G>(smax);
@@ -363,12 +431,8 @@ __device__ __forceinline__ void sweep_row_block(const Dev& d, const CandSink& sk
     return;
   }
   bool live = vr && on;
-  double lhs = 0.0, rhs = 0.0;
-  if (live) {
-    lhs = d.lhs[row];
-    rhs = d.rhs[row];
-    if (gl == 0) d.rinf[row] = make_int2(st.nmin, st.nmax);
-  }
+  double lhs = live ? in.lhs : 0.0, rhs = live ? in.rhs : 0.0;
+  if (live && gl == 0) d.rinf[row] = make_int2(st.nmin, st.nmax);
   RowDec dec = decide_row(d.cfg, lhs, rhs, L, st.nmin, st.nmax, st.minact, st.maxact);
   bool prop = live && dec.prop;
   bool uncap = false, mine = false;
@@ -396,15 +460,53 @@ __device__ __forceinline__ void sweep_row_block(const Dev& d, const CandSink& sk
   }
 }
 
-// the workgroup's row blocks of the bin, one after the other
-template <int G, int C, int MODE>
+// The workgroup's REP row blocks of the bin. With one position per lane the
+// loads of all REP blocks are issued level by level before any block is
+// processed, so a lane has REP rows' gathers in flight together.
+template <int G, int C, int MODE, int REP>
 __device__ __forceinline__ void sweep_rows(const Dev& d, const CandSink& sk, int bin, int lblock) {
-  const int rep = bin_rep(bin);
   int count = d.bin_off[bin + 1] - d.bin_off[bin];
-  for (int k = 0; k < rep; ++k) {
-    int vb = lblock * rep + k;
-    if (vb * (PSL_BLOCK / G) >= count) break;  // uniform over the workgroup
-    sweep_row_block<G, C, MODE>(d, sk, bin, vb);
+  int gl = threadIdx.x & (G - 1);
+  if (C == 1) {
+    RowIn<C> in[REP];
+    int j[REP];
+    double a[REP];
+#pragma unroll
+    for (int k = 0; k < REP; ++k) row_entry<G, C>(d, bin, lblock * REP + k, in[k]);
+#pragma unroll
+    for (int k = 0; k < REP; ++k) {
+      row_data<G, C>(d, in[k]);
+      bool v = gl < in[k].len;
+      int64_t p = v ? in[k].s0 + gl : 0;
+      j[k] = d.ci[p];
+      a[k] = d.va[p];
+      in[k].e[0].v = v;
+    }
+#pragma unroll
+    for (int k = 0; k < REP; ++k) {
+      double2 bb = d.bnd[j[k]];
+      bool v = in[k].e[0].v;
+      in[k].e[0].j = v ? j[k] : 0;
+      in[k].e[0].a = v ? a[k] : 0.0;
+      in[k].e[0].lb = v ? bb.x : 0.0;
+      in[k].e[0].ub = v ? bb.y : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < REP; ++k) {
+      if ((lblock * REP + k) * (PSL_BLOCK / G) >= count) break;  // uniform over the workgroup
+      row_block<G, C, MODE>(d, sk, in[k]);
+    }
+  } else {
+#pragma unroll 1
+    for (int k = 0; k < REP; ++k) {
+      int vb = lblock * REP + k;
+      if (vb * (PSL_BLOCK / G) >= count) break;  // uniform over the workgroup
+      RowIn<C> in;
+      row_entry<G, C>(d, bin, vb, in);
+      row_data<G, C>(d, in);
+      load_els<C>(d, in.s0, in.len, gl * C, true, in.e);
+      row_block<G, C, MODE>(d, sk, in);
+    }
   }
 }
 
@@ -591,35 +693,35 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_sweep(Dev d, SweepGrid g, int bas
   CandSink sk{d.cand + (start < 0 ? 0 : start), &lcount};
   if (KIND == KIND_ALL) {
     if (b < g.nb[BIN_G4]) {
-      sweep_rows<4, 1, MODE>(d, sk, BIN_G4, b);
+      sweep_rows<4, 1, MODE, 4>(d, sk, BIN_G4, b);
     } else if ((b -= g.nb[BIN_G4]) < g.nb[BIN_G8]) {
-      sweep_rows<8, 1, MODE>(d, sk, BIN_G8, b);
+      sweep_rows<8, 1, MODE, 4>(d, sk, BIN_G8, b);
     } else if ((b -= g.nb[BIN_G8]) < g.nb[BIN_G16]) {
-      sweep_rows<16, 1, MODE>(d, sk, BIN_G16, b);
+      sweep_rows<16, 1, MODE, 4>(d, sk, BIN_G16, b);
     } else if ((b -= g.nb[BIN_G16]) < g.nb[BIN_W1]) {
-      sweep_rows<64, 1, MODE>(d, sk, BIN_W1, b);
+      sweep_rows<64, 1, MODE, 2>(d, sk, BIN_W1, b);
     } else if ((b -= g.nb[BIN_W1]) < g.nb[BIN_W4]) {
-      sweep_rows<64, 4, MODE>(d, sk, BIN_W4, b);
+      sweep_rows<64, 4, MODE, 1>(d, sk, BIN_W4, b);
     } else if ((b -= g.nb[BIN_W4]) < g.nb[BIN_W8]) {
-      sweep_rows<64, 8, MODE>(d, sk, BIN_W8, b);
+      sweep_rows<64, 8, MODE, 1>(d, sk, BIN_W8, b);
     } else if (MODE == MODE_ROUND) {
       sweep_long_chunk(d, sk, gb - lfb, lds);
     }
   } else if (KIND == KIND_SHORT) {
     if (b < g.nb[BIN_G4]) {
-      sweep_rows<4, 1, MODE>(d, sk, BIN_G4, b);
+      sweep_rows<4, 1, MODE, 4>(d, sk, BIN_G4, b);
     } else if ((b -= g.nb[BIN_G4]) < g.nb[BIN_G8]) {
-      sweep_rows<8, 1, MODE>(d, sk, BIN_G8, b);
+      sweep_rows<8, 1, MODE, 4>(d, sk, BIN_G8, b);
     } else if ((b -= g.nb[BIN_G8]) < g.nb[BIN_G16]) {
-      sweep_rows<16, 1, MODE>(d, sk, BIN_G16, b);
+      sweep_rows<16, 1, MODE, 4>(d, sk, BIN_G16, b);
     } else {
       b -= g.nb[BIN_G16];
-      sweep_rows<64, 1, MODE>(d, sk, BIN_W1, b);
+      sweep_rows<64, 1, MODE, 2>(d, sk, BIN_W1, b);
     }
   } else if (KIND == KIND_WIDE) {
     b -= g.nb[BIN_G4] + g.nb[BIN_G8] + g.nb[BIN_G16] + g.nb[BIN_W1];
-    if (b < g.nb[BIN_W4]) sweep_rows<64, 4, MODE>(d, sk, BIN_W4, b);
-    else sweep_rows<64, 8, MODE>(d, sk, BIN_W8, b - g.nb[BIN_W4]);
+    if (b < g.nb[BIN_W4]) sweep_rows<64, 4, MODE, 1>(d, sk, BIN_W4, b);
+    else sweep_rows<64, 8, MODE, 1>(d, sk, BIN_W8, b - g.nb[BIN_W4]);
   } else if (MODE == MODE_ROUND) {
     sweep_long_chunk(d, sk, b - lfb, lds);
   }
@@ -720,12 +822,13 @@ __device__ __forceinline__ int rec_count_of(const Dev& d, int64_t t) {
 // one index per thread: the record stores of a wavefront stay contiguous and
 // the column decisions' loads overlap across lanes
 #define DEC_ITEMS 1
-#define DEC_TILE (PSL_BLOCK * DEC_ITEMS)
+#define DEC_BLOCK 1024
+#define DEC_TILE (DEC_BLOCK * DEC_ITEMS)
 
 // Column decisions of the touched columns (untouched ones cannot change: an
 // active column with unchanged bounds and rows is neither fixed nor empty),
 // and the record count of each tile of DEC_TILE indices.
-__global__ void __launch_bounds__(PSL_BLOCK) k_decide_count(Dev d, int32_t* tile_sum) {
+__global__ void __launch_bounds__(DEC_BLOCK) k_decide_count(Dev d, int32_t* tile_sum) {
   int64_t m = d.m, span = m + d.n;
   int64_t t0 = (int64_t)blockIdx.x * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
   int c = 0;
@@ -748,7 +851,7 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_decide_count(Dev d, int32_t* tile
     c += kk;
   }
   int tot;
-  block_excl_scan(c, &tot);
+  block_excl_scan_n<DEC_BLOCK>(c, &tot);
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.flags->rows_removed = 0;
@@ -828,7 +931,7 @@ __device__ __forceinline__ int emit_col(const Dev& d, int j, int round, Record* 
 // scanned tile sums, positions inside the tile from a block scan of the
 // counts. Also counts the removed rows and (batches) marks the LPs that
 // changed.
-__global__ void __launch_bounds__(PSL_BLOCK) k_decide_emit(Dev d, const int32_t* tile_off, int64_t base, int round) {
+__global__ void __launch_bounds__(DEC_BLOCK) k_decide_emit(Dev d, const int32_t* tile_off, int64_t base, int round) {
   int64_t m = d.m, span = m + d.n;
   int64_t t0 = (int64_t)blockIdx.x * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
   int cnt[DEC_ITEMS];
@@ -840,14 +943,14 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_decide_emit(Dev d, const int32_t*
     c += cnt[k];
   }
   int tot;
-  int pre = block_excl_scan(c, &tot);
+  int pre = block_excl_scan_n<DEC_BLOCK>(c, &tot);
   if (tot == 0) return;
   // removed rows of the tile: one atomic per workgroup
   int nrow = 0;
 #pragma unroll
   for (int k = 0; k < DEC_ITEMS; ++k) nrow += (t0 + k < m) ? cnt[k] : 0;
   int rtot;
-  block_excl_scan(nrow, &rtot);
+  block_excl_scan_n<DEC_BLOCK>(nrow, &rtot);
   if (rtot && threadIdx.x == 0) atomicAdd(&d.flags->rows_removed, rtot);
   Record* r = d.rec + base + tile_off[blockIdx.x] + pre;
   int fin = 0;
@@ -867,7 +970,7 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_decide_emit(Dev d, const int32_t*
     r += cnt[k];
   }
   int ftot;
-  block_excl_scan(fin, &ftot);
+  block_excl_scan_n<DEC_BLOCK>(fin, &ftot);
   if (ftot && threadIdx.x == 0) atomicAdd(&d.flags->fin_cols, ftot);
 }
 
@@ -921,9 +1024,9 @@ void launch_decide(const Dev& d, int64_t base, int round, int32_t* tile_sum, int
     fill_i32(&d.flags->rows_removed, 0, 1, s);
     return;
   }
-  hipLaunchKernelGGL(k_decide_count, dim3((unsigned)tiles), dim3(PSL_BLOCK), 0, s, d, tile_sum);
+  hipLaunchKernelGGL(k_decide_count, dim3((unsigned)tiles), dim3(DEC_BLOCK), 0, s, d, tile_sum);
   scan_excl(tile_sum, tile_off, tiles, &d.flags->round_total, ws, s);
-  hipLaunchKernelGGL(k_decide_emit, dim3((unsigned)tiles), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)tile_off, base,
+  hipLaunchKernelGGL(k_decide_emit, dim3((unsigned)tiles), dim3(DEC_BLOCK), 0, s, d, (const int32_t*)tile_off, base,
                      round);
 }
 
