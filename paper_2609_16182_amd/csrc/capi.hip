@@ -242,6 +242,7 @@ static psl_status setup_arena(psl_presolver* p) {
   // compaction
   ALLOC(p->cmp.row_new, m + 1);
   ALLOC(p->cmp.col_new, n + 1);
+  ALLOC(p->cmp.col_keep, n);
   ALLOC(p->cmp.terms, n);
   ALLOC(p->cmp.pws, pairwise_ws_doubles(n) + 2);
   ALLOC(p->cmp.totals, 4);

@@ -13,6 +13,8 @@
 
 namespace psl {
 
+// kept rows and columns (as counts to scan, and the columns also as bytes
+// for the position pass), the removed columns' cost terms
 __global__ void k_cmp_flags(Dev d, CompactScratch c) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -21,16 +23,20 @@ __global__ void k_cmp_flags(Dev d, CompactScratch c) {
     double2 b = d.bnd[j];
     bool kept = b.x != b.y;
     c.col_new[j] = kept;
+    c.col_keep[j] = kept;
     c.terms[j] = kept ? 0.0 : pos0(d.c[j] * b.x);
   }
-  for (int64_t p = t0; p <= d.nnz; p += stride) {
+}
+
+// kept positions of both layouts (a position is kept when its row and its
+// column are); the keep bytes are small enough to stay in cache
+__global__ void k_cmp_pos_flags(Dev d, CompactScratch c) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= d.nnz; p += stride) {
     int ef = 0, qf = 0;
     if (p < d.nnz) {
-      int row = c.rowid1[p + 1];
-      double2 b = d.bnd[d.ci[p]];
-      ef = d.row_on[row] && b.x != b.y;
-      double2 bq = d.bnd[c.colid[p]];
-      qf = d.row_on[d.ri[p]] && bq.x != bq.y;
+      ef = d.row_on[c.rowid1[p + 1]] & c.col_keep[d.ci[p]];
+      qf = d.row_on[d.ri[p]] & c.col_keep[c.colid[p]];
     }
     c.eflag[p] = ef;
     c.qflag[p] = qf;
@@ -131,6 +137,7 @@ void compact_flags(const Dev& d, const CompactScratch& c, hipStream_t s) {
   int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_cmp_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c);
+  hipLaunchKernelGGL(k_cmp_pos_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c);
   scan_excl(c.row_new, c.row_new, d.m, c.totals + 0, c.ws, s);
   scan_excl(c.col_new, c.col_new, d.n, c.totals + 1, c.ws, s);
   scan_excl(c.eflag, c.eflag, d.nnz + 1, c.totals + 2, c.ws, s);

@@ -174,17 +174,27 @@ const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, i
 // ---------------------------------------------------------------------------
 // row bins by CSR length, and the chunk table of long rows
 // ---------------------------------------------------------------------------
+// bin of every row, and the bin sizes (counted per wavefront by ballots, per
+// workgroup in LDS, then one global add per workgroup and bin)
 __global__ void k_bin_keys(Dev d, int32_t t_long, int32_t t_g8, uint32_t* keys, int32_t* counts) {
   __shared__ int c[NBINS];
   if (threadIdx.x < NBINS) c[threadIdx.x] = 0;
   __syncthreads();
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < d.m) {
-    int len = d.rp[i + 1] - d.rp[i];
-    uint32_t b = len <= 4 ? BIN_G4 : len <= t_g8 ? BIN_G8 : len <= 16 ? BIN_G16 : len > t_long ? BIN_LONG
-               : len <= 64 ? BIN_W1 : len <= 256 ? BIN_W4 : BIN_W8;
-    keys[i] = b;
-    atomicAdd(&c[b], 1);
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < d.m; i0 += stride) {
+    int64_t i = i0 + threadIdx.x;
+    int b = -1;
+    if (i < d.m) {
+      int len = d.rp[i + 1] - d.rp[i];
+      b = len <= 4 ? BIN_G4 : len <= t_g8 ? BIN_G8 : len <= 16 ? BIN_G16 : len > t_long ? BIN_LONG
+        : len <= 64 ? BIN_W1 : len <= 256 ? BIN_W4 : BIN_W8;
+      keys[i] = (uint32_t)b;
+    }
+#pragma unroll
+    for (int k = 0; k < NBINS; ++k) {
+      int cnt = __popcll(__ballot(b == k));
+      if (lane_id() == 0 && cnt) atomicAdd(&c[k], cnt);
+    }
   }
   __syncthreads();
   if (threadIdx.x < NBINS && c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], c[threadIdx.x]);
@@ -203,8 +213,8 @@ void build_bins(const Dev& d, const int32_t* thresholds, BinEnt* bins, int32_t* 
   fill_i32(counts, 0, NBINS, s);
   if (d.m == 0) return;
   unsigned blocks = (unsigned)((d.m + PSL_BLOCK - 1) / PSL_BLOCK);
-  hipLaunchKernelGGL(k_bin_keys, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, thresholds[0], thresholds[2], sc.k0,
-                     counts);
+  unsigned kb = blocks < 1024 ? blocks : 1024;
+  hipLaunchKernelGGL(k_bin_keys, dim3(kb), dim3(PSL_BLOCK), 0, s, d, thresholds[0], thresholds[2], sc.k0, counts);
   radix_pass(sc.k0, nullptr, sc.k1, sc.v0, d.m, 0, 3, sc.ws, s);
   hipLaunchKernelGGL(k_bin_fill, dim3(blocks), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)sc.v0, bins);
 }

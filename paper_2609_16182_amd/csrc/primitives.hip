@@ -9,12 +9,46 @@ namespace psl {
 #define SCAN_ITEMS 8
 #define SCAN_TILE (PSL_BLOCK * SCAN_ITEMS)
 
-__global__ void __launch_bounds__(PSL_BLOCK) k_scan_tile_sums(const int32_t* in, int64_t n, int32_t* sums) {
-  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-  int s = 0;
+static_assert(SCAN_ITEMS == 8, "load8 / store8 move eight ints");
+
+// eight consecutive ints from base (zero beyond n): two 16-byte loads when
+// all eight are in range and aligned, else one at a time
+__device__ __forceinline__ void load8(const int32_t* in, int64_t base, int64_t n, int (&v)[SCAN_ITEMS]) {
+  if (base + SCAN_ITEMS <= n && (((uintptr_t)(in + base)) & 15) == 0) {
+    int4 a = *(const int4*)(in + base);
+    int4 b = *(const int4*)(in + base + 4);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+    v[4] = b.x;
+    v[5] = b.y;
+    v[6] = b.z;
+    v[7] = b.w;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) v[k] = base + k < n ? in[base + k] : 0;
+}
+
+__device__ __forceinline__ void store8(int32_t* out, int64_t base, int64_t n, const int (&v)[SCAN_ITEMS]) {
+  if (base + SCAN_ITEMS <= n && (((uintptr_t)(out + base)) & 15) == 0) {
+    *(int4*)(out + base) = make_int4(v[0], v[1], v[2], v[3]);
+    *(int4*)(out + base + 4) = make_int4(v[4], v[5], v[6], v[7]);
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k)
-    if (base + k < n) s += in[base + k];
+    if (base + k < n) out[base + k] = v[k];
+}
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_scan_tile_sums(const int32_t* in, int64_t n, int32_t* sums) {
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  load8(in, base, n, v);
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
   int tot;
   block_excl_scan(s, &tot);
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
@@ -24,21 +58,21 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_scan_tile_apply(const int32_t* in
                                                                const int32_t* tile_off, int32_t* total) {
   int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
+  load8(in, base, n, v);
   int s = 0;
 #pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    v[k] = base + k < n ? in[base + k] : 0;
-    s += v[k];
-  }
+  for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
   int tot;
   int pre = block_excl_scan(s, &tot);
   int off = tile_off ? tile_off[blockIdx.x] : 0;
   int run = off + pre;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
+    int x = v[k];
+    v[k] = run;
+    run += x;
   }
+  store8(out, base, n, v);
   if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
 }
 

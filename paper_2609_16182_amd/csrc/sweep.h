@@ -119,6 +119,7 @@ struct LpRed {           // bases of an LP's reduced problem in the batch's arra
 struct CompactScratch {
   int32_t* row_new;       // [m]     kept flags -> new row ids
   int32_t* col_new;       // [n]     kept flags -> new column ids
+  uint8_t* col_keep;      // [n]     kept columns (bytes)
   double* terms;          // [n]     cost terms of removed columns
   double* pws;            // pairwise-sum workspace; pws[0] = the sum
   int32_t* totals;        // [4]     m', n', nnz' (CSR), nnz' (transposed)
