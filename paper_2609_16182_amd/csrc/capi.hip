@@ -184,9 +184,10 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(cnt, m + n + 1);
   ALLOC(off, m + n + 1);
   ALLOC(p->bins_a, m);
-  ALLOC(p->bins_b, m);
   ALLOC(p->bins_s, m);
-  ALLOC(p->rebin_dev, 16);
+  ALLOC(p->sel_dev, 16);
+  ALLOC(p->sel_keep, select_keep_bytes(m));
+  ALLOC(p->sel_cnt, select_count_ints(m));
   ALLOC(p->bin_counts_dev, NBINS);
   ALLOC(p->lb_in, n);
   ALLOC(p->ub_in, n);
@@ -206,12 +207,11 @@ static psl_status setup_arena(psl_presolver* p) {
   p->long_cap = N / ((int64_t)p->thresholds[0] + 1) + 1;
   p->chunk_cap = N / PASS_LEN + p->long_cap + 1;
   ALLOC(p->chunks_a, p->chunk_cap);
-  ALLOC(p->chunks_b, p->chunk_cap);
   ALLOC(p->chunks_s, p->chunk_cap);
-  ALLOC(p->rb_keep, rebin_flag_bytes(m, p->chunk_cap));
-  ALLOC(p->rb_tiles, (m + p->chunk_cap) / 1024 + 8);
+  ALLOC(p->chunks_0, p->chunk_cap);
   uint8_t* dirty;
   ALLOC(dirty, m);
+  ALLOC(d.dirty_tile, m / 1024 + 2);
   ALLOC(d.touch, n);
   ALLOC(d.rinf, m);
   ALLOC(d.dense_cols, N / 4096 + 2);
@@ -295,7 +295,6 @@ static psl_status setup_arena(psl_presolver* p) {
     ALLOC(p->lp_off_in, K);
     ALLOC(p->rec_off, K + 1);
     ALLOC(p->bins_0, m);
-    ALLOC(p->chunks_0, p->chunk_cap);
     HALLOC(p->h_row0, K + 1);
     HALLOC(p->h_col0, K + 1);
     HALLOC(p->h_z0, K + 1);
@@ -331,6 +330,7 @@ static psl_status setup_arena(psl_presolver* p) {
   d.col_code = col_code;
   d.row_out = row_out;
   d.cand = cand;
+  d.chunks0 = p->chunks_0;
   d.cand_cnt = p->cand_cnt;
   d.flags = flags;
   d.cnt = cnt;
@@ -360,12 +360,12 @@ static psl_status setup_arena(psl_presolver* p) {
   const void* ptrs[] = {d.rp, d.ci, d.va, d.cp, d.ri, d.cva, d.lhs, d.rhs, d.bnd, d.bkey, d.src, d.c,
                         d.col_len, d.row_on, d.row_code, d.col_code, d.dirty, d.row_out, d.cand, d.cand_cnt,
                         d.flags, d.cnt, d.off, d.rec, d.bins, d.lchunk, d.lpart, d.lrow, p->lpr,
-                        d.dense_cols, d.n_dense, d.touch, d.rinf};
+                        d.dense_cols, d.n_dense, d.touch, d.rinf, d.chunks0, d.dirty_tile};
   for (const void* q : ptrs)
     if (!q) return fail(p, PSL_ERR_DEVICE, "internal: a device array was not set up");
   if (K > 1) {
     const void* bp[] = {d.row_lp, d.col_lp, d.lp_row0, d.lp_col0, d.lp_ok, d.lp_round, d.lpf, d.lpo, p->lpt,
-                        p->lp_z0, p->descs, p->lp_off_in, p->rec_off, p->bins_0, p->chunks_0};
+                        p->lp_z0, p->descs, p->lp_off_in, p->rec_off, p->bins_0};
     for (const void* q : bp)
       if (!q) return fail(p, PSL_ERR_DEVICE, "internal: a batch array was not set up");
   }
@@ -423,24 +423,31 @@ static View view_of(BinEnt* bins, LongChunk* chunks, const int32_t* tot) {
   return v;
 }
 
-// dst = the active rows of src (only the dirty ones when dirty is set)
-static psl_status filter_view(psl_presolver* p, const View& src, BinEnt* bout, LongChunk* cout, bool dirty,
-                              View& dst, bool inert = false) {
+// every active row of an LP still presolving (lp_ok), read back at once
+static psl_status full_view(psl_presolver* p, View& dst) {
   Dev& d = p->d;
-  rebin(d, src.bins, src.off, src.chunks, src.nchunks, bout, cout, dirty ? d.dirty : nullptr, inert, nullptr,
-        p->rb_keep, p->rb_tiles, p->rebin_dev, p->rebin_dev + NBINS + 1, p->ws, p->stream);
-  HIPCHK(p, hipMemcpyAsync(p->htot, p->rebin_dev, (NBINS + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
+  select_rows(d, nullptr, 0, p->thresholds[0], p->thresholds[2], p->sel_keep, p->sel_cnt, p->bins_a, p->chunks_a,
+              p->sel_dev, p->ws, p->stream);
+  HIPCHK(p, hipMemcpyAsync(p->htot, p->sel_dev, (NBINS + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
-  dst = view_of(bout, cout, p->htot);
+  dst = view_of(p->bins_a, p->chunks_a, p->htot);
   return PSL_OK;
 }
 
-// queue the next round's selection from src with the mode the device decided
+// sweep every active row from now on
+static psl_status use_full_view(psl_presolver* p) {
+  View v;
+  psl_status e = full_view(p, v);
+  if (e == PSL_OK) use_view(p, v);
+  return e;
+}
+
+// queue the next round's selection with the mode the device decided
 // (d.flags->mode); read with the round's flags
-static void queue_selection(psl_presolver* p, const View& src) {
+static void queue_selection(psl_presolver* p) {
   Dev& d = p->d;
-  rebin(d, src.bins, src.off, src.chunks, src.nchunks, p->bins_s, p->chunks_s, nullptr, false, &d.flags->mode,
-        p->rb_keep, p->rb_tiles, d.flags->sel, d.flags->sel + NBINS + 1, p->ws, p->stream);
+  select_rows(d, &d.flags->mode, 0, p->thresholds[0], p->thresholds[2], p->sel_keep, p->sel_cnt, p->bins_s,
+              p->chunks_s, d.flags->sel, p->ws, p->stream);
 }
 
 static std::string error_what(int32_t bits) {
@@ -504,7 +511,7 @@ static psl_status ingest_rest(psl_presolver* p) {
   // bins (before the transpose: both use k0/k1); a batch keeps the bins of
   // all its rows apart (the compaction starts from them)
   BinEnt* bins0 = p->K > 1 ? p->bins_0 : p->bins_a;
-  LongChunk* chunks0 = p->K > 1 ? p->chunks_0 : p->chunks_a;
+  LongChunk* chunks0 = p->chunks_0;  // kept intact: the row selections copy from it
   d.bins = bins0;
   d.lchunk = chunks0;
   build_bins(d, p->thresholds, bins0, p->bin_counts_dev, p->isc, st);
@@ -537,8 +544,6 @@ static psl_status ingest_rest(psl_presolver* p) {
   mv.nchunks = d.nchunks;
   mv.rows = m;
   mv.nnz = N;
-  p->master = mv;
-  p->all = mv;
   use_view(p, mv);
   if (p->grid.long_base + (int64_t)p->htot[1] > p->cand_cap)
     return fail(p, PSL_ERR_CAPACITY, "candidate buffer too small for the row bins");
@@ -802,16 +807,11 @@ static psl_status queue_lp_read(psl_presolver* p, bool totals) {
   return PSL_OK;
 }
 
-// K > 1: LPs that stopped leave the master bin lists
+// K > 1: LPs that stopped leave the row selections (the device clears
+// lp_ok itself for an LP found infeasible or unbounded)
 static psl_status drop_done_lps(psl_presolver* p) {
   for (int k = 0; k < p->K; ++k) p->h_ok[k] = p->lst[k].phase != LP_DONE;
   HIPCHK(p, hipMemcpyAsync(p->lp_ok, p->h_ok, p->K, hipMemcpyHostToDevice, p->stream));
-  View nv;
-  BinEnt* bo = p->master.bins == p->bins_a ? p->bins_b : p->bins_a;
-  LongChunk* co = p->master.chunks == p->chunks_a ? p->chunks_b : p->chunks_a;
-  psl_status e = filter_view(p, p->master, bo, co, false, nv);
-  if (e != PSL_OK) return e;
-  p->master = nv;
   return PSL_OK;
 }
 
@@ -899,14 +899,11 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       p->lst[k].cycles = 1;
       any_done = true;
     }
-  use_view(p, p->master);
   if (B && any_done) {
     e = drop_done_lps(p);
     if (e != PSL_OK) return e;
-    use_view(p, p->master);
   }
 
-  bool was_incremental = false;
   int outer = 0;
   for (; outer < s.max_outer; ++outer) {
     int nprop = 0;
@@ -916,6 +913,9 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
         ++nprop;
       }
     if (nprop == 0) break;
+    // a cycle's first round sweeps every active row
+    e = use_full_view(p);
+    if (e != PSL_OK) return e;
     for (int r = 0; r < s.max_rounds; ++r) {
       ++round;
       for (int k = 0; k < K; ++k)
@@ -934,23 +934,23 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       launch_src(d, p->grid, st);
       launch_decide(d, p->rec_count, round, d.cnt, d.off, p->ws, st);
       HIPCHK(p, hipEventRecord(p->ev[6], st));
-      // The next round's selection is queued before the round's one read.
-      // Rows none of whose columns changed since they were last swept give
-      // the same statistics and no qualifying candidate, so after a round
-      // with few column changes only the touched rows are swept; and inert
-      // rows (their infinite-contribution counts, kept current as bounds
-      // become finite, rule out every outcome) are never swept. The counts
-      // are kept by decrements while few bounds become finite in a round.
-      // After a round with many, no decrement is made and the next round
-      // skips no row: it sweeps, and so recounts, every row one of whose
-      // bounds became finite (they are dirty), while the counts of the rows
-      // it does not sweep are still exact; after it the counts are exact
-      // again. The device takes these decisions from the round's totals
+      // The next round's selection is made before the round's one read, in
+      // one pass over the rows. Rows none of whose columns changed since they
+      // were last swept give the same statistics and no qualifying candidate,
+      // so after a round with few column changes only the touched (marked)
+      // rows are swept; and inert rows (their infinite-contribution counts,
+      // kept current as bounds become finite, rule out every outcome) are
+      // never swept. The counts are kept by decrements while few bounds
+      // become finite in a round. After a round with many, no decrement is
+      // made and the next round skips no row: it sweeps, and so recounts,
+      // every row one of whose bounds became finite, while the counts of the
+      // rows it does not sweep are still exact; after it the counts are
+      // exact again. The device takes these decisions from the round's totals
       // (d.flags->mode); an LP that stopped has left lp_ok already. When the
       // rounds end here the selection is not used.
       if (!d.dirty || !d.colid) return fail(p, PSL_ERR_DEVICE, "internal: incremental state not set up");
-      mark_dirty(d, !was_incremental, r + 1 < s.max_rounds, p->incr_factor, p->count_factor, st);
-      queue_selection(p, p->master);
+      mark_dirty(d, r + 1 < s.max_rounds, p->incr_factor, p->count_factor, st);
+      queue_selection(p);
       e = queue_lp_read(p, true);
       if (e != PSL_OK) return e;
       int32_t removed = 0;
@@ -986,26 +986,12 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
                      "bounds made finite %d, LPs propagating %d\n", round, (long long)p->cur.rows,
                      (long long)p->cur.nnz, p->hflags->round_total, removed, p->hflags->fin_cols, nprop);
       if (nprop == 0) break;
-      View sel = view_of(p->bins_s, p->chunks_s, p->hflags->sel);
-      // keep the master lists on live rows once a sixteenth of them went (and
-      // on live LPs)
-      if ((removed > 0 && (int64_t)removed * 16 >= p->master.rows) || (B && any_done)) {
-        if (B) {
-          e = drop_done_lps(p);
-        } else {
-          View nv;
-          BinEnt* bo = p->master.bins == p->bins_a ? p->bins_b : p->bins_a;
-          LongChunk* co = p->master.chunks == p->chunks_a ? p->chunks_b : p->chunks_a;
-          e = filter_view(p, p->master, bo, co, false, nv);
-          p->master = nv;
-        }
+      if (B && any_done) {
+        e = drop_done_lps(p);
         if (e != PSL_OK) return e;
       }
-      use_view(p, sel);
-      was_incremental = (p->hflags->mode & 1) != 0;
+      use_view(p, view_of(p->bins_s, p->chunks_s, p->hflags->sel));
     }
-    use_view(p, p->master);
-    was_incremental = false;
     // the cycle's parallel-row pass, for every LP still presolving
     int npar = 0;
     for (auto& L : p->lst)
@@ -1021,7 +1007,8 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
         ++p->lst[k].rounds;
         if (B) p->h_round[k] = p->lst[k].rounds;
       }
-    e = ensure_capacity(p, m + 16);
+    e = use_full_view(p);
+    if (e == PSL_OK) e = ensure_capacity(p, m + 16);
     if (e == PSL_OK) e = begin_lp_round(p);
     if (e != PSL_OK) return e;
     HIPCHK(p, hipEventRecord(p->ev[4], st));
@@ -1055,7 +1042,6 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     if (B && any_done) {
       e = drop_done_lps(p);
       if (e != PSL_OK) return e;
-      use_view(p, p->master);
     }
   }
 
@@ -1069,13 +1055,9 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     if (B) {
       for (int k = 0; k < K; ++k) p->h_ok[k] = !p->lst[k].infeasible && !p->lst[k].unbounded;
       HIPCHK(p, hipMemcpyAsync(p->lp_ok, p->h_ok, K, hipMemcpyHostToDevice, st));
-      View cv;
-      e = filter_view(p, p->all, p->bins_s, p->chunks_s, false, cv);
-      if (e != PSL_OK) return e;
-      use_view(p, cv);
-    } else {
-      use_view(p, p->master);
     }
+    e = use_full_view(p);
+    if (e != PSL_OK) return e;
     HIPCHK(p, hipEventRecord(p->ev[4], st));
     launch_long_stats(d, MODE_COMPACT, st);
     launch_sweep(d, p->grid, MODE_COMPACT, st);

@@ -79,7 +79,6 @@ struct psl_presolver {
   std::vector<psl_result> lp_result;
   BinEnt* bins_0 = nullptr;  // the ingest bins of all rows
   LongChunk* chunks_0 = nullptr;
-  View all;
   // records split by LP
   Record* rec_lp = nullptr;
   int64_t split_cap = 0;
@@ -105,15 +104,14 @@ struct psl_presolver {
   SweepGrid grid{};
   int64_t chunk_cap = 0, long_cap = 0, cand_cap = 0;
   int32_t* cand_cnt = nullptr;
-  // bin views: the master lists hold the active rows (filtered after
-  // removals); a selection holds the active rows touched by a column change
-  // since they were last swept
-  BinEnt *bins_a = nullptr, *bins_b = nullptr, *bins_s = nullptr;
-  uint8_t* rb_keep = nullptr;     // keep decisions of the bin-list filter
-  int32_t* rb_tiles = nullptr;    // its tile counts / offsets
-  LongChunk *chunks_a = nullptr, *chunks_b = nullptr, *chunks_s = nullptr;
-  int32_t* rebin_dev = nullptr;  // [NBINS+1] new offsets, then 3 totals
-  View master, cur;
+  // bin views: a full view holds every active row (of an LP still
+  // presolving); a round's selection the rows the device chose for it
+  BinEnt *bins_a = nullptr, *bins_s = nullptr;
+  LongChunk *chunks_a = nullptr, *chunks_s = nullptr;
+  uint8_t* sel_keep = nullptr;   // per-row decisions of the row selection
+  int32_t* sel_cnt = nullptr;    // its per-tile counts / offsets
+  int32_t* sel_dev = nullptr;    // [NBINS+1] offsets, rows, nonzeros, chunks of a full view
+  View cur;
 
   // records
   Record* rec = nullptr;

@@ -267,178 +267,243 @@ void build_long_chunks(const Dev& d, int npass0, LongChunk* chunks, int32_t* cnt
                      chunks);
 }
 
-struct BinOffsets {
-  int32_t off[NBINS + 1];
+// ---------------------------------------------------------------------------
+// row selection: the rows a round sweeps, as bin lists and long-row chunks
+// ---------------------------------------------------------------------------
+// A pass over all rows in tiles of SEL_TILE (SEL_ITEMS a thread, striped so
+// the loads coalesce): a first launch takes each row's decision (one byte:
+// 0, or 1 + its bin) and counts, per tile, the kept rows of every bin, the
+// chunks of the kept long rows and the kept nonzeros; one scan of the counts
+// (bin-major) gives every tile its output offsets; a second launch writes the
+// kept rows in row order into contiguous bins and copies the kept long rows'
+// chunks from the ingest chunk table. The row data of a row is read only
+// when its cheap tests (active; marked, when only marked rows are wanted)
+// pass, so a selection of few marked rows reads about a byte per row.
+#define SEL_ITEMS 4
+#define SEL_TILE (PSL_BLOCK * SEL_ITEMS)
+static_assert(SEL_TILE == 1024, "a selection tile is a tile of the marks");
+#define SEL_COUNTS (NBINS + 2)  // rows per bin, long-row chunks, nonzeros
+
+size_t select_keep_bytes(int64_t m) { return (size_t)(m + 2 * SEL_TILE); }
+size_t select_count_ints(int64_t m) { return (size_t)(SEL_COUNTS * ((m + SEL_TILE - 1) / SEL_TILE + 1) + 2); }
+
+struct SelArgs {
+  const int32_t* mode_dev;  // the device's mode (bit 0: marked rows only; bit 1:
+  int mode_host;            // inert rows skipped), or mode_host without one
+  int t_long, t_g8;         // bin thresholds of the ingest
+  uint8_t* keep;            // per row: 0, or 1 + its bin
+  int32_t* cnt;             // SEL_COUNTS * T + 1 counts, scanned in place
 };
 
-// The filter works in tiles of RB_TILE items (RB_ITEMS per thread, striped so
-// the loads coalesce): the entry tiles of the bin list, then the tiles of the
-// chunk list. A first launch takes the keep decisions (one byte per item) and
-// counts each tile's kept items, a scan of the tile counts gives each tile's
-// output offset, and a second launch writes the kept items in input order.
-// The decisions are taken once: the second launch clears dirty flags, which
-// the chunks of a long row would otherwise read after its entry cleared them.
-#define RB_ITEMS 4
-#define RB_TILE (PSL_BLOCK * RB_ITEMS)
-
-size_t rebin_flag_bytes(int64_t nent, int64_t nch) { return (size_t)(nent + nch + 2 * RB_TILE); }
-
-struct RebinArgs {
-  const BinEnt* bins;
-  int32_t nent;
-  const LongChunk* chunks;
-  int32_t nch;
-  uint8_t* dirty;        // dirty flags (used when the mode asks for them)
-  int use_dirty, inert;  // filter mode, unless mode != nullptr
-  const int32_t* mode;   // device: bit 0 = dirty rows only, bit 1 = skip inert rows
-  uint8_t* keep;         // [T * RB_TILE] keep decisions
-};
-
-__device__ __forceinline__ void rebin_mode(const RebinArgs& a, const uint8_t*& dirty, bool& inert) {
-  int md = a.mode ? *a.mode : ((a.use_dirty ? 1 : 0) | (a.inert ? 2 : 0));
-  dirty = (md & 1) ? a.dirty : nullptr;
-  inert = (md & 2) != 0;
+// bin of a row of len entries (the bins of the ingest)
+__device__ __forceinline__ int bin_of_len(int len, int t_long, int t_g8) {
+  return len <= 4 ? BIN_G4 : len <= t_g8 ? BIN_G8 : len <= 16 ? BIN_G16 : len > t_long ? BIN_LONG
+       : len <= 64 ? BIN_W1 : len <= 256 ? BIN_W4 : BIN_W8;
 }
 
-// keep a bin entry (and the chunks of a long row) when its row is active, its
-// LP still presolving, with a dirty array touched by a column change since it
-// was last swept, and with inert set not inert; no short-circuit loads, so the
-// loads of a thread's items are in flight together
-__device__ __forceinline__ bool keep_row_flat(const Dev& d, int row, const uint8_t* dirty, bool inert) {
-  bool on = d.row_on[row] != 0;
-  bool dt = dirty ? dirty[row] != 0 : true;
-  bool lp = d.K == 1 ? true : d.lp_ok[d.row_lp[row]] != 0;
-  bool live = true;
-  if (inert) live = !row_inert(d.rinf[row], d.lhs[row], d.rhs[row]);
-  return on && dt && lp && live;
+// index of long row `row` in d.lrow (ascending rows; the row is long)
+__device__ __forceinline__ int long_row_index(const Dev& d, int row) {
+  int lo = 0, hi = d.nlong - 1;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (d.lrow[mid].row < row) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
 }
 
-__global__ void __launch_bounds__(PSL_BLOCK) k_rebin_count(Dev d, RebinArgs a, int te, int T, int32_t* tile_sum,
-                                                           int32_t* totals) {
-  int c = 0;
+__device__ __forceinline__ int sel_mode(const SelArgs& a) { return a.mode_dev ? *a.mode_dev : a.mode_host; }
+
+__global__ void __launch_bounds__(PSL_BLOCK) k_sel_count(Dev d, SelArgs a, int T) {
+  __shared__ int red[PSL_BLOCK / PSL_WAVE][SEL_COUNTS];
   int tile = blockIdx.x;
+  int mode = sel_mode(a);
+  int c[SEL_COUNTS];
+#pragma unroll
+  for (int j = 0; j < SEL_COUNTS; ++j) c[j] = 0;
+  // marked rows only: a tile without a mark keeps nothing (its keep bytes
+  // are not read)
+  if ((mode & 1) && tile < T && !d.dirty_tile[tile]) {
+    if (threadIdx.x < SEL_COUNTS) a.cnt[(int64_t)threadIdx.x * T + tile] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[(int64_t)SEL_COUNTS * T] = 0;
+    return;
+  }
   if (tile < T) {
-    const uint8_t* dirty;
-    bool inert;
-    rebin_mode(a, dirty, inert);
-    bool ct = tile >= te;
-    int64_t base = (int64_t)(ct ? tile - te : tile) * RB_TILE + threadIdx.x;
-    int64_t lim = ct ? a.nch : a.nent;
-    int rows[RB_ITEMS];
+    // level by level for all items, without branches around the loads (a
+    // row that fails the cheap tests reads row 0's data, which is cached)
+    int64_t i[SEL_ITEMS];
+    bool cand[SEL_ITEMS];
 #pragma unroll
-    for (int k = 0; k < RB_ITEMS; ++k) {
-      int64_t idx = base + (int64_t)k * PSL_BLOCK;
-      rows[k] = idx < lim ? (ct ? a.chunks[idx].row : a.bins[idx].row) : -1;
+    for (int k = 0; k < SEL_ITEMS; ++k) {
+      i[k] = (int64_t)tile * SEL_TILE + k * PSL_BLOCK + threadIdx.x;
+      int64_t ii = i[k] < d.m ? i[k] : 0;
+      uint8_t on = d.row_on[ii], dt = d.dirty[ii];
+      cand[k] = i[k] < d.m && on != 0 && (!(mode & 1) || dt != 0);
+    }
+    int r0[SEL_ITEMS], r1[SEL_ITEMS], lpi[SEL_ITEMS];
+    int2 rf[SEL_ITEMS];
+    double lh[SEL_ITEMS], rh[SEL_ITEMS];
+#pragma unroll
+    for (int k = 0; k < SEL_ITEMS; ++k) {
+      int64_t jj = cand[k] ? i[k] : 0;
+      r0[k] = d.rp[jj];
+      r1[k] = d.rp[jj + 1];
+      lpi[k] = d.K > 1 ? d.row_lp[jj] : 0;
+      if (mode & 2) {
+        rf[k] = d.rinf[jj];
+        lh[k] = d.lhs[jj];
+        rh[k] = d.rhs[jj];
+      }
     }
 #pragma unroll
-    for (int k = 0; k < RB_ITEMS; ++k) {
-      bool f = keep_row_flat(d, rows[k] >= 0 ? rows[k] : 0, dirty, inert) & (rows[k] >= 0);
-      a.keep[(int64_t)tile * RB_TILE + k * PSL_BLOCK + threadIdx.x] = f ? 1 : 0;
-      c += f;
+    for (int k = 0; k < SEL_ITEMS; ++k) {
+      bool keep = cand[k];
+      if (d.K > 1) keep = keep && d.lp_ok[lpi[k]] != 0;
+      if (mode & 2) keep = keep && !row_inert(rf[k], lh[k], rh[k]);
+      uint8_t kb = 0;
+      if (keep) {
+        int len = r1[k] - r0[k];
+        int bin = bin_of_len(len, a.t_long, a.t_g8);
+        kb = (uint8_t)(1 + bin);
+#pragma unroll
+        for (int b = 0; b < NBINS; ++b) c[b] += bin == b;
+        if (bin == BIN_LONG) c[NBINS] += d.lrow[long_row_index(d, (int)i[k])].nchunk;
+        c[NBINS + 1] += len;
+      }
+      a.keep[(int64_t)tile * SEL_TILE + k * PSL_BLOCK + threadIdx.x] = kb;
     }
   }
-  int tot;
-  block_excl_scan(c, &tot);
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    tile_sum[T] = 0;
-    totals[1] = 0;  // kept nonzeros, summed by the scatter
-  }
-}
-
-// tile_off: exclusive scan of the tile counts (T + 1 entries)
-__global__ void __launch_bounds__(PSL_BLOCK) k_rebin_scatter(RebinArgs a, int te, int T, const int32_t* tile_off,
-                                                             BinEnt* out, LongChunk* cout, BinOffsets old,
-                                                             int32_t* new_off, int32_t* totals) {
-  __shared__ int wcnt[RB_ITEMS][PSL_BLOCK / PSL_WAVE];
   int w = threadIdx.x >> 6;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    totals[0] = tile_off[te];
-    totals[2] = tile_off[T] - tile_off[te];
+  // a tile without kept rows (most tiles of a round that sweeps few marked
+  // rows) writes zeros without the reductions
+  if (!__syncthreads_or(c[NBINS + 1] != 0 || c[BIN_G4] + c[BIN_G8] + c[BIN_G16] + c[BIN_W1] + c[BIN_W4] + c[BIN_W8] +
+                                                    c[BIN_LONG] != 0)) {
+    if (threadIdx.x < SEL_COUNTS && tile < T) a.cnt[(int64_t)threadIdx.x * T + tile] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[(int64_t)SEL_COUNTS * T] = 0;
+    return;
   }
-  if (blockIdx.x == 0 && threadIdx.x <= NBINS && old.off[threadIdx.x] == a.nent)
-    new_off[threadIdx.x] = tile_off[te];
-  int tile = blockIdx.x;
-  if (tile >= T) return;
-  bool ct = tile >= te;
-  int64_t base_idx = (int64_t)(ct ? tile - te : tile) * RB_TILE + threadIdx.x;
-  bool f[RB_ITEMS];
-  int pre[RB_ITEMS];
 #pragma unroll
-  for (int k = 0; k < RB_ITEMS; ++k) {
-    f[k] = a.keep[(int64_t)tile * RB_TILE + k * PSL_BLOCK + threadIdx.x] != 0;
-    unsigned long long bal = __ballot(f[k]);
-    pre[k] = __popcll(bal & lanemask_lt());
-    if (lane_id() == 0) wcnt[k][w] = __popcll(bal);
+  for (int j = 0; j < SEL_COUNTS; ++j) {
+    int x = c[j];
+#pragma unroll
+    for (int o = 1; o < PSL_WAVE; o <<= 1) x += __shfl_xor(x, o, PSL_WAVE);
+    if (lane_id() == 0) red[w][j] = x;
   }
   __syncthreads();
-  // exclusive prefix of item (k, thread) in index order (k-major)
-  int run = 0;
+  if (threadIdx.x < SEL_COUNTS && tile < T) {
+    int x = 0;
 #pragma unroll
-  for (int k = 0; k < RB_ITEMS; ++k) {
-    int row_tot = 0, before = 0;
-#pragma unroll
-    for (int v = 0; v < PSL_BLOCK / PSL_WAVE; ++v) {
-      int c = wcnt[k][v];
-      row_tot += c;
-      if (v < w) before += c;
-    }
-    pre[k] += run + before;
-    run += row_tot;
+    for (int v = 0; v < PSL_BLOCK / PSL_WAVE; ++v) x += red[v][threadIdx.x];
+    a.cnt[(int64_t)threadIdx.x * T + tile] = x;
   }
-  int64_t base = (int64_t)tile_off[tile] - (ct ? tile_off[te] : 0);
-  const uint8_t* dirty;
-  bool inert;
-  rebin_mode(a, dirty, inert);
-  int len = 0;
-#pragma unroll
-  for (int k = 0; k < RB_ITEMS; ++k) {
-    int64_t idx = base_idx + (int64_t)k * PSL_BLOCK;
-    int64_t pos = base + pre[k];
-    if (!ct) {
-      if (idx < a.nent) {
-#pragma unroll
-        for (int b = 0; b <= NBINS; ++b)
-          if (old.off[b] == idx) new_off[b] = (int32_t)pos;
-      }
-      if (f[k]) {
-        BinEnt be = a.bins[idx];
-        out[pos] = be;
-        len += be.len;
-        if (dirty) a.dirty[be.row] = 0;  // swept now
-      }
-    } else if (f[k]) {
-      cout[pos] = a.chunks[idx];
-    }
-  }
-  int tot;
-  block_excl_scan(len, &tot);
-  if (tot && threadIdx.x == 0) atomicAdd(&totals[1], tot);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt[(int64_t)SEL_COUNTS * T] = 0;
 }
 
-void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const LongChunk* chunks_in, int32_t nch,
-           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, const int32_t* mode,
-           uint8_t* keep, int32_t* tile_sum, int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s) {
-  BinOffsets bo;
-  for (int b = 0; b <= NBINS; ++b) bo.off[b] = off_in[b];
-  RebinArgs a;
-  a.bins = bins_in;
-  a.nent = off_in[NBINS];
-  a.chunks = chunks_in;
-  a.nch = nch;
-  a.dirty = mode ? d.dirty : dirty;
-  a.use_dirty = dirty != nullptr;
-  a.inert = inert ? 1 : 0;
-  a.mode = mode;
-  a.keep = keep;
-  int te = (int)(((int64_t)a.nent + RB_TILE - 1) / RB_TILE);
-  int tc = (int)(((int64_t)nch + RB_TILE - 1) / RB_TILE);
-  int T = te + tc;
+// out: bin lists; cout: chunk list; sel: offsets [0..NBINS], rows, nonzeros,
+// chunks. Kept rows are swept now: their marks are cleared.
+__global__ void __launch_bounds__(PSL_BLOCK) k_sel_scatter(Dev d, SelArgs a, int T, BinEnt* out, LongChunk* cout,
+                                                           int32_t* sel) {
+  __shared__ int wc[SEL_ITEMS][NBINS + 1][PSL_BLOCK / PSL_WAVE];  // per item row, bin (and chunks), wave
+  const int32_t* off = a.cnt;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int64_t R = (int64_t)NBINS * T, C = (int64_t)(NBINS + 1) * T, Z = (int64_t)(NBINS + 2) * T;
+    for (int b = 0; b < NBINS; ++b) sel[b] = off[(int64_t)b * T];
+    sel[NBINS] = off[R];
+    sel[NBINS + 1] = off[R];
+    sel[NBINS + 2] = off[Z] - off[C];
+    sel[NBINS + 3] = off[C] - off[R];
+  }
+  int tile = blockIdx.x;
+  if (tile >= T) return;
+  __shared__ int marked;
+  if (threadIdx.x == 0) {
+    marked = d.dirty_tile[tile];
+    d.dirty_tile[tile] = 0;  // the tile's marks are taken now (rows not kept keep
+                             // theirs, harmlessly: a change marks them again)
+  }
+  __syncthreads();
+  if ((sel_mode(a) & 1) && !marked) return;
+  int w = threadIdx.x >> 6;
+  int kb[SEL_ITEMS], nch[SEL_ITEMS], pre[SEL_ITEMS], cpre[SEL_ITEMS], r0[SEL_ITEMS], r1[SEL_ITEMS];
+  int64_t row[SEL_ITEMS];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < SEL_ITEMS; ++k) {
+    row[k] = (int64_t)tile * SEL_TILE + k * PSL_BLOCK + threadIdx.x;
+    kb[k] = a.keep[row[k]];
+    any |= kb[k] != 0;
+  }
+  if (!__syncthreads_or(any)) return;  // nothing kept in this tile
+#pragma unroll
+  for (int k = 0; k < SEL_ITEMS; ++k) {
+    int64_t jj = kb[k] ? row[k] : 0;  // a row not kept reads row 0 (cached)
+    r0[k] = d.rp[jj];
+    r1[k] = d.rp[jj + 1];
+  }
+#pragma unroll
+  for (int k = 0; k < SEL_ITEMS; ++k) {
+    nch[k] = 0;
+    if (kb[k] == 1 + BIN_LONG) nch[k] = d.lrow[long_row_index(d, (int)row[k])].nchunk;
+    // rank among this wave's lanes of the same bin, and the chunk counts
+    // before this lane in the wave (inclusive scan minus own)
+    int b = kb[k] - 1;
+    pre[k] = 0;
+#pragma unroll
+    for (int bb = 0; bb < NBINS; ++bb) {
+      unsigned long long bal = __ballot(b == bb);
+      if (b == bb) pre[k] = __popcll(bal & lanemask_lt());
+      if (lane_id() == 0) wc[k][bb][w] = __popcll(bal);
+    }
+    int x = nch[k];
+#pragma unroll
+    for (int o = 1; o < PSL_WAVE; o <<= 1) {
+      int y = __shfl_up(x, o, PSL_WAVE);
+      if (lane_id() >= o) x += y;
+    }
+    cpre[k] = x - nch[k];
+    if (lane_id() == PSL_WAVE - 1) wc[k][NBINS][w] = x;
+  }
+  __syncthreads();
+  // exclusive prefix of every (item row, wave) count in row order, per bin
+  // (and for the chunks): one thread per bin
+  if (threadIdx.x <= NBINS) {
+    int run = 0;
+#pragma unroll
+    for (int kk = 0; kk < SEL_ITEMS; ++kk)
+#pragma unroll
+      for (int v = 0; v < PSL_BLOCK / PSL_WAVE; ++v) {
+        int x = wc[kk][threadIdx.x][v];
+        wc[kk][threadIdx.x][v] = run;
+        run += x;
+      }
+  }
+  __syncthreads();
+  int cbase = off[(int64_t)NBINS * T + tile] - off[(int64_t)NBINS * T];
+#pragma unroll
+  for (int k = 0; k < SEL_ITEMS; ++k) {
+    int b = kb[k] - 1;
+    if (b < 0) continue;
+    int64_t i = row[k];
+    int start = r0[k];
+    int len = r1[k] - start;
+    out[off[(int64_t)b * T + tile] + wc[k][b][w] + pre[k]] = BinEnt{(int)i, start, len, 0};
+    d.dirty[i] = 0;
+    if (nch[k]) {
+      LongRow lr = d.lrow[long_row_index(d, (int)i)];
+      int cb = wc[k][NBINS][w] + cpre[k];
+      for (int c = 0; c < lr.nchunk; ++c) cout[cbase + cb + c] = d.chunks0[lr.chunk0 + c];
+    }
+  }
+}
+
+void select_rows(const Dev& d, const int32_t* mode_dev, int mode_host, int t_long, int t_g8, uint8_t* keep,
+                 int32_t* cnt, BinEnt* out, LongChunk* cout, int32_t* sel, int32_t* ws, hipStream_t s) {
+  SelArgs a{mode_dev, mode_host, t_long, t_g8, keep, cnt};
+  int T = (int)((d.m + SEL_TILE - 1) / SEL_TILE);
   unsigned grid = (unsigned)(T > 0 ? T : 1);
-  hipLaunchKernelGGL(k_rebin_count, dim3(grid), dim3(PSL_BLOCK), 0, s, d, a, te, T, tile_sum, totals);
-  scan_excl(tile_sum, tile_sum, (int64_t)T + 1, nullptr, ws, s);
-  hipLaunchKernelGGL(k_rebin_scatter, dim3(grid), dim3(PSL_BLOCK), 0, s, a, te, T, (const int32_t*)tile_sum,
-                     bins_out, chunks_out, bo, new_off, totals);
+  hipLaunchKernelGGL(k_sel_count, dim3(grid), dim3(PSL_BLOCK), 0, s, d, a, T);
+  scan_excl(cnt, cnt, (int64_t)SEL_COUNTS * T + 1, nullptr, ws, s);
+  hipLaunchKernelGGL(k_sel_scatter, dim3(grid), dim3(PSL_BLOCK), 0, s, d, a, T, out, cout, sel);
 }
 
 // Rows of the columns whose bounds changed (or that were fixed) this round,
@@ -454,7 +519,10 @@ void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const Lon
 // contribution counts when the column's lb / ub became finite.
 __device__ __forceinline__ void mark_entry(const Dev& d, int64_t q, int code, bool mark, bool count) {
   int i = d.ri[q];
-  if (mark) d.dirty[i] = 1;
+  if (mark) {
+    d.dirty[i] = 1;
+    d.dirty_tile[i >> 10] = 1;
+  }
   if (count && (code & (CC_LBFIN | CC_UBFIN))) {
     bool pos = d.cva[q] > 0;
     bool lbf = (code & CC_LBFIN) != 0, ubf = (code & CC_UBFIN) != 0;
@@ -548,18 +616,7 @@ void list_dense_cols(const Dev& d, hipStream_t s) {
     hipLaunchKernelGGL(k_dense_cols, dim3((unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d);
 }
 
-__global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-void mark_dirty(const Dev& d, bool clear_first, bool allow_incremental, int incr_factor, int count_factor,
-                hipStream_t s) {
-  if (clear_first && d.m > 0) {
-    int64_t b = (d.m + PSL_BLOCK - 1) / PSL_BLOCK;
-    hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)(b > 4096 ? 4096 : b)), dim3(PSL_BLOCK), 0, s, d.dirty, (uint8_t)0,
-                       (int64_t)d.m);
-  }
+void mark_dirty(const Dev& d, bool allow_incremental, int incr_factor, int count_factor, hipStream_t s) {
   RoundMode rm{allow_incremental ? 1 : 0, incr_factor, count_factor};
   unsigned blocks = (unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK);
   hipLaunchKernelGGL(k_mark_sparse, dim3(blocks > 0 ? blocks : 1), dim3(PSL_BLOCK), 0, s, d, rm);
@@ -574,7 +631,9 @@ __global__ void k_init_state(Dev d) {
   if (t < d.m) {
     d.row_on[t] = 1;
     d.row_code[t] = RC_KEEP;
+    d.dirty[t] = 0;
   }
+  if (t <= d.m / 1024) d.dirty_tile[t] = 0;
   if (t < d.n) {
     double2 b = d.bnd[t];
     d.touch[t] = 1;  // the first round decides every column

@@ -135,6 +135,9 @@ struct Dev {
   int32_t *col_len;
   uint8_t *row_on, *row_code, *col_code;
   uint8_t *dirty;          // rows touched by a column change since last swept
+  uint8_t *dirty_tile;     // per 1024 rows: some row of it was marked (the row
+                           // selection skips the other tiles when it takes
+                           // marked rows only)
   const int32_t *rowid1;   // row of CSR position p at index p + 1 (built at ingest)
   int2 *rinf;              // per row: infinite min / max contributions at its last
                            // sweep, lowered as bounds of its columns become finite
@@ -151,6 +154,7 @@ struct Dev {
   const BinEnt *bins;
   int32_t bin_off[NBINS + 1];
   const LongChunk *lchunk;
+  const LongChunk *chunks0;    // chunk table of all long rows (built at ingest)
   LongPart *lpart;
   LongRow *lrow;
   int32_t nlong, nchunks;

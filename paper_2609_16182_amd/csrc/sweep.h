@@ -53,26 +53,24 @@ const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, i
 // bins: writes the bin lists and per-bin counts (device counts[NBINS])
 void build_bins(const Dev& d, const int32_t* thresholds, BinEnt* bins, int32_t* counts, IngestScratch& sc,
                 hipStream_t s);
-// keep the active rows (and, with dirty != nullptr, only the dirty ones,
-// whose flags are then cleared; with inert, only rows that are not inert) of
-// a bin list and chunk list: new_off [0..NBINS], totals = {kept rows, their
-// nonzeros, kept chunks} (device). With mode != nullptr (device) the filter
-// takes dirty (d.dirty) and inert from *mode instead: bit 0 and bit 1.
-// keep: rebin_flag_bytes(entries, chunks) bytes; tile_sum: one int per 1024
-// entries and chunks, plus three.
-size_t rebin_flag_bytes(int64_t nent, int64_t nch);
-void rebin(const Dev& d, const BinEnt* bins_in, const int32_t* off_in, const LongChunk* chunks_in, int32_t nch,
-           BinEnt* bins_out, LongChunk* chunks_out, uint8_t* dirty, bool inert, const int32_t* mode,
-           uint8_t* keep, int32_t* tile_sum, int32_t* new_off, int32_t* totals, int32_t* ws, hipStream_t s);
+// The rows a round sweeps: every active row of an LP still presolving (and,
+// by the mode, only the marked ones / none that is inert) as bin lists in row
+// order in out, the kept long rows' chunks (from d.chunks0) in cout, and
+// sel = {bin offsets [0..NBINS], rows, nonzeros, chunks} (device). The mode
+// is *mode_dev (device: bit 0 marked rows only, bit 1 inert rows skipped), or
+// mode_host when mode_dev is null. Kept rows' marks are cleared. keep:
+// select_keep_bytes(m) bytes, cnt: select_count_ints(m) ints.
+size_t select_keep_bytes(int64_t m);
+size_t select_count_ints(int64_t m);
+void select_rows(const Dev& d, const int32_t* mode_dev, int mode_host, int t_long, int t_g8, uint8_t* keep,
+                 int32_t* cnt, BinEnt* out, LongChunk* cout, int32_t* sel, int32_t* ws, hipStream_t s);
 // after a round: decide on the device the next round's mode (d.flags->mode:
 // bit 0 = sweep the touched rows only, allowed with allow_incremental when
 // fewer than n / incr_factor columns changed; bit 1 = keep the infinite-
 // contribution counts, when fewer than n / count_factor bounds became
 // finite); with bit 1, lower the counts of the rows of columns whose bounds
 // became finite; with bit 0, mark the rows of the changed columns dirty
-// (clearing all marks first with clear_first)
-void mark_dirty(const Dev& d, bool clear_first, bool allow_incremental, int incr_factor, int count_factor,
-                hipStream_t s);
+void mark_dirty(const Dev& d, bool allow_incremental, int incr_factor, int count_factor, hipStream_t s);
 // d.dense_cols / d.n_dense from the transposed copy (after build_csc)
 void list_dense_cols(const Dev& d, hipStream_t s);
 // chunk table of the long rows (d.nlong set); total chunks to *total (device)
