@@ -94,6 +94,8 @@ def _load(path=None):
     lib.or_reduced_copy.argtypes = [C.c_void_p] + [C.c_void_p] * 15
     lib.or_postsolve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     lib.or_postsolve.restype = C.c_int
+    lib.or_postsolve_dual.argtypes = [C.c_void_p] + [C.c_void_p] * 5
+    lib.or_postsolve_dual.restype = C.c_int
     lib.or_pairwise_sum.argtypes = [C.c_void_p, C.c_int64]
     lib.or_pairwise_sum.restype = C.c_double
     lib.or_row_key.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
@@ -152,6 +154,17 @@ class Result:
             raise OracleError("postsolve needs a reduced problem")
         return x
 
+    def postsolve_dual(self, x_red, y_red):
+        """(x, y, z) of the original LP from the reduced problem's primal
+        solution and row duals (z = c - A'y)."""
+        x_red = np.ascontiguousarray(x_red, np.float64)
+        y_red = np.ascontiguousarray(y_red, np.float64)
+        n, m = self.n_orig, self.m_orig
+        x, y, z = np.zeros(n), np.zeros(m), np.zeros(n)
+        if self._lib.or_postsolve_dual(self._h, _ptr(x_red), _ptr(y_red), _ptr(x), _ptr(y), _ptr(z)):
+            raise OracleError("postsolve needs a reduced problem")
+        return x, y, z
+
     def close(self):
         if self._h:
             self._lib.or_free(self._h)
@@ -195,6 +208,7 @@ def presolve(lp, lib_path=None, **settings):
         raise OracleError(msg)
     res = Result(lib, h)
     res.n_orig = n
+    res.m_orig = m
     return res
 
 

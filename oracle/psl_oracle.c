@@ -812,6 +812,88 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* postsolve (dual): row duals y[m] and reduced costs z[n] of the original LP */
+/* from the reduced problem's row duals y_red (section 2.1, "Postsolver";     */
+/* section 3.3 asks for primal and dual solutions of the original problem).   */
+/* Convention: c - A'y - z = 0; y_i >= 0 when row i is at lhs, <= 0 at rhs;   */
+/* z_j >= 0 when x_j is at lb, <= 0 at ub. The records are undone in reverse  */
+/* order:                                                                     */
+/*   BOUND_CHANGE  a bound tightened from row k (x_j <= (rhs_k - resmin)/a    */
+/*       and the like) that carries a multiplier -- z_j = c_j - a_j'y with    */
+/*       that bound's sign -- holds only because row k is at the side that    */
+/*       gave it, so the multiplier moves into that row: y_k += z_j / a_kj    */
+/*       (then z_j = 0). The other columns of row k are then at the bounds    */
+/*       the residual activity used, which are their bounds before this       */
+/*       round: a reduced cost this induces is carried by the next earlier    */
+/*       tightening of that bound, reached later in the reverse pass (a       */
+/*       chain of rounds is followed back to the original bounds). A bound    */
+/*       superseded by a later tightening has z_j = 0 by then.                */
+/*   LEADER_SIDES  the merged side of a parallel-row leader L that is active  */
+/*       (y_L > 0: lhs, y_L < 0: rhs) is the side of the row r that gave it,  */
+/*       with a_r = lambda_r a_L: y_r = y_L / lambda_r and y_L = 0.           */
+/*   every other record leaves y: rows removed as empty, redundant or         */
+/*       singleton start at y = 0 (a singleton's bounds reach it through the  */
+/*       bound changes it sourced), fixed and empty columns take their        */
+/*       reduced cost from z = c - A'y.                                       */
+/* Every z_j = c_j - sum_i a_ij y_i is summed over the column's rows in      */
+/* ascending order, left to right.                                            */
+/* ------------------------------------------------------------------------- */
+
+static double col_red_cost(const or_handle *h, const int32_t *cp, const int32_t *ri, const double *cva,
+                           const double *y, int32_t j) {
+    double s = 0.0;
+    for (int32_t q = cp[j]; q < cp[j + 1]; ++q) s = s + cva[q] * y[ri[q]];
+    return h->c[j] - s;
+}
+
+int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_red,
+                      double *x, double *y, double *z) {
+    if (h->result >= RES_INFEASIBLE) return 1;
+    if (or_postsolve(h, x_red, x)) return 1;
+    int32_t m = h->m, n = h->n;
+    for (int32_t i = 0; i < m; ++i) y[i] = 0.0;
+    for (int32_t ri0 = 0; ri0 < h->rm; ++ri0) y[h->r_rowmap[ri0]] = y_red[ri0];
+    /* the original matrix by columns (rows ascending within a column) */
+    int32_t *cp = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    int32_t *ri = (int32_t *)xcalloc((size_t)h->nnz, sizeof(int32_t));
+    double *cva = (double *)xcalloc((size_t)h->nnz, sizeof(double));
+    for (int64_t k = 0; k < h->nnz; ++k) cp[h->ci[k] + 1]++;
+    for (int32_t j = 0; j < n; ++j) cp[j + 1] += cp[j];
+    int32_t *fill = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    for (int32_t j = 0; j < n; ++j) fill[j] = cp[j];
+    for (int32_t i = 0; i < m; ++i)
+        for (int32_t k = h->rp[i]; k < h->rp[i + 1]; ++k) {
+            int32_t q = fill[h->ci[k]]++;
+            ri[q] = i;
+            cva[q] = h->va[k];
+        }
+    /* lambda of every row removed as parallel (a_r = lambda a_leader) */
+    double *lam = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    for (int64_t t = 0; t < h->nrec; ++t)
+        if (h->rec[t].type == REC_PARALLEL_ROW) lam[h->rec[t].i] = h->rec[t].v[0];
+    for (int64_t t = h->nrec - 1; t >= 0; --t) {
+        const or_record *r = &h->rec[t];
+        if (r->type == REC_BOUND_CHANGE) {
+            int32_t j = r->j, k = r->k;
+            if (k < 0) continue;
+            double zj = col_red_cost(h, cp, ri, cva, y, j);
+            if ((r->side == 0 && zj > 0.0) || (r->side == 1 && zj < 0.0)) y[k] = y[k] + zj / r->v[2];
+        } else if (r->type == REC_LEADER_SIDES) {
+            int32_t L = r->i;
+            double yl = y[L];
+            int32_t src = yl > 0.0 ? r->j : (yl < 0.0 ? r->k : -1);
+            if (src >= 0 && src != L) {
+                y[src] = yl / lam[src];
+                y[L] = 0.0;
+            }
+        }
+    }
+    for (int32_t j = 0; j < n; ++j) z[j] = col_red_cost(h, cp, ri, cva, y, j);
+    free(cp); free(ri); free(cva); free(fill); free(lam);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* accessors                                                                  */
 /* ------------------------------------------------------------------------- */
 

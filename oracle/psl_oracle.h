@@ -66,6 +66,12 @@ void or_reduced_copy(const or_handle *h, int32_t *row_ptr, int32_t *col_idx, dou
 /* primal postsolve: x_red[n_red] -> x[n] */
 int or_postsolve(const or_handle *h, const double *x_red, double *x);
 
+/* primal and dual postsolve: x_red[n_red], y_red[m_red] (row duals of the
+ * reduced problem) -> x[n], y[m], z[n] (z = c - A'y); convention and rules in
+ * the .c */
+int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_red,
+                      double *x, double *y, double *z);
+
 /* stand-alone pieces exposed for the pin tests */
 double or_pairwise_sum(const double *x, int64_t len);
 uint64_t or_row_key(const int32_t *cols, const double *vals, int64_t len);

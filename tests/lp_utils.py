@@ -151,3 +151,81 @@ def highs(lp):
 def reduced_lp(red):
     return {k: red[k] for k in ("m", "n", "row_ptr", "col_idx", "val", "lhs", "rhs",
                                 "lb", "ub", "c", "obj_offset")}
+
+
+def highs_duals(lp):
+    """Solve with scipy's HiGHS and return (status, x, y): x the primal
+    solution, y the row multipliers in the convention c - A'y - z = 0 with
+    y_i >= 0 when row i is at lhs and <= 0 at rhs (from the marginals of the
+    two one-sided inequalities of each row). Only 'optimal' carries x, y."""
+    from scipy.optimize import linprog
+    from scipy.sparse import csr_matrix, vstack
+    m, n = lp["m"], lp["n"]
+    if n == 0:
+        return "empty", np.zeros(0), np.zeros(m)
+    A = csr_matrix((lp["val"], lp["col_idx"], lp["row_ptr"]), shape=(m, n))
+    lhs, rhs = lp["lhs"], lp["rhs"]
+    up = np.flatnonzero(np.isfinite(rhs))
+    lo = np.flatnonzero(np.isfinite(lhs))
+    kw = {}
+    if len(up) + len(lo):
+        kw["A_ub"] = vstack([A[up], -A[lo]]).tocsr()
+        kw["b_ub"] = np.concatenate([rhs[up], -lhs[lo]])
+    bounds = [(None if not np.isfinite(l) else l, None if not np.isfinite(u) else u)
+              for l, u in zip(lp["lb"], lp["ub"])]
+    res = linprog(lp["c"], bounds=bounds, method="highs", **kw)
+    if res.status != 0:
+        return {2: "infeasible", 3: "unbounded"}.get(res.status, "other"), None, None
+    y = np.zeros(m)
+    if len(up) + len(lo):
+        mu = res.ineqlin.marginals
+        y[up] += mu[:len(up)]
+        y[lo] -= mu[len(up):]
+    return "optimal", res.x, y
+
+
+def kkt_violations(lp, x, y, z, tol=1e-6):
+    """Violations of the optimality conditions of lp at (x, y, z) with
+    z = c - A'y: primal feasibility, the signs of y and z against the active
+    sides and bounds (complementary slackness), and the duality gap. Returns
+    a list of messages (empty when optimal within tol)."""
+    A = dense(lp)
+    out = []
+    if not feasible(lp, x, tol=tol):
+        out.append("primal infeasible")
+    ax = A @ x
+    st = lp["c"] - A.T @ y - z
+    if np.max(np.abs(st), initial=0.0) > tol * max(1.0, np.max(np.abs(lp["c"]), initial=0.0)):
+        out.append("stationarity")
+    for i in range(lp["m"]):
+        sc = tol * max(1.0, abs(ax[i]))
+        ys = tol * max(1.0, np.max(np.abs(y), initial=0.0))
+        if y[i] > ys and not (np.isfinite(lp["lhs"][i]) and abs(ax[i] - lp["lhs"][i]) <= sc):
+            out.append(f"y[{i}]={y[i]:.3g} > 0 but row {i} not at lhs")
+        if y[i] < -ys and not (np.isfinite(lp["rhs"][i]) and abs(ax[i] - lp["rhs"][i]) <= sc):
+            out.append(f"y[{i}]={y[i]:.3g} < 0 but row {i} not at rhs")
+    zs = tol * max(1.0, np.max(np.abs(z), initial=0.0))
+    for j in range(lp["n"]):
+        sc = tol * max(1.0, abs(x[j]))
+        if z[j] > zs and not (np.isfinite(lp["lb"][j]) and abs(x[j] - lp["lb"][j]) <= sc):
+            out.append(f"z[{j}]={z[j]:.3g} > 0 but x[{j}] not at lb")
+        if z[j] < -zs and not (np.isfinite(lp["ub"][j]) and abs(x[j] - lp["ub"][j]) <= sc):
+            out.append(f"z[{j}]={z[j]:.3g} < 0 but x[{j}] not at ub")
+    # duality gap: c'x against the dual objective of the active sides and bounds
+    # (multipliers within the tolerance of zero count as zero)
+    ys = tol * max(1.0, np.max(np.abs(y), initial=0.0))
+    dual = 0.0
+    for i in range(lp["m"]):
+        if y[i] > ys:
+            dual += y[i] * lp["lhs"][i]
+        elif y[i] < -ys:
+            dual += y[i] * lp["rhs"][i]
+    for j in range(lp["n"]):
+        if z[j] > zs:
+            dual += z[j] * lp["lb"][j]
+        elif z[j] < -zs:
+            dual += z[j] * lp["ub"][j]
+    primal = float(lp["c"] @ x)
+    if abs(primal - dual) > 1e-5 * max(1.0, abs(primal)):
+        out.append(f"duality gap {primal - dual:.3g}")
+    return out
