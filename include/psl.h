@@ -45,7 +45,8 @@ typedef enum {
     PSL_ERR_DEVICE = 3,      /* a HIP call failed                              */
     PSL_ERR_STATE = 4,       /* call not valid in the handle's current state   */
     PSL_ERR_CAPACITY = 5,    /* a size limit of the library was exceeded       */
-    PSL_ERR_UNSUPPORTED = 6  /* feature not provided (e.g. dual postsolve)     */
+    PSL_ERR_UNSUPPORTED = 6  /* feature not provided (e.g. dual postsolve of a
+                                server ticket)                                 */
 } psl_status;
 
 typedef enum {
@@ -191,12 +192,26 @@ psl_status psl_reduced_problem(const psl_presolver *p, psl_reduced_view *out);
  * HOST array out[cap] (cap >= count, else PSL_ERR_CAPACITY). */
 psl_status psl_records(const psl_presolver *p, int64_t *count, psl_record *out, int64_t cap);
 
-/* Postsolve on the host (section 3.3): map a HOST solution x_red of the
- * reduced problem to x[n] of the original. Kept columns come from x_red,
- * removed columns from their FIX_COL / EMPTY_COL records; the other record
- * types keep the feasible set and leave x unchanged. y_red / z_red (dual
- * values) must be NULL: dual postsolve is not provided (PSL_ERR_UNSUPPORTED),
- * and y, z are then not written. */
+/* Postsolve on the host (section 2.1, "Postsolver"; section 3.3 asks for the
+ * primal and dual solutions of the original problem). All arrays are HOST
+ * memory.
+ *   Primal: x_red[n_red] -> x[n]. Kept columns come from x_red, removed
+ *   columns from their FIX_COL / EMPTY_COL records; the other record types
+ *   keep the feasible set and leave x unchanged.
+ *   Dual (when y_red != NULL): the reduced problem's row duals y_red[m_red]
+ *   -> row duals y[m] and reduced costs z[n] of the original LP, with the
+ *   convention c - A'y - z = 0, y_i >= 0 at lhs and <= 0 at rhs, z_j >= 0 at
+ *   lb and <= 0 at ub. Kept rows take y_red, other rows start at 0, and the
+ *   records are undone last to first: a BOUND_CHANGE with a source row k whose
+ *   column carries a multiplier of that bound's sign (z_j > 0 for a lower,
+ *   < 0 for an upper bound) moves it into row k (y_k += z_j / a_kj); a
+ *   LEADER_SIDES record whose leader L has an active merged side (y_L > 0:
+ *   lhs, < 0: rhs) moves y_L to the row r that gave that side
+ *   (y_r = y_L / lambda_r, y_L = 0); the other records keep y. Then
+ *   z = c - A'y, each a_j'y summed over column j's rows in ascending order,
+ *   left to right. The original matrix is read back from the device.
+ *   z_red is accepted and not read (the reduced costs follow from y); y and
+ *   z are written only when y_red is given. */
 psl_status psl_postsolve(psl_presolver *p, const double *x_red, const double *y_red,
                          const double *z_red, double *x, double *y, double *z);
 
@@ -257,7 +272,7 @@ psl_status psl_batch_reduced_problem(const psl_batch *b, int32_t idx, psl_reduce
 /* As psl_records, for LP idx (LP-local indices). */
 psl_status psl_batch_records(const psl_batch *b, int32_t idx, int64_t *count, psl_record *out, int64_t cap);
 
-/* As psl_postsolve, for LP idx (x has that LP's n entries). */
+/* As psl_postsolve, for LP idx (x, z have that LP's n entries, y its m). */
 psl_status psl_batch_postsolve(psl_batch *b, int32_t idx, const double *x_red, const double *y_red,
                                const double *z_red, double *x, double *y, double *z);
 
@@ -338,7 +353,9 @@ psl_status psl_server_reduced_problem(psl_server *sv, uint64_t ticket, psl_reduc
 /* The ticket's postsolve records (host copy; LP-local indices). */
 psl_status psl_server_records(psl_server *sv, uint64_t ticket, int64_t *count, psl_record *out, int64_t cap);
 
-/* As psl_postsolve, for the ticket's LP. */
+/* As psl_postsolve, for the ticket's LP, primal only: y_red / z_red must be
+ * NULL (PSL_ERR_UNSUPPORTED otherwise), since a done ticket keeps its reduced
+ * problem and records but not the original matrix the dual pass reads. */
 psl_status psl_server_postsolve(psl_server *sv, uint64_t ticket, const double *x_red, const double *y_red,
                                 const double *z_red, double *x, double *y, double *z);
 

@@ -960,7 +960,10 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       sweep_ms += elapsed(p, 7, 5);
       decide_ms += elapsed(p, 5, 6);
       S.sweep_launches += 1;
-      S.sweep_bytes += 12.0 * p->cur.nnz + 24.0 * p->cur.rows + 16.0 * n;
+      // algorithmic bytes: the swept rows' positions (12 B a nonzero), their
+      // bin entry, sides and outputs (24 B a row), and the bounds of the
+      // columns they can touch (16 B each, at most one per nonzero)
+      S.sweep_bytes += 12.0 * p->cur.nnz + 24.0 * p->cur.rows + 16.0 * std::min<int64_t>(n, p->cur.nnz);
       p->rec_count += p->hflags->round_total;
       any_done = false;
       nprop = 0;
@@ -1222,24 +1225,62 @@ extern "C" psl_status psl_records(const psl_presolver* cp, int64_t* count, psl_r
   return records_of(p, 0, count, out, cap);
 }
 
-// primal postsolve of LP k: kept columns from x_red, removed ones from their
-// FIX_COL / EMPTY_COL records; the other records keep the feasible set
+// LP k's columns of the original (canonicalised) LP and their costs, copied
+// to the host; rows numbered within the LP
+static psl_status host_cols(psl_presolver* p, int k, HostCols& A) {
+  int64_t c0 = p->K == 1 ? 0 : p->h_col0[k], c1 = p->K == 1 ? p->n : p->h_col0[k + 1];
+  int64_t r0 = p->K == 1 ? 0 : p->h_row0[k];
+  int64_t n = c1 - c0;
+  A.cp.resize(n + 1);
+  A.c.resize(n);
+  HIPCHK(p, hipMemcpy(A.cp.data(), p->d.cp + c0, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (n) HIPCHK(p, hipMemcpy(A.c.data(), p->d.c + c0, n * sizeof(double), hipMemcpyDeviceToHost));
+  int64_t q0 = A.cp[0], q1 = A.cp[n];
+  A.ri.resize(q1 - q0);
+  A.cva.resize(q1 - q0);
+  if (q1 > q0) {
+    HIPCHK(p, hipMemcpy(A.ri.data(), p->d.ri + q0, (q1 - q0) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(p, hipMemcpy(A.cva.data(), p->d.cva + q0, (q1 - q0) * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  for (auto& v : A.cp) v -= (int32_t)q0;
+  if (r0)
+    for (auto& v : A.ri) v -= (int32_t)r0;
+  return PSL_OK;
+}
+
+// postsolve of LP k: the primal solution, and with y_red the row duals and
+// reduced costs as well
 static psl_status postsolve_of(psl_presolver* p, int k, const double* x_red, const double* y_red,
-                               const double* z_red, double* x) {
-  if (y_red || z_red) return fail(p, PSL_ERR_UNSUPPORTED, "dual postsolve is not provided");
+                               const double* z_red, double* x, double* y, double* z) {
+  (void)z_red;  // reduced costs are recomputed from the row duals
   if (!has_reduced(p, k)) return fail(p, PSL_ERR_STATE, "no reduced problem to postsolve");
   psl_reduced_view v = reduced_view(p, k);
   int32_t n = p->K == 1 ? p->n : p->h_col0[k + 1] - p->h_col0[k];
+  int32_t m = p->K == 1 ? p->m : p->h_row0[k + 1] - p->h_row0[k];
   if ((n > 0 && !x) || (v.n > 0 && !x_red)) return fail(p, PSL_ERR_INVALID, "null solution array");
+  if (y_red && ((m > 0 && !y) || (n > 0 && !z) || (v.m > 0 && !y_red)))
+    return fail(p, PSL_ERR_INVALID, "null dual array");
   const std::vector<psl_record>* rec = nullptr;
   psl_status st = fetch_lp_records(p, k, &rec);
   if (st != PSL_OK) return st;
   std::string err;
   st = postsolve_primal(rec->data(), (int64_t)rec->size(), v.col_map, n, v.n, x_red, x, &err);
-  if (st != PSL_OK) p->err = err;
-  return st;
+  if (st != PSL_OK) {
+    p->err = err;
+    return st;
+  }
+  if (!y_red) return PSL_OK;
+  std::vector<int32_t> rmap(v.m);
+  if (v.m) HIPCHK(p, hipMemcpy(rmap.data(), v.row_map, v.m * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HostCols A;
+  st = host_cols(p, k, A);
+  if (st != PSL_OK) return st;
+  postsolve_dual(rec->data(), (int64_t)rec->size(), m, n, rmap, y_red, A, y, z);
+  return PSL_OK;
 }
 
+// primal postsolve: kept columns from x_red, removed ones from their FIX_COL /
+// EMPTY_COL records; the other records keep the feasible set
 psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
                                  int32_t n_red, const double* x_red, double* x, std::string* err) {
   std::vector<int32_t> cmap(n_red);
@@ -1256,12 +1297,60 @@ psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int
   return PSL_OK;
 }
 
+// Dual postsolve (sections 2.1 "Postsolver" and 3.3). Convention:
+// c - A'y - z = 0, y_i >= 0 at lhs and <= 0 at rhs, z_j >= 0 at lb and <= 0
+// at ub. The kept rows take the reduced duals, every other row starts at 0,
+// and the records are undone last to first:
+//  * a tightened bound whose column carries a multiplier of that bound's sign
+//    (z_j = c_j - a_j'y > 0 for a lower, < 0 for an upper bound) is binding
+//    only through its source row k, which sits at the side that implied it:
+//    the multiplier moves there, y_k += z_j / a_kj. The row's other columns
+//    then sit at the bounds its residual activity used (those before that
+//    round), so a reduced cost this creates for them is moved on by their
+//    own earlier tightenings further down the pass;
+//  * an active merged side of a parallel-row leader L (y_L > 0: lhs, < 0:
+//    rhs) belongs to the row r that gave it, a_r = lambda_r a_L:
+//    y_r = y_L / lambda_r and y_L = 0;
+//  * the other records keep y.
+// Finally z = c - A'y. Every a_j'y is summed over column j's rows in
+// ascending order, left to right.
+static double reduced_cost(const HostCols& A, const double* y, int32_t j) {
+  double s = 0.0;
+  for (int32_t q = A.cp[j]; q < A.cp[j + 1]; ++q) s = s + A.cva[q] * y[A.ri[q]];
+  return A.c[j] - s;
+}
+
+void psl::postsolve_dual(const psl_record* rec, int64_t count, int32_t m, int32_t n,
+                         const std::vector<int32_t>& row_map, const double* y_red, const HostCols& A, double* y,
+                         double* z) {
+  for (int32_t i = 0; i < m; ++i) y[i] = 0.0;
+  for (size_t t = 0; t < row_map.size(); ++t) y[row_map[t]] = y_red[t];
+  std::vector<double> lambda(m > 0 ? m : 1, 0.0);  // rows removed as parallel
+  for (int64_t t = 0; t < count; ++t)
+    if (rec[t].type == REC_PARALLEL_ROW) lambda[rec[t].i] = rec[t].v[0];
+  for (int64_t t = count - 1; t >= 0; --t) {
+    const psl_record& r = rec[t];
+    if (r.type == REC_BOUND_CHANGE && r.k >= 0) {
+      double zj = reduced_cost(A, y, r.j);
+      bool binding = r.side == 0 ? zj > 0.0 : zj < 0.0;
+      if (binding) y[r.k] = y[r.k] + zj / r.v[2];
+    } else if (r.type == REC_LEADER_SIDES) {
+      int32_t L = r.i;
+      double yl = y[L];
+      int32_t from = yl > 0.0 ? r.j : (yl < 0.0 ? r.k : -1);
+      if (from >= 0 && from != L) {
+        y[from] = yl / lambda[from];
+        y[L] = 0.0;
+      }
+    }
+  }
+  for (int32_t j = 0; j < n; ++j) z[j] = reduced_cost(A, y, j);
+}
+
 extern "C" psl_status psl_postsolve(psl_presolver* p, const double* x_red, const double* y_red, const double* z_red,
                                     double* x, double* y, double* z) {
-  (void)y;
-  (void)z;
   if (!p) return PSL_ERR_INVALID;
-  return postsolve_of(p, 0, x_red, y_red, z_red, x);
+  return postsolve_of(p, 0, x_red, y_red, z_red, x, y, z);
 }
 
 extern "C" void psl_presolve_free(psl_presolver* p) {
@@ -1437,10 +1526,8 @@ extern "C" psl_status psl_batch_records(const psl_batch* b, int32_t idx, int64_t
 
 extern "C" psl_status psl_batch_postsolve(psl_batch* b, int32_t idx, const double* x_red, const double* y_red,
                                           const double* z_red, double* x, double* y, double* z) {
-  (void)y;
-  (void)z;
   if (!batch_idx_ok(b, idx)) return PSL_ERR_INVALID;
-  return postsolve_of(b->p, idx, x_red, y_red, z_red, x);
+  return postsolve_of(b->p, idx, x_red, y_red, z_red, x, y, z);
 }
 
 extern "C" void psl_batch_free(psl_batch* b) {

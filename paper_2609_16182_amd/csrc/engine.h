@@ -170,6 +170,16 @@ void engine_lp_stats(const psl_presolver* p, int k, psl_stats* out);
 // primal postsolve on the host from records and the reduced column map
 psl_status postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
                             int32_t n_red, const double* x_red, double* x, std::string* err);
+// the original LP by columns, on the host, for dual postsolve: column j's
+// rows ascending in ri[cp[j]..cp[j+1]) with values cva, and the costs c
+struct HostCols {
+  std::vector<int32_t> cp, ri;
+  std::vector<double> cva, c;
+};
+// dual postsolve on the host (row duals y[m], reduced costs z[n] of the
+// original LP from the reduced problem's row duals y_red[m_red])
+void postsolve_dual(const psl_record* rec, int64_t count, int32_t m, int32_t n, const std::vector<int32_t>& row_map,
+                    const double* y_red, const HostCols& A, double* y, double* z);
 size_t engine_arena_bytes(const psl_presolver* p);
 
 }  // namespace psl

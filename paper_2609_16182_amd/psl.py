@@ -220,12 +220,32 @@ def psl_records(h):
     return out
 
 
-def psl_postsolve(h, x_red, n):
+def _post_args(x_red, y_red, m, n):
+    """Host arrays of a postsolve call: the argument pointers (x_red, y_red,
+    z_red, x, y, z) and the outputs (x, or x, y, z when y_red is given)."""
     x_red = np.ascontiguousarray(x_red, np.float64)
     x = np.zeros(n)
-    _check(load().psl_postsolve(h, x_red.ctypes.data if x_red.size else None, None, None,
-                                x.ctypes.data if n else None, None, None), h)
-    return x
+    keep = [x_red]
+    args = [x_red.ctypes.data if x_red.size else None, None, None, x.ctypes.data if n else None, None, None]
+    if y_red is None:
+        return args, keep, (x,)
+    y_red = np.ascontiguousarray(y_red, np.float64)
+    y, z = np.zeros(m), np.zeros(n)
+    keep.append(y_red)
+    # a non-null y_red asks for the dual pass even when the reduced LP has no rows
+    y_buf = y_red if y_red.size else np.zeros(1)
+    keep.append(y_buf)
+    args[1] = y_buf.ctypes.data
+    args[4] = y.ctypes.data if m else None
+    args[5] = z.ctypes.data if n else None
+    return args, keep, (x, y, z)
+
+
+def psl_postsolve(h, x_red, n, y_red=None, m=0):
+    """x, or (x, y, z) with y_red (row duals of the reduced LP; m rows)."""
+    args, keep, out = _post_args(x_red, y_red, m, n)
+    _check(load().psl_postsolve(h, *args), h)
+    return out[0] if len(out) == 1 else out
 
 
 def psl_presolve_free(h):
@@ -284,12 +304,10 @@ def psl_batch_records(b, idx):
     return out
 
 
-def psl_batch_postsolve(b, idx, x_red, n):
-    x_red = np.ascontiguousarray(x_red, np.float64)
-    x = np.zeros(n)
-    _bcheck(load().psl_batch_postsolve(b, idx, x_red.ctypes.data if x_red.size else None, None, None,
-                                       x.ctypes.data if n else None, None, None), b)
-    return x
+def psl_batch_postsolve(b, idx, x_red, n, y_red=None, m=0):
+    args, keep, out = _post_args(x_red, y_red, m, n)
+    _bcheck(load().psl_batch_postsolve(b, idx, *args), b)
+    return out[0] if len(out) == 1 else out
 
 
 def psl_tune(lps, settings: psl_settings, reps=3):
@@ -500,6 +518,7 @@ class Presolver:
     def __init__(self, lp, stream=None, **settings):
         self._keep = []
         self.n = int(lp["n"])
+        self.m = int(lp["m"])
         self.settings = make_settings(stream=stream, **settings)
         self.h = psl_presolve_create(make_lp(lp, self._keep), self.settings)
         self._keep.clear()
@@ -507,6 +526,8 @@ class Presolver:
     def reload(self, lp):
         keep = []
         psl_presolve_reload(self.h, make_lp(lp, keep))
+        self.n = int(lp["n"])
+        self.m = int(lp["m"])
 
     def run(self):
         res, st = psl_presolve_run(self.h)
@@ -525,8 +546,10 @@ class Presolver:
         """Copy of the reduced problem on the host (numpy)."""
         return reduced_to_host(self.view())
 
-    def postsolve(self, x_red):
-        return psl_postsolve(self.h, x_red, self.n)
+    def postsolve(self, x_red, y_red=None):
+        """x of the original LP, or (x, y, z) when the reduced LP's row duals
+        y_red are given."""
+        return psl_postsolve(self.h, x_red, self.n, y_red, self.m)
 
     def close(self):
         if getattr(self, "h", None):
@@ -560,6 +583,7 @@ class LpSet:
     def __init__(self, lps):
         self._keep = []
         self.ns = [int(lp["n"]) for lp in lps]
+        self.ms = [int(lp["m"]) for lp in lps]
         self.arr = lp_array([make_lp(lp, self._keep) for lp in lps])
 
     def __len__(self):
@@ -572,12 +596,14 @@ class Batch:
     def __init__(self, lps, stream=None, **settings):
         lset = lps if isinstance(lps, LpSet) else LpSet(lps)
         self.ns = list(lset.ns)
+        self.ms = list(lset.ms)
         self.settings = make_settings(stream=stream, **settings)
         self.h = psl_batch_create(lset.arr, self.settings)
 
     def reload(self, lps):
         lset = lps if isinstance(lps, LpSet) else LpSet(lps)
         self.ns = list(lset.ns)
+        self.ms = list(lset.ms)
         psl_batch_reload(self.h, lset.arr)
 
     def run(self):
@@ -598,8 +624,8 @@ class Batch:
     def reduced(self, idx):
         return reduced_to_host(self.view(idx))
 
-    def postsolve(self, idx, x_red):
-        return psl_batch_postsolve(self.h, idx, x_red, self.ns[idx])
+    def postsolve(self, idx, x_red, y_red=None):
+        return psl_batch_postsolve(self.h, idx, x_red, self.ns[idx], y_red, self.ms[idx])
 
     def close(self):
         if getattr(self, "h", None):

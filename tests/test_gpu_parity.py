@@ -162,9 +162,9 @@ def test_postsolve_matches_oracle():
     rng = np.random.default_rng(0)
     xr = rng.normal(size=got["reduced"]["n"])
     assert np.array_equal(p.postsolve(xr), ref.postsolve(xr))
-    x = np.zeros(lp["n"])
-    st = psl.load().psl_postsolve(p.h, xr.ctypes.data, xr.ctypes.data, None, x.ctypes.data, None, None)
-    assert st == psl.PSL_ERR_UNSUPPORTED  # dual postsolve is not provided
+    yr = rng.normal(size=got["reduced"]["m"])
+    for a, b in zip(p.postsolve(xr, yr), ref.postsolve_dual(xr, yr)):
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
     p.close()
 
 
