@@ -21,6 +21,9 @@
  *     section 3.2, "Parallel rows".
  *   - Emission of a reduced LP of the same form and primal recovery:
  *     section 3.3.
+ *   - Optional (off by default): dual fixing from variable locks recounted
+ *     on demand (section 3.2, "Internal data structures"; dual explorers,
+ *     section 2.1), see dual_fix below.
  *
  * Readings where the paper is silent (they define the round semantics that
  * the GPU library must reproduce bit for bit):
@@ -61,10 +64,13 @@ enum { RES_REDUCED = 0, RES_UNCHANGED = 1, RES_INFEASIBLE = 2, RES_UNBOUNDED = 3
  *  PARALLEL_ROW   i = removed row, k = leader; v = {lambda, lhs_i, rhs_i}
  *  LEADER_SIDES   i = leader, j = row giving lhs, k = row giving rhs;
  *                 v = {old lhs, old rhs, new lhs, new rhs}
+ *  DUAL_FIX       j, side (0 fixed at its lower, 1 at its upper bound);
+ *                 v = {value, c_j}
  */
 enum {
     REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
-    REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8
+    REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
+    REC_DUAL_FIX = 9
 };
 
 /* classes of the reduced problem's rows and columns (listed, not applied) */
@@ -205,6 +211,7 @@ static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s
     if (!(s->feas_tol >= 0) || !(s->fix_tol >= 0) || !(s->min_improve >= 0) ||
         !(s->par_tol >= 0) || !(s->inf_value > 0) || !(s->coef_tol >= 0))
         return fail(h, "invalid tolerance");
+    if (s->enable_dual_fix != 0 && s->enable_dual_fix != 1) return fail(h, "invalid dual-fix switch");
     if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return fail(h, "negative size");
     int32_t m = lp->m, n = lp->n;
     if (m > 0 && (!lp->row_ptr || !lp->lhs || !lp->rhs)) return fail(h, "null row array");
@@ -308,6 +315,7 @@ typedef struct {
     double *tmin, *tmax;       /* per-row scratch                  */
     uint8_t *dec;
     row_stats *st;
+    int32_t *down, *up;        /* variable locks (dual fixing)      */
 } round_ws;
 
 /* Implied bounds of row i on each of its active columns, from the residual
@@ -364,6 +372,38 @@ static double coef_in_row(const or_handle *h, int32_t i, int32_t j) {
     for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k)
         if (h->ci[k] == j) return h->va[k];
     return 0.0;
+}
+
+/* Variable locks (section 3.2, "Internal data structures"): down[j] counts
+ * the active rows that keep x_j from decreasing -- a > 0 with a finite lhs,
+ * or a < 0 with a finite rhs -- and up[j] those that keep it from increasing
+ * (a > 0 with a finite rhs, a < 0 with a finite lhs). Recounted from the rows
+ * whenever they are needed. */
+static void count_locks(const or_handle *h, int32_t *down, int32_t *up) {
+    for (int32_t j = 0; j < h->n; ++j) down[j] = up[j] = 0;
+    for (int32_t i = 0; i < h->m; ++i) {
+        if (!h->row_on[i]) continue;
+        int lfin = !isinf(h->lhs[i]), rfin = !isinf(h->rhs[i]);
+        for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k) {
+            int32_t j = h->ci[k];
+            if (h->va[k] > 0) { down[j] += lfin; up[j] += rfin; }
+            else { down[j] += rfin; up[j] += lfin; }
+        }
+    }
+}
+
+/* Dual fixing, the lock-based dual reduction (a dominated column): if no
+ * active row keeps x_j from moving towards the bound its cost prefers
+ * (c_j > 0: down, c_j < 0: up), some optimal solution has x_j at that bound
+ * (an infinite one means the LP is unbounded if it is feasible). With
+ * c_j = 0 either direction without locks and a finite bound will do, the
+ * lower bound first. Returns 1 with the value (possibly infinite) and side. */
+static int dual_fix(double c, double lo, double up, int32_t down, int32_t upl, double *v, int *side) {
+    if (c > 0 && down == 0) { *v = lo; *side = 0; return 1; }
+    if (c < 0 && upl == 0) { *v = up; *side = 1; return 1; }
+    if (c == 0 && down == 0 && !isinf(lo)) { *v = lo; *side = 0; return 1; }
+    if (c == 0 && upl == 0 && !isinf(up)) { *v = up; *side = 1; return 1; }
+    return 0;
 }
 
 static void drop_row(or_handle *h, int32_t i) {
@@ -430,7 +470,13 @@ static int run_round(or_handle *h, round_ws *w) {
         drop_row(h, i);
     }
 
-    /* columns: bound changes, fixings, empty columns; ascending column index */
+    /* locks of the rows still active after this round's removals */
+    if (s->enable_dual_fix) count_locks(h, w->down, w->up);
+
+    /* columns: bound changes, fixings, empty columns, dual fixings;
+     * ascending column index */
+    double dv;
+    int dside;
     for (int32_t j = 0; j < n; ++j) {
         if (!h->col_on[j]) continue;
         double lo = w->lb_n[j], up = w->ub_n[j];
@@ -456,6 +502,15 @@ static int run_round(or_handle *h, round_ws *w) {
             } else {
                 push(h, REC_EMPTY_COL, 0, -1, j, -1, v, cj, 0, 0);
                 h->lb[j] = h->ub[j] = v;
+                h->col_on[j] = 0;
+            }
+        } else if (s->enable_dual_fix && dual_fix(h->c[j], lo, up, w->down[j], w->up[j], &dv, &dside)) {
+            if (isinf(dv)) {
+                unbounded = 1;
+                h->lb[j] = lo; h->ub[j] = up;
+            } else {
+                push(h, REC_DUAL_FIX, dside, -1, j, -1, dv, h->c[j], 0, 0);
+                h->lb[j] = h->ub[j] = dv;
                 h->col_on[j] = 0;
             }
         } else {
@@ -744,6 +799,8 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     w.tmax = (double *)xcalloc((size_t)maxlen, sizeof(double));
     w.dec = (uint8_t *)xcalloc((size_t)m, 1);
     w.st = (row_stats *)xcalloc((size_t)m, sizeof(row_stats));
+    w.down = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    w.up = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
 
     int stop = 0;
     for (int outer = 0; outer < s->max_outer && !stop; ++outer) {
@@ -761,6 +818,7 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     }
     free(w.lb_s); free(w.ub_s); free(w.lb_n); free(w.ub_n);
     free(w.src_lb); free(w.src_ub); free(w.tmin); free(w.tmax); free(w.dec); free(w.st);
+    free(w.down); free(w.up);
 
     if (h->result < RES_INFEASIBLE) {
         h->result = h->nrec ? RES_REDUCED : RES_UNCHANGED;
@@ -796,7 +854,7 @@ int or_activities(const or_lp *lp, double *minact, double *maxact,
 
 /* ------------------------------------------------------------------------- */
 /* postsolve (primal): kept columns from the reduced solution, removed ones   */
-/* from their FIX_COL / EMPTY_COL records; every other record on the hot path */
+/* from their FIX_COL / EMPTY_COL / DUAL_FIX records; every other record      */
 /* keeps the feasible set and leaves x unchanged.                             */
 /* ------------------------------------------------------------------------- */
 
@@ -806,7 +864,7 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
     for (int32_t rj = 0; rj < h->rn; ++rj) x[h->r_colmap[rj]] = x_red[rj];
     for (int64_t t = h->nrec - 1; t >= 0; --t) {
         const or_record *r = &h->rec[t];
-        if (r->type == REC_FIX_COL || r->type == REC_EMPTY_COL) x[r->j] = r->v[0];
+        if (r->type == REC_FIX_COL || r->type == REC_EMPTY_COL || r->type == REC_DUAL_FIX) x[r->j] = r->v[0];
     }
     return 0;
 }
@@ -833,8 +891,10 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
 /*       with a_r = lambda_r a_L: y_r = y_L / lambda_r and y_L = 0.           */
 /*   every other record leaves y: rows removed as empty, redundant or         */
 /*       singleton start at y = 0 (a singleton's bounds reach it through the  */
-/*       bound changes it sourced), fixed and empty columns take their        */
-/*       reduced cost from z = c - A'y.                                       */
+/*       bound changes it sourced), fixed, empty and dual-fixed columns take  */
+/*       their reduced cost from z = c - A'y (a dual-fixed column has no      */
+/*       locks towards its bound, so the active rows' multipliers can only    */
+/*       push z_j further to that bound's sign).                              */
 /* Every z_j = c_j - sum_i a_ij y_i is summed over the column's rows in      */
 /* ascending order, left to right.                                            */
 /* ------------------------------------------------------------------------- */
