@@ -80,7 +80,7 @@ typedef struct {
  *   max_rounds 16, max_outer 4, enable_parallel_rows 1,
  *   feas_tol 1e-9, fix_tol 1e-9, min_improve 1e-7, par_tol 1e-9,
  *   inf_value 1e20, coef_tol 1e-9, bin thresholds from the tuner (NULL),
- *   device 0, stream NULL.
+ *   device 0, stream NULL, split_sweep 0, enable_dual_fix 0.
  * bin_thresholds (optional, n_bins = 2 or 3): [0] the longest row swept by one
  * 64-lane wavefront (16..512, default 512); [1] positions per workgroup chunk
  * of longer rows (a power of two >= 2048, default 2048); [2] the longest row
@@ -105,6 +105,18 @@ typedef struct {
     int32_t split_sweep;           /* 0: one row-sweep launch per round; 1: three
                                       (short rows, wavefront rows, long-row
                                       chunks). Speed only, never a result.     */
+    int32_t enable_dual_fix;       /* 1: dual fixing in every round (a dual
+                                      explorer, section 2.1, on variable locks,
+                                      section 3.2): after the round's row
+                                      removals, a column with no alive row
+                                      keeping it from moving towards the bound
+                                      its cost prefers (c > 0: down, c < 0: up,
+                                      c = 0: either, a finite bound, lower
+                                      first) is fixed there (DUAL_FIX); such a
+                                      bound at infinity gives
+                                      PSL_RES_UNBOUNDED_OR_INFEASIBLE. Keeps an
+                                      optimal solution, not the feasible set.
+                                      0 (default) or 1.                        */
 } psl_settings;
 
 /* Postsolve record: 48 bytes, emitted in the order (round, phase, index,
@@ -120,6 +132,8 @@ typedef struct {
  *   type 7 PARALLEL_ROW   i = removed row, k = leader; v = {lambda, lhs, rhs}
  *   type 8 LEADER_SIDES   i = leader, j = row giving lhs, k = row giving rhs;
  *                         v = {old lhs, old rhs, new lhs, new rhs}
+ *   type 9 DUAL_FIX       j, side (0 at its lower, 1 at its upper bound);
+ *                         v = {value, c_j} (only with enable_dual_fix)
  * round 0 holds input fixings; each propagation round and each parallel-row
  * pass has its own round number. */
 typedef struct {

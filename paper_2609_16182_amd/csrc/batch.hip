@@ -123,7 +123,8 @@ __global__ void k_rec_keys(Dev d, const Record* rec, int64_t count, uint32_t* ke
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   Record r = rec[t];
-  bool col = r.type == REC_FIX_COL || r.type == REC_EMPTY_COL || r.type == REC_BOUND_CHANGE;
+  bool col = r.type == REC_FIX_COL || r.type == REC_EMPTY_COL || r.type == REC_BOUND_CHANGE ||
+             r.type == REC_DUAL_FIX;
   keys[t] = (uint32_t)(col ? d.col_lp[r.j] : d.row_lp[r.i]);
 }
 
@@ -143,6 +144,7 @@ __global__ void k_rec_gather(Dev d, const Record* rec, const uint32_t* keys, con
   switch (r.type) {
     case REC_FIX_COL:
     case REC_EMPTY_COL:
+    case REC_DUAL_FIX:
       r.j = local_idx(r.j, j0);
       break;
     case REC_BOUND_CHANGE:

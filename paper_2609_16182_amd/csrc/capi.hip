@@ -90,6 +90,7 @@ extern "C" void psl_settings_default(psl_settings* s) {
   s->device = 0;
   s->stream = nullptr;
   s->split_sweep = 0;
+  s->enable_dual_fix = 0;
 }
 
 std::string psl::check_settings(const psl_settings* s) {
@@ -98,6 +99,7 @@ std::string psl::check_settings(const psl_settings* s) {
   if (!(s->feas_tol >= 0) || !(s->fix_tol >= 0) || !(s->min_improve >= 0) || !(s->par_tol >= 0) ||
       !(s->inf_value > 0) || !(s->coef_tol >= 0))
     return "invalid tolerance";
+  if (s->enable_dual_fix != 0 && s->enable_dual_fix != 1) return "enable_dual_fix must be 0 or 1";
   if (s->bin_thresholds) {
     if (s->n_bins != 2 && s->n_bins != 3) return "bin_thresholds needs n_bins = 2 or 3";
     int a = s->bin_thresholds[0], b = s->bin_thresholds[1];
@@ -213,6 +215,7 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(dirty, m);
   ALLOC(d.dirty_tile, m / 1024 + 2);
   ALLOC(d.touch, n);
+  ALLOC(d.locks, n);
   ALLOC(d.rinf, m);
   ALLOC(d.dense_cols, N / 4096 + 2);
   ALLOC(d.n_dense, 1);
@@ -354,10 +357,10 @@ static psl_status setup_arena(psl_presolver* p) {
   d.lpf = p->lpf;
   d.lpo = p->lpo;
   const psl_settings& s = p->s;
-  d.cfg = Cfg{s.feas_tol, s.fix_tol, s.min_improve, s.par_tol, s.inf_value, s.coef_tol};
+  d.cfg = Cfg{s.feas_tol, s.fix_tol, s.min_improve, s.par_tol, s.inf_value, s.coef_tol, s.enable_dual_fix};
   // every device array the kernels index must exist (allocations are >= 64 B
   // even for empty problems); colid is set once the transposed copy exists
-  const void* ptrs[] = {d.rp, d.ci, d.va, d.cp, d.ri, d.cva, d.lhs, d.rhs, d.bnd, d.bkey, d.src, d.c,
+  const void* ptrs[] = {d.rp, d.ci, d.va, d.cp, d.ri, d.cva, d.lhs, d.rhs, d.bnd, d.bkey, d.src, d.c, d.locks,
                         d.col_len, d.row_on, d.row_code, d.col_code, d.dirty, d.row_out, d.cand, d.cand_cnt,
                         d.flags, d.cnt, d.off, d.rec, d.bins, d.lchunk, d.lpart, d.lrow, p->lpr,
                         d.dense_cols, d.n_dense, d.touch, d.rinf, d.chunks0, d.dirty_tile};
@@ -884,6 +887,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   launch_round0_count(d, st);
   scan_excl(d.cnt, d.off, m + n, &d.flags->round_total, p->ws, st);
   launch_round0_emit(d, 0, st);
+  if (s.enable_dual_fix) init_locks(d, p->isc.v0, p->isc.v1, p->ws, st);  // ingest scratch, free until compaction
   psl_status e = queue_lp_read(p, false);
   if (e != PSL_OK) return e;
   e = read_flags(p);
@@ -1280,7 +1284,7 @@ static psl_status postsolve_of(psl_presolver* p, int k, const double* x_red, con
 }
 
 // primal postsolve: kept columns from x_red, removed ones from their FIX_COL /
-// EMPTY_COL records; the other records keep the feasible set
+// EMPTY_COL / DUAL_FIX records; the other records keep the feasible set
 psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
                                  int32_t n_red, const double* x_red, double* x, std::string* err) {
   std::vector<int32_t> cmap(n_red);
@@ -1292,7 +1296,7 @@ psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int
   for (int32_t t = 0; t < n_red; ++t) x[cmap[t]] = x_red[t];
   for (int64_t t = count - 1; t >= 0; --t) {
     const psl_record& r = rec[t];
-    if (r.type == REC_FIX_COL || r.type == REC_EMPTY_COL) x[r.j] = r.v[0];
+    if (r.type == REC_FIX_COL || r.type == REC_EMPTY_COL || r.type == REC_DUAL_FIX) x[r.j] = r.v[0];
   }
   return PSL_OK;
 }
@@ -1311,7 +1315,8 @@ psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int
 //  * an active merged side of a parallel-row leader L (y_L > 0: lhs, < 0:
 //    rhs) belongs to the row r that gave it, a_r = lambda_r a_L:
 //    y_r = y_L / lambda_r and y_L = 0;
-//  * the other records keep y.
+//  * the other records keep y (a dual-fixed column has no lock towards its
+//    bound, so the alive rows' multipliers only push z_j to that bound's sign).
 // Finally z = c - A'y. Every a_j'y is summed over column j's rows in
 // ascending order, left to right.
 static double reduced_cost(const HostCols& A, const double* y, int32_t j) {

@@ -647,10 +647,45 @@ __global__ void k_init_state(Dev d) {
     Flags f;
     f.infeasible = f.unbounded = f.error = f.merged = 0;
     f.cand_count = f.round_total = f.vlist_count = f.rows_removed = 0;
-    f.fin_cols = f.mode = 0;
+    f.fin_cols = f.mode = f.lead_count = 0;
     f.error_pos = 0x7FFFFFFFFFFFFFFFLL;
     *d.flags = f;
   }
+}
+
+// Variable locks of every column from the alive rows (dual fixing): one bit
+// per position of the transposed copy for each direction, scanned, and each
+// column's count read off as the difference of the scans at its ends.
+__global__ void k_lock_bits(Dev d, int32_t* dn, int32_t* up) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= d.nnz; q += stride) {
+    unsigned long long b = 0;
+    if (q < d.nnz) {
+      int i = d.ri[q];
+      if (d.row_on[i]) b = lock_bits(d.cva[q], d.lhs[i], d.rhs[i]);
+    }
+    dn[q] = (int32_t)(b & 1ull);
+    up[q] = (int32_t)(b >> 32);
+  }
+}
+
+__global__ void k_lock_cols(Dev d, const int32_t* dn, const int32_t* up) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d.n) return;
+  int q0 = d.cp[j], q1 = d.cp[j + 1];
+  unsigned long long down = (unsigned)(dn[q1] - dn[q0]), upc = (unsigned)(up[q1] - up[q0]);
+  d.locks[j] = down | (upc << 32);
+}
+
+void init_locks(const Dev& d, int32_t* dn, int32_t* up, int32_t* ws, hipStream_t s) {
+  if (d.n == 0) return;
+  int64_t blocks = (d.nnz + 1 + PSL_BLOCK - 1) / PSL_BLOCK;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_lock_bits, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, dn, up);
+  scan_excl(dn, dn, d.nnz + 1, nullptr, ws, s);
+  scan_excl(up, up, d.nnz + 1, nullptr, ws, s);
+  hipLaunchKernelGGL(k_lock_cols, dim3((unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d,
+                     (const int32_t*)dn, (const int32_t*)up);
 }
 
 void launch_init_state(const Dev& d, hipStream_t s) {

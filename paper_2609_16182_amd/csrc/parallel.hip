@@ -107,6 +107,7 @@ __global__ void k_par_reset(Dev d, ParScratch P) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.flags->vlist_count = 0;
     d.flags->merged = 0;
+    d.flags->lead_count = 0;
   }
 }
 
@@ -337,8 +338,34 @@ __global__ void k_par_count(Dev d, ParScratch P) {
     bool inf;
     if (leader_sides(d, P, (int)i, lo, up, inf)) k = 1;
     if (inf) flag_infeasible(d, row_lp_of(d, (int)i));
+    // a side that becomes finite locks the leader's columns (dual fixing):
+    // listed in P.slot, which the pass no longer reads
+    bool new_fin = (is_inf(d.lhs[i]) && !is_inf(lo)) || (is_inf(d.rhs[i]) && !is_inf(up));
+    if (d.cfg.dual_fix && new_fin) P.slot[atomicAdd(&d.flags->lead_count, 1)] = (int)i;
   }
   d.cnt[i] = k;
+}
+
+// the listed leaders' new locks, before their sides are replaced: one
+// wavefront per leader
+__global__ void __launch_bounds__(PSL_BLOCK) k_par_locks(Dev d, ParScratch P) {
+  int nl = d.flags->lead_count;
+  int wstride = gridDim.x * (PSL_BLOCK / PSL_WAVE);
+  for (int k = blockIdx.x * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6); k < nl; k += wstride) {
+    int i = P.slot[k];
+    double lo, up;
+    bool inf;
+    leader_sides(d, P, i, lo, up, inf);
+    unsigned long long lnew = is_inf(d.lhs[i]) && !is_inf(lo) ? 1ull : 0ull;
+    unsigned long long rnew = is_inf(d.rhs[i]) && !is_inf(up) ? 1ull : 0ull;
+    for (int p = d.rp[i] + lane_id(); p < d.rp[i + 1]; p += PSL_WAVE) {
+      int j = d.ci[p];
+      double2 b = d.bnd[j];
+      if (b.x == b.y) continue;
+      unsigned long long add = d.va[p] > 0 ? (lnew | (rnew << 32)) : (rnew | (lnew << 32));
+      if (add) atomicAdd(&d.locks[j], add);
+    }
+  }
 }
 
 __global__ void k_par_emit(Dev d, ParScratch P, int64_t base, int round) {
@@ -396,10 +423,11 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_drop(Dev d, ParScratch P) {
   for (int k = blockIdx.x * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6); k < nv; k += wstride) {
     int r = P.vlist[k];
     if (P.lead[r] < 0) continue;
+    double lhs = d.lhs[r], rhs = d.rhs[r];  // a removed row is no leader: its own sides
     for (int p = d.rp[r] + lane_id(); p < d.rp[r + 1]; p += PSL_WAVE) {
       int j = d.ci[p];
       double2 b = d.bnd[j];
-      if (b.x != b.y) drop_col(d, j);
+      if (b.x != b.y) drop_col(d, j, d.va[p], lhs, rhs);
     }
   }
 }
@@ -425,6 +453,7 @@ void launch_par_verify(const Dev& d, const ParScratch& p, hipStream_t s) {
 void launch_par_count(const Dev& d, const ParScratch& p, hipStream_t s) {
   if (d.m == 0) return;
   hipLaunchKernelGGL(k_par_count, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);
+  if (d.cfg.dual_fix) hipLaunchKernelGGL(k_par_locks, dim3(1024), dim3(PSL_BLOCK), 0, s, d, p);
 }
 
 void launch_par_emit(const Dev& d, const ParScratch& p, int64_t base, int round, hipStream_t s) {

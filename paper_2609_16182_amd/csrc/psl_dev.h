@@ -22,7 +22,8 @@ namespace psl {
 
 enum : uint8_t {
   REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
-  REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8
+  REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
+  REC_DUAL_FIX = 9
 };
 
 // row decision codes written by the sweep for the current round
@@ -33,6 +34,8 @@ enum : uint8_t {
   CC_LB = 1, CC_UB = 2, CC_FIX = 4, CC_EMPTY = 8, CC_UNBOUNDED = 16, CC_INFEAS = 32,
   CC_LBFIN = 64, CC_UBFIN = 128  // set at emission: lb (ub) went from infinite to finite
 };
+// a dual fixing sets both CC_FIX and CC_EMPTY (never set together otherwise)
+#define CC_DUALFIX (CC_FIX | CC_EMPTY)
 
 // row length bins: rows of <= 4 / <= 8 / <= 16 entries by 4- / 8- / 16-lane
 // groups (the 8-lane bin is optional: its bound is 4 or 8), rows of <= 64 /
@@ -108,10 +111,12 @@ struct Flags {
   int64_t error_pos;
   int32_t sel[NBINS + 4];  // the next round's selection: bin offsets [0..NBINS],
                            // rows, their nonzeros, long-row chunks
+  int32_t lead_count;      // parallel pass: leaders whose merged sides add locks
 };
 
 struct Cfg {
   double feas_tol, fix_tol, min_improve, par_tol, inf_value, coef_tol;
+  int32_t dual_fix;        // lock-based dual fixing on
 };
 
 struct HashSlot {
@@ -144,6 +149,8 @@ struct Dev {
   int32_t *dense_cols;     // columns of more than 4096 entries (listed at ingest)
   int32_t *n_dense;
   uint8_t *touch;          // columns whose decision may change this round
+  unsigned long long *locks;  // dual fixing: per column, the alive rows keeping it
+                              // from decreasing (low 32 bits) / increasing (high)
   const uint32_t *colid;   // column of each position of the transposed copy
   RowOut *row_out;
   Cand *cand;
@@ -175,12 +182,6 @@ __device__ __forceinline__ int row_lp_of(const Dev& d, int i) { return d.K > 1 ?
 __device__ __forceinline__ int col_lp_of(const Dev& d, int j) { return d.K > 1 ? d.col_lp[j] : 0; }
 // round number written into a record of LP lp
 __device__ __forceinline__ int round_of(const Dev& d, int lp, int round) { return d.K > 1 ? d.lp_round[lp] : round; }
-// a row removal takes column j out of that row; a column left in no row is
-// decided this round
-__device__ __forceinline__ void drop_col(const Dev& d, int j) {
-  if (atomicSub(&d.col_len[j], 1) == 1) d.touch[j] = 1;
-}
-
 // an LP that stops leaves the next selection at once
 __device__ __forceinline__ void flag_infeasible(const Dev& d, int lp) {
   atomicOr(&d.flags->infeasible, 1);
@@ -207,6 +208,27 @@ __device__ __forceinline__ double mx1(double x) {
   return a > 1.0 ? a : 1.0;
 }
 __device__ __forceinline__ bool is_inf(double x) { return __builtin_isinf(x); }
+
+// the locks one row puts on a column with coefficient a (down in the low
+// word, up in the high word): a > 0 with a finite lhs (a < 0: rhs) keeps the
+// column from decreasing, a > 0 with a finite rhs (a < 0: lhs) from increasing
+__device__ __forceinline__ unsigned long long lock_bits(double a, double lhs, double rhs) {
+  unsigned long long lf = is_inf(lhs) ? 0ull : 1ull, rf = is_inf(rhs) ? 0ull : 1ull;
+  return a > 0 ? (lf | (rf << 32)) : (rf | (lf << 32));
+}
+
+// a row removal takes column j (coefficient a, the row's sides lhs / rhs) out
+// of that row; a column left in no row is decided this round, and with dual
+// fixing so is every column that lost a row (it may have lost its last lock)
+__device__ __forceinline__ void drop_col(const Dev& d, int j, double a, double lhs, double rhs) {
+  int left = atomicSub(&d.col_len[j], 1) - 1;
+  if (d.cfg.dual_fix) {
+    atomicAdd(&d.locks[j], 0ull - lock_bits(a, lhs, rhs));  // the counts never go below 0
+    d.touch[j] = 1;
+  } else if (left == 0) {
+    d.touch[j] = 1;
+  }
+}
 
 // A row whose every finite side has at least two infinite contributions on
 // the side's residual, and that cannot be redundant, gives no candidate, no

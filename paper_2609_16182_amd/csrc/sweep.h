@@ -80,6 +80,9 @@ void build_long_chunks(const Dev& d, int npass0, LongChunk* chunks, int32_t* cnt
 void launch_round0_count(const Dev& d, hipStream_t s);
 void launch_round0_emit(const Dev& d, int64_t base, hipStream_t s);
 void launch_init_state(const Dev& d, hipStream_t s);
+// d.locks of every column from the alive rows (dual fixing); dn, up: nnz + 1
+// ints of scratch each, ws: scan workspace for nnz + 1 items
+void init_locks(const Dev& d, int32_t* dn, int32_t* up, int32_t* ws, hipStream_t s);
 
 // parallel.hip
 struct LpTab {        // an LP's slice of the parallel-row table

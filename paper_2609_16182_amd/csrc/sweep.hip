@@ -335,7 +335,8 @@ __device__ __forceinline__ void lane_prop_stream(const Dev& d, const CandSink& s
 }
 
 template <int C>
-__device__ __forceinline__ void lane_drop_stream(const Dev& d, bool on, int64_t s0, int len, int base) {
+__device__ __forceinline__ void lane_drop_stream(const Dev& d, bool on, int64_t s0, int len, int base, double lhs,
+                                                 double rhs) {
   constexpr int GS = C < STREAM_GROUP ? C : STREAM_GROUP;
 #pragma unroll 1
   for (int g = 0; g < C; g += GS) {
@@ -343,15 +344,15 @@ __device__ __forceinline__ void lane_drop_stream(const Dev& d, bool on, int64_t 
     load_els<GS>(d, s0, len, base + g, on, e);
 #pragma unroll
     for (int k = 0; k < GS; ++k)
-      if (el_active(e[k])) drop_col(d, e[k].j);
+      if (el_active(e[k])) drop_col(d, e[k].j, e[k].a, lhs, rhs);
   }
 }
 
 template <int C>
-__device__ __forceinline__ void lane_drop(const Dev& d, const El (&e)[C]) {
+__device__ __forceinline__ void lane_drop(const Dev& d, const El (&e)[C], double lhs, double rhs) {
 #pragma unroll
   for (int k = 0; k < C; ++k)
-    if (el_active(e[k])) drop_col(d, e[k].j);
+    if (el_active(e[k])) drop_col(d, e[k].j, e[k].a, lhs, rhs);
 }
 
 // ---------------------------------------------------------------------------
@@ -452,11 +453,11 @@ __device__ __forceinline__ void row_block(const Dev& d, const CandSink& sk, RowI
   if (live && gl == 0 && (code == RC_EMPTY || code == RC_REDUNDANT)) d.row_out[row] = row_out_of(code, st);
   if (code == RC_SINGLETON && mine) {
     d.row_out[row] = RowOut{aa, 0.0, aj, 0};
-    drop_col(d, aj);
+    drop_col(d, aj, aa, lhs, rhs);
   }
   if (code == RC_REDUNDANT) {
-    if (C == 1) lane_drop<C>(d, e);
-    else lane_drop_stream<C>(d, live, s0, len, gl * C);
+    if (C == 1) lane_drop<C>(d, e, lhs, rhs);
+    else lane_drop_stream<C>(d, live, s0, len, gl * C, lhs, rhs);
   }
 }
 
@@ -645,7 +646,7 @@ __device__ __forceinline__ void sweep_long_chunk(const Dev& d, const CandSink& s
   for (int p = 0; p < ch.npass; ++p) {
     int base = ch.first + p * PASS_LEN + (int)threadIdx.x * 8;
     if (dec.prop) lane_prop_stream<8>(d, sk, row, true, s0, len, base, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
-    else if (dec.code == RC_REDUNDANT) lane_drop_stream<8>(d, true, s0, len, base);
+    else if (dec.code == RC_REDUNDANT) lane_drop_stream<8>(d, true, s0, len, base, lhs, rhs);
   }
   if (dec.prop && dec.single && !dec.infeasible) {
     // the one active entry decides whether its row becomes bounds
@@ -653,7 +654,7 @@ __device__ __forceinline__ void sweep_long_chunk(const Dev& d, const CandSink& s
       if (!uncap) {
         d.row_code[row] = RC_SINGLETON;
         d.row_out[row] = RowOut{aa, 0.0, aj, 0};
-        drop_col(d, aj);
+        drop_col(d, aj, aa, lhs, rhs);
       } else {
         d.row_code[row] = RC_KEEP;
       }
@@ -777,6 +778,28 @@ __device__ __forceinline__ double empty_value(double c, double lo, double up) {
 
 // decision of an active or removed column from the round's accumulators:
 // code bits, and the number of records it gives
+// Dual fixing (a lock-based dual reduction): when no alive row keeps column
+// j from moving towards the bound its cost prefers (c > 0: down, c < 0: up;
+// c = 0: either, with a finite bound, lower first), some optimal solution has
+// it there; an infinite such bound means the LP is unbounded if feasible.
+// Returns true with the value (possibly infinite) and side (0 lower, 1 upper).
+__device__ __forceinline__ bool dual_fix_of(double c, double lo, double up, unsigned long long locks, double& v,
+                                            int& side) {
+  bool free_down = (locks & 0xFFFFFFFFull) == 0, free_up = (locks >> 32) == 0;
+  side = 0;
+  v = lo;
+  if (c > 0) return free_down;
+  side = 1;
+  v = up;
+  if (c < 0) return free_up;
+  if (free_down && !is_inf(lo)) {
+    side = 0;
+    v = lo;
+    return true;
+  }
+  return free_up && !is_inf(up);
+}
+
 __device__ __forceinline__ uint8_t col_decide(const Dev& d, int j, int& k) {
   k = 0;
   double2 b = d.bnd[j];
@@ -804,6 +827,17 @@ __device__ __forceinline__ uint8_t col_decide(const Dev& d, int j, int& k) {
     } else {
       code |= CC_EMPTY;
       ++k;
+    }
+  } else if (d.cfg.dual_fix) {
+    double v;
+    int side;
+    if (dual_fix_of(d.c[j], lo, up, d.locks[j], v, side)) {
+      if (is_inf(v)) {
+        code |= CC_UNBOUNDED;
+      } else {
+        code |= CC_DUALFIX;
+        ++k;
+      }
     }
   }
   if (code & CC_INFEAS) flag_infeasible(d, col_lp_of(d, j));
@@ -907,7 +941,14 @@ __device__ __forceinline__ int emit_col(const Dev& d, int j, int round, Record* 
                  ok ? d.va[q] : __builtin_nan(""), 0.0);
   }
   double nlo = lo, nup = up;
-  if (code & CC_FIX) {
+  if ((code & CC_DUALFIX) == CC_DUALFIX) {
+    // the locks have not changed since the decision
+    double v;
+    int side;
+    dual_fix_of(d.c[j], lo, up, d.locks[j], v, side);
+    *r++ = mkrec(REC_DUAL_FIX, (uint8_t)side, round, -1, j, -1, v, d.c[j], 0.0, 0.0);
+    nlo = nup = v;
+  } else if (code & CC_FIX) {
     *r++ = mkrec(REC_FIX_COL, 0, round, -1, j, -1, lo, d.c[j], 0.0, 0.0);
     nlo = nup = lo;
   } else if (code & CC_EMPTY) {

@@ -24,7 +24,8 @@ RECORD_DTYPE = np.dtype([
     ("i", "<i4"), ("j", "<i4"), ("k", "<i4"), ("v", "<f8", (4,)),
 ])
 REC_NAMES = {1: "FIX_COL", 2: "EMPTY_COL", 3: "EMPTY_ROW", 4: "REDUNDANT_ROW",
-             5: "SINGLETON_ROW", 6: "BOUND_CHANGE", 7: "PARALLEL_ROW", 8: "LEADER_SIDES"}
+             5: "SINGLETON_ROW", 6: "BOUND_CHANGE", 7: "PARALLEL_ROW", 8: "LEADER_SIDES",
+             9: "DUAL_FIX"}
 
 
 class psl_lp(C.Structure):
@@ -39,7 +40,7 @@ class psl_settings(C.Structure):
                 ("feas_tol", C.c_double), ("fix_tol", C.c_double), ("min_improve", C.c_double),
                 ("par_tol", C.c_double), ("inf_value", C.c_double), ("coef_tol", C.c_double),
                 ("bin_thresholds", C.c_void_p), ("n_bins", C.c_int32), ("device", C.c_int32),
-                ("stream", C.c_void_p), ("split_sweep", C.c_int32)]
+                ("stream", C.c_void_p), ("split_sweep", C.c_int32), ("enable_dual_fix", C.c_int32)]
 
 
 class psl_stats(C.Structure):
@@ -476,7 +477,10 @@ def tune(lps, reps=3, stream=None, **settings):
 
 def make_settings(stream=None, **kw):
     s = psl_settings_default()
+    names = {f for f, _ in psl_settings._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown setting {k!r}")
         if k == "bin_thresholds":
             arr = (C.c_int32 * len(v))(*v)
             s.bin_thresholds = C.cast(arr, C.c_void_p)
