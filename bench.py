@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--workload", choices=("powerlaw", "large"), default="powerlaw",
                     help="single-LP workload: the power-law LP (default) or the large LP")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dual-fix-steps", type=int, default=10,
+                    help="timed steps of the same LP with dual fixing on (0 = skip)")
     ap.add_argument("--batch-lps", type=int, default=4096, help="LPs of the batched workload (0 = skip it)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--only-batch", action="store_true", help="run the batched workload only")
@@ -337,6 +339,31 @@ def main():
         "alg_bytes_per_launch": round(per_launch_bytes),
     }
 
+    dual_fix = None
+    if args.dual_fix_steps > 0:
+        # the same workload with the lock-based dual fixing switched on
+        q = psl.Presolver(dev, stream=stream.cuda_stream, enable_dual_fix=1)
+        for _ in range(2):
+            q.reload(dev)
+            q.run()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.dual_fix_steps):
+            q.reload(dev)
+            q.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        qs = q.stats
+        recs = q.records()
+        q.close()
+        dual_fix = {"metric": "presolve nnz/s with dual fixing", "value": round(nnz * args.dual_fix_steps / dt, 1),
+                    "unit": "nnz/s", "steps": args.dual_fix_steps,
+                    "ms_per_step": round(dt * 1e3 / args.dual_fix_steps, 3),
+                    "rounds": qs["rounds"], "records": qs["records"],
+                    "dual_fixes": int((recs["type"] == 9).sum()), "nnz_out": qs["nnz_out"],
+                    "m_out": qs["m_out"], "n_out": qs["n_out"],
+                    "ms_decide": round(qs["ms_decide"], 3), "ms_run_device": round(qs["ms_total"], 3)}
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -372,7 +399,9 @@ def main():
                    "ms_sweep": round(stats["ms_sweep"], 3), "ms_decide": round(stats["ms_decide"], 3),
                    "ms_parallel": round(stats["ms_parallel"], 3), "ms_compact": round(stats["ms_compact"], 3),
                    "step_ms_p50": round(float(np.median(step_ms)), 3),
-                   "first_run_ms": round(first["ms_total"], 3)},
+                   "first_run_ms": round(first["ms_total"], 3),
+                   "m_out": stats["m_out"], "n_out": stats["n_out"]},
+        "dual_fix": dual_fix,
         "batch": batch,
         "serving": serving,
     }

@@ -16,10 +16,16 @@ pytestmark = pytest.mark.gpu
 psl = pytest.importorskip("paper_2609_16182_amd.psl")
 
 
-def test_power_law_full_size():
+@pytest.fixture(scope="module")
+def power_lp():
     t0 = time.time()
     lp = lpgen.power_law(seed=1, scale=1.0)
     print(f"generated nnz={lpgen.nnz(lp)} in {time.time() - t0:.1f}s", flush=True)
+    return lp
+
+
+def test_power_law_full_size(power_lp):
+    lp = power_lp
     t0 = time.time()
     ref = O.presolve(lp)
     print(f"oracle {ref.result_name} rounds={ref.rounds} records={len(ref.records)} in {time.time() - t0:.1f}s",
@@ -33,6 +39,21 @@ def test_power_law_full_size():
     x0 = lp["x0"][r["col_map"]]
     sc = np.maximum(1.0, np.abs(x0))
     assert np.all(x0 >= r["lb"] - 1e-9 * sc) and np.all(x0 <= r["ub"] + 1e-9 * sc)
+
+
+def test_power_law_full_size_dual_fix(power_lp):
+    """The same LP with dual fixing on (the benchmark's dual-fixing leg)."""
+    lp = power_lp
+    t0 = time.time()
+    ref = O.presolve(lp, enable_dual_fix=1)
+    n_df = int((ref.records["type"] == O.REC["DUAL_FIX"]).sum())
+    print(f"oracle {ref.result_name} rounds={ref.rounds} records={len(ref.records)} dual fixes={n_df} "
+          f"in {time.time() - t0:.1f}s", flush=True)
+    assert n_df > 0
+    got, p = psl.presolve(lp, enable_dual_fix=1)
+    print(f"gpu stats {got['stats']}", flush=True)
+    p.close()
+    assert_same(got, ref, "power-law full size, dual fixing")
 
 
 def _load_digests(name):
