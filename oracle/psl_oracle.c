@@ -66,11 +66,13 @@ enum { RES_REDUCED = 0, RES_UNCHANGED = 1, RES_INFEASIBLE = 2, RES_UNBOUNDED = 3
  *                 v = {old lhs, old rhs, new lhs, new rhs}
  *  DUAL_FIX       j, side (0 fixed at its lower, 1 at its upper bound);
  *                 v = {value, c_j}
+ *  FREE_SINGLETON i = removed row, j = its free zero-cost column;
+ *                 v = {a_ij, lhs_i, rhs_i} (the sides at that point)
  */
 enum {
     REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
     REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
-    REC_DUAL_FIX = 9
+    REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10
 };
 
 /* classes of the reduced problem's rows and columns (listed, not applied) */
@@ -87,6 +89,10 @@ struct or_handle {
 
     uint8_t *row_on, *col_on;
     int32_t *col_len;
+    /* per side of each column: -1 the input bound was infinite and is
+     * unchanged, r >= 0 it was infinite and every tightening came from row r,
+     * -2 otherwise (free column singletons: bounds implied by their row) */
+    int32_t *lsrc, *usrc;
 
     or_record *rec;
     int64_t nrec, caprec;
@@ -212,6 +218,8 @@ static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s
         !(s->par_tol >= 0) || !(s->inf_value > 0) || !(s->coef_tol >= 0))
         return fail(h, "invalid tolerance");
     if (s->enable_dual_fix != 0 && s->enable_dual_fix != 1) return fail(h, "invalid dual-fix switch");
+    if (s->enable_free_singletons != 0 && s->enable_free_singletons != 1)
+        return fail(h, "invalid free-singleton switch");
     if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return fail(h, "negative size");
     int32_t m = lp->m, n = lp->n;
     if (m > 0 && (!lp->row_ptr || !lp->lhs || !lp->rhs)) return fail(h, "null row array");
@@ -316,6 +324,7 @@ typedef struct {
     uint8_t *dec;
     row_stats *st;
     int32_t *down, *up;        /* variable locks (dual fixing)      */
+    int32_t *pick;             /* free singleton column of each row */
 } round_ws;
 
 /* Implied bounds of row i on each of its active columns, from the residual
@@ -480,12 +489,16 @@ static int run_round(or_handle *h, round_ws *w) {
     for (int32_t j = 0; j < n; ++j) {
         if (!h->col_on[j]) continue;
         double lo = w->lb_n[j], up = w->ub_n[j];
-        if (lo != w->lb_s[j])
+        if (lo != w->lb_s[j]) {
             push(h, REC_BOUND_CHANGE, 0, -1, j, w->src_lb[j], w->lb_s[j], lo,
                  coef_in_row(h, w->src_lb[j], j), 0);
-        if (up != w->ub_s[j])
+            h->lsrc[j] = h->lsrc[j] == -1 || h->lsrc[j] == w->src_lb[j] ? w->src_lb[j] : -2;
+        }
+        if (up != w->ub_s[j]) {
             push(h, REC_BOUND_CHANGE, 1, -1, j, w->src_ub[j], w->ub_s[j], up,
                  coef_in_row(h, w->src_ub[j], j), 0);
+            h->usrc[j] = h->usrc[j] == -1 || h->usrc[j] == w->src_ub[j] ? w->src_ub[j] : -2;
+        }
         if (!isinf(lo) && !isinf(up) && lo > up + tol_of(s, up)) infeasible = 1;
         if (!isinf(lo) && !isinf(up) && up - lo <= s->fix_tol * mx1(lo)) {
             push(h, REC_FIX_COL, 0, -1, j, -1, lo, h->c[j], 0, 0);
@@ -516,6 +529,38 @@ static int run_round(or_handle *h, round_ws *w) {
         } else {
             h->lb[j] = lo;
             h->ub[j] = up;
+        }
+    }
+
+    /* Free column singletons with zero cost (section 3.2, "Column
+     * singletons", without the objective substitution, which is zero): a
+     * column with c_j = 0 and one alive row i whose bounds are infinite or
+     * implied by row i alone (each finite bound came only from tightenings
+     * sourced by row i, from an infinite input bound) can absorb any value of
+     * row i's other terms within those bounds, so row i and the column leave
+     * together; postsolve takes x_j from the row. Candidates are read from
+     * the state after this round's decisions (rows removed here create no
+     * new ones until the next round); a row keeps its lowest candidate. */
+    if (s->enable_free_singletons && !infeasible && !unbounded) {
+        for (int32_t i = 0; i < m; ++i) w->pick[i] = -1;
+        for (int32_t i = 0; i < m; ++i) {
+            if (!h->row_on[i]) continue;
+            for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k) {
+                int32_t j = h->ci[k];
+                if (h->col_on[j] && h->col_len[j] == 1 && h->c[j] == 0 &&
+                    (isinf(h->lb[j]) || h->lsrc[j] == i) && (isinf(h->ub[j]) || h->usrc[j] == i)) {
+                    w->pick[i] = j;  /* columns ascend within a row: the lowest */
+                    break;
+                }
+            }
+        }
+        for (int32_t i = 0; i < m; ++i) {
+            int32_t j = w->pick[i];
+            if (j < 0) continue;
+            push(h, REC_FREE_SINGLETON, 0, i, j, -1, coef_in_row(h, i, j), h->lhs[i], h->rhs[i], 0);
+            h->col_on[j] = 0;
+            h->lb[j] = h->ub[j] = 0.0;
+            drop_row(h, i);
         }
     }
 
@@ -766,6 +811,12 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     for (int32_t i = 0; i < m; ++i) h->row_on[i] = 1;
     for (int32_t j = 0; j < n; ++j) h->col_on[j] = 1;
     for (int64_t k = 0; k < h->nnz; ++k) h->col_len[h->ci[k]]++;
+    h->lsrc = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    h->usrc = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    for (int32_t j = 0; j < n; ++j) {
+        h->lsrc[j] = isinf(h->lb[j]) ? -1 : -2;
+        h->usrc[j] = isinf(h->ub[j]) ? -1 : -2;
+    }
 
     /* round 0: input fixings and crossed bounds / sides */
     h->round = 0;
@@ -801,6 +852,7 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     w.st = (row_stats *)xcalloc((size_t)m, sizeof(row_stats));
     w.down = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     w.up = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    w.pick = (int32_t *)xcalloc((size_t)m + 1, sizeof(int32_t));
 
     int stop = 0;
     for (int outer = 0; outer < s->max_outer && !stop; ++outer) {
@@ -818,7 +870,7 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     }
     free(w.lb_s); free(w.ub_s); free(w.lb_n); free(w.ub_n);
     free(w.src_lb); free(w.src_ub); free(w.tmin); free(w.tmax); free(w.dec); free(w.st);
-    free(w.down); free(w.up);
+    free(w.down); free(w.up); free(w.pick);
 
     if (h->result < RES_INFEASIBLE) {
         h->result = h->nrec ? RES_REDUCED : RES_UNCHANGED;
@@ -854,8 +906,11 @@ int or_activities(const or_lp *lp, double *minact, double *maxact,
 
 /* ------------------------------------------------------------------------- */
 /* postsolve (primal): kept columns from the reduced solution, removed ones   */
-/* from their FIX_COL / EMPTY_COL / DUAL_FIX records; every other record      */
-/* keeps the feasible set and leaves x unchanged.                             */
+/* from their FIX_COL / EMPTY_COL / DUAL_FIX records; then, last record       */
+/* first, each free singleton column from its row: with r = the row's other   */
+/* terms (its original entries, left to right) and s = r clamped to the sides */
+/* the row had, x_j = (s - r) / a_ij. Every other record keeps the feasible   */
+/* set and leaves x unchanged.                                                */
 /* ------------------------------------------------------------------------- */
 
 int or_postsolve(const or_handle *h, const double *x_red, double *x) {
@@ -865,6 +920,15 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
     for (int64_t t = h->nrec - 1; t >= 0; --t) {
         const or_record *r = &h->rec[t];
         if (r->type == REC_FIX_COL || r->type == REC_EMPTY_COL || r->type == REC_DUAL_FIX) x[r->j] = r->v[0];
+    }
+    for (int64_t t = h->nrec - 1; t >= 0; --t) {
+        const or_record *r = &h->rec[t];
+        if (r->type != REC_FREE_SINGLETON) continue;
+        double rest = 0.0;
+        for (int64_t k = h->rp[r->i]; k < h->rp[r->i + 1]; ++k)
+            if (h->ci[k] != r->j) rest = rest + h->va[k] * x[h->ci[k]];
+        double side = rest < r->v[1] ? r->v[1] : (rest > r->v[2] ? r->v[2] : rest);
+        x[r->j] = (side - rest) / r->v[0];
     }
     return 0;
 }
@@ -894,7 +958,8 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
 /*       bound changes it sourced), fixed, empty and dual-fixed columns take  */
 /*       their reduced cost from z = c - A'y (a dual-fixed column has no      */
 /*       locks towards its bound, so the active rows' multipliers can only    */
-/*       push z_j further to that bound's sign).                              */
+/*       push z_j further to that bound's sign); a row removed with a free    */
+/*       zero-cost singleton keeps y_i = c_j / a_ij = 0, so z_j = 0.          */
 /* Every z_j = c_j - sum_i a_ij y_i is summed over the column's rows in      */
 /* ascending order, left to right.                                            */
 /* ------------------------------------------------------------------------- */
@@ -960,7 +1025,7 @@ int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_r
 void or_free(or_handle *h) {
     if (!h) return;
     free(h->rp); free(h->ci); free(h->va); free(h->lhs); free(h->rhs);
-    free(h->lb); free(h->ub); free(h->c); free(h->row_on); free(h->col_on);
+    free(h->lb); free(h->ub); free(h->c); free(h->row_on); free(h->col_on); free(h->lsrc); free(h->usrc);
     free(h->col_len); free(h->rec);
     free(h->r_rp); free(h->r_ci); free(h->r_va); free(h->r_cp); free(h->r_ri); free(h->r_cva);
     free(h->r_lhs); free(h->r_rhs); free(h->r_lb); free(h->r_ub); free(h->r_c);

@@ -33,6 +33,7 @@ typedef struct {
     int32_t max_rounds, max_outer, enable_parallel_rows;
     double feas_tol, fix_tol, min_improve, par_tol, inf_value, coef_tol;
     int32_t enable_dual_fix;  /* 1: lock-based dual fixing in every round */
+    int32_t enable_free_singletons;  /* 1: zero-cost free column singletons */
 } or_settings;
 
 /* 48-byte postsolve record; the field meaning per type is listed in the .c */
