@@ -80,7 +80,8 @@ typedef struct {
  *   max_rounds 16, max_outer 4, enable_parallel_rows 1,
  *   feas_tol 1e-9, fix_tol 1e-9, min_improve 1e-7, par_tol 1e-9,
  *   inf_value 1e20, coef_tol 1e-9, bin thresholds from the tuner (NULL),
- *   device 0, stream NULL, split_sweep 0, enable_dual_fix 0.
+ *   device 0, stream NULL, split_sweep 0, enable_dual_fix 0,
+ *   enable_free_singletons 0.
  * bin_thresholds (optional, n_bins = 2 or 3): [0] the longest row swept by one
  * 64-lane wavefront (16..512, default 512); [1] positions per workgroup chunk
  * of longer rows (a power of two >= 2048, default 2048); [2] the longest row
@@ -117,6 +118,16 @@ typedef struct {
                                       PSL_RES_UNBOUNDED_OR_INFEASIBLE. Keeps an
                                       optimal solution, not the feasible set.
                                       0 (default) or 1.                        */
+    int32_t enable_free_singletons;/* 1: at the end of every round, a column
+                                      with c_j = 0 in one alive row i, whose
+                                      bounds are infinite or were tightened
+                                      only from row i (implied by it), leaves
+                                      with row i (FREE_SINGLETON, section 3.2
+                                      "Column singletons"; with c_j = 0 there
+                                      is no objective substitution); the
+                                      lowest such column of a row goes.
+                                      Postsolve takes x_j from the row.
+                                      0 (default) or 1.                        */
 } psl_settings;
 
 /* Postsolve record: 48 bytes, emitted in the order (round, phase, index,
@@ -134,6 +145,9 @@ typedef struct {
  *                         v = {old lhs, old rhs, new lhs, new rhs}
  *   type 9 DUAL_FIX       j, side (0 at its lower, 1 at its upper bound);
  *                         v = {value, c_j} (only with enable_dual_fix)
+ *   type 10 FREE_SINGLETON i = removed row, j = its free zero-cost column;
+ *                         v = {a_ij, lhs_i, rhs_i} (the sides at that point;
+ *                         only with enable_free_singletons)
  * round 0 holds input fixings; each propagation round and each parallel-row
  * pass has its own round number. */
 typedef struct {
@@ -210,8 +224,12 @@ psl_status psl_records(const psl_presolver *p, int64_t *count, psl_record *out, 
  * primal and dual solutions of the original problem). All arrays are HOST
  * memory.
  *   Primal: x_red[n_red] -> x[n]. Kept columns come from x_red, removed
- *   columns from their FIX_COL / EMPTY_COL records; the other record types
- *   keep the feasible set and leave x unchanged.
+ *   columns from their FIX_COL / EMPTY_COL / DUAL_FIX records; then, last
+ *   record first, a FREE_SINGLETON column from its row: with rest = the
+ *   row's other terms (its original entries, left to right) and s = rest
+ *   clamped to the recorded sides, x_j = (s - rest) / a_ij (the original rows
+ *   are read back from the device). The other record types keep the feasible
+ *   set and leave x unchanged.
  *   Dual (when y_red != NULL): the reduced problem's row duals y_red[m_red]
  *   -> row duals y[m] and reduced costs z[n] of the original LP, with the
  *   convention c - A'y - z = 0, y_i >= 0 at lhs and <= 0 at rhs, z_j >= 0 at
@@ -369,7 +387,8 @@ psl_status psl_server_records(psl_server *sv, uint64_t ticket, int64_t *count, p
 
 /* As psl_postsolve, for the ticket's LP, primal only: y_red / z_red must be
  * NULL (PSL_ERR_UNSUPPORTED otherwise), since a done ticket keeps its reduced
- * problem and records but not the original matrix the dual pass reads. */
+ * problem and records but not the original matrix the dual pass reads; for
+ * the same reason FREE_SINGLETON records give PSL_ERR_UNSUPPORTED. */
 psl_status psl_server_postsolve(psl_server *sv, uint64_t ticket, const double *x_red, const double *y_red,
                                 const double *z_red, double *x, double *y, double *z);
 

@@ -152,6 +152,7 @@ __global__ void k_rec_gather(Dev d, const Record* rec, const uint32_t* keys, con
       r.k = local_idx(r.k, i0);
       break;
     case REC_SINGLETON_ROW:
+    case REC_FREE_SINGLETON:
       r.i = local_idx(r.i, i0);
       r.j = local_idx(r.j, j0);
       break;

@@ -91,6 +91,7 @@ extern "C" void psl_settings_default(psl_settings* s) {
   s->stream = nullptr;
   s->split_sweep = 0;
   s->enable_dual_fix = 0;
+  s->enable_free_singletons = 0;
 }
 
 std::string psl::check_settings(const psl_settings* s) {
@@ -100,6 +101,8 @@ std::string psl::check_settings(const psl_settings* s) {
       !(s->inf_value > 0) || !(s->coef_tol >= 0))
     return "invalid tolerance";
   if (s->enable_dual_fix != 0 && s->enable_dual_fix != 1) return "enable_dual_fix must be 0 or 1";
+  if (s->enable_free_singletons != 0 && s->enable_free_singletons != 1)
+    return "enable_free_singletons must be 0 or 1";
   if (s->bin_thresholds) {
     if (s->n_bins != 2 && s->n_bins != 3) return "bin_thresholds needs n_bins = 2 or 3";
     int a = s->bin_thresholds[0], b = s->bin_thresholds[1];
@@ -216,6 +219,10 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(d.dirty_tile, m / 1024 + 2);
   ALLOC(d.touch, n);
   ALLOC(d.locks, n);
+  ALLOC(d.lsrc, n);
+  ALLOC(d.usrc, n);
+  ALLOC(d.fs_flag, n);
+  ALLOC(d.fs_pick, m);
   ALLOC(d.rinf, m);
   ALLOC(d.dense_cols, N / 4096 + 2);
   ALLOC(d.n_dense, 1);
@@ -357,10 +364,12 @@ static psl_status setup_arena(psl_presolver* p) {
   d.lpf = p->lpf;
   d.lpo = p->lpo;
   const psl_settings& s = p->s;
-  d.cfg = Cfg{s.feas_tol, s.fix_tol, s.min_improve, s.par_tol, s.inf_value, s.coef_tol, s.enable_dual_fix};
+  d.cfg = Cfg{s.feas_tol, s.fix_tol, s.min_improve, s.par_tol, s.inf_value, s.coef_tol, s.enable_dual_fix,
+              s.enable_free_singletons};
   // every device array the kernels index must exist (allocations are >= 64 B
   // even for empty problems); colid is set once the transposed copy exists
   const void* ptrs[] = {d.rp, d.ci, d.va, d.cp, d.ri, d.cva, d.lhs, d.rhs, d.bnd, d.bkey, d.src, d.c, d.locks,
+                        d.lsrc, d.usrc, d.fs_flag, d.fs_pick,
                         d.col_len, d.row_on, d.row_code, d.col_code, d.dirty, d.row_out, d.cand, d.cand_cnt,
                         d.flags, d.cnt, d.off, d.rec, d.bins, d.lchunk, d.lpart, d.lrow, p->lpr,
                         d.dense_cols, d.n_dense, d.touch, d.rinf, d.chunks0, d.dirty_tile};
@@ -937,6 +946,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       HIPCHK(p, hipEventRecord(p->ev[5], st));
       launch_src(d, p->grid, st);
       launch_decide(d, p->rec_count, round, d.cnt, d.off, p->ws, st);
+      if (s.enable_free_singletons) launch_free_singletons(d, p->par.vlist, p->rec_count, round, p->ws, st);
       HIPCHK(p, hipEventRecord(p->ev[6], st));
       // The next round's selection is made before the round's one read, in
       // one pass over the rows. Rows none of whose columns changed since they
@@ -1229,6 +1239,27 @@ extern "C" psl_status psl_records(const psl_presolver* cp, int64_t* count, psl_r
   return records_of(p, 0, count, out, cap);
 }
 
+// LP k's rows of the original LP (columns numbered within the LP), copied to
+// the host
+static psl_status host_rows(psl_presolver* p, int k, HostRows& A) {
+  int64_t r0 = p->K == 1 ? 0 : p->h_row0[k], r1 = p->K == 1 ? p->m : p->h_row0[k + 1];
+  int64_t c0 = p->K == 1 ? 0 : p->h_col0[k];
+  int64_t m = r1 - r0;
+  A.rp.resize(m + 1);
+  HIPCHK(p, hipMemcpy(A.rp.data(), p->d.rp + r0, (m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  int64_t e0 = A.rp[0], e1 = A.rp[m];
+  A.ci.resize(e1 - e0);
+  A.va.resize(e1 - e0);
+  if (e1 > e0) {
+    HIPCHK(p, hipMemcpy(A.ci.data(), p->d.ci + e0, (e1 - e0) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(p, hipMemcpy(A.va.data(), p->d.va + e0, (e1 - e0) * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  for (auto& v : A.rp) v -= (int32_t)e0;
+  if (c0)
+    for (auto& v : A.ci) v -= (int32_t)c0;
+  return PSL_OK;
+}
+
 // LP k's columns of the original (canonicalised) LP and their costs, copied
 // to the host; rows numbered within the LP
 static psl_status host_cols(psl_presolver* p, int k, HostCols& A) {
@@ -1268,7 +1299,14 @@ static psl_status postsolve_of(psl_presolver* p, int k, const double* x_red, con
   psl_status st = fetch_lp_records(p, k, &rec);
   if (st != PSL_OK) return st;
   std::string err;
-  st = postsolve_primal(rec->data(), (int64_t)rec->size(), v.col_map, n, v.n, x_red, x, &err);
+  HostRows R;
+  bool need_rows = records_need_rows(rec->data(), (int64_t)rec->size());
+  if (need_rows) {
+    st = host_rows(p, k, R);
+    if (st != PSL_OK) return st;
+  }
+  st = postsolve_primal(rec->data(), (int64_t)rec->size(), v.col_map, n, v.n, x_red, x, need_rows ? &R : nullptr,
+                        &err);
   if (st != PSL_OK) {
     p->err = err;
     return st;
@@ -1283,10 +1321,24 @@ static psl_status postsolve_of(psl_presolver* p, int k, const double* x_red, con
   return PSL_OK;
 }
 
+bool psl::records_need_rows(const psl_record* rec, int64_t count) {
+  for (int64_t t = 0; t < count; ++t)
+    if (rec[t].type == REC_FREE_SINGLETON) return true;
+  return false;
+}
+
 // primal postsolve: kept columns from x_red, removed ones from their FIX_COL /
-// EMPTY_COL / DUAL_FIX records; the other records keep the feasible set
+// EMPTY_COL / DUAL_FIX records; then, last record first, each free singleton
+// column from its row: with rest = the row's other terms (its original
+// entries, left to right) and s = rest clamped to the sides the row had,
+// x_j = (s - rest) / a_ij. The other records keep the feasible set.
 psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
-                                 int32_t n_red, const double* x_red, double* x, std::string* err) {
+                                 int32_t n_red, const double* x_red, double* x, const HostRows* rows,
+                                 std::string* err) {
+  if (!rows && records_need_rows(rec, count)) {
+    *err = "free-singleton records need the original rows, which this handle does not keep";
+    return PSL_ERR_UNSUPPORTED;
+  }
   std::vector<int32_t> cmap(n_red);
   if (n_red && hipMemcpy(cmap.data(), col_map_dev, n_red * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
     *err = "HIP error copying the column map";
@@ -1297,6 +1349,15 @@ psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int
   for (int64_t t = count - 1; t >= 0; --t) {
     const psl_record& r = rec[t];
     if (r.type == REC_FIX_COL || r.type == REC_EMPTY_COL || r.type == REC_DUAL_FIX) x[r.j] = r.v[0];
+  }
+  for (int64_t t = count - 1; t >= 0; --t) {
+    const psl_record& r = rec[t];
+    if (r.type != REC_FREE_SINGLETON) continue;
+    double rest = 0.0;
+    for (int32_t q = rows->rp[r.i]; q < rows->rp[r.i + 1]; ++q)
+      if (rows->ci[q] != r.j) rest = rest + rows->va[q] * x[rows->ci[q]];
+    double side = rest < r.v[1] ? r.v[1] : (rest > r.v[2] ? r.v[2] : rest);
+    x[r.j] = (side - rest) / r.v[0];
   }
   return PSL_OK;
 }
@@ -1316,7 +1377,8 @@ psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int
 //    rhs) belongs to the row r that gave it, a_r = lambda_r a_L:
 //    y_r = y_L / lambda_r and y_L = 0;
 //  * the other records keep y (a dual-fixed column has no lock towards its
-//    bound, so the alive rows' multipliers only push z_j to that bound's sign).
+//    bound, so the alive rows' multipliers only push z_j to that bound's sign;
+//    a row that left with a free zero-cost singleton keeps y_i = c_j / a_ij = 0).
 // Finally z = c - A'y. Every a_j'y is summed over column j's rows in
 // ascending order, left to right.
 static double reduced_cost(const HostCols& A, const double* y, int32_t j) {

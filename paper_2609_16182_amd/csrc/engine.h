@@ -167,9 +167,18 @@ const std::string& engine_error(const psl_presolver* p);
 int32_t engine_error_lp(const psl_presolver* p);
 // per-LP statistics of the last run (as psl_batch_stats)
 void engine_lp_stats(const psl_presolver* p, int k, psl_stats* out);
-// primal postsolve on the host from records and the reduced column map
+// the original LP by rows, on the host: row i's columns in ci[rp[i]..rp[i+1])
+// with values va (free-singleton records take x_j from their row)
+struct HostRows {
+  std::vector<int32_t> rp, ci;
+  std::vector<double> va;
+};
+// true when a record needs the original rows in primal postsolve
+bool records_need_rows(const psl_record* rec, int64_t count);
+// primal postsolve on the host from records and the reduced column map; rows
+// may be null when records_need_rows is false (else PSL_ERR_UNSUPPORTED)
 psl_status postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
-                            int32_t n_red, const double* x_red, double* x, std::string* err);
+                            int32_t n_red, const double* x_red, double* x, const HostRows* rows, std::string* err);
 // the original LP by columns, on the host, for dual postsolve: column j's
 // rows ascending in ri[cp[j]..cp[j+1]) with values cva, and the costs c
 struct HostCols {

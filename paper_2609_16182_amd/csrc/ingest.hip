@@ -632,11 +632,15 @@ __global__ void k_init_state(Dev d) {
     d.row_on[t] = 1;
     d.row_code[t] = RC_KEEP;
     d.dirty[t] = 0;
+    d.fs_pick[t] = 0x7FFFFFFF;
   }
   if (t <= d.m / 1024) d.dirty_tile[t] = 0;
   if (t < d.n) {
     double2 b = d.bnd[t];
-    d.touch[t] = 1;  // the first round decides every column
+    d.touch[t] = 1;    // the first round decides every column
+    d.fs_flag[t] = 1;  // and checks every column for a free singleton
+    d.lsrc[t] = is_inf(b.x) ? -1 : -2;
+    d.usrc[t] = is_inf(b.y) ? -1 : -2;
     d.bkey[2 * t] = dkey(b.x);
     d.bkey[2 * t + 1] = dkey(b.y);
     d.src[2 * t] = 0x7FFFFFFF;
@@ -647,7 +651,7 @@ __global__ void k_init_state(Dev d) {
     Flags f;
     f.infeasible = f.unbounded = f.error = f.merged = 0;
     f.cand_count = f.round_total = f.vlist_count = f.rows_removed = 0;
-    f.fin_cols = f.mode = f.lead_count = 0;
+    f.fin_cols = f.mode = f.lead_count = f.fs_total = f.fs_rows = 0;
     f.error_pos = 0x7FFFFFFFFFFFFFFFLL;
     *d.flags = f;
   }

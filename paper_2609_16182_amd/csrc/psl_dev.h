@@ -23,7 +23,7 @@ namespace psl {
 enum : uint8_t {
   REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
   REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
-  REC_DUAL_FIX = 9
+  REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10
 };
 
 // row decision codes written by the sweep for the current round
@@ -112,11 +112,14 @@ struct Flags {
   int32_t sel[NBINS + 4];  // the next round's selection: bin offsets [0..NBINS],
                            // rows, their nonzeros, long-row chunks
   int32_t lead_count;      // parallel pass: leaders whose merged sides add locks
+  int32_t fs_total;        // free singleton eliminations of the round
+  int32_t fs_rows;         // rows listed for their column drops
 };
 
 struct Cfg {
   double feas_tol, fix_tol, min_improve, par_tol, inf_value, coef_tol;
   int32_t dual_fix;        // lock-based dual fixing on
+  int32_t free_sing;       // zero-cost free column singletons eliminated
 };
 
 struct HashSlot {
@@ -151,6 +154,11 @@ struct Dev {
   uint8_t *touch;          // columns whose decision may change this round
   unsigned long long *locks;  // dual fixing: per column, the alive rows keeping it
                               // from decreasing (low 32 bits) / increasing (high)
+  // free singletons: per column and side, -1 = infinite input bound not changed,
+  // r >= 0 = infinite input bound tightened only from row r, -2 = otherwise
+  int32_t *lsrc, *usrc;
+  uint8_t *fs_flag;        // column to check for a free singleton this round
+  int32_t *fs_pick;        // per row: lowest candidate column (INT32_MAX: none)
   const uint32_t *colid;   // column of each position of the transposed copy
   RowOut *row_out;
   Cand *cand;
@@ -219,7 +227,8 @@ __device__ __forceinline__ unsigned long long lock_bits(double a, double lhs, do
 
 // a row removal takes column j (coefficient a, the row's sides lhs / rhs) out
 // of that row; a column left in no row is decided this round, and with dual
-// fixing so is every column that lost a row (it may have lost its last lock)
+// fixing so is every column that lost a row (it may have lost its last lock);
+// a column left in one row is checked for a free singleton
 __device__ __forceinline__ void drop_col(const Dev& d, int j, double a, double lhs, double rhs) {
   int left = atomicSub(&d.col_len[j], 1) - 1;
   if (d.cfg.dual_fix) {
@@ -228,6 +237,7 @@ __device__ __forceinline__ void drop_col(const Dev& d, int j, double a, double l
   } else if (left == 0) {
     d.touch[j] = 1;
   }
+  if (d.cfg.free_sing && left == 1) d.fs_flag[j] = 1;  // now in one row: a candidate
 }
 
 // A row whose every finite side has at least two infinite contributions on

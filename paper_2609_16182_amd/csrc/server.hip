@@ -628,8 +628,9 @@ extern "C" psl_status psl_server_postsolve(psl_server* sv, uint64_t ticket, cons
   if (!t->has_block) return sfail(sv, PSL_ERR_STATE, "no reduced problem to postsolve");
   if ((t->lp.n > 0 && !x) || (t->view.n > 0 && !x_red)) return sfail(sv, PSL_ERR_INVALID, "null solution array");
   std::string err;
+  // a done ticket keeps no original rows (free-singleton records need them)
   st = postsolve_primal(t->records.data(), (int64_t)t->records.size(), t->view.col_map, t->lp.n, t->view.n, x_red,
-                        x, &err);
+                        x, nullptr, &err);
   if (st != PSL_OK) sv->err = err;
   return st;
 }

@@ -931,14 +931,18 @@ __device__ __forceinline__ int emit_col(const Dev& d, int j, int round, Record* 
   if (code & CC_LB) {
     int q = d.src[2 * (int64_t)j];
     bool ok = q >= 0 && q < d.nnz;
-    *r++ = mkrec(REC_BOUND_CHANGE, 0, round, -1, j, ok ? d.rowid1[q + 1] : -1, b.x, lo,
-                 ok ? d.va[q] : __builtin_nan(""), 0.0);
+    int k = ok ? d.rowid1[q + 1] : -1;
+    *r++ = mkrec(REC_BOUND_CHANGE, 0, round, -1, j, k, b.x, lo, ok ? d.va[q] : __builtin_nan(""), 0.0);
+    int ls = d.lsrc[j];
+    d.lsrc[j] = ls == -1 || ls == k ? k : -2;  // a bound from one row only keeps it implied by that row
   }
   if (code & CC_UB) {
     int q = d.src[2 * (int64_t)j + 1];
     bool ok = q >= 0 && q < d.nnz;
-    *r++ = mkrec(REC_BOUND_CHANGE, 1, round, -1, j, ok ? d.rowid1[q + 1] : -1, b.y, up,
-                 ok ? d.va[q] : __builtin_nan(""), 0.0);
+    int k = ok ? d.rowid1[q + 1] : -1;
+    *r++ = mkrec(REC_BOUND_CHANGE, 1, round, -1, j, k, b.y, up, ok ? d.va[q] : __builtin_nan(""), 0.0);
+    int us = d.usrc[j];
+    d.usrc[j] = us == -1 || us == k ? k : -2;
   }
   double nlo = lo, nup = up;
   if ((code & CC_DUALFIX) == CC_DUALFIX) {

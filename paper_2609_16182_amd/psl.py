@@ -25,7 +25,7 @@ RECORD_DTYPE = np.dtype([
 ])
 REC_NAMES = {1: "FIX_COL", 2: "EMPTY_COL", 3: "EMPTY_ROW", 4: "REDUNDANT_ROW",
              5: "SINGLETON_ROW", 6: "BOUND_CHANGE", 7: "PARALLEL_ROW", 8: "LEADER_SIDES",
-             9: "DUAL_FIX"}
+             9: "DUAL_FIX", 10: "FREE_SINGLETON"}
 
 
 class psl_lp(C.Structure):
@@ -40,7 +40,8 @@ class psl_settings(C.Structure):
                 ("feas_tol", C.c_double), ("fix_tol", C.c_double), ("min_improve", C.c_double),
                 ("par_tol", C.c_double), ("inf_value", C.c_double), ("coef_tol", C.c_double),
                 ("bin_thresholds", C.c_void_p), ("n_bins", C.c_int32), ("device", C.c_int32),
-                ("stream", C.c_void_p), ("split_sweep", C.c_int32), ("enable_dual_fix", C.c_int32)]
+                ("stream", C.c_void_p), ("split_sweep", C.c_int32), ("enable_dual_fix", C.c_int32),
+                ("enable_free_singletons", C.c_int32)]
 
 
 class psl_stats(C.Structure):
@@ -650,7 +651,10 @@ class Server:
     def __init__(self, stream=None, **config):
         settings = {k: config.pop(k) for k in list(config) if k in {f for f, _ in psl_settings._fields_}}
         self.cfg = psl_server_config_default()
+        names = {f for f, _ in psl_server_config._fields_}
         for k, v in config.items():
+            if k not in names:
+                raise TypeError(f"unknown server setting {k!r}")
             setattr(self.cfg, k, v)
         self.settings = make_settings(**settings)
         self.h = psl_server_create(self.cfg, self.settings)
