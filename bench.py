@@ -39,8 +39,8 @@ def parse():
     ap.add_argument("--workload", choices=("powerlaw", "large"), default="powerlaw",
                     help="single-LP workload: the power-law LP (default) or the large LP")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--dual-fix-steps", type=int, default=10,
-                    help="timed steps of the same LP with dual fixing on (0 = skip)")
+    ap.add_argument("--reduction-steps", type=int, default=10,
+                    help="timed steps of the same LP with each optional reduction on (0 = skip)")
     ap.add_argument("--batch-lps", type=int, default=4096, help="LPs of the batched workload (0 = skip it)")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--only-batch", action="store_true", help="run the batched workload only")
@@ -339,30 +339,34 @@ def main():
         "alg_bytes_per_launch": round(per_launch_bytes),
     }
 
-    dual_fix = None
-    if args.dual_fix_steps > 0:
-        # the same workload with the lock-based dual fixing switched on
-        q = psl.Presolver(dev, stream=stream.cuda_stream, enable_dual_fix=1)
-        for _ in range(2):
-            q.reload(dev)
-            q.run()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.dual_fix_steps):
-            q.reload(dev)
-            q.run()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        qs = q.stats
-        recs = q.records()
-        q.close()
-        dual_fix = {"metric": "presolve nnz/s with dual fixing", "value": round(nnz * args.dual_fix_steps / dt, 1),
-                    "unit": "nnz/s", "steps": args.dual_fix_steps,
-                    "ms_per_step": round(dt * 1e3 / args.dual_fix_steps, 3),
-                    "rounds": qs["rounds"], "records": qs["records"],
-                    "dual_fixes": int((recs["type"] == 9).sum()), "nnz_out": qs["nnz_out"],
-                    "m_out": qs["m_out"], "n_out": qs["n_out"],
-                    "ms_decide": round(qs["ms_decide"], 3), "ms_run_device": round(qs["ms_total"], 3)}
+    # the same workload with the optional reductions switched on
+    reductions = None
+    if args.reduction_steps > 0:
+        reductions = {}
+        for name, extra in (("dual_fix", dict(enable_dual_fix=1)),
+                            ("free_singletons", dict(enable_free_singletons=1)),
+                            ("both", dict(enable_dual_fix=1, enable_free_singletons=1))):
+            q = psl.Presolver(dev, stream=stream.cuda_stream, **extra)
+            for _ in range(2):
+                q.reload(dev)
+                q.run()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.reduction_steps):
+                q.reload(dev)
+                q.run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            qs = q.stats
+            recs = q.records()
+            q.close()
+            reductions[name] = {
+                "value": round(nnz * args.reduction_steps / dt, 1), "unit": "nnz/s", "steps": args.reduction_steps,
+                "ms_per_step": round(dt * 1e3 / args.reduction_steps, 3), "rounds": qs["rounds"],
+                "records": qs["records"], "dual_fixes": int((recs["type"] == 9).sum()),
+                "free_singletons": int((recs["type"] == 10).sum()), "nnz_out": qs["nnz_out"],
+                "m_out": qs["m_out"], "n_out": qs["n_out"], "ms_decide": round(qs["ms_decide"], 3),
+                "ms_run_device": round(qs["ms_total"], 3)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -401,7 +405,7 @@ def main():
                    "step_ms_p50": round(float(np.median(step_ms)), 3),
                    "first_run_ms": round(first["ms_total"], 3),
                    "m_out": stats["m_out"], "n_out": stats["n_out"]},
-        "dual_fix": dual_fix,
+        "reductions": reductions,
         "batch": batch,
         "serving": serving,
     }

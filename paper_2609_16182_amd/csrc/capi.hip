@@ -946,7 +946,9 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       HIPCHK(p, hipEventRecord(p->ev[5], st));
       launch_src(d, p->grid, st);
       launch_decide(d, p->rec_count, round, d.cnt, d.off, p->ws, st);
-      if (s.enable_free_singletons) launch_free_singletons(d, p->par.vlist, p->rec_count, round, p->ws, st);
+      // (the candidate regions are free until the next sweep)
+      if (s.enable_free_singletons)
+        launch_free_singletons(d, reinterpret_cast<int32_t*>(d.cand), p->rec_count, round, p->ws, st);
       HIPCHK(p, hipEventRecord(p->ev[6], st));
       // The next round's selection is made before the round's one read, in
       // one pass over the rows. Rows none of whose columns changed since they

@@ -63,8 +63,16 @@ __device__ __forceinline__ double coef_of(const Dev& d, int i, int j) {
   return d.va[lo];
 }
 
+// rows of at most this many entries leave their columns in the emitting
+// thread; longer ones are listed in chunks of FS_CHUNK positions, one
+// workgroup each
+#define FS_SHORT 32
+#define FS_CHUNK PSL_BLOCK
+
 // records after the round's decision records; the row leaves, the column is
-// set to lb = ub = 0 (its cost is 0, so it adds nothing to the objective)
+// set to lb = ub = 0 (its cost is 0, so it adds nothing to the objective),
+// and a short row leaves its other active columns here (no other row of this
+// pass holds column j: it had one alive row)
 __global__ void k_fs_emit(Dev d, int32_t* list, int64_t base, int round) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d.m) return;
@@ -89,25 +97,51 @@ __global__ void k_fs_emit(Dev d, int32_t* list, int64_t base, int round) {
   d.bnd[j] = make_double2(0.0, 0.0);
   d.bkey[2 * (int64_t)j] = dkey(0.0);
   d.bkey[2 * (int64_t)j + 1] = dkey(0.0);
-  list[atomicAdd(&d.flags->fs_rows, 1)] = i;
   if (d.K > 1) d.lpo[lp].total = 1;  // the LP changed this round
+  int p0 = d.rp[i], len = d.rp[i + 1] - p0;
+  if (len > FS_SHORT) {
+    int nch = (len + FS_CHUNK - 1) / FS_CHUNK;
+    int c0 = atomicAdd(&d.flags->fs_rows, nch);
+    for (int c = 0; c < nch; ++c) list[c0 + c] = p0 + c * FS_CHUNK;
+    return;
+  }
+  double lhs = r.v[1], rhs = r.v[2];
+  // groups of four entries: their loads in flight together, then the drops
+#pragma unroll 1
+  for (int g = 0; g < len; g += 4) {
+    int jj[4];
+    double a[4];
+    double2 bb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int p = p0 + (g + k < len ? g + k : 0);
+      jj[k] = d.ci[p];
+      a[k] = d.va[p];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bb[k] = jj[k] == j ? make_double2(0.0, 0.0) : d.bnd[jj[k]];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (g + k < len && bb[k].x != bb[k].y) drop_col(d, jj[k], a[k], lhs, rhs);
+  }
 }
 
-// the removed rows leave their other active columns: one wavefront per row
+// the listed chunks of long removed rows leave their other active columns:
+// one workgroup per chunk (its first CSR position listed), a position a thread
 __global__ void __launch_bounds__(PSL_BLOCK) k_fs_drop(Dev d, const int32_t* list) {
-  int nr = d.flags->fs_rows;
+  int nc = d.flags->fs_rows;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.flags->round_total += d.flags->fs_total;
     d.flags->rows_removed += d.flags->fs_total;
   }
-  int wstride = gridDim.x * (PSL_BLOCK / PSL_WAVE);
-  for (int k = blockIdx.x * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6); k < nr; k += wstride) {
-    int i = list[k];
-    double lhs = d.lhs[i], rhs = d.rhs[i];
-    for (int p = d.rp[i] + lane_id(); p < d.rp[i + 1]; p += PSL_WAVE) {
+  for (int k = blockIdx.x; k < nc; k += gridDim.x) {
+    int p0 = list[k];
+    int i = d.rowid1[p0 + 1];
+    int p = p0 + (int)threadIdx.x;
+    if (p < d.rp[i + 1]) {
       int j = d.ci[p];
       double2 b = d.bnd[j];
-      if (b.x != b.y) drop_col(d, j, d.va[p], lhs, rhs);
+      if (b.x != b.y) drop_col(d, j, d.va[p], d.lhs[i], d.rhs[i]);
     }
   }
 }

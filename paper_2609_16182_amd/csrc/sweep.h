@@ -85,8 +85,9 @@ void launch_init_state(const Dev& d, hipStream_t s);
 void init_locks(const Dev& d, int32_t* dn, int32_t* up, int32_t* ws, hipStream_t s);
 
 // singleton.hip: zero-cost free column singletons at the end of a round
-// (records from base + the round's record total; list: m ints of scratch;
-// adds its records to d.flags->round_total and its rows to rows_removed)
+// (records from base + the round's record total; list: nnz / 32 + m ints of
+// scratch; adds its records to d.flags->round_total and its rows to
+// rows_removed)
 void launch_free_singletons(const Dev& d, int32_t* list, int64_t base, int round, int32_t* ws, hipStream_t s);
 
 // parallel.hip

@@ -41,19 +41,25 @@ def test_power_law_full_size(power_lp):
     assert np.all(x0 >= r["lb"] - 1e-9 * sc) and np.all(x0 <= r["ub"] + 1e-9 * sc)
 
 
-def test_power_law_full_size_dual_fix(power_lp):
-    """The same LP with dual fixing on (the benchmark's dual-fixing leg)."""
+@pytest.mark.parametrize("extra", [dict(enable_dual_fix=1), dict(enable_free_singletons=1),
+                                   dict(enable_dual_fix=1, enable_free_singletons=1)],
+                         ids=["dual_fix", "free_singletons", "both"])
+def test_power_law_full_size_next_reductions(power_lp, extra):
+    """The same LP with the optional reductions on (the benchmark's legs)."""
     lp = power_lp
     t0 = time.time()
-    ref = O.presolve(lp, enable_dual_fix=1)
-    n_df = int((ref.records["type"] == O.REC["DUAL_FIX"]).sum())
-    print(f"oracle {ref.result_name} rounds={ref.rounds} records={len(ref.records)} dual fixes={n_df} "
+    ref = O.presolve(lp, **extra)
+    kinds = {name: int((ref.records["type"] == O.REC[name]).sum()) for name in ("DUAL_FIX", "FREE_SINGLETON")}
+    print(f"oracle {ref.result_name} rounds={ref.rounds} records={len(ref.records)} {kinds} "
           f"in {time.time() - t0:.1f}s", flush=True)
-    assert n_df > 0
-    got, p = psl.presolve(lp, enable_dual_fix=1)
+    if extra.get("enable_dual_fix"):
+        assert kinds["DUAL_FIX"] > 0
+    if extra.get("enable_free_singletons"):
+        assert kinds["FREE_SINGLETON"] > 0
+    got, p = psl.presolve(lp, **extra)
     print(f"gpu stats {got['stats']}", flush=True)
     p.close()
-    assert_same(got, ref, "power-law full size, dual fixing")
+    assert_same(got, ref, f"power-law full size, {extra}")
 
 
 def _load_digests(name):
