@@ -68,12 +68,18 @@ enum { RES_REDUCED = 0, RES_UNCHANGED = 1, RES_INFEASIBLE = 2, RES_UNBOUNDED = 3
  *                 v = {value, c_j}
  *  FREE_SINGLETON i = removed row, j = its free zero-cost column;
  *                 v = {a_ij, lhs_i, rhs_i} (the sides at that point)
+ *  PARALLEL_COL   j = merged column, k = its leader; v = {lambda, lb_j, ub_j}
+ *  LEADER_BOUNDS  j = leader; v = {old lb, old ub, new lb, new ub}
  */
 enum {
     REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
     REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
-    REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10
+    REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10, REC_PARALLEL_COL = 11, REC_LEADER_BOUNDS = 12
 };
+
+/* parallel columns are searched among columns stored with at most this many
+ * entries */
+#define PC_MAX_LEN 64
 
 /* classes of the reduced problem's rows and columns (listed, not applied) */
 enum { RCLS_OTHER = 0, RCLS_SINGLETON = 1, RCLS_DOUBLETON_EQ = 2, RCLS_DOUBLETON_INEQ = 3 };
@@ -93,6 +99,9 @@ struct or_handle {
      * unchanged, r >= 0 it was infinite and every tightening came from row r,
      * -2 otherwise (free column singletons: bounds implied by their row) */
     int32_t *lsrc, *usrc;
+    /* the matrix by columns (rows ascending within a column) */
+    int32_t *cp, *ri;
+    double *cva;
 
     or_record *rec;
     int64_t nrec, caprec;
@@ -220,6 +229,8 @@ static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s
     if (s->enable_dual_fix != 0 && s->enable_dual_fix != 1) return fail(h, "invalid dual-fix switch");
     if (s->enable_free_singletons != 0 && s->enable_free_singletons != 1)
         return fail(h, "invalid free-singleton switch");
+    if (s->enable_parallel_cols != 0 && s->enable_parallel_cols != 1)
+        return fail(h, "invalid parallel-column switch");
     if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return fail(h, "negative size");
     int32_t m = lp->m, n = lp->n;
     if (m > 0 && (!lp->row_ptr || !lp->lhs || !lp->rhs)) return fail(h, "null row array");
@@ -687,6 +698,151 @@ static int parallel_rows(or_handle *h) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* parallel columns (section 3.2): parallel rows of [c A'] -- columns j, k   */
+/* with a_j = lambda a_k and c_j = lambda c_k -- merge into one variable     */
+/* x_k + lambda x_j whose bounds are the sum of the intervals.               */
+/* ------------------------------------------------------------------------- */
+
+/* first entry of column j's augmented row [c_j, a_ij over alive rows i] */
+static double col_first(const or_handle *h, int32_t j) {
+    if (h->c[j] != 0) return h->c[j];
+    for (int32_t q = h->cp[j]; q < h->cp[j + 1]; ++q)
+        if (h->row_on[h->ri[q]]) return h->cva[q];
+    return 0.0;
+}
+
+/* 31-bit key of the augmented row: the parallel-row key over its entries,
+ * with the cost as an entry of id 2^32 - 1 before the rows, normalised by the
+ * first entry, top 31 bits */
+static uint32_t col_key(const or_handle *h, int32_t j) {
+    double f = col_first(h, j);
+    uint64_t h1 = 0, h2 = 0;
+    if (h->c[j] != 0) {
+        uint64_t id = splitmix(0xFFFFFFFFULL);
+        h1 += 1 + id;
+        h2 += splitmix(id ^ quantize(h->c[j] / f));
+    }
+    for (int32_t q = h->cp[j]; q < h->cp[j + 1]; ++q) {
+        if (!h->row_on[h->ri[q]]) continue;
+        uint64_t id = splitmix((uint64_t)(uint32_t)h->ri[q]);
+        h1 += 1 + id;
+        h2 += splitmix(id ^ quantize(h->cva[q] / f));
+    }
+    return (uint32_t)((splitmix(h1) ^ h2) >> 33);
+}
+
+/* same augmented pattern and entries within par_tol after normalisation */
+static int cols_parallel(const or_handle *h, int32_t j, int32_t k) {
+    if ((h->c[j] != 0) != (h->c[k] != 0)) return 0;
+    double fj = col_first(h, j), fk = col_first(h, k);
+    int32_t qj = h->cp[j], qk = h->cp[k];
+    for (;;) {
+        while (qj < h->cp[j + 1] && !h->row_on[h->ri[qj]]) qj++;
+        while (qk < h->cp[k + 1] && !h->row_on[h->ri[qk]]) qk++;
+        int ej = qj < h->cp[j + 1], ek = qk < h->cp[k + 1];
+        if (ej != ek) return 0;
+        if (!ej) break;
+        if (h->ri[qj] != h->ri[qk]) return 0;
+        double a = h->cva[qj] / fj, b = h->cva[qk] / fk;
+        double scale = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+        if (!(fabs(a - b) <= h->s.par_tol * scale)) return 0;
+        qj++;
+        qk++;
+    }
+    return 1;
+}
+
+/* a merged bound: |v| >= inf_value is infinite, -0 is +0 */
+static double canon_bound(const or_handle *h, double v) {
+    if (fabs(v) >= h->s.inf_value) return v > 0 ? INFINITY : -INFINITY;
+    return pos0(v);
+}
+
+/* interval of the merged variable after adding lambda * [lb, ub] */
+static void add_scaled(const or_handle *h, double lam, double lb, double ub, double *lo, double *up) {
+    if (lam > 0) {
+        *lo = canon_bound(h, *lo + lam * lb);
+        *up = canon_bound(h, *up + lam * ub);
+    } else {
+        *lo = canon_bound(h, *lo + lam * ub);
+        *up = canon_bound(h, *up + lam * lb);
+    }
+}
+
+typedef struct { uint32_t key; int32_t col; } keycol;
+
+static int cmp_keycol(const void *a, const void *b) {
+    const keycol *x = (const keycol *)a, *y = (const keycol *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return (x->col > y->col) - (x->col < y->col);
+}
+
+/* Candidates: active columns in at least one alive row, stored with at most
+ * PC_MAX_LEN entries. Groups: equal keys, in ascending column order; the
+ * leader is the group's first column, every other member is verified
+ * against it and merged into it in ascending order. Records in one pass
+ * over the columns: LEADER_BOUNDS for a leader, PARALLEL_COL for a merged
+ * column. Returns 1 if any column merged. */
+static int parallel_cols(or_handle *h) {
+    int32_t n = h->n;
+    keycol *kc = (keycol *)xcalloc((size_t)n + 1, sizeof(keycol));
+    int32_t nk = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        if (!h->col_on[j] || h->col_len[j] < 1 || h->cp[j + 1] - h->cp[j] > PC_MAX_LEN) continue;
+        kc[nk].key = col_key(h, j);
+        kc[nk].col = j;
+        nk++;
+    }
+    qsort(kc, (size_t)nk, sizeof(keycol), cmp_keycol);
+    int32_t *lead = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    double *lam = (double *)xcalloc((size_t)n + 1, sizeof(double));
+    double *nlo = (double *)xcalloc((size_t)n + 1, sizeof(double));
+    double *nup = (double *)xcalloc((size_t)n + 1, sizeof(double));
+    for (int32_t j = 0; j < n; ++j) lead[j] = -1;
+    for (int32_t g0 = 0; g0 < nk;) {
+        int32_t g1 = g0 + 1;
+        while (g1 < nk && kc[g1].key == kc[g0].key) g1++;
+        int32_t k = kc[g0].col;
+        double lo = h->lb[k], up = h->ub[k];
+        double fk = col_first(h, k);
+        int any = 0;
+        for (int32_t t = g0 + 1; t < g1; ++t) {
+            int32_t j = kc[t].col;
+            if (!cols_parallel(h, j, k)) continue;
+            double la = col_first(h, j) / fk;
+            add_scaled(h, la, h->lb[j], h->ub[j], &lo, &up);
+            lead[j] = k;
+            lam[j] = la;
+            any = 1;
+        }
+        if (any) {
+            lead[k] = k;
+            nlo[k] = lo;
+            nup[k] = up;
+        }
+        g0 = g1;
+    }
+    int merged = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        if (lead[j] < 0) continue;
+        if (lead[j] == j) {
+            push(h, REC_LEADER_BOUNDS, 0, -1, j, -1, h->lb[j], h->ub[j], nlo[j], nup[j]);
+            h->lb[j] = nlo[j];
+            h->ub[j] = nup[j];
+            h->lsrc[j] = isinf(nlo[j]) ? -1 : -2;
+            h->usrc[j] = isinf(nup[j]) ? -1 : -2;
+        } else {
+            push(h, REC_PARALLEL_COL, 0, -1, j, lead[j], lam[j], h->lb[j], h->ub[j], 0);
+            h->col_on[j] = 0;
+            h->lb[j] = h->ub[j] = 0.0;
+            merged = 1;
+        }
+    }
+    free(kc); free(lead); free(lam); free(nlo); free(nup);
+    return merged;
+}
+
+/* ------------------------------------------------------------------------- */
 /* reduced problem (section 3.3)                                              */
 /* ------------------------------------------------------------------------- */
 
@@ -811,6 +967,22 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     for (int32_t i = 0; i < m; ++i) h->row_on[i] = 1;
     for (int32_t j = 0; j < n; ++j) h->col_on[j] = 1;
     for (int64_t k = 0; k < h->nnz; ++k) h->col_len[h->ci[k]]++;
+    h->cp = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    h->ri = (int32_t *)xcalloc((size_t)h->nnz + 1, sizeof(int32_t));
+    h->cva = (double *)xcalloc((size_t)h->nnz + 1, sizeof(double));
+    for (int64_t k = 0; k < h->nnz; ++k) h->cp[h->ci[k] + 1]++;
+    for (int32_t j = 0; j < n; ++j) h->cp[j + 1] += h->cp[j];
+    {
+        int32_t *fill = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+        for (int32_t j = 0; j < n; ++j) fill[j] = h->cp[j];
+        for (int32_t i = 0; i < m; ++i)
+            for (int32_t k = h->rp[i]; k < h->rp[i + 1]; ++k) {
+                int32_t q = fill[h->ci[k]]++;
+                h->ri[q] = i;
+                h->cva[q] = h->va[k];
+            }
+        free(fill);
+    }
     h->lsrc = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     h->usrc = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     for (int32_t j = 0; j < n; ++j) {
@@ -862,10 +1034,11 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
             if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
             if (!changed) break;
         }
-        if (stop || !s->enable_parallel_rows) break;
+        if (stop || (!s->enable_parallel_rows && !s->enable_parallel_cols)) break;
         h->round++;
-        int merged = parallel_rows(h);
+        int merged = s->enable_parallel_rows ? parallel_rows(h) : 0;
         if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
+        if (s->enable_parallel_cols) merged |= parallel_cols(h);
         if (!merged) break;
     }
     free(w.lb_s); free(w.ub_s); free(w.lb_n); free(w.ub_n);
@@ -906,12 +1079,60 @@ int or_activities(const or_lp *lp, double *minact, double *maxact,
 
 /* ------------------------------------------------------------------------- */
 /* postsolve (primal): kept columns from the reduced solution, removed ones   */
-/* from their FIX_COL / EMPTY_COL / DUAL_FIX records; then, last record       */
-/* first, each free singleton column from its row: with r = the row's other   */
-/* terms (its original entries, left to right) and s = r clamped to the sides */
-/* the row had, x_j = (s - r) / a_ij. Every other record keeps the feasible   */
-/* set and leaves x unchanged.                                                */
+/* from their FIX_COL / EMPTY_COL / DUAL_FIX records (constants); then, last  */
+/* record first:                                                              */
+/*   FREE_SINGLETON  with r = the row's other terms (its original entries,    */
+/*       left to right) and s = r clamped to the sides the row had,           */
+/*       x_j = (s - r) / a_ij;                                                */
+/*   LEADER_BOUNDS   the leader holds the merged value v of its group (the    */
+/*       group's PARALLEL_COL records follow it in the same pass); the        */
+/*       intervals B_0 = the leader's old bounds, B_s = B_{s-1} + lambda_s    */
+/*       [lb_s, ub_s] are rebuilt as presolve built them, and the members,    */
+/*       last first, take x_s = the value in [lb_s, ub_s] that keeps          */
+/*       v - lambda_s x_s in B_{s-1} (from lb_s if finite, else ub_s, else 0, */
+/*       clamped to that range), v -= lambda_s x_s; the leader keeps the rest.*/
+/* Every other record keeps the feasible set and leaves x unchanged.          */
 /* ------------------------------------------------------------------------- */
+
+static void split_group(const or_handle *h, int64_t t, double *x) {
+    const or_record *L = &h->rec[t];
+    int32_t k = L->j;
+    int64_t e = t + 1;  /* the pass's column records follow */
+    while (e < h->nrec && h->rec[e].round == L->round &&
+           (h->rec[e].type == REC_PARALLEL_COL || h->rec[e].type == REC_LEADER_BOUNDS)) e++;
+    int64_t cnt = 0;
+    for (int64_t q = t + 1; q < e; ++q)
+        if (h->rec[q].type == REC_PARALLEL_COL && h->rec[q].k == k) cnt++;
+    double *blo = (double *)xcalloc((size_t)cnt + 1, sizeof(double));
+    double *bup = (double *)xcalloc((size_t)cnt + 1, sizeof(double));
+    const or_record **mem = (const or_record **)xcalloc((size_t)cnt + 1, sizeof(or_record *));
+    int64_t s = 0;
+    blo[0] = L->v[0];
+    bup[0] = L->v[1];
+    for (int64_t q = t + 1; q < e; ++q) {
+        const or_record *r = &h->rec[q];
+        if (r->type != REC_PARALLEL_COL || r->k != k) continue;
+        mem[s] = r;
+        blo[s + 1] = blo[s];
+        bup[s + 1] = bup[s];
+        add_scaled(h, r->v[0], r->v[1], r->v[2], &blo[s + 1], &bup[s + 1]);
+        s++;
+    }
+    double v = x[k];
+    for (int64_t q = cnt - 1; q >= 0; --q) {
+        double lam = mem[q]->v[0], l = mem[q]->v[1], u = mem[q]->v[2];
+        double a, b;
+        if (lam > 0) { a = (v - bup[q]) / lam; b = (v - blo[q]) / lam; }
+        else { a = (v - blo[q]) / lam; b = (v - bup[q]) / lam; }
+        double lo = a > l ? a : l, hi = b < u ? b : u;
+        double pref = !isinf(l) ? l : (!isinf(u) ? u : 0.0);
+        double xs = pref < lo ? lo : (pref > hi ? hi : pref);
+        x[mem[q]->j] = xs;
+        v = v - lam * xs;
+    }
+    x[k] = v;
+    free(blo); free(bup); free(mem);
+}
 
 int or_postsolve(const or_handle *h, const double *x_red, double *x) {
     if (h->result >= RES_INFEASIBLE) return 1;
@@ -923,12 +1144,15 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
     }
     for (int64_t t = h->nrec - 1; t >= 0; --t) {
         const or_record *r = &h->rec[t];
-        if (r->type != REC_FREE_SINGLETON) continue;
-        double rest = 0.0;
-        for (int64_t k = h->rp[r->i]; k < h->rp[r->i + 1]; ++k)
-            if (h->ci[k] != r->j) rest = rest + h->va[k] * x[h->ci[k]];
-        double side = rest < r->v[1] ? r->v[1] : (rest > r->v[2] ? r->v[2] : rest);
-        x[r->j] = (side - rest) / r->v[0];
+        if (r->type == REC_LEADER_BOUNDS) {
+            split_group(h, t, x);
+        } else if (r->type == REC_FREE_SINGLETON) {
+            double rest = 0.0;
+            for (int64_t k = h->rp[r->i]; k < h->rp[r->i + 1]; ++k)
+                if (h->ci[k] != r->j) rest = rest + h->va[k] * x[h->ci[k]];
+            double side = rest < r->v[1] ? r->v[1] : (rest > r->v[2] ? r->v[2] : rest);
+            x[r->j] = (side - rest) / r->v[0];
+        }
     }
     return 0;
 }
@@ -1026,6 +1250,7 @@ void or_free(or_handle *h) {
     if (!h) return;
     free(h->rp); free(h->ci); free(h->va); free(h->lhs); free(h->rhs);
     free(h->lb); free(h->ub); free(h->c); free(h->row_on); free(h->col_on); free(h->lsrc); free(h->usrc);
+    free(h->cp); free(h->ri); free(h->cva);
     free(h->col_len); free(h->rec);
     free(h->r_rp); free(h->r_ci); free(h->r_va); free(h->r_cp); free(h->r_ri); free(h->r_cva);
     free(h->r_lhs); free(h->r_rhs); free(h->r_lb); free(h->r_ub); free(h->r_c);

@@ -34,6 +34,7 @@ typedef struct {
     double feas_tol, fix_tol, min_improve, par_tol, inf_value, coef_tol;
     int32_t enable_dual_fix;  /* 1: lock-based dual fixing in every round */
     int32_t enable_free_singletons;  /* 1: zero-cost free column singletons */
+    int32_t enable_parallel_cols;    /* 1: parallel columns in the parallel pass */
 } or_settings;
 
 /* 48-byte postsolve record; the field meaning per type is listed in the .c */
