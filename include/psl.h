@@ -81,7 +81,7 @@ typedef struct {
  *   feas_tol 1e-9, fix_tol 1e-9, min_improve 1e-7, par_tol 1e-9,
  *   inf_value 1e20, coef_tol 1e-9, bin thresholds from the tuner (NULL),
  *   device 0, stream NULL, split_sweep 0, enable_dual_fix 0,
- *   enable_free_singletons 0.
+ *   enable_free_singletons 0, enable_parallel_cols 0.
  * bin_thresholds (optional, n_bins = 2 or 3): [0] the longest row swept by one
  * 64-lane wavefront (16..512, default 512); [1] positions per workgroup chunk
  * of longer rows (a power of two >= 2048, default 2048); [2] the longest row
@@ -128,6 +128,17 @@ typedef struct {
                                       lowest such column of a row goes.
                                       Postsolve takes x_j from the row.
                                       0 (default) or 1.                        */
+    int32_t enable_parallel_cols;  /* 1: after the parallel rows, parallel
+                                      columns (section 3.2, "Parallel
+                                      columns": parallel rows of [c A'] over
+                                      the alive rows, among columns stored
+                                      with at most 64 entries) merge into the
+                                      first column of their group, whose
+                                      interval becomes the sum of the scaled
+                                      intervals (in column order);
+                                      PARALLEL_COL / LEADER_BOUNDS. 0 (default)
+                                      or 1. The parallel pass runs when either
+                                      this or enable_parallel_rows is set.     */
 } psl_settings;
 
 /* Postsolve record: 48 bytes, emitted in the order (round, phase, index,
@@ -148,6 +159,11 @@ typedef struct {
  *   type 10 FREE_SINGLETON i = removed row, j = its free zero-cost column;
  *                         v = {a_ij, lhs_i, rhs_i} (the sides at that point;
  *                         only with enable_free_singletons)
+ *   type 11 PARALLEL_COL  j = merged column, k = its leader;
+ *                         v = {lambda (a_j = lambda a_k), lb_j, ub_j}
+ *   type 12 LEADER_BOUNDS j = leader; v = {old lb, old ub, new lb, new ub}
+ *                         (both only with enable_parallel_cols; a leader's
+ *                         record precedes its group's PARALLEL_COL records)
  * round 0 holds input fixings; each propagation round and each parallel-row
  * pass has its own round number. */
 typedef struct {
@@ -228,8 +244,13 @@ psl_status psl_records(const psl_presolver *p, int64_t *count, psl_record *out, 
  *   record first, a FREE_SINGLETON column from its row: with rest = the
  *   row's other terms (its original entries, left to right) and s = rest
  *   clamped to the recorded sides, x_j = (s - rest) / a_ij (the original rows
- *   are read back from the device). The other record types keep the feasible
- *   set and leave x unchanged.
+ *   are read back from the device); a LEADER_BOUNDS group splits its
+ *   leader's merged value v: with B_0 = the old leader bounds and B_s =
+ *   B_{s-1} + lambda_s [lb_s, ub_s] rebuilt in member order, members, last
+ *   first, take the value in [lb_s, ub_s] keeping v - lambda_s x_s in
+ *   B_{s-1} (from lb_s if finite, else ub_s, else 0, clamped), v -= lambda_s
+ *   x_s, and the leader keeps the rest. The other record types keep the
+ *   feasible set and leave x unchanged.
  *   Dual (when y_red != NULL): the reduced problem's row duals y_red[m_red]
  *   -> row duals y[m] and reduced costs z[n] of the original LP, with the
  *   convention c - A'y - z = 0, y_i >= 0 at lhs and <= 0 at rhs, z_j >= 0 at

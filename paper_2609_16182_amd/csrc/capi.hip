@@ -92,6 +92,7 @@ extern "C" void psl_settings_default(psl_settings* s) {
   s->split_sweep = 0;
   s->enable_dual_fix = 0;
   s->enable_free_singletons = 0;
+  s->enable_parallel_cols = 0;
 }
 
 std::string psl::check_settings(const psl_settings* s) {
@@ -103,6 +104,7 @@ std::string psl::check_settings(const psl_settings* s) {
   if (s->enable_dual_fix != 0 && s->enable_dual_fix != 1) return "enable_dual_fix must be 0 or 1";
   if (s->enable_free_singletons != 0 && s->enable_free_singletons != 1)
     return "enable_free_singletons must be 0 or 1";
+  if (s->enable_parallel_cols != 0 && s->enable_parallel_cols != 1) return "enable_parallel_cols must be 0 or 1";
   if (s->bin_thresholds) {
     if (s->n_bins != 2 && s->n_bins != 3) return "bin_thresholds needs n_bins = 2 or 3";
     int a = s->bin_thresholds[0], b = s->bin_thresholds[1];
@@ -204,7 +206,8 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->isc.v0, big);
   ALLOC(p->isc.v1, big);
   size_t wsn = std::max<size_t>(scan_ws_ints(N + 1), radix_ws_ints(std::max<int64_t>(N, m)));
-  wsn = std::max<size_t>(wsn, scan_ws_ints(m + n + 1)) + 64;
+  wsn = std::max<size_t>(wsn, scan_ws_ints(m + n + 1));
+  wsn = std::max<size_t>(wsn, par_cols_ws_ints(n)) + 64;
   ALLOC(p->ws, wsn);
   p->isc.ws = p->ws;
 
@@ -248,6 +251,17 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->par.vlist, m);
   ALLOC(p->par.hacc, 3 * p->long_cap);
   p->par.lpt = nullptr;
+  if (p->s.enable_parallel_cols) {
+    ALLOC(p->pc.key, n);
+    ALLOC(p->pc.keys, n);
+    ALLOC(p->pc.keys2, n);
+    ALLOC(p->pc.vals, n);
+    ALLOC(p->pc.vals2, n);
+    ALLOC(p->pc.lead, n);
+    ALLOC(p->pc.lam, n);
+    ALLOC(p->pc.nb, n);
+    ALLOC(p->pc.total, 1);
+  }
 
   // compaction
   ALLOC(p->cmp.row_new, m + 1);
@@ -1016,7 +1030,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     for (auto& L : p->lst)
       if (L.phase != LP_DONE) ++npar;
     if (npar == 0) break;
-    if (!s.enable_parallel_rows) {
+    if (!s.enable_parallel_rows && !s.enable_parallel_cols) {
       for (auto& L : p->lst) L.phase = LP_DONE;
       break;
     }
@@ -1027,17 +1041,24 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
         if (B) p->h_round[k] = p->lst[k].rounds;
       }
     e = use_full_view(p);
-    if (e == PSL_OK) e = ensure_capacity(p, m + 16);
+    if (e == PSL_OK) e = ensure_capacity(p, m + n + 16);  // row records, then column records
     if (e == PSL_OK) e = begin_lp_round(p);
     if (e != PSL_OK) return e;
     HIPCHK(p, hipEventRecord(p->ev[4], st));
     launch_par_reset(d, p->par, st);
-    launch_par_hash(d, p->par, p->grid, st);
-    launch_par_verify(d, p->par, st);
-    launch_par_count(d, p->par, st);
-    scan_excl(d.cnt, d.off, m, &d.flags->round_total, p->ws, st);
-    launch_par_emit(d, p->par, p->rec_count, round, st);
-    launch_par_drop(d, p->par, st);
+    if (s.enable_parallel_rows) {
+      launch_par_hash(d, p->par, p->grid, st);
+      launch_par_verify(d, p->par, st);
+      launch_par_count(d, p->par, st);
+      scan_excl(d.cnt, d.off, m, &d.flags->round_total, p->ws, st);
+      launch_par_emit(d, p->par, p->rec_count, round, st);
+      launch_par_drop(d, p->par, st);
+    } else {
+      fill_i32(&d.flags->round_total, 0, 1, st);
+    }
+    // parallel columns on the rows the row pass left (an LP it found
+    // infeasible has stopped)
+    if (s.enable_parallel_cols) launch_par_cols(d, p->pc, p->rec_count, round, p->ws, st);
     HIPCHK(p, hipEventRecord(p->ev[5], st));
     e = queue_lp_read(p, false);
     if (e == PSL_OK) e = read_flags(p);
@@ -1308,7 +1329,7 @@ static psl_status postsolve_of(psl_presolver* p, int k, const double* x_red, con
     if (st != PSL_OK) return st;
   }
   st = postsolve_primal(rec->data(), (int64_t)rec->size(), v.col_map, n, v.n, x_red, x, need_rows ? &R : nullptr,
-                        &err);
+                        p->s.inf_value, &err);
   if (st != PSL_OK) {
     p->err = err;
     return st;
@@ -1331,12 +1352,72 @@ bool psl::records_need_rows(const psl_record* rec, int64_t count) {
 
 // primal postsolve: kept columns from x_red, removed ones from their FIX_COL /
 // EMPTY_COL / DUAL_FIX records; then, last record first, each free singleton
-// column from its row: with rest = the row's other terms (its original
-// entries, left to right) and s = rest clamped to the sides the row had,
-// x_j = (s - rest) / a_ij. The other records keep the feasible set.
+// column from its row (with rest = the row's other terms, its original
+// entries left to right, and s = rest clamped to the sides the row had,
+// x_j = (s - rest) / a_ij) and each group of parallel columns split from its
+// leader's merged value. The other records keep the feasible set.
+// a merged interval bound: |v| >= inf_value is infinite, -0 is +0
+static double merged_bound(double v, double inf_value) {
+  if (std::fabs(v) >= inf_value) return v > 0 ? INFINITY : -INFINITY;
+  return v == 0.0 ? 0.0 : v;
+}
+
+// the interval [lo, up] + lam * [l, u]
+static void add_scaled(double lam, double l, double u, double inf_value, double& lo, double& up) {
+  if (lam > 0) {
+    lo = merged_bound(lo + lam * l, inf_value);
+    up = merged_bound(up + lam * u, inf_value);
+  } else {
+    lo = merged_bound(lo + lam * u, inf_value);
+    up = merged_bound(up + lam * l, inf_value);
+  }
+}
+
+// Split the merged value of the group led by rec[t] (LEADER_BOUNDS; its
+// PARALLEL_COL records follow in the same pass): the intervals B_0 (the
+// leader's old bounds), B_s = B_{s-1} + lambda_s [lb_s, ub_s] are rebuilt as
+// presolve built them; members, last first, take the value in [lb_s, ub_s]
+// that keeps v - lambda_s x_s in B_{s-1} (from lb_s if finite, else ub_s,
+// else 0, clamped to that range) and v -= lambda_s x_s; the leader keeps v.
+static void split_group(const psl_record* rec, int64_t count, int64_t t, double inf_value, double* x) {
+  const psl_record& L = rec[t];
+  int32_t k = L.j;
+  std::vector<const psl_record*> mem;
+  for (int64_t q = t + 1; q < count && rec[q].round == L.round &&
+                          (rec[q].type == REC_PARALLEL_COL || rec[q].type == REC_LEADER_BOUNDS);
+       ++q)
+    if (rec[q].type == REC_PARALLEL_COL && rec[q].k == k) mem.push_back(&rec[q]);
+  std::vector<double> blo(mem.size() + 1), bup(mem.size() + 1);
+  blo[0] = L.v[0];
+  bup[0] = L.v[1];
+  for (size_t s = 0; s < mem.size(); ++s) {
+    blo[s + 1] = blo[s];
+    bup[s + 1] = bup[s];
+    add_scaled(mem[s]->v[0], mem[s]->v[1], mem[s]->v[2], inf_value, blo[s + 1], bup[s + 1]);
+  }
+  double v = x[k];
+  for (size_t q = mem.size(); q-- > 0;) {
+    double lam = mem[q]->v[0], l = mem[q]->v[1], u = mem[q]->v[2];
+    double a, b;
+    if (lam > 0) {
+      a = (v - bup[q]) / lam;
+      b = (v - blo[q]) / lam;
+    } else {
+      a = (v - blo[q]) / lam;
+      b = (v - bup[q]) / lam;
+    }
+    double lo = a > l ? a : l, hi = b < u ? b : u;
+    double pref = !std::isinf(l) ? l : (!std::isinf(u) ? u : 0.0);
+    double xs = pref < lo ? lo : (pref > hi ? hi : pref);
+    x[mem[q]->j] = xs;
+    v = v - lam * xs;
+  }
+  x[k] = v;
+}
+
 psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
                                  int32_t n_red, const double* x_red, double* x, const HostRows* rows,
-                                 std::string* err) {
+                                 double inf_value, std::string* err) {
   if (!rows && records_need_rows(rec, count)) {
     *err = "free-singleton records need the original rows, which this handle does not keep";
     return PSL_ERR_UNSUPPORTED;
@@ -1354,6 +1435,10 @@ psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int
   }
   for (int64_t t = count - 1; t >= 0; --t) {
     const psl_record& r = rec[t];
+    if (r.type == REC_LEADER_BOUNDS) {
+      split_group(rec, count, t, inf_value, x);
+      continue;
+    }
     if (r.type != REC_FREE_SINGLETON) continue;
     double rest = 0.0;
     for (int32_t q = rows->rp[r.i]; q < rows->rp[r.i + 1]; ++q)

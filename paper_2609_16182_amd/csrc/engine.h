@@ -120,6 +120,7 @@ struct psl_presolver {
   bool host_rec_valid = false;
 
   ParScratch par{};
+  psl::ColScratch pc{};  // parallel columns (allocated when enabled)
   CompactScratch cmp{};
   Reduced red{};
   int32_t red_m = 0, red_n = 0;
@@ -178,7 +179,8 @@ bool records_need_rows(const psl_record* rec, int64_t count);
 // primal postsolve on the host from records and the reduced column map; rows
 // may be null when records_need_rows is false (else PSL_ERR_UNSUPPORTED)
 psl_status postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
-                            int32_t n_red, const double* x_red, double* x, const HostRows* rows, std::string* err);
+                            int32_t n_red, const double* x_red, double* x, const HostRows* rows, double inf_value,
+                            std::string* err);
 // the original LP by columns, on the host, for dual postsolve: column j's
 // rows ascending in ri[cp[j]..cp[j+1]) with values cva, and the costs c
 struct HostCols {

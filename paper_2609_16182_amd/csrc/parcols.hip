@@ -1,0 +1,231 @@
+// parcols.hip -- parallel columns (section 3.2, "Parallel columns"): columns
+// j, k with a_j = lambda a_k (over the alive rows) and c_j = lambda c_k are
+// parallel rows of [c A'] and merge into one variable x_k + lambda x_j, whose
+// interval is [lb_k, ub_k] + lambda [lb_j, ub_j].
+//
+// Candidates are the active columns in at least one alive row that are
+// stored with at most PC_MAX_LEN entries. Each gets a 31-bit key of its
+// augmented row (the cost as an entry of id 2^32 - 1 before the rows, rows in
+// the LP's own numbering, entries over the first one); the candidates are
+// sorted stably by key (and by LP in a batch), so that a group of equal keys
+// lists its columns in ascending order. The group's first column leads; its
+// thread verifies the others in order and adds their scaled intervals in that
+// order. Records in one pass over the columns (LEADER_BOUNDS for a leader,
+// PARALLEL_COL for a merged column); a merged column is set to 0, since the
+// leader carries it.
+#include <utility>
+
+#include "psl_kern.h"
+#include "sweep.h"
+
+namespace psl {
+
+#define PC_MAX_LEN 64
+#define PC_NONE 0xFFFFFFFFu
+
+__device__ __forceinline__ bool pc_lp_stopped(const Dev& d, int lp) {
+  if (d.K > 1) return d.lp_ok[lp] == 0;
+  return (d.flags->infeasible | d.flags->unbounded) != 0;
+}
+
+// first entry of the augmented row of column j (its cost, else its first
+// alive coefficient)
+__device__ __forceinline__ double pc_first(const Dev& d, int j) {
+  if (d.c[j] != 0.0) return d.c[j];
+  for (int q = d.cp[j]; q < d.cp[j + 1]; ++q)
+    if (d.row_on[d.ri[q]]) return d.cva[q];
+  return 0.0;
+}
+
+__global__ void k_pc_keys(Dev d, ColScratch P) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.n) return;
+  int j = (int)t;
+  P.lead[j] = -1;
+  P.vals[j] = j;
+  uint32_t key = PC_NONE;
+  double2 b = d.bnd[j];
+  int lp = col_lp_of(d, j);
+  int q0 = d.cp[j], q1 = d.cp[j + 1];
+  if (b.x != b.y && d.col_len[j] >= 1 && q1 - q0 <= PC_MAX_LEN && !pc_lp_stopped(d, lp)) {
+    int row0 = d.K > 1 ? d.lp_row0[lp] : 0;
+    double f = pc_first(d, j);
+    unsigned long long h1 = 0, h2 = 0;
+    double c = d.c[j];
+    if (c != 0.0) {
+      unsigned long long id = splitmix(0xFFFFFFFFull);
+      h1 += 1 + id;
+      h2 += splitmix(id ^ quantize(c / f));
+    }
+    for (int q = q0; q < q1; ++q) {
+      int i = d.ri[q];
+      if (!d.row_on[i]) continue;
+      unsigned long long id = splitmix((unsigned long long)(uint32_t)(i - row0));
+      h1 += 1 + id;
+      h2 += splitmix(id ^ quantize(d.cva[q] / f));
+    }
+    key = (uint32_t)((splitmix(h1) ^ h2) >> 33);
+  }
+  P.key[j] = key;
+  P.keys[j] = key;
+}
+
+// batch: the LP of each sorted column, for the sort by LP
+__global__ void k_pc_lpkeys(Dev d, const int32_t* vals, uint32_t* keys) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < d.n) keys[t] = (uint32_t)d.col_lp[vals[t]];
+}
+
+// same augmented pattern and entries within par_tol after normalisation
+__device__ bool pc_parallel(const Dev& d, int j, int k, double fj, double fk) {
+  if ((d.c[j] != 0.0) != (d.c[k] != 0.0)) return false;
+  int qj = d.cp[j], ej = d.cp[j + 1], qk = d.cp[k], ek = d.cp[k + 1];
+  for (;;) {
+    while (qj < ej && !d.row_on[d.ri[qj]]) ++qj;
+    while (qk < ek && !d.row_on[d.ri[qk]]) ++qk;
+    bool hj = qj < ej, hk = qk < ek;
+    if (hj != hk) return false;
+    if (!hj) return true;
+    if (d.ri[qj] != d.ri[qk]) return false;
+    double a = d.cva[qj] / fj, bb = d.cva[qk] / fk;
+    double scale = fabs(a) > fabs(bb) ? fabs(a) : fabs(bb);
+    if (!(fabs(a - bb) <= d.cfg.par_tol * scale)) return false;
+    ++qj;
+    ++qk;
+  }
+}
+
+__device__ __forceinline__ double pc_canon(const Cfg& c, double v) {
+  if (fabs(v) >= c.inf_value) return v > 0 ? __builtin_inf() : -__builtin_inf();
+  return pos0(v);
+}
+
+// one thread per group head (sorted position): verify and merge in order
+__global__ void k_pc_group(Dev d, ColScratch P) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.n) return;
+  int k = P.vals[p];
+  uint32_t key = P.key[k];
+  if (key == PC_NONE) return;
+  int lp = col_lp_of(d, k);
+  if (p > 0) {
+    int kp = P.vals[p - 1];
+    if (P.key[kp] == key && col_lp_of(d, kp) == lp) return;  // not the group's first
+  }
+  double2 bk = d.bnd[k];
+  double lo = bk.x, up = bk.y;
+  double fk = pc_first(d, k);
+  bool any = false;
+  for (int64_t q = p + 1; q < d.n; ++q) {
+    int j = P.vals[q];
+    if (P.key[j] != key || col_lp_of(d, j) != lp) break;
+    double fj = pc_first(d, j);
+    if (!pc_parallel(d, j, k, fj, fk)) continue;
+    double lam = fj / fk;
+    double2 bj = d.bnd[j];
+    if (lam > 0) {
+      lo = pc_canon(d.cfg, lo + lam * bj.x);
+      up = pc_canon(d.cfg, up + lam * bj.y);
+    } else {
+      lo = pc_canon(d.cfg, lo + lam * bj.y);
+      up = pc_canon(d.cfg, up + lam * bj.x);
+    }
+    P.lead[j] = k;
+    P.lam[j] = lam;
+    any = true;
+  }
+  if (any) {
+    P.lead[k] = k;
+    P.nb[k] = make_double2(lo, up);
+  }
+}
+
+__global__ void k_pc_count(Dev d, ColScratch P) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < d.n) d.cnt[j] = P.lead[j] >= 0;
+}
+
+__global__ void k_pc_emit(Dev d, ColScratch P, int64_t base, int round) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.n) return;
+  int j = (int)t;
+  int k = P.lead[j];
+  if (k < 0) return;
+  int lp = col_lp_of(d, j);
+  double2 b = d.bnd[j];
+  Record r;
+  r.side = 0;
+  r.round = (uint16_t)round_of(d, lp, round);
+  r.i = -1;
+  r.j = j;
+  if (k == j) {
+    double2 nb = P.nb[j];
+    r.type = REC_LEADER_BOUNDS;
+    r.k = -1;
+    r.v[0] = b.x;
+    r.v[1] = b.y;
+    r.v[2] = nb.x;
+    r.v[3] = nb.y;
+    d.bnd[j] = nb;
+    d.bkey[2 * (int64_t)j] = dkey(nb.x);
+    d.bkey[2 * (int64_t)j + 1] = dkey(nb.y);
+    d.lsrc[j] = is_inf(nb.x) ? -1 : -2;
+    d.usrc[j] = is_inf(nb.y) ? -1 : -2;
+    d.touch[j] = 1;
+    // an interval that became infinite can make it a free singleton: check it
+    // at the next round's end
+    if (d.cfg.free_sing) d.fs_flag[j] = 1;
+  } else {
+    r.type = REC_PARALLEL_COL;
+    r.k = k;
+    r.v[0] = P.lam[j];
+    r.v[1] = b.x;
+    r.v[2] = b.y;
+    r.v[3] = 0.0;
+    d.bnd[j] = make_double2(0.0, 0.0);
+    d.bkey[2 * (int64_t)j] = dkey(0.0);
+    d.bkey[2 * (int64_t)j + 1] = dkey(0.0);
+    d.flags->merged = 1;
+    if (d.K > 1) d.lpf[lp].merged = 1;
+  }
+  d.rec[base + d.flags->round_total + d.off[t]] = r;
+}
+
+__global__ void k_pc_close(Dev d, const int32_t* total) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) d.flags->round_total += *total;
+}
+
+size_t par_cols_ws_ints(int64_t n) { return radix_ws_ints(n); }
+
+void launch_par_cols(const Dev& d, const ColScratch& P, int64_t base, int round, int32_t* ws, hipStream_t s) {
+  if (d.n == 0) return;
+  unsigned nb = (unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK);
+  hipLaunchKernelGGL(k_pc_keys, dim3(nb), dim3(PSL_BLOCK), 0, s, d, P);
+  // stable LSD sort of the columns by key (31 bits; non-candidates last)
+  uint32_t* ka = P.keys;
+  uint32_t* kb = P.keys2;
+  int32_t* va = P.vals;
+  int32_t* vb = P.vals2;
+  for (int shift = 0; shift < 32; shift += 8) {
+    radix_pass(ka, va, kb, vb, d.n, shift, 8, ws, s);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (d.K > 1) {  // then by LP, keeping the key order inside an LP
+    hipLaunchKernelGGL(k_pc_lpkeys, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)va, ka);
+    for (int shift = 0; (1ll << shift) < d.K; shift += 8) {
+      radix_pass(ka, va, kb, vb, d.n, shift, 8, ws, s);
+      std::swap(ka, kb);
+      std::swap(va, vb);
+    }
+  }
+  ColScratch Q = P;
+  Q.vals = va;  // the sorted order
+  hipLaunchKernelGGL(k_pc_group, dim3(nb), dim3(PSL_BLOCK), 0, s, d, Q);
+  hipLaunchKernelGGL(k_pc_count, dim3(nb), dim3(PSL_BLOCK), 0, s, d, Q);
+  scan_excl(d.cnt, d.off, d.n, P.total, ws, s);
+  hipLaunchKernelGGL(k_pc_emit, dim3(nb), dim3(PSL_BLOCK), 0, s, d, Q, base, round);
+  hipLaunchKernelGGL(k_pc_close, dim3(1), dim3(64), 0, s, d, (const int32_t*)P.total);
+}
+
+}  // namespace psl

@@ -630,7 +630,7 @@ extern "C" psl_status psl_server_postsolve(psl_server* sv, uint64_t ticket, cons
   std::string err;
   // a done ticket keeps no original rows (free-singleton records need them)
   st = postsolve_primal(t->records.data(), (int64_t)t->records.size(), t->view.col_map, t->lp.n, t->view.n, x_red,
-                        x, nullptr, &err);
+                        x, nullptr, sv->s.inf_value, &err);
   if (st != PSL_OK) sv->err = err;
   return st;
 }

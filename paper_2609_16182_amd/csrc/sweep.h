@@ -84,6 +84,21 @@ void launch_init_state(const Dev& d, hipStream_t s);
 // ints of scratch each, ws: scan workspace for nnz + 1 items
 void init_locks(const Dev& d, int32_t* dn, int32_t* up, int32_t* ws, hipStream_t s);
 
+// parcols.hip: parallel columns, after the parallel-row pass (records from
+// base + d.flags->round_total, which it raises by its own count; merged LPs
+// flagged in d.flags->merged / d.lpf). Scratch of n entries each:
+struct ColScratch {
+  uint32_t* key;            // per column: its key (0xFFFFFFFF: no candidate)
+  uint32_t *keys, *keys2;   // sort keys
+  int32_t *vals, *vals2;    // sort payload (columns)
+  int32_t* lead;            // per column: its leader (itself for a leader), else -1
+  double* lam;              // per merged column: lambda
+  double2* nb;              // per leader: merged interval
+  int32_t* total;           // [1] records
+};
+size_t par_cols_ws_ints(int64_t n);
+void launch_par_cols(const Dev& d, const ColScratch& P, int64_t base, int round, int32_t* ws, hipStream_t s);
+
 // singleton.hip: zero-cost free column singletons at the end of a round
 // (records from base + the round's record total; list: nnz / 32 + m ints of
 // scratch; adds its records to d.flags->round_total and its rows to
