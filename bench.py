@@ -345,7 +345,8 @@ def main():
         reductions = {}
         for name, extra in (("dual_fix", dict(enable_dual_fix=1)),
                             ("free_singletons", dict(enable_free_singletons=1)),
-                            ("both", dict(enable_dual_fix=1, enable_free_singletons=1))):
+                            ("parallel_cols", dict(enable_parallel_cols=1)),
+                            ("all", dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1))):
             q = psl.Presolver(dev, stream=stream.cuda_stream, **extra)
             for _ in range(2):
                 q.reload(dev)
@@ -364,7 +365,8 @@ def main():
                 "value": round(nnz * args.reduction_steps / dt, 1), "unit": "nnz/s", "steps": args.reduction_steps,
                 "ms_per_step": round(dt * 1e3 / args.reduction_steps, 3), "rounds": qs["rounds"],
                 "records": qs["records"], "dual_fixes": int((recs["type"] == 9).sum()),
-                "free_singletons": int((recs["type"] == 10).sum()), "nnz_out": qs["nnz_out"],
+                "free_singletons": int((recs["type"] == 10).sum()),
+                "parallel_cols": int((recs["type"] == 11).sum()), "nnz_out": qs["nnz_out"],
                 "m_out": qs["m_out"], "n_out": qs["n_out"], "ms_decide": round(qs["ms_decide"], 3),
                 "ms_run_device": round(qs["ms_total"], 3)}
 

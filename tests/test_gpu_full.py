@@ -42,20 +42,24 @@ def test_power_law_full_size(power_lp):
 
 
 @pytest.mark.parametrize("extra", [dict(enable_dual_fix=1), dict(enable_free_singletons=1),
-                                   dict(enable_dual_fix=1, enable_free_singletons=1)],
-                         ids=["dual_fix", "free_singletons", "both"])
+                                   dict(enable_parallel_cols=1),
+                                   dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1)],
+                         ids=["dual_fix", "free_singletons", "parallel_cols", "all"])
 def test_power_law_full_size_next_reductions(power_lp, extra):
     """The same LP with the optional reductions on (the benchmark's legs)."""
     lp = power_lp
     t0 = time.time()
     ref = O.presolve(lp, **extra)
-    kinds = {name: int((ref.records["type"] == O.REC[name]).sum()) for name in ("DUAL_FIX", "FREE_SINGLETON")}
+    kinds = {name: int((ref.records["type"] == O.REC[name]).sum())
+             for name in ("DUAL_FIX", "FREE_SINGLETON", "PARALLEL_COL")}
     print(f"oracle {ref.result_name} rounds={ref.rounds} records={len(ref.records)} {kinds} "
           f"in {time.time() - t0:.1f}s", flush=True)
     if extra.get("enable_dual_fix"):
         assert kinds["DUAL_FIX"] > 0
     if extra.get("enable_free_singletons"):
         assert kinds["FREE_SINGLETON"] > 0
+    if extra.get("enable_parallel_cols"):
+        assert kinds["PARALLEL_COL"] > 0
     got, p = psl.presolve(lp, **extra)
     print(f"gpu stats {got['stats']}", flush=True)
     p.close()
