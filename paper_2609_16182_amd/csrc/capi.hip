@@ -260,6 +260,7 @@ static psl_status setup_arena(psl_presolver* p) {
     ALLOC(p->pc.lead, n);
     ALLOC(p->pc.lam, n);
     ALLOC(p->pc.nb, n);
+    ALLOC(p->pc.terms, n);
     ALLOC(p->pc.total, 1);
   }
 

@@ -100,44 +100,75 @@ __device__ __forceinline__ double pc_canon(const Cfg& c, double v) {
   return pos0(v);
 }
 
-// one thread per group head (sorted position): verify and merge in order
-__global__ void k_pc_group(Dev d, ColScratch P) {
+// kind of each sorted position: 1 the first column of a group, 0 another
+// member of a group, 2 no candidate
+__global__ void k_pc_heads(Dev d, const int32_t* vals, const uint32_t* key, int32_t* kind) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.n) return;
-  int k = P.vals[p];
-  uint32_t key = P.key[k];
-  if (key == PC_NONE) return;
-  int lp = col_lp_of(d, k);
-  if (p > 0) {
-    int kp = P.vals[p - 1];
-    if (P.key[kp] == key && col_lp_of(d, kp) == lp) return;  // not the group's first
+  int k = vals[p];
+  uint32_t kk = key[k];
+  int r = 2;
+  if (kk != PC_NONE) {
+    r = 1;
+    if (p > 0) {
+      int kp = vals[p - 1];
+      if (key[kp] == kk && col_lp_of(d, kp) == col_lp_of(d, k)) r = 0;
+    }
   }
-  double2 bk = d.bnd[k];
-  double lo = bk.x, up = bk.y;
-  double fk = pc_first(d, k);
-  bool any = false;
-  for (int64_t q = p + 1; q < d.n; ++q) {
-    int j = P.vals[q];
-    if (P.key[j] != key || col_lp_of(d, j) != lp) break;
-    double fj = pc_first(d, j);
-    if (!pc_parallel(d, j, k, fj, fk)) continue;
+  kind[p] = r;
+}
+
+// heads[g] = sorted position of the first column of group g (seg: exclusive
+// scan of the head flags)
+__global__ void k_pc_headpos(Dev d, const int32_t* kind, const int32_t* seg, int32_t* heads) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < d.n && kind[p] == 1) heads[seg[p]] = (int)p;
+}
+
+// each other member against its group's first column; a merged member leaves
+// its scaled interval at its sorted position (NaN: not merged)
+__global__ void k_pc_verify(Dev d, ColScratch P, const int32_t* vals, const int32_t* kind, const int32_t* seg,
+                            const int32_t* heads) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.n || kind[p] != 0) return;
+  int j = vals[p];
+  int k = vals[heads[seg[p] - 1]];
+  double fj = pc_first(d, j), fk = pc_first(d, k);
+  double2 t = make_double2(__builtin_nan(""), 0.0);
+  if (pc_parallel(d, j, k, fj, fk)) {
     double lam = fj / fk;
     double2 bj = d.bnd[j];
-    if (lam > 0) {
-      lo = pc_canon(d.cfg, lo + lam * bj.x);
-      up = pc_canon(d.cfg, up + lam * bj.y);
-    } else {
-      lo = pc_canon(d.cfg, lo + lam * bj.y);
-      up = pc_canon(d.cfg, up + lam * bj.x);
-    }
+    t = lam > 0 ? make_double2(lam * bj.x, lam * bj.y) : make_double2(lam * bj.y, lam * bj.x);
     P.lead[j] = k;
     P.lam[j] = lam;
+  }
+  P.terms[p] = t;
+}
+
+// one thread per group: the merged interval, members added in column order
+__global__ void k_pc_accum(Dev d, ColScratch P, const int32_t* vals, const int32_t* kind) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.n || kind[p] != 1) return;
+  int k = vals[p];
+  double2 bk = d.bnd[k];
+  double lo = bk.x, up = bk.y;
+  bool any = false;
+  for (int64_t q = p + 1; q < d.n && kind[q] == 0; ++q) {
+    double2 t = P.terms[q];
+    if (t.x != t.x) continue;  // not merged
+    lo = pc_canon(d.cfg, lo + t.x);
+    up = pc_canon(d.cfg, up + t.y);
     any = true;
   }
   if (any) {
     P.lead[k] = k;
     P.nb[k] = make_double2(lo, up);
   }
+}
+
+__global__ void k_pc_flag1(Dev d, const int32_t* kind, int32_t* flag) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < d.n) flag[p] = kind[p] == 1;
 }
 
 __global__ void k_pc_count(Dev d, ColScratch P) {
@@ -219,9 +250,21 @@ void launch_par_cols(const Dev& d, const ColScratch& P, int64_t base, int round,
       std::swap(va, vb);
     }
   }
+  // groups: kinds (in the free key buffer), group numbers by a scan of the
+  // head flags, first positions (in the free value buffer)
+  int32_t* kind = reinterpret_cast<int32_t*>(ka);
+  int32_t* seg = reinterpret_cast<int32_t*>(kb);
+  int32_t* heads = vb;
+  hipLaunchKernelGGL(k_pc_heads, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)va, (const uint32_t*)P.key,
+                     kind);
+  hipLaunchKernelGGL(k_pc_flag1, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)kind, seg);
+  scan_excl(seg, seg, d.n, nullptr, ws, s);
+  hipLaunchKernelGGL(k_pc_headpos, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)kind, (const int32_t*)seg,
+                     heads);
+  hipLaunchKernelGGL(k_pc_verify, dim3(nb), dim3(PSL_BLOCK), 0, s, d, P, (const int32_t*)va, (const int32_t*)kind,
+                     (const int32_t*)seg, (const int32_t*)heads);
+  hipLaunchKernelGGL(k_pc_accum, dim3(nb), dim3(PSL_BLOCK), 0, s, d, P, (const int32_t*)va, (const int32_t*)kind);
   ColScratch Q = P;
-  Q.vals = va;  // the sorted order
-  hipLaunchKernelGGL(k_pc_group, dim3(nb), dim3(PSL_BLOCK), 0, s, d, Q);
   hipLaunchKernelGGL(k_pc_count, dim3(nb), dim3(PSL_BLOCK), 0, s, d, Q);
   scan_excl(d.cnt, d.off, d.n, P.total, ws, s);
   hipLaunchKernelGGL(k_pc_emit, dim3(nb), dim3(PSL_BLOCK), 0, s, d, Q, base, round);

@@ -94,6 +94,7 @@ struct ColScratch {
   int32_t* lead;            // per column: its leader (itself for a leader), else -1
   double* lam;              // per merged column: lambda
   double2* nb;              // per leader: merged interval
+  double2* terms;           // per sorted position: a merged member's scaled interval
   int32_t* total;           // [1] records
 };
 size_t par_cols_ws_ints(int64_t n);
