@@ -82,6 +82,8 @@ def test_batch_mixed_matches_oracle():
 @pytest.mark.parametrize("settings", [
     dict(enable_parallel_rows=0), dict(max_rounds=1), dict(max_outer=1), dict(max_rounds=2, max_outer=3),
     dict(min_improve=0.0), dict(bin_thresholds=(16, 2048)),
+    dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1),
+    dict(enable_parallel_rows=0, enable_parallel_cols=1, max_outer=2),
 ])
 def test_batch_settings(settings):
     lps = [lpgen.tiny(s) for s in range(20, 30)] + [lpgen.batch_member(i, m=150 + 50 * i) for i in range(6)]
@@ -96,6 +98,9 @@ def test_batch_of_one_and_empty_members():
     nocols = make(2, 0, [[], []], [-1.0, 0.0], [1.0, 0.0], [], [], [])
     nothing = make(0, 0, [], [], [], [], [], [])
     b, _ = check_batch([empty, lpgen.tiny(3), nocols, nothing, lpgen.tiny(4), empty, nothing], "empty members")
+    b.close()
+    b, _ = check_batch([empty, lpgen.tiny(3), nocols, nothing, lpgen.tiny(4), empty, nothing], "empty members, all",
+                       enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1)
     b.close()
 
 

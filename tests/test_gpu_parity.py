@@ -96,9 +96,12 @@ def test_edge_cases():
         "free row": make(1, 2, [[(0, 1.0), (1, 1.0)]], [-INF], [INF], [-INF, 0], [INF, 1], [0, 1]),
         "huge sides": make(1, 2, [[(0, 1.0), (1, 1.0)]], [-1e25], [1e21], [0, 0], [INF, 1], [1, 1]),
     }
+    options = ({}, dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1),
+               dict(enable_parallel_rows=0, enable_parallel_cols=1))
     for name, lp in cases.items():
-        got, ref = run_both(lp)
-        assert_same(got, ref, name)
+        for extra in options:
+            got, ref = run_both(lp, **extra)
+            assert_same(got, ref, f"{name} {extra}")
 
 
 def test_invalid_input_rejected_on_device():
