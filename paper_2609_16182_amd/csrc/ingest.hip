@@ -512,6 +512,7 @@ void select_rows(const Dev& d, const int32_t* mode_dev, int mode_host, int t_lon
 // its changed columns; columns of more than MARK_DENSE entries (listed once
 // at ingest) are walked by every workgroup of a second launch.
 #define MARK_DENSE 4096
+#define MARK_SHORT 16
 #define MARK_MASK (CC_LB | CC_UB | CC_FIX)
 
 // One entry (q, row i) of a changed column: mark the row (when the next
@@ -562,8 +563,14 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_mark_sparse(Dev d, RoundMode rm) 
   if (mark_col(code, mode)) {
     q0 = d.cp[j];
     q1 = d.cp[j + 1];
-    ch = q1 - q0 <= MARK_DENSE;
+    if (q1 - q0 <= MARK_SHORT) {
+      // a short column: its own lane walks it, beside the other lanes
+      for (int q = q0; q < q1; ++q) mark_entry(d, q, code, mode & 1, mode & 2);
+    } else {
+      ch = q1 - q0 <= MARK_DENSE;
+    }
   }
+  // longer ones: the wavefront walks them one after another
   unsigned long long mask = __ballot(ch);
   int lane = lane_id();
   while (mask) {

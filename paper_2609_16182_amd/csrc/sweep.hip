@@ -884,8 +884,8 @@ __global__ void __launch_bounds__(DEC_BLOCK) k_decide_count(Dev d, int32_t* tile
     d.col_code[j] = col_decide(d, j, kk);
     c += kk;
   }
-  int tot;
-  block_excl_scan_n<DEC_BLOCK>(c, &tot);
+  int tot = 0;
+  if (__syncthreads_or(c != 0)) block_excl_scan_n<DEC_BLOCK>(c, &tot);  // else a tile without records
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.flags->rows_removed = 0;
@@ -976,7 +976,9 @@ __device__ __forceinline__ int emit_col(const Dev& d, int j, int round, Record* 
 // scanned tile sums, positions inside the tile from a block scan of the
 // counts. Also counts the removed rows and (batches) marks the LPs that
 // changed.
-__global__ void __launch_bounds__(DEC_BLOCK) k_decide_emit(Dev d, const int32_t* tile_off, int64_t base, int round) {
+__global__ void __launch_bounds__(DEC_BLOCK) k_decide_emit(Dev d, const int32_t* tile_sum, const int32_t* tile_off,
+                                                            int64_t base, int round) {
+  if (tile_sum[blockIdx.x] == 0) return;  // a tile without records
   int64_t m = d.m, span = m + d.n;
   int64_t t0 = (int64_t)blockIdx.x * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
   int cnt[DEC_ITEMS];
@@ -1071,8 +1073,8 @@ void launch_decide(const Dev& d, int64_t base, int round, int32_t* tile_sum, int
   }
   hipLaunchKernelGGL(k_decide_count, dim3((unsigned)tiles), dim3(DEC_BLOCK), 0, s, d, tile_sum);
   scan_excl(tile_sum, tile_off, tiles, &d.flags->round_total, ws, s);
-  hipLaunchKernelGGL(k_decide_emit, dim3((unsigned)tiles), dim3(DEC_BLOCK), 0, s, d, (const int32_t*)tile_off, base,
-                     round);
+  hipLaunchKernelGGL(k_decide_emit, dim3((unsigned)tiles), dim3(DEC_BLOCK), 0, s, d, (const int32_t*)tile_sum,
+                     (const int32_t*)tile_off, base, round);
 }
 
 int long_max_passes() { return LONG_MAX_PASSES; }
