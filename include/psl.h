@@ -357,6 +357,12 @@ typedef struct {
     int32_t max_batch_lps;    /* LPs per batch                               */
     int32_t max_batch_rows, max_batch_cols;
     int64_t max_batch_nnz;    /* also the largest LP that can be served      */
+    int32_t keep_original;    /* 1: a done ticket keeps its LP's rows and
+                                 columns on the host (about 28 B per nonzero)
+                                 so that psl_server_postsolve can undo
+                                 FREE_SINGLETON records and give duals; 0
+                                 (default): primal postsolve only, without
+                                 FREE_SINGLETON records                      */
 } psl_server_config;
 
 /* Defaults: 64 GiB, 2 slots, threaded, 1024 LPs, 2.6e6 rows, 3.9e6 columns,
@@ -406,10 +412,11 @@ psl_status psl_server_reduced_problem(psl_server *sv, uint64_t ticket, psl_reduc
 /* The ticket's postsolve records (host copy; LP-local indices). */
 psl_status psl_server_records(psl_server *sv, uint64_t ticket, int64_t *count, psl_record *out, int64_t cap);
 
-/* As psl_postsolve, for the ticket's LP, primal only: y_red / z_red must be
- * NULL (PSL_ERR_UNSUPPORTED otherwise), since a done ticket keeps its reduced
- * problem and records but not the original matrix the dual pass reads; for
- * the same reason FREE_SINGLETON records give PSL_ERR_UNSUPPORTED. */
+/* As psl_postsolve, for the ticket's LP. A done ticket keeps its reduced
+ * problem and records; the original matrix that the dual pass and the undoing
+ * of FREE_SINGLETON records read is kept only when the server was created
+ * with keep_original = 1. Without it, a non-NULL y_red, or a FREE_SINGLETON
+ * record, gives PSL_ERR_UNSUPPORTED. */
 psl_status psl_server_postsolve(psl_server *sv, uint64_t ticket, const double *x_red, const double *y_red,
                                 const double *z_red, double *x, double *y, double *z);
 

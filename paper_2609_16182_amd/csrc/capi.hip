@@ -1284,6 +1284,8 @@ static psl_status host_rows(psl_presolver* p, int k, HostRows& A) {
   return PSL_OK;
 }
 
+psl_status psl::engine_host_rows(psl_presolver* p, int k, HostRows& A) { return host_rows(p, k, A); }
+
 // LP k's columns of the original (canonicalised) LP and their costs, copied
 // to the host; rows numbered within the LP
 static psl_status host_cols(psl_presolver* p, int k, HostCols& A) {
@@ -1344,6 +1346,8 @@ static psl_status postsolve_of(psl_presolver* p, int k, const double* x_red, con
   postsolve_dual(rec->data(), (int64_t)rec->size(), m, n, rmap, y_red, A, y, z);
   return PSL_OK;
 }
+
+psl_status psl::engine_host_cols(psl_presolver* p, int k, HostCols& A) { return host_cols(p, k, A); }
 
 bool psl::records_need_rows(const psl_record* rec, int64_t count) {
   for (int64_t t = 0; t < count; ++t)

@@ -192,5 +192,8 @@ struct HostCols {
 void postsolve_dual(const psl_record* rec, int64_t count, int32_t m, int32_t n, const std::vector<int32_t>& row_map,
                     const double* y_red, const HostCols& A, double* y, double* z);
 size_t engine_arena_bytes(const psl_presolver* p);
+// LP k's original rows / columns on the host (after a run; for postsolve)
+psl_status engine_host_rows(psl_presolver* p, int k, HostRows& A);
+psl_status engine_host_cols(psl_presolver* p, int k, HostCols& A);
 
 }  // namespace psl

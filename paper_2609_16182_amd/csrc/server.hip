@@ -167,6 +167,9 @@ struct Ticket {
   psl_reduced_view view{};
   std::vector<psl_record> records;
   std::string err;
+  bool kept = false;     // keep_original: the LP's rows and columns on the host
+  HostRows rows;
+  HostCols cols;
 };
 
 struct Slot {
@@ -210,6 +213,7 @@ extern "C" void psl_server_config_default(psl_server_config* c) {
   c->max_batch_rows = 2600000;
   c->max_batch_cols = 3900000;
   c->max_batch_nnz = 30000000;
+  c->keep_original = 0;
 }
 
 static size_t footprint(const psl_lp& lp) { return layout_of(lp.m, lp.n, lp.nnz).total; }
@@ -374,6 +378,20 @@ static void run_batch(psl_server* sv, Slot& sl, std::vector<Ticket*>& b) {
     if (!live[k]->records.empty())
       std::memcpy(live[k]->records.data(), sl.rec_host.data() + rec_at[k],
                   live[k]->records.size() * sizeof(psl_record));
+  // keep_original: the LPs' rows and columns, for postsolves that need them
+  if (sv->cfg.keep_original) {
+    for (size_t k = 0; k < live.size(); ++k) {
+      Ticket* t = live[k];
+      if (!t->has_block) continue;
+      psl_status s1 = engine_host_rows(sl.eng, (int)k, t->rows);
+      if (s1 == PSL_OK) s1 = engine_host_cols(sl.eng, (int)k, t->cols);
+      if (s1 != PSL_OK) {
+        fail_ticket(t, s1, engine_error(sl.eng));
+        continue;
+      }
+      t->kept = true;
+    }
+  }
 }
 
 static void worker(psl_server* sv, Slot* sl) {
@@ -616,10 +634,8 @@ extern "C" psl_status psl_server_records(psl_server* sv, uint64_t ticket, int64_
 
 extern "C" psl_status psl_server_postsolve(psl_server* sv, uint64_t ticket, const double* x_red, const double* y_red,
                                            const double* z_red, double* x, double* y, double* z) {
-  (void)y;
-  (void)z;
+  (void)z_red;  // reduced costs follow from the row duals
   if (!sv) return PSL_ERR_INVALID;
-  if (y_red || z_red) return sfail(sv, PSL_ERR_UNSUPPORTED, "dual postsolve is not provided");
   std::lock_guard<std::mutex> lk(sv->mu);
   Ticket* t = nullptr;
   psl_status st = done_ticket(sv, ticket, &t);
@@ -627,12 +643,25 @@ extern "C" psl_status psl_server_postsolve(psl_server* sv, uint64_t ticket, cons
   if (t->info.status != PSL_OK) return sfail(sv, t->info.status, t->err);
   if (!t->has_block) return sfail(sv, PSL_ERR_STATE, "no reduced problem to postsolve");
   if ((t->lp.n > 0 && !x) || (t->view.n > 0 && !x_red)) return sfail(sv, PSL_ERR_INVALID, "null solution array");
+  if (y_red && !t->kept)
+    return sfail(sv, PSL_ERR_UNSUPPORTED, "dual postsolve needs the original LP: create the server with keep_original");
+  if (y_red && ((t->lp.m > 0 && !y) || (t->lp.n > 0 && !z))) return sfail(sv, PSL_ERR_INVALID, "null dual array");
   std::string err;
-  // a done ticket keeps no original rows (free-singleton records need them)
+  // without keep_original a done ticket has no original rows (free-singleton
+  // records need them: PSL_ERR_UNSUPPORTED then)
   st = postsolve_primal(t->records.data(), (int64_t)t->records.size(), t->view.col_map, t->lp.n, t->view.n, x_red,
-                        x, nullptr, sv->s.inf_value, &err);
-  if (st != PSL_OK) sv->err = err;
-  return st;
+                        x, t->kept ? &t->rows : nullptr, sv->s.inf_value, &err);
+  if (st != PSL_OK) {
+    sv->err = err;
+    return st;
+  }
+  if (!y_red) return PSL_OK;
+  std::vector<int32_t> rmap(t->view.m);
+  if (t->view.m && hipMemcpy(rmap.data(), t->view.row_map, t->view.m * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+                       hipSuccess)
+    return sfail(sv, PSL_ERR_DEVICE, "HIP error copying the row map");
+  postsolve_dual(t->records.data(), (int64_t)t->records.size(), t->lp.m, t->lp.n, rmap, y_red, t->cols, y, z);
+  return PSL_OK;
 }
 
 extern "C" psl_status psl_server_release(psl_server* sv, uint64_t ticket) {

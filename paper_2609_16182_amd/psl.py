@@ -73,7 +73,7 @@ class psl_tuning(C.Structure):
 class psl_server_config(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("slots", C.c_int32), ("threaded", C.c_int32),
                 ("max_batch_lps", C.c_int32), ("max_batch_rows", C.c_int32), ("max_batch_cols", C.c_int32),
-                ("max_batch_nnz", C.c_int64)]
+                ("max_batch_nnz", C.c_int64), ("keep_original", C.c_int32)]
 
 
 class psl_ticket_info(C.Structure):
@@ -387,12 +387,10 @@ def psl_server_records(sv, ticket):
     return out
 
 
-def psl_server_postsolve(sv, ticket, x_red, n):
-    x_red = np.ascontiguousarray(x_red, np.float64)
-    x = np.zeros(n)
-    _scheck(load().psl_server_postsolve(sv, ticket, x_red.ctypes.data if x_red.size else None, None, None,
-                                        x.ctypes.data if n else None, None, None), sv)
-    return x
+def psl_server_postsolve(sv, ticket, x_red, n, y_red=None, m=0):
+    args, keep, out = _post_args(x_red, y_red, m, n)
+    _scheck(load().psl_server_postsolve(sv, ticket, *args), sv)
+    return out[0] if len(out) == 1 else out
 
 
 def psl_server_release(sv, ticket):
@@ -660,12 +658,14 @@ class Server:
         self.h = psl_server_create(self.cfg, self.settings)
         self._keep = {}
         self._n = {}
+        self._m = {}
 
     def submit(self, lp):
         keep = []
         t = psl_server_submit(self.h, make_lp(lp, keep))
         self._keep[t] = keep
         self._n[t] = int(lp["n"])
+        self._m[t] = int(lp["m"])
         return t
 
     def step(self):
@@ -691,13 +691,14 @@ class Server:
     def reduced(self, ticket):
         return reduced_to_host(self.view(ticket))
 
-    def postsolve(self, ticket, x_red):
-        return psl_server_postsolve(self.h, ticket, x_red, self._n[ticket])
+    def postsolve(self, ticket, x_red, y_red=None):
+        return psl_server_postsolve(self.h, ticket, x_red, self._n[ticket], y_red, self._m[ticket])
 
     def release(self, ticket):
         psl_server_release(self.h, ticket)
         self._keep.pop(ticket, None)
         self._n.pop(ticket, None)
+        self._m.pop(ticket, None)
 
     def drain(self):
         psl_server_drain(self.h)

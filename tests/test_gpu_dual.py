@@ -130,7 +130,7 @@ def test_dual_arguments_checked():
         p.close()
 
 
-def test_server_refuses_dual_postsolve():
+def test_server_refuses_dual_postsolve_without_original():
     lp = lpgen.single_small(seed=12)
     sv = psl.Server(hbm_budget_bytes=2 << 30, max_batch_lps=4, max_batch_rows=20_000, max_batch_cols=30_000,
                     max_batch_nnz=200_000)
@@ -148,5 +148,30 @@ def test_server_refuses_dual_postsolve():
         ref = O.presolve(lp)
         assert np.array_equal(_bits(sv.postsolve(t, xr)), _bits(ref.postsolve(xr)))
         sv.release(t)
+    finally:
+        sv.close()
+
+
+def test_server_dual_postsolve_with_original_kept():
+    """keep_original: every optional reduction on, several LPs per batch; the
+    server's primal and dual postsolves equal the oracle's bit for bit."""
+    extra = dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1)
+    lps = [lpgen.single_small(seed=s) for s in (12, 13)] + [lpgen.tiny(s) for s in range(6)]
+    sv = psl.Server(hbm_budget_bytes=2 << 30, max_batch_lps=8, max_batch_rows=20_000, max_batch_cols=30_000,
+                    max_batch_nnz=200_000, keep_original=1, **extra)
+    try:
+        ts = [sv.submit(lp) for lp in lps]
+        sv.drain()
+        for k, (t, lp) in enumerate(zip(ts, lps)):
+            sv.wait(t, 60_000)
+            ref = O.presolve(lp, **extra)
+            if ref.result_name not in ("REDUCED", "UNCHANGED"):
+                sv.release(t)
+                continue
+            red = psl.reduced_to_host(sv.view(t))
+            xr, yr = _random_duals(red, 50 + k)
+            _same_dual(sv.postsolve(t, xr, yr), ref.postsolve_dual(xr, yr), f"server LP {k}")
+            assert np.array_equal(_bits(sv.postsolve(t, xr)), _bits(ref.postsolve(xr)))
+            sv.release(t)
     finally:
         sv.close()
