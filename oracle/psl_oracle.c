@@ -66,8 +66,9 @@ enum { RES_REDUCED = 0, RES_UNCHANGED = 1, RES_INFEASIBLE = 2, RES_UNBOUNDED = 3
  *                 v = {old lhs, old rhs, new lhs, new rhs}
  *  DUAL_FIX       j, side (0 fixed at its lower, 1 at its upper bound);
  *                 v = {value, c_j}
- *  FREE_SINGLETON i = removed row, j = its free zero-cost column;
- *                 v = {a_ij, lhs_i, rhs_i} (the sides at that point)
+ *  FREE_SINGLETON i = removed row, j = its (implied) free column; side 0:
+ *                 c_j = 0, 1: the row went to its lhs, 2: to its rhs;
+ *                 v = {a_ij, lhs_i, rhs_i (the sides then), c_j (then)}
  *  PARALLEL_COL   j = merged column, k = its leader; v = {lambda, lb_j, ub_j}
  *  LEADER_BOUNDS  j = leader; v = {old lb, old ub, new lb, new ub}
  */
@@ -91,6 +92,7 @@ struct or_handle {
     int32_t *rp, *ci;
     double *va;
     double *lhs, *rhs, *lb, *ub, *c, off;
+    double *c0;  /* the input costs (c changes when a singleton is substituted) */
     or_settings s;
 
     uint8_t *row_on, *col_on;
@@ -269,6 +271,7 @@ static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s
     h->lb = (double *)xcalloc((size_t)n, sizeof(double));
     h->ub = (double *)xcalloc((size_t)n, sizeof(double));
     h->c = (double *)xcalloc((size_t)n, sizeof(double));
+    h->c0 = (double *)xcalloc((size_t)n + 1, sizeof(double));
     if (m > 0) memcpy(h->rp, lp->row_ptr, ((size_t)m + 1) * sizeof(int32_t));
     if (lp->nnz > 0) {
         memcpy(h->ci, lp->col_idx, (size_t)lp->nnz * sizeof(int32_t));
@@ -282,6 +285,7 @@ static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s
         h->lb[j] = canon_inf(lp->lb[j], s->inf_value);
         h->ub[j] = canon_inf(lp->ub[j], s->inf_value);
         h->c[j] = pos0(lp->c[j]);
+        h->c0[j] = h->c[j];
     }
     h->off = pos0(lp->obj_offset);
     return 0;
@@ -336,6 +340,7 @@ typedef struct {
     row_stats *st;
     int32_t *down, *up;        /* variable locks (dual fixing)      */
     int32_t *pick;             /* free singleton column of each row */
+    int32_t *owner;            /* lowest substituting row of each column */
 } round_ws;
 
 /* Implied bounds of row i on each of its active columns, from the residual
@@ -543,22 +548,29 @@ static int run_round(or_handle *h, round_ws *w) {
         }
     }
 
-    /* Free column singletons with zero cost (section 3.2, "Column
-     * singletons", without the objective substitution, which is zero): a
-     * column with c_j = 0 and one alive row i whose bounds are infinite or
-     * implied by row i alone (each finite bound came only from tightenings
-     * sourced by row i, from an infinite input bound) can absorb any value of
-     * row i's other terms within those bounds, so row i and the column leave
-     * together; postsolve takes x_j from the row. Candidates are read from
-     * the state after this round's decisions (rows removed here create no
-     * new ones until the next round); a row keeps its lowest candidate. */
+    /* Free column singletons (section 3.2, "Column singletons"): a column in
+     * one alive row i whose bounds are infinite or implied by row i alone
+     * (each finite bound came only from tightenings sourced by row i, from an
+     * infinite input bound) can absorb any value of row i's other terms
+     * within those bounds, so row i and the column leave together; postsolve
+     * takes x_j from the row. With c_j != 0 the column is substituted into
+     * the objective, x_j = (s - sum_k a_ik x_k) / a_ij with the row's
+     * activity s at the side the cost prefers (r = c_j / a_ij > 0: lhs,
+     * < 0: rhs; an infinite one: the LP is unbounded if feasible): every
+     * other cost of the row becomes c_k - r a_ik and the offset gains r s
+     * (the column is kept at s / a_ij with its cost). Such rows claim their
+     * columns and one applies only where it is the lowest claimant of each
+     * (an independent set by the lowest-index rule; the others wait for the
+     * next round). Candidates are read from the state after this round's
+     * decisions (rows removed here create none until the next round); a row
+     * keeps its lowest candidate. */
     if (s->enable_free_singletons && !infeasible && !unbounded) {
         for (int32_t i = 0; i < m; ++i) w->pick[i] = -1;
         for (int32_t i = 0; i < m; ++i) {
             if (!h->row_on[i]) continue;
             for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k) {
                 int32_t j = h->ci[k];
-                if (h->col_on[j] && h->col_len[j] == 1 && h->c[j] == 0 &&
+                if (h->col_on[j] && h->col_len[j] == 1 &&
                     (isinf(h->lb[j]) || h->lsrc[j] == i) && (isinf(h->ub[j]) || h->usrc[j] == i)) {
                     w->pick[i] = j;  /* columns ascend within a row: the lowest */
                     break;
@@ -567,11 +579,39 @@ static int run_round(or_handle *h, round_ws *w) {
         }
         for (int32_t i = 0; i < m; ++i) {
             int32_t j = w->pick[i];
-            if (j < 0) continue;
-            push(h, REC_FREE_SINGLETON, 0, i, j, -1, coef_in_row(h, i, j), h->lhs[i], h->rhs[i], 0);
-            h->col_on[j] = 0;
-            h->lb[j] = h->ub[j] = 0.0;
-            drop_row(h, i);
+            if (j < 0 || h->c[j] == 0) continue;
+            double r = h->c[j] / coef_in_row(h, i, j);
+            if (isinf(r > 0 ? h->lhs[i] : h->rhs[i])) unbounded = 1;
+        }
+        if (!unbounded) {
+            for (int32_t j = 0; j < n; ++j) w->owner[j] = INT32_MAX;
+            for (int32_t i = 0; i < m; ++i) {
+                int32_t j = w->pick[i];
+                if (j < 0 || h->c[j] == 0) continue;
+                for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k)
+                    if (w->owner[h->ci[k]] > i) w->owner[h->ci[k]] = i;
+            }
+            for (int32_t i = 0; i < m; ++i) {
+                int32_t j = w->pick[i];
+                if (j < 0) continue;
+                double a = coef_in_row(h, i, j), cj = h->c[j], v = 0.0;
+                int side = 0;
+                if (cj != 0) {
+                    int mine = 1;
+                    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k) mine &= w->owner[h->ci[k]] == i;
+                    if (!mine) continue;
+                    double r = cj / a;
+                    side = r > 0 ? 1 : 2;
+                    double sv = side == 1 ? h->lhs[i] : h->rhs[i];
+                    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k)
+                        if (h->ci[k] != j) h->c[h->ci[k]] = pos0(h->c[h->ci[k]] - r * h->va[k]);
+                    v = pos0(sv / a);
+                }
+                push(h, REC_FREE_SINGLETON, side, i, j, -1, a, h->lhs[i], h->rhs[i], cj);
+                h->col_on[j] = 0;
+                h->lb[j] = h->ub[j] = v;
+                drop_row(h, i);
+            }
         }
     }
 
@@ -1025,6 +1065,7 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     w.down = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     w.up = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     w.pick = (int32_t *)xcalloc((size_t)m + 1, sizeof(int32_t));
+    w.owner = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
 
     int stop = 0;
     for (int outer = 0; outer < s->max_outer && !stop; ++outer) {
@@ -1043,7 +1084,7 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     }
     free(w.lb_s); free(w.ub_s); free(w.lb_n); free(w.ub_n);
     free(w.src_lb); free(w.src_ub); free(w.tmin); free(w.tmax); free(w.dec); free(w.st);
-    free(w.down); free(w.up); free(w.pick);
+    free(w.down); free(w.up); free(w.pick); free(w.owner);
 
     if (h->result < RES_INFEASIBLE) {
         h->result = h->nrec ? RES_REDUCED : RES_UNCHANGED;
@@ -1150,7 +1191,8 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
             double rest = 0.0;
             for (int64_t k = h->rp[r->i]; k < h->rp[r->i + 1]; ++k)
                 if (h->ci[k] != r->j) rest = rest + h->va[k] * x[h->ci[k]];
-            double side = rest < r->v[1] ? r->v[1] : (rest > r->v[2] ? r->v[2] : rest);
+            double side = r->side == 1 ? r->v[1] : r->side == 2 ? r->v[2]
+                        : (rest < r->v[1] ? r->v[1] : (rest > r->v[2] ? r->v[2] : rest));
             x[r->j] = (side - rest) / r->v[0];
         }
     }
@@ -1192,7 +1234,7 @@ static double col_red_cost(const or_handle *h, const int32_t *cp, const int32_t 
                            const double *y, int32_t j) {
     double s = 0.0;
     for (int32_t q = cp[j]; q < cp[j + 1]; ++q) s = s + cva[q] * y[ri[q]];
-    return h->c[j] - s;
+    return h->c0[j] - s;
 }
 
 int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_red,
@@ -1227,6 +1269,9 @@ int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_r
             if (k < 0) continue;
             double zj = col_red_cost(h, cp, ri, cva, y, j);
             if ((r->side == 0 && zj > 0.0) || (r->side == 1 && zj < 0.0)) y[k] = y[k] + zj / r->v[2];
+        } else if (r->type == REC_FREE_SINGLETON) {
+            /* the substituted column is free: z_j = 0 gives the row's dual */
+            y[r->i] = r->v[3] / r->v[0];
         } else if (r->type == REC_LEADER_SIDES) {
             int32_t L = r->i;
             double yl = y[L];
@@ -1249,7 +1294,7 @@ int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_r
 void or_free(or_handle *h) {
     if (!h) return;
     free(h->rp); free(h->ci); free(h->va); free(h->lhs); free(h->rhs);
-    free(h->lb); free(h->ub); free(h->c); free(h->row_on); free(h->col_on); free(h->lsrc); free(h->usrc);
+    free(h->lb); free(h->ub); free(h->c); free(h->c0); free(h->row_on); free(h->col_on); free(h->lsrc); free(h->usrc);
     free(h->cp); free(h->ri); free(h->cva);
     free(h->col_len); free(h->rec);
     free(h->r_rp); free(h->r_ci); free(h->r_va); free(h->r_cp); free(h->r_ri); free(h->r_cva);

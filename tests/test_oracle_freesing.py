@@ -48,7 +48,13 @@ def replay_free_singletons(lp, res):
     n = 0
     for r in _fs(res):
         rd, i, j = int(r["round"]), int(r["i"]), int(r["j"])
-        assert lp["c"][j] == 0
+        side, cj = int(r["side"]), r["v"][3]
+        # the side the cost prefers (lhs for c_j / a_ij > 0), finite; 0 for no cost
+        if cj == 0:
+            assert side == 0
+        else:
+            assert side == (1 if cj / r["v"][0] > 0 else 2)
+            assert np.isfinite(r["v"][side])
         cols = ci[rp[i]:rp[i + 1]]
         assert j in cols
         assert va[rp[i] + int(np.nonzero(cols == j)[0][0])] == r["v"][0]
@@ -148,9 +154,11 @@ def test_finite_input_bound_cost_or_foreign_bound_excludes():
     # finite input lower bound
     lp = make(2, 3, base, [-INF, 1.0], [4.0, INF], [0, 0, 0], [INF, 5, 5], [0.0, 1.0, 1.0])
     assert not _fs(O.presolve(lp, **FS))
-    # nonzero cost
+    # nonzero cost towards an infinite side: unbounded, nothing eliminated
     lp = make(2, 3, base, [-INF, 1.0], [4.0, INF], [-INF, 0, 0], [INF, 5, 5], [1.0, 1.0, 1.0])
-    assert not _fs(O.presolve(lp, **FS))
+    res = O.presolve(lp, **FS)
+    assert res.result_name == "UNBOUNDED_OR_INFEASIBLE" and not _fs(res)
+    assert highs(lp)[0] == "unbounded"
     # the lower bound comes from another row (a singleton row x0 >= -3, removed)
     lp = make(3, 3, base + [[(0, 1.0)]], [-INF, 1.0, -3.0], [4.0, INF, INF], [-INF, 0, 0], [INF, 5, 5],
               [0.0, 1.0, 1.0])
@@ -202,3 +210,59 @@ def test_medium(seed):
 def test_tiny_family_fires():
     total = sum(len(_fs(O.presolve(zero_cost_free(lpgen.tiny(s)), **FS))) for s in range(300))
     assert total > 30
+
+
+def test_substitution_into_the_objective():
+    """min 2 x0 + x1 with x0 free in row 0 (x0 + x1 + x2 = 4) and row 1
+    (x1 + x2 >= 1), x1, x2 in [0, 5]: x0 = 4 - x1 - x2 leaves with row 0
+    (r = 2 > 0: the row at its lhs 4); the reduced costs are c1 = 1 - 2 = -1,
+    c2 = 0 - 2 = -2 and the offset 2 * 4 = 8; optimum -7 at x1 = x2 = 5,
+    x0 = -6."""
+    lp = make(2, 3, [[(0, 1.0), (1, 1.0), (2, 1.0)], [(1, 1.0), (2, 1.0)]], [4.0, 1.0], [4.0, INF],
+              [-INF, 0, 0], [INF, 5, 5], [2.0, 1.0, 0.0])
+    res = O.presolve(lp, **FS)
+    r = _fs(res)[0]
+    assert (int(r["i"]), int(r["j"]), int(r["side"]), int(r["round"])) == (0, 0, 1, 1)
+    red = res.reduced
+    assert list(red["c"]) == [-1.0, -2.0] and red["obj_offset"] == 8.0
+    x = res.postsolve(np.array([5.0, 5.0]))
+    assert np.array_equal(x, [-6.0, 5.0, 5.0])
+    _check_optimal(lp, res)
+
+
+def test_rows_sharing_a_column_take_turns():
+    """x0 (row 0: x0 + x2 = 3) and x1 (row 1: x1 + x2 = 5) are free with cost
+    1; both substitutions would change c2, so row 0 (the lowest) goes in
+    round 1 and row 1 in round 2: c2 = 0 - 1 - 1 = -2, offset 3 + 5 = 8; x2,
+    now in no row with cost -2, is fixed at its upper bound 10 in round 3:
+    offset 8 - 20 = -12 (min of x0 + x1 = 8 - 2 x2 over x2 in [0, 10])."""
+    lp = make(2, 3, [[(0, 1.0), (2, 1.0)], [(1, 1.0), (2, 1.0)]], [3.0, 5.0], [3.0, 5.0], [-INF, -INF, 0],
+              [INF, INF, 10], [1.0, 1.0, 0.0])
+    res = O.presolve(lp, **FS)
+    got = [(int(r["i"]), int(r["round"])) for r in _fs(res)]
+    assert got == [(0, 1), (1, 2)]
+    empty = [r for r in res.records if r["type"] == R["EMPTY_COL"]]
+    assert [(int(r["j"]), float(r["v"][0]), float(r["v"][1]), int(r["round"])) for r in empty] == [(2, 10.0, -2.0, 3)]
+    red = res.reduced
+    assert red["n"] == 0 and red["obj_offset"] == -12.0
+    x = res.postsolve(np.zeros(0))
+    assert np.array_equal(x, [-7.0, -5.0, 10.0])
+    _check_optimal(lp, res)
+
+
+@pytest.mark.parametrize("seed", range(300))
+def test_tiny_with_costs_replay_and_optimal(seed):
+    """The tiny family as generated: free columns with costs."""
+    lp = lpgen.tiny(seed, finite_bounds=False)
+    for df in (0, 1):
+        res = O.presolve(lp, **FS, enable_dual_fix=df)
+        replay_free_singletons(lp, res)
+        _check_optimal(lp, res)
+
+
+def test_tiny_with_costs_fire():
+    total = 0
+    for seed in range(300):
+        res = O.presolve(lpgen.tiny(seed, finite_bounds=False), **FS)
+        total += sum(1 for r in _fs(res) if r["v"][3] != 0)
+    assert total > 20
