@@ -119,15 +119,21 @@ typedef struct {
                                       optimal solution, not the feasible set.
                                       0 (default) or 1.                        */
     int32_t enable_free_singletons;/* 1: at the end of every round, a column
-                                      with c_j = 0 in one alive row i, whose
-                                      bounds are infinite or were tightened
-                                      only from row i (implied by it), leaves
-                                      with row i (FREE_SINGLETON, section 3.2
-                                      "Column singletons"; with c_j = 0 there
-                                      is no objective substitution); the
-                                      lowest such column of a row goes.
-                                      Postsolve takes x_j from the row.
-                                      0 (default) or 1.                        */
+                                      in one alive row i, whose bounds are
+                                      infinite or were tightened only from
+                                      row i (implied by it), leaves with row i
+                                      (FREE_SINGLETON, section 3.2 "Column
+                                      singletons"); the lowest such column of
+                                      a row goes. A column with a cost is
+                                      substituted into the objective: with
+                                      r = c_j / a_ij the row goes to its lhs
+                                      (r > 0) or rhs (r < 0; infinite:
+                                      PSL_RES_UNBOUNDED_OR_INFEASIBLE), the
+                                      row's other costs become c_k - r a_ik,
+                                      the offset gains r * side; rows sharing
+                                      a column then take turns, lowest first.
+                                      Postsolve takes x_j from the row, and
+                                      the row's dual is r. 0 (default) or 1.   */
     int32_t enable_parallel_cols;  /* 1: after the parallel rows, parallel
                                       columns (section 3.2, "Parallel
                                       columns": parallel rows of [c A'] over
@@ -156,9 +162,10 @@ typedef struct {
  *                         v = {old lhs, old rhs, new lhs, new rhs}
  *   type 9 DUAL_FIX       j, side (0 at its lower, 1 at its upper bound);
  *                         v = {value, c_j} (only with enable_dual_fix)
- *   type 10 FREE_SINGLETON i = removed row, j = its free zero-cost column;
- *                         v = {a_ij, lhs_i, rhs_i} (the sides at that point;
- *                         only with enable_free_singletons)
+ *   type 10 FREE_SINGLETON i = removed row, j = its (implied) free column;
+ *                         side 0: c_j = 0, 1: the row went to its lhs, 2: to
+ *                         its rhs; v = {a_ij, lhs_i, rhs_i, c_j} (the values
+ *                         then; only with enable_free_singletons)
  *   type 11 PARALLEL_COL  j = merged column, k = its leader;
  *                         v = {lambda (a_j = lambda a_k), lb_j, ub_j}
  *   type 12 LEADER_BOUNDS j = leader; v = {old lb, old ub, new lb, new ub}
@@ -242,9 +249,10 @@ psl_status psl_records(const psl_presolver *p, int64_t *count, psl_record *out, 
  *   Primal: x_red[n_red] -> x[n]. Kept columns come from x_red, removed
  *   columns from their FIX_COL / EMPTY_COL / DUAL_FIX records; then, last
  *   record first, a FREE_SINGLETON column from its row: with rest = the
- *   row's other terms (its original entries, left to right) and s = rest
- *   clamped to the recorded sides, x_j = (s - rest) / a_ij (the original rows
- *   are read back from the device); a LEADER_BOUNDS group splits its
+ *   row's other terms (its original entries, left to right) and s = the
+ *   recorded side (side 1: lhs, 2: rhs) or, for side 0, rest clamped to the
+ *   recorded sides, x_j = (s - rest) / a_ij (the original rows are read back
+ *   from the device); a LEADER_BOUNDS group splits its
  *   leader's merged value v: with B_0 = the old leader bounds and B_s =
  *   B_{s-1} + lambda_s [lb_s, ub_s] rebuilt in member order, members, last
  *   first, take the value in [lb_s, ub_s] keeping v - lambda_s x_s in
@@ -260,7 +268,8 @@ psl_status psl_records(const psl_presolver *p, int64_t *count, psl_record *out, 
  *   < 0 for an upper bound) moves it into row k (y_k += z_j / a_kj); a
  *   LEADER_SIDES record whose leader L has an active merged side (y_L > 0:
  *   lhs, < 0: rhs) moves y_L to the row r that gave that side
- *   (y_r = y_L / lambda_r, y_L = 0); the other records keep y. Then
+ *   (y_r = y_L / lambda_r, y_L = 0); a FREE_SINGLETON row takes
+ *   y_i = c_j / a_ij (recorded values); the other records keep y. Then
  *   z = c - A'y, each a_j'y summed over column j's rows in ascending order,
  *   left to right. The original matrix is read back from the device.
  *   z_red is accepted and not read (the reduced costs follow from y); y and

@@ -174,6 +174,7 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(bkey, 2 * n);
   ALLOC(src, 2 * n);
   ALLOC(p->c_mut, n);
+  ALLOC(p->c_work, n);
   ALLOC(col_len, n);
   ALLOC(row_on, m);
   ALLOC(row_code, m);
@@ -226,6 +227,8 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(d.usrc, n);
   ALLOC(d.fs_flag, n);
   ALLOC(d.fs_pick, m);
+  ALLOC(d.owner, n);
+  ALLOC(d.fs_bad, m);
   ALLOC(d.rinf, m);
   ALLOC(d.dense_cols, N / 4096 + 2);
   ALLOC(d.n_dense, 1);
@@ -348,7 +351,7 @@ static psl_status setup_arena(psl_presolver* p) {
   d.bnd = bnd;
   d.bkey = bkey;
   d.src = src;
-  d.c = p->c_mut;
+  d.c = p->c_work;
   d.col_len = col_len;
   d.row_on = row_on;
   d.row_code = row_code;
@@ -384,7 +387,7 @@ static psl_status setup_arena(psl_presolver* p) {
   // every device array the kernels index must exist (allocations are >= 64 B
   // even for empty problems); colid is set once the transposed copy exists
   const void* ptrs[] = {d.rp, d.ci, d.va, d.cp, d.ri, d.cva, d.lhs, d.rhs, d.bnd, d.bkey, d.src, d.c, d.locks,
-                        d.lsrc, d.usrc, d.fs_flag, d.fs_pick,
+                        d.lsrc, d.usrc, d.fs_flag, d.fs_pick, d.owner, d.fs_bad,
                         d.col_len, d.row_on, d.row_code, d.col_code, d.dirty, d.row_out, d.cand, d.cand_cnt,
                         d.flags, d.cnt, d.off, d.rec, d.bins, d.lchunk, d.lpart, d.lrow, p->lpr,
                         d.dense_cols, d.n_dense, d.touch, d.rinf, d.chunks0, d.dirty_tile};
@@ -906,6 +909,9 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   auto lp_merged = [&](int k) { return B ? p->h_lpf[k].merged != 0 : p->hflags->merged != 0; };
   auto lp_total = [&](int k) { return B ? p->h_lpo[k].total : p->hflags->round_total; };
 
+  // the run works on a copy of the costs (free-singleton substitutions
+  // change it); the input's stay for postsolve
+  if (n) HIPCHK(p, hipMemcpyAsync(p->c_work, p->c_mut, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   // round 0: input fixings
   launch_init_state(d, st);
   launch_round0_count(d, st);
@@ -1295,7 +1301,7 @@ static psl_status host_cols(psl_presolver* p, int k, HostCols& A) {
   A.cp.resize(n + 1);
   A.c.resize(n);
   HIPCHK(p, hipMemcpy(A.cp.data(), p->d.cp + c0, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
-  if (n) HIPCHK(p, hipMemcpy(A.c.data(), p->d.c + c0, n * sizeof(double), hipMemcpyDeviceToHost));
+  if (n) HIPCHK(p, hipMemcpy(A.c.data(), p->c_mut + c0, n * sizeof(double), hipMemcpyDeviceToHost));
   int64_t q0 = A.cp[0], q1 = A.cp[n];
   A.ri.resize(q1 - q0);
   A.cva.resize(q1 - q0);
@@ -1358,9 +1364,10 @@ bool psl::records_need_rows(const psl_record* rec, int64_t count) {
 // primal postsolve: kept columns from x_red, removed ones from their FIX_COL /
 // EMPTY_COL / DUAL_FIX records; then, last record first, each free singleton
 // column from its row (with rest = the row's other terms, its original
-// entries left to right, and s = rest clamped to the sides the row had,
-// x_j = (s - rest) / a_ij) and each group of parallel columns split from its
-// leader's merged value. The other records keep the feasible set.
+// entries left to right, and s = the recorded side the row went to, or rest
+// clamped to the sides without a cost, x_j = (s - rest) / a_ij) and each
+// group of parallel columns split from its leader's merged value. The other
+// records keep the feasible set.
 // a merged interval bound: |v| >= inf_value is infinite, -0 is +0
 static double merged_bound(double v, double inf_value) {
   if (std::fabs(v) >= inf_value) return v > 0 ? INFINITY : -INFINITY;
@@ -1448,7 +1455,7 @@ psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int
     double rest = 0.0;
     for (int32_t q = rows->rp[r.i]; q < rows->rp[r.i + 1]; ++q)
       if (rows->ci[q] != r.j) rest = rest + rows->va[q] * x[rows->ci[q]];
-    double side = rest < r.v[1] ? r.v[1] : (rest > r.v[2] ? r.v[2] : rest);
+    double side = r.side == 1 ? r.v[1] : r.side == 2 ? r.v[2] : (rest < r.v[1] ? r.v[1] : (rest > r.v[2] ? r.v[2] : rest));
     x[r.j] = (side - rest) / r.v[0];
   }
   return PSL_OK;
@@ -1469,8 +1476,9 @@ psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int
 //    rhs) belongs to the row r that gave it, a_r = lambda_r a_L:
 //    y_r = y_L / lambda_r and y_L = 0;
 //  * the other records keep y (a dual-fixed column has no lock towards its
-//    bound, so the alive rows' multipliers only push z_j to that bound's sign;
-//    a row that left with a free zero-cost singleton keeps y_i = c_j / a_ij = 0).
+//    bound, so the alive rows' multipliers only push z_j to that bound's sign);
+//  * a row that left with a free singleton takes y_i = c_j / a_ij (its column
+//    is free, z_j = 0; c_j is the cost it had then).
 // Finally z = c - A'y. Every a_j'y is summed over column j's rows in
 // ascending order, left to right.
 static double reduced_cost(const HostCols& A, const double* y, int32_t j) {
@@ -1493,6 +1501,8 @@ void psl::postsolve_dual(const psl_record* rec, int64_t count, int32_t m, int32_
       double zj = reduced_cost(A, y, r.j);
       bool binding = r.side == 0 ? zj > 0.0 : zj < 0.0;
       if (binding) y[r.k] = y[r.k] + zj / r.v[2];
+    } else if (r.type == REC_FREE_SINGLETON) {
+      y[r.i] = r.v[3] / r.v[0];  // the substituted column is free: z_j = 0
     } else if (r.type == REC_LEADER_SIDES) {
       int32_t L = r.i;
       double yl = y[L];

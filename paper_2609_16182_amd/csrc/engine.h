@@ -95,6 +95,7 @@ struct psl_presolver {
 
   // staging and persistent scratch
   double *lb_in = nullptr, *ub_in = nullptr, *c_mut = nullptr;
+  double* c_work = nullptr;  // the run's costs (c_mut holds the input's)
   IngestScratch isc{};
   int32_t* ws = nullptr;
   const uint32_t* colid = nullptr;

@@ -658,7 +658,7 @@ __global__ void k_init_state(Dev d) {
     Flags f;
     f.infeasible = f.unbounded = f.error = f.merged = 0;
     f.cand_count = f.round_total = f.vlist_count = f.rows_removed = 0;
-    f.fin_cols = f.mode = f.lead_count = f.fs_total = f.fs_rows = 0;
+    f.fin_cols = f.mode = f.lead_count = f.fs_total = f.fs_rows = f.fs_claims = 0;
     f.error_pos = 0x7FFFFFFFFFFFFFFFLL;
     *d.flags = f;
   }

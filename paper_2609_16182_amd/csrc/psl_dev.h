@@ -113,7 +113,8 @@ struct Flags {
                            // rows, their nonzeros, long-row chunks
   int32_t lead_count;      // parallel pass: leaders whose merged sides add locks
   int32_t fs_total;        // free singleton eliminations of the round
-  int32_t fs_rows;         // rows listed for their column drops
+  int32_t fs_rows;         // chunks of long eliminated rows listed
+  int32_t fs_claims;       // chunks of long substituting rows listed
 };
 
 struct Cfg {
@@ -139,7 +140,9 @@ struct Dev {
   double2 *bnd;
   long long *bkey;
   int32_t *src;
-  const double *c;
+  double *c;                   // costs (a working copy: substitutions change them)
+  int32_t *owner;              // free singletons: lowest substituting row per column
+  uint8_t *fs_bad;             // per row: a long substituting row lost a column
   int32_t *col_len;
   uint8_t *row_on, *row_code, *col_code;
   uint8_t *dirty;          // rows touched by a column change since last swept

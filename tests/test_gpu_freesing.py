@@ -1,6 +1,8 @@
-"""Zero-cost free column singletons on the GPU against the oracle, bit for
-bit (result, records, reduced problem), with enable_free_singletons = 1,
-alone and with dual fixing.
+"""Free column singletons on the GPU against the oracle, bit for bit
+(result, records, reduced problem), with enable_free_singletons = 1, alone
+and with dual fixing: zero-cost eliminations, and substitutions of columns
+with a cost (cost updates, the lowest-index turns of rows sharing a column,
+long rows through the chunked claim and update kernels).
 
 The library flags a column when it comes down to one row (and every column
 in the first round), finds its alive row on the transposed copy, tracks per
@@ -171,3 +173,73 @@ def test_setting_validated():
     with pytest.raises(psl.PslError) as ei:
         psl.Presolver(lpgen.tiny(0), enable_free_singletons=3)
     assert ei.value.status == psl.PSL_ERR_INVALID
+
+
+# ---- substitution of singletons with a cost ---------------------------------
+
+@pytest.mark.parametrize("seed", range(0, 120))
+def test_tiny_with_costs(seed):
+    lp = lpgen.tiny(seed, finite_bounds=False)
+    got, ref = run_both(lp, enable_dual_fix=seed % 2)
+    assert_same(got, ref, f"tiny with costs {seed}")
+
+
+def long_rows_sharing_columns(seed, m=6, width=80):
+    """Equality rows of `width` entries, each with one free column with a cost
+    and columns shared with the next row, so that long rows claim, lose and
+    substitute over rounds."""
+    rng = np.random.default_rng(seed)
+    n_shared = width - 1
+    n = m + n_shared * m // 2 + n_shared
+    rows, lhs, rhs = [], [], []
+    for i in range(m):
+        shared = list(range(m + (i * n_shared) // 2, m + (i * n_shared) // 2 + n_shared))
+        cols = [i] + shared
+        vals = rng.choice([-2.0, -1.0, 0.5, 1.0, 3.0], size=len(cols))
+        rows.append(list(zip(cols, vals)))
+        s = float(rng.uniform(1, 5))
+        lhs.append(s)
+        rhs.append(s)
+    lb = [-INF] * m + [0.0] * (n - m)
+    ub = [INF] * m + [2.0] * (n - m)
+    c = list(rng.choice([-1.0, 1.0, 2.0], size=m)) + list(rng.uniform(-1, 1, size=n - m))
+    return make(m, n, rows, lhs, rhs, lb, ub, c)
+
+
+def test_substitution_cases_and_long_rows():
+    cases = [
+        make(2, 3, [[(0, 1.0), (1, 1.0), (2, 1.0)], [(1, 1.0), (2, 1.0)]], [4.0, 1.0], [4.0, INF],
+             [-INF, 0, 0], [INF, 5, 5], [2.0, 1.0, 0.0]),
+        make(2, 3, [[(0, 1.0), (2, 1.0)], [(1, 1.0), (2, 1.0)]], [3.0, 5.0], [3.0, 5.0], [-INF, -INF, 0],
+             [INF, INF, 10], [1.0, 1.0, 0.0]),
+    ] + [long_rows_sharing_columns(s) for s in range(6)]
+    for k, lp in enumerate(cases):
+        ref = O.presolve(lp, **FS)
+        if k >= 2:
+            assert _n_fs(ref.records) > 0, k
+        got, ref = run_both(lp)
+        assert_same(got, ref, f"substitution case {k}")
+        if ref.result_name in ("REDUCED", "UNCHANGED"):
+            p = psl.Presolver(lp, **FS)
+            p.run()
+            rng = np.random.default_rng(k)
+            xr = rng.normal(size=got["reduced"]["n"])
+            yr = rng.normal(size=got["reduced"]["m"])
+            for a, b in zip(p.postsolve(xr, yr), ref.postsolve_dual(xr, yr)):
+                assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), k
+            p.close()
+
+
+def test_batch_with_costs_equals_alone():
+    lps = [lpgen.tiny(s, finite_bounds=False) for s in range(40)] + [long_rows_sharing_columns(s) for s in range(4)]
+    b = psl.Batch(lps, **FS, enable_dual_fix=1)
+    try:
+        b.run()
+        for idx, lp in enumerate(lps):
+            ref = O.presolve(lp, **FS, enable_dual_fix=1)
+            name = b.results[idx]
+            got = {"result_name": name, "records": b.records(idx),
+                   "reduced": b.reduced(idx) if name in ("REDUCED", "UNCHANGED") else None}
+            assert_same(got, ref, f"batch LP {idx}")
+    finally:
+        b.close()
