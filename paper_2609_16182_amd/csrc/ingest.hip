@@ -104,7 +104,12 @@ __global__ void k_csc_gather(Dev d, const int32_t* perm, const int32_t* rowid1, 
 
 // cp from the column-sorted keys: position q starts every column in
 // (keys[q-1], keys[q]] (keys[-1] = -1, keys[nnz] = n), so empty columns get
-// the next column's start
+// the next column's start. A thread writes at most the last COLPTR_RUN
+// entries of its run (always cp[keys[q]], the start of a nonempty column, and
+// cp[n]); longer runs of empty columns, e.g. a block of columns that appear in
+// no row, are left at -1 (cp is filled with -1 before) and resolved per column
+// in k_col_len, so no thread loops over a long run.
+#define COLPTR_RUN 64
 __global__ void k_col_ptr(Dev d, const uint32_t* keys, int32_t* cp) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= d.nnz; q += (int64_t)gridDim.x * blockDim.x) {
     int64_t prev = q > 0 ? (int64_t)keys[q - 1] : -1;
@@ -112,14 +117,34 @@ __global__ void k_col_ptr(Dev d, const uint32_t* keys, int32_t* cp) {
     // keys were validated (< n); clamped all the same so no store leaves cp
     prev = prev < (int64_t)d.n ? prev : (int64_t)d.n;
     cur = cur < (int64_t)d.n ? cur : (int64_t)d.n;
-    for (int64_t j = prev + 1; j <= cur; ++j) cp[j] = (int32_t)q;
+    int64_t j0 = cur - prev > COLPTR_RUN ? cur - COLPTR_RUN : prev;
+    for (int64_t j = j0 + 1; j <= cur; ++j) cp[j] = (int32_t)q;
   }
 }
 
-__global__ void k_col_len(Dev d, const int32_t* cp, int32_t* col_len) {
+// first position whose key is >= j (keys ascend): the start of column j
+__device__ __forceinline__ int32_t col_start(const uint32_t* keys, int64_t nnz, int64_t j) {
+  int64_t lo = 0, hi = nnz;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)keys[mid] < j) lo = mid + 1;
+    else hi = mid;
+  }
+  return (int32_t)lo;
+}
+
+// column lengths; entries of cp a long run left at -1 get the start of the
+// next nonempty column by a search over the keys (cp[n] is always written)
+__global__ void k_col_len(Dev d, const uint32_t* keys, int32_t* cp, int32_t* col_len) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= d.n) return;
-  col_len[j] = cp[j + 1] - cp[j];
+  int32_t a = cp[j], b = cp[j + 1];
+  if (a < 0) {
+    a = col_start(keys, d.nnz, j);
+    cp[j] = a;
+  }
+  if (b < 0) b = col_start(keys, d.nnz, j + 1);  // written by thread j + 1
+  col_len[j] = b - a;
 }
 
 // Stable transpose by LSD radix passes over the column index (at most 8 bits
@@ -160,14 +185,15 @@ const uint32_t* build_csc(const Dev& d, int32_t* cp, int32_t* ri, double* cva, i
       vin = vout;
     }
   }
+  fill_i32(cp, -1, d.n + 1, s);
   {
     int64_t blocks = (d.nnz + 1 + PSL_BLOCK - 1) / PSL_BLOCK;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_col_ptr, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, kin, cp);
   }
   if (d.n > 0)
-    hipLaunchKernelGGL(k_col_len, dim3((d.n + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d,
-                       (const int32_t*)cp, col_len);
+    hipLaunchKernelGGL(k_col_len, dim3((d.n + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, kin, cp,
+                       col_len);
   return kin;
 }
 

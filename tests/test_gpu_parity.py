@@ -104,6 +104,55 @@ def test_edge_cases():
             assert_same(got, ref, f"{name} {extra}")
 
 
+def with_empty_block(lp, at, size, seed=0):
+    """The LP with `size` columns that appear in no row inserted before column
+    `at` (bounds [0, 1], costs of both signs and zero)."""
+    rng = np.random.default_rng(seed)
+    ci = np.asarray(lp["col_idx"]).astype(np.int64)
+    out = dict(lp)
+    out["col_idx"] = np.where(ci >= at, ci + size, ci).astype(np.int32)
+    out["n"] = lp["n"] + size
+    for k, v in (("lb", 0.0), ("ub", 1.0)):
+        a = np.asarray(lp[k], float)
+        out[k] = np.concatenate([a[:at], np.full(size, v), a[at:]])
+    c = np.asarray(lp["c"], float)
+    out["c"] = np.concatenate([c[:at], rng.choice([-1.0, 0.0, 2.0], size=size), c[at:]])
+    return out
+
+
+def by_popularity(lp):
+    """The LP with its columns renumbered by descending count (stable), the
+    entries of each row sorted again: dense columns first, empty ones last."""
+    n = lp["n"]
+    ci = np.asarray(lp["col_idx"])
+    order = np.argsort(-np.bincount(ci, minlength=n), kind="stable")
+    new_of = np.empty(n, np.int64)
+    new_of[order] = np.arange(n)
+    nci = new_of[ci]
+    rows = np.repeat(np.arange(lp["m"]), np.diff(np.asarray(lp["row_ptr"])))
+    o = np.lexsort((nci, rows))
+    out = dict(lp)
+    out["col_idx"] = nci[o].astype(np.int32)
+    out["val"] = np.asarray(lp["val"])[o]
+    for k in ("lb", "ub", "c"):
+        out[k] = np.asarray(lp[k])[order]
+    return out
+
+
+def test_long_runs_of_empty_columns():
+    """Column pointers of the transposed copy where thousands of columns in a
+    row appear in no row: at the start, in the middle, at the end, an LP with
+    no entries, and the power-law LP with its empty columns last."""
+    base = lpgen.single_small(seed=3)
+    cases = {f"block at {at}": with_empty_block(base, at, 5000, seed=at) for at in (0, 1500, base["n"])}
+    cases["no entries"] = make(3, 3000, [[], [], []], [-1.0, -INF, 0.0], [1.0, INF, INF], [0.0] * 3000, [1.0] * 3000,
+                               list(np.resize([1.0, -1.0, 0.0], 3000)))
+    cases["power-law by popularity"] = by_popularity(lpgen.power_law(scale=0.02))
+    for name, lp in cases.items():
+        got, ref = run_both(lp)
+        assert_same(got, ref, name)
+
+
 def test_invalid_input_rejected_on_device():
     good = make(2, 3, [[(0, 1.0), (2, 1.0)], [(1, 2.0)]], [-INF, 0.0], [4.0, 1.0], [0, 0, 0], [1, 1, 1], [0, 0, 0])
     bad = []
