@@ -36,26 +36,60 @@ __device__ __forceinline__ bool lp_stopped(const Dev& d, int lp) {
   return (d.flags->infeasible | d.flags->unbounded) != 0;
 }
 
-__global__ void k_fs_pick(Dev d) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= d.n || !d.fs_flag[j]) return;
-  d.fs_flag[j] = 0;
+// the column's one alive row i takes the column when each bound side is
+// infinite or was tightened only from row i
+__device__ __forceinline__ void fs_offer(const Dev& d, int j, int i) {
   double2 b = d.bnd[j];
-  if (b.x == b.y || d.col_len[j] != 1) return;
-  if (lp_stopped(d, col_lp_of(d, (int)j))) return;
-  // its one alive row
-  int i = -1;
-  for (int q = d.cp[j]; q < d.cp[j + 1]; ++q) {
-    int r = d.ri[q];
-    if (d.row_on[r]) {
-      i = r;
-      break;
-    }
-  }
-  if (i < 0) return;
   bool lo_ok = is_inf(b.x) || d.lsrc[j] == i;
   bool up_ok = is_inf(b.y) || d.usrc[j] == i;
-  if (lo_ok && up_ok) atomicMin(&d.fs_pick[i], (int)j);
+  if (lo_ok && up_ok) atomicMin(&d.fs_pick[i], j);
+}
+
+// flagged columns of length 1 find their alive row on the transposed copy:
+// columns stored with at most FS_PICK_SHORT entries in their own lane, longer
+// ones (a dense column down to one row) by the whole wavefront, one after
+// another, 64 positions a step
+#define FS_PICK_SHORT 64
+__global__ void __launch_bounds__(PSL_BLOCK) k_fs_pick(Dev d) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool want = false;
+  if (j < d.n && d.fs_flag[j]) {
+    d.fs_flag[j] = 0;
+    double2 b = d.bnd[j];
+    want = b.x != b.y && d.col_len[j] == 1 && !lp_stopped(d, col_lp_of(d, (int)j));
+  }
+  int q0 = 0, q1 = 0;
+  if (want) {
+    q0 = d.cp[j];
+    q1 = d.cp[j + 1];
+  }
+  bool longc = want && q1 - q0 > FS_PICK_SHORT;
+  if (want && !longc) {
+    for (int q = q0; q < q1; ++q) {
+      int r = d.ri[q];
+      if (d.row_on[r]) {
+        fs_offer(d, (int)j, r);
+        break;
+      }
+    }
+  }
+  unsigned long long mask = __ballot(longc);
+  int lane = lane_id();
+  while (mask) {
+    int l = __ffsll((long long)mask) - 1;
+    mask &= mask - 1;
+    int jl = __shfl((int)j, l, PSL_WAVE), a = __shfl(q0, l, PSL_WAVE), e = __shfl(q1, l, PSL_WAVE);
+    for (int base = a; base < e; base += PSL_WAVE) {
+      int q = base + lane;
+      int r = q < e ? d.ri[q] : -1;
+      unsigned long long hit = __ballot(r >= 0 && d.row_on[r]);
+      if (hit) {  // the same on every lane
+        int i = __shfl(r, __ffsll((long long)hit) - 1, PSL_WAVE);
+        if (lane == 0) fs_offer(d, jl, i);
+        break;
+      }
+    }
+  }
 }
 
 // coefficient of column j in row i (columns ascend within a row)

@@ -243,3 +243,26 @@ def test_batch_with_costs_equals_alone():
             assert_same(got, ref, f"batch LP {idx}")
     finally:
         b.close()
+
+
+def dense_column_down_to_one_row(rows, cost, seed=0):
+    """`rows` scaled copies of x0 + x1 (inequalities, removed as parallel to
+    the leader) and, last, the equality x0 + x1 = 5 that leads them: the free
+    column x0, stored with `rows` entries, keeps one alive row, its last."""
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(0.5, 3.0, size=rows - 1) * rng.choice([-1.0, 1.0], size=rows - 1)
+    body = [[(0, l), (1, l)] for l in lam] + [[(0, 1.0), (1, 1.0)]]
+    lhs = [(-INF if l > 0 else 7.0 * l) for l in lam] + [5.0]
+    rhs = [(7.0 * l if l > 0 else INF) for l in lam] + [5.0]
+    return make(rows, 3, body + [], lhs, rhs, [-INF, 0.0, 0.0], [INF, 10.0, 1.0], [cost, 1.0, -1.0])
+
+
+def test_dense_column_down_to_one_row():
+    """A free column stored with up to 5000 entries becomes a singleton after
+    the parallel-row pass; its row is found by the wavefront walk."""
+    for rows in (65, 200, 5000):
+        for cost in (0.0, 2.0, -1.0):
+            lp = dense_column_down_to_one_row(rows, cost, seed=rows)
+            got, ref = run_both(lp)
+            assert _n_fs(ref.records) == 1, (rows, cost)
+            assert_same(got, ref, f"dense column {rows} cost {cost}")
