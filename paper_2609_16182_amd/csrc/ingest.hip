@@ -672,6 +672,7 @@ __global__ void k_init_state(Dev d) {
     double2 b = d.bnd[t];
     d.touch[t] = 1;    // the first round decides every column
     d.fs_flag[t] = 1;  // and checks every column for a free singleton
+    d.owner[t] = ~0ull;
     d.lsrc[t] = is_inf(b.x) ? -1 : -2;
     d.usrc[t] = is_inf(b.y) ? -1 : -2;
     d.bkey[2 * t] = dkey(b.x);

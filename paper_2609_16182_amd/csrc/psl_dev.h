@@ -141,7 +141,8 @@ struct Dev {
   long long *bkey;
   int32_t *src;
   double *c;                   // costs (a working copy: substitutions change them)
-  int32_t *owner;              // free singletons: lowest substituting row per column
+  unsigned long long *owner;   // free singletons: per column the lowest claim, (~round << 32) | row,
+                               // so a claim of the current round beats an older one (reset per run)
   uint8_t *fs_bad;             // per row: a long substituting row lost a column
   int32_t *col_len;
   uint8_t *row_on, *row_code, *col_code;

@@ -52,6 +52,7 @@ __device__ __forceinline__ void fs_offer(const Dev& d, int j, int i) {
 #define FS_PICK_SHORT 64
 __global__ void __launch_bounds__(PSL_BLOCK) k_fs_pick(Dev d) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0) d.flags->fs_claims = 0;
   bool want = false;
   if (j < d.n && d.fs_flag[j]) {
     d.fs_flag[j] = 0;
@@ -110,9 +111,15 @@ __device__ __forceinline__ void list_chunks(int32_t* list, int32_t* count, int p
   for (int c = 0; c < nch; ++c) list[c0 + c] = p0 + c * FS_CHUNK;
 }
 
+// the claim of row i in a round: claims of the round compare by row, and any
+// of them is below a claim left from an earlier round of the run
+__device__ __forceinline__ unsigned long long fs_key(int round, int i) {
+  return ((unsigned long long)(0xFFFFFFFFu - (unsigned)round) << 32) | (unsigned)i;
+}
+
 // rows whose column has a cost: an infinite preferred side stops the LP;
 // otherwise they claim their columns (long rows through the claim list)
-__global__ void k_fs_claim(Dev d, int32_t* clist) {
+__global__ void k_fs_claim(Dev d, int32_t* clist, int round) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d.m) return;
   int i = (int)t;
@@ -131,51 +138,59 @@ __global__ void k_fs_claim(Dev d, int32_t* clist) {
     list_chunks(clist, &d.flags->fs_claims, p0, len);
     return;
   }
-  for (int p = p0; p < p0 + len; ++p) atomicMin(&d.owner[d.ci[p]], i);
+  unsigned long long key = fs_key(round, i);
+  for (int p = p0; p < p0 + len; ++p) atomicMin(&d.owner[d.ci[p]], key);
 }
 
 // chunks of long claiming rows: MODE 0 claims the columns, MODE 1 marks the
 // row when a lower row holds one of them
 template <int MODE>
-__global__ void __launch_bounds__(PSL_BLOCK) k_fs_claim_long(Dev d, const int32_t* clist) {
+__global__ void __launch_bounds__(PSL_BLOCK) k_fs_claim_long(Dev d, const int32_t* clist, int round) {
   int nc = d.flags->fs_claims;
   for (int k = blockIdx.x; k < nc; k += gridDim.x) {
     int p0 = clist[k];
     int i = d.rowid1[p0 + 1];
     int p = p0 + (int)threadIdx.x;
     if (p < d.rp[i + 1]) {
-      if (MODE == 0) atomicMin(&d.owner[d.ci[p]], i);
-      else if (d.owner[d.ci[p]] != i) d.fs_bad[i] = 1;
+      unsigned long long key = fs_key(round, i);
+      if (MODE == 0) atomicMin(&d.owner[d.ci[p]], key);
+      else if (d.owner[d.ci[p]] != key) d.fs_bad[i] = 1;
     }
   }
 }
 
 // a row applies when its LP goes on and, with a cost, it holds every column
-__device__ __forceinline__ bool fs_applies(const Dev& d, int i, int j) {
+__device__ __forceinline__ bool fs_applies(const Dev& d, int i, int j, int round) {
   if (lp_stopped(d, row_lp_of(d, i))) return false;
   if (d.c[j] == 0.0) return true;
   int p0 = d.rp[i], len = d.rp[i + 1] - p0;
   if (len > FS_SHORT) return d.fs_bad[i] == 0;
+  unsigned long long key = fs_key(round, i);
   for (int p = p0; p < p0 + len; ++p)
-    if (d.owner[d.ci[p]] != i) return false;
+    if (d.owner[d.ci[p]] != key) return false;
   return true;
 }
 
-__global__ void k_fs_count(Dev d) {
+// applying rows keep their pick, the others drop it; d.cnt gets the count
+// of each tile of PSL_BLOCK rows
+__global__ void __launch_bounds__(PSL_BLOCK) k_fs_count(Dev d, int round) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) d.flags->fs_rows = 0;
-  if (i >= d.m) return;
-  int j = d.fs_pick[i];
   int k = 0;
-  if (j != FS_NONE) {
-    if (fs_applies(d, (int)i, j)) {
-      k = 1;
-    } else {  // waits for the next round: its column is checked again then
-      d.fs_pick[i] = FS_NONE;
-      d.fs_flag[j] = 1;
+  if (i < d.m) {
+    int j = d.fs_pick[i];
+    if (j != FS_NONE) {
+      if (fs_applies(d, (int)i, j, round)) {
+        k = 1;
+      } else {  // waits for the next round: its column is checked again then
+        d.fs_pick[i] = FS_NONE;
+        d.fs_flag[j] = 1;
+      }
     }
   }
-  d.cnt[i] = k;
+  int tot;
+  block_excl_scan(k, &tot);
+  if (threadIdx.x == 0) d.cnt[blockIdx.x] = tot;
 }
 
 // the other columns of an applying row: a new cost (with a substitution) and
@@ -189,16 +204,19 @@ __device__ __forceinline__ void fs_entry(const Dev& d, int jj, double a, double2
   if (b.x != b.y) drop_col(d, jj, a, lhs, rhs);
 }
 
-// records after the round's decision records; the row leaves, its column is
-// set to s / a_ij (0 without a cost); a short row updates and leaves its
-// other columns here, a long one is listed in chunks (and keeps its pick for
-// them)
-__global__ void k_fs_emit(Dev d, int32_t* list, int64_t base, int round) {
+// records after the round's decision records, in row order (tile offsets
+// from the scanned tile counts, a block scan inside the tile); the row
+// leaves, its column is set to s / a_ij (0 without a cost); a short row
+// updates and leaves its other columns here, a long one is listed in chunks
+// (and keeps its pick for them)
+__global__ void __launch_bounds__(PSL_BLOCK) k_fs_emit(Dev d, int32_t* list, int64_t base, int round) {
+  if (d.cnt[blockIdx.x] == 0) return;  // no row of the tile applies
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= d.m) return;
-  int i = (int)t;
-  int j = d.fs_pick[i];
+  int j = t < d.m ? d.fs_pick[t] : FS_NONE;
+  int tot;
+  int pre = block_excl_scan(j != FS_NONE ? 1 : 0, &tot);
   if (j == FS_NONE) return;
+  int i = (int)t;
   int lp = row_lp_of(d, i);
   double a = coef_of(d, i, j), cj = d.c[j];
   double lhs = d.lhs[i], rhs = d.rhs[i];
@@ -216,7 +234,7 @@ __global__ void k_fs_emit(Dev d, int32_t* list, int64_t base, int round) {
   rec.v[1] = lhs;
   rec.v[2] = rhs;
   rec.v[3] = cj;
-  d.rec[base + d.flags->round_total + d.off[t]] = rec;
+  d.rec[base + d.flags->round_total + d.off[blockIdx.x] + pre] = rec;
   d.row_on[i] = 0;
   d.bnd[j] = make_double2(v, v);
   d.bkey[2 * (int64_t)j] = dkey(v);
@@ -287,14 +305,13 @@ void launch_free_singletons(const Dev& d, int32_t* list, int64_t base, int round
   int32_t* clist = list + (d.nnz / FS_SHORT + d.m + 64);
   unsigned cb = (unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK);
   unsigned rb = (unsigned)((d.m + PSL_BLOCK - 1) / PSL_BLOCK);
-  fill_i32(d.owner, FS_NONE, d.n, s);
-  fill_i32(&d.flags->fs_claims, 0, 1, s);
   hipLaunchKernelGGL(k_fs_pick, dim3(cb), dim3(PSL_BLOCK), 0, s, d);
-  hipLaunchKernelGGL(k_fs_claim, dim3(rb), dim3(PSL_BLOCK), 0, s, d, clist);
-  hipLaunchKernelGGL((k_fs_claim_long<0>), dim3(1024), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)clist);
-  hipLaunchKernelGGL((k_fs_claim_long<1>), dim3(1024), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)clist);
-  hipLaunchKernelGGL(k_fs_count, dim3(rb), dim3(PSL_BLOCK), 0, s, d);
-  scan_excl(d.cnt, d.off, d.m, &d.flags->fs_total, ws, s);
+  hipLaunchKernelGGL(k_fs_claim, dim3(rb), dim3(PSL_BLOCK), 0, s, d, clist, round);
+  hipLaunchKernelGGL((k_fs_claim_long<0>), dim3(1024), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)clist, round);
+  hipLaunchKernelGGL((k_fs_claim_long<1>), dim3(1024), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)clist, round);
+  hipLaunchKernelGGL(k_fs_count, dim3(rb), dim3(PSL_BLOCK), 0, s, d, round);
+  // tile counts (rb <= m entries of d.cnt) scanned
+  scan_excl(d.cnt, d.off, rb, &d.flags->fs_total, ws, s);
   hipLaunchKernelGGL(k_fs_emit, dim3(rb), dim3(PSL_BLOCK), 0, s, d, list, base, round);
   hipLaunchKernelGGL(k_fs_drop, dim3(1024), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)list);
   hipLaunchKernelGGL(k_fs_reset, dim3(64), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)list);

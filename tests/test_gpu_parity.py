@@ -153,6 +153,39 @@ def test_long_runs_of_empty_columns():
         assert_same(got, ref, name)
 
 
+def rows_by_length(lp, longest_first=True):
+    """The LP with its rows reordered by length (stable): long rows adjacent."""
+    rp = np.asarray(lp["row_ptr"], np.int64)
+    lens = np.diff(rp)
+    order = np.argsort(-lens if longest_first else lens, kind="stable")
+    starts = rp[order]
+    idx = np.concatenate([np.arange(a, a + k) for a, k in zip(starts, lens[order])]) if len(order) else starts
+    out = dict(lp)
+    out["row_ptr"] = np.concatenate([[0], np.cumsum(lens[order])]).astype(np.int32)
+    out["col_idx"] = np.asarray(lp["col_idx"])[idx]
+    out["val"] = np.asarray(lp["val"])[idx]
+    for k in ("lhs", "rhs"):
+        out[k] = np.asarray(lp[k])[order]
+    return out
+
+
+ALL_OPTIONS = dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1)
+
+
+@pytest.mark.parametrize("order", ["columns by popularity", "rows longest first", "both"])
+def test_orderings_with_every_option(order):
+    """Dense columns adjacent and long rows adjacent (as real LPs often store
+    them), default settings and every optional reduction."""
+    lp = lpgen.power_law(seed=3, scale=0.02)
+    if order != "rows longest first":
+        lp = by_popularity(lp)
+    if order != "columns by popularity":
+        lp = rows_by_length(lp)
+    for extra in ({}, ALL_OPTIONS):
+        got, ref = run_both(lp, **extra)
+        assert_same(got, ref, f"{order} {extra}")
+
+
 def test_invalid_input_rejected_on_device():
     good = make(2, 3, [[(0, 1.0), (2, 1.0)], [(1, 2.0)]], [-INF, 0.0], [4.0, 1.0], [0, 0, 0], [1, 1, 1], [0, 0, 0])
     bad = []
