@@ -63,8 +63,10 @@ typedef enum { PSL_MEM_HOST = 0, PSL_MEM_DEVICE = 1 } psl_mem;
  * non-decreasing, row_ptr[m] = nnz), col_idx[nnz] strictly ascending within
  * each row and in [0, n), val[nnz] finite and non-zero. lhs/rhs[m], lb/ub/c[n].
  * lhs must not be +inf, rhs not -inf; lb not +inf, ub not -inf; no NaN.
- * nnz < 2^30. The library copies everything at create/reload: the caller
- * keeps ownership of these arrays and may free them once the call returns. */
+ * m, n and nnz < 2^30 (so that sums of row and column counts, and twice
+ * either, stay within int32 on the device). The library copies everything
+ * at create/reload: the caller keeps ownership of these arrays and may free
+ * them once the call returns. */
 typedef struct {
     int32_t m, n;
     int64_t nnz;
@@ -311,7 +313,8 @@ typedef struct psl_batch psl_batch;
 /* k >= 1 LPs, all with the same mem kind, each checked as at
  * psl_presolve_create (the message names the first invalid LP). The totals of
  * these LPs (rows, columns, nonzeros, and k) are the batch's capacity; their
- * total nnz must be below 2^30. Settings apply to every LP. */
+ * total rows, columns and nnz must each be below 2^30. Settings apply to
+ * every LP. */
 psl_status psl_batch_create(int32_t k, const psl_lp *lps, const psl_settings *s, psl_batch **out);
 
 /* Replace the LPs by k others (any shapes) whose totals fit the capacity,

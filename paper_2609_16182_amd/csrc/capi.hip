@@ -120,6 +120,7 @@ std::string psl::check_settings(const psl_settings* s) {
 std::string psl::check_lp_shape(const psl_lp* lp) {
   if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return "negative size";
   if (lp->nnz >= ((int64_t)1 << 30)) return "nnz must be below 2^30";
+  if (lp->m >= (1 << 30) || lp->n >= (1 << 30)) return "m and n must be below 2^30";
   if (lp->m == 0 && lp->nnz != 0) return "entries without rows";
   if (lp->m > 0 && (!lp->row_ptr || !lp->lhs || !lp->rhs)) return "null row array";
   if (lp->n > 0 && (!lp->lb || !lp->ub || !lp->c)) return "null column array";

@@ -61,6 +61,13 @@ def test_argument_errors_without_device():
     assert "negative" in psl.psl_last_error(None)
     lp = psl.psl_lp(1, 1, 1, 0, None, None, None, None, None, None, None, None, 0.0)
     assert lib.psl_presolve_create(C.byref(lp), C.byref(s), C.byref(h)) == psl.PSL_ERR_INVALID
+    # the size limits are checked before any array is read
+    for dims, word in (((1, 1, 1 << 30), "nnz"), ((1 << 30, 1, 0), "m and n"), ((1, 1 << 30, 0), "m and n")):
+        lp = psl.psl_lp(*dims, 0, None, None, None, None, None, None, None, None, 0.0)
+        assert lib.psl_presolve_create(C.byref(lp), C.byref(s), C.byref(h)) == psl.PSL_ERR_INVALID
+        assert psl.psl_last_error(None).startswith(word), psl.psl_last_error(None)
+    lp = psl.psl_lp(1, 1, 1, 0, None, None, None, None, None, None, None, None, 0.0)
+    assert lib.psl_presolve_create(C.byref(lp), C.byref(s), C.byref(h)) == psl.PSL_ERR_INVALID
     bad = psl.psl_settings_default()
     bad.max_rounds = 0
     arrs = []
