@@ -855,6 +855,13 @@ static int parallel_cols(or_handle *h) {
             lam[j] = la;
             any = 1;
         }
+        if (any && (lo == INFINITY || up == -INFINITY)) {
+            /* the merged interval passed inf_value on the wrong side: no
+             * finite value would satisfy it, so the group is not merged */
+            for (int32_t t = g0 + 1; t < g1; ++t)
+                if (lead[kc[t].col] == k) lead[kc[t].col] = -1;
+            any = 0;
+        }
         if (any) {
             lead[k] = k;
             nlo[k] = lo;

@@ -189,6 +189,27 @@ def test_not_proportional_or_too_long():
     assert not _recs(O.presolve(lp, **PC), "PARALLEL_COL")
 
 
+def test_merged_interval_past_inf_value_is_not_merged():
+    """x0, x1 = 2 x0, x2 = 3 x0 (coefficients and costs): the scaled bounds
+    sum to a lower bound of 4e19 + 2 * 3e19 = 1e20 = inf_value, infinite under
+    the convention, which no finite value satisfies: the group stays as it is.
+    With bounds a thousand times smaller the same group merges, to the sum of
+    the scaled intervals."""
+    rows = [[(0, 1.0), (1, 2.0), (2, 3.0), (3, 1.0)], [(0, 2.0), (1, 4.0), (2, 6.0), (3, -1.0)]]
+    c = [1.0, 2.0, 3.0, 0.5]
+    lp = make(2, 4, rows, [-1e19, -INF], [INF, 1e19], [4e19, 3e19, -9e19, -1], [5e19, 4e19, 1.0, 1], c)
+    res = O.presolve(lp, **PC, enable_parallel_rows=0)
+    assert not _recs(res, "PARALLEL_COL", "LEADER_BOUNDS")
+    assert res.result_name == "REDUCED" and res.reduced["n"] == 4
+    # sides that keep both rows and tighten no bound (the merge sees the input bounds)
+    lp = make(2, 4, rows, [-1.6e17, -INF], [INF, 2.5e17], [4e16, 3e16, -9e16, -1], [5e16, 4e16, 1.0, 1], c)
+    res = O.presolve(lp, **PC, enable_parallel_rows=0)
+    assert [(int(r["j"]), int(r["k"]), float(r["v"][0])) for r in _recs(res, "PARALLEL_COL")] == [(1, 0, 2.0),
+                                                                                                   (2, 0, 3.0)]
+    lbr = _recs(res, "LEADER_BOUNDS")[0]
+    assert (float(lbr["v"][2]), float(lbr["v"][3])) == (4e16 + 2 * 3e16 + 3 * -9e16, 5e16 + 2 * 4e16 + 3 * 1.0)
+
+
 @pytest.mark.parametrize("seed", range(300))
 def test_tiny_planted_replay_optimal(seed):
     lp = with_parallel_copies(lpgen.tiny(seed, finite_bounds=seed % 2 == 0), seed)
