@@ -145,20 +145,75 @@ __global__ void k_pc_verify(Dev d, ColScratch P, const int32_t* vals, const int3
   P.terms[p] = t;
 }
 
-// one thread per group: the merged interval, members added in column order
+// the fold of a group's member terms onto its leader's interval, members in
+// column order; the loads of the next PC_ACC members are issued together
+// ahead of the chain of adds (a group ends at the next non-member position).
+// EXACT: canonical after every add. Otherwise plain adds, canonical once at
+// the end, and *big set when a partial sum is finite with |v| >= inf_value:
+// until then the two folds agree up to the sign of a zero (x + 0 = x), and an
+// infinite term makes both infinite from there on (lower sums only meet -inf,
+// upper sums +inf), so the results are identical unless *big is set.
+#define PC_ACC 16
+template <bool EXACT>
+__device__ __forceinline__ bool pc_fold(const Dev& d, const ColScratch& P, const int32_t* kind, int64_t p,
+                                        double& lo, double& up, bool* big) {
+  bool any = false, done = false, huge = false;
+  double inf_v = d.cfg.inf_value;
+  for (int64_t q = p + 1; !done; q += PC_ACC) {
+    int kk[PC_ACC];
+    double2 tt[PC_ACC];
+#pragma unroll
+    for (int b = 0; b < PC_ACC; ++b) {
+      bool in = q + b < d.n;
+      kk[b] = in ? kind[q + b] : 1;
+      tt[b] = in ? P.terms[q + b] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < PC_ACC; ++b) {
+      if (done) continue;
+      if (kk[b] != 0) {
+        done = true;
+      } else if (tt[b].x == tt[b].x) {  // NaN: not merged
+        if (EXACT) {
+          lo = pc_canon(d.cfg, lo + tt[b].x);
+          up = pc_canon(d.cfg, up + tt[b].y);
+        } else {
+          lo = lo + tt[b].x;
+          up = up + tt[b].y;
+          huge = huge || (fabs(lo) >= inf_v && !is_inf(lo)) || (fabs(up) >= inf_v && !is_inf(up));
+        }
+        any = true;
+      }
+    }
+  }
+  if (!EXACT) {
+    lo = pc_canon(d.cfg, lo);
+    up = pc_canon(d.cfg, up);
+    *big = huge;
+  }
+  return any;
+}
+
+// one thread per group: the merged interval
 __global__ void k_pc_accum(Dev d, ColScratch P, const int32_t* vals, const int32_t* kind) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.n || kind[p] != 1) return;
+  if (p + 1 >= d.n || kind[p + 1] != 0) return;  // a group of one
   int k = vals[p];
   double2 bk = d.bnd[k];
   double lo = bk.x, up = bk.y;
-  bool any = false;
-  for (int64_t q = p + 1; q < d.n && kind[q] == 0; ++q) {
-    double2 t = P.terms[q];
-    if (t.x != t.x) continue;  // not merged
-    lo = pc_canon(d.cfg, lo + t.x);
-    up = pc_canon(d.cfg, up + t.y);
-    any = true;
+  bool big = false;
+  bool any = pc_fold<false>(d, P, kind, p, lo, up, &big);
+  if (big) {  // a partial sum reached inf_value: the canonical fold itself
+    lo = bk.x;
+    up = bk.y;
+    pc_fold<true>(d, P, kind, p, lo, up, nullptr);
+  }
+  if (any && (lo == __builtin_inf() || up == -__builtin_inf())) {
+    // the merged interval passed inf_value on the wrong side: no finite value
+    // would satisfy it, so the group is not merged (its members let go)
+    for (int64_t q = p + 1; q < d.n && kind[q] == 0; ++q) P.lead[vals[q]] = -1;
+    any = false;
   }
   if (any) {
     P.lead[k] = k;

@@ -148,3 +148,43 @@ def test_setting_validated():
     with pytest.raises(psl.PslError) as ei:
         psl.Presolver(lpgen.tiny(0), enable_parallel_cols=2)
     assert ei.value.status == psl.PSL_ERR_INVALID
+
+
+def proportional_group(size, seed, infinite=True):
+    """`size` columns proportional to one pattern in two rows (scales of both
+    signs, costs scaled alike) beside one other column; bounds mix ordinary,
+    huge (near 1e20) and infinite values, so that partial sums of the merged
+    interval cross inf_value and infinite terms enter it."""
+    rng = np.random.default_rng(seed)
+    lam = rng.choice([0.5, 1.0, 2.0, 3.0, -1.0, -2.5], size=size)
+    rows = [[(j, 1.0 * lam[j]) for j in range(size)] + [(size, 1.0)],
+            [(j, 2.0 * lam[j]) for j in range(size)] + [(size, -1.0)]]
+    lb, ub = [], []
+    for _ in range(size):
+        kind = rng.integers(0, 4 if infinite else 2)
+        if kind == 0:
+            a = float(rng.uniform(-5, 5)); lb.append(a); ub.append(a + float(rng.uniform(0, 3)))
+        elif kind == 1:
+            a = float(rng.uniform(3e19, 9e19)) * rng.choice([-1, 1]); lb.append(min(a, 0.0)); ub.append(max(a, 0.0))
+        elif kind == 2:
+            lb.append(-INF); ub.append(float(rng.uniform(0, 5)))
+        else:
+            lb.append(float(rng.uniform(-5, 0))); ub.append(INF)
+    return make(2, size + 1, rows, [-1e19, -INF], [INF, 1e19], lb + [-1.0], ub + [1.0],
+                [float(l) for l in lam] + [0.5])
+
+
+def test_merged_intervals_crossing_inf_value():
+    """Groups whose merged interval passes inf_value part way (the canonical
+    fold turns it infinite for good) or meets infinite terms, in groups longer
+    than one batch of loads of the accumulation."""
+    cases = [make(2, 4, [[(0, 1.0), (1, 2.0), (2, 3.0), (3, 1.0)], [(0, 2.0), (1, 4.0), (2, 6.0), (3, -1.0)]],
+                  [-1e19, -INF], [INF, 1e19], [4e19, 3e19, -9e19, -1], [5e19, 4e19, 1.0, 1], [1.0, 2.0, 3.0, 0.5])]
+    cases += [proportional_group(size, seed) for seed, size in enumerate((3, 5, 17, 40, 40, 40))]
+    cases += [proportional_group(size, 10 + seed, infinite=False) for seed, size in enumerate((4, 17, 33, 40))]
+    merged = 0
+    for k, lp in enumerate(cases):
+        got, ref = run_both(lp)
+        assert_same(got, ref, f"group case {k}")
+        merged += int((ref.records["type"] == O.REC["LEADER_BOUNDS"]).sum())
+    assert merged >= 3
