@@ -145,20 +145,19 @@ __global__ void k_pc_verify(Dev d, ColScratch P, const int32_t* vals, const int3
   P.terms[p] = t;
 }
 
-// the fold of a group's member terms onto its leader's interval, members in
-// column order; the loads of the next PC_ACC members are issued together
-// ahead of the chain of adds (a group ends at the next non-member position).
-// EXACT: canonical after every add. Otherwise plain adds, canonical once at
-// the end, and *big set when a partial sum is finite with |v| >= inf_value:
-// until then the two folds agree up to the sign of a zero (x + 0 = x), and an
-// infinite term makes both infinite from there on (lower sums only meet -inf,
-// upper sums +inf), so the results are identical unless *big is set.
+// The fold of a group's member terms onto its leader's interval, members in
+// column order, canonical after every add (the reference definition); the
+// loads of the next PC_ACC members are issued together ahead of the adds. The
+// fast path (pc_step, k_pc_accum) uses plain adds, canonical once at the end,
+// and flags a partial sum that is finite with |v| >= inf_value: until then the
+// two folds agree up to the sign of a zero (x + 0 = x), and an infinite term
+// makes both infinite from there on (lower sums only meet -inf, upper sums
+// +inf), so the results are identical unless that flag is set, and then this
+// fold is run instead.
 #define PC_ACC 16
-template <bool EXACT>
-__device__ __forceinline__ bool pc_fold(const Dev& d, const ColScratch& P, const int32_t* kind, int64_t p,
-                                        double& lo, double& up, bool* big) {
-  bool any = false, done = false, huge = false;
-  double inf_v = d.cfg.inf_value;
+__device__ __forceinline__ void pc_fold(const Dev& d, const ColScratch& P, const int32_t* kind, int64_t p, double& lo,
+                                        double& up) {
+  bool done = false;
   for (int64_t q = p + 1; !done; q += PC_ACC) {
     int kk[PC_ACC];
     double2 tt[PC_ACC];
@@ -174,40 +173,115 @@ __device__ __forceinline__ bool pc_fold(const Dev& d, const ColScratch& P, const
       if (kk[b] != 0) {
         done = true;
       } else if (tt[b].x == tt[b].x) {  // NaN: not merged
-        if (EXACT) {
-          lo = pc_canon(d.cfg, lo + tt[b].x);
-          up = pc_canon(d.cfg, up + tt[b].y);
-        } else {
-          lo = lo + tt[b].x;
-          up = up + tt[b].y;
-          huge = huge || (fabs(lo) >= inf_v && !is_inf(lo)) || (fabs(up) >= inf_v && !is_inf(up));
-        }
-        any = true;
+        lo = pc_canon(d.cfg, lo + tt[b].x);
+        up = pc_canon(d.cfg, up + tt[b].y);
       }
     }
   }
-  if (!EXACT) {
-    lo = pc_canon(d.cfg, lo);
-    up = pc_canon(d.cfg, up);
-    *big = huge;
-  }
-  return any;
 }
 
-// one thread per group: the merged interval
-__global__ void k_pc_accum(Dev d, ColScratch P, const int32_t* vals, const int32_t* kind) {
+// lane l's value of v (l the same on every lane), through two readlanes
+__device__ __forceinline__ double lane_value(double v, int l) {
+  long long bits = __double_as_longlong(v);
+  unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(bits & 0xFFFFFFFFll), l);
+  unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// one fast-fold step over a lane's PC_ACC positions from q
+__device__ __forceinline__ void pc_step(const Dev& d, const ColScratch& P, const int32_t* kind, int64_t q, double& lo,
+                                        double& up, bool& any, bool& huge, bool& done) {
+  double inf_v = d.cfg.inf_value;
+  int kk[PC_ACC];
+  double2 tt[PC_ACC];
+#pragma unroll
+  for (int b = 0; b < PC_ACC; ++b) {
+    bool in = q + b < d.n;
+    kk[b] = in ? kind[q + b] : 1;
+    tt[b] = in ? P.terms[q + b] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int b = 0; b < PC_ACC; ++b) {
+    if (done) continue;
+    if (kk[b] != 0) {
+      done = true;
+    } else if (tt[b].x == tt[b].x) {
+      lo = lo + tt[b].x;
+      up = up + tt[b].y;
+      huge = huge || (fabs(lo) >= inf_v && !is_inf(lo)) || (fabs(up) >= inf_v && !is_inf(up));
+      any = true;
+    }
+  }
+}
+
+// The merged interval of each group. The head's lane folds the first PC_ACC
+// members; a longer group is continued by the whole wavefront (groups one
+// after another), 64 positions a step: coalesced loads, the group's end from a
+// ballot, the next step's loads issued before this step's terms are folded
+// (every lane folds them in order, reading them lane by lane). Then the
+// canonical end (or the exact fold, see pc_fold) and the wrong-side check.
+__global__ void __launch_bounds__(PSL_BLOCK) k_pc_accum(Dev d, ColScratch P, const int32_t* vals, const int32_t* kind) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= d.n || kind[p] != 1) return;
-  if (p + 1 >= d.n || kind[p + 1] != 0) return;  // a group of one
-  int k = vals[p];
-  double2 bk = d.bnd[k];
-  double lo = bk.x, up = bk.y;
-  bool big = false;
-  bool any = pc_fold<false>(d, P, kind, p, lo, up, &big);
-  if (big) {  // a partial sum reached inf_value: the canonical fold itself
+  // a head of a group of two or more
+  bool head = p + 1 < d.n && kind[p] == 1 && kind[p + 1] == 0;
+  int k = 0;
+  double lo = 0.0, up = 0.0;
+  bool any = false, huge = false, done = true;
+  if (head) {
+    k = vals[p];
+    double2 bk = d.bnd[k];
     lo = bk.x;
     up = bk.y;
-    pc_fold<true>(d, P, kind, p, lo, up, nullptr);
+    done = false;
+    pc_step(d, P, kind, p + 1, lo, up, any, huge, done);
+  }
+  int lane = lane_id();
+  double inf_v = d.cfg.inf_value;
+  unsigned long long mask = __ballot(head && !done);
+  while (mask) {
+    int l = __ffsll((long long)mask) - 1;
+    mask &= mask - 1;
+    int q = __shfl((int)p, l, PSL_WAVE) + 1 + PC_ACC;
+    double glo = __shfl(lo, l, PSL_WAVE), gup = __shfl(up, l, PSL_WAVE);
+    bool gany = __shfl((int)any, l, PSL_WAVE) != 0, ghuge = __shfl((int)huge, l, PSL_WAVE) != 0;
+    int qq = q + lane;
+    int kq = qq < d.n ? kind[qq] : 1;
+    double2 t = qq < d.n ? P.terms[qq] : make_double2(0.0, 0.0);
+    for (bool gdone = false; !gdone; q += PSL_WAVE) {
+      unsigned long long endm = __ballot(kq != 0);
+      int cnt = endm ? __ffsll((long long)endm) - 1 : PSL_WAVE;
+      gdone = endm != 0;
+      double2 cur = t;
+      if (!gdone) {  // the next step's loads, ahead of this step's fold
+        int qn = q + PSL_WAVE + lane;
+        kq = qn < d.n ? kind[qn] : 1;
+        t = qn < d.n ? P.terms[qn] : make_double2(0.0, 0.0);
+      }
+      for (int b = 0; b < cnt; ++b) {
+        double tx = lane_value(cur.x, b), ty = lane_value(cur.y, b);
+        if (tx == tx) {
+          glo = glo + tx;
+          gup = gup + ty;
+          ghuge = ghuge || (fabs(glo) >= inf_v && !is_inf(glo)) || (fabs(gup) >= inf_v && !is_inf(gup));
+          gany = true;
+        }
+      }
+    }
+    if (lane == l) {
+      lo = glo;
+      up = gup;
+      any = gany;
+      huge = ghuge;
+    }
+  }
+  if (!head) return;
+  lo = pc_canon(d.cfg, lo);
+  up = pc_canon(d.cfg, up);
+  if (huge) {  // a partial sum reached inf_value: the canonical fold itself
+    double2 bk = d.bnd[k];
+    lo = bk.x;
+    up = bk.y;
+    pc_fold(d, P, kind, p, lo, up);
   }
   if (any && (lo == __builtin_inf() || up == -__builtin_inf())) {
     // the merged interval passed inf_value on the wrong side: no finite value
