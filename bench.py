@@ -274,8 +274,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the presolve would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the presolve has no multi-GPU path "
+              "(batched and served LPs would shard across GPUs as whole LPs).", file=sys.stderr)
         sys.exit(2)
 
     import torch
