@@ -136,3 +136,24 @@ def test_batch_4096_digests():
             bad.append(i)
     b.close()
     assert not bad, f"{len(bad)} LPs differ, first {bad[:10]}"
+
+
+@pytest.fixture(scope="module")
+def power_lp_reordered(power_lp):
+    """The same LP with its dense columns first (empty ones last, in one run of
+    hundreds of thousands) and its longest rows first."""
+    from tests.test_gpu_parity import by_popularity, rows_by_length
+    return rows_by_length(by_popularity(power_lp))
+
+
+@pytest.mark.parametrize("extra", [{}, dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1)],
+                         ids=["default", "all"])
+def test_power_law_full_size_reordered(power_lp_reordered, extra):
+    lp = power_lp_reordered
+    t0 = time.time()
+    ref = O.presolve(lp, **extra)
+    print(f"oracle {ref.result_name} rounds={ref.rounds} records={len(ref.records)} in {time.time() - t0:.1f}s",
+          flush=True)
+    got, p = psl.presolve(lp, **extra)
+    p.close()
+    assert_same(got, ref, f"power-law full size reordered, {extra}")

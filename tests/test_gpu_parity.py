@@ -158,10 +158,11 @@ def rows_by_length(lp, longest_first=True):
     rp = np.asarray(lp["row_ptr"], np.int64)
     lens = np.diff(rp)
     order = np.argsort(-lens if longest_first else lens, kind="stable")
-    starts = rp[order]
-    idx = np.concatenate([np.arange(a, a + k) for a, k in zip(starts, lens[order])]) if len(order) else starts
+    new_rp = np.concatenate([[0], np.cumsum(lens[order])]).astype(np.int64)
+    # position t of the new order reads old position rp[order[r]] + (t - new_rp[r])
+    idx = np.arange(new_rp[-1]) + np.repeat(rp[order] - new_rp[:-1], lens[order])
     out = dict(lp)
-    out["row_ptr"] = np.concatenate([[0], np.cumsum(lens[order])]).astype(np.int32)
+    out["row_ptr"] = new_rp.astype(np.int32)
     out["col_idx"] = np.asarray(lp["col_idx"])[idx]
     out["val"] = np.asarray(lp["val"])[idx]
     for k in ("lhs", "rhs"):
