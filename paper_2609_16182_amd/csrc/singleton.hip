@@ -12,7 +12,8 @@
 // Runs at the end of a propagation round, on the state after the round's
 // decisions. Candidates (columns flagged when they came down to one row, and
 // every column in the first round) pick the lowest candidate per row. Rows
-// whose column has a cost claim all their columns (atomic min of the row);
+// whose column has a cost claim all their columns (an atomic min of a key of
+// the round and the row, so the previous rounds' claims need no clearing);
 // such a row applies only where it is the lowest claimant of each column, so
 // no cost changes twice in a round (the others wait for the next round). The
 // applying rows are counted, scanned and emitted in row order after the
