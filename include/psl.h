@@ -143,7 +143,10 @@ typedef struct {
                                       with at most 64 entries) merge into the
                                       first column of their group, whose
                                       interval becomes the sum of the scaled
-                                      intervals (in column order);
+                                      intervals (in column order; a group
+                                      whose sum reaches a lower bound of +inf
+                                      or an upper bound of -inf, |v| >=
+                                      inf_value, is not merged);
                                       PARALLEL_COL / LEADER_BOUNDS. 0 (default)
                                       or 1. The parallel pass runs when either
                                       this or enable_parallel_rows is set.     */
