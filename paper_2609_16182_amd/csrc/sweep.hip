@@ -858,6 +858,19 @@ __device__ __forceinline__ int rec_count_of(const Dev& d, int64_t t) {
 #define DEC_ITEMS 1
 #define DEC_BLOCK 1024
 #define DEC_TILE (DEC_BLOCK * DEC_ITEMS)
+#define DEC_WAVES (DEC_BLOCK / PSL_WAVE)
+// an index has at most 3 records (a row 1; a column: each bound side and one
+// of fixed, empty or dual-fixed), so a thread's count fits in 3 bits
+static_assert(3 * DEC_ITEMS < 8, "record counts per thread must fit in 3 bits");
+
+// prefix (lanes below) and total of per-lane counts 0..7 across the
+// wavefront, from one ballot per bit
+__device__ __forceinline__ void wave_small_scan(int v, int& pre, int& tot) {
+  unsigned long long below = (1ull << lane_id()) - 1ull;
+  unsigned long long b0 = __ballot(v & 1), b1 = __ballot(v & 2), b2 = __ballot(v & 4);
+  pre = __popcll(b0 & below) + 2 * __popcll(b1 & below) + 4 * __popcll(b2 & below);
+  tot = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+}
 
 // Column decisions of the touched columns (untouched ones cannot change: an
 // active column with unchanged bounds and rows is neither fixed nor empty),
@@ -884,9 +897,18 @@ __global__ void __launch_bounds__(DEC_BLOCK) k_decide_count(Dev d, int32_t* tile
     d.col_code[j] = col_decide(d, j, kk);
     c += kk;
   }
-  int tot = 0;
-  if (__syncthreads_or(c != 0)) block_excl_scan_n<DEC_BLOCK>(c, &tot);  // else a tile without records
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+  // the tile's record count: wavefront totals by ballots, summed by thread 0
+  __shared__ int wtot[DEC_WAVES];
+  int pre_w, tot_w;
+  wave_small_scan(c, pre_w, tot_w);
+  if (lane_id() == 0) wtot[threadIdx.x >> 6] = tot_w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+#pragma unroll
+    for (int k = 0; k < DEC_WAVES; ++k) tot += wtot[k];
+    tile_sum[blockIdx.x] = tot;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.flags->rows_removed = 0;
     d.flags->fin_cols = 0;
@@ -989,36 +1011,61 @@ __global__ void __launch_bounds__(DEC_BLOCK) k_decide_emit(Dev d, const int32_t*
     cnt[k] = t < span ? rec_count_of(d, t) : 0;
     c += cnt[k];
   }
-  int tot;
-  int pre = block_excl_scan_n<DEC_BLOCK>(c, &tot);
-  if (tot == 0) return;
-  // removed rows of the tile: one atomic per workgroup
+  // record positions: the prefix inside the wavefront by ballots, the
+  // wavefronts' totals through LDS (the one barrier); the removed rows go
+  // the same way, one atomic per workgroup
+  __shared__ int wtot[DEC_WAVES], wrow[DEC_WAVES];
+  int w = threadIdx.x >> 6;
   int nrow = 0;
 #pragma unroll
   for (int k = 0; k < DEC_ITEMS; ++k) nrow += (t0 + k < m) ? cnt[k] : 0;
-  int rtot;
-  block_excl_scan_n<DEC_BLOCK>(nrow, &rtot);
-  if (rtot && threadIdx.x == 0) atomicAdd(&d.flags->rows_removed, rtot);
-  Record* r = d.rec + base + tile_off[blockIdx.x] + pre;
-  int fin = 0;
-#pragma unroll
-  for (int k = 0; k < DEC_ITEMS; ++k) {
-    if (!cnt[k]) continue;
-    int64_t t = t0 + k;
-    int lp;
-    if (t < m) {
-      lp = row_lp_of(d, (int)t);
-      emit_row(d, (int)t, round_of(d, lp, round), r);
-    } else {
-      lp = col_lp_of(d, (int)(t - m));
-      fin += emit_col(d, (int)(t - m), round_of(d, lp, round), r);
-    }
-    if (d.K > 1) d.lpo[lp].total = 1;  // the LP changed this round
-    r += cnt[k];
+  int pre, tot_w, rpre, rtot_w;
+  wave_small_scan(c, pre, tot_w);
+  wave_small_scan(nrow, rpre, rtot_w);
+  if (lane_id() == 0) {
+    wtot[w] = tot_w;
+    wrow[w] = rtot_w;
   }
-  int ftot;
-  block_excl_scan_n<DEC_BLOCK>(fin, &ftot);
-  if (ftot && threadIdx.x == 0) atomicAdd(&d.flags->fin_cols, ftot);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < DEC_WAVES; ++k) pre += k < w ? wtot[k] : 0;
+  if (threadIdx.x == 0) {
+    int rtot = 0;
+#pragma unroll
+    for (int k = 0; k < DEC_WAVES; ++k) rtot += wrow[k];
+    if (rtot) atomicAdd(&d.flags->rows_removed, rtot);
+  }
+  int fin = 0;
+  if (tot_w != 0) {  // a wavefront with records (the others wait at the barrier below)
+    Record* r = d.rec + base + tile_off[blockIdx.x] + pre;
+#pragma unroll
+    for (int k = 0; k < DEC_ITEMS; ++k) {
+      if (!cnt[k]) continue;
+      int64_t t = t0 + k;
+      int lp;
+      if (t < m) {
+        lp = row_lp_of(d, (int)t);
+        emit_row(d, (int)t, round_of(d, lp, round), r);
+      } else {
+        lp = col_lp_of(d, (int)(t - m));
+        fin += emit_col(d, (int)(t - m), round_of(d, lp, round), r);
+      }
+      if (d.K > 1) d.lpo[lp].total = 1;  // the LP changed this round
+      r += cnt[k];
+    }
+  }
+  // columns whose bound became finite: the same way, one atomic per workgroup
+  __shared__ int wfin[DEC_WAVES];
+  int fpre, ftot_w;
+  wave_small_scan(fin, fpre, ftot_w);
+  if (lane_id() == 0) wfin[w] = ftot_w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ftot = 0;
+#pragma unroll
+    for (int k = 0; k < DEC_WAVES; ++k) ftot += wfin[k];
+    if (ftot) atomicAdd(&d.flags->fin_cols, ftot);
+  }
 }
 
 // ---------------------------------------------------------------------------
