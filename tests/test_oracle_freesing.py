@@ -266,3 +266,20 @@ def test_tiny_with_costs_fire():
         res = O.presolve(lpgen.tiny(seed, finite_bounds=False), **FS)
         total += sum(1 for r in _fs(res) if r["v"][3] != 0)
     assert total > 20
+
+
+def test_three_rows_sharing_a_column_substitute_one_round_each():
+    """Rows i = 0, 1, 2: x_i + x_3 = s_i (3, 5, 7), x_i free with cost c_i
+    (1, 2, -1), x_3 in [0, 10] without cost. The rows share x_3, so one row
+    substitutes per round, lowest first: rounds 1, 2, 3. x_3's cost becomes
+    0 - 1 - 2 + 1 = -2 and it leaves empty at its upper bound 10. The offset is
+    1*3 + 2*5 + (-1)*7 (the rows at the sides their costs prefer) - 2*10 = -14."""
+    lp = make(3, 4, [[(0, 1.0), (3, 1.0)], [(1, 1.0), (3, 1.0)], [(2, 1.0), (3, 1.0)]], [3.0, 5.0, 7.0],
+              [3.0, 5.0, 7.0], [-INF, -INF, -INF, 0.0], [INF, INF, INF, 10.0], [1.0, 2.0, -1.0, 0.0])
+    res = O.presolve(lp, enable_free_singletons=1)
+    fs = [r for r in res.records if O.REC_NAMES[int(r["type"])] == "FREE_SINGLETON"]
+    assert [(int(r["i"]), int(r["j"]), int(r["round"]), int(r["side"])) for r in fs] == [(0, 0, 1, 1), (1, 1, 2, 1),
+                                                                                          (2, 2, 3, 2)]
+    ec = [r for r in res.records if O.REC_NAMES[int(r["type"])] == "EMPTY_COL"]
+    assert [(int(r["j"]), float(r["v"][0]), float(r["v"][1])) for r in ec] == [(3, 10.0, -2.0)]
+    assert res.reduced["obj_offset"] == -14.0
