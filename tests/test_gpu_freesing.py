@@ -212,10 +212,12 @@ def test_substitution_cases_and_long_rows():
              [-INF, 0, 0], [INF, 5, 5], [2.0, 1.0, 0.0]),
         make(2, 3, [[(0, 1.0), (2, 1.0)], [(1, 1.0), (2, 1.0)]], [3.0, 5.0], [3.0, 5.0], [-INF, -INF, 0],
              [INF, INF, 10], [1.0, 1.0, 0.0]),
+        make(3, 4, [[(0, 1.0), (3, 1.0)], [(1, 1.0), (3, 1.0)], [(2, 1.0), (3, 1.0)]], [3.0, 5.0, 7.0],
+             [3.0, 5.0, 7.0], [-INF, -INF, -INF, 0.0], [INF, INF, INF, 10.0], [1.0, 2.0, -1.0, 0.0]),
     ] + [long_rows_sharing_columns(s) for s in range(6)]
     for k, lp in enumerate(cases):
         ref = O.presolve(lp, **FS)
-        if k >= 2:
+        if k >= 3:
             assert _n_fs(ref.records) > 0, k
         got, ref = run_both(lp)
         assert_same(got, ref, f"substitution case {k}")
