@@ -179,7 +179,9 @@ def test_merged_intervals_crossing_inf_value():
     fold turns it infinite for good) or meets infinite terms, in groups longer
     than one batch of loads of the accumulation."""
     cases = [make(2, 4, [[(0, 1.0), (1, 2.0), (2, 3.0), (3, 1.0)], [(0, 2.0), (1, 4.0), (2, 6.0), (3, -1.0)]],
-                  [-1e19, -INF], [INF, 1e19], [4e19, 3e19, -9e19, -1], [5e19, 4e19, 1.0, 1], [1.0, 2.0, 3.0, 0.5])]
+                  [-1e19, -INF], [INF, 1e19], [4e19, 3e19, -9e19, -1], [5e19, 4e19, 1.0, 1], [1.0, 2.0, 3.0, 0.5]),
+             make(2, 4, [[(0, 1.0), (1, 2.0), (2, 3.0), (3, 1.0)], [(0, 2.0), (1, 4.0), (2, 6.0), (3, -1.0)]],
+                  [-INF, -1e19], [1e19, INF], [-5e19, -4e19, -1.0, -1], [-4e19, -3e19, 9e19, 1], [1.0, 2.0, 3.0, 0.5])]
     cases += [proportional_group(size, seed) for seed, size in enumerate((3, 5, 17, 40, 40, 40))]
     cases += [proportional_group(size, 10 + seed, infinite=False) for seed, size in enumerate((4, 17, 33, 40))]
     merged = 0

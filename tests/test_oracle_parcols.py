@@ -201,6 +201,11 @@ def test_merged_interval_past_inf_value_is_not_merged():
     res = O.presolve(lp, **PC, enable_parallel_rows=0)
     assert not _recs(res, "PARALLEL_COL", "LEADER_BOUNDS")
     assert res.result_name == "REDUCED" and res.reduced["n"] == 4
+    # the mirror: bounds negated, the upper sum's partial -4e19 + 2 * -3e19 = -1e20
+    lp = make(2, 4, rows, [-INF, -1e19], [1e19, INF], [-5e19, -4e19, -1.0, -1], [-4e19, -3e19, 9e19, 1], c)
+    res = O.presolve(lp, **PC, enable_parallel_rows=0)
+    assert not _recs(res, "PARALLEL_COL", "LEADER_BOUNDS")
+    assert res.result_name == "REDUCED" and res.reduced["n"] == 4
     # sides that keep both rows and tighten no bound (the merge sees the input bounds)
     lp = make(2, 4, rows, [-1.6e17, -INF], [INF, 2.5e17], [4e16, 3e16, -9e16, -1], [5e16, 4e16, 1.0, 1], c)
     res = O.presolve(lp, **PC, enable_parallel_rows=0)
