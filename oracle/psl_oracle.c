@@ -39,9 +39,11 @@
  *   R-Tol     tol(s) = feas_tol * max(1, |s|); candidate bound qualifies if it
  *             improves by more than min_improve * max(1, |bound|) (any strict
  *             improvement for a row with one active column).
- *   R-Hash    parallel-row key over the row's stored entries (pattern and
- *             coefficients normalised by the first stored coefficient), mixed
- *             with the SplitMix64 finaliser (Steele, Lea & Flood 2014).
+ *   R-Hash    parallel-row key over the row's active entries (pattern and
+ *             coefficients normalised by the first active coefficient), mixed
+ *             with the SplitMix64 finaliser (Steele, Lea & Flood 2014);
+ *             merged sides are compared after moving the removed columns'
+ *             constant contribution out of them (see parallel_rows).
  *   R-Order   records ordered by (round, phase, index, side).
  */
 #include "psl_oracle.h"
@@ -632,19 +634,45 @@ static int cmp_keyrow(const void *a, const void *b) {
     return (x->row > y->row) - (x->row < y->row);
 }
 
-static int active_len(const or_handle *h, int32_t i) {
-    int L = 0;
-    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k) L += h->col_on[h->ci[k]];
+/* Constant contribution of the removed (fixed) columns of row i: the
+ * canonical pairwise sum over the row's CSR positions, a removed column's
+ * position holding a_ij * v_j and an active one +0. The rows of the current
+ * problem are sum over active j of a_ij x_j in [lhs_i - k_i, rhs_i - k_i]
+ * (section 3.2, "Internal data structures": inactive columns are ignored
+ * when streaming A). Compaction shifts the sides by the same constant. */
+static double removed_constant(const or_handle *h, int32_t i, double *tmp) {
+    int64_t s0 = h->rp[i], len = h->rp[i + 1] - h->rp[i];
+    for (int64_t t = 0; t < len; ++t) {
+        int32_t j = h->ci[s0 + t];
+        tmp[t] = h->col_on[j] ? 0.0 : pos0(h->va[s0 + t] * h->lb[j]);
+    }
+    return or_pairwise_sum(tmp, len);
+}
+
+/* a side moved by -k (infinite sides stay) */
+static double side_minus(double side, double k) { return isinf(side) ? side : pos0(side - k); }
+static double side_plus(double side, double k) { return isinf(side) ? side : pos0(side + k); }
+
+/* row i's active entries in CSR order; returns their number */
+static int32_t active_entries(const or_handle *h, int32_t i, int32_t *cols, double *vals) {
+    int32_t L = 0;
+    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k)
+        if (h->col_on[h->ci[k]]) {
+            cols[L] = h->ci[k];
+            vals[L] = h->va[k];
+            L++;
+        }
     return L;
 }
 
-/* same stored pattern and coefficients proportional within par_tol */
-static int rows_parallel(const or_handle *h, int32_t r, int32_t l) {
-    int64_t lr = h->rp[r + 1] - h->rp[r], ll = h->rp[l + 1] - h->rp[l];
-    if (lr != ll) return 0;
-    const int32_t *cr = h->ci + h->rp[r], *cl = h->ci + h->rp[l];
-    const double *vr = h->va + h->rp[r], *vl = h->va + h->rp[l];
-    for (int64_t t = 0; t < lr; ++t) {
+/* Rows r and l of the current problem are parallel when their active entries
+ * have the same columns and, each divided by the row's first active
+ * coefficient, agree within par_tol (relative to the larger magnitude). */
+static int rows_parallel(const or_handle *h, int32_t r, int32_t l, int32_t *cr, double *vr,
+                         int32_t *cl, double *vl) {
+    int32_t lr = active_entries(h, r, cr, vr), ll = active_entries(h, l, cl, vl);
+    if (lr != ll || lr == 0) return 0;
+    for (int32_t t = 0; t < lr; ++t) {
         if (cr[t] != cl[t]) return 0;
         double a = vr[t] / vr[0], b = vl[t] / vl[0];
         double scale = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
@@ -653,27 +681,54 @@ static int rows_parallel(const or_handle *h, int32_t r, int32_t l) {
     return 1;
 }
 
-/* returns 1 if any row was merged */
+/* first active coefficient of row i (the row has one) */
+static double first_active(const or_handle *h, int32_t i) {
+    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k)
+        if (h->col_on[h->ci[k]]) return h->va[k];
+    return 0.0;
+}
+
+/* Parallel rows of the current problem (section 3.2, "Parallel rows"):
+ * rows with a_r = lambda a_L over their active entries. Key = the two-level
+ * hash of the active entries; leader of a key group = its lowest equality
+ * row, else its lowest row; every other row of the group is verified
+ * against the leader. With k = the removed-column constant of a row, a
+ * verified row r maps its effective sides [lhs_r - k_r, rhs_r - k_r] through
+ * lambda = (first active a_r) / (first active a_L) (lambda < 0 swaps them);
+ * the leader's effective sides become the intersection with its own, the
+ * source of each side being the lowest row that gives it. A side the leader
+ * keeps keeps its stored value; a side from another row is stored as
+ * effective + k_L. Returns 1 if any row was merged. */
 static int parallel_rows(or_handle *h) {
     const or_settings *s = &h->s;
     int32_t m = h->m;
-    keyrow *kr = (keyrow *)xcalloc((size_t)m, sizeof(keyrow));
+    int64_t maxlen = 1;
+    for (int32_t i = 0; i < m; ++i)
+        if (h->rp[i + 1] - h->rp[i] > maxlen) maxlen = h->rp[i + 1] - h->rp[i];
+    int32_t *c1 = (int32_t *)xcalloc((size_t)maxlen, sizeof(int32_t));
+    int32_t *c2 = (int32_t *)xcalloc((size_t)maxlen, sizeof(int32_t));
+    double *v1 = (double *)xcalloc((size_t)maxlen, sizeof(double));
+    double *v2 = (double *)xcalloc((size_t)maxlen, sizeof(double));
+    keyrow *kr = (keyrow *)xcalloc((size_t)m + 1, sizeof(keyrow));
     int32_t nk = 0;
     for (int32_t i = 0; i < m; ++i) {
-        if (!h->row_on[i] || active_len(h, i) < 2) continue;
-        kr[nk].key = or_row_key(h->ci + h->rp[i], h->va + h->rp[i], h->rp[i + 1] - h->rp[i]);
+        if (!h->row_on[i]) continue;
+        int32_t L = active_entries(h, i, c1, v1);
+        if (L < 2) continue;
+        kr[nk].key = or_row_key(c1, v1, L);
         kr[nk].row = i;
         nk++;
     }
     qsort(kr, (size_t)nk, sizeof(keyrow), cmp_keyrow);
 
-    int32_t *leader_of = (int32_t *)xcalloc((size_t)m, sizeof(int32_t));
-    double *lam = (double *)xcalloc((size_t)m, sizeof(double));
-    double *new_l = (double *)xcalloc((size_t)m, sizeof(double));
-    double *new_u = (double *)xcalloc((size_t)m, sizeof(double));
-    int32_t *src_l = (int32_t *)xcalloc((size_t)m, sizeof(int32_t));
-    int32_t *src_u = (int32_t *)xcalloc((size_t)m, sizeof(int32_t));
-    uint8_t *is_leader = (uint8_t *)xcalloc((size_t)m, 1);
+    int32_t *leader_of = (int32_t *)xcalloc((size_t)m + 1, sizeof(int32_t));
+    double *lam = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    double *new_l = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    double *new_u = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    int32_t *src_l = (int32_t *)xcalloc((size_t)m + 1, sizeof(int32_t));
+    int32_t *src_u = (int32_t *)xcalloc((size_t)m + 1, sizeof(int32_t));
+    double *kconst = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    uint8_t *is_leader = (uint8_t *)xcalloc((size_t)m + 1, 1);
     for (int32_t i = 0; i < m; ++i) leader_of[i] = -1;
 
     for (int32_t g0 = 0; g0 < nk;) {
@@ -685,17 +740,20 @@ static int parallel_rows(or_handle *h) {
             for (int32_t t = g0; t < g1 && L < 0; ++t)
                 if (h->lhs[kr[t].row] == h->rhs[kr[t].row]) L = kr[t].row;
             if (L < 0) L = kr[g0].row;
+            double kL = removed_constant(h, L, v1);
             /* members in ascending row order; the leader's own sides first */
-            double lo = h->lhs[L], up = h->rhs[L];
+            double lo = side_minus(h->lhs[L], kL), up = side_minus(h->rhs[L], kL);
             int32_t sl = L, su = L;
             int any = 0;
             for (int32_t t = g0; t < g1; ++t) {
                 int32_t r = kr[t].row;
-                if (r == L || !rows_parallel(h, r, L)) continue;
-                double la = h->va[h->rp[r]] / h->va[h->rp[L]];
+                if (r == L || !rows_parallel(h, r, L, c1, v1, c2, v2)) continue;
+                double kr_ = removed_constant(h, r, v1);
+                double el = side_minus(h->lhs[r], kr_), eu = side_minus(h->rhs[r], kr_);
+                double la = first_active(h, r) / first_active(h, L);
                 double ml, mu;
-                if (la > 0) { ml = h->lhs[r] / la; mu = h->rhs[r] / la; }
-                else { ml = h->rhs[r] / la; mu = h->lhs[r] / la; }
+                if (la > 0) { ml = el / la; mu = eu / la; }
+                else { ml = eu / la; mu = el / la; }
                 ml = pos0(ml); mu = pos0(mu);
                 if (ml > lo || (ml == lo && r < sl)) { lo = ml; sl = r; }
                 if (mu < up || (mu == up && r < su)) { up = mu; su = r; }
@@ -707,6 +765,7 @@ static int parallel_rows(or_handle *h) {
                 is_leader[L] = 1;
                 new_l[L] = lo; new_u[L] = up;
                 src_l[L] = sl; src_u[L] = su;
+                kconst[L] = kL;
             }
         }
         g0 = g1;
@@ -720,20 +779,25 @@ static int parallel_rows(or_handle *h) {
             merged = 1;
         } else if (is_leader[i]) {
             double lo = new_l[i], up = new_u[i];
+            int snapped = 0;
             if (!isinf(lo) && !isinf(up) && lo > up) {
                 if (lo > up + tol_of(s, up)) infeasible = 1;
-                else lo = up;
+                else { lo = up; snapped = 1; }
             }
-            if (lo != h->lhs[i] || up != h->rhs[i]) {
-                push(h, REC_LEADER_SIDES, 0, i, src_l[i], src_u[i], h->lhs[i], h->rhs[i], lo, up);
-                h->lhs[i] = lo;
-                h->rhs[i] = up;
+            /* back to stored sides: a side the leader gave itself is kept */
+            double nu = src_u[i] == i ? h->rhs[i] : side_plus(up, kconst[i]);
+            double nl = snapped ? nu : (src_l[i] == i ? h->lhs[i] : side_plus(lo, kconst[i]));
+            if (nl != h->lhs[i] || nu != h->rhs[i]) {
+                push(h, REC_LEADER_SIDES, 0, i, src_l[i], src_u[i], h->lhs[i], h->rhs[i], nl, nu);
+                h->lhs[i] = nl;
+                h->rhs[i] = nu;
             }
         }
     }
     if (infeasible) h->result = RES_INFEASIBLE;
     free(kr); free(leader_of); free(lam); free(new_l); free(new_u);
-    free(src_l); free(src_u); free(is_leader);
+    free(src_l); free(src_u); free(is_leader); free(kconst);
+    free(c1); free(c2); free(v1); free(v2);
     return merged;
 }
 
@@ -932,23 +996,19 @@ static void compact(or_handle *h) {
         if (!h->row_on[i]) continue;
         int32_t ri = nr[i];
         h->r_rowmap[ri] = i;
-        int64_t s0 = h->rp[i], len = h->rp[i + 1] - h->rp[i];
-        for (int64_t t = 0; t < len; ++t) {
-            int32_t j = h->ci[s0 + t];
+        for (int64_t q = h->rp[i]; q < h->rp[i + 1]; ++q) {
+            int32_t j = h->ci[q];
             if (h->col_on[j]) {
                 h->r_ci[pos] = nc[j];
-                h->r_va[pos] = h->va[s0 + t];
+                h->r_va[pos] = h->va[q];
                 pos++;
-                tmp[t] = 0.0;
-            } else {
-                tmp[t] = pos0(h->va[s0 + t] * h->lb[j]);
             }
         }
         h->r_rp[ri + 1] = (int32_t)pos;
         /* sides shifted by the removed columns' constant contribution */
-        double k = or_pairwise_sum(tmp, len);
-        h->r_lhs[ri] = isinf(h->lhs[i]) ? h->lhs[i] : pos0(h->lhs[i] - k);
-        h->r_rhs[ri] = isinf(h->rhs[i]) ? h->rhs[i] : pos0(h->rhs[i] - k);
+        double k = removed_constant(h, i, tmp);
+        h->r_lhs[ri] = side_minus(h->lhs[i], k);
+        h->r_rhs[ri] = side_minus(h->rhs[i], k);
         int32_t L = h->r_rp[ri + 1] - h->r_rp[ri];
         h->r_rcls[ri] = L == 1 ? RCLS_SINGLETON
                       : L == 2 ? (h->r_lhs[ri] == h->r_rhs[ri] ? RCLS_DOUBLETON_EQ : RCLS_DOUBLETON_INEQ)
