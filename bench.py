@@ -3,14 +3,19 @@
 A step is one full pass of the hot path over one LP already resident in HBM:
 ingest (validation, transposed copy, bins; psl_presolve_reload) followed by
 psl_presolve_run (all propagation rounds, parallel rows, compaction). The
-workload is the power-law LP (m = 1e6, n = 1.5e6, row lengths 2 + Zipf(2)
-capped at 1e5, power-law column choice, about 9.2e6 nonzeros, FP64 values,
-int32 indices).
+headline workload is the large LP (m = 1e7, n = 1.5e7, U{3..12} nnz/row,
+20 dense rows of 1e6 entries, 20 dense columns in 1e5 rows, 1% planted
+reductions with 8-row propagation chains; about 9.7e7 nonzeros, FP64 values,
+int32 indices), the largest single-GPU configuration.
 
 Prints one JSON line. `value` = input nonzeros x steps / wall time of the
 timed steps (nnz/s). `roofline` describes the row-sweep kernel: algorithmic
-bytes of its launches / its device time (HIP events on the library's stream).
-`cpu_baseline` times the sequential CPU oracle on the same LP.
+bytes of its launches / its device time (HIP events on the library's
+stream); `hbm_whole_run` the algorithmic bytes of every pass of a step
+(ingest, rounds, parallel passes, compaction) over the step's wall time.
+`cpu_baseline` times the sequential CPU oracle on a bounded sample of the
+workload (the same generator at 5% scale), in a child process that runs
+beside the GPU legs. The batched (4096 LPs) and served workloads follow.
 """
 from __future__ import annotations
 
@@ -36,8 +41,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the full-size LP)")
-    ap.add_argument("--workload", choices=("powerlaw", "large"), default="powerlaw",
-                    help="single-LP workload: the power-law LP (default) or the large LP")
+    ap.add_argument("--workload", choices=("powerlaw", "large"), default="large",
+                    help="single-LP workload: the large LP (default) or the power-law LP")
+    ap.add_argument("--cpu-sample-scale", type=float, default=0.05,
+                    help="scale of the workload instance the CPU oracle presolves (bounded sample)")
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--reduction-steps", type=int, default=10,
                     help="timed steps of the same LP with each optional reduction on (0 = skip)")
@@ -45,24 +53,53 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--only-batch", action="store_true", help="run the batched workload only")
     ap.add_argument("--batch-no-seq", action="store_true", help="skip the sequential single-LP baseline")
-    ap.add_argument("--serve-pool", type=int, default=64, help="LPs in the serving pool (0 = skip serving)")
-    ap.add_argument("--serve-rates", default="50,200,1000")
+    ap.add_argument("--serve-pool", type=int, default=256, help="LPs in the serving pool (0 = skip serving)")
+    ap.add_argument("--serve-rates", default="50,200,1000,2000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--only-serving", action="store_true", help="run the serving workload only")
     return ap.parse_args()
 
 
+def _workload(name, scale):
+    from paper_2609_16182_amd import lpgen
+    return lpgen.power_law(seed=1, scale=scale) if name == "powerlaw" else lpgen.large(seed=2, scale=scale)
+
+
+def cpu_baseline_child(args):
+    """The CPU oracle on a bounded sample of the workload (no GPU is touched
+    here): prints one JSON line."""
+    from oracle import oracle as O
+    from paper_2609_16182_amd import lpgen
+    lp = _workload(args.workload, args.cpu_sample_scale)
+    nnz = lpgen.nnz(lp)
+    t = time.perf_counter()
+    ref = O.presolve(lp)
+    dt = time.perf_counter() - t
+    print(json.dumps({"value": round(nnz / dt, 1), "unit": "nnz/s", "cores": 1, "kind": "oracle",
+                      "sample": f"one sequential presolve of the same generator at {args.cpu_sample_scale:g} scale "
+                                f"(m={lp['m']}, n={lp['n']}, {nnz} nnz, {ref.rounds} rounds), {dt:.2f}s on one "
+                                f"host core"}), flush=True)
+
+
+def start_cpu_baseline(args):
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--workload", args.workload,
+           "--cpu-sample-scale", str(args.cpu_sample_scale)]
+    return subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                            env=dict(os.environ, OMP_NUM_THREADS="1"))
+
+
+def finish_cpu_baseline(proc):
+    out, err = proc.communicate(timeout=900)
+    if proc.returncode != 0:
+        print(f"[bench] CPU baseline failed: {err[-2000:]}", file=sys.stderr, flush=True)
+        return None
+    return json.loads(out.strip().splitlines()[-1])
+
+
 def _member(i):
     from paper_2609_16182_amd import lpgen
     return lpgen.batch_member(i)
-
-
-def _oracle_nnz(i):
-    from oracle import oracle as O
-    from paper_2609_16182_amd import lpgen
-    lp = lpgen.batch_member(i)
-    O.presolve(lp)
-    return lpgen.nnz(lp)
 
 
 def _serving_member(i):
@@ -230,14 +267,16 @@ def batch_leg(args, torch, psl):
 
     cpu = None
     if not args.no_cpu_baseline:
+        from oracle import oracle as O
         n_s = min(K, 256)
+        nnz_s = sum(int(lp["row_ptr"][-1]) for lp in lps[:n_s])
         ts = time.perf_counter()
-        with ProcessPoolExecutor(workers) as ex:
-            nnz_s = sum(ex.map(_oracle_nnz, range(n_s), chunksize=8))
+        for lp in lps[:n_s]:
+            O.presolve(lp)
         dt = time.perf_counter() - ts
-        cpu = {"value": round(n_s / dt, 1), "unit": "LPs/s", "cores": workers, "kind": "oracle",
-               "sample": f"the first {n_s} LPs of the batch ({nnz_s} nnz, generation included) on a pool of "
-                         f"{workers} processes"}
+        cpu = {"value": round(n_s / dt, 1), "unit": "LPs/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {n_s} LPs of the batch ({nnz_s} nnz, already generated), one after the "
+                         f"other on one host core, {dt:.2f}s"}
     return {
         "metric": "batched LPs/s", "lps": K, "nnz": total_nnz,
         "value": round(K / (batch_ms * 1e-3), 1), "unit": "LPs/s",
@@ -255,11 +294,13 @@ def batch_leg(args, torch, psl):
     }
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    or None when the sweep's sources changed since the counters were taken."""
+def measured_traffic(workload):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+    of the workload, or None when there is none or the sweep's sources changed
+    since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "powerlaw_1e6_k_sweep_traffic.json")
+    name = {"powerlaw": "powerlaw_1e6", "large": "large_1e7"}[workload]
+    path = os.path.join(ROOT, "profiles", f"{name}_k_sweep_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -272,11 +313,20 @@ def measured_traffic():
 
 def main():
     args = parse()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the presolve has no multi-GPU path "
               "(batched and served LPs would shard across GPUs as whole LPs).", file=sys.stderr)
         sys.exit(2)
+
+    # the CPU oracle's bounded sample runs in a child process beside the GPU
+    # legs (started before anything touches the GPU)
+    cpu_proc = None
+    if not args.no_cpu_baseline and not (args.only_batch or args.only_serving):
+        cpu_proc = start_cpu_baseline(args)
 
     import torch
 
@@ -290,14 +340,15 @@ def main():
         print(json.dumps(serving_leg(args, torch, psl)), flush=True)
         return
     t0 = time.time()
-    lp = (lpgen.power_law(seed=1, scale=args.scale) if args.workload == "powerlaw"
-          else lpgen.large(seed=2, scale=args.scale))
+    lp = _workload(args.workload, args.scale)
     nnz = lpgen.nnz(lp)
     print(f"[bench] workload m={lp['m']} n={lp['n']} nnz={nnz} generated in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
     keys = ("row_ptr", "col_idx", "val", "lhs", "rhs", "lb", "ub", "c")
     dev = {k: torch.from_numpy(np.ascontiguousarray(lp[k])).cuda() for k in keys}
     dev.update(m=lp["m"], n=lp["n"], nnz=nnz)
+    m_in, n_in = lp["m"], lp["n"]
+    del lp
     stream = torch.cuda.current_stream()
     p = psl.Presolver(dev, stream=stream.cuda_stream)
     p.run()
@@ -310,6 +361,7 @@ def main():
     sweep_ms = 0.0
     sweep_bytes = 0.0
     sweep_launches = 0
+    run_bytes = 0.0
     step_ms = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -322,22 +374,29 @@ def main():
         sweep_ms += st["ms_sweep"]
         sweep_bytes += st["sweep_bytes"]
         sweep_launches += st["sweep_launches"]
+        run_bytes += st["alg_bytes"] + st["ingest_bytes"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     stats = p.stats
     p.close()
+    print(f"[bench] {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
 
     value = nnz * args.steps / elapsed
     achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
     per_launch_bytes = sweep_bytes / max(1, sweep_launches)
+    whole = run_bytes / elapsed / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic() if args.workload == "powerlaw" and args.scale == 1.0 else None,
-        "kernel": "k_sweep<0> (row sweep: activities, decisions, implied bounds)",
+        "traffic": measured_traffic(args.workload) if args.scale == 1.0 else None,
+        "kernel": "k_sweep (row sweep: activities, decisions, implied bounds)",
         "launches": sweep_launches, "avg_launch_us": round(sweep_ms * 1e3 / max(1, sweep_launches), 2),
         "alg_bytes_per_launch": round(per_launch_bytes),
     }
+    hbm_whole = {"achieved": round(whole, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(whole / HBM_PEAK_GBS, 4), "alg_bytes_per_step": round(run_bytes / args.steps),
+                 "note": "algorithmic bytes of every pass of a step (ingest, rounds, parallel passes, compaction) "
+                         "over the step's wall time"}
 
     # the same workload with the optional reductions switched on
     reductions = None
@@ -369,40 +428,34 @@ def main():
                 "parallel_cols": int((recs["type"] == 11).sum()), "nnz_out": qs["nnz_out"],
                 "m_out": qs["m_out"], "n_out": qs["n_out"], "ms_decide": round(qs["ms_decide"], 3),
                 "ms_run_device": round(qs["ms_total"], 3)}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        t = time.perf_counter()
-        ref = O.presolve(lp)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(nnz / dt, 1), "unit": "nnz/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full sequential presolve of the same LP ({nnz} nnz, {ref.rounds} rounds), "
-                         f"{dt:.2f}s on one host core"}
-        if ref.records.shape[0] != stats["records"]:
-            print("[bench] WARNING: record counts differ from the oracle", file=sys.stderr)
+            print(f"[bench] reductions {name}: {reductions[name]['ms_per_step']} ms/step", file=sys.stderr,
+                  flush=True)
+    del dev
+    torch.cuda.empty_cache()
 
     batch = batch_leg(args, torch, psl) if args.batch_lps > 0 else None
     serving = serving_leg(args, torch, psl) if args.serve_pool > 0 else None
+    cpu = finish_cpu_baseline(cpu_proc) if cpu_proc is not None else None
 
+    desc = {"powerlaw": "power-law LP: m=1e6, n=1.5e6, rows 2+Zipf(2) capped 1e5, power-law columns, planted 2% "
+                        "singleton/doubleton/duplicate rows",
+            "large": "large LP: m=1e7, n=1.5e7, rows U{3..12}, 20 dense rows of 1e6, 20 dense columns of 1e5, "
+                     "1% planted reductions with 8-row propagation chains"}[args.workload]
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "nnz/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": ("power-law LP: m=1e6, n=1.5e6, rows 2+Zipf(2) capped 1e5, "
-                                "power-law columns, planted 2% singleton/doubleton/duplicate rows")
-                   if args.workload == "powerlaw" else
-                   ("large LP: m=1e7, n=1.5e7, rows U{3..12}, 20 dense rows of 1e6, 20 dense columns of 1e5, "
-                    "1% planted reductions with 8-row propagation chains"),
-                   "m": lp["m"], "n": lp["n"], "nnz": nnz, "scale": args.scale,
+        "config": {"workload": desc, "m": m_in, "n": n_in, "nnz": nnz, "scale": args.scale,
                    "parallelism": "single GPU"},
         "roofline": roofline,
+        "hbm_whole_run": hbm_whole,
         "cpu_baseline": cpu,
         "detail": {"rounds": stats["rounds"], "records": stats["records"], "nnz_out": stats["nnz_out"],
                    "ms_ingest": round(stats["ms_ingest"], 3), "ms_run_device": round(stats["ms_total"], 3),
-                   "ms_sweep": round(stats["ms_sweep"], 3), "ms_decide": round(stats["ms_decide"], 3),
+                   "ms_sweep": round(stats["ms_sweep"], 3), "ms_long": round(stats["ms_long"], 3),
+                   "ms_decide": round(stats["ms_decide"], 3),
                    "ms_parallel": round(stats["ms_parallel"], 3), "ms_compact": round(stats["ms_compact"], 3),
                    "step_ms_p50": round(float(np.median(step_ms)), 3),
                    "first_run_ms": round(first["ms_total"], 3),

@@ -83,7 +83,7 @@ typedef struct {
  *   feas_tol 1e-9, fix_tol 1e-9, min_improve 1e-7, par_tol 1e-9,
  *   inf_value 1e20, coef_tol 1e-9, bin thresholds from the tuner (NULL),
  *   device 0, stream NULL, split_sweep 0, enable_dual_fix 0,
- *   enable_free_singletons 0, enable_parallel_cols 0.
+ *   enable_free_singletons 0, enable_parallel_cols 0, enable_forcing_rows 0.
  * bin_thresholds (optional, n_bins = 2 or 3): [0] the longest row swept by one
  * 64-lane wavefront (16..512, default 512); [1] positions per workgroup chunk
  * of longer rows (a power of two >= 2048, default 2048); [2] the longest row
@@ -150,6 +150,17 @@ typedef struct {
                                       PARALLEL_COL / LEADER_BOUNDS. 0 (default)
                                       or 1. The parallel pass runs when either
                                       this or enable_parallel_rows is set.     */
+    int32_t enable_forcing_rows;   /* 1: forcing rows in every round (a primal
+                                      explorer, section 2.1): a row with at
+                                      least two active columns whose finite min
+                                      activity reaches its rhs within feas_tol
+                                      (or max activity its lhs) leaves
+                                      (FORCING_ROW), and every active column is
+                                      fixed at the bound giving that activity
+                                      (its other bound becomes a candidate of
+                                      the round, so the column decisions fix
+                                      it). Rows with an active |a| < coef_tol
+                                      are not forcing. 0 (default) or 1.       */
 } psl_settings;
 
 /* Postsolve record: 48 bytes, emitted in the order (round, phase, index,
@@ -176,6 +187,11 @@ typedef struct {
  *   type 12 LEADER_BOUNDS j = leader; v = {old lb, old ub, new lb, new ub}
  *                         (both only with enable_parallel_cols; a leader's
  *                         record precedes its group's PARALLEL_COL records)
+ *   type 13 FORCING_ROW   i; side 0: the min activity reached rhs, 1: the
+ *                         max activity reached lhs; v = {that activity, lhs,
+ *                         rhs} (only with enable_forcing_rows; its columns'
+ *                         BOUND_CHANGE and FIX_COL records follow in the same
+ *                         round)
  * round 0 holds input fixings; each propagation round and each parallel-row
  * pass has its own round number. */
 typedef struct {
@@ -197,6 +213,20 @@ typedef struct {
     double sweep_bytes;            /* algorithmic bytes of those launches       */
     double ms_long;                /* long-row chunk statistics (before each
                                       sweep launch)                             */
+    double alg_bytes;              /* algorithmic (compulsory) HBM bytes of
+                                      every pass of the run: per round the
+                                      sweep (12 B per swept nonzero, 48 B per
+                                      swept row, 32 B per column it can touch)
+                                      and the decisions (40 B per row and
+                                      column, 48 B per record); per parallel
+                                      pass 40 B per row, 12 B per nonzero and
+                                      the records; compaction 12 B per input
+                                      and 24 B per reduced nonzero, 32 B per
+                                      reduced row, 40 B per reduced column     */
+    double ingest_bytes;           /* the same for the ingest of the LP (create
+                                      or reload): 36 B per nonzero (read, copy,
+                                      transposed copy), 32 B per row, 48 B per
+                                      column                                    */
 } psl_stats;
 
 /* The reduced problem. DEVICE pointers owned by the handle, valid until the

@@ -73,11 +73,15 @@ enum { RES_REDUCED = 0, RES_UNCHANGED = 1, RES_INFEASIBLE = 2, RES_UNBOUNDED = 3
  *                 v = {a_ij, lhs_i, rhs_i (the sides then), c_j (then)}
  *  PARALLEL_COL   j = merged column, k = its leader; v = {lambda, lb_j, ub_j}
  *  LEADER_BOUNDS  j = leader; v = {old lb, old ub, new lb, new ub}
+ *  FORCING_ROW    i; side 0: the min activity reaches rhs (every active
+ *                 column at the bound of its min contribution), 1: the max
+ *                 activity reaches lhs; v = {that activity, lhs, rhs}
  */
 enum {
     REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
     REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
-    REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10, REC_PARALLEL_COL = 11, REC_LEADER_BOUNDS = 12
+    REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10, REC_PARALLEL_COL = 11, REC_LEADER_BOUNDS = 12,
+    REC_FORCING_ROW = 13
 };
 
 /* parallel columns are searched among columns stored with at most this many
@@ -233,6 +237,7 @@ static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s
     if (s->enable_dual_fix != 0 && s->enable_dual_fix != 1) return fail(h, "invalid dual-fix switch");
     if (s->enable_free_singletons != 0 && s->enable_free_singletons != 1)
         return fail(h, "invalid free-singleton switch");
+    if (s->enable_forcing_rows != 0 && s->enable_forcing_rows != 1) return fail(h, "invalid settings");
     if (s->enable_parallel_cols != 0 && s->enable_parallel_cols != 1)
         return fail(h, "invalid parallel-column switch");
     if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return fail(h, "negative size");
@@ -331,7 +336,7 @@ static void compute_stats(const or_handle *h, int32_t i, const double *lb, const
 /* one propagation round (reading R-Jacobi)                                   */
 /* ------------------------------------------------------------------------- */
 
-enum { DEC_KEEP = 0, DEC_EMPTY = 1, DEC_REDUNDANT = 2, DEC_SINGLETON = 3 };
+enum { DEC_KEEP = 0, DEC_EMPTY = 1, DEC_REDUNDANT = 2, DEC_SINGLETON = 3, DEC_FORCE_MIN = 4, DEC_FORCE_MAX = 5 };
 
 typedef struct {
     double *lb_s, *ub_s;       /* snapshot                         */
@@ -348,6 +353,48 @@ typedef struct {
 /* Implied bounds of row i on each of its active columns, from the residual
  * activity with the column's own contribution taken out. Returns 1 when the
  * row (with one active column) is fully captured by the candidates it gave. */
+/* Forcing rows (a primal explorer; Andersen & Andersen 1995, cited by the
+ * paper for its explorers): a row with at least two active columns whose
+ * finite min activity reaches its rhs (within tol, no infinite contribution)
+ * can hold only with every active column at the bound giving its min
+ * contribution (a > 0: lb, a < 0: ub); symmetrically a max activity reaching
+ * the lhs. Returns 1 (min side) or 2 (max side), else 0. Every active
+ * coefficient must be at least coef_tol in magnitude (a tiny one would let
+ * its column move far within the tolerance). */
+static int forcing_side(const or_handle *h, int32_t i, const row_stats *st) {
+    const or_settings *s = &h->s;
+    if (!s->enable_forcing_rows || st->L < 2) return 0;
+    double lhs = h->lhs[i], rhs = h->rhs[i];
+    int side = 0;
+    if (st->ninf_min == 0 && !isinf(rhs) && st->minact >= rhs - tol_of(s, rhs)) side = 1;
+    else if (st->ninf_max == 0 && !isinf(lhs) && st->maxact <= lhs + tol_of(s, lhs)) side = 2;
+    if (!side) return 0;
+    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k)
+        if (h->col_on[h->ci[k]] && fabs(h->va[k]) < s->coef_tol) return 0;
+    return side;
+}
+
+/* The forced bounds of a forcing row as candidates: each active column's
+ * other bound moves onto the bound its side forces (qualifying whenever it
+ * is tighter; the columns are then fixed by the column decisions). */
+static void force_row(or_handle *h, int32_t i, int side, round_ws *w) {
+    for (int64_t k = h->rp[i]; k < h->rp[i + 1]; ++k) {
+        int32_t j = h->ci[k];
+        if (!h->col_on[j]) continue;
+        double a = h->va[k];
+        /* min side: a > 0 sits at lb (its ub moves down to lb), a < 0 at ub;
+         * max side the other way round */
+        int at_lb = (side == 1) == (a > 0);
+        if (at_lb) {
+            double t_ = w->lb_s[j];
+            if (t_ < w->ub_s[j] && t_ < w->ub_n[j]) { w->ub_n[j] = t_; w->src_ub[j] = i; }
+        } else {
+            double t_ = w->ub_s[j];
+            if (t_ > w->lb_s[j] && t_ > w->lb_n[j]) { w->lb_n[j] = t_; w->src_lb[j] = i; }
+        }
+    }
+}
+
 static int propagate_row(or_handle *h, int32_t i, const row_stats *st, round_ws *w) {
     const or_settings *s = &h->s;
     int64_t s0 = h->rp[i], len = h->rp[i + 1] - h->rp[i];
@@ -474,6 +521,12 @@ static int run_round(or_handle *h, round_ws *w) {
             propagate_row(h, i, st, w);
             continue;
         }
+        int fs = forcing_side(h, i, st);
+        if (fs) {
+            w->dec[i] = fs == 1 ? DEC_FORCE_MIN : DEC_FORCE_MAX;
+            force_row(h, i, fs, w);
+            continue;
+        }
         if (propagate_row(h, i, st, w)) w->dec[i] = DEC_SINGLETON;
     }
 
@@ -487,6 +540,9 @@ static int run_round(or_handle *h, round_ws *w) {
             push(h, REC_REDUNDANT_ROW, 0, i, -1, -1,
                  st->ninf_min ? -INFINITY : st->minact, st->ninf_max ? INFINITY : st->maxact,
                  h->lhs[i], h->rhs[i]);
+        } else if (w->dec[i] == DEC_FORCE_MIN || w->dec[i] == DEC_FORCE_MAX) {
+            int mx = w->dec[i] == DEC_FORCE_MAX;
+            push(h, REC_FORCING_ROW, mx, i, -1, -1, mx ? st->maxact : st->minact, h->lhs[i], h->rhs[i], 0);
         } else {
             int32_t jj = -1;
             double a = 0;
@@ -919,9 +975,11 @@ static int parallel_cols(or_handle *h) {
             lam[j] = la;
             any = 1;
         }
-        if (any && (lo == INFINITY || up == -INFINITY)) {
+        if (any && (!(lo < INFINITY) || !(up > -INFINITY))) {
             /* the merged interval passed inf_value on the wrong side: no
-             * finite value would satisfy it, so the group is not merged */
+             * finite value would satisfy it, so the group is not merged. A
+             * lower sum that reached +inf and then met a -inf term is NaN
+             * (and the mirror for the upper sum): not merged either. */
             for (int32_t t = g0 + 1; t < g1; ++t)
                 if (lead[kc[t].col] == k) lead[kc[t].col] = -1;
             any = 0;

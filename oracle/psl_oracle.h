@@ -35,6 +35,7 @@ typedef struct {
     int32_t enable_dual_fix;  /* 1: lock-based dual fixing in every round */
     int32_t enable_free_singletons;  /* 1: zero-cost free column singletons */
     int32_t enable_parallel_cols;    /* 1: parallel columns in the parallel pass */
+    int32_t enable_forcing_rows;     /* 1: forcing rows in every round */
 } or_settings;
 
 /* 48-byte postsolve record; the field meaning per type is listed in the .c */

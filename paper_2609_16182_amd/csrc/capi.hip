@@ -93,6 +93,7 @@ extern "C" void psl_settings_default(psl_settings* s) {
   s->enable_dual_fix = 0;
   s->enable_free_singletons = 0;
   s->enable_parallel_cols = 0;
+  s->enable_forcing_rows = 0;
 }
 
 std::string psl::check_settings(const psl_settings* s) {
@@ -105,6 +106,7 @@ std::string psl::check_settings(const psl_settings* s) {
   if (s->enable_free_singletons != 0 && s->enable_free_singletons != 1)
     return "enable_free_singletons must be 0 or 1";
   if (s->enable_parallel_cols != 0 && s->enable_parallel_cols != 1) return "enable_parallel_cols must be 0 or 1";
+  if (s->enable_forcing_rows != 0 && s->enable_forcing_rows != 1) return "enable_forcing_rows must be 0 or 1";
   if (s->bin_thresholds) {
     if (s->n_bins != 2 && s->n_bins != 3) return "bin_thresholds needs n_bins = 2 or 3";
     int a = s->bin_thresholds[0], b = s->bin_thresholds[1];
@@ -238,8 +240,6 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(lpart, p->chunk_cap);
   ALLOC(lrow, p->long_cap);
 
-  p->rec_cap = 2 * m + 4 * n + 1024;
-  ALLOC(p->rec, p->rec_cap);
 
   // parallel rows: a table of >= 2m slots (per LP in a batch)
   int64_t cap = 64;
@@ -253,7 +253,8 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->par.side_src, 2 * m);
   ALLOC(p->par.is_leader, m);
   ALLOC(p->par.vlist, m);
-  ALLOC(p->par.hacc, 3 * p->long_cap);
+  ALLOC(p->par.hacc, 4 * p->long_cap);
+  ALLOC(p->par.lam, m);
   p->par.lpt = nullptr;
   if (p->s.enable_parallel_cols) {
     ALLOC(p->pc.key, n);
@@ -302,6 +303,11 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(r.col_map, n);
   ALLOC(r.row_class, m);
   ALLOC(r.col_class, n);
+
+  // postsolve records: room for one record per row and two per column and
+  // some; grown in a run when needed
+  p->rec_cap = 2 * m + 4 * n + 1024;
+  ALLOC(p->rec, p->rec_cap);
 
   HALLOC(p->hflags, 1);
   HALLOC(p->htot, 64);
@@ -384,7 +390,7 @@ static psl_status setup_arena(psl_presolver* p) {
   d.lpo = p->lpo;
   const psl_settings& s = p->s;
   d.cfg = Cfg{s.feas_tol, s.fix_tol, s.min_improve, s.par_tol, s.inf_value, s.coef_tol, s.enable_dual_fix,
-              s.enable_free_singletons};
+              s.enable_free_singletons, s.enable_forcing_rows};
   // every device array the kernels index must exist (allocations are >= 64 B
   // even for empty problems); colid is set once the transposed copy exists
   const void* ptrs[] = {d.rp, d.ci, d.va, d.cp, d.ri, d.cva, d.lhs, d.rhs, d.bnd, d.bkey, d.src, d.c, d.locks,
@@ -737,6 +743,20 @@ static psl_status ingest_batch(psl_presolver* p, int32_t k, const psl_lp* lps) {
   return ingest_rest(p);
 }
 
+// settings of a new handle (thresholds copied, the caller's array not kept)
+static void take_settings(psl_presolver* p, const psl_settings* s) {
+  p->s = *s;
+  p->s.bin_thresholds = nullptr;
+  if (s->bin_thresholds) {
+    p->thresholds[0] = s->bin_thresholds[0];
+    p->thresholds[1] = s->bin_thresholds[1];
+    if (s->n_bins == 3) p->thresholds[2] = s->bin_thresholds[2];
+  }
+  p->stream = (hipStream_t)s->stream;
+  p->sweep_mode = s->split_sweep ? 2 : MODE_ROUND;
+  if (const char* e = std::getenv("PSL_TRACE")) p->trace = std::atoi(e) != 0;
+}
+
 extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* s, psl_presolver** out) {
   if (!lp || !out) {
     g_create_error = "null argument";
@@ -756,16 +776,7 @@ extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* 
     return PSL_ERR_DEVICE;
   }
   psl_presolver* p = new psl_presolver();
-  p->s = *s;
-  p->s.bin_thresholds = nullptr;
-  if (s->bin_thresholds) {
-    p->thresholds[0] = s->bin_thresholds[0];
-    p->thresholds[1] = s->bin_thresholds[1];
-    if (s->n_bins == 3) p->thresholds[2] = s->bin_thresholds[2];
-  }
-  p->stream = (hipStream_t)s->stream;
-  p->sweep_mode = s->split_sweep ? 2 : MODE_ROUND;
-  if (const char* e = std::getenv("PSL_TRACE")) p->trace = std::atoi(e) != 0;
+  take_settings(p, s);
   p->cap_m = lp->m;
   p->cap_n = lp->n;
   p->cap_nnz = lp->nnz;
@@ -1001,7 +1012,16 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       // algorithmic bytes: the swept rows' positions (12 B a nonzero), their
       // bin entry, sides and outputs (24 B a row), and the bounds of the
       // columns they can touch (16 B each, at most one per nonzero)
-      S.sweep_bytes += 12.0 * p->cur.nnz + 24.0 * p->cur.rows + 16.0 * std::min<int64_t>(n, p->cur.nnz);
+      // algorithmic bytes of the sweep launch: the swept rows' positions
+      // (12 B a nonzero); per swept row its bin entry, row pointer, sides and
+      // statistics (48 B); per column it can touch (at most one per nonzero)
+      // the bound read and the new-bound write (32 B)
+      {
+        double sb = 12.0 * p->cur.nnz + 48.0 * p->cur.rows + 32.0 * std::min<int64_t>(n, p->cur.nnz);
+        S.sweep_bytes += sb;
+        // the decisions over every row and column, and the round's records
+        S.alg_bytes += sb + 40.0 * ((double)m + n) + 48.0 * p->hflags->round_total;
+      }
       p->rec_count += p->hflags->round_total;
       any_done = false;
       nprop = 0;
@@ -1053,6 +1073,10 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     if (e == PSL_OK) e = begin_lp_round(p);
     if (e != PSL_OK) return e;
     HIPCHK(p, hipEventRecord(p->ev[4], st));
+    // every live row's removed-column constant and active length go to
+    // row_out (free once the round's records are emitted): long rows from
+    // their chunk partials here, the others in the hash pass
+    if (s.enable_parallel_rows) launch_long_consts(d, st);
     launch_par_reset(d, p->par, st);
     if (s.enable_parallel_rows) {
       launch_par_hash(d, p->par, p->grid, st);
@@ -1072,6 +1096,8 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     if (e == PSL_OK) e = read_flags(p);
     if (e != PSL_OK) return e;
     par_ms += elapsed(p, 4, 5);
+    // keys and table per row, one pass over the positions, the records
+    S.alg_bytes += 40.0 * m + 12.0 * (double)p->nnz + 48.0 * p->hflags->round_total;
     p->rec_count += p->hflags->round_total;
     any_done = false;
     for (int k = 0; k < K; ++k) {
@@ -1122,6 +1148,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     p->red_n = p->htot[1];
     p->red_nnz = p->htot[2];
     p->red_off = B ? 0.0 : *p->hoff;
+    S.alg_bytes += 12.0 * (double)p->nnz + 24.0 * (double)p->red_nnz + 32.0 * p->red_m + 40.0 * p->red_n;
     if (p->htot[2] != p->htot[3]) return fail(p, PSL_ERR_DEVICE, "reduced CSR and transposed copy disagree");
     for (int k = 0; k < K; ++k)
       if (p->h_lpr[k + 1].eb - p->h_lpr[k].eb != p->h_lpr[k + 1].qb - p->h_lpr[k].qb)
@@ -1152,6 +1179,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   S.m_out = p->red_m;
   S.n_out = p->red_n;
   S.ms_ingest = p->ms_ingest;
+  S.ingest_bytes = 36.0 * (double)p->nnz + 32.0 * p->m + 48.0 * p->n;
   S.ms_sweep = sweep_ms;
   S.ms_long = long_ms;
   S.ms_decide = decide_ms;
@@ -1355,167 +1383,6 @@ static psl_status postsolve_of(psl_presolver* p, int k, const double* x_red, con
 }
 
 psl_status psl::engine_host_cols(psl_presolver* p, int k, HostCols& A) { return host_cols(p, k, A); }
-
-bool psl::records_need_rows(const psl_record* rec, int64_t count) {
-  for (int64_t t = 0; t < count; ++t)
-    if (rec[t].type == REC_FREE_SINGLETON) return true;
-  return false;
-}
-
-// primal postsolve: kept columns from x_red, removed ones from their FIX_COL /
-// EMPTY_COL / DUAL_FIX records; then, last record first, each free singleton
-// column from its row (with rest = the row's other terms, its original
-// entries left to right, and s = the recorded side the row went to, or rest
-// clamped to the sides without a cost, x_j = (s - rest) / a_ij) and each
-// group of parallel columns split from its leader's merged value. The other
-// records keep the feasible set.
-// a merged interval bound: |v| >= inf_value is infinite, -0 is +0
-static double merged_bound(double v, double inf_value) {
-  if (std::fabs(v) >= inf_value) return v > 0 ? INFINITY : -INFINITY;
-  return v == 0.0 ? 0.0 : v;
-}
-
-// the interval [lo, up] + lam * [l, u]
-static void add_scaled(double lam, double l, double u, double inf_value, double& lo, double& up) {
-  if (lam > 0) {
-    lo = merged_bound(lo + lam * l, inf_value);
-    up = merged_bound(up + lam * u, inf_value);
-  } else {
-    lo = merged_bound(lo + lam * u, inf_value);
-    up = merged_bound(up + lam * l, inf_value);
-  }
-}
-
-// Split the merged value of the group led by rec[t] (LEADER_BOUNDS; its
-// PARALLEL_COL records follow in the same pass): the intervals B_0 (the
-// leader's old bounds), B_s = B_{s-1} + lambda_s [lb_s, ub_s] are rebuilt as
-// presolve built them; members, last first, take the value in [lb_s, ub_s]
-// that keeps v - lambda_s x_s in B_{s-1} (from lb_s if finite, else ub_s,
-// else 0, clamped to that range) and v -= lambda_s x_s; the leader keeps v.
-static void split_group(const psl_record* rec, int64_t count, int64_t t, double inf_value, double* x) {
-  const psl_record& L = rec[t];
-  int32_t k = L.j;
-  std::vector<const psl_record*> mem;
-  for (int64_t q = t + 1; q < count && rec[q].round == L.round &&
-                          (rec[q].type == REC_PARALLEL_COL || rec[q].type == REC_LEADER_BOUNDS);
-       ++q)
-    if (rec[q].type == REC_PARALLEL_COL && rec[q].k == k) mem.push_back(&rec[q]);
-  std::vector<double> blo(mem.size() + 1), bup(mem.size() + 1);
-  blo[0] = L.v[0];
-  bup[0] = L.v[1];
-  for (size_t s = 0; s < mem.size(); ++s) {
-    blo[s + 1] = blo[s];
-    bup[s + 1] = bup[s];
-    add_scaled(mem[s]->v[0], mem[s]->v[1], mem[s]->v[2], inf_value, blo[s + 1], bup[s + 1]);
-  }
-  double v = x[k];
-  for (size_t q = mem.size(); q-- > 0;) {
-    double lam = mem[q]->v[0], l = mem[q]->v[1], u = mem[q]->v[2];
-    double a, b;
-    if (lam > 0) {
-      a = (v - bup[q]) / lam;
-      b = (v - blo[q]) / lam;
-    } else {
-      a = (v - blo[q]) / lam;
-      b = (v - bup[q]) / lam;
-    }
-    double lo = a > l ? a : l, hi = b < u ? b : u;
-    double pref = !std::isinf(l) ? l : (!std::isinf(u) ? u : 0.0);
-    double xs = pref < lo ? lo : (pref > hi ? hi : pref);
-    x[mem[q]->j] = xs;
-    v = v - lam * xs;
-  }
-  x[k] = v;
-}
-
-psl_status psl::postsolve_primal(const psl_record* rec, int64_t count, const int32_t* col_map_dev, int32_t n,
-                                 int32_t n_red, const double* x_red, double* x, const HostRows* rows,
-                                 double inf_value, std::string* err) {
-  if (!rows && records_need_rows(rec, count)) {
-    *err = "free-singleton records need the original rows, which this handle does not keep";
-    return PSL_ERR_UNSUPPORTED;
-  }
-  std::vector<int32_t> cmap(n_red);
-  if (n_red && hipMemcpy(cmap.data(), col_map_dev, n_red * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
-    *err = "HIP error copying the column map";
-    return PSL_ERR_DEVICE;
-  }
-  for (int32_t j = 0; j < n; ++j) x[j] = 0.0;
-  for (int32_t t = 0; t < n_red; ++t) x[cmap[t]] = x_red[t];
-  for (int64_t t = count - 1; t >= 0; --t) {
-    const psl_record& r = rec[t];
-    if (r.type == REC_FIX_COL || r.type == REC_EMPTY_COL || r.type == REC_DUAL_FIX) x[r.j] = r.v[0];
-  }
-  for (int64_t t = count - 1; t >= 0; --t) {
-    const psl_record& r = rec[t];
-    if (r.type == REC_LEADER_BOUNDS) {
-      split_group(rec, count, t, inf_value, x);
-      continue;
-    }
-    if (r.type != REC_FREE_SINGLETON) continue;
-    double rest = 0.0;
-    for (int32_t q = rows->rp[r.i]; q < rows->rp[r.i + 1]; ++q)
-      if (rows->ci[q] != r.j) rest = rest + rows->va[q] * x[rows->ci[q]];
-    double side = r.side == 1 ? r.v[1] : r.side == 2 ? r.v[2] : (rest < r.v[1] ? r.v[1] : (rest > r.v[2] ? r.v[2] : rest));
-    x[r.j] = (side - rest) / r.v[0];
-  }
-  return PSL_OK;
-}
-
-// Dual postsolve (sections 2.1 "Postsolver" and 3.3). Convention:
-// c - A'y - z = 0, y_i >= 0 at lhs and <= 0 at rhs, z_j >= 0 at lb and <= 0
-// at ub. The kept rows take the reduced duals, every other row starts at 0,
-// and the records are undone last to first:
-//  * a tightened bound whose column carries a multiplier of that bound's sign
-//    (z_j = c_j - a_j'y > 0 for a lower, < 0 for an upper bound) is binding
-//    only through its source row k, which sits at the side that implied it:
-//    the multiplier moves there, y_k += z_j / a_kj. The row's other columns
-//    then sit at the bounds its residual activity used (those before that
-//    round), so a reduced cost this creates for them is moved on by their
-//    own earlier tightenings further down the pass;
-//  * an active merged side of a parallel-row leader L (y_L > 0: lhs, < 0:
-//    rhs) belongs to the row r that gave it, a_r = lambda_r a_L:
-//    y_r = y_L / lambda_r and y_L = 0;
-//  * the other records keep y (a dual-fixed column has no lock towards its
-//    bound, so the alive rows' multipliers only push z_j to that bound's sign);
-//  * a row that left with a free singleton takes y_i = c_j / a_ij (its column
-//    is free, z_j = 0; c_j is the cost it had then).
-// Finally z = c - A'y. Every a_j'y is summed over column j's rows in
-// ascending order, left to right.
-static double reduced_cost(const HostCols& A, const double* y, int32_t j) {
-  double s = 0.0;
-  for (int32_t q = A.cp[j]; q < A.cp[j + 1]; ++q) s = s + A.cva[q] * y[A.ri[q]];
-  return A.c[j] - s;
-}
-
-void psl::postsolve_dual(const psl_record* rec, int64_t count, int32_t m, int32_t n,
-                         const std::vector<int32_t>& row_map, const double* y_red, const HostCols& A, double* y,
-                         double* z) {
-  for (int32_t i = 0; i < m; ++i) y[i] = 0.0;
-  for (size_t t = 0; t < row_map.size(); ++t) y[row_map[t]] = y_red[t];
-  std::vector<double> lambda(m > 0 ? m : 1, 0.0);  // rows removed as parallel
-  for (int64_t t = 0; t < count; ++t)
-    if (rec[t].type == REC_PARALLEL_ROW) lambda[rec[t].i] = rec[t].v[0];
-  for (int64_t t = count - 1; t >= 0; --t) {
-    const psl_record& r = rec[t];
-    if (r.type == REC_BOUND_CHANGE && r.k >= 0) {
-      double zj = reduced_cost(A, y, r.j);
-      bool binding = r.side == 0 ? zj > 0.0 : zj < 0.0;
-      if (binding) y[r.k] = y[r.k] + zj / r.v[2];
-    } else if (r.type == REC_FREE_SINGLETON) {
-      y[r.i] = r.v[3] / r.v[0];  // the substituted column is free: z_j = 0
-    } else if (r.type == REC_LEADER_SIDES) {
-      int32_t L = r.i;
-      double yl = y[L];
-      int32_t from = yl > 0.0 ? r.j : (yl < 0.0 ? r.k : -1);
-      if (from >= 0 && from != L) {
-        y[from] = yl / lambda[from];
-        y[L] = 0.0;
-      }
-    }
-  }
-  for (int32_t j = 0; j < n; ++j) z[j] = reduced_cost(A, y, j);
-}
 
 extern "C" psl_status psl_postsolve(psl_presolver* p, const double* x_red, const double* y_red, const double* z_red,
                                     double* x, double* y, double* z) {

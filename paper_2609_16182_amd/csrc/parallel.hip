@@ -1,26 +1,35 @@
-// parallel.hip -- parallel rows (section 3.2, "Parallel rows").
+// parallel.hip -- parallel rows (section 3.2, "Parallel rows") of the
+// current problem: columns that are fixed or removed are ignored, as when A
+// is streamed (section 3.2, "Internal data structures").
 //
-// Two rows are parallel when a_i = lambda a_k. Every active row with at least
-// two active columns is hashed independently (two levels: the stored sparsity
-// pattern, then the coefficients normalised by the row's first stored
-// coefficient and quantised), the keys go into an open-addressing table, and
-// each row of a key group is checked against the group's leader: the lowest
-// equality row of the group, else its lowest row. Verified rows are removed
-// and the leader's sides become the intersection of the mapped sides; the row
-// giving each final side is the lowest such row.
+// Two rows are parallel when a_i = lambda a_k over their active entries.
+// Every active row with at least two active columns is hashed independently
+// (two levels: the active sparsity pattern, then the active coefficients
+// normalised by the row's first active coefficient and quantised), the keys
+// go into an open-addressing table, and each row of a key group is checked
+// against the group's leader: the lowest equality row of the group, else its
+// lowest row. The hash pass also leaves every live row's removed-column
+// constant k_i (canonical pairwise sum over its positions; long rows from
+// their chunk partials) and active length in row_out. Sides are compared in the
+// effective frame [lhs - k, rhs - k]: verified rows are removed and the
+// leader's effective sides become the intersection of the mapped sides; the
+// row giving each final side is the lowest such row. A side the leader keeps
+// keeps its stored value, one taken from another row is stored as
+// effective + k_leader.
 #include "psl_kern.h"
 #include "sweep.h"
 
 namespace psl {
 
 // col0: first column of the row's LP (the pattern is hashed in the LP's own
-// column numbering, so a row's key does not depend on its place in a batch)
+// column numbering, so a row's key does not depend on its place in a batch).
+// Only active entries (column bounds not equal) enter the key.
 __device__ __forceinline__ void hash_el(int j, double a, double2 b, bool v, double a0, int col0,
                                         unsigned long long& h1, unsigned long long& h2, bool& act) {
-  unsigned long long cj = splitmix((unsigned long long)(uint32_t)(j - col0));
-  h1 = v ? cj : 0ULL;
-  h2 = v ? splitmix(cj ^ quantize(a / a0)) : 0ULL;
   act = v && b.x != b.y;
+  unsigned long long cj = splitmix((unsigned long long)(uint32_t)(j - col0));
+  h1 = act ? cj : 0ULL;
+  h2 = act ? splitmix(cj ^ quantize(a / a0)) : 0ULL;
 }
 
 // Hash terms of the positions q = q0 + u * STRIDE + lane (u < U, valid when
@@ -55,11 +64,35 @@ __device__ __forceinline__ void hash_batch(const Dev& d, int64_t s0, int q0, int
   }
 }
 
+// First active position of a row (one wavefront, all lanes return it), or
+// -1 when no column of the row is active.
+__device__ __forceinline__ int first_active_pos(const Dev& d, int64_t s0, int len) {
+  int lane = lane_id();
+  for (int q0 = 0; q0 < len; q0 += PSL_WAVE) {
+    int q = q0 + lane;
+    bool act = false;
+    if (q < len) {
+      double2 b = d.bnd[d.ci[s0 + q]];
+      act = b.x != b.y;
+    }
+    unsigned long long mask = __ballot(act);
+    if (mask) return q0 + __ffsll((long long)mask) - 1;
+  }
+  return -1;
+}
+
 __device__ __forceinline__ unsigned long long row_key(int len, unsigned long long s1, unsigned long long s2) {
   return (splitmix((unsigned long long)len + s1) ^ s2) | 1ULL;
 }
 
 __device__ __forceinline__ int lp_col0(const Dev& d, int row) { return d.K > 1 ? d.lp_col0[d.row_lp[row]] : 0; }
+
+// a stored side of live row i in the frame of its active columns: moved by
+// the removed columns' constant (row_out[i].v0, from the hash pass);
+// infinite sides stay
+__device__ __forceinline__ double eff_side(const Dev& d, int i, double side) {
+  return is_inf(side) ? side : pos0(side - d.row_out[i].v0);
+}
 
 // every LP has its own table (a power-of-two slice of the slot array), so key
 // groups never mix rows of different LPs
@@ -80,7 +113,6 @@ __device__ __forceinline__ void par_insert(const Dev& d, const ParScratch& P, in
   }
   bool eq = d.lhs[row] == d.rhs[row];
   atomicMin(&tab[h].leader, (eq ? 0u : 0x80000000u) | (unsigned)row);
-  atomicAdd(&tab[h].count, 1u);
   P.slot[row] = (int)(base + (int64_t)h);
 }
 
@@ -90,19 +122,17 @@ __global__ void k_par_reset(Dev d, ParScratch P) {
     HashSlot z;
     z.key = 0;
     z.leader = 0xFFFFFFFFu;
-    z.count = 0;
+    z.pad = 0;
     P.table[t] = z;
   }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.m; i += stride) {
     P.slot[i] = -1;
     P.lead[i] = -1;
     P.is_leader[i] = 0;
-    P.side_key[2 * i] = dkey(d.lhs[i]);
-    P.side_key[2 * i + 1] = dkey(d.rhs[i]);
     P.side_src[2 * i] = 0x7FFFFFFF;
     P.side_src[2 * i + 1] = 0x7FFFFFFF;
   }
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 3 * (int64_t)d.nlong; k += stride)
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < 4 * (int64_t)d.nlong; k += stride)
     P.hacc[k] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.flags->vlist_count = 0;
@@ -113,7 +143,8 @@ __global__ void k_par_reset(Dev d, ParScratch P) {
 
 // G-lane groups, rows of at most G entries, one position per lane (a lane
 // without a row reads the bin's first entry, which exists, and position 0
-// or the row's first position, so that no load is conditional)
+// or the row's first position, so that no load is conditional); the first
+// active coefficient comes from the lowest active lane of the group
 template <int G>
 __device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, int bin, int lblock) {
   int gid = lblock * (PSL_BLOCK / G) + (int)(threadIdx.x / G);
@@ -127,35 +158,115 @@ __device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, i
   int64_t p0 = len > 0 ? s0 : 0;
   int64_t p = gl < len ? s0 + gl : p0;
   bool on = vr && d.row_on[row] != 0;
-  double a0 = d.va[p0];
   int j = d.ci[p];
   double a = d.va[p];
   double2 bb = d.bnd[j];
+  bool act0 = on && gl < len && bb.x != bb.y;
+  unsigned long long gmask = __ballot(act0) & group_mask<G>();
+  int first = gmask ? __ffsll((long long)gmask) - 1 : lane_id();
+  double a0 = __shfl(a, first, PSL_WAVE);
+  if (!gmask) a0 = 1.0;
   int col0 = lp_col0(d, row);
   unsigned long long h1, h2;
   bool act;
-  hash_el(j, a, bb, on && gl < len, len > 0 ? a0 : 1.0, col0, h1, h2, act);
+  hash_el(j, a, bb, on && gl < len, a0, col0, h1, h2, act);
   h1 = group_sum_u64<G>(h1);
   h2 = group_sum_u64<G>(h2);
-  int L = __popcll(__ballot(act) & group_mask<G>());
-  if (vr && on && gl == 0 && L >= 2) par_insert(d, P, row, row_key(len, h1, h2));
+  int L = __popcll(gmask);
+  // the removed columns' constant: a butterfly over the group's lanes is the
+  // canonical pairwise tree of the row's positions
+  double k = group_sum<G>(on && gl < len && !act0 ? pos0(a * bb.x) : 0.0);
+  if (vr && on && gl == 0) {
+    d.row_out[row].v0 = k;
+    d.row_out[row].j = L;
+    if (L >= 2) par_insert(d, P, row, row_key(L, h1, h2));
+  }
 }
 
-// one wavefront per row (rows of at most 512 entries)
+// pairwise tree over C values held in registers (C a power of two)
+template <int C>
+__device__ __forceinline__ double reg_tree(double (&x)[C]) {
+#pragma unroll
+  for (int w = 1; w < C; w <<= 1)
+#pragma unroll
+    for (int i = 0; i < C; i += 2 * w) x[i] = x[i] + x[i + w];
+  return x[0];
+}
+
+// One wavefront per row of at most 64 * C entries, C contiguous positions
+// per lane (the sweep's layout, so that the lane trees and a butterfly over
+// the wavefront give the canonical pairwise tree of the removed columns'
+// constant). The first active coefficient is that of the lowest lane with
+// an active entry, at its first active position.
+template <int C>
 __device__ __forceinline__ void hash_wave_row(const Dev& d, const ParScratch& P, int row) {
   int lane = lane_id();
   int64_t s0 = d.rp[row];
   int len = d.rp[row + 1] - (int)s0;
-  if (!d.row_on[row] || len < 2) return;
-  double a0 = d.va[s0];
+  if (!d.row_on[row]) return;
+  int j[C];
+  double a[C];
+  bool v[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    int q = lane * C + k;
+    v[k] = q < len;
+    int64_t p = v[k] ? s0 + q : (len > 0 ? s0 : 0);
+    j[k] = d.ci[p];
+    a[k] = d.va[p];
+  }
+  double2 b[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) b[k] = d.bnd[j[k]];
+  bool act[C];
+  int lf = C;
+  double af = 1.0;
+#pragma unroll
+  for (int k = C - 1; k >= 0; --k) {
+    act[k] = v[k] && b[k].x != b[k].y;
+    if (act[k]) {
+      lf = k;
+      af = a[k];
+    }
+  }
+  unsigned long long mask = __ballot(lf < C);
+  double a0 = mask ? __shfl(af, __ffsll((long long)mask) - 1, PSL_WAVE) : 1.0;
   int col0 = lp_col0(d, row);
   unsigned long long s1 = 0, s2 = 0;
   int L = 0;
-  for (int q0 = 0; q0 < len; q0 += 4 * PSL_WAVE) hash_batch<4, PSL_WAVE>(d, s0, q0, lane, len, a0, col0, s1, s2, L);
+  double t[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    unsigned long long h1, h2;
+    bool ak;
+    hash_el(j[k], a[k], b[k], v[k], a0, col0, h1, h2, ak);
+    s1 += h1;
+    s2 += h2;
+    L += ak ? 1 : 0;
+    t[k] = v[k] && !ak ? pos0(a[k] * b[k].x) : 0.0;
+  }
+  double kc = group_sum<PSL_WAVE>(reg_tree<C>(t));
   s1 = group_sum_u64<PSL_WAVE>(s1);
   s2 = group_sum_u64<PSL_WAVE>(s2);
   L = (int)group_sum_u64<PSL_WAVE>((unsigned long long)L);
-  if (lane == 0 && L >= 2) par_insert(d, P, row, row_key(len, s1, s2));
+  if (lane == 0) {
+    d.row_out[row].v0 = kc;
+    d.row_out[row].j = L;
+    if (L >= 2) par_insert(d, P, row, row_key(L, s1, s2));
+  }
+}
+
+// long rows: the first active coefficient of each (one wavefront per row),
+// kept in the fourth accumulator word (0 when none is active)
+__global__ void __launch_bounds__(PSL_BLOCK) k_par_long_first(Dev d, ParScratch P) {
+  int k = blockIdx.x * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6);
+  if (k >= d.nlong) return;
+  int row = d.lrow[k].row;
+  if (!d.row_on[row]) return;
+  int64_t s0 = d.rp[row];
+  int len = d.rp[row + 1] - (int)s0;
+  int f = first_active_pos(d, s0, len);
+  if (lane_id() == 0) P.hacc[4 * (int64_t)k + 3] = f < 0 ? 0ull : (unsigned long long)__double_as_longlong(d.va[s0 + f]);
 }
 
 // long rows: one workgroup per chunk, accumulated with 64-bit atomic adds
@@ -164,9 +275,11 @@ __device__ __forceinline__ void hash_long_chunk(const Dev& d, const ParScratch& 
   LongChunk ch = d.lchunk[chunk];
   int row = ch.row;
   if (!d.row_on[row]) return;
+  unsigned long long a0b = P.hacc[4 * (int64_t)ch.lrow + 3];
+  if (a0b == 0ull) return;  // no active column
+  double a0 = __longlong_as_double((long long)a0b);
   int64_t s0 = d.rp[row];
   int len = d.rp[row + 1] - (int)s0;
-  double a0 = d.va[s0];
   int col0 = lp_col0(d, row);
   unsigned long long s1 = 0, s2 = 0;
   int L = 0;
@@ -177,16 +290,20 @@ __device__ __forceinline__ void hash_long_chunk(const Dev& d, const ParScratch& 
   s2 = group_sum_u64<PSL_WAVE>(s2);
   unsigned long long l64 = group_sum_u64<PSL_WAVE>((unsigned long long)L);
   if (lane_id() == 0) {
-    atomicAdd(&P.hacc[3 * (int64_t)ch.lrow], s1);
-    atomicAdd(&P.hacc[3 * (int64_t)ch.lrow + 1], s2);
-    atomicAdd(&P.hacc[3 * (int64_t)ch.lrow + 2], l64);
+    atomicAdd(&P.hacc[4 * (int64_t)ch.lrow], s1);
+    atomicAdd(&P.hacc[4 * (int64_t)ch.lrow + 1], s2);
+    atomicAdd(&P.hacc[4 * (int64_t)ch.lrow + 2], l64);
   }
 }
 
 // the wavefront rows of a row block (four per workgroup)
 __device__ __forceinline__ void hash_wave_block(const Dev& d, const ParScratch& P, int bin, int vb) {
   int wid = vb * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6);
-  if (wid < d.bin_off[bin + 1] - d.bin_off[bin]) hash_wave_row(d, P, d.bins[d.bin_off[bin] + wid].row);
+  if (wid >= d.bin_off[bin + 1] - d.bin_off[bin]) return;
+  int row = d.bins[d.bin_off[bin] + wid].row;
+  if (bin == BIN_W1) hash_wave_row<1>(d, P, row);
+  else if (bin == BIN_W4) hash_wave_row<4>(d, P, row);
+  else hash_wave_row<8>(d, P, row);
 }
 
 // one workgroup per workgroup of the sweep's grid (the same row blocks)
@@ -217,20 +334,23 @@ __global__ void k_par_long_insert(Dev d, ParScratch P) {
   if (k >= d.nlong) return;
   int row = d.lrow[k].row;
   if (!d.row_on[row]) return;
-  int len = d.rp[row + 1] - d.rp[row];
-  if ((int64_t)P.hacc[3 * (int64_t)k + 2] >= 2)
-    par_insert(d, P, row, row_key(len, P.hacc[3 * (int64_t)k], P.hacc[3 * (int64_t)k + 1]));
+  int64_t L = (int64_t)P.hacc[4 * (int64_t)k + 2];
+  if (L >= 2) par_insert(d, P, row, row_key((int)L, P.hacc[4 * (int64_t)k], P.hacc[4 * (int64_t)k + 1]));
 }
 
-// rows of a key group (other than its leader) go to the verify list
+// rows of a key group other than its leader go to the verify list (a row
+// whose slot names another row as leader is in a group of two or more)
 __global__ void k_par_vlist(Dev d, ParScratch P) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool pred = false;
   if (i < d.m) {
     int s = P.slot[i];
     if (s >= 0) {
-      HashSlot h = P.table[s];
-      pred = h.count >= 2 && (int)(h.leader & 0x7FFFFFFFu) != (int)i;
+      pred = (int)(P.table[s].leader & 0x7FFFFFFFu) != (int)i;
+      // a possible leader's merged sides start from its own effective ones
+      // (its constant is known once the hash pass is done)
+      P.side_key[2 * i] = dkey(eff_side(d, (int)i, d.lhs[i]));
+      P.side_key[2 * i + 1] = dkey(eff_side(d, (int)i, d.rhs[i]));
     }
   }
   unsigned long long mask = __ballot(pred);
@@ -242,9 +362,9 @@ __global__ void k_par_vlist(Dev d, ParScratch P) {
   if (pred) P.vlist[base + __popcll(mask & lanemask_lt())] = (int)i;
 }
 
-__device__ __forceinline__ void mapped_sides(const Dev& d, int r, int L, double& lam, double& ml, double& mu) {
-  lam = d.va[d.rp[r]] / d.va[d.rp[L]];
-  double lr = d.lhs[r], rr = d.rhs[r];
+// effective sides of row r mapped through lambda onto its leader's frame
+__device__ __forceinline__ void mapped_sides(const Dev& d, int r, double lam, double& ml, double& mu) {
+  double lr = eff_side(d, r, d.lhs[r]), rr = eff_side(d, r, d.rhs[r]);
   if (lam > 0) {
     ml = lr / lam;
     mu = rr / lam;
@@ -256,7 +376,22 @@ __device__ __forceinline__ void mapped_sides(const Dev& d, int r, int L, double&
   mu = pos0(mu);
 }
 
-// one wavefront per listed row: same stored pattern, proportional coefficients
+// position of column j among positions [s, s + len) of a row (ascending
+// columns), or -1
+__device__ __forceinline__ int64_t find_col(const Dev& d, int64_t s, int len, int j) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (d.ci[s + mid] < j) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < len && d.ci[s + lo] == j ? s + lo : -1;
+}
+
+// One wavefront per listed row r: parallel to its leader L when both have
+// the same number of active entries and every active entry of r is in L
+// (found by binary search in L's ascending columns) with the same value
+// after dividing each row by its first active coefficient, within par_tol.
 __global__ void __launch_bounds__(PSL_BLOCK) k_par_verify(Dev d, ParScratch P) {
   int nv = d.flags->vlist_count;
   int lane = lane_id();
@@ -265,28 +400,38 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_verify(Dev d, ParScratch P) {
     int r = P.vlist[k];
     int L = (int)(P.table[P.slot[r]].leader & 0x7FFFFFFFu);
     int64_t sr = d.rp[r], sl = d.rp[L];
-    int len = d.rp[r + 1] - (int)sr;
-    bool ok = len == d.rp[L + 1] - (int)sl;
+    int len = d.rp[r + 1] - (int)sr, lenL = d.rp[L + 1] - (int)sl;
+    bool ok = d.row_out[r].j == d.row_out[L].j;
+    int fr = -1, fl = -1;
     if (ok) {
-      double r0 = d.va[sr], l0 = d.va[sl];
-      for (int q0 = 0; q0 < len && ok; q0 += PSL_WAVE) {
-        int q = q0 + lane;
-        bool bad = false;
-        if (q < len) {
-          if (d.ci[sr + q] != d.ci[sl + q]) {
+      fr = first_active_pos(d, sr, len);
+      fl = first_active_pos(d, sl, lenL);
+      ok = fr >= 0 && fl >= 0;
+    }
+    double r0 = ok ? d.va[sr + fr] : 1.0, l0 = ok ? d.va[sl + fl] : 1.0;
+    for (int q0 = fr; ok && q0 < len; q0 += PSL_WAVE) {
+      int q = q0 + lane;
+      bool bad = false;
+      if (q < len) {
+        int j = d.ci[sr + q];
+        double2 b = d.bnd[j];
+        if (b.x != b.y) {
+          int64_t pl = find_col(d, sl, lenL, j);
+          if (pl < 0) {
             bad = true;
           } else {
-            double a = d.va[sr + q] / r0, b = d.va[sl + q] / l0;
-            double scale = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
-            bad = !(fabs(a - b) <= d.cfg.par_tol * scale);
+            double x = d.va[sr + q] / r0, y = d.va[pl] / l0;
+            double scale = fabs(x) > fabs(y) ? fabs(x) : fabs(y);
+            bad = !(fabs(x - y) <= d.cfg.par_tol * scale);
           }
         }
-        ok = __ballot(bad) == 0;
       }
+      ok = __ballot(bad) == 0;
     }
     if (ok && lane == 0) {
-      double lam, ml, mu;
-      mapped_sides(d, r, L, lam, ml, mu);
+      double lam = r0 / l0, ml, mu;
+      mapped_sides(d, r, lam, ml, mu);
+      P.lam[r] = lam;
       P.lead[r] = L;
       P.is_leader[L] = 1;
       atomicMax(&P.side_key[2 * (int64_t)L], dkey(ml));
@@ -302,27 +447,36 @@ __global__ void k_par_src(Dev d, ParScratch P) {
     int r = P.vlist[k];
     int L = P.lead[r];
     if (L < 0) continue;
-    double lam, ml, mu;
-    mapped_sides(d, r, L, lam, ml, mu);
+    double ml, mu;
+    mapped_sides(d, r, P.lam[r], ml, mu);
     double lo = dunkey(P.side_key[2 * (int64_t)L]);
     double up = dunkey(P.side_key[2 * (int64_t)L + 1]);
     if (ml == lo) atomicMin(&P.side_src[2 * (int64_t)L], r);
     if (mu == up) atomicMin(&P.side_src[2 * (int64_t)L + 1], r);
-    if (d.lhs[L] == lo) atomicMin(&P.side_src[2 * (int64_t)L], L);
-    if (d.rhs[L] == up) atomicMin(&P.side_src[2 * (int64_t)L + 1], L);
+    if (eff_side(d, L, d.lhs[L]) == lo) atomicMin(&P.side_src[2 * (int64_t)L], L);
+    if (eff_side(d, L, d.rhs[L]) == up) atomicMin(&P.side_src[2 * (int64_t)L + 1], L);
   }
 }
 
-__device__ __forceinline__ bool leader_sides(const Dev& d, const ParScratch& P, int i, double& lo, double& up,
+// The leader's new stored sides (nl, nu) from the merged effective ones;
+// returns whether they differ from its current sides.
+__device__ __forceinline__ bool leader_sides(const Dev& d, const ParScratch& P, int i, double& nl, double& nu,
                                              bool& infeasible) {
-  lo = dunkey(P.side_key[2 * (int64_t)i]);
-  up = dunkey(P.side_key[2 * (int64_t)i + 1]);
+  double lo = dunkey(P.side_key[2 * (int64_t)i]);
+  double up = dunkey(P.side_key[2 * (int64_t)i + 1]);
   infeasible = false;
+  bool snapped = false;
   if (!is_inf(lo) && !is_inf(up) && lo > up) {
     if (lo > up + tol_of(d.cfg, up)) infeasible = true;
-    else lo = up;
+    else {
+      lo = up;
+      snapped = true;
+    }
   }
-  return lo != d.lhs[i] || up != d.rhs[i];
+  double k = d.row_out[i].v0;
+  nu = P.side_src[2 * (int64_t)i + 1] == i ? d.rhs[i] : (is_inf(up) ? up : pos0(up + k));
+  nl = snapped ? nu : (P.side_src[2 * (int64_t)i] == i ? d.lhs[i] : (is_inf(lo) ? lo : pos0(lo + k)));
+  return nl != d.lhs[i] || nu != d.rhs[i];
 }
 
 __global__ void k_par_count(Dev d, ParScratch P) {
@@ -377,13 +531,11 @@ __global__ void k_par_emit(Dev d, ParScratch P, int64_t base, int round) {
   r.round = (uint16_t)round_of(d, row_lp_of(d, i), round);
   if (P.lead[i] >= 0) {
     int L = P.lead[i];
-    double lam, ml, mu;
-    mapped_sides(d, i, L, lam, ml, mu);
     r.type = REC_PARALLEL_ROW;
     r.i = i;
     r.j = -1;
     r.k = L;
-    r.v[0] = lam;
+    r.v[0] = P.lam[i];
     r.v[1] = d.lhs[i];
     r.v[2] = d.rhs[i];
     r.v[3] = 0.0;
@@ -435,6 +587,8 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_drop(Dev d, ParScratch P) {
 void launch_par_hash(const Dev& d, const ParScratch& p, const SweepGrid& g, hipStream_t s) {
   int total = 0;
   for (int b = 0; b < NBINS; ++b) total += g.nb[b];
+  if (d.nlong > 0)
+    hipLaunchKernelGGL(k_par_long_first, dim3((d.nlong + 3) / 4), dim3(PSL_BLOCK), 0, s, d, p);
   if (total > 0) hipLaunchKernelGGL(k_par_hash, dim3(total), dim3(PSL_BLOCK), 0, s, d, p, g);
   if (d.nlong > 0)
     hipLaunchKernelGGL(k_par_long_insert, dim3((d.nlong + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);

@@ -283,9 +283,11 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_pc_accum(Dev d, ColScratch P, con
     up = bk.y;
     pc_fold(d, P, kind, p, lo, up);
   }
-  if (any && (lo == __builtin_inf() || up == -__builtin_inf())) {
+  if (any && (!(lo < __builtin_inf()) || !(up > -__builtin_inf()))) {
     // the merged interval passed inf_value on the wrong side: no finite value
-    // would satisfy it, so the group is not merged (its members let go)
+    // would satisfy it, so the group is not merged (its members let go); a
+    // lower sum at +inf that then met a -inf term is NaN (the mirror for the
+    // upper sum) and is not merged either
     for (int64_t q = p + 1; q < d.n && kind[q] == 0; ++q) P.lead[vals[q]] = -1;
     any = false;
   }

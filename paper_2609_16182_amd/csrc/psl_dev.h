@@ -23,11 +23,12 @@ namespace psl {
 enum : uint8_t {
   REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
   REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
-  REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10, REC_PARALLEL_COL = 11, REC_LEADER_BOUNDS = 12
+  REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10, REC_PARALLEL_COL = 11, REC_LEADER_BOUNDS = 12,
+  REC_FORCING_ROW = 13
 };
 
 // row decision codes written by the sweep for the current round
-enum : uint8_t { RC_KEEP = 0, RC_EMPTY = 1, RC_REDUNDANT = 2, RC_SINGLETON = 3 };
+enum : uint8_t { RC_KEEP = 0, RC_EMPTY = 1, RC_REDUNDANT = 2, RC_SINGLETON = 3, RC_FORCE_MIN = 4, RC_FORCE_MAX = 5 };
 
 // column decision bits of a round
 enum : uint8_t {
@@ -83,7 +84,7 @@ struct BinEnt {      // one row of a bin list
 
 struct LongPart {    // partial statistics of one chunk (an aligned subtree)
   double smin, smax;
-  int32_t nmin, nmax, L, pad;
+  int32_t nmin, nmax, L, tiny;  // tiny: active entries with |a| < coef_tol
 };
 
 struct LongRow {     // per long row
@@ -121,12 +122,13 @@ struct Cfg {
   double feas_tol, fix_tol, min_improve, par_tol, inf_value, coef_tol;
   int32_t dual_fix;        // lock-based dual fixing on
   int32_t free_sing;       // zero-cost free column singletons eliminated
+  int32_t forcing;         // forcing rows on
 };
 
 struct HashSlot {
   unsigned long long key;
   unsigned int leader;   // (inequality << 31) | row, minimised
-  unsigned int count;
+  unsigned int pad;
 };
 
 struct Dev {
@@ -315,8 +317,8 @@ __device__ __forceinline__ unsigned long long group_sum_u64(unsigned long long x
 
 template <int G>
 __device__ __forceinline__ unsigned long long group_mask() {
-  if (G == 64) return ~0ull;
-  return ((1ull << G) - 1) << (lane_id() & ~(G - 1));
+  if constexpr (G == 64) return ~0ull;
+  else return ((1ull << G) - 1) << (lane_id() & ~(G - 1));
 }
 
 // Pairwise tree over v[0..n) padded with +0 to the next power of two,

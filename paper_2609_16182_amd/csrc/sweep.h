@@ -26,6 +26,7 @@ __host__ __device__ __forceinline__ int64_t cand_region_start(const SweepGrid& g
 // sweep.hip
 void launch_long_stats(const Dev& d, int mode, hipStream_t s);
 void launch_sweep(const Dev& d, const SweepGrid& g, int mode, hipStream_t s);
+void launch_long_consts(const Dev& d, hipStream_t s);
 void launch_src(const Dev& d, const SweepGrid& g, hipStream_t s);
 // decisions, counts and records of a round (tile_sum / tile_off: one int per
 // 1024 rows and columns, ws: scan workspace)
@@ -120,7 +121,9 @@ struct ParScratch {
   int32_t* side_src;  // [2m]
   uint8_t* is_leader; // [m]
   int32_t* vlist;     // [m] rows to verify
-  unsigned long long* hacc;  // [3 * long rows] hash accumulators (h1, h2, L)
+  unsigned long long* hacc;  // [4 * long rows] hash accumulators (h1, h2, L)
+                             // and the row's first active coefficient (bits)
+  double* lam;        // [m] lambda of a verified row (a_r = lambda a_leader)
 };
 void launch_par_reset(const Dev& d, const ParScratch& p, hipStream_t s);
 void launch_par_hash(const Dev& d, const ParScratch& p, const SweepGrid& g, hipStream_t s);

@@ -133,11 +133,15 @@ __device__ __forceinline__ void lane_stats(const Dev& d, int64_t s0, int len, in
 struct RowDec {
   uint8_t code;
   bool infeasible, prop, single;
+  int force;  // forcing row: 1 at its min activity (= rhs), 2 at its max (= lhs)
 };
 
+// Row decisions from the round's statistics. any_tiny: the row has an active
+// entry with |a| < coef_tol (such a row is never forcing: its column could
+// move far within the tolerance).
 __device__ __forceinline__ RowDec decide_row(const Cfg& c, double lhs, double rhs, int L, int nmin, int nmax,
-                                             double minact, double maxact) {
-  RowDec r{RC_KEEP, false, false, false};
+                                             double minact, double maxact, bool any_tiny) {
+  RowDec r{RC_KEEP, false, false, false, 0};
   bool lo_ok = is_inf(lhs) || (nmin == 0 && minact >= lhs - tol_of(c, lhs));
   bool up_ok = is_inf(rhs) || (nmax == 0 && maxact <= rhs + tol_of(c, rhs));
   if (L == 0) {
@@ -159,8 +163,19 @@ __device__ __forceinline__ RowDec decide_row(const Cfg& c, double lhs, double rh
   // side, so it always propagates on its finite sides.)
   r.prop = (!is_inf(rhs) && nmin <= 1) || (!is_inf(lhs) && nmax <= 1);
   r.single = (L == 1);
+  // Forcing rows (at least two active columns): the finite min activity
+  // reaching rhs (or the max reaching lhs) within tol leaves every active
+  // column at the bound of that contribution; the row leaves and those
+  // bounds become candidates.
+  if (c.forcing && !r.infeasible && L >= 2 && !any_tiny) {
+    if (nmin == 0 && !is_inf(rhs) && minact >= rhs - tol_of(c, rhs)) r.force = 1;
+    else if (nmax == 0 && !is_inf(lhs) && maxact <= lhs + tol_of(c, lhs)) r.force = 2;
+    if (r.force) r.code = r.force == 1 ? RC_FORCE_MIN : RC_FORCE_MAX;
+  }
   return r;
 }
+
+__device__ __forceinline__ bool is_forcing(uint8_t code) { return code == RC_FORCE_MIN || code == RC_FORCE_MAX; }
 
 struct RowStat {
   double minact, maxact;
@@ -174,11 +189,24 @@ struct RowStat {
 // no bound (it matters for rows with one active column, which are removed only
 // when every finite side became a bound).
 __device__ __forceinline__ void prop_el(const Cfg& c, bool on, const El& e, double lhs, double rhs, const RowStat& st,
-                                        bool single, bool& cap, bool& hlo, double& tlo, bool& hup, double& tup) {
+                                        bool single, int force, bool& cap, bool& hlo, double& tlo, bool& hup,
+                                        double& tup) {
   cap = true;
   hlo = hup = false;
   tlo = tup = 0.0;
   if (!on) return;
+  if (force) {
+    // a forcing row: the column's other bound moves onto the forced one
+    // (min side: a > 0 at lb, a < 0 at ub; max side the other way round)
+    if ((force == 1) == (e.a > 0)) {
+      hup = e.lb < e.ub;
+      tup = e.lb;
+    } else {
+      hlo = e.ub > e.lb;
+      tlo = e.ub;
+    }
+    return;
+  }
   if (fabs(e.a) < c.coef_tol) {
     cap = false;
     return;
@@ -271,8 +299,11 @@ __device__ __forceinline__ RowOut row_out_of(uint8_t code, const RowStat& st) {
   RowOut o;
   o.j = -1;
   o.pad = 0;
-  if (code == RC_EMPTY) {
+  if (code == RC_EMPTY || code == RC_FORCE_MIN) {
     o.v0 = st.minact;
+    o.v1 = 0.0;
+  } else if (code == RC_FORCE_MAX) {
+    o.v0 = st.maxact;
     o.v1 = 0.0;
   } else {
     o.v0 = st.nmin ? -__builtin_huge_val() : st.minact;
@@ -286,14 +317,14 @@ __device__ __forceinline__ RowOut row_out_of(uint8_t code, const RowStat& st) {
 template <int C>
 __device__ __forceinline__ void lane_prop(const Dev& d, const CandSink& sk, int64_t p0, bool prop, const El (&e)[C],
                                           double lhs, double rhs,
-                                          const RowStat& st, bool single, bool& uncap, bool& mine, int& aj,
-                                          double& aa) {
+                                          const RowStat& st, bool single, int force, bool& uncap, bool& mine,
+                                          int& aj, double& aa) {
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     bool act = prop && el_active(e[k]);
     bool cap, hlo, hup;
     double tlo, tup;
-    prop_el(d.cfg, act, e[k], lhs, rhs, st, single, cap, hlo, tlo, hup, tup);
+    prop_el(d.cfg, act, e[k], lhs, rhs, st, single, force, cap, hlo, tlo, hup, tup);
     commit_cands(d, sk, (int)(p0 + k), e[k].j, hlo, tlo, hup, tup);
     if (act && !cap) uncap = true;
     if (act) {
@@ -311,7 +342,8 @@ __device__ __forceinline__ void lane_prop(const Dev& d, const CandSink& sk, int6
 template <int C>
 __device__ __forceinline__ void lane_prop_stream(const Dev& d, const CandSink& sk, int row, bool prop, int64_t s0,
                                                  int len, int base, double lhs, double rhs, const RowStat& st,
-                                                 bool single, bool& uncap, bool& mine, int& aj, double& aa) {
+                                                 bool single, int force, bool& uncap, bool& mine, int& aj,
+                                                 double& aa) {
   constexpr int GS = C < STREAM_GROUP ? C : STREAM_GROUP;
 #pragma unroll 1
   for (int g = 0; g < C; g += GS) {
@@ -322,7 +354,7 @@ __device__ __forceinline__ void lane_prop_stream(const Dev& d, const CandSink& s
       bool act = el_active(e[k]);
       bool cap, hlo, hup;
       double tlo, tup;
-      prop_el(d.cfg, act, e[k], lhs, rhs, st, single, cap, hlo, tlo, hup, tup);
+      prop_el(d.cfg, act, e[k], lhs, rhs, st, single, force, cap, hlo, tlo, hup, tup);
       commit_cands(d, sk, (int)(s0 + base + g + k), e[k].j, hlo, tlo, hup, tup);
       if (act && !cap) uncap = true;
       if (act) {
@@ -434,14 +466,19 @@ __device__ __forceinline__ void row_block(const Dev& d, const CandSink& sk, RowI
   bool live = vr && on;
   double lhs = live ? in.lhs : 0.0, rhs = live ? in.rhs : 0.0;
   if (live && gl == 0) d.rinf[row] = make_int2(st.nmin, st.nmax);
-  RowDec dec = decide_row(d.cfg, lhs, rhs, L, st.nmin, st.nmax, st.minact, st.maxact);
+  bool tiny = false;
+#pragma unroll
+  for (int k = 0; k < C; ++k) tiny = tiny || (el_active(e[k]) && fabs(e[k].a) < d.cfg.coef_tol);
+  bool any_tiny = (__ballot(tiny) & group_mask<G>()) != 0;
+  RowDec dec = decide_row(d.cfg, lhs, rhs, L, st.nmin, st.nmax, st.minact, st.maxact, any_tiny);
   bool prop = live && dec.prop;
   bool uncap = false, mine = false;
   int aj = 0;
   double aa = 0.0;
-  if (C == 1) lane_prop<C>(d, sk, s0 + gl * C, prop, e, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
+  int force = live ? dec.force : 0;
+  if (C == 1) lane_prop<C>(d, sk, s0 + gl * C, prop, e, lhs, rhs, st, dec.single, force, uncap, mine, aj, aa);
   else  // reload (L1/L2 hits) instead of keeping C elements live through the sums
-    lane_prop_stream<C>(d, sk, row, prop, s0, len, gl * C, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
+    lane_prop_stream<C>(d, sk, row, prop, s0, len, gl * C, lhs, rhs, st, dec.single, force, uncap, mine, aj, aa);
   bool captured = (__ballot(uncap) & group_mask<G>()) == 0;
   uint8_t code = RC_KEEP;
   if (live) {
@@ -450,12 +487,13 @@ __device__ __forceinline__ void row_block(const Dev& d, const CandSink& sk, RowI
     if (dec.infeasible && gl == 0) flag_infeasible(d, row_lp_of(d, row));
   }
   if (vr && gl == 0) d.row_code[row] = code;
-  if (live && gl == 0 && (code == RC_EMPTY || code == RC_REDUNDANT)) d.row_out[row] = row_out_of(code, st);
+  if (live && gl == 0 && (code == RC_EMPTY || code == RC_REDUNDANT || is_forcing(code)))
+    d.row_out[row] = row_out_of(code, st);
   if (code == RC_SINGLETON && mine) {
     d.row_out[row] = RowOut{aa, 0.0, aj, 0};
     drop_col(d, aj, aa, lhs, rhs);
   }
-  if (code == RC_REDUNDANT) {
+  if (code == RC_REDUNDANT || is_forcing(code)) {
     if (C == 1) lane_drop<C>(d, e, lhs, rhs);
     else lane_drop_stream<C>(d, live, s0, len, gl * C, lhs, rhs);
   }
@@ -557,6 +595,7 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_long_stats(Dev d) {
   int len = d.rp[row + 1] - (int)s0;
   int tmin = 0, tmax = 0, tl = 0;
   int np = ch.npass;
+  bool tiny = false;  // an active entry with |a| < coef_tol (forcing rows)
   for (int p = 0; p < np; ++p) {
     El e[8];
     double a, b;
@@ -569,7 +608,10 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_long_stats(Dev d) {
     tmin += x;
     tmax += y;
     tl += z;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tiny = tiny || (el_active(e[k]) && fabs(e[k].a) < d.cfg.coef_tol);
   }
+  int any_tiny = __syncthreads_or(tiny ? 1 : 0);
   if (threadIdx.x == 0) {
     LongPart pt;
     pt.smin = tree_inplace(ps, np);
@@ -577,15 +619,15 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_long_stats(Dev d) {
     pt.nmin = tmin;
     pt.nmax = tmax;
     pt.L = tl;
-    pt.pad = 0;
+    pt.tiny = any_tiny ? 1 : 0;
     d.lpart[ch.id] = pt;
   }
 }
 
 // row totals from the chunk partials: one wavefront, 8 chunks per lane
-__device__ __forceinline__ void long_totals(const Dev& d, const LongRow& lr, RowStat& st, int& L) {
+__device__ __forceinline__ void long_totals(const Dev& d, const LongRow& lr, RowStat& st, int& L, int& tiny) {
   double a[8], b[8];
-  int n0 = 0, n1 = 0, n2 = 0;
+  int n0 = 0, n1 = 0, n2 = 0, n3 = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     int c = lane_id() * 8 + k;
@@ -597,6 +639,7 @@ __device__ __forceinline__ void long_totals(const Dev& d, const LongRow& lr, Row
       n0 += pt.nmin;
       n1 += pt.nmax;
       n2 += pt.L;
+      n3 += pt.tiny;
     }
   }
   st.minact = group_sum<PSL_WAVE>(lane_tree<8>(a));
@@ -604,6 +647,7 @@ __device__ __forceinline__ void long_totals(const Dev& d, const LongRow& lr, Row
   st.nmin = group_sum_int<PSL_WAVE>(n0);
   st.nmax = group_sum_int<PSL_WAVE>(n1);
   L = group_sum_int<PSL_WAVE>(n2);
+  tiny = group_sum_int<PSL_WAVE>(n3);
 }
 
 // decisions and propagation over one chunk of a long row
@@ -618,14 +662,15 @@ __device__ __forceinline__ void sweep_long_chunk(const Dev& d, const CandSink& s
   int* li = (int*)(lds + 2);
   if (threadIdx.x < PSL_WAVE) {
     RowStat st;
-    int L;
-    long_totals(d, lr, st, L);
+    int L, tiny;
+    long_totals(d, lr, st, L, tiny);
     if (threadIdx.x == 0) {
       lds[0] = st.minact;
       lds[1] = st.maxact;
       li[0] = st.nmin;
       li[1] = st.nmax;
       li[2] = L;
+      li[3] = tiny;
     }
   }
   __syncthreads();
@@ -638,15 +683,16 @@ __device__ __forceinline__ void sweep_long_chunk(const Dev& d, const CandSink& s
   int64_t s0 = d.rp[row];
   int len = d.rp[row + 1] - (int)s0;
   double lhs = d.lhs[row], rhs = d.rhs[row];
-  RowDec dec = decide_row(d.cfg, lhs, rhs, L, st.nmin, st.nmax, st.minact, st.maxact);
+  RowDec dec = decide_row(d.cfg, lhs, rhs, L, st.nmin, st.nmax, st.minact, st.maxact, li[3] != 0);
   if (ch.first == 0 && threadIdx.x == 0) d.rinf[row] = make_int2(st.nmin, st.nmax);
   bool uncap = false, mine = false;
   int aj = 0;
   double aa = 0.0;
   for (int p = 0; p < ch.npass; ++p) {
     int base = ch.first + p * PASS_LEN + (int)threadIdx.x * 8;
-    if (dec.prop) lane_prop_stream<8>(d, sk, row, true, s0, len, base, lhs, rhs, st, dec.single, uncap, mine, aj, aa);
-    else if (dec.code == RC_REDUNDANT) lane_drop_stream<8>(d, true, s0, len, base, lhs, rhs);
+    if (dec.prop)
+      lane_prop_stream<8>(d, sk, row, true, s0, len, base, lhs, rhs, st, dec.single, dec.force, uncap, mine, aj, aa);
+    if (dec.code == RC_REDUNDANT || is_forcing(dec.code)) lane_drop_stream<8>(d, true, s0, len, base, lhs, rhs);
   }
   if (dec.prop && dec.single && !dec.infeasible) {
     // the one active entry decides whether its row becomes bounds
@@ -662,7 +708,8 @@ __device__ __forceinline__ void sweep_long_chunk(const Dev& d, const CandSink& s
   } else if (ch.first == 0 && threadIdx.x == 0) {
     d.row_code[row] = dec.code;
     if (dec.infeasible) flag_infeasible(d, row_lp_of(d, row));
-    if (dec.code == RC_EMPTY || dec.code == RC_REDUNDANT) d.row_out[row] = row_out_of(dec.code, st);
+    if (dec.code == RC_EMPTY || dec.code == RC_REDUNDANT || is_forcing(dec.code))
+      d.row_out[row] = row_out_of(dec.code, st);
   }
 }
 
@@ -740,7 +787,8 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_long_finish_compact(Dev d) {
   bool on = d.row_on[lr.row] != 0;
   RowStat st;
   int L = 0;
-  if (on) long_totals(d, lr, st, L);
+  int tiny = 0;
+  if (on) long_totals(d, lr, st, L, tiny);
   else st.minact = 0.0;
   if (lane_id() == 0) {
     d.row_out[lr.row].v0 = st.minact;
@@ -936,6 +984,8 @@ __device__ __forceinline__ void emit_row(const Dev& d, int i, int round, Record*
   RowOut o = d.row_out[i];
   if (code == RC_EMPTY) *r = mkrec(REC_EMPTY_ROW, 0, round, i, -1, -1, o.v0, d.lhs[i], d.rhs[i], 0.0);
   else if (code == RC_REDUNDANT) *r = mkrec(REC_REDUNDANT_ROW, 0, round, i, -1, -1, o.v0, o.v1, d.lhs[i], d.rhs[i]);
+  else if (is_forcing(code))
+    *r = mkrec(REC_FORCING_ROW, code == RC_FORCE_MAX ? 1 : 0, round, i, -1, -1, o.v0, d.lhs[i], d.rhs[i], 0.0);
   else *r = mkrec(REC_SINGLETON_ROW, 0, round, i, o.j, -1, o.v0, d.lhs[i], d.rhs[i], 0.0);
   d.row_on[i] = 0;
   d.row_code[i] = RC_KEEP;
@@ -1099,6 +1149,14 @@ void launch_sweep(const Dev& d, const SweepGrid& g, int mode, hipStream_t s) {
     if (d.nlong > 0)
       hipLaunchKernelGGL(k_long_finish_compact, dim3((d.nlong + 3) / 4), dim3(PSL_BLOCK), 0, s, d);
   }
+}
+
+// every long row's removed-column constant and active length (row_out), from
+// the compaction-mode chunk partials
+void launch_long_consts(const Dev& d, hipStream_t s) {
+  if (d.nlong == 0) return;
+  launch_long_stats(d, MODE_COMPACT, s);
+  hipLaunchKernelGGL(k_long_finish_compact, dim3((d.nlong + 3) / 4), dim3(PSL_BLOCK), 0, s, d);
 }
 
 void launch_src(const Dev& d, const SweepGrid& g, hipStream_t s) {

@@ -25,7 +25,8 @@ RECORD_DTYPE = np.dtype([
 ])
 REC_NAMES = {1: "FIX_COL", 2: "EMPTY_COL", 3: "EMPTY_ROW", 4: "REDUNDANT_ROW",
              5: "SINGLETON_ROW", 6: "BOUND_CHANGE", 7: "PARALLEL_ROW", 8: "LEADER_SIDES",
-             9: "DUAL_FIX", 10: "FREE_SINGLETON", 11: "PARALLEL_COL", 12: "LEADER_BOUNDS"}
+             9: "DUAL_FIX", 10: "FREE_SINGLETON", 11: "PARALLEL_COL", 12: "LEADER_BOUNDS",
+             13: "FORCING_ROW"}
 
 
 class psl_lp(C.Structure):
@@ -41,7 +42,8 @@ class psl_settings(C.Structure):
                 ("par_tol", C.c_double), ("inf_value", C.c_double), ("coef_tol", C.c_double),
                 ("bin_thresholds", C.c_void_p), ("n_bins", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p), ("split_sweep", C.c_int32), ("enable_dual_fix", C.c_int32),
-                ("enable_free_singletons", C.c_int32), ("enable_parallel_cols", C.c_int32)]
+                ("enable_free_singletons", C.c_int32), ("enable_parallel_cols", C.c_int32),
+                ("enable_forcing_rows", C.c_int32)]
 
 
 class psl_stats(C.Structure):
@@ -49,7 +51,8 @@ class psl_stats(C.Structure):
                 ("nnz_in", C.c_int64), ("nnz_out", C.c_int64), ("m_out", C.c_int32), ("n_out", C.c_int32),
                 ("ms_ingest", C.c_double), ("ms_sweep", C.c_double), ("ms_decide", C.c_double),
                 ("ms_parallel", C.c_double), ("ms_compact", C.c_double), ("ms_total", C.c_double),
-                ("sweep_launches", C.c_int64), ("sweep_bytes", C.c_double), ("ms_long", C.c_double)]
+                ("sweep_launches", C.c_int64), ("sweep_bytes", C.c_double), ("ms_long", C.c_double),
+                ("alg_bytes", C.c_double), ("ingest_bytes", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

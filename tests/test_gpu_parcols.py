@@ -59,6 +59,15 @@ def test_hand_cases():
             assert_same(got, ref, f"hand {k} rows {rows_on}")
 
 
+def test_wrong_side_then_infinite_member():
+    from tests.test_oracle_parcols import nan_cases
+    for name, lp in nan_cases().items():
+        for rows_on in (0, 1):
+            got, ref = run_both(lp, enable_parallel_cols=1, enable_parallel_rows=rows_on)
+            assert not (ref.records["type"] == O.REC["PARALLEL_COL"]).any()
+            assert_same(got, ref, f"{name} rows {rows_on}")
+
+
 @pytest.mark.parametrize("seed", range(3))
 def test_medium_planted(seed):
     lp = with_parallel_copies(lpgen.make_lp(300, 450, seed=500 + seed, row_len=(2, 7), singleton=10, empty=5,

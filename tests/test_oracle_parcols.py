@@ -215,6 +215,33 @@ def test_merged_interval_past_inf_value_is_not_merged():
     assert (float(lbr["v"][2]), float(lbr["v"][3])) == (4e16 + 2 * 3e16 + 3 * -9e16, 5e16 + 2 * 4e16 + 3 * 1.0)
 
 
+def nan_cases():
+    """Groups x0, x1 = 2 x0, x2 = 3 x0 (coefficients and costs) whose partial
+    sum reaches inf_value on the wrong side before an infinite member term:
+    lower: 4e19 + 2 * 3e19 = 1e20 -> +inf, then 3 * -inf; upper: the mirror.
+    x2 is free and x4 (not proportional) is free too, so every row has two
+    infinite contributions on each side and no bound is tightened first."""
+    rows = [[(0, 1.0), (1, 2.0), (2, 3.0), (3, 1.0), (4, 1.0)],
+            [(0, 2.0), (1, 4.0), (2, 6.0), (3, -1.0), (4, -1.0)]]
+    c = [1.0, 2.0, 3.0, 0.5, 0.25]
+    lower = make(2, 5, rows, [-1e19, -INF], [INF, 1e19], [4e19, 3e19, -INF, -1, -INF], [5e19, 4e19, INF, 1, INF], c)
+    upper = make(2, 5, rows, [-1e19, -INF], [INF, 1e19], [-5e19, -4e19, -INF, -1, -INF], [-4e19, -3e19, INF, 1, INF],
+                 c)
+    return {"lower": lower, "upper": upper}
+
+
+def test_wrong_side_then_infinite_member_not_merged():
+    """The partial sum is +inf (-inf for the upper side) when the infinite
+    member's term comes: +inf + -inf is NaN, and the group is not merged
+    (no NaN bound may reach the reduced problem)."""
+    for name, lp in nan_cases().items():
+        res = O.presolve(lp, **PC, enable_parallel_rows=0)
+        assert not _recs(res, "PARALLEL_COL", "LEADER_BOUNDS"), name
+        assert res.result_name == "REDUCED" or res.result_name == "UNCHANGED", name
+        red = res.reduced
+        assert red["n"] == 5 and not np.isnan(red["lb"]).any() and not np.isnan(red["ub"]).any(), name
+
+
 @pytest.mark.parametrize("seed", range(300))
 def test_tiny_planted_replay_optimal(seed):
     lp = with_parallel_copies(lpgen.tiny(seed, finite_bounds=seed % 2 == 0), seed)
