@@ -318,6 +318,65 @@ void psl_presolve_free(psl_presolver *p);
  * NULL). Never NULL. */
 const char *psl_last_error(const psl_presolver *p);
 
+/* ---- Presolve without allocation --------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture
+ * of the surrounding work, tight serving loops, harnesses that forbid
+ * hipMalloc. psl_presolve_noalloc performs the same presolve as
+ * psl_presolve_create + psl_presolve_run (identical outcome, records and
+ * reduced problem) but keeps all of its device working memory (the copy of
+ * the LP and its transpose, round state, bins, candidates, records, the
+ * reduced problem before it is copied out) in one static device array of
+ * PSL_NOALLOC_SCRATCH_BYTES per device, which the library's code object
+ * reserves when it is loaded on a device and holds until the process ends.
+ * A call allocates and frees no device memory and no pinned host memory;
+ * its host-side bookkeeping uses the ordinary C++ heap. */
+#define PSL_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* Caller-owned DEVICE buffers for the results, sized for the INPUT LP (the
+ * reduced problem is never larger), and the sizes written on PSL_OK. */
+typedef struct {
+    int32_t *row_ptr;              /* [m + 1] reduced CSR                        */
+    int32_t *col_idx;              /* [nnz]                                      */
+    double *val;                   /* [nnz]                                      */
+    int32_t *col_ptr;              /* [n + 1] reduced transposed copy            */
+    int32_t *row_idx;              /* [nnz]                                      */
+    double *cval;                  /* [nnz]                                      */
+    double *lhs, *rhs;             /* [m]                                        */
+    double *lb, *ub, *c;           /* [n]                                        */
+    int32_t *row_map;              /* [m] reduced -> original row                */
+    int32_t *col_map;              /* [n] reduced -> original column             */
+    uint8_t *row_class;            /* [m] as in psl_reduced_view                 */
+    uint8_t *col_class;            /* [n]                                        */
+    psl_record *records;           /* [records_cap] postsolve records            */
+    int64_t records_cap;
+    /* outputs */
+    int32_t m_out, n_out;          /* reduced sizes (0 when infeasible or
+                                      unbounded: no reduced problem)             */
+    int64_t nnz_out;
+    double obj_offset;
+    int64_t records_out;           /* records written                            */
+} psl_noalloc_out;
+
+/* Presolve lp (host or device arrays, checked as at psl_presolve_create) with
+ * settings s (NULL: defaults; the stream orders all device work, and the call
+ * returns when it is complete) in the static scratch of device s->device, and
+ * copy the reduced problem and the records into out's buffers. The scratch
+ * set-up (its device address, the timing events) is done once per device, at
+ * the first call on it.
+ * Errors: PSL_ERR_INVALID (null arguments or output buffers, invalid LP or
+ * settings), PSL_ERR_CAPACITY (the LP's working set exceeds
+ * PSL_NOALLOC_SCRATCH_BYTES -- about 250 bytes per nonzero plus about 200 per
+ * row and column -- or its records exceed records_cap or the scratch left for
+ * them), PSL_ERR_DEVICE. The message is psl_last_error(NULL) on the calling
+ * thread. out's outputs are written only on PSL_OK.
+ * Concurrency: every call on one device uses that device's scratch, which
+ * keeps the last call's contents (a call clears the part it uses before
+ * reading it). The library takes a per-device lock for the whole call, so
+ * calls from several threads on one device run one after another; without
+ * that lock two overlapping calls on one GPU would race on the scratch. */
+psl_status psl_presolve_noalloc(const psl_lp *lp, const psl_settings *s, psl_noalloc_out *out, psl_result *res,
+                                psl_stats *stats);
+
 /* ---- Autotuning -------------------------------------------------------------
  * The launch shapes (bin thresholds, one or three sweep launches) change only
  * the speed. psl_tune times presolves of the given LPs (one batch when k > 1)

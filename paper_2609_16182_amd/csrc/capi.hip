@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -55,6 +56,16 @@ static psl_status dalloc(psl_presolver* p, T** out, size_t count) {
   size_t bytes = count * sizeof(T);
   if (bytes == 0) bytes = 64;
   bytes = (bytes + 255) & ~(size_t)255;
+  if (p->carve) {  // static-scratch mode: the next 256-byte aligned piece
+    if (bytes > p->carve_cap - p->carve_used) {
+      p->err = "the static scratch (" + std::to_string(p->carve_cap) + " bytes) is too small for this LP";
+      return PSL_ERR_CAPACITY;
+    }
+    *out = (T*)(p->carve + p->carve_used);
+    p->carve_used += bytes;
+    p->arena_bytes += bytes;
+    return PSL_OK;
+  }
   hipError_t e = hipMalloc(&ptr, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -136,6 +147,16 @@ template <class T>
 static psl_status halloc(psl_presolver* p, T** out, size_t count) {
   size_t bytes = count * sizeof(T);
   if (bytes == 0) bytes = 64;
+  if (p->hcarve) {  // static-scratch mode: host staging from a static buffer
+    bytes = (bytes + 63) & ~(size_t)63;
+    if (bytes > p->hcarve_cap - p->hcarve_used) {
+      p->err = "internal: static host staging too small";
+      return PSL_ERR_CAPACITY;
+    }
+    *out = (T*)(p->hcarve + p->hcarve_used);
+    p->hcarve_used += bytes;
+    return PSL_OK;
+  }
   if (hipHostMalloc((void**)out, bytes, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     *out = nullptr;
@@ -305,15 +326,21 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(r.col_class, n);
 
   // postsolve records: room for one record per row and two per column and
-  // some; grown in a run when needed
+  // some; grown in a run when needed (in static-scratch mode: the rest of
+  // the scratch, and a run needing more fails with PSL_ERR_CAPACITY)
   p->rec_cap = 2 * m + 4 * n + 1024;
+  if (p->carve) {
+    int64_t rest = (int64_t)((p->carve_cap - p->carve_used) / sizeof(Record));
+    if (rest > p->rec_cap) p->rec_cap = rest;
+  }
   ALLOC(p->rec, p->rec_cap);
 
   HALLOC(p->hflags, 1);
   HALLOC(p->htot, 64);
   HALLOC(p->hoff, 1);
   HALLOC(p->h_lpr, K + 1);
-  for (auto& e : p->ev) HIPCHK(p, hipEventCreate(&e));
+  if (!p->borrowed_events)
+    for (auto& e : p->ev) HIPCHK(p, hipEventCreate(&e));
 
   if (K > 1) {
     ALLOC(p->row_lp, m);
@@ -807,6 +834,7 @@ extern "C" psl_status psl_presolve_reload(psl_presolver* p, const psl_lp* lp) {
 
 static psl_status ensure_capacity(psl_presolver* p, int64_t need) {
   if (p->rec_count + need <= p->rec_cap) return PSL_OK;
+  if (p->carve) return fail(p, PSL_ERR_CAPACITY, "the postsolve records outgrow the static scratch");
   int64_t cap = std::max<int64_t>(2 * p->rec_cap, p->rec_count + need + 1024);
   Record* nr = nullptr;
   psl_status st = dalloc(p, &nr, cap);
@@ -1397,10 +1425,13 @@ extern "C" void psl_presolve_free(psl_presolver* p) {
   else (void)hipDeviceSynchronize();
   for (void* a : p->allocs) (void)hipFree(a);
   for (void* a : p->hallocs) (void)hipHostFree(a);
-  for (auto& e : p->ev)
-    if (e) (void)hipEventDestroy(e);
+  if (!p->borrowed_events)
+    for (auto& e : p->ev)
+      if (e) (void)hipEventDestroy(e);
   delete p;
 }
+
+void psl::set_create_error(const std::string& msg) { g_create_error = msg; }
 
 extern "C" const char* psl_last_error(const psl_presolver* p) {
   if (!p) return g_create_error.c_str();
@@ -1410,6 +1441,89 @@ extern "C" const char* psl_last_error(const psl_presolver* p) {
 // ---------------------------------------------------------------------------
 // batched presolve
 // ---------------------------------------------------------------------------
+// One presolve of lp with every device array carved from dev_scratch and the
+// host staging from host_stage (see psl_presolve_noalloc): create, run and a
+// copy of the reduced problem and the records into the caller's buffers, in
+// one call that allocates no device or pinned host memory.
+psl_status psl::engine_run_static(const psl_lp* lp, const psl_settings* s, unsigned char* dev_scratch,
+                                  size_t dev_bytes, unsigned char* host_stage, size_t host_bytes, hipEvent_t* ev,
+                                  psl_noalloc_out* out, psl_result* res, psl_stats* stats, std::string* err) {
+  std::unique_ptr<psl_presolver> h(new psl_presolver());
+  psl_presolver* p = h.get();
+  take_settings(p, s);
+  p->carve = dev_scratch;
+  p->carve_cap = dev_bytes;
+  p->hcarve = host_stage;
+  p->hcarve_cap = host_bytes;
+  p->borrowed_events = true;
+  for (int k = 0; k < 8; ++k) p->ev[k] = ev[k];
+  p->cap_m = lp->m;
+  p->cap_n = lp->n;
+  p->cap_nnz = lp->nnz;
+  p->cap_K = 1;
+  set_sizes(p, 1, lp->m, lp->n, lp->nnz);
+  psl_status st = setup_arena(p);
+  // the scratch keeps the previous call's contents, laid out for another
+  // LP: clear the part this LP uses, so it starts as fresh memory would
+  if (st == PSL_OK) fill_i32((int32_t*)dev_scratch, 0, (int64_t)(p->carve_used / 4), p->stream);
+  if (st == PSL_OK) st = ingest(p, lp);
+  psl_stats S{};
+  if (st == PSL_OK) st = run_engine(p, &S);
+  if (st == PSL_OK && p->rec_count > out->records_cap)
+    st = fail(p, PSL_ERR_CAPACITY, "records_cap (" + std::to_string(out->records_cap) + ") below the " +
+                                       std::to_string(p->rec_count) + " records of this presolve");
+  if (st == PSL_OK && has_reduced(p, 0)) {
+    psl_reduced_view v = reduced_view(p, 0);
+    hipStream_t q = p->stream;
+    auto cp = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+      return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, q) : hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    auto chain = [&](hipError_t x) {
+      if (e == hipSuccess) e = x;
+    };
+    chain(cp(out->row_ptr, v.row_ptr, (v.m + 1) * sizeof(int32_t)));
+    chain(cp(out->col_idx, v.col_idx, v.nnz * sizeof(int32_t)));
+    chain(cp(out->val, v.val, v.nnz * sizeof(double)));
+    chain(cp(out->col_ptr, v.col_ptr, (v.n + 1) * sizeof(int32_t)));
+    chain(cp(out->row_idx, v.row_idx, v.nnz * sizeof(int32_t)));
+    chain(cp(out->cval, v.cval, v.nnz * sizeof(double)));
+    chain(cp(out->lhs, v.lhs, v.m * sizeof(double)));
+    chain(cp(out->rhs, v.rhs, v.m * sizeof(double)));
+    chain(cp(out->lb, v.lb, v.n * sizeof(double)));
+    chain(cp(out->ub, v.ub, v.n * sizeof(double)));
+    chain(cp(out->c, v.c, v.n * sizeof(double)));
+    chain(cp(out->row_map, v.row_map, v.m * sizeof(int32_t)));
+    chain(cp(out->col_map, v.col_map, v.n * sizeof(int32_t)));
+    chain(cp(out->row_class, v.row_class, v.m));
+    chain(cp(out->col_class, v.col_class, v.n));
+    out->m_out = v.m;
+    out->n_out = v.n;
+    out->nnz_out = v.nnz;
+    out->obj_offset = v.obj_offset;
+    if (e != hipSuccess) st = fail(p, PSL_ERR_DEVICE, std::string("HIP error copying the reduced problem: ") +
+                                                          hipGetErrorString(e));
+  } else if (st == PSL_OK) {
+    out->m_out = out->n_out = 0;
+    out->nnz_out = 0;
+    out->obj_offset = 0.0;
+  }
+  if (st == PSL_OK && p->rec_count &&
+      hipMemcpyAsync(out->records, p->rec, p->rec_count * sizeof(Record), hipMemcpyDeviceToDevice, p->stream) !=
+          hipSuccess)
+    st = fail(p, PSL_ERR_DEVICE, "HIP error copying the records");
+  if (st == PSL_OK && hipStreamSynchronize(p->stream) != hipSuccess) st = fail(p, PSL_ERR_DEVICE, "HIP error");
+  if (st == PSL_OK) {
+    out->records_out = p->rec_count;
+    *res = p->result;
+    if (stats) *stats = S;
+  } else {
+    *err = p->err;
+    (void)hipStreamSynchronize(p->stream);
+  }
+  return st;
+}
+
 struct psl_batch {
   psl_presolver* p = nullptr;
 };

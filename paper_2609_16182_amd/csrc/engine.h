@@ -133,6 +133,15 @@ struct psl_presolver {
   int32_t* htot = nullptr;  // pinned [4] + offset
   double* hoff = nullptr;
 
+  // Static-scratch mode (psl_presolve_noalloc): device arrays are carved from
+  // one caller-provided region and host staging from a static buffer; the
+  // HIP events are borrowed. Nothing is allocated or freed by the handle.
+  unsigned char* carve = nullptr;
+  size_t carve_cap = 0, carve_used = 0;
+  unsigned char* hcarve = nullptr;
+  size_t hcarve_cap = 0, hcarve_used = 0;
+  bool borrowed_events = false;
+
   int state = 0;  // 0 loaded, 1 ran
   int sweep_mode = MODE_ROUND;  // 2: three launches by register class
   bool trace = false;  // PSL_TRACE=1: one line per round on stderr
@@ -193,6 +202,13 @@ struct HostCols {
 void postsolve_dual(const psl_record* rec, int64_t count, int32_t m, int32_t n, const std::vector<int32_t>& row_map,
                     const double* y_red, const HostCols& A, double* y, double* z);
 size_t engine_arena_bytes(const psl_presolver* p);
+// the message psl_last_error(NULL) returns on this thread
+void set_create_error(const std::string& msg);
+// one presolve in static scratch (psl_presolve_noalloc's work): device arrays
+// carved from dev_scratch, host staging from host_stage, the 8 events given
+psl_status engine_run_static(const psl_lp* lp, const psl_settings* s, unsigned char* dev_scratch, size_t dev_bytes,
+                             unsigned char* host_stage, size_t host_bytes, hipEvent_t* ev, psl_noalloc_out* out,
+                             psl_result* res, psl_stats* stats, std::string* err);
 // LP k's original rows / columns on the host (after a run; for postsolve)
 psl_status engine_host_rows(psl_presolver* p, int k, HostRows& A);
 psl_status engine_host_cols(psl_presolver* p, int k, HostCols& A);

@@ -84,6 +84,17 @@ class psl_ticket_info(C.Structure):
                 ("batch_lps", C.c_int32), ("slot", C.c_int32), ("stats", psl_stats)]
 
 
+class psl_noalloc_out(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("col_ptr", C.c_void_p), ("row_idx", C.c_void_p), ("cval", C.c_void_p),
+                ("lhs", C.c_void_p), ("rhs", C.c_void_p), ("lb", C.c_void_p), ("ub", C.c_void_p),
+                ("c", C.c_void_p), ("row_map", C.c_void_p), ("col_map", C.c_void_p),
+                ("row_class", C.c_void_p), ("col_class", C.c_void_p),
+                ("records", C.c_void_p), ("records_cap", C.c_int64),
+                ("m_out", C.c_int32), ("n_out", C.c_int32), ("nnz_out", C.c_int64),
+                ("obj_offset", C.c_double), ("records_out", C.c_int64)]
+
+
 class PslError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
@@ -122,6 +133,9 @@ def load(path=None):
     lib.psl_batch_reduced_problem.argtypes = [C.c_void_p, C.c_int32, C.POINTER(psl_reduced_view)]
     lib.psl_batch_records.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.c_void_p, C.c_int64]
     lib.psl_batch_postsolve.argtypes = [C.c_void_p, C.c_int32] + [C.c_void_p] * 6
+    lib.psl_presolve_noalloc.argtypes = [C.POINTER(psl_lp), C.POINTER(psl_settings), C.POINTER(psl_noalloc_out),
+                                         C.POINTER(C.c_int), C.POINTER(psl_stats)]
+    lib.psl_presolve_noalloc.restype = C.c_int
     lib.psl_tune.argtypes = [C.c_int32, C.c_void_p, C.POINTER(psl_settings), C.c_int32, C.POINTER(psl_tuning)]
     lib.psl_tune.restype = C.c_int
     lib.psl_batch_free.argtypes = [C.c_void_p]
@@ -251,6 +265,15 @@ def psl_postsolve(h, x_red, n, y_red=None, m=0):
     args, keep, out = _post_args(x_red, y_red, m, n)
     _check(load().psl_postsolve(h, *args), h)
     return out[0] if len(out) == 1 else out
+
+
+def psl_presolve_noalloc(lp: psl_lp, settings: psl_settings, out: psl_noalloc_out):
+    """One presolve in the library's static device scratch; results go into
+    the caller's device buffers named in `out`. Returns (result, stats)."""
+    res = C.c_int(0)
+    st = psl_stats()
+    _check(load().psl_presolve_noalloc(C.byref(lp), C.byref(settings), C.byref(out), C.byref(res), C.byref(st)))
+    return res.value, st
 
 
 def psl_presolve_free(h):
