@@ -83,7 +83,8 @@ typedef struct {
  *   feas_tol 1e-9, fix_tol 1e-9, min_improve 1e-7, par_tol 1e-9,
  *   inf_value 1e20, coef_tol 1e-9, bin thresholds from the tuner (NULL),
  *   device 0, stream NULL, split_sweep 0, enable_dual_fix 0,
- *   enable_free_singletons 0, enable_parallel_cols 0, enable_forcing_rows 0.
+ *   enable_free_singletons 0, enable_parallel_cols 0, enable_forcing_rows 0,
+ *   enable_doubletons 0.
  * bin_thresholds (optional, n_bins = 2 or 3): [0] the longest row swept by one
  * 64-lane wavefront (16..512, default 512); [1] positions per workgroup chunk
  * of longer rows (a power of two >= 2048, default 2048); [2] the longest row
@@ -161,6 +162,18 @@ typedef struct {
                                       the round, so the column decisions fix
                                       it). Rows with an active |a| < coef_tol
                                       are not forcing. 0 (default) or 1.       */
+    int32_t enable_doubletons;     /* 1: doubleton-equality substitution (the
+                                      doubleton-row explorer, section 2.1) once
+                                      per outer cycle after the parallel
+                                      passes: an alive row with lhs = rhs and
+                                      two active columns eliminates one,
+                                      x_k = (b - a_j x_j) / a_k, from its other
+                                      rows (fill-in on column j, rows rewritten
+                                      in place), costs and bounds; rows sharing
+                                      a column take turns, lowest first; a
+                                      column kept by a substitution takes part
+                                      in no other (DOUBLETON_ROW). 0 (default)
+                                      or 1.                                    */
 } psl_settings;
 
 /* Postsolve record: 48 bytes, emitted in the order (round, phase, index,
@@ -192,6 +205,11 @@ typedef struct {
  *                         rhs} (only with enable_forcing_rows; its columns'
  *                         BOUND_CHANGE and FIX_COL records follow in the same
  *                         round)
+ *   type 14 DOUBLETON_ROW i = the equality row, j = the kept column, k = the
+ *                         eliminated one; v = {a_ij, a_ik, b, c_k then}, b the
+ *                         row's side less its removed columns' constant (only
+ *                         with enable_doubletons; the bounds it moves to x_j
+ *                         follow as BOUND_CHANGE records from row i)
  * round 0 holds input fixings; each propagation round and each parallel-row
  * pass has its own round number. */
 typedef struct {

@@ -76,12 +76,15 @@ enum { RES_REDUCED = 0, RES_UNCHANGED = 1, RES_INFEASIBLE = 2, RES_UNBOUNDED = 3
  *  FORCING_ROW    i; side 0: the min activity reaches rhs (every active
  *                 column at the bound of its min contribution), 1: the max
  *                 activity reaches lhs; v = {that activity, lhs, rhs}
+ *  DOUBLETON_ROW  i = the equality row, j = the kept column, k = the
+ *                 eliminated one; v = {a_ij, a_ik, b (the row's side moved by
+ *                 its removed columns' constant), c_k (then)}
  */
 enum {
     REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
     REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
     REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10, REC_PARALLEL_COL = 11, REC_LEADER_BOUNDS = 12,
-    REC_FORCING_ROW = 13
+    REC_FORCING_ROW = 13, REC_DOUBLETON_ROW = 14
 };
 
 /* parallel columns are searched among columns stored with at most this many
@@ -99,6 +102,9 @@ struct or_handle {
     double *va;
     double *lhs, *rhs, *lb, *ub, *c, off;
     double *c0;  /* the input costs (c changes when a singleton is substituted) */
+    int32_t *ci0; /* the input matrix's entries (doubleton substitutions rewrite */
+    double *va0;  /* rows in place; the dual postsolve needs the input's)       */
+    uint8_t *col_mod; /* column kept by a doubleton substitution (entries changed) */
     or_settings s;
 
     uint8_t *row_on, *col_on;
@@ -238,6 +244,7 @@ static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s
     if (s->enable_free_singletons != 0 && s->enable_free_singletons != 1)
         return fail(h, "invalid free-singleton switch");
     if (s->enable_forcing_rows != 0 && s->enable_forcing_rows != 1) return fail(h, "invalid settings");
+    if (s->enable_doubletons != 0 && s->enable_doubletons != 1) return fail(h, "invalid settings");
     if (s->enable_parallel_cols != 0 && s->enable_parallel_cols != 1)
         return fail(h, "invalid parallel-column switch");
     if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return fail(h, "negative size");
@@ -280,9 +287,14 @@ static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s
     h->c = (double *)xcalloc((size_t)n, sizeof(double));
     h->c0 = (double *)xcalloc((size_t)n + 1, sizeof(double));
     if (m > 0) memcpy(h->rp, lp->row_ptr, ((size_t)m + 1) * sizeof(int32_t));
+    h->ci0 = (int32_t *)xcalloc((size_t)lp->nnz + 1, sizeof(int32_t));
+    h->va0 = (double *)xcalloc((size_t)lp->nnz + 1, sizeof(double));
+    h->col_mod = (uint8_t *)xcalloc((size_t)n + 1, 1);
     if (lp->nnz > 0) {
         memcpy(h->ci, lp->col_idx, (size_t)lp->nnz * sizeof(int32_t));
         memcpy(h->va, lp->val, (size_t)lp->nnz * sizeof(double));
+        memcpy(h->ci0, lp->col_idx, (size_t)lp->nnz * sizeof(int32_t));
+        memcpy(h->va0, lp->val, (size_t)lp->nnz * sizeof(double));
     }
     for (int32_t i = 0; i < m; ++i) {
         h->lhs[i] = canon_inf(lp->lhs[i], s->inf_value);
@@ -1118,6 +1130,235 @@ static void compact(or_handle *h) {
 /* driver                                                                     */
 /* ------------------------------------------------------------------------- */
 
+/* the matrix by columns from the (current) rows: rows ascending within a
+ * column */
+static void build_columns(or_handle *h) {
+    int32_t m = h->m, n = h->n;
+    memset(h->cp, 0, ((size_t)n + 1) * sizeof(int32_t));
+    for (int64_t k = 0; k < h->nnz; ++k) h->cp[h->ci[k] + 1]++;
+    for (int32_t j = 0; j < n; ++j) h->cp[j + 1] += h->cp[j];
+    int32_t *fill = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    for (int32_t j = 0; j < n; ++j) fill[j] = h->cp[j];
+    for (int32_t i = 0; i < m; ++i)
+        for (int32_t k = h->rp[i]; k < h->rp[i + 1]; ++k) {
+            int32_t q = fill[h->ci[k]]++;
+            h->ri[q] = i;
+            h->cva[q] = h->va[k];
+        }
+    free(fill);
+}
+
+/* ------------------------------------------------------------------------- */
+/* doubleton equalities (section 2.1, "Explorers": the doubleton-row explorer */
+/* uses an equality with two nonzeros to eliminate one of its variables)      */
+/* ------------------------------------------------------------------------- */
+
+/* position of column j in row i (ascending columns), or -1 */
+static int64_t find_in_row(const or_handle *h, int32_t i, int32_t j) {
+    int64_t lo = h->rp[i], hi = h->rp[i + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (h->ci[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < h->rp[i + 1] && h->ci[lo] == j ? lo : -1;
+}
+
+/* Row r loses column k and gains coefficient v on column j, in place: with j
+ * already in the row its coefficient becomes v and k's entry turns into a
+ * dead entry (column k, coefficient +0: k is removed, so the entry adds +0
+ * to every sum); otherwise k's entry is taken out and j inserted at its
+ * sorted place, the entries between moving by one. The row keeps its
+ * length. Returns 1 when j was inserted. */
+static int rewrite_row(or_handle *h, int32_t r, int32_t k, int32_t j, double v) {
+    int64_t pk = find_in_row(h, r, k), pj = find_in_row(h, r, j);
+    if (pj >= 0) {
+        h->va[pj] = v;
+        h->va[pk] = 0.0;
+        return 0;
+    }
+    if (j > k) {
+        int64_t q = pk;
+        while (q + 1 < h->rp[r + 1] && h->ci[q + 1] < j) {
+            h->ci[q] = h->ci[q + 1];
+            h->va[q] = h->va[q + 1];
+            q++;
+        }
+        h->ci[q] = j;
+        h->va[q] = v;
+    } else {
+        int64_t q = pk;
+        while (q > h->rp[r] && h->ci[q - 1] > j) {
+            h->ci[q] = h->ci[q - 1];
+            h->va[q] = h->va[q - 1];
+            q--;
+        }
+        h->ci[q] = j;
+        h->va[q] = v;
+    }
+    return 1;
+}
+
+/* The substitution pass (after the parallel passes of an outer cycle).
+ * Candidates: alive rows with lhs = rhs (finite) and exactly two active
+ * columns, both |a| >= coef_tol, neither a column kept by an earlier
+ * substitution (its entries were rewritten). The row is a_j x_j + a_k x_k = b
+ * with b = rhs - (the removed columns' constant). Eliminated: the column in
+ * fewer alive rows, then the one with the larger |a|, then the lower index;
+ * the other is kept. A candidate is dropped when rewriting one of its rows
+ * would cancel a coefficient to exactly zero. Conflicts: each candidate
+ * claims its two columns and every alive row of the eliminated column; it
+ * applies when it is the lowest-index claimant of all of them (the others
+ * wait for a later cycle). Applying (x_k = (b - a_j x_j) / a_k):
+ *   - each other alive row r of column k, with f = a_rk / a_k, gets
+ *     a_rj - f a_j on column j (inserted when absent) and loses k, its sides
+ *     moving by f b;
+ *   - x_k's bounds move to x_j: (b - a_k bound) / a_j for each finite bound
+ *     of k becomes a bound of j when strictly tighter (BOUND_CHANGE from row
+ *     i); a value with |v| >= inf_value gives none;
+ *   - costs: with r = c_k / a_k, c_j becomes c_j - r a_j; column k leaves at
+ *     the value b / a_k (its cost stays, so the offset gains c_k b / a_k);
+ *   - row i leaves.
+ * Records: DOUBLETON_ROW in ascending row order, then the transferred bounds
+ * in ascending column order (lower, then upper). Returns 1 when any
+ * substitution applied. */
+static int doubleton_pass(or_handle *h) {
+    const or_settings *s = &h->s;
+    int32_t m = h->m, n = h->n;
+    int64_t maxlen = 1;
+    for (int32_t i = 0; i < m; ++i)
+        if (h->rp[i + 1] - h->rp[i] > maxlen) maxlen = h->rp[i + 1] - h->rp[i];
+    int32_t *cols = (int32_t *)xcalloc((size_t)maxlen, sizeof(int32_t));
+    double *vals = (double *)xcalloc((size_t)maxlen, sizeof(double));
+    int32_t *cj = (int32_t *)xcalloc((size_t)m + 1, sizeof(int32_t));
+    int32_t *ck = (int32_t *)xcalloc((size_t)m + 1, sizeof(int32_t));
+    double *aj = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    double *ak = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    double *bb = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    int32_t *row_claim = (int32_t *)xcalloc((size_t)m + 1, sizeof(int32_t));
+    int32_t *col_claim = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+    for (int32_t i = 0; i < m; ++i) { cj[i] = -1; row_claim[i] = INT32_MAX; }
+    for (int32_t j = 0; j < n; ++j) col_claim[j] = INT32_MAX;
+
+    /* candidates */
+    for (int32_t i = 0; i < m; ++i) {
+        if (!h->row_on[i] || h->lhs[i] != h->rhs[i] || isinf(h->rhs[i])) continue;
+        if (active_entries(h, i, cols, vals) != 2) continue;
+        if (fabs(vals[0]) < s->coef_tol || fabs(vals[1]) < s->coef_tol) continue;
+        if (h->col_mod[cols[0]] || h->col_mod[cols[1]]) continue;
+        int e;  /* index of the eliminated one among the two */
+        int32_t l0 = h->col_len[cols[0]], l1 = h->col_len[cols[1]];
+        if (l0 != l1) e = l0 < l1 ? 0 : 1;
+        else if (fabs(vals[0]) != fabs(vals[1])) e = fabs(vals[0]) > fabs(vals[1]) ? 0 : 1;
+        else e = 0;  /* the lower column index */
+        int32_t k = cols[e], j = cols[1 - e];
+        double a_k = vals[e], a_j = vals[1 - e];
+        /* no rewritten coefficient may cancel to zero */
+        int cancels = 0;
+        for (int32_t q = h->cp[k]; q < h->cp[k + 1] && !cancels; ++q) {
+            int32_t r = h->ri[q];
+            if (r == i || !h->row_on[r]) continue;
+            int64_t pj = find_in_row(h, r, j);
+            if (pj >= 0 && h->va[pj] - (h->cva[q] / a_k) * a_j == 0.0) cancels = 1;
+        }
+        if (cancels) continue;
+        cj[i] = j; ck[i] = k; aj[i] = a_j; ak[i] = a_k;
+        bb[i] = side_minus(h->rhs[i], removed_constant(h, i, vals));
+    }
+    /* claims */
+    for (int32_t i = 0; i < m; ++i) {
+        if (cj[i] < 0) continue;
+        if (i < col_claim[cj[i]]) col_claim[cj[i]] = i;
+        if (i < col_claim[ck[i]]) col_claim[ck[i]] = i;
+        for (int32_t q = h->cp[ck[i]]; q < h->cp[ck[i] + 1]; ++q) {
+            int32_t r = h->ri[q];
+            if (h->row_on[r] && i < row_claim[r]) row_claim[r] = i;
+        }
+    }
+    int any = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        if (cj[i] < 0) continue;
+        int own = col_claim[cj[i]] == i && col_claim[ck[i]] == i;
+        for (int32_t q = h->cp[ck[i]]; q < h->cp[ck[i] + 1] && own; ++q) {
+            int32_t r = h->ri[q];
+            if (h->row_on[r] && row_claim[r] != i) own = 0;
+        }
+        if (!own) { cj[i] = -1; continue; }
+        any = 1;
+        push(h, REC_DOUBLETON_ROW, 0, i, cj[i], ck[i], aj[i], ak[i], bb[i], h->c[ck[i]]);
+    }
+    if (!any) goto done;
+
+    /* transferred bounds of the kept columns, ascending column order */
+    {
+        double *tlo = (double *)xcalloc((size_t)n + 1, sizeof(double));
+        double *thi = (double *)xcalloc((size_t)n + 1, sizeof(double));
+        int32_t *by = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
+        for (int32_t j = 0; j < n; ++j) by[j] = -1;
+        for (int32_t i = 0; i < m; ++i) {
+            if (cj[i] < 0) continue;
+            int32_t j = cj[i], k = ck[i];
+            double lo = -INFINITY, hi = INFINITY;
+            /* x_j = (b - a_k x_k) / a_j is decreasing in x_k when a_k / a_j > 0 */
+            int dec = (ak[i] > 0) == (aj[i] > 0);
+            double from_lb = isinf(h->lb[k]) ? (dec ? INFINITY : -INFINITY)
+                                             : pos0((bb[i] - ak[i] * h->lb[k]) / aj[i]);
+            double from_ub = isinf(h->ub[k]) ? (dec ? -INFINITY : INFINITY)
+                                             : pos0((bb[i] - ak[i] * h->ub[k]) / aj[i]);
+            if (dec) { lo = from_ub; hi = from_lb; }
+            else { lo = from_lb; hi = from_ub; }
+            if (fabs(lo) >= s->inf_value) lo = -INFINITY;
+            if (fabs(hi) >= s->inf_value) hi = INFINITY;
+            tlo[j] = lo; thi[j] = hi; by[j] = i;
+        }
+        for (int32_t j = 0; j < n; ++j) {
+            int32_t i = by[j];
+            if (i < 0) continue;
+            if (tlo[j] > h->lb[j]) {
+                push(h, REC_BOUND_CHANGE, 0, -1, j, i, h->lb[j], tlo[j], aj[i], 0);
+                h->lb[j] = tlo[j];
+                h->lsrc[j] = h->lsrc[j] == -1 || h->lsrc[j] == i ? i : -2;
+            }
+            if (thi[j] < h->ub[j]) {
+                push(h, REC_BOUND_CHANGE, 1, -1, j, i, h->ub[j], thi[j], aj[i], 0);
+                h->ub[j] = thi[j];
+                h->usrc[j] = h->usrc[j] == -1 || h->usrc[j] == i ? i : -2;
+            }
+            if (!isinf(h->lb[j]) && !isinf(h->ub[j]) && h->lb[j] > h->ub[j] + tol_of(s, h->ub[j]))
+                h->result = RES_INFEASIBLE;
+        }
+        free(tlo); free(thi); free(by);
+    }
+    /* rows, costs, the eliminated columns, the equality rows */
+    for (int32_t i = 0; i < m; ++i) {
+        if (cj[i] < 0) continue;
+        int32_t j = cj[i], k = ck[i];
+        for (int32_t q = h->cp[k]; q < h->cp[k + 1]; ++q) {
+            int32_t r = h->ri[q];
+            if (r == i || !h->row_on[r]) continue;
+            double f = h->cva[q] / ak[i];
+            int64_t pj = find_in_row(h, r, j);
+            double v = (pj >= 0 ? h->va[pj] : 0.0) - f * aj[i];
+            double sh = f * bb[i];
+            h->lhs[r] = side_minus(h->lhs[r], sh);
+            h->rhs[r] = side_minus(h->rhs[r], sh);
+            h->col_len[j] += rewrite_row(h, r, k, j, v);
+        }
+        double rc = h->c[k] / ak[i];
+        h->c[j] = pos0(h->c[j] - rc * aj[i]);
+        h->col_mod[j] = 1;
+        drop_row(h, i);
+        double vk = pos0(bb[i] / ak[i]);
+        h->col_on[k] = 0;
+        h->lb[k] = h->ub[k] = vk;
+    }
+    build_columns(h);
+done:
+    free(cols); free(vals); free(cj); free(ck); free(aj); free(ak); free(bb);
+    free(row_claim); free(col_claim);
+    return any;
+}
+
 int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     or_handle *h = (or_handle *)xcalloc(1, sizeof(or_handle));
     *out = h;
@@ -1135,19 +1376,7 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
     h->cp = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     h->ri = (int32_t *)xcalloc((size_t)h->nnz + 1, sizeof(int32_t));
     h->cva = (double *)xcalloc((size_t)h->nnz + 1, sizeof(double));
-    for (int64_t k = 0; k < h->nnz; ++k) h->cp[h->ci[k] + 1]++;
-    for (int32_t j = 0; j < n; ++j) h->cp[j + 1] += h->cp[j];
-    {
-        int32_t *fill = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
-        for (int32_t j = 0; j < n; ++j) fill[j] = h->cp[j];
-        for (int32_t i = 0; i < m; ++i)
-            for (int32_t k = h->rp[i]; k < h->rp[i + 1]; ++k) {
-                int32_t q = fill[h->ci[k]]++;
-                h->ri[q] = i;
-                h->cva[q] = h->va[k];
-            }
-        free(fill);
-    }
+    build_columns(h);
     h->lsrc = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     h->usrc = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     for (int32_t j = 0; j < n; ++j) {
@@ -1200,11 +1429,15 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
             if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
             if (!changed) break;
         }
-        if (stop || (!s->enable_parallel_rows && !s->enable_parallel_cols)) break;
+        if (stop || (!s->enable_parallel_rows && !s->enable_parallel_cols && !s->enable_doubletons)) break;
         h->round++;
         int merged = s->enable_parallel_rows ? parallel_rows(h) : 0;
         if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
         if (s->enable_parallel_cols) merged |= parallel_cols(h);
+        if (s->enable_doubletons) {
+            merged |= doubleton_pass(h);
+            if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
+        }
         if (!merged) break;
     }
     free(w.lb_s); free(w.ub_s); free(w.lb_n); free(w.ub_n);
@@ -1312,6 +1545,9 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
         const or_record *r = &h->rec[t];
         if (r->type == REC_LEADER_BOUNDS) {
             split_group(h, t, x);
+        } else if (r->type == REC_DOUBLETON_ROW) {
+            /* the equality row a_j x_j + a_k x_k = b gives the eliminated x_k */
+            x[r->k] = (r->v[2] - r->v[0] * x[r->j]) / r->v[1];
         } else if (r->type == REC_FREE_SINGLETON) {
             double rest = 0.0;
             for (int64_t k = h->rp[r->i]; k < h->rp[r->i + 1]; ++k)
@@ -1362,6 +1598,34 @@ static double col_red_cost(const or_handle *h, const int32_t *cp, const int32_t 
     return h->c0[j] - s;
 }
 
+/* The dual a doubleton substitution gives its row (r = the DOUBLETON_ROW
+ * record): with x_k between its bounds, z_k = c_k - a_k'y = 0, i.e.
+ * (c_k - sum over the input's column k of a_rk y_r, row i left out) / a_ik,
+ * c_k the cost x_k had then. Column k's entries were never rewritten before
+ * (only kept columns are), so the input's column is the one of that time. */
+static double doubleton_dual(const int32_t *cp, const int32_t *ri, const double *cva, const double *y,
+                             const or_record *r) {
+    double ay = 0.0;
+    for (int32_t q = cp[r->k]; q < cp[r->k + 1]; ++q)
+        if (ri[q] != r->i) ay = ay + cva[q] * y[ri[q]];
+    return (r->v[3] - ay) / r->v[1];
+}
+
+/* Reduced cost of column j in the problem of the time being undone: the
+ * input's column j, and, while the substitution that kept j is not undone
+ * yet, its rows carry the row's multiplier too (each rewritten row r is
+ * r - f_r row_i, and the cost c_j - (c_k/a_k) a_j): z_j - a_ij * (that
+ * row's dual as the substitution would give it now). */
+static double cur_red_cost(const or_handle *h, const int32_t *cp, const int32_t *ri, const double *cva,
+                           const double *y, const int64_t *pending, int32_t j) {
+    double z = col_red_cost(h, cp, ri, cva, y, j);
+    if (pending[j] >= 0) {
+        const or_record *r = &h->rec[pending[j]];
+        z = z - r->v[0] * doubleton_dual(cp, ri, cva, y, r);
+    }
+    return z;
+}
+
 int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_red,
                       double *x, double *y, double *z) {
     if (h->result >= RES_INFEASIBLE) return 1;
@@ -1373,30 +1637,41 @@ int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_r
     int32_t *cp = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     int32_t *ri = (int32_t *)xcalloc((size_t)h->nnz, sizeof(int32_t));
     double *cva = (double *)xcalloc((size_t)h->nnz, sizeof(double));
-    for (int64_t k = 0; k < h->nnz; ++k) cp[h->ci[k] + 1]++;
+    for (int64_t k = 0; k < h->nnz; ++k) cp[h->ci0[k] + 1]++;
     for (int32_t j = 0; j < n; ++j) cp[j + 1] += cp[j];
     int32_t *fill = (int32_t *)xcalloc((size_t)n + 1, sizeof(int32_t));
     for (int32_t j = 0; j < n; ++j) fill[j] = cp[j];
     for (int32_t i = 0; i < m; ++i)
         for (int32_t k = h->rp[i]; k < h->rp[i + 1]; ++k) {
-            int32_t q = fill[h->ci[k]]++;
+            int32_t q = fill[h->ci0[k]]++;
             ri[q] = i;
-            cva[q] = h->va[k];
+            cva[q] = h->va0[k];
         }
-    /* lambda of every row removed as parallel (a_r = lambda a_leader) */
+    /* lambda of every row removed as parallel (a_r = lambda a_leader); the
+     * doubleton substitution that kept each column, not undone yet */
     double *lam = (double *)xcalloc((size_t)m + 1, sizeof(double));
-    for (int64_t t = 0; t < h->nrec; ++t)
+    int64_t *pending = (int64_t *)xcalloc((size_t)n + 1, sizeof(int64_t));
+    for (int32_t j = 0; j < n; ++j) pending[j] = -1;
+    for (int64_t t = 0; t < h->nrec; ++t) {
         if (h->rec[t].type == REC_PARALLEL_ROW) lam[h->rec[t].i] = h->rec[t].v[0];
+        if (h->rec[t].type == REC_DOUBLETON_ROW) pending[h->rec[t].j] = t;
+    }
     for (int64_t t = h->nrec - 1; t >= 0; --t) {
         const or_record *r = &h->rec[t];
         if (r->type == REC_BOUND_CHANGE) {
             int32_t j = r->j, k = r->k;
             if (k < 0) continue;
-            double zj = col_red_cost(h, cp, ri, cva, y, j);
+            double zj = cur_red_cost(h, cp, ri, cva, y, pending, j);
             if ((r->side == 0 && zj > 0.0) || (r->side == 1 && zj < 0.0)) y[k] = y[k] + zj / r->v[2];
         } else if (r->type == REC_FREE_SINGLETON) {
             /* the substituted column is free: z_j = 0 gives the row's dual */
             y[r->i] = r->v[3] / r->v[0];
+        } else if (r->type == REC_DOUBLETON_ROW) {
+            /* the row's dual: the part that makes z_k = 0, added to what a
+             * binding bound moved from x_k to x_j gave it (undone just before;
+             * then z_j = 0 and x_k sits at its bound) */
+            y[r->i] = y[r->i] + doubleton_dual(cp, ri, cva, y, r);
+            pending[r->j] = -1;
         } else if (r->type == REC_LEADER_SIDES) {
             int32_t L = r->i;
             double yl = y[L];
@@ -1408,7 +1683,7 @@ int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_r
         }
     }
     for (int32_t j = 0; j < n; ++j) z[j] = col_red_cost(h, cp, ri, cva, y, j);
-    free(cp); free(ri); free(cva); free(fill); free(lam);
+    free(cp); free(ri); free(cva); free(fill); free(lam); free(pending);
     return 0;
 }
 
@@ -1420,6 +1695,7 @@ void or_free(or_handle *h) {
     if (!h) return;
     free(h->rp); free(h->ci); free(h->va); free(h->lhs); free(h->rhs);
     free(h->lb); free(h->ub); free(h->c); free(h->c0); free(h->row_on); free(h->col_on); free(h->lsrc); free(h->usrc);
+    free(h->ci0); free(h->va0); free(h->col_mod);
     free(h->cp); free(h->ri); free(h->cva);
     free(h->col_len); free(h->rec);
     free(h->r_rp); free(h->r_ci); free(h->r_va); free(h->r_cp); free(h->r_ri); free(h->r_cva);

@@ -36,6 +36,7 @@ typedef struct {
     int32_t enable_free_singletons;  /* 1: zero-cost free column singletons */
     int32_t enable_parallel_cols;    /* 1: parallel columns in the parallel pass */
     int32_t enable_forcing_rows;     /* 1: forcing rows in every round */
+    int32_t enable_doubletons;       /* 1: doubleton-equality substitution pass */
 } or_settings;
 
 /* 48-byte postsolve record; the field meaning per type is listed in the .c */

@@ -105,6 +105,7 @@ extern "C" void psl_settings_default(psl_settings* s) {
   s->enable_free_singletons = 0;
   s->enable_parallel_cols = 0;
   s->enable_forcing_rows = 0;
+  s->enable_doubletons = 0;
 }
 
 std::string psl::check_settings(const psl_settings* s) {
@@ -118,6 +119,7 @@ std::string psl::check_settings(const psl_settings* s) {
     return "enable_free_singletons must be 0 or 1";
   if (s->enable_parallel_cols != 0 && s->enable_parallel_cols != 1) return "enable_parallel_cols must be 0 or 1";
   if (s->enable_forcing_rows != 0 && s->enable_forcing_rows != 1) return "enable_forcing_rows must be 0 or 1";
+  if (s->enable_doubletons != 0 && s->enable_doubletons != 1) return "enable_doubletons must be 0 or 1";
   if (s->bin_thresholds) {
     if (s->n_bins != 2 && s->n_bins != 3) return "bin_thresholds needs n_bins = 2 or 3";
     int a = s->bin_thresholds[0], b = s->bin_thresholds[1];

@@ -26,7 +26,7 @@ RECORD_DTYPE = np.dtype([
 REC_NAMES = {1: "FIX_COL", 2: "EMPTY_COL", 3: "EMPTY_ROW", 4: "REDUNDANT_ROW",
              5: "SINGLETON_ROW", 6: "BOUND_CHANGE", 7: "PARALLEL_ROW", 8: "LEADER_SIDES",
              9: "DUAL_FIX", 10: "FREE_SINGLETON", 11: "PARALLEL_COL", 12: "LEADER_BOUNDS",
-             13: "FORCING_ROW"}
+             13: "FORCING_ROW", 14: "DOUBLETON_ROW"}
 
 
 class psl_lp(C.Structure):
@@ -43,7 +43,7 @@ class psl_settings(C.Structure):
                 ("bin_thresholds", C.c_void_p), ("n_bins", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p), ("split_sweep", C.c_int32), ("enable_dual_fix", C.c_int32),
                 ("enable_free_singletons", C.c_int32), ("enable_parallel_cols", C.c_int32),
-                ("enable_forcing_rows", C.c_int32)]
+                ("enable_forcing_rows", C.c_int32), ("enable_doubletons", C.c_int32)]
 
 
 class psl_stats(C.Structure):
