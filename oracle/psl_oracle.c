@@ -1585,8 +1585,11 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
 /*       bound changes it sourced), fixed, empty and dual-fixed columns take  */
 /*       their reduced cost from z = c - A'y (a dual-fixed column has no      */
 /*       locks towards its bound, so the active rows' multipliers can only    */
-/*       push z_j further to that bound's sign); a row removed with a free    */
-/*       zero-cost singleton keeps y_i = c_j / a_ij = 0, so z_j = 0.          */
+/*       push z_j further to that bound's sign).                              */
+/*   FREE_SINGLETON  the row's dual is y_i = c_j / a_ij (z_j = 0 for the free */
+/*       column), set before the pass: after the substitution every other    */
+/*       column of the row costs c_k - y_i a_ik, so the reduced costs that   */
+/*       later records read already hold the row's share.                     */
 /* Every z_j = c_j - sum_i a_ij y_i is summed over the column's rows in      */
 /* ascending order, left to right.                                            */
 /* ------------------------------------------------------------------------- */
@@ -1655,6 +1658,10 @@ int or_postsolve_dual(const or_handle *h, const double *x_red, const double *y_r
     for (int64_t t = 0; t < h->nrec; ++t) {
         if (h->rec[t].type == REC_PARALLEL_ROW) lam[h->rec[t].i] = h->rec[t].v[0];
         if (h->rec[t].type == REC_DOUBLETON_ROW) pending[h->rec[t].j] = t;
+        /* a row substituted into the objective has the dual c_j / a_ij from
+         * the moment it leaves: the costs the later problems carry are
+         * c_k - y_i a_ik, so the reduced costs read while undoing them see it */
+        if (h->rec[t].type == REC_FREE_SINGLETON) y[h->rec[t].i] = h->rec[t].v[3] / h->rec[t].v[0];
     }
     for (int64_t t = h->nrec - 1; t >= 0; --t) {
         const or_record *r = &h->rec[t];

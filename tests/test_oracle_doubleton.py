@@ -196,6 +196,31 @@ def test_tiny_planted_bruteforce_and_kkt(seed):
     assert not bad, bad[:5]
 
 
+ALL = dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1, enable_forcing_rows=1)
+
+
+@pytest.mark.parametrize("seed", range(200))
+def test_tiny_planted_every_reduction_kkt(seed):
+    """The planted family with every optional reduction: the postsolved
+    (x, y, z) of a HiGHS optimum of the reduced LP is optimal for the input
+    (the doubleton rows often become singleton rows after a substitution into
+    the objective, so the dual of a substituted row has to reach them)."""
+    lp = with_doubletons(lpgen.tiny(seed, finite_bounds=seed % 2 == 0), seed)
+    res = O.presolve(lp, **DB, **ALL)
+    if res.result_name not in ("REDUCED", "UNCHANGED"):
+        assert highs(lp)[0] in ("infeasible", "unbounded")
+        return
+    red = reduced_lp(res.reduced)
+    st, xr, yr = highs_duals(red)
+    if st == "empty":
+        xr, yr = np.zeros(0), np.zeros(red["m"])
+    elif st != "optimal":
+        return
+    x, y, z = res.postsolve_dual(xr, yr)
+    bad = kkt_violations(lp, x, y, z)
+    assert not bad, bad[:5]
+
+
 def test_tiny_planted_fire():
     fired = sum(len(_recs(O.presolve(with_doubletons(lpgen.tiny(s, finite_bounds=s < 120), s), **DB),
                           "DOUBLETON_ROW")) for s in range(200))

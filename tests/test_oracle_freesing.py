@@ -230,6 +230,28 @@ def test_substitution_into_the_objective():
     _check_optimal(lp, res)
 
 
+def test_dual_of_a_substituted_row_in_later_rounds():
+    """min 2 x0 - x1 + 2 x2 s.t. 0.25 <= x0 + 2 x1 <= 1.75 (row 0), x2 = 0.25
+    (row 1), 3 x0 - 2 x2 = -2.75 (row 2), 0.5 x0 - x2 = -0.625 (row 3),
+    x0 in [-2, 2], x1 free, x2 in [0, 1]. Round 1 fixes x2 = 0.25 and
+    substitutes the free x1 out of row 0 (y0 = -1/2, c0 becomes 2.5); round 2
+    fixes x0 = -0.75 from rows 2 and 3, whose dual must carry x0's cost as it
+    was then (2.5). The optimum x = (-0.75, 1.25, 0.25) has every column
+    strictly inside its bounds, so z = 0, and y0 = c1 / 2 = -1/2."""
+    lp = make(4, 3, [[(0, 1.0), (1, 2.0)], [(2, 1.0)], [(0, 3.0), (2, -2.0)], [(0, 0.5), (2, -1.0)]],
+              [0.25, 0.25, -2.75, -0.625], [1.75, 0.25, -2.75, -0.625], [-2.0, -INF, 0.0], [2.0, INF, 1.0],
+              [2.0, -1.0, 2.0])
+    res = O.presolve(lp, **FS)
+    fs = _fs(res)
+    assert [(int(r["i"]), int(r["j"]), int(r["side"]), int(r["round"])) for r in fs] == [(0, 1, 2, 1)]
+    assert res.reduced["n"] == 0
+    x, y, z = res.postsolve_dual(np.zeros(0), np.zeros(0))
+    assert np.allclose(x, [-0.75, 1.25, 0.25], rtol=0, atol=1e-12)
+    assert y[0] == -0.5
+    assert np.allclose(z, 0.0, rtol=0, atol=1e-12), z
+    assert not kkt_violations(lp, x, y, z)
+
+
 def test_rows_sharing_a_column_take_turns():
     """x0 (row 0: x0 + x2 = 3) and x1 (row 1: x1 + x2 = 5) are free with cost
     1; both substitutions would change c2, so row 0 (the lowest) goes in
