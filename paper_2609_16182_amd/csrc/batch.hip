@@ -170,6 +170,11 @@ __global__ void k_rec_gather(Dev d, const Record* rec, const uint32_t* keys, con
       r.j = local_idx(r.j, i0);
       r.k = local_idx(r.k, i0);
       break;
+    case REC_DOUBLETON_ROW:
+      r.i = local_idx(r.i, i0);
+      r.j = local_idx(r.j, j0);
+      r.k = local_idx(r.k, j0);
+      break;
     default:
       r.i = local_idx(r.i, i0);
       break;

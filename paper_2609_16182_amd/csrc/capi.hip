@@ -279,6 +279,23 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->par.hacc, 4 * p->long_cap);
   ALLOC(p->par.lam, m);
   p->par.lpt = nullptr;
+  if (p->s.enable_doubletons) {
+    ALLOC(p->dbl.list, m);
+    ALLOC(p->dbl.cj, m);
+    ALLOC(p->dbl.ck, m);
+    ALLOC(p->dbl.aj, m);
+    ALLOC(p->dbl.ak, m);
+    ALLOC(p->dbl.b, m);
+    ALLOC(p->dbl.row_claim, m);
+    ALLOC(p->dbl.col_claim, n);
+    ALLOC(p->dbl.col_mod, n);
+    ALLOC(p->dbl.by, n);
+    ALLOC(p->dbl.tb, n);
+    ALLOC(p->dbl.total, 2);
+    ALLOC(p->cp0, n + 1);
+    ALLOC(p->ri0, N);
+    ALLOC(p->cva0, N);
+  }
   if (p->s.enable_parallel_cols) {
     ALLOC(p->pc.key, n);
     ALLOC(p->pc.keys, n);
@@ -619,6 +636,15 @@ static psl_status ingest_rest(psl_presolver* p) {
   p->cmp.colid = p->colid;
   d.colid = p->colid;
   list_dense_cols(d, st);
+  if (p->s.enable_doubletons) {
+    // the input's transposed copy for the dual postsolve; no column kept yet
+    HIPCHK(p, hipMemcpyAsync(p->cp0, d.cp, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (N) {
+      HIPCHK(p, hipMemcpyAsync(p->ri0, d.ri, N * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+      HIPCHK(p, hipMemcpyAsync(p->cva0, d.cva, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    launch_doubleton_init(d, p->dbl, st);
+  }
 
   // parallel-row table: one slice of >= 2 m_k slots per LP
   if (p->K == 1) {
@@ -1088,7 +1114,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     for (auto& L : p->lst)
       if (L.phase != LP_DONE) ++npar;
     if (npar == 0) break;
-    if (!s.enable_parallel_rows && !s.enable_parallel_cols) {
+    if (!s.enable_parallel_rows && !s.enable_parallel_cols && !s.enable_doubletons) {
       for (auto& L : p->lst) L.phase = LP_DONE;
       break;
     }
@@ -1099,7 +1125,8 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
         if (B) p->h_round[k] = p->lst[k].rounds;
       }
     e = use_full_view(p);
-    if (e == PSL_OK) e = ensure_capacity(p, m + n + 16);  // row records, then column records
+    // row records, then column records (and a substitution pass's)
+    if (e == PSL_OK) e = ensure_capacity(p, (s.enable_doubletons ? 2 * m + 3 * n : m + n) + 16);
     if (e == PSL_OK) e = begin_lp_round(p);
     if (e != PSL_OK) return e;
     HIPCHK(p, hipEventRecord(p->ev[4], st));
@@ -1121,10 +1148,26 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     // parallel columns on the rows the row pass left (an LP it found
     // infeasible has stopped)
     if (s.enable_parallel_cols) launch_par_cols(d, p->pc, p->rec_count, round, p->ws, st);
+    if (s.enable_doubletons) {
+      // active lengths and removed-column constants after the parallel
+      // passes (row_out), then the substitutions
+      launch_long_stats(d, MODE_COMPACT, st);
+      launch_sweep(d, p->grid, MODE_COMPACT, st);
+      launch_doubletons(d, p->dbl, p->rec_count, round, p->ws, st);
+    }
     HIPCHK(p, hipEventRecord(p->ev[5], st));
     e = queue_lp_read(p, false);
     if (e == PSL_OK) e = read_flags(p);
     if (e != PSL_OK) return e;
+    if (s.enable_doubletons && p->hflags->dbl_applied) {
+      // rows were rewritten: the transposed copy (and what hangs on it) again
+      p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.cnt, p->isc, p->red.val, st);
+      p->cmp.colid = p->colid;
+      d.colid = p->colid;
+      list_dense_cols(d, st);
+      launch_doubleton_relock(d, p->dbl, st);
+      S.alg_bytes += 36.0 * (double)p->nnz;
+    }
     par_ms += elapsed(p, 4, 5);
     // keys and table per row, one pass over the positions, the records
     S.alg_bytes += 40.0 * m + 12.0 * (double)p->nnz + 48.0 * p->hflags->round_total;
@@ -1359,14 +1402,18 @@ static psl_status host_cols(psl_presolver* p, int k, HostCols& A) {
   int64_t n = c1 - c0;
   A.cp.resize(n + 1);
   A.c.resize(n);
-  HIPCHK(p, hipMemcpy(A.cp.data(), p->d.cp + c0, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+  // substitutions rewrite the rows: the dual postsolve reads the input's columns
+  const int32_t* dcp = p->cp0 ? p->cp0 : p->d.cp;
+  const int32_t* dri = p->ri0 ? p->ri0 : p->d.ri;
+  const double* dcva = p->cva0 ? p->cva0 : p->d.cva;
+  HIPCHK(p, hipMemcpy(A.cp.data(), dcp + c0, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
   if (n) HIPCHK(p, hipMemcpy(A.c.data(), p->c_mut + c0, n * sizeof(double), hipMemcpyDeviceToHost));
   int64_t q0 = A.cp[0], q1 = A.cp[n];
   A.ri.resize(q1 - q0);
   A.cva.resize(q1 - q0);
   if (q1 > q0) {
-    HIPCHK(p, hipMemcpy(A.ri.data(), p->d.ri + q0, (q1 - q0) * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIPCHK(p, hipMemcpy(A.cva.data(), p->d.cva + q0, (q1 - q0) * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(p, hipMemcpy(A.ri.data(), dri + q0, (q1 - q0) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(p, hipMemcpy(A.cva.data(), dcva + q0, (q1 - q0) * sizeof(double), hipMemcpyDeviceToHost));
   }
   for (auto& v : A.cp) v -= (int32_t)q0;
   if (r0)

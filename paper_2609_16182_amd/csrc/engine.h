@@ -122,6 +122,11 @@ struct psl_presolver {
 
   ParScratch par{};
   psl::ColScratch pc{};  // parallel columns (allocated when enabled)
+  psl::DblScratch dbl{};  // doubleton substitution (allocated when enabled)
+  // the input's transposed copy, kept when substitutions rewrite the rows (the
+  // dual postsolve reads the input's columns)
+  int32_t *cp0 = nullptr, *ri0 = nullptr;
+  double* cva0 = nullptr;
   CompactScratch cmp{};
   Reduced red{};
   int32_t red_m = 0, red_n = 0;

@@ -24,13 +24,21 @@
 //     [lb_s, ub_s] that keeps the remainder in B_{s-1}, starting from lb_s if
 //     finite, else ub_s, else 0, moved into that range (below -> its low end,
 //     else above -> its high end); the leader keeps the remainder;
+//   * a doubleton substitution gives the eliminated column x_k =
+//     (b - a_j x_j) / a_k;
 //   * dual: kept rows take the reduced duals, the others start at 0; a
 //     BOUND_CHANGE whose column carries a multiplier of its bound's sign
-//     (z_j = c_j - a_j'y, summed over the column's rows ascending, left to
+//     (z_j = c_j - a_j'y, summed over the input's column j ascending, left to
 //     right) passes it to its source row k: y_k += z_j / a_kj; an active merged
 //     side of a parallel-row leader (y_L > 0: lhs, < 0: rhs) goes back to the
 //     row r that gave it, y_r = y_L / lambda_r, y_L = 0; a FREE_SINGLETON row
-//     takes y_i = c_j / a_ij; finally z = c - A'y.
+//     has y_i = c_j / a_ij from the start of the pass (the costs of the
+//     problems after it include -y_i a_ik); a DOUBLETON_ROW adds to its row the multiplier
+//     that makes z_k = c_k - a_k'y zero (c_k the cost then, the sum over the
+//     input's column k without row i): Y = (c_k - sum) / a_k. Until that record
+//     is undone, the reduced cost of its kept column j is taken in the problem
+//     of that time, whose rows of k were rewritten by -f_r row_i and whose
+//     cost lost (c_k / a_k) a_j: z_j - a_j Y. Finally z = c - A'y.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -47,7 +55,7 @@ namespace {
 // documentation in psl.h).
 enum : uint8_t {
   T_FIX_COL = 1, T_EMPTY_COL = 2, T_BOUND_CHANGE = 6, T_PARALLEL_ROW = 7, T_LEADER_SIDES = 8,
-  T_DUAL_FIX = 9, T_FREE_SINGLETON = 10, T_PARALLEL_COL = 11, T_LEADER_BOUNDS = 12
+  T_DUAL_FIX = 9, T_FREE_SINGLETON = 10, T_PARALLEL_COL = 11, T_LEADER_BOUNDS = 12, T_DOUBLETON_ROW = 14
 };
 
 // value of a merged interval end under the library's infinity convention
@@ -123,9 +131,13 @@ class RecordStack {
           break;
         case T_FREE_SINGLETON:
           needs_rows_ = true;
+          substituted_.push_back({r.i, r.v[3] / r.v[0]});
           break;
         case T_PARALLEL_ROW:
           row_lambda_[r.i] = r.v[0];
+          break;
+        case T_DOUBLETON_ROW:
+          kept_by_[r.j] = t;
           break;
         case T_LEADER_BOUNDS: {
           if (r.round != pass) {
@@ -162,21 +174,26 @@ class RecordStack {
       const psl_record& r = rec_[t];
       if (r.type == T_LEADER_BOUNDS) groups_.at(t).split(inf_value, x);
       else if (r.type == T_FREE_SINGLETON) x[r.j] = singleton_value(r, *rows, x);
+      else if (r.type == T_DOUBLETON_ROW) x[r.k] = (r.v[2] - r.v[0] * x[r.j]) / r.v[1];
     }
   }
 
-  void dual(const HostCols& A, double* y) const {
+  void dual(const HostCols& A, double* y) {
+    // rows substituted into the objective carry their dual in every problem
+    // after their removal (the other columns' costs lost y_i a_ik)
+    for (const auto& rd : substituted_) y[rd.first] = rd.second;
     for (int64_t t = count_ - 1; t >= 0; --t) {
       const psl_record& r = rec_[t];
       switch (r.type) {
         case T_BOUND_CHANGE:
           undo_tightening(r, A, y);
           break;
+        case T_DOUBLETON_ROW:
+          y[r.i] = y[r.i] + substitution_dual(r, A, y);
+          kept_by_.erase(r.j);
+          break;
         case T_LEADER_SIDES:
           undo_merged_sides(r, y);
-          break;
-        case T_FREE_SINGLETON:
-          y[r.i] = r.v[3] / r.v[0];  // its column is free: z_j = 0
           break;
         default:
           break;
@@ -201,10 +218,29 @@ class RecordStack {
     return (s - rest) / r.v[0];
   }
 
+  // the multiplier a doubleton substitution's row takes to zero z_k
+  static double substitution_dual(const psl_record& r, const HostCols& A, const double* y) {
+    double ay = 0.0;
+    for (int32_t q = A.cp[r.k]; q < A.cp[r.k + 1]; ++q)
+      if (A.ri[q] != r.i) ay = ay + A.cva[q] * y[A.ri[q]];
+    return (r.v[3] - ay) / r.v[1];
+  }
+
+  // reduced cost of column j in the problem of the record being undone
+  double reduced_cost_then(const HostCols& A, const double* y, int32_t j) const {
+    double z = reduced_cost(A, y, j);
+    auto it = kept_by_.find(j);
+    if (it != kept_by_.end()) {
+      const psl_record& s = rec_[it->second];
+      z = z - s.v[0] * substitution_dual(s, A, y);
+    }
+    return z;
+  }
+
   // a tightened bound with a multiplier of its sign holds through its row
-  static void undo_tightening(const psl_record& r, const HostCols& A, double* y) {
+  void undo_tightening(const psl_record& r, const HostCols& A, double* y) const {
     if (r.k < 0) return;
-    double zj = reduced_cost(A, y, r.j);
+    double zj = reduced_cost_then(A, y, r.j);
     bool carries = (r.side == 0 && zj > 0.0) || (r.side == 1 && zj < 0.0);
     if (carries) y[r.k] = y[r.k] + zj / r.v[2];
   }
@@ -226,6 +262,8 @@ class RecordStack {
   std::vector<std::pair<int32_t, double>> fixed_;
   std::unordered_map<int64_t, ColumnGroup> groups_;  // keyed by the LEADER_BOUNDS record's position
   std::unordered_map<int32_t, double> row_lambda_;   // merged row -> lambda
+  std::unordered_map<int32_t, int64_t> kept_by_;     // kept column -> its DOUBLETON_ROW record, not undone yet
+  std::vector<std::pair<int32_t, double>> substituted_;  // FREE_SINGLETON row -> c_j / a_ij
 };
 
 }  // namespace
@@ -259,7 +297,8 @@ void postsolve_dual(const psl_record* rec, int64_t count, int32_t m, int32_t n, 
                     const double* y_red, const HostCols& A, double* y, double* z) {
   std::fill(y, y + m, 0.0);
   for (size_t t = 0; t < row_map.size(); ++t) y[row_map[t]] = y_red[t];
-  RecordStack(rec, count).dual(A, y);
+  RecordStack st(rec, count);
+  st.dual(A, y);
   for (int32_t j = 0; j < n; ++j) z[j] = RecordStack::reduced_cost(A, y, j);
 }
 

@@ -132,6 +132,22 @@ void launch_par_count(const Dev& d, const ParScratch& p, hipStream_t s);
 void launch_par_emit(const Dev& d, const ParScratch& p, int64_t base, int round, hipStream_t s);
 void launch_par_drop(const Dev& d, const ParScratch& p, hipStream_t s);
 
+// doubleton.hip: doubleton-equality substitution (allocated when enabled)
+struct DblScratch {
+  int32_t* list;       // [m] candidate rows
+  int32_t *cj, *ck;    // [m] kept / eliminated column of a candidate (-1: none)
+  double *aj, *ak, *b; // [m] its coefficients and right-hand side
+  int32_t* row_claim;  // [m] lowest claiming candidate of each row
+  int32_t* col_claim;  // [n] ... of each column
+  uint8_t* col_mod;    // [n] kept by an earlier substitution (for the run)
+  int32_t* by;         // [n] applied row whose kept column this is, -1
+  double2* tb;         // [n] interval x_k's bounds give a kept column
+  int32_t* total;      // [2] records: rows, transferred bounds
+};
+void launch_doubletons(const Dev& d, const DblScratch& S, int64_t base, int round, int32_t* ws, hipStream_t s);
+void launch_doubleton_relock(const Dev& d, const DblScratch& S, hipStream_t s);
+void launch_doubleton_init(const Dev& d, const DblScratch& S, hipStream_t s);  // no column kept yet
+
 // compact.hip
 struct Reduced {
   int32_t *row_ptr, *col_idx, *col_ptr, *row_idx, *row_map, *col_map;
