@@ -278,6 +278,7 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->par.vlist, m);
   ALLOC(p->par.hacc, 4 * p->long_cap);
   ALLOC(p->par.lam, m);
+  ALLOC(p->par.abits, n / 64 + 1);
   p->par.lpt = nullptr;
   if (p->s.enable_doubletons) {
     ALLOC(p->dbl.list, m);
@@ -313,6 +314,8 @@ static psl_status setup_arena(psl_presolver* p) {
   ALLOC(p->cmp.row_new, m + 1);
   ALLOC(p->cmp.col_new, n + 1);
   ALLOC(p->cmp.col_keep, n);
+  ALLOC(p->cmp.rbits, m / 64 + 1);
+  ALLOC(p->cmp.cbits, n / 64 + 1);
   ALLOC(p->cmp.terms, n);
   ALLOC(p->cmp.pws, pairwise_ws_doubles(n) + 2);
   ALLOC(p->cmp.totals, 4);
@@ -1007,6 +1010,10 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   }
 
   int outer = 0;
+  // row_out holds every live row's removed-column constant and active
+  // length of the current bounds (a parallel pass hashed every live row and
+  // then changed nothing), so the compaction need not sweep for them again
+  bool consts_current = false;
   for (; outer < s.max_outer; ++outer) {
     int nprop = 0;
     for (auto& L : p->lst)
@@ -1015,6 +1022,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
         ++nprop;
       }
     if (nprop == 0) break;
+    consts_current = false;
     // a cycle's first round sweeps every active row
     e = use_full_view(p);
     if (e != PSL_OK) return e;
@@ -1159,6 +1167,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     e = queue_lp_read(p, false);
     if (e == PSL_OK) e = read_flags(p);
     if (e != PSL_OK) return e;
+    consts_current = !B && s.enable_parallel_rows && !p->hflags->merged;
     if (s.enable_doubletons && p->hflags->dbl_applied) {
       // rows were rewritten: the transposed copy (and what hangs on it) again
       p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.cnt, p->isc, p->red.val, st);
@@ -1206,8 +1215,10 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     e = use_full_view(p);
     if (e != PSL_OK) return e;
     HIPCHK(p, hipEventRecord(p->ev[4], st));
-    launch_long_stats(d, MODE_COMPACT, st);
-    launch_sweep(d, p->grid, MODE_COMPACT, st);
+    if (!consts_current) {
+      launch_long_stats(d, MODE_COMPACT, st);
+      launch_sweep(d, p->grid, MODE_COMPACT, st);
+    }
     compact_flags(d, p->cmp, st);
     compact_write(d, p->cmp, p->red, p->obj_offset, st);
     HIPCHK(p, hipEventRecord(p->ev[5], st));

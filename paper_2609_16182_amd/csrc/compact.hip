@@ -8,6 +8,7 @@
 // positions and over the transposed copy's positions, so the kept entries keep
 // their order in both layouts. In a batch the LPs are blocks of one LP, so
 // each LP's kept rows, columns and entries are contiguous in these scans.
+#include "bits.h"
 #include "psl_kern.h"
 #include "sweep.h"
 
@@ -28,19 +29,34 @@ __global__ void k_cmp_flags(Dev d, CompactScratch c) {
   }
 }
 
+// the kept rows and columns as bits (L2-resident for the random lookups of
+// the position and gather passes)
+__global__ void k_cmp_bits(Dev d, CompactScratch c) {
+  write_bits(c.rbits, d.m, [&](int64_t i) { return d.row_on[i] != 0; });
+  write_bits(c.cbits, d.n, [&](int64_t j) { return c.col_keep[j] != 0; });
+}
+
 // kept positions of both layouts (a position is kept when its row and its
-// column are); the keep bytes are small enough to stay in cache
+// column are): in CSR order the row is monotone and the column random, in
+// the transposed copy the other way round; the random side reads bits
 __global__ void k_cmp_pos_flags(Dev d, CompactScratch c) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= d.nnz; p += stride) {
     int ef = 0, qf = 0;
     if (p < d.nnz) {
-      ef = d.row_on[c.rowid1[p + 1]] & c.col_keep[d.ci[p]];
-      qf = d.row_on[d.ri[p]] & c.col_keep[c.colid[p]];
+      ef = d.row_on[c.rowid1[p + 1]] && bit_of(c.cbits, d.ci[p]);
+      qf = bit_of(c.rbits, d.ri[p]) && c.col_keep[c.colid[p]];
     }
     c.eflag[p] = ef;
     c.qflag[p] = qf;
   }
+}
+
+// after the scans: the kept rows / columns before each bit word
+__global__ void k_cmp_pre(Dev d, CompactScratch c) {
+  int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (64 * w < d.m) c.rbits[w].pre = c.row_new[64 * w];
+  if (64 * w < d.n) c.cbits[w].pre = c.col_new[64 * w];
 }
 
 __global__ void k_cmp_offset(const double* sum, double off, double* out) {
@@ -72,19 +88,27 @@ __global__ void k_cmp_lpbase(Dev d, CompactScratch c, Reduced r) {
   }
 }
 
-__global__ void k_cmp_gather(Dev d, CompactScratch c, Reduced r) {
+// kept entries of the CSR (new column ids from the column bits) ...
+__global__ void k_cmp_gather_rows(Dev d, CompactScratch c, Reduced r) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < d.nnz; p += stride) {
     int pe = c.eflag[p];
     if (c.eflag[p + 1] != pe) {  // kept
       int j = d.ci[p];
-      r.col_idx[pe] = c.col_new[j] - (d.K > 1 ? c.lpr[d.col_lp[j]].cb : 0);
+      r.col_idx[pe] = rank_of(c.cbits, j) - (d.K > 1 ? c.lpr[d.col_lp[j]].cb : 0);
       r.val[pe] = d.va[p];
     }
+  }
+}
+
+// ... and of the transposed copy (new row ids from the row bits)
+__global__ void k_cmp_gather_cols(Dev d, CompactScratch c, Reduced r) {
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < d.nnz; p += stride) {
     int pq = c.qflag[p];
     if (c.qflag[p + 1] != pq) {
       int i = d.ri[p];
-      r.row_idx[pq] = c.row_new[i] - (d.K > 1 ? c.lpr[d.row_lp[i]].rb : 0);
+      r.row_idx[pq] = rank_of(c.rbits, i) - (d.K > 1 ? c.lpr[d.row_lp[i]].rb : 0);
       r.cval[pq] = d.cva[p];
     }
   }
@@ -137,9 +161,12 @@ void compact_flags(const Dev& d, const CompactScratch& c, hipStream_t s) {
   int64_t blocks = (t + PSL_BLOCK - 1) / PSL_BLOCK;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_cmp_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c);
+  hipLaunchKernelGGL(k_cmp_bits, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c);
   hipLaunchKernelGGL(k_cmp_pos_flags, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c);
   scan_excl(c.row_new, c.row_new, d.m, c.totals + 0, c.ws, s);
   scan_excl(c.col_new, c.col_new, d.n, c.totals + 1, c.ws, s);
+  int64_t words = (d.m > d.n ? d.m : d.n) / 64 + 1;
+  hipLaunchKernelGGL(k_cmp_pre, dim3((unsigned)((words + PSL_BLOCK - 1) / PSL_BLOCK)), dim3(PSL_BLOCK), 0, s, d, c);
   scan_excl(c.eflag, c.eflag, d.nnz + 1, c.totals + 2, c.ws, s);
   scan_excl(c.qflag, c.qflag, d.nnz + 1, c.totals + 3, c.ws, s);
 }
@@ -155,7 +182,8 @@ void compact_write(const Dev& d, const CompactScratch& c, const Reduced& r, doub
   if (d.nnz > 0) {
     int64_t blocks = (d.nnz + PSL_BLOCK - 1) / PSL_BLOCK;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_cmp_gather, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c, r);
+    hipLaunchKernelGGL(k_cmp_gather_rows, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c, r);
+    hipLaunchKernelGGL(k_cmp_gather_cols, dim3((unsigned)blocks), dim3(PSL_BLOCK), 0, s, d, c, r);
   }
   int64_t t = (int64_t)d.m + d.n;
   if (t < 1) t = 1;

@@ -16,6 +16,7 @@
 // row giving each final side is the lowest such row. A side the leader keeps
 // keeps its stored value, one taken from another row is stored as
 // effective + k_leader.
+#include "bits.h"
 #include "psl_kern.h"
 #include "sweep.h"
 
@@ -23,10 +24,11 @@ namespace psl {
 
 // col0: first column of the row's LP (the pattern is hashed in the LP's own
 // column numbering, so a row's key does not depend on its place in a batch).
-// Only active entries (column bounds not equal) enter the key.
-__device__ __forceinline__ void hash_el(int j, double a, double2 b, bool v, double a0, int col0,
-                                        unsigned long long& h1, unsigned long long& h2, bool& act) {
-  act = v && b.x != b.y;
+// Only active entries (column bounds not equal) enter the key; whether a
+// column is active comes from the pass's bit array (one bit per column, in
+// L2), and only a fixed column's entry reads its bounds (for the constant).
+__device__ __forceinline__ void hash_el(int j, double a, bool act, double a0, int col0, unsigned long long& h1,
+                                        unsigned long long& h2) {
   unsigned long long cj = splitmix((unsigned long long)(uint32_t)(j - col0));
   h1 = act ? cj : 0ULL;
   h2 = act ? splitmix(cj ^ quantize(a / a0)) : 0ULL;
@@ -37,8 +39,9 @@ __device__ __forceinline__ void hash_el(int j, double a, double2 b, bool v, doub
 // entries), added to s1 / s2, active ones counted in L. All loads are issued
 // before any is used.
 template <int U, int STRIDE>
-__device__ __forceinline__ void hash_batch(const Dev& d, int64_t s0, int q0, int lane, int end, double a0, int col0,
-                                           unsigned long long& s1, unsigned long long& s2, int& L) {
+__device__ __forceinline__ void hash_batch(const Dev& d, const uint64_t* abits, int64_t s0, int q0, int lane, int end,
+                                           double a0, int col0, unsigned long long& s1, unsigned long long& s2,
+                                           int& L) {
   int j[U];
   double a[U];
   bool v[U];
@@ -50,31 +53,26 @@ __device__ __forceinline__ void hash_batch(const Dev& d, int64_t s0, int q0, int
     j[u] = d.ci[p];
     a[u] = d.va[p];
   }
-  double2 b[U];
+  bool act[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) b[u] = d.bnd[j[u]];
+  for (int u = 0; u < U; ++u) act[u] = v[u] && bit_of(abits, j[u]);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     unsigned long long h1, h2;
-    bool act;
-    hash_el(j[u], a[u], b[u], v[u], a0, col0, h1, h2, act);
+    hash_el(j[u], a[u], act[u], a0, col0, h1, h2);
     s1 += h1;
     s2 += h2;
-    L += act ? 1 : 0;
+    L += act[u] ? 1 : 0;
   }
 }
 
 // First active position of a row (one wavefront, all lanes return it), or
 // -1 when no column of the row is active.
-__device__ __forceinline__ int first_active_pos(const Dev& d, int64_t s0, int len) {
+__device__ __forceinline__ int first_active_pos(const Dev& d, const uint64_t* abits, int64_t s0, int len) {
   int lane = lane_id();
   for (int q0 = 0; q0 < len; q0 += PSL_WAVE) {
     int q = q0 + lane;
-    bool act = false;
-    if (q < len) {
-      double2 b = d.bnd[d.ci[s0 + q]];
-      act = b.x != b.y;
-    }
+    bool act = q < len && bit_of(abits, d.ci[s0 + q]);
     unsigned long long mask = __ballot(act);
     if (mask) return q0 + __ffsll((long long)mask) - 1;
   }
@@ -160,22 +158,23 @@ __device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, i
   bool on = vr && d.row_on[row] != 0;
   int j = d.ci[p];
   double a = d.va[p];
-  double2 bb = d.bnd[j];
-  bool act0 = on && gl < len && bb.x != bb.y;
+  bool in_row = on && gl < len;
+  bool act0 = in_row && bit_of(P.abits, j);
+  double xf = 0.0;  // a fixed column's value
+  if (in_row && !act0) xf = d.bnd[j].x;
   unsigned long long gmask = __ballot(act0) & group_mask<G>();
   int first = gmask ? __ffsll((long long)gmask) - 1 : lane_id();
   double a0 = __shfl(a, first, PSL_WAVE);
   if (!gmask) a0 = 1.0;
   int col0 = lp_col0(d, row);
   unsigned long long h1, h2;
-  bool act;
-  hash_el(j, a, bb, on && gl < len, a0, col0, h1, h2, act);
+  hash_el(j, a, act0, a0, col0, h1, h2);
   h1 = group_sum_u64<G>(h1);
   h2 = group_sum_u64<G>(h2);
   int L = __popcll(gmask);
   // the removed columns' constant: a butterfly over the group's lanes is the
   // canonical pairwise tree of the row's positions
-  double k = group_sum<G>(on && gl < len && !act0 ? pos0(a * bb.x) : 0.0);
+  double k = group_sum<G>(in_row && !act0 ? pos0(a * xf) : 0.0);
   if (vr && on && gl == 0) {
     d.row_out[row].v0 = k;
     d.row_out[row].j = L;
@@ -215,15 +214,18 @@ __device__ __forceinline__ void hash_wave_row(const Dev& d, const ParScratch& P,
     j[k] = d.ci[p];
     a[k] = d.va[p];
   }
-  double2 b[C];
-#pragma unroll
-  for (int k = 0; k < C; ++k) b[k] = d.bnd[j[k]];
   bool act[C];
+  double x[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    act[k] = v[k] && bit_of(P.abits, j[k]);
+    x[k] = 0.0;
+    if (v[k] && !act[k]) x[k] = d.bnd[j[k]].x;  // a fixed column's value
+  }
   int lf = C;
   double af = 1.0;
 #pragma unroll
   for (int k = C - 1; k >= 0; --k) {
-    act[k] = v[k] && b[k].x != b[k].y;
     if (act[k]) {
       lf = k;
       af = a[k];
@@ -238,12 +240,11 @@ __device__ __forceinline__ void hash_wave_row(const Dev& d, const ParScratch& P,
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     unsigned long long h1, h2;
-    bool ak;
-    hash_el(j[k], a[k], b[k], v[k], a0, col0, h1, h2, ak);
+    hash_el(j[k], a[k], act[k], a0, col0, h1, h2);
     s1 += h1;
     s2 += h2;
-    L += ak ? 1 : 0;
-    t[k] = v[k] && !ak ? pos0(a[k] * b[k].x) : 0.0;
+    L += act[k] ? 1 : 0;
+    t[k] = v[k] && !act[k] ? pos0(a[k] * x[k]) : 0.0;
   }
   double kc = group_sum<PSL_WAVE>(reg_tree<C>(t));
   s1 = group_sum_u64<PSL_WAVE>(s1);
@@ -265,7 +266,7 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_long_first(Dev d, ParScratch 
   if (!d.row_on[row]) return;
   int64_t s0 = d.rp[row];
   int len = d.rp[row + 1] - (int)s0;
-  int f = first_active_pos(d, s0, len);
+  int f = first_active_pos(d, P.abits, s0, len);
   if (lane_id() == 0) P.hacc[4 * (int64_t)k + 3] = f < 0 ? 0ull : (unsigned long long)__double_as_longlong(d.va[s0 + f]);
 }
 
@@ -285,7 +286,7 @@ __device__ __forceinline__ void hash_long_chunk(const Dev& d, const ParScratch& 
   int L = 0;
   int end = min(len, ch.first + ch.npass * PASS_LEN);
   for (int q0 = ch.first; q0 < end; q0 += 4 * PSL_BLOCK)
-    hash_batch<4, PSL_BLOCK>(d, s0, q0, (int)threadIdx.x, end, a0, col0, s1, s2, L);
+    hash_batch<4, PSL_BLOCK>(d, P.abits, s0, q0, (int)threadIdx.x, end, a0, col0, s1, s2, L);
   s1 = group_sum_u64<PSL_WAVE>(s1);
   s2 = group_sum_u64<PSL_WAVE>(s2);
   unsigned long long l64 = group_sum_u64<PSL_WAVE>((unsigned long long)L);
@@ -404,8 +405,8 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_verify(Dev d, ParScratch P) {
     bool ok = d.row_out[r].j == d.row_out[L].j;
     int fr = -1, fl = -1;
     if (ok) {
-      fr = first_active_pos(d, sr, len);
-      fl = first_active_pos(d, sl, lenL);
+      fr = first_active_pos(d, P.abits, sr, len);
+      fl = first_active_pos(d, P.abits, sl, lenL);
       ok = fr >= 0 && fl >= 0;
     }
     double r0 = ok ? d.va[sr + fr] : 1.0, l0 = ok ? d.va[sl + fl] : 1.0;
@@ -414,8 +415,7 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_verify(Dev d, ParScratch P) {
       bool bad = false;
       if (q < len) {
         int j = d.ci[sr + q];
-        double2 b = d.bnd[j];
-        if (b.x != b.y) {
+        if (bit_of(P.abits, j)) {
           int64_t pl = find_col(d, sl, lenL, j);
           if (pl < 0) {
             bad = true;
@@ -584,7 +584,19 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_drop(Dev d, ParScratch P) {
   }
 }
 
+__global__ void k_par_bits(Dev d, ParScratch P) {
+  write_bits(P.abits, d.n, [&](int64_t j) {
+    double2 b = d.bnd[j];
+    return b.x != b.y;
+  });
+}
+
 void launch_par_hash(const Dev& d, const ParScratch& p, const SweepGrid& g, hipStream_t s) {
+  if (d.n > 0) {
+    int64_t b = (d.n + PSL_BLOCK - 1) / PSL_BLOCK;
+    if (b > 16384) b = 16384;
+    hipLaunchKernelGGL(k_par_bits, dim3((unsigned)b), dim3(PSL_BLOCK), 0, s, d, p);
+  }
   int total = 0;
   for (int b = 0; b < NBINS; ++b) total += g.nb[b];
   if (d.nlong > 0)

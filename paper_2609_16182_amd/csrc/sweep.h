@@ -1,6 +1,7 @@
 // sweep.h -- launchers of the per-round kernels (sweep.hip), the parallel-row
 // pass (parallel.hip), ingest (ingest.hip) and compaction (compact.hip).
 #pragma once
+#include "bits.h"
 #include "psl_dev.h"
 
 namespace psl {
@@ -124,6 +125,7 @@ struct ParScratch {
   unsigned long long* hacc;  // [4 * long rows] hash accumulators (h1, h2, L)
                              // and the row's first active coefficient (bits)
   double* lam;        // [m] lambda of a verified row (a_r = lambda a_leader)
+  uint64_t* abits;    // [n/64+1] active columns (lb != ub), one bit each
 };
 void launch_par_reset(const Dev& d, const ParScratch& p, hipStream_t s);
 void launch_par_hash(const Dev& d, const ParScratch& p, const SweepGrid& g, hipStream_t s);
@@ -162,6 +164,8 @@ struct CompactScratch {
   int32_t* row_new;       // [m]     kept flags -> new row ids
   int32_t* col_new;       // [n]     kept flags -> new column ids
   uint8_t* col_keep;      // [n]     kept columns (bytes)
+  RankWord* rbits;        // [m/64+1] kept rows, one bit each, with ranks
+  RankWord* cbits;        // [n/64+1] kept columns, one bit each, with ranks
   double* terms;          // [n]     cost terms of removed columns
   double* pws;            // pairwise-sum workspace; pws[0] = the sum
   int32_t* totals;        // [4]     m', n', nnz' (CSR), nnz' (transposed)
