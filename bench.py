@@ -311,6 +311,27 @@ def measured_traffic(workload):
     return t["traffic_bytes_per_launch"]
 
 
+def gather_ceiling(entries, sweep_rate):
+    """The sweep's gathers against what this GPU serves for its pattern:
+    random 16-byte gathers from a table of the workload's column count, with
+    a streamed index and coefficient per gather (libpsl_probe.so). None when
+    the probe is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2609_16182_amd", "libpsl_probe.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    lib.psl_probe_gather.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    rate = ctypes.c_double(0.0)
+    if lib.psl_probe_gather(int(entries), 100_000_000, 4, ctypes.byref(rate)) != 0:
+        return None
+    return {"gathers_per_s": round(rate.value), "table_entries": int(entries), "bytes_per_gather": 16,
+            "sweep_gathers_per_s": round(sweep_rate), "frac": round(sweep_rate / rate.value, 4),
+            "note": "random 16-byte gathers (one cache line each) beside a streamed 12 B per gather: the "
+                    "practical ceiling of the sweep's bound gathers; frac = the sweep's swept nonzeros per "
+                    "second of sweep time over that rate"}
+
+
 def main():
     args = parse()
     if args.cpu_baseline_child:
@@ -361,6 +382,7 @@ def main():
     sweep_ms = 0.0
     sweep_bytes = 0.0
     sweep_launches = 0
+    sweep_nnz = 0
     run_bytes = 0.0
     step_ms = []
     torch.cuda.synchronize()
@@ -374,6 +396,7 @@ def main():
         sweep_ms += st["ms_sweep"]
         sweep_bytes += st["sweep_bytes"]
         sweep_launches += st["sweep_launches"]
+        sweep_nnz += st["sweep_nnz"]
         run_bytes += st["alg_bytes"] + st["ingest_bytes"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -432,6 +455,7 @@ def main():
                   flush=True)
     del dev
     torch.cuda.empty_cache()
+    ceiling = gather_ceiling(n_in, sweep_nnz / (sweep_ms * 1e-3) if sweep_ms > 0 else 0.0)
 
     batch = batch_leg(args, torch, psl) if args.batch_lps > 0 else None
     serving = serving_leg(args, torch, psl) if args.serve_pool > 0 else None
@@ -451,6 +475,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "hbm_whole_run": hbm_whole,
+        "gather_ceiling": ceiling,
         "cpu_baseline": cpu,
         "detail": {"rounds": stats["rounds"], "records": stats["records"], "nnz_out": stats["nnz_out"],
                    "ms_ingest": round(stats["ms_ingest"], 3), "ms_run_device": round(stats["ms_total"], 3),

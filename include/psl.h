@@ -245,6 +245,8 @@ typedef struct {
                                       or reload): 36 B per nonzero (read, copy,
                                       transposed copy), 32 B per row, 48 B per
                                       column                                    */
+    int64_t sweep_nnz;             /* nonzeros swept by those launches (each
+                                      gathers its column's bounds once)         */
 } psl_stats;
 
 /* The reduced problem. DEVICE pointers owned by the handle, valid until the

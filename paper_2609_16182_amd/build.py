@@ -41,6 +41,23 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+PROBE = os.path.join(HERE, "libpsl_probe.so")
+
+
+def build_probe(verbose=False):
+    """Compile the gather-rate probe (probe/*.hip) into libpsl_probe.so."""
+    tmp = PROBE + f".tmp{os.getpid()}"
+    cmd = [hipcc(), *FLAGS, *sorted(glob.glob(os.path.join(HERE, "probe", "*.hip"))), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building libpsl_probe.so")
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 def build(verbose=False):
     """Compile every HIP source into libpsl.so (always rebuilds)."""
     tmp = LIB + f".tmp{os.getpid()}"
@@ -59,3 +76,4 @@ def build(verbose=False):
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))

@@ -1073,9 +1073,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       sweep_ms += elapsed(p, 7, 5);
       decide_ms += elapsed(p, 5, 6);
       S.sweep_launches += 1;
-      // algorithmic bytes: the swept rows' positions (12 B a nonzero), their
-      // bin entry, sides and outputs (24 B a row), and the bounds of the
-      // columns they can touch (16 B each, at most one per nonzero)
+      S.sweep_nnz += p->cur.nnz;
       // algorithmic bytes of the sweep launch: the swept rows' positions
       // (12 B a nonzero); per swept row its bin entry, row pointer, sides and
       // statistics (48 B); per column it can touch (at most one per nonzero)

@@ -578,27 +578,55 @@ __device__ __forceinline__ int round_mode(const Dev& d, const RoundMode& rm) {
   return (incr ? 1 : 0) | (counts ? 2 : 0);
 }
 
+// exclusive prefix (lanes below) and total of per-lane values 0..31 across
+// the wavefront, from one ballot per bit
+__device__ __forceinline__ void wave_scan5(int v, int& pre, int& tot) {
+  unsigned long long below = lanemask_lt();
+  pre = tot = 0;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    unsigned long long m = __ballot((v >> b) & 1);
+    pre += __popcll(m & below) << b;
+    tot += __popcll(m) << b;
+  }
+}
+
 __global__ void __launch_bounds__(PSL_BLOCK) k_mark_sparse(Dev d, RoundMode rm) {
   int mode = round_mode(d, rm);
   if (blockIdx.x == 0 && threadIdx.x == 0) d.flags->mode = mode;
   if (mode == 0) return;
   int64_t j = (int64_t)blockIdx.x * PSL_BLOCK + threadIdx.x;
-  bool ch = false;
   int q0 = 0, q1 = 0, code = 0;
   if (j < d.n) code = d.col_code[j];
   if (mark_col(code, mode)) {
     q0 = d.cp[j];
     q1 = d.cp[j + 1];
-    if (q1 - q0 <= MARK_SHORT) {
-      // a short column: its own lane walks it, beside the other lanes
-      for (int q = q0; q < q1; ++q) mark_entry(d, q, code, mode & 1, mode & 2);
-    } else {
-      ch = q1 - q0 <= MARK_DENSE;
+  }
+  int len = q1 - q0;
+  int lane = lane_id();
+  // short columns: the wavefront's entries, concatenated in column order,
+  // one per lane (a column's entries are contiguous, so the row-index loads
+  // of a step touch a few lines, and no lane walks a column alone)
+  int sl = len <= MARK_SHORT ? len : 0;
+  int pre, tot;
+  wave_scan5(sl, pre, tot);
+  for (int e0 = 0; e0 < tot; e0 += PSL_WAVE) {
+    int e = e0 + lane;
+    // the entry's column: the last lane whose prefix is <= e
+    int lo = 0, hi = PSL_WAVE - 1;
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+      int mid = (lo + hi + 1) >> 1;
+      bool le = __shfl(pre, mid, PSL_WAVE) <= e;
+      lo = le ? mid : lo;
+      hi = le ? hi : mid - 1;
     }
+    int q = __shfl(q0, lo, PSL_WAVE) + (e - __shfl(pre, lo, PSL_WAVE));
+    int cl = __shfl(code, lo, PSL_WAVE);
+    if (e < tot) mark_entry(d, q, cl, mode & 1, mode & 2);
   }
   // longer ones: the wavefront walks them one after another
-  unsigned long long mask = __ballot(ch);
-  int lane = lane_id();
+  unsigned long long mask = __ballot(len > MARK_SHORT && len <= MARK_DENSE);
   while (mask) {
     int l = __ffsll((long long)mask) - 1;
     mask &= mask - 1;

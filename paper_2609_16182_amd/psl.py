@@ -52,7 +52,7 @@ class psl_stats(C.Structure):
                 ("ms_ingest", C.c_double), ("ms_sweep", C.c_double), ("ms_decide", C.c_double),
                 ("ms_parallel", C.c_double), ("ms_compact", C.c_double), ("ms_total", C.c_double),
                 ("sweep_launches", C.c_int64), ("sweep_bytes", C.c_double), ("ms_long", C.c_double),
-                ("alg_bytes", C.c_double), ("ingest_bytes", C.c_double)]
+                ("alg_bytes", C.c_double), ("ingest_bytes", C.c_double), ("sweep_nnz", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
