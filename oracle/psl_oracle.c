@@ -89,7 +89,6 @@ enum {
 
 /* parallel columns are searched among columns stored with at most this many
  * entries */
-#define PC_MAX_LEN 64
 
 /* classes of the reduced problem's rows and columns (listed, not applied) */
 enum { RCLS_OTHER = 0, RCLS_SINGLETON = 1, RCLS_DOUBLETON_EQ = 2, RCLS_DOUBLETON_INEQ = 3 };
@@ -883,10 +882,11 @@ static double col_first(const or_handle *h, int32_t j) {
     return 0.0;
 }
 
-/* 31-bit key of the augmented row: the parallel-row key over its entries,
+/* 63-bit key of the augmented row: the parallel-row key over its entries,
  * with the cost as an entry of id 2^32 - 1 before the rows, normalised by the
- * first entry, top 31 bits */
-static uint32_t col_key(const or_handle *h, int32_t j) {
+ * first entry, top 63 bits (columns that are not candidates sort after every
+ * key) */
+static uint64_t col_key(const or_handle *h, int32_t j) {
     double f = col_first(h, j);
     uint64_t h1 = 0, h2 = 0;
     if (h->c[j] != 0) {
@@ -900,7 +900,7 @@ static uint32_t col_key(const or_handle *h, int32_t j) {
         h1 += 1 + id;
         h2 += splitmix(id ^ quantize(h->cva[q] / f));
     }
-    return (uint32_t)((splitmix(h1) ^ h2) >> 33);
+    return (splitmix(h1) ^ h2) >> 1;
 }
 
 /* same augmented pattern and entries within par_tol after normalisation */
@@ -941,7 +941,7 @@ static void add_scaled(const or_handle *h, double lam, double lb, double ub, dou
     }
 }
 
-typedef struct { uint32_t key; int32_t col; } keycol;
+typedef struct { uint64_t key; int32_t col; } keycol;
 
 static int cmp_keycol(const void *a, const void *b) {
     const keycol *x = (const keycol *)a, *y = (const keycol *)b;
@@ -949,8 +949,8 @@ static int cmp_keycol(const void *a, const void *b) {
     return (x->col > y->col) - (x->col < y->col);
 }
 
-/* Candidates: active columns in at least one alive row, stored with at most
- * PC_MAX_LEN entries. Groups: equal keys, in ascending column order; the
+/* Candidates: active columns in at least one alive row, of any length (the
+ * paper sets no limit). Groups: equal keys, in ascending column order; the
  * leader is the group's first column, every other member is verified
  * against it and merged into it in ascending order. Records in one pass
  * over the columns: LEADER_BOUNDS for a leader, PARALLEL_COL for a merged
@@ -960,7 +960,7 @@ static int parallel_cols(or_handle *h) {
     keycol *kc = (keycol *)xcalloc((size_t)n + 1, sizeof(keycol));
     int32_t nk = 0;
     for (int32_t j = 0; j < n; ++j) {
-        if (!h->col_on[j] || h->col_len[j] < 1 || h->cp[j + 1] - h->cp[j] > PC_MAX_LEN) continue;
+        if (!h->col_on[j] || h->col_len[j] < 1) continue;
         kc[nk].key = col_key(h, j);
         kc[nk].col = j;
         nk++;

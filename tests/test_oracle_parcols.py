@@ -5,8 +5,11 @@ bounds follow from both; found as parallel rows of [c A']).
 Pins that do not reuse the oracle's arithmetic:
   * closed forms: merged intervals for lambda > 0 and < 0 and for a group of
     three (summed in ascending column order), costs that are not
-    proportional, a column stored with more than 64 entries, and the
-    postsolve split of a merged value;
+    proportional, columns stored with 300 entries (no length limit), and
+    the postsolve split of a merged value;
+  * completeness on tiny LPs with planted scaled copies: no two active
+    columns of the reduced LP are parallel (a group lost to a key collision
+    or to a length limit fails here);
   * a replay of every PARALLEL_COL record against the original LP: on the
     rows alive at that pass the column equals lambda times its leader's, and
     so does its cost (within the tolerance); each LEADER_BOUNDS interval is
@@ -180,13 +183,24 @@ def test_merge_negative_lambda_and_group_of_three():
     _check_optimal(lp, res)
 
 
-def test_not_proportional_or_too_long():
+def test_not_proportional():
     lp = make(2, 3, BASE_ROWS, [1.0, -INF], [10.0, 4.0], [0, 1, 0], [3, 2, 5], [1.0, 3.0, 1.0])
     assert not _recs(O.presolve(lp, **PC), "PARALLEL_COL")
-    # 65 rows: the two columns are stored with 65 entries each
-    rows = [[(0, 1.0), (1, 2.0), (2, 1.0)] for _ in range(65)]
-    lp = make(65, 3, rows, [-INF] * 65, [100.0 + i for i in range(65)], [0, 1, 0], [3, 2, 5], [1.0, 2.0, 1.0])
-    assert not _recs(O.presolve(lp, **PC), "PARALLEL_COL")
+
+
+def test_long_columns_merge():
+    """No length limit: x0 and x1 = 2 x0 in 300 rows x0 + 2 x1 + (1 + i % 3)
+    x2 >= 5 + i / 100 (no bound tightens: the residual maxima are too large),
+    costs 1 and 2: one PARALLEL_COL (1, 0, lambda 2), interval [0, 3] + 2 [1, 2]."""
+    rows = [[(0, 1.0), (1, 2.0), (2, 1.0 + i % 3)] for i in range(300)]
+    lp = make(300, 3, rows, [5.0 + i / 100 for i in range(300)], [INF] * 300, [0, 1, 0], [3, 2, 5],
+              [1.0, 2.0, 1.0])
+    res = O.presolve(lp, **PC, enable_parallel_rows=0)
+    pc = _recs(res, "PARALLEL_COL")
+    assert [(int(r["j"]), int(r["k"]), float(r["v"][0])) for r in pc] == [(1, 0, 2.0)]
+    lbr = _recs(res, "LEADER_BOUNDS")[0]
+    assert (float(lbr["v"][2]), float(lbr["v"][3])) == (2.0, 7.0)
+    _check_optimal(lp, res)
 
 
 def test_merged_interval_past_inf_value_is_not_merged():
@@ -249,6 +263,79 @@ def test_tiny_planted_replay_optimal(seed):
         res = O.presolve(lp, **PC, **extra)
         replay_parallel_cols(lp, res)
         _check_optimal(lp, res)
+
+
+def with_long_parallel(seed, m=400, n=600, dense=6, copies=4):
+    """A random LP whose first `dense` columns sit in about half of the rows
+    (stored with far more than 64 entries), plus `copies` columns that are
+    lambda times dense ones (some of them, with a few of their entries on
+    rows that then get removed, in fewer alive rows than stored). Rows have
+    feasible sides around a random point."""
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(-1, 1, n + copies)
+    rows = []
+    for i in range(m):
+        cols = set(rng.choice(np.arange(dense, n), size=int(rng.integers(2, 6)), replace=False).tolist())
+        cols |= {j for j in range(dense) if rng.random() < 0.5}
+        rows.append({int(j): float(rng.choice([-2.0, -1.0, 1.0, 1.5, 3.0])) for j in cols})
+    srcs = rng.choice(dense, size=copies, replace=True)
+    c = list(rng.choice([0.0, 1.0, -1.0, 2.0], size=n))
+    lb = [-1.0 - rng.random() * 2 for _ in range(n)]
+    ub = [1.0 + rng.random() * 2 for _ in range(n)]
+    for t, j in enumerate(srcs):
+        lam = float(rng.choice([-2.0, 0.5, 3.0]))
+        for r in rows:
+            if int(j) in r:
+                r[n + t] = lam * r[int(j)]
+        c.append(lam * c[int(j)])
+        lb.append(float(rng.choice([-1.0, -INF])))
+        ub.append(float(rng.choice([2.0, INF])))
+    lhs, rhs = [], []
+    for r in rows:
+        act = sum(a * x0[j] for j, a in r.items())
+        kind = rng.random()
+        lhs.append(act - 1.0 if kind < 0.7 else -INF)
+        rhs.append(act + 1.0 if kind > 0.3 else INF)
+    return make(m, n + copies, [sorted(r.items()) for r in rows], lhs, rhs, lb, ub, c)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_long_parallel_family(seed):
+    lp = with_long_parallel(seed)
+    for extra in ({}, dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_rows=0)):
+        res = O.presolve(lp, **PC, **extra)
+        assert replay_parallel_cols(lp, res) >= 1
+        assert any(lp["row_ptr"][-1] and int(r["k"]) < 6 for r in _recs(res, "PARALLEL_COL"))
+        if res.result_name in ("REDUCED", "UNCHANGED"):
+            assert_no_parallel_left(res)
+        _check_optimal(lp, res)
+
+
+def assert_no_parallel_left(res):
+    """No two active columns of the reduced LP (each in at least one row)
+    are parallel: same rows, a_j = lambda a_k, c_j = lambda c_k."""
+    red = res.reduced
+    cols = _cols(red)
+    c = red["c"]
+    for j in range(red["n"]):
+        if not cols[j]:
+            continue
+        for k in range(j):
+            if set(cols[j]) != set(cols[k]) or (c[j] != 0) != (c[k] != 0):
+                continue
+            fj = c[j] if c[j] != 0 else cols[j][min(cols[j])]
+            fk = c[k] if c[k] != 0 else cols[k][min(cols[k])]
+            lam = fj / fk
+            same = all(abs(cols[j][i] - lam * cols[k][i]) <= 1e-12 * max(1.0, abs(cols[j][i])) for i in cols[j])
+            assert not same, (j, k, lam)
+
+
+@pytest.mark.parametrize("seed", range(300))
+def test_tiny_planted_complete(seed):
+    lp = with_parallel_copies(lpgen.tiny(seed, finite_bounds=seed % 2 == 0), seed)
+    res = O.presolve(lp, **PC)
+    if res.result_name in ("REDUCED", "UNCHANGED"):
+        assert_no_parallel_left(res)
 
 
 def test_tiny_planted_fire():
