@@ -3,16 +3,19 @@
 // parallel rows of [c A'] and merge into one variable x_k + lambda x_j, whose
 // interval is [lb_k, ub_k] + lambda [lb_j, ub_j].
 //
-// Candidates are the active columns in at least one alive row that are
-// stored with at most PC_MAX_LEN entries. Each gets a 31-bit key of its
-// augmented row (the cost as an entry of id 2^32 - 1 before the rows, rows in
-// the LP's own numbering, entries over the first one); the candidates are
-// sorted stably by key (and by LP in a batch), so that a group of equal keys
-// lists its columns in ascending order. The group's first column leads; its
-// thread verifies the others in order and adds their scaled intervals in that
-// order. Records in one pass over the columns (LEADER_BOUNDS for a leader,
-// PARALLEL_COL for a merged column); a merged column is set to 0, since the
-// leader carries it.
+// Candidates are the active columns in at least one alive row, of any length.
+// Each gets a 63-bit key of its augmented row (the cost as an entry of id
+// 2^32 - 1 before the rows, rows in the LP's own numbering, entries over the
+// first one): a thread per column of at most PC_SHORT stored entries, a
+// wavefront per longer one (the key is a sum modulo 2^64, so the lanes' order
+// does not matter). The candidates are sorted stably by key (two LSD passes
+// of four digits over the key's halves; then by LP in a batch), so that a group
+// of equal keys lists its columns in ascending order. The group's first column
+// leads; every other member is verified against it (a thread, or a wavefront
+// when either column is long) and the head adds their scaled intervals in
+// column order. Records in one pass over the columns (LEADER_BOUNDS for a
+// leader, PARALLEL_COL for a merged column); a merged column is set to 0,
+// since the leader carries it.
 #include <utility>
 
 #include "psl_kern.h"
@@ -20,8 +23,8 @@
 
 namespace psl {
 
-#define PC_MAX_LEN 64
-#define PC_NONE 0xFFFFFFFFu
+#define PC_SHORT 64
+#define PC_NONE 0xFFFFFFFFFFFFFFFFull
 
 __device__ __forceinline__ bool pc_lp_stopped(const Dev& d, int lp) {
   if (d.K > 1) return d.lp_ok[lp] == 0;
@@ -37,37 +40,94 @@ __device__ __forceinline__ double pc_first(const Dev& d, int j) {
   return 0.0;
 }
 
-__global__ void k_pc_keys(Dev d, ColScratch P) {
+// the same from one wavefront (every lane returns it)
+__device__ __forceinline__ double pc_first_wave(const Dev& d, int j) {
+  if (d.c[j] != 0.0) return d.c[j];
+  int q1 = d.cp[j + 1];
+  for (int q0 = d.cp[j]; q0 < q1; q0 += PSL_WAVE) {
+    int q = q0 + lane_id();
+    unsigned long long m = __ballot(q < q1 && d.row_on[d.ri[q]]);
+    if (m) return d.cva[q0 + __ffsll((long long)m) - 1];
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ bool pc_candidate(const Dev& d, int j) {
+  double2 b = d.bnd[j];
+  return b.x != b.y && d.col_len[j] >= 1 && !pc_lp_stopped(d, col_lp_of(d, j));
+}
+
+// the hash terms of entry q of column j (alive rows only)
+__device__ __forceinline__ void pc_term(const Dev& d, int q, int row0, double f, unsigned long long& h1,
+                                        unsigned long long& h2) {
+  int i = d.ri[q];
+  if (!d.row_on[i]) return;
+  unsigned long long id = splitmix((unsigned long long)(uint32_t)(i - row0));
+  h1 += 1 + id;
+  h2 += splitmix(id ^ quantize(d.cva[q] / f));
+}
+
+__device__ __forceinline__ void pc_cost_term(double c, double f, unsigned long long& h1, unsigned long long& h2) {
+  if (c == 0.0) return;
+  unsigned long long id = splitmix(0xFFFFFFFFull);
+  h1 += 1 + id;
+  h2 += splitmix(id ^ quantize(c / f));
+}
+
+__device__ __forceinline__ void pc_set_key(const ColScratch& P, int j, unsigned long long key) {
+  P.key[j] = key;
+  P.keys[j] = (uint32_t)key;
+}
+
+// keys of the short candidates; the long ones go to a list (n_long counts it)
+__global__ void k_pc_keys(Dev d, ColScratch P, int32_t* long_list, int32_t* n_long) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d.n) return;
   int j = (int)t;
   P.lead[j] = -1;
   P.vals[j] = j;
-  uint32_t key = PC_NONE;
-  double2 b = d.bnd[j];
-  int lp = col_lp_of(d, j);
-  int q0 = d.cp[j], q1 = d.cp[j + 1];
-  if (b.x != b.y && d.col_len[j] >= 1 && q1 - q0 <= PC_MAX_LEN && !pc_lp_stopped(d, lp)) {
+  unsigned long long key = PC_NONE;
+  if (pc_candidate(d, j)) {
+    int q0 = d.cp[j], q1 = d.cp[j + 1];
+    if (q1 - q0 > PC_SHORT) {
+      long_list[atomicAdd(n_long, 1)] = j;
+      return;  // keyed by k_pc_keys_long
+    }
+    int lp = col_lp_of(d, j);
     int row0 = d.K > 1 ? d.lp_row0[lp] : 0;
     double f = pc_first(d, j);
     unsigned long long h1 = 0, h2 = 0;
-    double c = d.c[j];
-    if (c != 0.0) {
-      unsigned long long id = splitmix(0xFFFFFFFFull);
-      h1 += 1 + id;
-      h2 += splitmix(id ^ quantize(c / f));
-    }
-    for (int q = q0; q < q1; ++q) {
-      int i = d.ri[q];
-      if (!d.row_on[i]) continue;
-      unsigned long long id = splitmix((unsigned long long)(uint32_t)(i - row0));
-      h1 += 1 + id;
-      h2 += splitmix(id ^ quantize(d.cva[q] / f));
-    }
-    key = (uint32_t)((splitmix(h1) ^ h2) >> 33);
+    pc_cost_term(d.c[j], f, h1, h2);
+    for (int q = q0; q < q1; ++q) pc_term(d, q, row0, f, h1, h2);
+    key = (splitmix(h1) ^ h2) >> 1;
   }
-  P.key[j] = key;
-  P.keys[j] = key;
+  pc_set_key(P, j, key);
+}
+
+// keys of the long candidates, one wavefront each
+__global__ void __launch_bounds__(PSL_BLOCK) k_pc_keys_long(Dev d, ColScratch P, const int32_t* long_list,
+                                                             const int32_t* n_long) {
+  int nl = *n_long;
+  int wstride = gridDim.x * (PSL_BLOCK / PSL_WAVE);
+  for (int w = blockIdx.x * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6); w < nl; w += wstride) {
+    int j = long_list[w];
+    int lp = col_lp_of(d, j);
+    int row0 = d.K > 1 ? d.lp_row0[lp] : 0;
+    double f = pc_first_wave(d, j);
+    unsigned long long h1 = 0, h2 = 0;
+    if (lane_id() == 0) pc_cost_term(d.c[j], f, h1, h2);
+    int q1 = d.cp[j + 1];
+    for (int q = d.cp[j] + lane_id(); q < q1; q += PSL_WAVE) pc_term(d, q, row0, f, h1, h2);
+    h1 = group_sum_u64<PSL_WAVE>(h1);
+    h2 = group_sum_u64<PSL_WAVE>(h2);
+    if (lane_id() == 0) pc_set_key(P, j, (splitmix(h1) ^ h2) >> 1);
+  }
+}
+
+// the high halves of the keys in the order of the sort by the low halves
+__global__ void k_pc_hikeys(Dev d, const int32_t* vals, const uint64_t* key, uint32_t* out) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < d.n) out[p] = (uint32_t)(key[vals[p]] >> 32);
 }
 
 // batch: the LP of each sorted column, for the sort by LP
@@ -102,11 +162,11 @@ __device__ __forceinline__ double pc_canon(const Cfg& c, double v) {
 
 // kind of each sorted position: 1 the first column of a group, 0 another
 // member of a group, 2 no candidate
-__global__ void k_pc_heads(Dev d, const int32_t* vals, const uint32_t* key, int32_t* kind) {
+__global__ void k_pc_heads(Dev d, const int32_t* vals, const uint64_t* key, int32_t* kind) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.n) return;
   int k = vals[p];
-  uint32_t kk = key[k];
+  uint64_t kk = key[k];
   int r = 2;
   if (kk != PC_NONE) {
     r = 1;
@@ -125,17 +185,11 @@ __global__ void k_pc_headpos(Dev d, const int32_t* kind, const int32_t* seg, int
   if (p < d.n && kind[p] == 1) heads[seg[p]] = (int)p;
 }
 
-// each other member against its group's first column; a merged member leaves
-// its scaled interval at its sorted position (NaN: not merged)
-__global__ void k_pc_verify(Dev d, ColScratch P, const int32_t* vals, const int32_t* kind, const int32_t* seg,
-                            const int32_t* heads) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= d.n || kind[p] != 0) return;
-  int j = vals[p];
-  int k = vals[heads[seg[p] - 1]];
-  double fj = pc_first(d, j), fk = pc_first(d, k);
+// a merged member's scaled interval at its sorted position (NaN: not merged)
+__device__ __forceinline__ void pc_member(const Dev& d, const ColScratch& P, int64_t p, int j, int k, bool par,
+                                          double fj, double fk) {
   double2 t = make_double2(__builtin_nan(""), 0.0);
-  if (pc_parallel(d, j, k, fj, fk)) {
+  if (par) {
     double lam = fj / fk;
     double2 bj = d.bnd[j];
     t = lam > 0 ? make_double2(lam * bj.x, lam * bj.y) : make_double2(lam * bj.y, lam * bj.x);
@@ -143,6 +197,67 @@ __global__ void k_pc_verify(Dev d, ColScratch P, const int32_t* vals, const int3
     P.lam[j] = lam;
   }
   P.terms[p] = t;
+}
+
+// each other member against its group's first column, by a thread when both
+// are short; the others go to a list (n_long counts it)
+__global__ void k_pc_verify(Dev d, ColScratch P, const int32_t* vals, const int32_t* kind, const int32_t* seg,
+                            const int32_t* heads, int32_t* long_list, int32_t* n_long) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.n || kind[p] != 0) return;
+  int j = vals[p];
+  int k = vals[heads[seg[p] - 1]];
+  if (d.cp[j + 1] - d.cp[j] > PC_SHORT || d.cp[k + 1] - d.cp[k] > PC_SHORT) {
+    long_list[atomicAdd(n_long, 1)] = (int)p;
+    return;
+  }
+  double fj = pc_first(d, j), fk = pc_first(d, k);
+  pc_member(d, P, p, j, k, pc_parallel(d, j, k, fj, fk), fj, fk);
+}
+
+// position of row i in column k (rows ascending), or -1
+__device__ __forceinline__ int pc_find(const Dev& d, int k, int i) {
+  int lo = d.cp[k], hi = d.cp[k + 1];
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (d.ri[mid] < i) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < d.cp[k + 1] && d.ri[lo] == i ? lo : -1;
+}
+
+// the listed members, one wavefront each: parallel when both columns are in
+// as many alive rows and every alive entry of the member is in the leader
+// (binary search) with the same normalised value within par_tol
+__global__ void __launch_bounds__(PSL_BLOCK) k_pc_verify_long(Dev d, ColScratch P, const int32_t* vals,
+                                                               const int32_t* seg, const int32_t* heads,
+                                                               const int32_t* long_list, const int32_t* n_long) {
+  int nl = *n_long;
+  int wstride = gridDim.x * (PSL_BLOCK / PSL_WAVE);
+  for (int w = blockIdx.x * (PSL_BLOCK / PSL_WAVE) + (threadIdx.x >> 6); w < nl; w += wstride) {
+    int64_t p = long_list[w];
+    int j = vals[p];
+    int k = vals[heads[seg[p] - 1]];
+    double fj = pc_first_wave(d, j), fk = pc_first_wave(d, k);
+    bool ok = (d.c[j] != 0.0) == (d.c[k] != 0.0) && d.col_len[j] == d.col_len[k];
+    int q1 = d.cp[j + 1];
+    for (int q0 = d.cp[j]; ok && q0 < q1; q0 += PSL_WAVE) {
+      int q = q0 + lane_id();
+      bool bad = false;
+      if (q < q1 && d.row_on[d.ri[q]]) {
+        int qk = pc_find(d, k, d.ri[q]);
+        if (qk < 0) {
+          bad = true;
+        } else {
+          double a = d.cva[q] / fj, bb = d.cva[qk] / fk;
+          double scale = fabs(a) > fabs(bb) ? fabs(a) : fabs(bb);
+          bad = !(fabs(a - bb) <= d.cfg.par_tol * scale);
+        }
+      }
+      ok = __ballot(bad) == 0;
+    }
+    if (lane_id() == 0) pc_member(d, P, p, j, k, ok, fj, fk);
+  }
 }
 
 // The fold of a group's member terms onto its leader's interval, members in
@@ -362,16 +477,27 @@ size_t par_cols_ws_ints(int64_t n) { return radix_ws_ints(n); }
 void launch_par_cols(const Dev& d, const ColScratch& P, int64_t base, int round, int32_t* ws, hipStream_t s) {
   if (d.n == 0) return;
   unsigned nb = (unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK);
-  hipLaunchKernelGGL(k_pc_keys, dim3(nb), dim3(PSL_BLOCK), 0, s, d, P);
-  // stable LSD sort of the columns by key (31 bits; non-candidates last)
+  // the long candidates' list in d.cnt (free until the count pass), its
+  // length in P.total
+  fill_i32(P.total, 0, 1, s);
+  hipLaunchKernelGGL(k_pc_keys, dim3(nb), dim3(PSL_BLOCK), 0, s, d, P, d.cnt, P.total);
+  hipLaunchKernelGGL(k_pc_keys_long, dim3(1024), dim3(PSL_BLOCK), 0, s, d, P, (const int32_t*)d.cnt,
+                     (const int32_t*)P.total);
+  // stable LSD sort of the columns by key (63 bits; non-candidates last):
+  // four passes over the low half, then four over the high half
   uint32_t* ka = P.keys;
   uint32_t* kb = P.keys2;
   int32_t* va = P.vals;
   int32_t* vb = P.vals2;
-  for (int shift = 0; shift < 32; shift += 8) {
-    radix_pass(ka, va, kb, vb, d.n, shift, 8, ws, s);
-    std::swap(ka, kb);
-    std::swap(va, vb);
+  for (int half = 0; half < 2; ++half) {
+    if (half == 1)
+      hipLaunchKernelGGL(k_pc_hikeys, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)va, (const uint64_t*)P.key,
+                         ka);
+    for (int shift = 0; shift < 32; shift += 8) {
+      radix_pass(ka, va, kb, vb, d.n, shift, 8, ws, s);
+      std::swap(ka, kb);
+      std::swap(va, vb);
+    }
   }
   if (d.K > 1) {  // then by LP, keeping the key order inside an LP
     hipLaunchKernelGGL(k_pc_lpkeys, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)va, ka);
@@ -386,14 +512,20 @@ void launch_par_cols(const Dev& d, const ColScratch& P, int64_t base, int round,
   int32_t* kind = reinterpret_cast<int32_t*>(ka);
   int32_t* seg = reinterpret_cast<int32_t*>(kb);
   int32_t* heads = vb;
-  hipLaunchKernelGGL(k_pc_heads, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)va, (const uint32_t*)P.key,
+  hipLaunchKernelGGL(k_pc_heads, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)va, (const uint64_t*)P.key,
                      kind);
   hipLaunchKernelGGL(k_pc_flag1, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)kind, seg);
   scan_excl(seg, seg, d.n, nullptr, ws, s);
   hipLaunchKernelGGL(k_pc_headpos, dim3(nb), dim3(PSL_BLOCK), 0, s, d, (const int32_t*)kind, (const int32_t*)seg,
                      heads);
+  // members with a long column: listed in the key array (free once the
+  // groups are known), verified by wavefronts
+  int32_t* long_list = reinterpret_cast<int32_t*>(P.key);
+  fill_i32(P.total, 0, 1, s);
   hipLaunchKernelGGL(k_pc_verify, dim3(nb), dim3(PSL_BLOCK), 0, s, d, P, (const int32_t*)va, (const int32_t*)kind,
-                     (const int32_t*)seg, (const int32_t*)heads);
+                     (const int32_t*)seg, (const int32_t*)heads, long_list, P.total);
+  hipLaunchKernelGGL(k_pc_verify_long, dim3(1024), dim3(PSL_BLOCK), 0, s, d, P, (const int32_t*)va,
+                     (const int32_t*)seg, (const int32_t*)heads, (const int32_t*)long_list, (const int32_t*)P.total);
   hipLaunchKernelGGL(k_pc_accum, dim3(nb), dim3(PSL_BLOCK), 0, s, d, P, (const int32_t*)va, (const int32_t*)kind);
   ColScratch Q = P;
   hipLaunchKernelGGL(k_pc_count, dim3(nb), dim3(PSL_BLOCK), 0, s, d, Q);

@@ -90,8 +90,8 @@ void init_locks(const Dev& d, int32_t* dn, int32_t* up, int32_t* ws, hipStream_t
 // base + d.flags->round_total, which it raises by its own count; merged LPs
 // flagged in d.flags->merged / d.lpf). Scratch of n entries each:
 struct ColScratch {
-  uint32_t* key;            // per column: its key (0xFFFFFFFF: no candidate)
-  uint32_t *keys, *keys2;   // sort keys
+  uint64_t* key;            // per column: its 63-bit key (all ones: no candidate)
+  uint32_t *keys, *keys2;   // sort keys (the key's low, then high half)
   int32_t *vals, *vals2;    // sort payload (columns)
   int32_t* lead;            // per column: its leader (itself for a leader), else -1
   double* lam;              // per merged column: lambda

@@ -16,7 +16,7 @@ from oracle import oracle as O
 from paper_2609_16182_amd import lpgen
 from tests.lp_utils import make
 from tests.parity_util import assert_same
-from tests.test_oracle_parcols import BASE_ROWS, with_parallel_copies
+from tests.test_oracle_parcols import BASE_ROWS, with_long_parallel, with_parallel_copies
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +44,25 @@ def test_tiny_planted(seed):
     lp = with_parallel_copies(lpgen.tiny(seed, finite_bounds=seed % 2 == 0), seed)
     got, ref = run_both(lp, **(ALL if seed % 3 == 0 else {}))
     assert_same(got, ref, f"tiny {seed}")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_long_columns(seed):
+    """Columns stored with about 200 entries and their scaled copies: keyed
+    and verified by wavefronts."""
+    lp = with_long_parallel(seed)
+    for extra in ({}, dict(ALL, enable_parallel_rows=0)):
+        got, ref = run_both(lp, **extra)
+        assert _n_pc(ref.records) >= 1
+        assert_same(got, ref, f"long {seed} {extra}")
+
+
+def test_long_hand_case():
+    rows = [[(0, 1.0), (1, 2.0), (2, 1.0 + i % 3)] for i in range(300)]
+    lp = make(300, 3, rows, [5.0 + i / 100 for i in range(300)], [INF] * 300, [0, 1, 0], [3, 2, 5], [1.0, 2.0, 1.0])
+    got, ref = run_both(lp, enable_parallel_rows=0)
+    assert _n_pc(ref.records) == 1
+    assert_same(got, ref, "long hand case")
 
 
 def test_hand_cases():
