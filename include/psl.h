@@ -140,8 +140,8 @@ typedef struct {
     int32_t enable_parallel_cols;  /* 1: after the parallel rows, parallel
                                       columns (section 3.2, "Parallel
                                       columns": parallel rows of [c A'] over
-                                      the alive rows, among columns stored
-                                      with at most 64 entries) merge into the
+                                      the alive rows, columns of any length)
+                                      merge into the
                                       first column of their group, whose
                                       interval becomes the sum of the scaled
                                       intervals (in column order; a group
@@ -174,6 +174,20 @@ typedef struct {
                                       column kept by a substitution takes part
                                       in no other (DOUBLETON_ROW). 0 (default)
                                       or 1.                                    */
+    int64_t device_records;        /* the postsolve stack (section 3.3): 0
+                                      (default) lets the device record buffer
+                                      grow as a run needs it; R > 0 keeps a
+                                      fixed device stack of R records that is
+                                      flushed to host memory (and emptied)
+                                      whenever the next phase's records might
+                                      not fit. R must hold one phase's worst
+                                      case, m + 3n + 16 records (2m + 3n + 16
+                                      with enable_doubletons), else
+                                      PSL_ERR_INVALID at create. Single-LP
+                                      presolvers only (batches and servers:
+                                      PSL_ERR_UNSUPPORTED); not with
+                                      psl_presolve_noalloc. Records, reduced
+                                      problem and postsolve are the same.     */
 } psl_settings;
 
 /* Postsolve record: 48 bytes, emitted in the order (round, phase, index,
@@ -247,6 +261,8 @@ typedef struct {
                                       column                                    */
     int64_t sweep_nnz;             /* nonzeros swept by those launches (each
                                       gathers its column's bounds once)         */
+    int64_t record_flushes;        /* flushes of the device record stack to
+                                      host memory (device_records > 0)          */
 } psl_stats;
 
 /* The reduced problem. DEVICE pointers owned by the handle, valid until the

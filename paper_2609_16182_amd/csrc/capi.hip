@@ -106,6 +106,7 @@ extern "C" void psl_settings_default(psl_settings* s) {
   s->enable_parallel_cols = 0;
   s->enable_forcing_rows = 0;
   s->enable_doubletons = 0;
+  s->device_records = 0;
 }
 
 std::string psl::check_settings(const psl_settings* s) {
@@ -120,6 +121,7 @@ std::string psl::check_settings(const psl_settings* s) {
   if (s->enable_parallel_cols != 0 && s->enable_parallel_cols != 1) return "enable_parallel_cols must be 0 or 1";
   if (s->enable_forcing_rows != 0 && s->enable_forcing_rows != 1) return "enable_forcing_rows must be 0 or 1";
   if (s->enable_doubletons != 0 && s->enable_doubletons != 1) return "enable_doubletons must be 0 or 1";
+  if (s->device_records < 0) return "device_records must be >= 0";
   if (s->bin_thresholds) {
     if (s->n_bins != 2 && s->n_bins != 3) return "bin_thresholds needs n_bins = 2 or 3";
     int a = s->bin_thresholds[0], b = s->bin_thresholds[1];
@@ -349,8 +351,9 @@ static psl_status setup_arena(psl_presolver* p) {
 
   // postsolve records: room for one record per row and two per column and
   // some; grown in a run when needed (in static-scratch mode: the rest of
-  // the scratch, and a run needing more fails with PSL_ERR_CAPACITY)
-  p->rec_cap = 2 * m + 4 * n + 1024;
+  // the scratch, and a run needing more fails with PSL_ERR_CAPACITY); a
+  // fixed stack of device_records records when that is set (flushed)
+  p->rec_cap = p->s.device_records > 0 ? p->s.device_records : 2 * m + 4 * n + 1024;
   if (p->carve) {
     int64_t rest = (int64_t)((p->carve_cap - p->carve_used) / sizeof(Record));
     if (rest > p->rec_cap) p->rec_cap = rest;
@@ -815,6 +818,14 @@ static void take_settings(psl_presolver* p, const psl_settings* s) {
   if (const char* e = std::getenv("PSL_TRACE")) p->trace = std::atoi(e) != 0;
 }
 
+// records one phase may add: a round (a row record per row, two bound changes
+// and a fixing per column) or a parallel pass (with doubletons: two per row)
+static int64_t phase_records(const psl_settings* s, int64_t m, int64_t n) {
+  int64_t round = m + 3 * n + 16;
+  int64_t pass = (s->enable_doubletons ? 2 * m + 3 * n : m + n) + 16;
+  return std::max(round, pass);
+}
+
 extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* s, psl_presolver** out) {
   if (!lp || !out) {
     g_create_error = "null argument";
@@ -825,6 +836,8 @@ extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* 
   if (!s) s = &def;
   std::string e = check_settings(s);
   if (e.empty()) e = check_lp_shape(lp);
+  if (e.empty() && s->device_records > 0 && s->device_records < phase_records(s, lp->m, lp->n))
+    e = "device_records must hold one phase's records: at least " + std::to_string(phase_records(s, lp->m, lp->n));
   if (!e.empty()) {
     g_create_error = e;
     return PSL_ERR_INVALID;
@@ -863,8 +876,22 @@ extern "C" psl_status psl_presolve_reload(psl_presolver* p, const psl_lp* lp) {
   return st;
 }
 
+// Room for `need` more records on the device: a fixed stack (device_records
+// > 0) is flushed to host memory and emptied; otherwise the buffer grows.
 static psl_status ensure_capacity(psl_presolver* p, int64_t need) {
-  if (p->rec_count + need <= p->rec_cap) return PSL_OK;
+  int64_t used = p->rec_count - p->rec_flushed;
+  if (used + need <= p->rec_cap) return PSL_OK;
+  if (p->s.device_records > 0) {
+    if (need > p->rec_cap) return fail(p, PSL_ERR_CAPACITY, "a phase's records exceed device_records");
+    size_t at = p->flushed.size();
+    p->flushed.resize(at + (size_t)used);
+    HIPCHK(p, hipMemcpyAsync(p->flushed.data() + at, p->rec, used * sizeof(Record), hipMemcpyDeviceToHost,
+                             p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    p->rec_flushed = p->rec_count;
+    p->flushes += 1;
+    return PSL_OK;
+  }
   if (p->carve) return fail(p, PSL_ERR_CAPACITY, "the postsolve records outgrow the static scratch");
   int64_t cap = std::max<int64_t>(2 * p->rec_cap, p->rec_count + need + 1024);
   Record* nr = nullptr;
@@ -961,6 +988,9 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   psl_stats S{};
   S.nnz_in = p->nnz;
   p->rec_count = 0;
+  p->rec_flushed = 0;
+  p->flushes = 0;
+  p->flushed.clear();
   p->host_rec_valid = false;
   p->lp_host_rec.clear();
   p->state = 1;
@@ -1042,10 +1072,11 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       launch_sweep(d, p->grid, p->sweep_mode, st);
       HIPCHK(p, hipEventRecord(p->ev[5], st));
       launch_src(d, p->grid, st);
-      launch_decide(d, p->rec_count, round, d.cnt, d.off, p->ws, st);
+      launch_decide(d, p->rec_count - p->rec_flushed, round, d.cnt, d.off, p->ws, st);
       // (the candidate regions are free until the next sweep)
       if (s.enable_free_singletons)
-        launch_free_singletons(d, reinterpret_cast<int32_t*>(d.cand), p->rec_count, round, p->ws, st);
+        launch_free_singletons(d, reinterpret_cast<int32_t*>(d.cand), p->rec_count - p->rec_flushed, round, p->ws,
+                               st);
       HIPCHK(p, hipEventRecord(p->ev[6], st));
       // The next round's selection is made before the round's one read, in
       // one pass over the rows. Rows none of whose columns changed since they
@@ -1146,20 +1177,20 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       launch_par_verify(d, p->par, st);
       launch_par_count(d, p->par, st);
       scan_excl(d.cnt, d.off, m, &d.flags->round_total, p->ws, st);
-      launch_par_emit(d, p->par, p->rec_count, round, st);
+      launch_par_emit(d, p->par, p->rec_count - p->rec_flushed, round, st);
       launch_par_drop(d, p->par, st);
     } else {
       fill_i32(&d.flags->round_total, 0, 1, st);
     }
     // parallel columns on the rows the row pass left (an LP it found
     // infeasible has stopped)
-    if (s.enable_parallel_cols) launch_par_cols(d, p->pc, p->rec_count, round, p->ws, st);
+    if (s.enable_parallel_cols) launch_par_cols(d, p->pc, p->rec_count - p->rec_flushed, round, p->ws, st);
     if (s.enable_doubletons) {
       // active lengths and removed-column constants after the parallel
       // passes (row_out), then the substitutions
       launch_long_stats(d, MODE_COMPACT, st);
       launch_sweep(d, p->grid, MODE_COMPACT, st);
-      launch_doubletons(d, p->dbl, p->rec_count, round, p->ws, st);
+      launch_doubletons(d, p->dbl, p->rec_count - p->rec_flushed, round, p->ws, st);
     }
     HIPCHK(p, hipEventRecord(p->ev[5], st));
     e = queue_lp_read(p, false);
@@ -1257,6 +1288,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   S.outer_cycles = 1;
   for (auto& L : p->lst) S.outer_cycles = std::max(S.outer_cycles, L.cycles);
   S.records = p->rec_count;
+  S.record_flushes = p->flushes;
   S.nnz_out = p->red_nnz;
   S.m_out = p->red_m;
   S.n_out = p->red_n;
@@ -1331,10 +1363,13 @@ extern "C" psl_status psl_reduced_problem(const psl_presolver* p, psl_reduced_vi
 static psl_status fetch_lp_records(psl_presolver* p, int k, const std::vector<psl_record>** out) {
   if (p->K == 1) {
     if (!p->host_rec_valid) {
+      // the flushed records, then the device stack's
+      int64_t dev = p->rec_count - p->rec_flushed;
       p->host_rec.resize((size_t)p->rec_count);
-      if (p->rec_count) {
-        HIPCHK(p, hipMemcpyAsync(p->host_rec.data(), p->rec, p->rec_count * sizeof(Record), hipMemcpyDeviceToHost,
-                                 p->stream));
+      if (p->rec_flushed) std::memcpy(p->host_rec.data(), p->flushed.data(), p->rec_flushed * sizeof(psl_record));
+      if (dev) {
+        HIPCHK(p, hipMemcpyAsync(p->host_rec.data() + p->rec_flushed, p->rec, dev * sizeof(Record),
+                                 hipMemcpyDeviceToHost, p->stream));
         HIPCHK(p, hipStreamSynchronize(p->stream));
       }
       p->host_rec_valid = true;
@@ -1629,6 +1664,10 @@ extern "C" psl_status psl_batch_create(int32_t k, const psl_lp* lps, const psl_s
   if (!e.empty()) {
     g_batch_error = e;
     return PSL_ERR_INVALID;
+  }
+  if (s->device_records > 0) {
+    g_batch_error = "device_records (a flushed record stack) is for single-LP presolvers";
+    return PSL_ERR_UNSUPPORTED;
   }
   if (hipSetDevice(s->device) != hipSuccess) {
     g_batch_error = "cannot select the device";

@@ -117,6 +117,11 @@ struct psl_presolver {
   // records
   Record* rec = nullptr;
   int64_t rec_cap = 0, rec_count = 0;
+  // the postsolve stack with flushing (settings.device_records > 0): records
+  // [0, rec_flushed) are in `flushed` on the host, the rest on the device
+  // from rec[0]; new records go to rec[rec_count - rec_flushed]
+  int64_t rec_flushed = 0, flushes = 0;
+  std::vector<psl_record> flushed;
   std::vector<psl_record> host_rec;
   bool host_rec_valid = false;
 

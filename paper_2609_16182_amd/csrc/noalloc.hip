@@ -71,6 +71,8 @@ extern "C" psl_status psl_presolve_noalloc(const psl_lp* lp, const psl_settings*
   std::string e = psl::check_settings(s);
   if (e.empty()) e = psl::check_lp_shape(lp);
   if (!e.empty()) return reject(PSL_ERR_INVALID, e);
+  if (s->device_records > 0)
+    return reject(PSL_ERR_UNSUPPORTED, "device_records (a flushed record stack) needs a presolver handle");
   bool rows = lp->m > 0, cols = lp->n > 0, ents = lp->nnz > 0;
   if (!out->row_ptr || !out->col_ptr || (rows && (!out->lhs || !out->rhs || !out->row_map || !out->row_class)) ||
       (cols && (!out->lb || !out->ub || !out->c || !out->col_map || !out->col_class)) ||

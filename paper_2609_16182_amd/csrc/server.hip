@@ -453,6 +453,10 @@ extern "C" psl_status psl_server_create(const psl_server_config* c, const psl_se
     g_server_error = e;
     return PSL_ERR_INVALID;
   }
+  if (s->device_records > 0) {
+    g_server_error = "device_records (a flushed record stack) is for single-LP presolvers";
+    return PSL_ERR_UNSUPPORTED;
+  }
   if (hipSetDevice(s->device) != hipSuccess) {
     g_server_error = "cannot select the device";
     return PSL_ERR_DEVICE;

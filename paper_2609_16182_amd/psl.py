@@ -43,7 +43,8 @@ class psl_settings(C.Structure):
                 ("bin_thresholds", C.c_void_p), ("n_bins", C.c_int32), ("device", C.c_int32),
                 ("stream", C.c_void_p), ("split_sweep", C.c_int32), ("enable_dual_fix", C.c_int32),
                 ("enable_free_singletons", C.c_int32), ("enable_parallel_cols", C.c_int32),
-                ("enable_forcing_rows", C.c_int32), ("enable_doubletons", C.c_int32)]
+                ("enable_forcing_rows", C.c_int32), ("enable_doubletons", C.c_int32),
+                ("device_records", C.c_int64)]
 
 
 class psl_stats(C.Structure):
@@ -52,7 +53,8 @@ class psl_stats(C.Structure):
                 ("ms_ingest", C.c_double), ("ms_sweep", C.c_double), ("ms_decide", C.c_double),
                 ("ms_parallel", C.c_double), ("ms_compact", C.c_double), ("ms_total", C.c_double),
                 ("sweep_launches", C.c_int64), ("sweep_bytes", C.c_double), ("ms_long", C.c_double),
-                ("alg_bytes", C.c_double), ("ingest_bytes", C.c_double), ("sweep_nnz", C.c_int64)]
+                ("alg_bytes", C.c_double), ("ingest_bytes", C.c_double), ("sweep_nnz", C.c_int64),
+                ("record_flushes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
