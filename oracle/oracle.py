@@ -26,7 +26,7 @@ assert RECORD_DTYPE.itemsize == 48
 REC_NAMES = {1: "FIX_COL", 2: "EMPTY_COL", 3: "EMPTY_ROW", 4: "REDUNDANT_ROW",
              5: "SINGLETON_ROW", 6: "BOUND_CHANGE", 7: "PARALLEL_ROW", 8: "LEADER_SIDES",
              9: "DUAL_FIX", 10: "FREE_SINGLETON", 11: "PARALLEL_COL", 12: "LEADER_BOUNDS",
-             13: "FORCING_ROW", 14: "DOUBLETON_ROW"}
+             13: "FORCING_ROW", 14: "DOUBLETON_ROW", 15: "DOMINATED_COL"}
 REC = {v: k for k, v in REC_NAMES.items()}
 RESULT_NAMES = {0: "REDUCED", 1: "UNCHANGED", 2: "INFEASIBLE", 3: "UNBOUNDED_OR_INFEASIBLE"}
 
@@ -35,7 +35,7 @@ RESULT_NAMES = {0: "REDUCED", 1: "UNCHANGED", 2: "INFEASIBLE", 3: "UNBOUNDED_OR_
 DEFAULTS = dict(max_rounds=16, max_outer=4, enable_parallel_rows=1,
                 feas_tol=1e-9, fix_tol=1e-9, min_improve=1e-7, par_tol=1e-9,
                 inf_value=1e20, coef_tol=1e-9, enable_dual_fix=0, enable_free_singletons=0,
-                enable_parallel_cols=0, enable_forcing_rows=0, enable_doubletons=0)
+                enable_parallel_cols=0, enable_forcing_rows=0, enable_doubletons=0, enable_dominated=0)
 
 
 class _LP(C.Structure):
@@ -53,7 +53,7 @@ class _Settings(C.Structure):
                 ("inf_value", C.c_double), ("coef_tol", C.c_double),
                 ("enable_dual_fix", C.c_int32), ("enable_free_singletons", C.c_int32),
                 ("enable_parallel_cols", C.c_int32), ("enable_forcing_rows", C.c_int32),
-                ("enable_doubletons", C.c_int32)]
+                ("enable_doubletons", C.c_int32), ("enable_dominated", C.c_int32)]
 
 
 def build(force=False, extra_flags=()):
@@ -206,7 +206,8 @@ def presolve(lp, lib_path=None, **settings):
     cs = _Settings(int(s["max_rounds"]), int(s["max_outer"]), int(s["enable_parallel_rows"]),
                    s["feas_tol"], s["fix_tol"], s["min_improve"], s["par_tol"],
                    s["inf_value"], s["coef_tol"], int(s["enable_dual_fix"]), int(s["enable_free_singletons"]),
-                   int(s["enable_parallel_cols"]), int(s["enable_forcing_rows"]), int(s["enable_doubletons"]))
+                   int(s["enable_parallel_cols"]), int(s["enable_forcing_rows"]), int(s["enable_doubletons"]),
+                   int(s["enable_dominated"]))
     h = C.c_void_p()
     st = lib.or_presolve(C.byref(clp), C.byref(cs), C.byref(h))
     if st != 0:

@@ -79,16 +79,15 @@ enum { RES_REDUCED = 0, RES_UNCHANGED = 1, RES_INFEASIBLE = 2, RES_UNBOUNDED = 3
  *  DOUBLETON_ROW  i = the equality row, j = the kept column, k = the
  *                 eliminated one; v = {a_ij, a_ik, b (the row's side moved by
  *                 its removed columns' constant), c_k (then)}
+ *  DOMINATED_COL  j, side (0 fixed at its lower, 1 at its upper bound);
+ *                 v = {value, c_j}
  */
 enum {
     REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
     REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
     REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10, REC_PARALLEL_COL = 11, REC_LEADER_BOUNDS = 12,
-    REC_FORCING_ROW = 13, REC_DOUBLETON_ROW = 14
+    REC_FORCING_ROW = 13, REC_DOUBLETON_ROW = 14, REC_DOMINATED_COL = 15
 };
-
-/* parallel columns are searched among columns stored with at most this many
- * entries */
 
 /* classes of the reduced problem's rows and columns (listed, not applied) */
 enum { RCLS_OTHER = 0, RCLS_SINGLETON = 1, RCLS_DOUBLETON_EQ = 2, RCLS_DOUBLETON_INEQ = 3 };
@@ -244,6 +243,7 @@ static int validate_and_copy(or_handle *h, const or_lp *lp, const or_settings *s
         return fail(h, "invalid free-singleton switch");
     if (s->enable_forcing_rows != 0 && s->enable_forcing_rows != 1) return fail(h, "invalid settings");
     if (s->enable_doubletons != 0 && s->enable_doubletons != 1) return fail(h, "invalid settings");
+    if (s->enable_dominated != 0 && s->enable_dominated != 1) return fail(h, "invalid settings");
     if (s->enable_parallel_cols != 0 && s->enable_parallel_cols != 1)
         return fail(h, "invalid parallel-column switch");
     if (lp->m < 0 || lp->n < 0 || lp->nnz < 0) return fail(h, "negative size");
@@ -1024,6 +1024,107 @@ static int parallel_cols(or_handle *h) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* dominated columns through implied dual bounds (a dual explorer, section    */
+/* 2.1; reading R-DomCol)                                                     */
+/* ------------------------------------------------------------------------- */
+
+/* Bounds on the row duals y (c - A'y - z = 0) that every optimal solution of
+ * the current problem satisfies: an alive row with only a finite lhs has
+ * y_i >= 0, with only a finite rhs y_i <= 0; and an active column j in one
+ * alive row i (coefficient a, |a| >= coef_tol) has z_j >= 0 when ub_j = +inf
+ * and z_j <= 0 when lb_j = -inf, i.e. a y_i <= c_j, resp. a y_i >= c_j.
+ * Then for every active column k in at least one alive row, z_k lies in
+ * [c_k - sum_i max(a_ik y_i), c_k - sum_i min(a_ik y_i)] over those bounds
+ * (each sum canonical pairwise over the column's stored positions, the other
+ * positions contributing +0; an infinite term makes that end infinite). A
+ * lower end above feas_tol * max(1, |c_k|) puts x_k at its lower bound in
+ * every optimal solution, an upper end below -feas_tol * max(1, |c_k|) at its
+ * upper bound; an infinite such bound means the LP is unbounded if feasible.
+ * All fixings of the pass are taken from the problem before it (each holds
+ * in every optimal solution, so together too); records in column order. The
+ * bounds hold for every dual-feasible y, so bounds of a row that cross by
+ * more than feas_tol * max(1, |upper|) leave no dual solution: the LP is
+ * unbounded if it is feasible; a smaller crossing changes nothing. */
+static int dominated_cols(or_handle *h) {
+    const or_settings *s = &h->s;
+    int32_t m = h->m, n = h->n;
+    double *ylo = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    double *yhi = (double *)xcalloc((size_t)m + 1, sizeof(double));
+    for (int32_t i = 0; i < m; ++i) {
+        ylo[i] = yhi[i] = 0.0;
+        if (!h->row_on[i]) continue;
+        int lf = !isinf(h->lhs[i]), rf = !isinf(h->rhs[i]);
+        if (!lf && !rf) continue;
+        ylo[i] = lf && !rf ? 0.0 : -INFINITY;
+        yhi[i] = rf && !lf ? 0.0 : INFINITY;
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        if (!h->col_on[j] || h->col_len[j] != 1) continue;
+        int32_t i = -1;
+        double a = 0.0;
+        for (int32_t q = h->cp[j]; q < h->cp[j + 1]; ++q)
+            if (h->row_on[h->ri[q]]) { i = h->ri[q]; a = h->cva[q]; }
+        if (i < 0 || fabs(a) < s->coef_tol) continue;
+        double v = h->c[j] / a;
+        if (isinf(h->ub[j])) {
+            if (a > 0) yhi[i] = v < yhi[i] ? v : yhi[i];
+            else ylo[i] = v > ylo[i] ? v : ylo[i];
+        }
+        if (isinf(h->lb[j])) {
+            if (a > 0) ylo[i] = v > ylo[i] ? v : ylo[i];
+            else yhi[i] = v < yhi[i] ? v : yhi[i];
+        }
+    }
+    for (int32_t i = 0; i < m; ++i)
+        if (ylo[i] > yhi[i]) {
+            if (ylo[i] > yhi[i] + tol_of(s, yhi[i])) h->result = RES_UNBOUNDED;
+            free(ylo); free(yhi);
+            return 0;
+        }
+    int64_t maxlen = 0;
+    for (int32_t j = 0; j < n; ++j)
+        if (h->cp[j + 1] - h->cp[j] > maxlen) maxlen = h->cp[j + 1] - h->cp[j];
+    double *thi = (double *)xcalloc((size_t)maxlen + 1, sizeof(double));
+    double *tlo = (double *)xcalloc((size_t)maxlen + 1, sizeof(double));
+    int8_t *side = (int8_t *)xcalloc((size_t)n + 1, 1);
+    for (int32_t k = 0; k < n; ++k) {
+        side[k] = -1;
+        if (!h->col_on[k] || h->col_len[k] < 1) continue;
+        int64_t len = h->cp[k + 1] - h->cp[k];
+        int inf_hi = 0, inf_lo = 0;
+        for (int64_t t = 0; t < len; ++t) {
+            int32_t q = h->cp[k] + (int32_t)t;
+            double a = h->cva[q];
+            int32_t i = h->ri[q];
+            thi[t] = tlo[t] = 0.0;
+            if (!h->row_on[i] || a == 0.0) continue;
+            double hi = a > 0 ? a * yhi[i] : a * ylo[i];  /* max of a y_i */
+            double lo = a > 0 ? a * ylo[i] : a * yhi[i];  /* min of a y_i */
+            if (isinf(hi)) inf_hi++; else thi[t] = pos0(hi);
+            if (isinf(lo)) inf_lo++; else tlo[t] = pos0(lo);
+        }
+        double ck = h->c[k], tol = tol_of(s, ck);
+        if (inf_hi == 0 && ck - or_pairwise_sum(thi, len) > tol) side[k] = 0;
+        else if (inf_lo == 0 && ck - or_pairwise_sum(tlo, len) < -tol) side[k] = 1;
+    }
+    int any = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        if (side[k] < 0) continue;
+        double v = side[k] == 0 ? h->lb[k] : h->ub[k];
+        if (isinf(v)) {
+            h->result = RES_UNBOUNDED;
+            continue;
+        }
+        push(h, REC_DOMINATED_COL, side[k], -1, k, -1, v, h->c[k], 0, 0);
+        h->lb[k] = h->ub[k] = v;
+        h->col_on[k] = 0;
+        any = 1;
+    }
+    free(ylo); free(yhi); free(thi); free(tlo); free(side);
+    return any;
+}
+
+/* ------------------------------------------------------------------------- */
 /* reduced problem (section 3.3)                                              */
 /* ------------------------------------------------------------------------- */
 
@@ -1429,11 +1530,17 @@ int or_presolve(const or_lp *lp, const or_settings *s, or_handle **out) {
             if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
             if (!changed) break;
         }
-        if (stop || (!s->enable_parallel_rows && !s->enable_parallel_cols && !s->enable_doubletons)) break;
+        if (stop || (!s->enable_parallel_rows && !s->enable_parallel_cols && !s->enable_doubletons &&
+                     !s->enable_dominated))
+            break;
         h->round++;
         int merged = s->enable_parallel_rows ? parallel_rows(h) : 0;
         if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
         if (s->enable_parallel_cols) merged |= parallel_cols(h);
+        if (s->enable_dominated) {
+            merged |= dominated_cols(h);
+            if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
+        }
         if (s->enable_doubletons) {
             merged |= doubleton_pass(h);
             if (h->result >= RES_INFEASIBLE) { stop = 1; break; }
@@ -1478,8 +1585,8 @@ int or_activities(const or_lp *lp, double *minact, double *maxact,
 
 /* ------------------------------------------------------------------------- */
 /* postsolve (primal): kept columns from the reduced solution, removed ones   */
-/* from their FIX_COL / EMPTY_COL / DUAL_FIX records (constants); then, last  */
-/* record first:                                                              */
+/* from their FIX_COL / EMPTY_COL / DUAL_FIX / DOMINATED_COL records         */
+/* (constants); then, last record first:                                      */
 /*   FREE_SINGLETON  with r = the row's other terms (its original entries,    */
 /*       left to right) and s = r clamped to the sides the row had,           */
 /*       x_j = (s - r) / a_ij;                                                */
@@ -1539,7 +1646,9 @@ int or_postsolve(const or_handle *h, const double *x_red, double *x) {
     for (int32_t rj = 0; rj < h->rn; ++rj) x[h->r_colmap[rj]] = x_red[rj];
     for (int64_t t = h->nrec - 1; t >= 0; --t) {
         const or_record *r = &h->rec[t];
-        if (r->type == REC_FIX_COL || r->type == REC_EMPTY_COL || r->type == REC_DUAL_FIX) x[r->j] = r->v[0];
+        if (r->type == REC_FIX_COL || r->type == REC_EMPTY_COL || r->type == REC_DUAL_FIX ||
+            r->type == REC_DOMINATED_COL)
+            x[r->j] = r->v[0];
     }
     for (int64_t t = h->nrec - 1; t >= 0; --t) {
         const or_record *r = &h->rec[t];

@@ -37,6 +37,7 @@ typedef struct {
     int32_t enable_parallel_cols;    /* 1: parallel columns in the parallel pass */
     int32_t enable_forcing_rows;     /* 1: forcing rows in every round */
     int32_t enable_doubletons;       /* 1: doubleton-equality substitution pass */
+    int32_t enable_dominated;        /* 1: dominated columns (implied dual bounds) pass */
 } or_settings;
 
 /* 48-byte postsolve record; the field meaning per type is listed in the .c */
