@@ -181,13 +181,28 @@ typedef struct {
                                       flushed to host memory (and emptied)
                                       whenever the next phase's records might
                                       not fit. R must hold one phase's worst
-                                      case, m + 3n + 16 records (2m + 3n + 16
-                                      with enable_doubletons), else
+                                      case, the larger of m + 3n + 16 (a
+                                      round) and m + n + 16 (a parallel pass)
+                                      plus n with enable_dominated and m + 2n
+                                      with enable_doubletons, else
                                       PSL_ERR_INVALID at create. Single-LP
                                       presolvers only (batches and servers:
                                       PSL_ERR_UNSUPPORTED); not with
                                       psl_presolve_noalloc. Records, reduced
                                       problem and postsolve are the same.     */
+    int32_t enable_dominated;      /* 1: dominated columns once per outer cycle
+                                      after the parallel columns (a dual
+                                      explorer, section 2.1): row duals are
+                                      bounded by the sides' signs and by column
+                                      singletons (no upper bound: z >= 0, no
+                                      lower bound: z <= 0); a column whose
+                                      reduced cost is then above feas_tol *
+                                      max(1, |c|) for every such dual is fixed
+                                      at its lower bound, below the negative
+                                      tolerance at its upper bound
+                                      (DOMINATED_COL; an infinite one, or
+                                      crossing dual bounds: unbounded or
+                                      infeasible). 0 (default) or 1.           */
 } psl_settings;
 
 /* Postsolve record: 48 bytes, emitted in the order (round, phase, index,
@@ -224,6 +239,8 @@ typedef struct {
  *                         row's side less its removed columns' constant (only
  *                         with enable_doubletons; the bounds it moves to x_j
  *                         follow as BOUND_CHANGE records from row i)
+ *   type 15 DOMINATED_COL j, side 0 (at its lower bound) or 1 (upper);
+ *                         v = {value, c_j} (only with enable_dominated)
  * round 0 holds input fixings; each propagation round and each parallel-row
  * pass has its own round number. */
 typedef struct {

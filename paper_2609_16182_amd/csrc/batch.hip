@@ -124,7 +124,8 @@ __global__ void k_rec_keys(Dev d, const Record* rec, int64_t count, uint32_t* ke
   if (t >= count) return;
   Record r = rec[t];
   bool col = r.type == REC_FIX_COL || r.type == REC_EMPTY_COL || r.type == REC_BOUND_CHANGE ||
-             r.type == REC_DUAL_FIX || r.type == REC_PARALLEL_COL || r.type == REC_LEADER_BOUNDS;
+             r.type == REC_DUAL_FIX || r.type == REC_PARALLEL_COL || r.type == REC_LEADER_BOUNDS ||
+             r.type == REC_DOMINATED_COL;
   keys[t] = (uint32_t)(col ? d.col_lp[r.j] : d.row_lp[r.i]);
 }
 
@@ -145,6 +146,7 @@ __global__ void k_rec_gather(Dev d, const Record* rec, const uint32_t* keys, con
     case REC_FIX_COL:
     case REC_EMPTY_COL:
     case REC_DUAL_FIX:
+    case REC_DOMINATED_COL:
     case REC_LEADER_BOUNDS:
       r.j = local_idx(r.j, j0);
       break;

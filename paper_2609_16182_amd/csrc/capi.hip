@@ -107,6 +107,7 @@ extern "C" void psl_settings_default(psl_settings* s) {
   s->enable_forcing_rows = 0;
   s->enable_doubletons = 0;
   s->device_records = 0;
+  s->enable_dominated = 0;
 }
 
 std::string psl::check_settings(const psl_settings* s) {
@@ -122,6 +123,7 @@ std::string psl::check_settings(const psl_settings* s) {
   if (s->enable_forcing_rows != 0 && s->enable_forcing_rows != 1) return "enable_forcing_rows must be 0 or 1";
   if (s->enable_doubletons != 0 && s->enable_doubletons != 1) return "enable_doubletons must be 0 or 1";
   if (s->device_records < 0) return "device_records must be >= 0";
+  if (s->enable_dominated != 0 && s->enable_dominated != 1) return "enable_dominated must be 0 or 1";
   if (s->bin_thresholds) {
     if (s->n_bins != 2 && s->n_bins != 3) return "bin_thresholds needs n_bins = 2 or 3";
     int a = s->bin_thresholds[0], b = s->bin_thresholds[1];
@@ -298,6 +300,12 @@ static psl_status setup_arena(psl_presolver* p) {
     ALLOC(p->cp0, n + 1);
     ALLOC(p->ri0, N);
     ALLOC(p->cva0, N);
+  }
+  if (p->s.enable_dominated) {
+    ALLOC(p->dom.ykey, 2 * m);
+    ALLOC(p->dom.side, n);
+    ALLOC(p->dom.lp_flag, K);
+    ALLOC(p->dom.total, 1);
   }
   if (p->s.enable_parallel_cols) {
     ALLOC(p->pc.key, n);
@@ -819,11 +827,15 @@ static void take_settings(psl_presolver* p, const psl_settings* s) {
 }
 
 // records one phase may add: a round (a row record per row, two bound changes
-// and a fixing per column) or a parallel pass (with doubletons: two per row)
+// and a fixing per column) or a parallel pass (a record per row and column for
+// the parallel rows and columns, one per column for dominated columns, and
+// for doubletons one per row and two per column)
+static int64_t pass_records(const psl_settings* s, int64_t m, int64_t n) {
+  return m + n + (s->enable_dominated ? n : 0) + (s->enable_doubletons ? m + 2 * n : 0) + 16;
+}
+
 static int64_t phase_records(const psl_settings* s, int64_t m, int64_t n) {
-  int64_t round = m + 3 * n + 16;
-  int64_t pass = (s->enable_doubletons ? 2 * m + 3 * n : m + n) + 16;
-  return std::max(round, pass);
+  return std::max(m + 3 * n + 16, pass_records(s, m, n));
 }
 
 extern "C" psl_status psl_presolve_create(const psl_lp* lp, const psl_settings* s, psl_presolver** out) {
@@ -1151,7 +1163,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     for (auto& L : p->lst)
       if (L.phase != LP_DONE) ++npar;
     if (npar == 0) break;
-    if (!s.enable_parallel_rows && !s.enable_parallel_cols && !s.enable_doubletons) {
+    if (!s.enable_parallel_rows && !s.enable_parallel_cols && !s.enable_doubletons && !s.enable_dominated) {
       for (auto& L : p->lst) L.phase = LP_DONE;
       break;
     }
@@ -1163,7 +1175,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       }
     e = use_full_view(p);
     // row records, then column records (and a substitution pass's)
-    if (e == PSL_OK) e = ensure_capacity(p, (s.enable_doubletons ? 2 * m + 3 * n : m + n) + 16);
+    if (e == PSL_OK) e = ensure_capacity(p, pass_records(&s, m, n));
     if (e == PSL_OK) e = begin_lp_round(p);
     if (e != PSL_OK) return e;
     HIPCHK(p, hipEventRecord(p->ev[4], st));
@@ -1185,6 +1197,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
     // parallel columns on the rows the row pass left (an LP it found
     // infeasible has stopped)
     if (s.enable_parallel_cols) launch_par_cols(d, p->pc, p->rec_count - p->rec_flushed, round, p->ws, st);
+    if (s.enable_dominated) launch_dominated(d, p->dom, p->rec_count - p->rec_flushed, round, p->ws, st);
     if (s.enable_doubletons) {
       // active lengths and removed-column constants after the parallel
       // passes (row_out), then the substitutions
@@ -1217,6 +1230,9 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
       if (lp_inf(k)) {
         L.phase = LP_DONE;
         L.infeasible = true;
+      } else if (lp_unb(k)) {  // dominated columns: an infinite fixing or crossing dual bounds
+        L.phase = LP_DONE;
+        L.unbounded = true;
       } else if (lp_merged(k) && outer + 1 < s.max_outer) {
         L.phase = LP_PROP;
       } else {

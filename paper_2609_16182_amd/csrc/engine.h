@@ -128,6 +128,7 @@ struct psl_presolver {
   ParScratch par{};
   psl::ColScratch pc{};  // parallel columns (allocated when enabled)
   psl::DblScratch dbl{};  // doubleton substitution (allocated when enabled)
+  psl::DomScratch dom{};  // dominated columns (allocated when enabled)
   // the input's transposed copy, kept when substitutions rewrite the rows (the
   // dual postsolve reads the input's columns)
   int32_t *cp0 = nullptr, *ri0 = nullptr;

@@ -55,7 +55,8 @@ namespace {
 // documentation in psl.h).
 enum : uint8_t {
   T_FIX_COL = 1, T_EMPTY_COL = 2, T_BOUND_CHANGE = 6, T_PARALLEL_ROW = 7, T_LEADER_SIDES = 8,
-  T_DUAL_FIX = 9, T_FREE_SINGLETON = 10, T_PARALLEL_COL = 11, T_LEADER_BOUNDS = 12, T_DOUBLETON_ROW = 14
+  T_DUAL_FIX = 9, T_FREE_SINGLETON = 10, T_PARALLEL_COL = 11, T_LEADER_BOUNDS = 12, T_DOUBLETON_ROW = 14,
+  T_DOMINATED_COL = 15
 };
 
 // value of a merged interval end under the library's infinity convention
@@ -127,6 +128,7 @@ class RecordStack {
         case T_FIX_COL:
         case T_EMPTY_COL:
         case T_DUAL_FIX:
+        case T_DOMINATED_COL:
           fixed_.push_back({r.j, r.v[0]});
           break;
         case T_FREE_SINGLETON:

@@ -24,7 +24,7 @@ enum : uint8_t {
   REC_FIX_COL = 1, REC_EMPTY_COL = 2, REC_EMPTY_ROW = 3, REC_REDUNDANT_ROW = 4,
   REC_SINGLETON_ROW = 5, REC_BOUND_CHANGE = 6, REC_PARALLEL_ROW = 7, REC_LEADER_SIDES = 8,
   REC_DUAL_FIX = 9, REC_FREE_SINGLETON = 10, REC_PARALLEL_COL = 11, REC_LEADER_BOUNDS = 12,
-  REC_FORCING_ROW = 13, REC_DOUBLETON_ROW = 14
+  REC_FORCING_ROW = 13, REC_DOUBLETON_ROW = 14, REC_DOMINATED_COL = 15
 };
 
 // row decision codes written by the sweep for the current round

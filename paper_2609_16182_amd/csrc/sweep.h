@@ -150,6 +150,16 @@ void launch_doubletons(const Dev& d, const DblScratch& S, int64_t base, int roun
 void launch_doubleton_relock(const Dev& d, const DblScratch& S, hipStream_t s);
 void launch_doubleton_init(const Dev& d, const DblScratch& S, hipStream_t s);  // no column kept yet
 
+// dominated.hip: dominated columns through implied dual bounds (allocated
+// when enabled); records from base + the pass's record total, added to it
+struct DomScratch {
+  long long* ykey;     // [2m] order-mapped bounds (lower, upper) of each row's dual
+  int8_t* side;        // [n] the fixing of each column: 0 lower, 1 upper, -1 none
+  int32_t* lp_flag;    // [K] crossing dual bounds: 1 skip the LP, 2 unbounded
+  int32_t* total;      // [1] records
+};
+void launch_dominated(const Dev& d, const DomScratch& S, int64_t base, int round, int32_t* ws, hipStream_t s);
+
 // compact.hip
 struct Reduced {
   int32_t *row_ptr, *col_idx, *col_ptr, *row_idx, *row_map, *col_map;

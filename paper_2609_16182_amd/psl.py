@@ -26,7 +26,7 @@ RECORD_DTYPE = np.dtype([
 REC_NAMES = {1: "FIX_COL", 2: "EMPTY_COL", 3: "EMPTY_ROW", 4: "REDUNDANT_ROW",
              5: "SINGLETON_ROW", 6: "BOUND_CHANGE", 7: "PARALLEL_ROW", 8: "LEADER_SIDES",
              9: "DUAL_FIX", 10: "FREE_SINGLETON", 11: "PARALLEL_COL", 12: "LEADER_BOUNDS",
-             13: "FORCING_ROW", 14: "DOUBLETON_ROW"}
+             13: "FORCING_ROW", 14: "DOUBLETON_ROW", 15: "DOMINATED_COL"}
 
 
 class psl_lp(C.Structure):
@@ -44,7 +44,7 @@ class psl_settings(C.Structure):
                 ("stream", C.c_void_p), ("split_sweep", C.c_int32), ("enable_dual_fix", C.c_int32),
                 ("enable_free_singletons", C.c_int32), ("enable_parallel_cols", C.c_int32),
                 ("enable_forcing_rows", C.c_int32), ("enable_doubletons", C.c_int32),
-                ("device_records", C.c_int64)]
+                ("device_records", C.c_int64), ("enable_dominated", C.c_int32)]
 
 
 class psl_stats(C.Structure):
