@@ -425,10 +425,15 @@ def main():
     reductions = None
     if args.reduction_steps > 0:
         reductions = {}
+        every = dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1, enable_forcing_rows=1,
+                     enable_doubletons=1, enable_dominated=1)
         for name, extra in (("dual_fix", dict(enable_dual_fix=1)),
                             ("free_singletons", dict(enable_free_singletons=1)),
                             ("parallel_cols", dict(enable_parallel_cols=1)),
-                            ("all", dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1))):
+                            ("forcing_rows", dict(enable_forcing_rows=1)),
+                            ("doubletons", dict(enable_doubletons=1)),
+                            ("dominated_cols", dict(enable_dominated=1)),
+                            ("all", every)):
             q = psl.Presolver(dev, stream=stream.cuda_stream, **extra)
             for _ in range(2):
                 q.reload(dev)
@@ -448,7 +453,9 @@ def main():
                 "ms_per_step": round(dt * 1e3 / args.reduction_steps, 3), "rounds": qs["rounds"],
                 "records": qs["records"], "dual_fixes": int((recs["type"] == 9).sum()),
                 "free_singletons": int((recs["type"] == 10).sum()),
-                "parallel_cols": int((recs["type"] == 11).sum()), "nnz_out": qs["nnz_out"],
+                "parallel_cols": int((recs["type"] == 11).sum()),
+                "forcing_rows": int((recs["type"] == 13).sum()), "doubletons": int((recs["type"] == 14).sum()),
+                "dominated_cols": int((recs["type"] == 15).sum()), "nnz_out": qs["nnz_out"],
                 "m_out": qs["m_out"], "n_out": qs["n_out"], "ms_decide": round(qs["ms_decide"], 3),
                 "ms_run_device": round(qs["ms_total"], 3)}
             print(f"[bench] reductions {name}: {reductions[name]['ms_per_step']} ms/step", file=sys.stderr,
