@@ -323,7 +323,11 @@ psl_status psl_presolve_reload(psl_presolver *p, const psl_lp *lp);
  * PSL_ERR_DEVICE, PSL_ERR_OOM. */
 psl_status psl_presolve_run(psl_presolver *p, psl_result *res, psl_stats *stats);
 
-/* View of the reduced problem (device pointers). PSL_ERR_STATE unless the
+/* View of the reduced problem (section 3.3: the presolver emits a reduced LP
+ * of the same form as the input, kept rows by kept columns in their original
+ * order, sides shifted by the removed columns' constants, the removed
+ * columns' costs in the objective offset; device pointers owned by the
+ * handle, valid until the next run, reload or free). PSL_ERR_STATE unless the
  * last run gave PSL_RES_REDUCED or PSL_RES_UNCHANGED. */
 psl_status psl_reduced_problem(const psl_presolver *p, psl_reduced_view *out);
 

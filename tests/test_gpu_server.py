@@ -154,3 +154,36 @@ def test_server_device_inputs():
         assert_same(got, O.presolve(lp), "device")
         sv.release(t)
     sv.close()
+
+
+class _Alone:
+    """psl.presolve's result in the shape assert_same expects."""
+
+    def __init__(self, got):
+        self.result_name = got["result_name"]
+        self.records = got["records"]
+        self.reduced = got["reduced"]
+
+
+def test_server_serving_sizes():
+    """LPs of the serving pool's sizes, up to m = 1e6 (about 1.2e7 nonzeros),
+    mixed with small ones on the default server (two slots): each ticket
+    equals the LP presolved alone, bit for bit; the one of m near 2e5 also
+    equals the oracle."""
+    big = [lpgen.serving_member(0, m_lo=900_000, m_hi=1_000_000), lpgen.serving_member(1, m_lo=150_000,
+                                                                                       m_hi=250_000)]
+    lps = [big[0], lpgen.tiny(3), big[1], lpgen.batch_member(2, m=500), lpgen.single_small(seed=12)]
+    sv = psl.Server()
+    try:
+        tickets = [sv.submit(lp) for lp in lps]
+        for t in tickets:
+            sv.wait(t, 120_000)
+        for k, (lp, t) in enumerate(zip(lps, tickets)):
+            got, info = got_of(sv, t)
+            alone, p = psl.presolve(lp)
+            p.close()
+            assert_same(got, _Alone(alone), f"serving size LP {k} (m = {lp['m']})")
+        got, _ = got_of(sv, tickets[2])
+        assert_same(got, O.presolve(lps[2]), "m near 2e5 against the oracle")
+    finally:
+        sv.close()
