@@ -41,17 +41,25 @@ def test_power_law_full_size(power_lp):
     assert np.all(x0 >= r["lb"] - 1e-9 * sc) and np.all(x0 <= r["ub"] + 1e-9 * sc)
 
 
+EVERY = dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1, enable_forcing_rows=1,
+             enable_doubletons=1, enable_dominated=1)
+
+
 @pytest.mark.parametrize("extra", [dict(enable_dual_fix=1), dict(enable_free_singletons=1),
                                    dict(enable_parallel_cols=1),
-                                   dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1)],
-                         ids=["dual_fix", "free_singletons", "parallel_cols", "all"])
+                                   dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1),
+                                   dict(enable_forcing_rows=1), dict(enable_doubletons=1), dict(enable_dominated=1),
+                                   EVERY],
+                         ids=["dual_fix", "free_singletons", "parallel_cols", "all", "forcing_rows", "doubletons",
+                              "dominated", "every"])
 def test_power_law_full_size_next_reductions(power_lp, extra):
     """The same LP with the optional reductions on (the benchmark's legs)."""
     lp = power_lp
     t0 = time.time()
     ref = O.presolve(lp, **extra)
     kinds = {name: int((ref.records["type"] == O.REC[name]).sum())
-             for name in ("DUAL_FIX", "FREE_SINGLETON", "PARALLEL_COL")}
+             for name in ("DUAL_FIX", "FREE_SINGLETON", "PARALLEL_COL", "FORCING_ROW", "DOUBLETON_ROW",
+                          "DOMINATED_COL")}
     print(f"oracle {ref.result_name} rounds={ref.rounds} records={len(ref.records)} {kinds} "
           f"in {time.time() - t0:.1f}s", flush=True)
     if extra.get("enable_dual_fix"):
@@ -60,6 +68,10 @@ def test_power_law_full_size_next_reductions(power_lp, extra):
         assert kinds["FREE_SINGLETON"] > 0
     if extra.get("enable_parallel_cols"):
         assert kinds["PARALLEL_COL"] > 0
+    if extra.get("enable_doubletons"):
+        assert kinds["DOUBLETON_ROW"] > 0
+    if extra.get("enable_dominated"):
+        assert kinds["DOMINATED_COL"] > 0
     got, p = psl.presolve(lp, **extra)
     print(f"gpu stats {got['stats']}", flush=True)
     p.close()
@@ -146,7 +158,7 @@ def power_lp_reordered(power_lp):
     return rows_by_length(by_popularity(power_lp))
 
 
-@pytest.mark.parametrize("extra", [{}, dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1)],
+@pytest.mark.parametrize("extra", [{}, EVERY],
                          ids=["default", "all"])
 def test_power_law_full_size_reordered(power_lp_reordered, extra):
     lp = power_lp_reordered

@@ -96,12 +96,20 @@ def test_edge_cases():
         "free row": make(1, 2, [[(0, 1.0), (1, 1.0)]], [-INF], [INF], [-INF, 0], [INF, 1], [0, 1]),
         "huge sides": make(1, 2, [[(0, 1.0), (1, 1.0)]], [-1e25], [1e21], [0, 0], [INF, 1], [1, 1]),
     }
+    every = dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1, enable_forcing_rows=1,
+                 enable_doubletons=1, enable_dominated=1)
     options = ({}, dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1),
-               dict(enable_parallel_rows=0, enable_parallel_cols=1))
+               dict(enable_parallel_rows=0, enable_parallel_cols=1), every,
+               dict(every, enable_parallel_rows=0))
     for name, lp in cases.items():
+        m, n = int(lp["m"]), int(lp["n"])
         for extra in options:
             got, ref = run_both(lp, **extra)
             assert_same(got, ref, f"{name} {extra}")
+        # the smallest flushed record stack gives the same outcome
+        stack = max(m + 3 * n + 16, 2 * m + 4 * n + 16)
+        got, ref = run_both(lp, device_records=stack, **every)
+        assert_same(got, ref, f"{name} flushed stack")
 
 
 def with_empty_block(lp, at, size, seed=0):
@@ -170,7 +178,8 @@ def rows_by_length(lp, longest_first=True):
     return out
 
 
-ALL_OPTIONS = dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1)
+ALL_OPTIONS = dict(enable_dual_fix=1, enable_free_singletons=1, enable_parallel_cols=1, enable_forcing_rows=1,
+                   enable_doubletons=1, enable_dominated=1)
 
 
 @pytest.mark.parametrize("order", ["columns by popularity", "rows longest first", "both"])
