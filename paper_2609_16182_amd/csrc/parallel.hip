@@ -114,6 +114,42 @@ __device__ __forceinline__ void par_insert(const Dev& d, const ParScratch& P, in
   P.slot[row] = (int)(base + (int64_t)h);
 }
 
+// R rows' inserts of one lane: the first compare-and-swap of each is issued
+// before any result is used (their latencies overlap); a row whose home slot
+// holds another key probes on as par_insert does
+template <int R>
+__device__ __forceinline__ void par_insert_n(const Dev& d, const ParScratch& P, const int (&row)[R],
+                                             const unsigned long long (&key)[R], const bool (&ins)[R]) {
+  HashSlot* tab[R];
+  unsigned long long mask[R], h[R], old[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    int64_t base = 0, cap = P.cap;
+    if (ins[k] && d.K > 1) {
+      LpTab t = P.lpt[d.row_lp[row[k]]];
+      base = t.base;
+      cap = t.cap;
+    }
+    tab[k] = P.table + base;
+    mask[k] = (unsigned long long)cap - 1;
+    h[k] = splitmix(key[k]) & mask[k];
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) old[k] = ins[k] ? atomicCAS(&tab[k][h[k]].key, 0ULL, key[k]) : 0ULL;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (!ins[k]) continue;
+    unsigned long long o = old[k];
+    for (unsigned long long probe = 1; o != 0ULL && o != key[k] && probe <= mask[k]; ++probe) {
+      h[k] = (h[k] + 1) & mask[k];
+      o = atomicCAS(&tab[k][h[k]].key, 0ULL, key[k]);
+    }
+    bool eq = d.lhs[row[k]] == d.rhs[row[k]];
+    atomicMin(&tab[k][h[k]].leader, (eq ? 0u : 0x80000000u) | (unsigned)row[k]);
+    P.slot[row[k]] = (int)((tab[k] - P.table) + (int64_t)h[k]);
+  }
+}
+
 __global__ void k_par_reset(Dev d, ParScratch P) {
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P.cap; t += stride) {
@@ -139,47 +175,78 @@ __global__ void k_par_reset(Dev d, ParScratch P) {
   }
 }
 
-// G-lane groups, rows of at most G entries, one position per lane (a lane
-// without a row reads the bin's first entry, which exists, and position 0
-// or the row's first position, so that no load is conditional); the first
-// active coefficient comes from the lowest active lane of the group
-template <int G>
-__device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, int bin, int lblock) {
-  int gid = lblock * (PSL_BLOCK / G) + (int)(threadIdx.x / G);
+// G-lane groups, rows of at most G entries, one position per lane, for REP
+// row blocks of the workgroup: the loads of all REP blocks are issued level by
+// level (bin entries, then rows and positions, then the active bits and the
+// fixed columns' values) before any block is hashed, so a lane has REP rows'
+// loads in flight together. A lane without a row reads the bin's first entry
+// (which exists) and position 0 or the row's first position, so no load of a
+// level is conditional; the first active coefficient comes from the lowest
+// active lane of the group.
+template <int G, int REP>
+__device__ __forceinline__ void hash_groups(const Dev& d, const ParScratch& P, int bin, int lblock0) {
+  const int per_block = PSL_BLOCK / G;
   int count = d.bin_off[bin + 1] - d.bin_off[bin];
-  bool vr = gid < count;
-  BinEnt be = d.bins[d.bin_off[bin] + (vr ? gid : 0)];
-  int row = be.row;
-  int64_t s0 = be.start;
-  int len = vr ? be.len : 0;
   int gl = threadIdx.x & (G - 1);
-  int64_t p0 = len > 0 ? s0 : 0;
-  int64_t p = gl < len ? s0 + gl : p0;
-  bool on = vr && d.row_on[row] != 0;
-  int j = d.ci[p];
-  double a = d.va[p];
-  bool in_row = on && gl < len;
-  bool act0 = in_row && bit_of(P.abits, j);
-  double xf = 0.0;  // a fixed column's value
-  if (in_row && !act0) xf = d.bnd[j].x;
-  unsigned long long gmask = __ballot(act0) & group_mask<G>();
-  int first = gmask ? __ffsll((long long)gmask) - 1 : lane_id();
-  double a0 = __shfl(a, first, PSL_WAVE);
-  if (!gmask) a0 = 1.0;
-  int col0 = lp_col0(d, row);
-  unsigned long long h1, h2;
-  hash_el(j, a, act0, a0, col0, h1, h2);
-  h1 = group_sum_u64<G>(h1);
-  h2 = group_sum_u64<G>(h2);
-  int L = __popcll(gmask);
-  // the removed columns' constant: a butterfly over the group's lanes is the
-  // canonical pairwise tree of the row's positions
-  double k = group_sum<G>(in_row && !act0 ? pos0(a * xf) : 0.0);
-  if (vr && on && gl == 0) {
-    d.row_out[row].v0 = k;
-    d.row_out[row].j = L;
-    if (L >= 2) par_insert(d, P, row, row_key(L, h1, h2));
+  int row[REP], len[REP];
+  int64_t p[REP];
+  bool vr[REP];
+#pragma unroll
+  for (int k = 0; k < REP; ++k) {
+    int gid = (lblock0 + k) * per_block + (int)(threadIdx.x / G);
+    vr[k] = gid < count;
+    BinEnt be = d.bins[d.bin_off[bin] + (vr[k] ? gid : 0)];
+    row[k] = be.row;
+    len[k] = vr[k] ? be.len : 0;
+    int64_t p0 = len[k] > 0 ? be.start : 0;
+    p[k] = gl < len[k] ? be.start + gl : p0;
   }
+  bool on[REP];
+  int j[REP];
+  double a[REP];
+#pragma unroll
+  for (int k = 0; k < REP; ++k) {
+    on[k] = vr[k] && d.row_on[row[k]] != 0;
+    j[k] = d.ci[p[k]];
+    a[k] = d.va[p[k]];
+  }
+  bool in_row[REP], act0[REP];
+  double xf[REP];  // a fixed column's value
+#pragma unroll
+  for (int k = 0; k < REP; ++k) {
+    in_row[k] = on[k] && gl < len[k];
+    act0[k] = in_row[k] && bit_of(P.abits, j[k]);
+    xf[k] = 0.0;
+    if (in_row[k] && !act0[k]) xf[k] = d.bnd[j[k]].x;
+  }
+  unsigned long long key[REP];
+  bool ins[REP];
+#pragma unroll
+  for (int k = 0; k < REP; ++k) {
+    ins[k] = false;
+    key[k] = 0;
+    if ((lblock0 + k) * per_block >= count) continue;  // uniform over the workgroup
+    unsigned long long gmask = __ballot(act0[k]) & group_mask<G>();
+    int first = gmask ? __ffsll((long long)gmask) - 1 : lane_id();
+    double a0 = __shfl(a[k], first, PSL_WAVE);
+    if (!gmask) a0 = 1.0;
+    int col0 = lp_col0(d, row[k]);
+    unsigned long long h1, h2;
+    hash_el(j[k], a[k], act0[k], a0, col0, h1, h2);
+    h1 = group_sum_u64<G>(h1);
+    h2 = group_sum_u64<G>(h2);
+    int L = __popcll(gmask);
+    // the removed columns' constant: a butterfly over the group's lanes is the
+    // canonical pairwise tree of the row's positions
+    double kc = group_sum<G>(in_row[k] && !act0[k] ? pos0(a[k] * xf[k]) : 0.0);
+    if (vr[k] && on[k] && gl == 0) {
+      d.row_out[row[k]].v0 = kc;
+      d.row_out[row[k]].j = L;
+      ins[k] = L >= 2;
+      key[k] = row_key(L, h1, h2);
+    }
+  }
+  par_insert_n<REP>(d, P, row, key, ins);
 }
 
 // pairwise tree over C values held in registers (C a power of two)
@@ -317,14 +384,15 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_par_hash(Dev d, ParScratch P, Swe
     }
     int rep = bin_rep(bin);
     int count = d.bin_off[bin + 1] - d.bin_off[bin];
-    for (int k = 0; k < rep; ++k) {
-      int vb = b * rep + k;
-      if (vb * bin_rows(bin) >= count) break;
-      if (bin == BIN_G4) hash_groups<4>(d, P, bin, vb);
-      else if (bin == BIN_G8) hash_groups<8>(d, P, bin, vb);
-      else if (bin == BIN_G16) hash_groups<16>(d, P, bin, vb);
-      else hash_wave_block(d, P, bin, vb);
-    }
+    if (bin == BIN_G4) hash_groups<4, 4>(d, P, bin, b * rep);
+    else if (bin == BIN_G8) hash_groups<8, 4>(d, P, bin, b * rep);
+    else if (bin == BIN_G16) hash_groups<16, 4>(d, P, bin, b * rep);
+    else
+      for (int k = 0; k < rep; ++k) {
+        int vb = b * rep + k;
+        if (vb * bin_rows(bin) >= count) break;
+        hash_wave_block(d, P, bin, vb);
+      }
     return;
   }
   if (b < g.nb[BIN_LONG]) hash_long_chunk(d, P, b);
