@@ -893,69 +893,106 @@ __device__ __forceinline__ uint8_t col_decide(const Dev& d, int j, int& k) {
   return code;
 }
 
-// records of index t of the round's index space (rows, then columns), from
-// the codes written by the sweep and by k_decide_count
-__device__ __forceinline__ int rec_count_of(const Dev& d, int64_t t) {
-  if (t < d.m) return d.row_code[t] != RC_KEEP;
-  uint8_t code = d.col_code[t - d.m];
-  return (code & CC_LB ? 1 : 0) + (code & CC_UB ? 1 : 0) + (code & (CC_FIX | CC_EMPTY) ? 1 : 0);
-}
-
-// one index per thread: the record stores of a wavefront stay contiguous and
-// the column decisions' loads overlap across lanes
-#define DEC_ITEMS 1
-#define DEC_BLOCK 1024
+// Decision tiles: the rows in tiles of DEC_TILE, then the columns in tiles of
+// DEC_TILE (index order, so the records keep the order rows, then columns).
+// A lane loads the codes of DEC_ITEMS consecutive indices as one word (the
+// arrays are 256-byte aligned and padded, so a word starting below the end
+// stays inside them); the indices with work (touched columns, indices with
+// records) are then compacted per wavefront in LDS and dealt out to its lanes,
+// so the lanes stay busy whether few or all indices have work, and a tile
+// costs four wavefronts instead of one per 64 indices.
+#define DEC_ITEMS 4
+#define DEC_BLOCK 256
 #define DEC_TILE (DEC_BLOCK * DEC_ITEMS)
 #define DEC_WAVES (DEC_BLOCK / PSL_WAVE)
+#define DEC_WAVE_ITEMS (PSL_WAVE * DEC_ITEMS)
 // an index has at most 3 records (a row 1; a column: each bound side and one
-// of fixed, empty or dual-fixed), so a thread's count fits in 3 bits
-static_assert(3 * DEC_ITEMS < 8, "record counts per thread must fit in 3 bits");
+// of fixed, empty or dual-fixed), so a lane's count fits in 4 bits
+static_assert(3 * DEC_ITEMS < 16, "record counts per lane must fit in 4 bits");
+static_assert(DEC_ITEMS == 4, "a lane's codes are one 32-bit word");
 
-// prefix (lanes below) and total of per-lane counts 0..7 across the
+// prefix (lanes below) and total of per-lane counts 0..15 across the
 // wavefront, from one ballot per bit
 __device__ __forceinline__ void wave_small_scan(int v, int& pre, int& tot) {
   unsigned long long below = (1ull << lane_id()) - 1ull;
-  unsigned long long b0 = __ballot(v & 1), b1 = __ballot(v & 2), b2 = __ballot(v & 4);
-  pre = __popcll(b0 & below) + 2 * __popcll(b1 & below) + 4 * __popcll(b2 & below);
-  tot = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+  unsigned long long b0 = __ballot(v & 1), b1 = __ballot(v & 2), b2 = __ballot(v & 4), b3 = __ballot(v & 8);
+  pre = __popcll(b0 & below) + 2 * __popcll(b1 & below) + 4 * __popcll(b2 & below) + 8 * __popcll(b3 & below);
+  tot = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2) + 8 * __popcll(b3);
+}
+
+// bytes of a lane's word that hold indices below the end (rem of them)
+__device__ __forceinline__ uint32_t valid_bytes(int64_t rem) {
+  return rem >= 4 ? 0xFFFFFFFFu : (1u << (8 * (int)rem)) - 1u;
+}
+
+// the codes' word of a lane: 4 consecutive indices from i0 (a multiple of 4)
+__device__ __forceinline__ uint32_t code_word(const uint8_t* a, int64_t i0) {
+  return reinterpret_cast<const uint32_t*>(a)[i0 >> 2];
+}
+
+// records of a column with decision code `code`
+__device__ __forceinline__ int col_recs(uint32_t code) {
+  return (code & CC_LB ? 1 : 0) + (code & CC_UB ? 1 : 0) + (code & (CC_FIX | CC_EMPTY) ? 1 : 0);
 }
 
 // Column decisions of the touched columns (untouched ones cannot change: an
 // active column with unchanged bounds and rows is neither fixed nor empty),
-// and the record count of each tile of DEC_TILE indices.
-__global__ void __launch_bounds__(DEC_BLOCK) k_decide_count(Dev d, int32_t* tile_sum) {
-  int64_t m = d.m, span = m + d.n;
-  int64_t t0 = (int64_t)blockIdx.x * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
-  int c = 0;
+// and the record count of each tile.
+__global__ void __launch_bounds__(DEC_BLOCK) k_decide_count(Dev d, int32_t* tile_sum, int64_t row_tiles) {
+  __shared__ int list[DEC_TILE];
+  __shared__ int wtot[DEC_WAVES];
+  int w = threadIdx.x >> 6, lane = lane_id();
+  int* wl = list + w * DEC_WAVE_ITEMS;
+  int64_t tile = blockIdx.x;
+  int c = 0, nt = 0, ntot = 0;
+  if (tile < row_tiles) {
+    int64_t i0 = tile * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
+    if (i0 < d.m) {
+      uint32_t cw = code_word(d.row_code, i0) & valid_bytes(d.m - i0);
 #pragma unroll
-  for (int k = 0; k < DEC_ITEMS; ++k) {
-    int64_t t = t0 + k;
-    if (t >= span) break;
-    if (t < m) {
-      c += d.row_code[t] != RC_KEEP;
-      continue;
+      for (int b = 0; b < 4; ++b) c += ((cw >> (8 * b)) & 0xFFu) != RC_KEEP;
     }
-    int j = (int)(t - m);
-    if (!d.touch[j]) {
-      if (d.col_code[j]) d.col_code[j] = 0;
-      continue;
+  } else {
+    int64_t j0 = (tile - row_tiles) * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
+    uint32_t tw = 0;
+    if (j0 < d.n) {
+      uint32_t vm = valid_bytes(d.n - j0);
+      uint32_t traw = code_word(d.touch, j0);
+      tw = traw & vm;
+      uint32_t cw = code_word(d.col_code, j0) & vm;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        bool touched = ((tw >> (8 * b)) & 0xFFu) != 0;
+        nt += touched;
+        // a code left from an earlier round of an untouched column
+        if (!touched && ((cw >> (8 * b)) & 0xFFu)) d.col_code[j0 + b] = 0;
+      }
+      if (tw) reinterpret_cast<uint32_t*>(d.touch)[j0 >> 2] = traw & ~vm;
     }
-    d.touch[j] = 0;
+    // the touched columns of the wavefront, in LDS, dealt out to its lanes
+    int pre;
+    wave_small_scan(nt, pre, ntot);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if ((tw >> (8 * b)) & 0xFFu) wl[pre++] = (int)(j0 + b);
+  }
+  __syncthreads();
+  for (int e = lane; e < ntot; e += PSL_WAVE) {
+    int j = wl[e];
     int kk;
     d.col_code[j] = col_decide(d, j, kk);
     c += kk;
   }
   // the tile's record count: wavefront totals by ballots, summed by thread 0
-  __shared__ int wtot[DEC_WAVES];
   int pre_w, tot_w;
   wave_small_scan(c, pre_w, tot_w);
-  if (lane_id() == 0) wtot[threadIdx.x >> 6] = tot_w;
+  if (lane == 0) wtot[w] = tot_w;
   __syncthreads();
   if (threadIdx.x == 0) {
     int tot = 0;
 #pragma unroll
     for (int k = 0; k < DEC_WAVES; ++k) tot += wtot[k];
-    tile_sum[blockIdx.x] = tot;
+    tile_sum[tile] = tot;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.flags->rows_removed = 0;
@@ -1045,70 +1082,83 @@ __device__ __forceinline__ int emit_col(const Dev& d, int j, int round, Record* 
 }
 
 // Records of the round in index order: each tile's offset comes from the
-// scanned tile sums, positions inside the tile from a block scan of the
-// counts. Also counts the removed rows and (batches) marks the LPs that
-// changed.
+// scanned tile sums, the position of an index's records inside the tile from
+// the counts of the indices before it (ballots inside the wavefront, the
+// wavefronts' totals through LDS). The indices with records are compacted per
+// wavefront and dealt out to its lanes, each writing its index's records at
+// that position. Also counts the removed rows (a row tile's records are its
+// removed rows) and (batches) marks the LPs that changed.
 __global__ void __launch_bounds__(DEC_BLOCK) k_decide_emit(Dev d, const int32_t* tile_sum, const int32_t* tile_off,
-                                                            int64_t base, int round) {
-  if (tile_sum[blockIdx.x] == 0) return;  // a tile without records
-  int64_t m = d.m, span = m + d.n;
-  int64_t t0 = (int64_t)blockIdx.x * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
-  int cnt[DEC_ITEMS];
-  int c = 0;
+                                                            int64_t row_tiles, int64_t base, int round) {
+  int64_t tile = blockIdx.x;
+  int tsum = tile_sum[tile];
+  if (tsum == 0) return;  // a tile without records
+  __shared__ int list[DEC_TILE], lpos[DEC_TILE];
+  __shared__ int wtot[DEC_WAVES], wfin[DEC_WAVES];
+  int w = threadIdx.x >> 6, lane = lane_id();
+  bool rows = tile < row_tiles;
+  int64_t t0 = (rows ? tile : tile - row_tiles) * DEC_TILE + (int64_t)threadIdx.x * DEC_ITEMS;
+  int64_t lim = rows ? d.m : d.n;
+  uint32_t cnt4 = 0;  // the records of the lane's 4 indices, a byte each
+  if (t0 < lim) {
+    uint32_t vm = valid_bytes(lim - t0);
+    uint32_t cw = code_word(rows ? d.row_code : d.col_code, t0) & vm;
 #pragma unroll
-  for (int k = 0; k < DEC_ITEMS; ++k) {
-    int64_t t = t0 + k;
-    cnt[k] = t < span ? rec_count_of(d, t) : 0;
-    c += cnt[k];
+    for (int b = 0; b < 4; ++b) {
+      uint32_t code = (cw >> (8 * b)) & 0xFFu;
+      cnt4 |= (uint32_t)(rows ? code != RC_KEEP : col_recs(code)) << (8 * b);
+    }
   }
-  // record positions: the prefix inside the wavefront by ballots, the
-  // wavefronts' totals through LDS (the one barrier); the removed rows go
-  // the same way, one atomic per workgroup
-  __shared__ int wtot[DEC_WAVES], wrow[DEC_WAVES];
-  int w = threadIdx.x >> 6;
-  int nrow = 0;
+  int c = 0, ni = 0;
 #pragma unroll
-  for (int k = 0; k < DEC_ITEMS; ++k) nrow += (t0 + k < m) ? cnt[k] : 0;
-  int pre, tot_w, rpre, rtot_w;
+  for (int b = 0; b < 4; ++b) {
+    int k = (cnt4 >> (8 * b)) & 0xFF;
+    c += k;
+    ni += k != 0;
+  }
+  int pre, tot_w, ipre, itot;
   wave_small_scan(c, pre, tot_w);
-  wave_small_scan(nrow, rpre, rtot_w);
-  if (lane_id() == 0) {
-    wtot[w] = tot_w;
-    wrow[w] = rtot_w;
-  }
+  wave_small_scan(ni, ipre, itot);
+  if (lane == 0) wtot[w] = tot_w;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < DEC_WAVES; ++k) pre += k < w ? wtot[k] : 0;
-  if (threadIdx.x == 0) {
-    int rtot = 0;
+  int* wl = list + w * DEC_WAVE_ITEMS;
+  int* wp = lpos + w * DEC_WAVE_ITEMS;
 #pragma unroll
-    for (int k = 0; k < DEC_WAVES; ++k) rtot += wrow[k];
-    if (rtot) atomicAdd(&d.flags->rows_removed, rtot);
-  }
-  int fin = 0;
-  if (tot_w != 0) {  // a wavefront with records (the others wait at the barrier below)
-    Record* r = d.rec + base + tile_off[blockIdx.x] + pre;
-#pragma unroll
-    for (int k = 0; k < DEC_ITEMS; ++k) {
-      if (!cnt[k]) continue;
-      int64_t t = t0 + k;
-      int lp;
-      if (t < m) {
-        lp = row_lp_of(d, (int)t);
-        emit_row(d, (int)t, round_of(d, lp, round), r);
-      } else {
-        lp = col_lp_of(d, (int)(t - m));
-        fin += emit_col(d, (int)(t - m), round_of(d, lp, round), r);
-      }
-      if (d.K > 1) d.lpo[lp].total = 1;  // the LP changed this round
-      r += cnt[k];
+  for (int b = 0; b < 4; ++b) {
+    int k = (cnt4 >> (8 * b)) & 0xFF;
+    if (k) {
+      wl[ipre] = (int)(t0 + b);
+      wp[ipre] = pre;
+      ++ipre;
+      pre += k;
     }
   }
-  // columns whose bound became finite: the same way, one atomic per workgroup
-  __shared__ int wfin[DEC_WAVES];
+  __syncthreads();
+  Record* r0 = d.rec + base + tile_off[tile];
+  int fin = 0;
+  for (int e = lane; e < itot; e += PSL_WAVE) {
+    int x = wl[e];
+    Record* r = r0 + wp[e];
+    int lp;
+    if (rows) {
+      lp = row_lp_of(d, x);
+      emit_row(d, x, round_of(d, lp, round), r);
+    } else {
+      lp = col_lp_of(d, x);
+      fin += emit_col(d, x, round_of(d, lp, round), r);
+    }
+    if (d.K > 1) d.lpo[lp].total = 1;  // the LP changed this round
+  }
+  if (rows) {
+    if (threadIdx.x == 0) atomicAdd(&d.flags->rows_removed, tsum);
+    return;
+  }
+  // columns whose bound became finite: one atomic per workgroup
   int fpre, ftot_w;
   wave_small_scan(fin, fpre, ftot_w);
-  if (lane_id() == 0) wfin[w] = ftot_w;
+  if (lane == 0) wfin[w] = ftot_w;
   __syncthreads();
   if (threadIdx.x == 0) {
     int ftot = 0;
@@ -1169,17 +1219,17 @@ void launch_src(const Dev& d, const SweepGrid& g, hipStream_t s) {
 // record total goes to d.flags->round_total
 void launch_decide(const Dev& d, int64_t base, int round, int32_t* tile_sum, int32_t* tile_off, int32_t* ws,
                    hipStream_t s) {
-  int64_t span = (int64_t)d.m + d.n;
-  int64_t tiles = (span + DEC_TILE - 1) / DEC_TILE;
+  int64_t row_tiles = ((int64_t)d.m + DEC_TILE - 1) / DEC_TILE;
+  int64_t tiles = row_tiles + ((int64_t)d.n + DEC_TILE - 1) / DEC_TILE;
   if (tiles == 0) {
     fill_i32(&d.flags->round_total, 0, 1, s);
     fill_i32(&d.flags->rows_removed, 0, 1, s);
     return;
   }
-  hipLaunchKernelGGL(k_decide_count, dim3((unsigned)tiles), dim3(DEC_BLOCK), 0, s, d, tile_sum);
+  hipLaunchKernelGGL(k_decide_count, dim3((unsigned)tiles), dim3(DEC_BLOCK), 0, s, d, tile_sum, row_tiles);
   scan_excl(tile_sum, tile_off, tiles, &d.flags->round_total, ws, s);
   hipLaunchKernelGGL(k_decide_emit, dim3((unsigned)tiles), dim3(DEC_BLOCK), 0, s, d, (const int32_t*)tile_sum,
-                     (const int32_t*)tile_off, base, round);
+                     (const int32_t*)tile_off, row_tiles, base, round);
 }
 
 int long_max_passes() { return LONG_MAX_PASSES; }
