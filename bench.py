@@ -210,9 +210,10 @@ def batch_leg(args, torch, psl):
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream().cuda_stream
     lset = psl.LpSet(dev)
-    # launch shapes picked by the tuner on a sample of the batch (every 8th LP)
+    # launch shapes picked by the tuner on the batch itself: the fastest shape
+    # of a smaller sample (fewer waves per launch) need not be the batch's
     t0 = time.time()
-    tuned = psl.tune(psl.LpSet(dev[::8]), reps=2, stream=stream)
+    tuned = psl.tune(lset, reps=2, stream=stream)
     print(f"[bench] tuner: {tuned} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     shape = dict(bin_thresholds=tuned["bin_thresholds"], split_sweep=tuned["split_sweep"])
     b = psl.Batch(lset, stream=stream, **shape)

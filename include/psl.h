@@ -443,7 +443,7 @@ typedef struct {
     int32_t bin_thresholds[3];     /* fastest: as psl_settings.bin_thresholds   */
     int32_t split_sweep;           /* fastest launch split                       */
     int32_t candidates;            /* shapes timed                               */
-    double ms_best;                /* median device ms of a presolve, fastest     */
+    double ms_best;                /* device ms of a presolve (fastest rep), fastest */
     double ms_default;             /* the same with the default shape            */
 } psl_tuning;
 
