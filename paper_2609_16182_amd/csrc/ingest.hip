@@ -591,47 +591,75 @@ __device__ __forceinline__ void wave_scan5(int v, int& pre, int& tot) {
   }
 }
 
+// A lane reads the codes of MARK_COLS consecutive columns as one word (the
+// code array is 256-byte aligned and padded, so a word starting below n stays
+// inside it); the wavefront's columns to walk are listed in LDS and taken 64
+// at a time, one per lane.
+#define MARK_COLS 4
+#define MARK_TILE (PSL_BLOCK * MARK_COLS)
+
 __global__ void __launch_bounds__(PSL_BLOCK) k_mark_sparse(Dev d, RoundMode rm) {
   int mode = round_mode(d, rm);
   if (blockIdx.x == 0 && threadIdx.x == 0) d.flags->mode = mode;
   if (mode == 0) return;
-  int64_t j = (int64_t)blockIdx.x * PSL_BLOCK + threadIdx.x;
-  int q0 = 0, q1 = 0, code = 0;
-  if (j < d.n) code = d.col_code[j];
-  if (mark_col(code, mode)) {
-    q0 = d.cp[j];
-    q1 = d.cp[j + 1];
-  }
-  int len = q1 - q0;
+  __shared__ int32_t list[MARK_TILE];
   int lane = lane_id();
-  // short columns: the wavefront's entries, concatenated in column order,
-  // one per lane (a column's entries are contiguous, so the row-index loads
-  // of a step touch a few lines, and no lane walks a column alone)
-  int sl = len <= MARK_SHORT ? len : 0;
-  int pre, tot;
-  wave_scan5(sl, pre, tot);
-  for (int e0 = 0; e0 < tot; e0 += PSL_WAVE) {
-    int e = e0 + lane;
-    // the entry's column: the last lane whose prefix is <= e
-    int lo = 0, hi = PSL_WAVE - 1;
-#pragma unroll
-    for (int it = 0; it < 6; ++it) {
-      int mid = (lo + hi + 1) >> 1;
-      bool le = __shfl(pre, mid, PSL_WAVE) <= e;
-      lo = le ? mid : lo;
-      hi = le ? hi : mid - 1;
-    }
-    int q = __shfl(q0, lo, PSL_WAVE) + (e - __shfl(pre, lo, PSL_WAVE));
-    int cl = __shfl(code, lo, PSL_WAVE);
-    if (e < tot) mark_entry(d, q, cl, mode & 1, mode & 2);
+  int32_t* wl = list + (threadIdx.x >> 6) * (PSL_WAVE * MARK_COLS);
+  int64_t j0 = (int64_t)blockIdx.x * MARK_TILE + (int64_t)threadIdx.x * MARK_COLS;
+  uint32_t cw = 0;
+  if (j0 < d.n) {
+    int64_t rem = d.n - j0;
+    cw = reinterpret_cast<const uint32_t*>(d.col_code)[j0 >> 2];
+    if (rem < 4) cw &= (1u << (8 * (int)rem)) - 1u;
   }
-  // longer ones: the wavefront walks them one after another
-  unsigned long long mask = __ballot(len > MARK_SHORT && len <= MARK_DENSE);
-  while (mask) {
-    int l = __ffsll((long long)mask) - 1;
-    mask &= mask - 1;
-    int a = __shfl(q0, l, PSL_WAVE), b = __shfl(q1, l, PSL_WAVE), cl = __shfl(code, l, PSL_WAVE);
-    for (int q = a + lane; q < b; q += PSL_WAVE) mark_entry(d, q, cl, mode & 1, mode & 2);
+  int nm = 0;
+#pragma unroll
+  for (int b = 0; b < MARK_COLS; ++b) nm += mark_col((cw >> (8 * b)) & 0xFF, mode);
+  int mpre, mtot;
+  wave_scan5(nm, mpre, mtot);
+#pragma unroll
+  for (int b = 0; b < MARK_COLS; ++b)
+    if (mark_col((cw >> (8 * b)) & 0xFF, mode)) wl[mpre++] = (int32_t)(j0 + b);
+  __syncthreads();
+  for (int c0 = 0; c0 < mtot; c0 += PSL_WAVE) {
+    int q0 = 0, q1 = 0, code = 0;
+    if (c0 + lane < mtot) {
+      int j = wl[c0 + lane];
+      code = d.col_code[j];
+      q0 = d.cp[j];
+      q1 = d.cp[j + 1];
+    }
+    int len = q1 - q0;
+    // short columns: the entries of the lanes' columns, concatenated in
+    // column order, one per lane (a column's entries are contiguous, so the
+    // row-index loads of a step touch a few lines, and no lane walks a
+    // column alone)
+    int sl = len <= MARK_SHORT ? len : 0;
+    int pre, tot;
+    wave_scan5(sl, pre, tot);
+    for (int e0 = 0; e0 < tot; e0 += PSL_WAVE) {
+      int e = e0 + lane;
+      // the entry's column: the last lane whose prefix is <= e
+      int lo = 0, hi = PSL_WAVE - 1;
+#pragma unroll
+      for (int it = 0; it < 6; ++it) {
+        int mid = (lo + hi + 1) >> 1;
+        bool le = __shfl(pre, mid, PSL_WAVE) <= e;
+        lo = le ? mid : lo;
+        hi = le ? hi : mid - 1;
+      }
+      int q = __shfl(q0, lo, PSL_WAVE) + (e - __shfl(pre, lo, PSL_WAVE));
+      int cl = __shfl(code, lo, PSL_WAVE);
+      if (e < tot) mark_entry(d, q, cl, mode & 1, mode & 2);
+    }
+    // longer ones: the wavefront walks them one after another
+    unsigned long long mask = __ballot(len > MARK_SHORT && len <= MARK_DENSE);
+    while (mask) {
+      int l = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      int a = __shfl(q0, l, PSL_WAVE), b = __shfl(q1, l, PSL_WAVE), cl = __shfl(code, l, PSL_WAVE);
+      for (int q = a + lane; q < b; q += PSL_WAVE) mark_entry(d, q, cl, mode & 1, mode & 2);
+    }
   }
 }
 
@@ -679,7 +707,7 @@ void list_dense_cols(const Dev& d, hipStream_t s) {
 
 void mark_dirty(const Dev& d, bool allow_incremental, int incr_factor, int count_factor, hipStream_t s) {
   RoundMode rm{allow_incremental ? 1 : 0, incr_factor, count_factor};
-  unsigned blocks = (unsigned)((d.n + PSL_BLOCK - 1) / PSL_BLOCK);
+  unsigned blocks = (unsigned)((d.n + MARK_TILE - 1) / MARK_TILE);
   hipLaunchKernelGGL(k_mark_sparse, dim3(blocks > 0 ? blocks : 1), dim3(PSL_BLOCK), 0, s, d, rm);
   if (d.nnz > 0 && d.n > 0) hipLaunchKernelGGL(k_mark_dense, dim3(1024), dim3(PSL_BLOCK), 0, s, d, rm);
 }
