@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--serve-pool", type=int, default=256, help="LPs in the serving pool (0 = skip serving)")
     ap.add_argument("--serve-rates", default="50,200,1000,2000")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-slots", type=int, default=4, help="batch engines of the continuous-batching server")
     ap.add_argument("--only-serving", action="store_true", help="run the serving workload only")
     return ap.parse_args()
 
@@ -148,7 +149,7 @@ def _replay(psl, sv, pool, rate, seconds, seed):
 def serving_leg(args, torch, psl):
     """Poisson arrivals of LPs from a device-resident pool (m log-uniform in
     [1e3, 1e6], n = 1.5m, U{4..20} nnz/row); latency = submit -> reduced LP
-    ready on the device. The continuous-batching server (2 slots) is compared
+    ready on the device. The continuous-batching server (--serve-slots) is compared
     with a one-LP-per-launch FIFO server (1 slot, batches of 1) at each rate."""
     from concurrent.futures import ProcessPoolExecutor
 
@@ -170,7 +171,12 @@ def serving_leg(args, torch, psl):
     rates = [float(r) for r in args.serve_rates.split(",")]
     out = {"metric": "serving LPs/s and latency", "pool": len(pool), "mean_nnz": round(float(np.mean(pool_nnz))),
            "seconds_per_rate": args.serve_seconds, "batched": [], "fifo_one_lp_per_launch": []}
-    for kind, cfg in (("batched", dict(slots=2)), ("fifo_one_lp_per_launch", dict(slots=1, max_batch_lps=1))):
+    out["slots"] = args.serve_slots
+    # each slot's arena holds a batch of up to 2.6e6 rows / 3e7 nonzeros (about
+    # 9.5 GB); the rest of the budget is the heap of device-resident results
+    budget = (24 + 10 * args.serve_slots) << 30
+    for kind, cfg in (("batched", dict(slots=args.serve_slots, hbm_budget_bytes=budget)),
+                      ("fifo_one_lp_per_launch", dict(slots=1, max_batch_lps=1))):
         sv = psl.Server(**cfg)
         for lp in pool[:2]:  # warm up
             sv.wait(sv.submit(lp))

@@ -526,7 +526,7 @@ typedef struct {
                                  FREE_SINGLETON records                      */
 } psl_server_config;
 
-/* Defaults: 64 GiB, 2 slots, threaded, 1024 LPs, 2.6e6 rows, 3.9e6 columns,
+/* Defaults: 64 GiB, 4 slots, threaded, 1024 LPs, 2.6e6 rows, 3.9e6 columns,
  * 3e7 nonzeros per batch. */
 void psl_server_config_default(psl_server_config *c);
 

@@ -207,7 +207,7 @@ extern "C" void psl_server_config_default(psl_server_config* c) {
   if (!c) return;
   std::memset(c, 0, sizeof *c);
   c->hbm_budget_bytes = (size_t)64 << 30;
-  c->slots = 2;
+  c->slots = 4;
   c->threaded = 1;
   c->max_batch_lps = 1024;
   c->max_batch_rows = 2600000;

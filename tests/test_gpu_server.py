@@ -167,7 +167,7 @@ class _Alone:
 
 def test_server_serving_sizes():
     """LPs of the serving pool's sizes, up to m = 1e6 (about 1.2e7 nonzeros),
-    mixed with small ones on the default server (two slots): each ticket
+    mixed with small ones on the default server (four slots): each ticket
     equals the LP presolved alone, bit for bit; the one of m near 2e5 also
     equals the oracle."""
     big = [lpgen.serving_member(0, m_lo=900_000, m_hi=1_000_000), lpgen.serving_member(1, m_lo=150_000,
