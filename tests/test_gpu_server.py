@@ -49,7 +49,8 @@ def mix_lps():
 
 def test_server_mix_equals_alone():
     lps = mix_lps()
-    sv = psl.Server(**SMALL)
+    # two slots: arrivals come faster than two slots finish, so LPs share batches
+    sv = psl.Server(slots=2, **SMALL)
     tickets = [None] * len(lps)
     rng = np.random.default_rng(1)
     delays = rng.exponential(0.002, len(lps))
