@@ -297,6 +297,8 @@ static psl_status setup_arena(psl_presolver* p) {
     ALLOC(p->dbl.by, n);
     ALLOC(p->dbl.tb, n);
     ALLOC(p->dbl.total, 2);
+    ALLOC(p->dbl.long_task, doubleton_long_cap(N));
+    ALLOC(p->dbl.long_cnt, 1);
     ALLOC(p->cp0, n + 1);
     ALLOC(p->ri0, N);
     ALLOC(p->cva0, N);

@@ -24,6 +24,11 @@
 // Records: DOUBLETON_ROW per applied row (ascending), then the transferred
 // bounds per kept column (ascending, lower then upper). The transposed copy is
 // rebuilt afterwards from the rewritten rows (by the caller).
+//
+// A row is rewritten by one lane, except a row longer than DBL_LANE_ROW that
+// must take the kept column in: its entries between the two columns move by
+// one, which a workgroup does afterwards in chunks (every load of a chunk
+// before any of its stores).
 #include <climits>
 
 #include "psl_kern.h"
@@ -37,6 +42,13 @@ __device__ __forceinline__ bool dbl_lp_stopped(const Dev& d, int lp) {
 }
 
 __device__ __forceinline__ double dbl_side_minus(double side, double k) { return is_inf(side) ? side : pos0(side - k); }
+
+// longest row a lane rewrites itself
+#define DBL_LANE_ROW 256
+#define DBL_SHIFT_BLOCK 1024
+#define DBL_SHIFT_ITEMS 4
+
+int64_t doubleton_long_cap(int64_t nnz) { return nnz / (DBL_LANE_ROW + 1) + 1; }
 
 // position of column j among positions [s, s + len) of a row (ascending
 // columns; dead entries keep their column), or -1
@@ -63,6 +75,7 @@ __global__ void k_dbl_reset(Dev d, DblScratch S) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     d.flags->dbl_count = 0;
     d.flags->dbl_applied = 0;
+    *S.long_cnt = 0;
   }
 }
 
@@ -322,12 +335,25 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_dbl_apply(Dev d, DblScratch S) {
       if (r == i || !d.row_on[r]) continue;
       double f = d.cva[q] / ak;
       int64_t sr = d.rp[r];
-      int64_t pj = dbl_find(d, sr, d.rp[r + 1] - (int)sr, j);
+      int len = d.rp[r + 1] - (int)sr;
+      int64_t pj = dbl_find(d, sr, len, j);
       double v = (pj >= 0 ? d.va[pj] : 0.0) - f * aj;
       double sh = f * b;
       d.lhs[r] = dbl_side_minus(d.lhs[r], sh);
       d.rhs[r] = dbl_side_minus(d.rhs[r], sh);
-      if (dbl_rewrite(d, r, k, j, v)) atomicAdd(&d.col_len[j], 1);
+      if (pj < 0 && len > DBL_LANE_ROW) {
+        // the insertion moves up to the whole row: left to a workgroup
+        DblTask tk;
+        tk.r = r;
+        tk.k = k;
+        tk.j = j;
+        tk.pad = 0;
+        tk.v = v;
+        S.long_task[atomicAdd(S.long_cnt, 1)] = tk;
+        atomicAdd(&d.col_len[j], 1);
+      } else if (dbl_rewrite(d, r, k, j, v)) {
+        atomicAdd(&d.col_len[j], 1);
+      }
     }
     if (lane == 0) {
       double rc = d.c[k] / ak;
@@ -342,6 +368,73 @@ __global__ void __launch_bounds__(PSL_BLOCK) k_dbl_apply(Dev d, DblScratch S) {
       d.bkey[2 * (int64_t)k] = dkey(vk);
       d.bkey[2 * (int64_t)k + 1] = dkey(vk);
     }
+  }
+}
+
+// The deferred long-row insertions (one workgroup each, grid-striding): the
+// entries strictly between column k's position and the kept column's sorted
+// place move by one towards k's position, then j takes the freed place, as a
+// lane's rewrite does. Chunks of DBL_SHIFT_BLOCK * DBL_SHIFT_ITEMS entries go
+// away from k's position; a chunk's loads all precede its stores (a barrier),
+// and the next chunk stores only after its own barrier, so no entry is
+// overwritten before it is read.
+__global__ void __launch_bounds__(DBL_SHIFT_BLOCK) k_dbl_shift(Dev d, DblScratch S) {
+  __shared__ int64_t sh_pk, sh_q;
+  int nt = *S.long_cnt;
+  int32_t* ci = const_cast<int32_t*>(d.ci);
+  double* va = const_cast<double*>(d.va);
+  const int C = DBL_SHIFT_BLOCK * DBL_SHIFT_ITEMS;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    DblTask tk = S.long_task[t];
+    int64_t s = d.rp[tk.r];
+    int len = d.rp[tk.r + 1] - (int)s;
+    if (threadIdx.x == 0) {
+      sh_pk = dbl_find(d, s, len, tk.k);
+      // the first position whose column exceeds j (j is absent)
+      int lo = 0, hi = len;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (d.ci[s + mid] < tk.j) lo = mid + 1;
+        else hi = mid;
+      }
+      sh_q = s + lo;
+    }
+    __syncthreads();
+    int64_t pk = sh_pk, ub = sh_q;
+    // j > k: entries (pk, ub) move down by one, j lands at ub - 1;
+    // j < k: entries [ub, pk) move up by one, j lands at ub
+    bool down = tk.j > tk.k;
+    int64_t a = down ? pk + 1 : ub, e = down ? ub : pk;  // sources [a, e)
+    int64_t L = e - a;
+    for (int64_t c0 = 0; c0 < L; c0 += C) {
+      int32_t cv[DBL_SHIFT_ITEMS];
+      double vv[DBL_SHIFT_ITEMS];
+      int64_t src[DBL_SHIFT_ITEMS];
+#pragma unroll
+      for (int u = 0; u < DBL_SHIFT_ITEMS; ++u) {
+        int64_t o = c0 + u * DBL_SHIFT_BLOCK + threadIdx.x;  // offset from the end nearest k
+        src[u] = o < L ? (down ? a + o : e - 1 - o) : -1;
+        if (src[u] >= 0) {
+          cv[u] = ci[src[u]];
+          vv[u] = va[src[u]];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < DBL_SHIFT_ITEMS; ++u)
+        if (src[u] >= 0) {
+          int64_t dst = down ? src[u] - 1 : src[u] + 1;
+          ci[dst] = cv[u];
+          va[dst] = vv[u];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t q = down ? ub - 1 : ub;
+      ci[q] = tk.j;
+      va[q] = tk.v;
+    }
+    __syncthreads();  // sh_pk, sh_q are set again for the next task
   }
 }
 
@@ -397,7 +490,10 @@ void launch_doubletons(const Dev& d, const DblScratch& S, int64_t base, int roun
     fill_i32(S.total + 1, 0, 1, s);
   }
   hipLaunchKernelGGL(k_dbl_close, dim3(1), dim3(64), 0, s, d, (const int32_t*)S.total);
-  if (d.m > 0) hipLaunchKernelGGL(k_dbl_apply, dim3(2048), dim3(PSL_BLOCK), 0, s, d, S);
+  if (d.m > 0) {
+    hipLaunchKernelGGL(k_dbl_apply, dim3(2048), dim3(PSL_BLOCK), 0, s, d, S);
+    hipLaunchKernelGGL(k_dbl_shift, dim3(256), dim3(DBL_SHIFT_BLOCK), 0, s, d, S);
+  }
 }
 
 void launch_doubleton_relock(const Dev& d, const DblScratch& S, hipStream_t s) {

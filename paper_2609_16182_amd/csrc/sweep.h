@@ -135,6 +135,12 @@ void launch_par_emit(const Dev& d, const ParScratch& p, int64_t base, int round,
 void launch_par_drop(const Dev& d, const ParScratch& p, hipStream_t s);
 
 // doubleton.hip: doubleton-equality substitution (allocated when enabled)
+// a rewrite of a long row that inserts the kept column (entries move by one
+// over up to the whole row), done by a workgroup after the substitutions
+struct DblTask {
+  int32_t r, k, j, pad;  // row, eliminated column, kept column
+  double v;              // the kept column's new coefficient
+};
 struct DblScratch {
   int32_t* list;       // [m] candidate rows
   int32_t *cj, *ck;    // [m] kept / eliminated column of a candidate (-1: none)
@@ -145,7 +151,10 @@ struct DblScratch {
   int32_t* by;         // [n] applied row whose kept column this is, -1
   double2* tb;         // [n] interval x_k's bounds give a kept column
   int32_t* total;      // [2] records: rows, transferred bounds
+  DblTask* long_task;  // [doubleton_long_cap(nnz)] deferred long-row rewrites
+  int32_t* long_cnt;   // [1]
 };
+int64_t doubleton_long_cap(int64_t nnz);  // rows longer than the lane-rewrite limit, at most
 void launch_doubletons(const Dev& d, const DblScratch& S, int64_t base, int round, int32_t* ws, hipStream_t s);
 void launch_doubleton_relock(const Dev& d, const DblScratch& S, hipStream_t s);
 void launch_doubleton_init(const Dev& d, const DblScratch& S, hipStream_t s);  // no column kept yet

@@ -120,6 +120,30 @@ def test_postsolve_bit_exact_and_kkt():
     assert checked >= 60
 
 
+def _long_row_lp(k0, j0, n=12002, j_in_long=False):
+    """x_k0 + 2 x_j0 = 3 eliminates k0 (two alive rows against three), whose
+    other row is long (every column but j0, unless j_in_long): the rewrite
+    inserts j0 and moves the entries between the two columns by one."""
+    long_row = [(c, 1.0 + 0.25 * (c % 7)) for c in range(n) if j_in_long or c != j0]
+    rows = [[(k0, 1.0), (j0, 2.0)], long_row, [(j0, 1.0), (100, 1.0)], [(j0, 1.0), (200, 1.0)]]
+    half = 0.5 * sum(10.0 * a for _, a in long_row)
+    c = np.random.default_rng(k0 + j0).uniform(-1, 1, n)
+    return make(4, n, rows, [3.0, -INF, -INF, -INF], [3.0, half, 5.0, 6.0], [0.0] * n, [10.0] * n, c)
+
+
+@pytest.mark.parametrize("k0,j0,j_in_long", [(7, 11000, False), (11000, 7, False), (7, 11000, True),
+                                             (5000, 5001, False), (12001, 0, False)])
+def test_long_row_rewrite(k0, j0, j_in_long):
+    """A long row (12001 entries) rewritten by a substitution: the kept column
+    inserted far from the eliminated one, in either direction, across several
+    chunks of the workgroup's move; next to it; or already present."""
+    lp = _long_row_lp(k0, j0, j_in_long=j_in_long)
+    got, ref = run_both(lp)
+    db = ref.records[ref.records["type"] == O.REC["DOUBLETON_ROW"]]
+    assert len(db) == 1 and db["j"][0] == j0 and db["k"][0] == k0, db
+    assert_same(got, ref, f"long row k={k0} j={j0}")
+
+
 def test_batch_equals_alone():
     lps = [with_doubletons(lpgen.tiny(s, finite_bounds=s % 2 == 0), s) for s in range(24)]
     lps += [lpgen.make_lp(300, 450, seed=410, row_len=(2, 7), singleton=10, empty=5, doubleton=40, duplicate=10,
