@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--batch-no-seq", action="store_true", help="skip the sequential single-LP baseline")
     ap.add_argument("--serve-pool", type=int, default=256, help="LPs in the serving pool (0 = skip serving)")
     ap.add_argument("--serve-rates", default="50,200,1000,2000")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--serve-slots", type=int, default=4, help="batch engines of the continuous-batching server")
     ap.add_argument("--only-serving", action="store_true", help="run the serving workload only")
     return ap.parse_args()
