@@ -514,7 +514,8 @@ typedef struct {
                                  resident reduced problems                   */
     int32_t slots;            /* batches in flight at once (>= 1)            */
     int32_t threaded;         /* 1: each slot has a worker thread; 0: no
-                                 threads, psl_server_step runs one batch     */
+                                 threads, the caller steps the server with
+                                 psl_server_step                             */
     int32_t max_batch_lps;    /* LPs per batch                               */
     int32_t max_batch_rows, max_batch_cols;
     int64_t max_batch_nnz;    /* also the largest LP that can be served      */
@@ -541,9 +542,15 @@ psl_status psl_server_create(const psl_server_config *c, const psl_settings *s, 
  * result heap; shape errors as at create (PSL_ERR_INVALID). */
 psl_status psl_server_submit(psl_server *sv, const psl_lp *lp, uint64_t *ticket);
 
-/* Without worker threads (threaded = 0): admit waiting LPs into a batch on
- * slot 0 and presolve it before returning. *n_run = LPs presolved (0 when the
- * queue was empty or the head does not fit yet). PSL_ERR_STATE if threaded. */
+/* Without worker threads (threaded = 0): one step of the request loop. Every
+ * free slot admits a batch of waiting LPs from the queue head (as a worker
+ * would); every resident batch then advances by one unit of its run -- a
+ * propagation round, an outer cycle's reduction pass, or the compaction --
+ * with all slots' kernels queued before the step waits for any; batches
+ * whose run ended are retired (their tickets done, reduced problems copied
+ * to the result heap, records to the host). Nothing runs between steps.
+ * *n_run = LPs resident during the step (0: the server is idle -- nothing
+ * waiting, or the head does not fit yet). PSL_ERR_STATE if threaded. */
 psl_status psl_server_step(psl_server *sv, int32_t *n_run);
 
 /* Copy up to cap tickets completed since the last poll into tickets[], in
@@ -584,7 +591,9 @@ psl_status psl_server_postsolve(psl_server *sv, uint64_t ticket, const double *x
 /* Free the ticket's device memory and state. */
 psl_status psl_server_release(psl_server *sv, uint64_t ticket);
 
-/* Block until the queue is empty and no batch runs. */
+/* Block until the queue is empty and no batch runs (without threads: step
+ * the server until then; PSL_ERR_CAPACITY if the queue head cannot be
+ * admitted on an idle server). */
 psl_status psl_server_drain(psl_server *sv);
 
 /* Device memory of the server: the slot arenas, the result heap's size, the

@@ -991,16 +991,32 @@ static psl_status split_records(psl_presolver* p) {
 // pass, another cycle only if that pass merged rows; infeasible or unbounded
 // ends it at once. In a batch an LP that converged waits for the cycle's
 // parallel pass (sweeping its rows again changes nothing); LPs that stopped
-// are dropped from the bin lists.
-static psl_status run_engine(psl_presolver* p, psl_stats* out) {
-  Dev& d = p->d;
-  hipStream_t st = p->stream;
-  const psl_settings& s = p->s;
+// are dropped from the bin lists. The run goes unit by unit (EngRun): each
+// launch queues a unit's kernels and the reads of its results, each
+// completion waits for them and decides the next unit.
+
+static bool lp_inf(const psl_presolver* p, int k) {
+  return p->K > 1 ? p->h_lpf[k].infeasible != 0 : p->hflags->infeasible != 0;
+}
+static bool lp_unb(const psl_presolver* p, int k) {
+  return p->K > 1 ? p->h_lpf[k].unbounded != 0 : p->hflags->unbounded != 0;
+}
+static bool lp_merged(const psl_presolver* p, int k) {
+  return p->K > 1 ? p->h_lpf[k].merged != 0 : p->hflags->merged != 0;
+}
+static int32_t lp_total(const psl_presolver* p, int k) {
+  return p->K > 1 ? p->h_lpo[k].total : p->hflags->round_total;
+}
+
+// queue the read of the device flags (completed by the unit's wait)
+static psl_status queue_flags(psl_presolver* p) {
+  HIPCHK(p, hipMemcpyAsync(p->hflags, p->d.flags, sizeof(Flags), hipMemcpyDeviceToHost, p->stream));
+  return PSL_OK;
+}
+
+psl_status psl::engine_start(psl_presolver* p) {
+  if (p->state != 0) return fail(p, PSL_ERR_STATE, "run needs a fresh load");
   const int K = p->K;
-  const bool B = K > 1;
-  int64_t m = p->m, n = p->n;
-  psl_stats S{};
-  S.nnz_in = p->nnz;
   p->rec_count = 0;
   p->rec_flushed = 0;
   p->flushes = 0;
@@ -1009,21 +1025,66 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   p->lp_host_rec.clear();
   p->state = 1;
   p->lst.assign(K, LpState{});
-  HIPCHK(p, hipEventRecord(p->ev[2], st));
-  if (B) {
+  p->run = EngRun{};
+  p->run.S.nnz_in = p->nnz;
+  p->run.unit = U_ROUND0;
+  HIPCHK(p, hipEventRecord(p->ev[2], p->stream));
+  if (K > 1) {
     for (int k = 0; k < K; ++k) {
       p->h_ok[k] = 1;
       p->h_round[k] = 0;
     }
-    HIPCHK(p, hipMemcpyAsync(p->lp_ok, p->h_ok, K, hipMemcpyHostToDevice, st));
+    HIPCHK(p, hipMemcpyAsync(p->lp_ok, p->h_ok, K, hipMemcpyHostToDevice, p->stream));
     psl_status e0 = begin_lp_round(p);
     if (e0 != PSL_OK) return e0;
   }
-  auto lp_inf = [&](int k) { return B ? p->h_lpf[k].infeasible != 0 : p->hflags->infeasible != 0; };
-  auto lp_unb = [&](int k) { return B ? p->h_lpf[k].unbounded != 0 : p->hflags->unbounded != 0; };
-  auto lp_merged = [&](int k) { return B ? p->h_lpf[k].merged != 0 : p->hflags->merged != 0; };
-  auto lp_total = [&](int k) { return B ? p->h_lpo[k].total : p->hflags->round_total; };
+  return PSL_OK;
+}
 
+// the top of an outer cycle: its first round, or the compaction when no LP
+// propagates any more
+static psl_status cycle_start(psl_presolver* p) {
+  EngRun& R = p->run;
+  int nprop = 0;
+  if (R.outer < p->s.max_outer)
+    for (auto& L : p->lst)
+      if (L.phase == LP_PROP) {
+        L.cycles = R.outer + 1;
+        ++nprop;
+      }
+  if (nprop == 0) {
+    R.unit = U_COMPACT;
+    return PSL_OK;
+  }
+  R.consts_current = false;
+  R.r = 0;
+  R.unit = U_ROUND;
+  // a cycle's first round sweeps every active row
+  return use_full_view(p);
+}
+
+// after a cycle's rounds: its reduction pass, or the compaction
+static void rounds_end(psl_presolver* p) {
+  const psl_settings& s = p->s;
+  int npar = 0;
+  for (auto& L : p->lst)
+    if (L.phase != LP_DONE) ++npar;
+  if (npar == 0) {
+    p->run.unit = U_COMPACT;
+    return;
+  }
+  if (!s.enable_parallel_rows && !s.enable_parallel_cols && !s.enable_doubletons && !s.enable_dominated) {
+    for (auto& L : p->lst) L.phase = LP_DONE;
+    p->run.unit = U_COMPACT;
+    return;
+  }
+  p->run.unit = U_PASS;
+}
+
+static psl_status launch_round0(psl_presolver* p) {
+  Dev& d = p->d;
+  hipStream_t st = p->stream;
+  int64_t m = p->m, n = p->n;
   // the run works on a copy of the costs (free-singleton substitutions
   // change it); the input's stay for postsolve
   if (n) HIPCHK(p, hipMemcpyAsync(p->c_work, p->c_mut, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1032,249 +1093,273 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   launch_round0_count(d, st);
   scan_excl(d.cnt, d.off, m + n, &d.flags->round_total, p->ws, st);
   launch_round0_emit(d, 0, st);
-  if (s.enable_dual_fix) init_locks(d, p->isc.v0, p->isc.v1, p->ws, st);  // ingest scratch, free until compaction
+  if (p->s.enable_dual_fix) init_locks(d, p->isc.v0, p->isc.v1, p->ws, st);  // ingest scratch, free until compaction
   psl_status e = queue_lp_read(p, false);
   if (e != PSL_OK) return e;
-  e = read_flags(p);
-  if (e != PSL_OK) return e;
+  return queue_flags(p);
+}
+
+static psl_status complete_round0(psl_presolver* p) {
   p->rec_count += p->hflags->round_total;
-  int round = 0;
-  double sweep_ms = 0.0, decide_ms = 0.0, par_ms = 0.0, long_ms = 0.0;
   bool any_done = false;
-  for (int k = 0; k < K; ++k)
-    if (lp_inf(k)) {
+  for (int k = 0; k < p->K; ++k)
+    if (lp_inf(p, k)) {
       p->lst[k].phase = LP_DONE;
       p->lst[k].infeasible = true;
       p->lst[k].cycles = 1;
       any_done = true;
     }
-  if (B && any_done) {
-    e = drop_done_lps(p);
+  if (p->K > 1 && any_done) {
+    psl_status e = drop_done_lps(p);
     if (e != PSL_OK) return e;
   }
+  return cycle_start(p);
+}
 
-  int outer = 0;
-  // row_out holds every live row's removed-column constant and active
-  // length of the current bounds (a parallel pass hashed every live row and
-  // then changed nothing), so the compaction need not sweep for them again
-  bool consts_current = false;
-  for (; outer < s.max_outer; ++outer) {
-    int nprop = 0;
-    for (auto& L : p->lst)
-      if (L.phase == LP_PROP) {
-        L.cycles = outer + 1;
-        ++nprop;
-      }
-    if (nprop == 0) break;
-    consts_current = false;
-    // a cycle's first round sweeps every active row
-    e = use_full_view(p);
-    if (e != PSL_OK) return e;
-    for (int r = 0; r < s.max_rounds; ++r) {
-      ++round;
-      for (int k = 0; k < K; ++k)
-        if (p->lst[k].phase == LP_PROP) {
-          ++p->lst[k].rounds;
-          if (B) p->h_round[k] = p->lst[k].rounds;
-        }
-      e = ensure_capacity(p, m + 3 * n + 16);
-      if (e == PSL_OK) e = begin_lp_round(p);
-      if (e != PSL_OK) return e;
-      HIPCHK(p, hipEventRecord(p->ev[4], st));
-      launch_long_stats(d, MODE_ROUND, st);
-      HIPCHK(p, hipEventRecord(p->ev[7], st));
-      launch_sweep(d, p->grid, p->sweep_mode, st);
-      HIPCHK(p, hipEventRecord(p->ev[5], st));
-      launch_src(d, p->grid, st);
-      launch_decide(d, p->rec_count - p->rec_flushed, round, d.cnt, d.off, p->ws, st);
-      // (the candidate regions are free until the next sweep)
-      if (s.enable_free_singletons)
-        launch_free_singletons(d, reinterpret_cast<int32_t*>(d.cand), p->rec_count - p->rec_flushed, round, p->ws,
-                               st);
-      HIPCHK(p, hipEventRecord(p->ev[6], st));
-      // The next round's selection is made before the round's one read, in
-      // one pass over the rows. Rows none of whose columns changed since they
-      // were last swept give the same statistics and no qualifying candidate,
-      // so after a round with few column changes only the touched (marked)
-      // rows are swept; and inert rows (their infinite-contribution counts,
-      // kept current as bounds become finite, rule out every outcome) are
-      // never swept. The counts are kept by decrements while few bounds
-      // become finite in a round. After a round with many, no decrement is
-      // made and the next round skips no row: it sweeps, and so recounts,
-      // every row one of whose bounds became finite, while the counts of the
-      // rows it does not sweep are still exact; after it the counts are
-      // exact again. The device takes these decisions from the round's totals
-      // (d.flags->mode); an LP that stopped has left lp_ok already. When the
-      // rounds end here the selection is not used.
-      if (!d.dirty || !d.colid) return fail(p, PSL_ERR_DEVICE, "internal: incremental state not set up");
-      mark_dirty(d, r + 1 < s.max_rounds, p->incr_factor, p->count_factor, st);
-      queue_selection(p);
-      e = queue_lp_read(p, true);
-      if (e != PSL_OK) return e;
-      int32_t removed = 0;
-      e = read_round(p, &removed);
-      if (e != PSL_OK) return e;
-      long_ms += elapsed(p, 4, 7);
-      sweep_ms += elapsed(p, 7, 5);
-      decide_ms += elapsed(p, 5, 6);
-      S.sweep_launches += 1;
-      S.sweep_nnz += p->cur.nnz;
-      // algorithmic bytes of the sweep launch: the swept rows' positions
-      // (12 B a nonzero); per swept row its bin entry, row pointer, sides and
-      // statistics (48 B); per column it can touch (at most one per nonzero)
-      // the bound read and the new-bound write (32 B)
-      {
-        double sb = 12.0 * p->cur.nnz + 48.0 * p->cur.rows + 32.0 * std::min<int64_t>(n, p->cur.nnz);
-        S.sweep_bytes += sb;
-        // the decisions over every row and column, and the round's records
-        S.alg_bytes += sb + 40.0 * ((double)m + n) + 48.0 * p->hflags->round_total;
-      }
-      p->rec_count += p->hflags->round_total;
-      any_done = false;
-      nprop = 0;
-      for (int k = 0; k < K; ++k) {
-        LpState& L = p->lst[k];
-        if (L.phase != LP_PROP) continue;
-        if (lp_inf(k)) {
-          L.phase = LP_DONE;
-          L.infeasible = true;
-          any_done = true;
-        } else if (lp_unb(k)) {
-          L.phase = LP_DONE;
-          L.unbounded = true;
-          any_done = true;
-        } else if (lp_total(k) == 0) {
-          L.phase = LP_WAIT;
-        } else {
-          ++nprop;
-        }
-      }
-      if (p->trace)
-        std::fprintf(stderr, "[psl] round %d: swept rows %lld nnz %lld, records %d, rows removed %d, "
-                     "bounds made finite %d, LPs propagating %d\n", round, (long long)p->cur.rows,
-                     (long long)p->cur.nnz, p->hflags->round_total, removed, p->hflags->fin_cols, nprop);
-      if (nprop == 0) break;
-      if (B && any_done) {
-        e = drop_done_lps(p);
-        if (e != PSL_OK) return e;
-      }
-      use_view(p, view_of(p->bins_s, p->chunks_s, p->hflags->sel));
+static psl_status launch_round(psl_presolver* p) {
+  Dev& d = p->d;
+  hipStream_t st = p->stream;
+  const psl_settings& s = p->s;
+  EngRun& R = p->run;
+  int64_t m = p->m, n = p->n;
+  ++R.round;
+  for (int k = 0; k < p->K; ++k)
+    if (p->lst[k].phase == LP_PROP) {
+      ++p->lst[k].rounds;
+      if (p->K > 1) p->h_round[k] = p->lst[k].rounds;
     }
-    // the cycle's parallel-row pass, for every LP still presolving
-    int npar = 0;
-    for (auto& L : p->lst)
-      if (L.phase != LP_DONE) ++npar;
-    if (npar == 0) break;
-    if (!s.enable_parallel_rows && !s.enable_parallel_cols && !s.enable_doubletons && !s.enable_dominated) {
-      for (auto& L : p->lst) L.phase = LP_DONE;
-      break;
-    }
-    ++round;
-    for (int k = 0; k < K; ++k)
-      if (p->lst[k].phase != LP_DONE) {
-        ++p->lst[k].rounds;
-        if (B) p->h_round[k] = p->lst[k].rounds;
-      }
-    e = use_full_view(p);
-    // row records, then column records (and a substitution pass's)
-    if (e == PSL_OK) e = ensure_capacity(p, pass_records(&s, m, n));
-    if (e == PSL_OK) e = begin_lp_round(p);
-    if (e != PSL_OK) return e;
-    HIPCHK(p, hipEventRecord(p->ev[4], st));
-    // every live row's removed-column constant and active length go to
-    // row_out (free once the round's records are emitted): long rows from
-    // their chunk partials here, the others in the hash pass
-    if (s.enable_parallel_rows) launch_long_consts(d, st);
-    launch_par_reset(d, p->par, st);
-    if (s.enable_parallel_rows) {
-      launch_par_hash(d, p->par, p->grid, st);
-      launch_par_verify(d, p->par, st);
-      launch_par_count(d, p->par, st);
-      scan_excl(d.cnt, d.off, m, &d.flags->round_total, p->ws, st);
-      launch_par_emit(d, p->par, p->rec_count - p->rec_flushed, round, st);
-      launch_par_drop(d, p->par, st);
+  psl_status e = ensure_capacity(p, m + 3 * n + 16);
+  if (e == PSL_OK) e = begin_lp_round(p);
+  if (e != PSL_OK) return e;
+  HIPCHK(p, hipEventRecord(p->ev[4], st));
+  launch_long_stats(d, MODE_ROUND, st);
+  HIPCHK(p, hipEventRecord(p->ev[7], st));
+  launch_sweep(d, p->grid, p->sweep_mode, st);
+  HIPCHK(p, hipEventRecord(p->ev[5], st));
+  launch_src(d, p->grid, st);
+  launch_decide(d, p->rec_count - p->rec_flushed, R.round, d.cnt, d.off, p->ws, st);
+  // (the candidate regions are free until the next sweep)
+  if (s.enable_free_singletons)
+    launch_free_singletons(d, reinterpret_cast<int32_t*>(d.cand), p->rec_count - p->rec_flushed, R.round, p->ws,
+                           st);
+  HIPCHK(p, hipEventRecord(p->ev[6], st));
+  // The next round's selection is made before the round's one read, in
+  // one pass over the rows. Rows none of whose columns changed since they
+  // were last swept give the same statistics and no qualifying candidate,
+  // so after a round with few column changes only the touched (marked)
+  // rows are swept; and inert rows (their infinite-contribution counts,
+  // kept current as bounds become finite, rule out every outcome) are
+  // never swept. The counts are kept by decrements while few bounds
+  // become finite in a round. After a round with many, no decrement is
+  // made and the next round skips no row: it sweeps, and so recounts,
+  // every row one of whose bounds became finite, while the counts of the
+  // rows it does not sweep are still exact; after it the counts are
+  // exact again. The device takes these decisions from the round's totals
+  // (d.flags->mode); an LP that stopped has left lp_ok already. When the
+  // rounds end here the selection is not used.
+  if (!d.dirty || !d.colid) return fail(p, PSL_ERR_DEVICE, "internal: incremental state not set up");
+  mark_dirty(d, R.r + 1 < s.max_rounds, p->incr_factor, p->count_factor, st);
+  queue_selection(p);
+  e = queue_lp_read(p, true);
+  if (e != PSL_OK) return e;
+  return queue_flags(p);
+}
+
+static psl_status complete_round(psl_presolver* p) {
+  EngRun& R = p->run;
+  psl_stats& S = R.S;
+  int64_t m = p->m, n = p->n;
+  int32_t removed = p->hflags->rows_removed;
+  R.long_ms += elapsed(p, 4, 7);
+  R.sweep_ms += elapsed(p, 7, 5);
+  R.decide_ms += elapsed(p, 5, 6);
+  S.sweep_launches += 1;
+  S.sweep_nnz += p->cur.nnz;
+  // algorithmic bytes of the sweep launch: the swept rows' positions
+  // (12 B a nonzero); per swept row its bin entry, row pointer, sides and
+  // statistics (48 B); per column it can touch (at most one per nonzero)
+  // the bound read and the new-bound write (32 B)
+  {
+    double sb = 12.0 * p->cur.nnz + 48.0 * p->cur.rows + 32.0 * std::min<int64_t>(n, p->cur.nnz);
+    S.sweep_bytes += sb;
+    // the decisions over every row and column, and the round's records
+    S.alg_bytes += sb + 40.0 * ((double)m + n) + 48.0 * p->hflags->round_total;
+  }
+  p->rec_count += p->hflags->round_total;
+  bool any_done = false;
+  int nprop = 0;
+  for (int k = 0; k < p->K; ++k) {
+    LpState& L = p->lst[k];
+    if (L.phase != LP_PROP) continue;
+    if (lp_inf(p, k)) {
+      L.phase = LP_DONE;
+      L.infeasible = true;
+      any_done = true;
+    } else if (lp_unb(p, k)) {
+      L.phase = LP_DONE;
+      L.unbounded = true;
+      any_done = true;
+    } else if (lp_total(p, k) == 0) {
+      L.phase = LP_WAIT;
     } else {
-      fill_i32(&d.flags->round_total, 0, 1, st);
-    }
-    // parallel columns on the rows the row pass left (an LP it found
-    // infeasible has stopped)
-    if (s.enable_parallel_cols) launch_par_cols(d, p->pc, p->rec_count - p->rec_flushed, round, p->ws, st);
-    if (s.enable_dominated) launch_dominated(d, p->dom, p->rec_count - p->rec_flushed, round, p->ws, st);
-    if (s.enable_doubletons) {
-      // active lengths and removed-column constants after the parallel
-      // passes (row_out), then the substitutions
-      launch_long_stats(d, MODE_COMPACT, st);
-      launch_sweep(d, p->grid, MODE_COMPACT, st);
-      launch_doubletons(d, p->dbl, p->rec_count - p->rec_flushed, round, p->ws, st);
-    }
-    HIPCHK(p, hipEventRecord(p->ev[5], st));
-    e = queue_lp_read(p, false);
-    if (e == PSL_OK) e = read_flags(p);
-    if (e != PSL_OK) return e;
-    consts_current = !B && s.enable_parallel_rows && !p->hflags->merged;
-    if (s.enable_doubletons && p->hflags->dbl_applied) {
-      // rows were rewritten: the transposed copy (and what hangs on it) again
-      p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.cnt, p->isc, p->red.val, st);
-      p->cmp.colid = p->colid;
-      d.colid = p->colid;
-      list_dense_cols(d, st);
-      launch_doubleton_relock(d, p->dbl, st);
-      S.alg_bytes += 36.0 * (double)p->nnz;
-    }
-    par_ms += elapsed(p, 4, 5);
-    // keys and table per row, one pass over the positions, the records
-    S.alg_bytes += 40.0 * m + 12.0 * (double)p->nnz + 48.0 * p->hflags->round_total;
-    p->rec_count += p->hflags->round_total;
-    any_done = false;
-    for (int k = 0; k < K; ++k) {
-      LpState& L = p->lst[k];
-      if (L.phase == LP_DONE) continue;
-      if (lp_inf(k)) {
-        L.phase = LP_DONE;
-        L.infeasible = true;
-      } else if (lp_unb(k)) {  // dominated columns: an infinite fixing or crossing dual bounds
-        L.phase = LP_DONE;
-        L.unbounded = true;
-      } else if (lp_merged(k) && outer + 1 < s.max_outer) {
-        L.phase = LP_PROP;
-      } else {
-        L.phase = LP_DONE;
-      }
-      any_done |= L.phase == LP_DONE;
-    }
-    if (B && any_done) {
-      e = drop_done_lps(p);
-      if (e != PSL_OK) return e;
+      ++nprop;
     }
   }
+  if (p->trace)
+    std::fprintf(stderr, "[psl] round %d: swept rows %lld nnz %lld, records %d, rows removed %d, "
+                 "bounds made finite %d, LPs propagating %d\n", R.round, (long long)p->cur.rows,
+                 (long long)p->cur.nnz, p->hflags->round_total, removed, p->hflags->fin_cols, nprop);
+  if (nprop == 0) {
+    rounds_end(p);
+    return PSL_OK;
+  }
+  if (p->K > 1 && any_done) {
+    psl_status e = drop_done_lps(p);
+    if (e != PSL_OK) return e;
+  }
+  use_view(p, view_of(p->bins_s, p->chunks_s, p->hflags->sel));
+  if (++R.r < p->s.max_rounds) R.unit = U_ROUND;
+  else rounds_end(p);
+  return PSL_OK;
+}
 
-  // compaction of the LPs that ended feasible
-  bool any_feasible = false;
-  for (auto& L : p->lst) any_feasible |= !L.infeasible && !L.unbounded;
-  double cmp_ms = 0.0;
+// the cycle's reduction pass (parallel rows, then the optional column
+// explorers), for every LP still presolving
+static psl_status launch_pass(psl_presolver* p) {
+  Dev& d = p->d;
+  hipStream_t st = p->stream;
+  const psl_settings& s = p->s;
+  EngRun& R = p->run;
+  int64_t m = p->m, n = p->n;
+  ++R.round;
+  for (int k = 0; k < p->K; ++k)
+    if (p->lst[k].phase != LP_DONE) {
+      ++p->lst[k].rounds;
+      if (p->K > 1) p->h_round[k] = p->lst[k].rounds;
+    }
+  psl_status e = use_full_view(p);
+  // row records, then column records (and a substitution pass's)
+  if (e == PSL_OK) e = ensure_capacity(p, pass_records(&s, m, n));
+  if (e == PSL_OK) e = begin_lp_round(p);
+  if (e != PSL_OK) return e;
+  HIPCHK(p, hipEventRecord(p->ev[4], st));
+  // every live row's removed-column constant and active length go to
+  // row_out (free once the round's records are emitted): long rows from
+  // their chunk partials here, the others in the hash pass
+  if (s.enable_parallel_rows) launch_long_consts(d, st);
+  launch_par_reset(d, p->par, st);
+  if (s.enable_parallel_rows) {
+    launch_par_hash(d, p->par, p->grid, st);
+    launch_par_verify(d, p->par, st);
+    launch_par_count(d, p->par, st);
+    scan_excl(d.cnt, d.off, m, &d.flags->round_total, p->ws, st);
+    launch_par_emit(d, p->par, p->rec_count - p->rec_flushed, R.round, st);
+    launch_par_drop(d, p->par, st);
+  } else {
+    fill_i32(&d.flags->round_total, 0, 1, st);
+  }
+  // parallel columns on the rows the row pass left (an LP it found
+  // infeasible has stopped)
+  if (s.enable_parallel_cols) launch_par_cols(d, p->pc, p->rec_count - p->rec_flushed, R.round, p->ws, st);
+  if (s.enable_dominated) launch_dominated(d, p->dom, p->rec_count - p->rec_flushed, R.round, p->ws, st);
+  if (s.enable_doubletons) {
+    // active lengths and removed-column constants after the parallel
+    // passes (row_out), then the substitutions
+    launch_long_stats(d, MODE_COMPACT, st);
+    launch_sweep(d, p->grid, MODE_COMPACT, st);
+    launch_doubletons(d, p->dbl, p->rec_count - p->rec_flushed, R.round, p->ws, st);
+  }
+  HIPCHK(p, hipEventRecord(p->ev[5], st));
+  e = queue_lp_read(p, false);
+  if (e != PSL_OK) return e;
+  return queue_flags(p);
+}
+
+static psl_status complete_pass(psl_presolver* p) {
+  Dev& d = p->d;
+  hipStream_t st = p->stream;
+  const psl_settings& s = p->s;
+  EngRun& R = p->run;
+  psl_stats& S = R.S;
+  int64_t m = p->m;
+  R.consts_current = p->K == 1 && s.enable_parallel_rows && !p->hflags->merged;
+  R.par_ms += elapsed(p, 4, 5);
+  if (s.enable_doubletons && p->hflags->dbl_applied) {
+    // rows were rewritten: the transposed copy (and what hangs on it) again
+    p->colid = build_csc(d, (int32_t*)d.cp, (int32_t*)d.ri, (double*)d.cva, d.cnt, p->isc, p->red.val, st);
+    p->cmp.colid = p->colid;
+    d.colid = p->colid;
+    list_dense_cols(d, st);
+    launch_doubleton_relock(d, p->dbl, st);
+    S.alg_bytes += 36.0 * (double)p->nnz;
+  }
+  // keys and table per row, one pass over the positions, the records
+  S.alg_bytes += 40.0 * m + 12.0 * (double)p->nnz + 48.0 * p->hflags->round_total;
+  p->rec_count += p->hflags->round_total;
+  bool any_done = false;
+  for (int k = 0; k < p->K; ++k) {
+    LpState& L = p->lst[k];
+    if (L.phase == LP_DONE) continue;
+    if (lp_inf(p, k)) {
+      L.phase = LP_DONE;
+      L.infeasible = true;
+    } else if (lp_unb(p, k)) {  // dominated columns: an infinite fixing or crossing dual bounds
+      L.phase = LP_DONE;
+      L.unbounded = true;
+    } else if (lp_merged(p, k) && R.outer + 1 < s.max_outer) {
+      L.phase = LP_PROP;
+    } else {
+      L.phase = LP_DONE;
+    }
+    any_done |= L.phase == LP_DONE;
+  }
+  if (p->K > 1 && any_done) {
+    psl_status e = drop_done_lps(p);
+    if (e != PSL_OK) return e;
+  }
+  ++R.outer;
+  return cycle_start(p);
+}
+
+// compaction of the LPs that ended feasible
+static psl_status launch_compact(psl_presolver* p) {
+  Dev& d = p->d;
+  hipStream_t st = p->stream;
+  EngRun& R = p->run;
+  const int K = p->K;
+  R.any_feasible = false;
+  for (auto& L : p->lst) R.any_feasible |= !L.infeasible && !L.unbounded;
   p->red_m = p->red_n = 0;
   p->red_nnz = 0;
-  if (any_feasible) {
-    if (B) {
-      for (int k = 0; k < K; ++k) p->h_ok[k] = !p->lst[k].infeasible && !p->lst[k].unbounded;
-      HIPCHK(p, hipMemcpyAsync(p->lp_ok, p->h_ok, K, hipMemcpyHostToDevice, st));
-    }
-    e = use_full_view(p);
-    if (e != PSL_OK) return e;
-    HIPCHK(p, hipEventRecord(p->ev[4], st));
-    if (!consts_current) {
-      launch_long_stats(d, MODE_COMPACT, st);
-      launch_sweep(d, p->grid, MODE_COMPACT, st);
-    }
-    compact_flags(d, p->cmp, st);
-    compact_write(d, p->cmp, p->red, p->obj_offset, st);
-    HIPCHK(p, hipEventRecord(p->ev[5], st));
-    HIPCHK(p, hipMemcpyAsync(p->htot, p->cmp.totals, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(p, hipMemcpyAsync(p->h_lpr, p->lpr, (K + 1) * sizeof(LpRed), hipMemcpyDeviceToHost, st));
-    if (B) HIPCHK(p, hipMemcpyAsync(p->h_off, p->cmp.offset, K * sizeof(double), hipMemcpyDeviceToHost, st));
-    else HIPCHK(p, hipMemcpyAsync(p->hoff, p->cmp.offset, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(p, hipStreamSynchronize(st));
-    cmp_ms = elapsed(p, 4, 5);
+  if (!R.any_feasible) return PSL_OK;
+  if (K > 1) {
+    for (int k = 0; k < K; ++k) p->h_ok[k] = !p->lst[k].infeasible && !p->lst[k].unbounded;
+    HIPCHK(p, hipMemcpyAsync(p->lp_ok, p->h_ok, K, hipMemcpyHostToDevice, st));
+  }
+  psl_status e = use_full_view(p);
+  if (e != PSL_OK) return e;
+  HIPCHK(p, hipEventRecord(p->ev[4], st));
+  if (!R.consts_current) {
+    launch_long_stats(d, MODE_COMPACT, st);
+    launch_sweep(d, p->grid, MODE_COMPACT, st);
+  }
+  compact_flags(d, p->cmp, st);
+  compact_write(d, p->cmp, p->red, p->obj_offset, st);
+  HIPCHK(p, hipEventRecord(p->ev[5], st));
+  HIPCHK(p, hipMemcpyAsync(p->htot, p->cmp.totals, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(p, hipMemcpyAsync(p->h_lpr, p->lpr, (K + 1) * sizeof(LpRed), hipMemcpyDeviceToHost, st));
+  if (K > 1) HIPCHK(p, hipMemcpyAsync(p->h_off, p->cmp.offset, K * sizeof(double), hipMemcpyDeviceToHost, st));
+  else HIPCHK(p, hipMemcpyAsync(p->hoff, p->cmp.offset, sizeof(double), hipMemcpyDeviceToHost, st));
+  return PSL_OK;
+}
+
+static psl_status complete_compact(psl_presolver* p) {
+  EngRun& R = p->run;
+  psl_stats& S = R.S;
+  const int K = p->K;
+  const bool B = K > 1;
+  if (R.any_feasible) {
+    R.cmp_ms = elapsed(p, 4, 5);
     p->red_m = p->htot[0];
     p->red_n = p->htot[1];
     p->red_nnz = p->htot[2];
@@ -1286,10 +1371,10 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
         return fail(p, PSL_ERR_DEVICE, "reduced CSR and transposed copy disagree");
   }
   if (B) {
-    e = split_records(p);
+    psl_status e = split_records(p);
     if (e != PSL_OK) return e;
   }
-  HIPCHK(p, hipEventRecord(p->ev[3], st));
+  HIPCHK(p, hipEventRecord(p->ev[3], p->stream));
   HIPCHK(p, hipEventSynchronize(p->ev[3]));
 
   p->lp_result.resize(K);
@@ -1302,7 +1387,7 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
                              : PSL_RES_UNCHANGED;
   }
   p->result = p->lp_result[0];
-  S.rounds = round;
+  S.rounds = R.round;
   S.outer_cycles = 1;
   for (auto& L : p->lst) S.outer_cycles = std::max(S.outer_cycles, L.cycles);
   S.records = p->rec_count;
@@ -1312,14 +1397,51 @@ static psl_status run_engine(psl_presolver* p, psl_stats* out) {
   S.n_out = p->red_n;
   S.ms_ingest = p->ms_ingest;
   S.ingest_bytes = 36.0 * (double)p->nnz + 32.0 * p->m + 48.0 * p->n;
-  S.ms_sweep = sweep_ms;
-  S.ms_long = long_ms;
-  S.ms_decide = decide_ms;
-  S.ms_parallel = par_ms;
-  S.ms_compact = cmp_ms;
+  S.ms_sweep = R.sweep_ms;
+  S.ms_long = R.long_ms;
+  S.ms_decide = R.decide_ms;
+  S.ms_parallel = R.par_ms;
+  S.ms_compact = R.cmp_ms;
   S.ms_total = elapsed(p, 2, 3);
   p->stats = S;
-  if (out) *out = S;
+  R.unit = U_DONE;
+  return PSL_OK;
+}
+
+psl_status psl::engine_launch(psl_presolver* p) {
+  switch (p->run.unit) {
+    case U_ROUND0: return launch_round0(p);
+    case U_ROUND: return launch_round(p);
+    case U_PASS: return launch_pass(p);
+    case U_COMPACT: return launch_compact(p);
+    default: return fail(p, PSL_ERR_STATE, "the run has ended");
+  }
+}
+
+psl_status psl::engine_complete(psl_presolver* p, bool* done) {
+  *done = false;
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  psl_status e;
+  switch (p->run.unit) {
+    case U_ROUND0: e = complete_round0(p); break;
+    case U_ROUND: e = complete_round(p); break;
+    case U_PASS: e = complete_pass(p); break;
+    case U_COMPACT: e = complete_compact(p); break;
+    default: return fail(p, PSL_ERR_STATE, "the run has ended");
+  }
+  *done = e == PSL_OK && p->run.unit == U_DONE;
+  return e;
+}
+
+static psl_status run_engine(psl_presolver* p, psl_stats* out) {
+  psl_status e = psl::engine_start(p);
+  bool done = false;
+  while (e == PSL_OK && !done) {
+    e = psl::engine_launch(p);
+    if (e == PSL_OK) e = psl::engine_complete(p, &done);
+  }
+  if (e != PSL_OK) return e;
+  if (out) *out = p->stats;
   return PSL_OK;
 }
 

@@ -44,6 +44,22 @@ struct LpState {
   int32_t rounds = 0, cycles = 0;
 };
 
+// A run is a sequence of units, each one launch (kernels and the
+// asynchronous reads of their results, on the engine's stream) and one
+// completion (the wait for those reads, then the host's decisions): round 0,
+// the propagation rounds of each outer cycle, each cycle's reduction pass, the
+// compaction. psl_presolve_run runs them back to back; a stepped server
+// interleaves the units of several batches.
+enum EngUnit { U_ROUND0 = 0, U_ROUND = 1, U_PASS = 2, U_COMPACT = 3, U_DONE = 4 };
+struct EngRun {
+  int unit = U_DONE;               // the unit the next launch starts
+  int outer = 0, r = 0, round = 0;  // cycle, round in the cycle, rounds so far
+  bool consts_current = false;     // row_out current for the compaction
+  bool any_feasible = false;       // the compaction unit has work
+  double sweep_ms = 0.0, decide_ms = 0.0, par_ms = 0.0, long_ms = 0.0, cmp_ms = 0.0;
+  psl_stats S{};
+};
+
 struct psl_presolver {
   using Dev = psl::Dev;
   Dev d{};
@@ -164,6 +180,7 @@ struct psl_presolver {
   psl_stats stats{};
   double ms_ingest = 0.0;
   hipEvent_t ev[8] = {nullptr};
+  EngRun run;
 };
 
 namespace psl {
@@ -180,6 +197,11 @@ void engine_free(psl_presolver* p);
 // load k LPs (totals within the capacity) and run them
 psl_status engine_load(psl_presolver* p, int32_t k, const psl_lp* lps);
 psl_status engine_run(psl_presolver* p, psl_stats* out);
+// the same run one unit at a time: start, then launch / complete until
+// *done (the statistics then as engine_run gives them)
+psl_status engine_start(psl_presolver* p);
+psl_status engine_launch(psl_presolver* p);
+psl_status engine_complete(psl_presolver* p, bool* done);
 psl_result engine_result(const psl_presolver* p, int k);
 bool engine_has_reduced(const psl_presolver* p, int k);
 psl_reduced_view engine_view(const psl_presolver* p, int k);

@@ -11,6 +11,12 @@
 // budget left after the arenas; a block stays allocated until its ticket is
 // released, and the head of the queue waits while its reservation does not
 // fit (admission by HBM footprint, no overtaking).
+//
+// Without worker threads the server is stepped: each psl_server_step admits
+// waiting LPs into the free slots, advances every resident batch by one unit
+// of its run (a propagation round, a cycle's reduction pass, or the
+// compaction; all slots' launches before any wait, so their streams overlap)
+// and retires the batches whose run ended.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -181,6 +187,10 @@ struct Slot {
   int64_t seg_cap = 0;
   std::vector<psl_record> rec_host;
   std::thread th;
+  // stepped server: the batch resident on the slot (its tickets, and those
+  // loaded) while its run goes unit by unit
+  bool busy = false;
+  std::vector<Ticket*> batch, live;
 };
 
 }  // namespace
@@ -271,15 +281,17 @@ static void fail_ticket(Ticket* t, psl_status st, const std::string& msg) {
   t->view = psl_reduced_view{};
 }
 
-// presolve one batch on a slot and copy its results out (lock not held)
-static void run_batch(psl_server* sv, Slot& sl, std::vector<Ticket*>& b) {
-  std::vector<Ticket*> live = b;
+// load a batch's LPs on a slot's engine (lock not held): an invalid LP fails
+// its ticket and the others are loaded again; live = the loaded tickets
+// (empty when none is left)
+static psl_status load_batch(Slot& sl, const std::vector<Ticket*>& b, std::vector<Ticket*>& live) {
+  live = b;
   std::vector<psl_lp> lps;
   psl_status st = PSL_OK;
   for (;;) {
     lps.clear();
     for (Ticket* t : live) lps.push_back(t->lp);
-    if (lps.empty()) return;
+    if (lps.empty()) return PSL_OK;
     st = engine_load(sl.eng, (int32_t)lps.size(), lps.data());
     if (st == PSL_ERR_INVALID && engine_error_lp(sl.eng) >= 0 && engine_error_lp(sl.eng) < (int)live.size()) {
       // drop the invalid LP and load the others again
@@ -290,12 +302,31 @@ static void run_batch(psl_server* sv, Slot& sl, std::vector<Ticket*>& b) {
     }
     break;
   }
+  if (st != PSL_OK) {
+    for (Ticket* t : live) fail_ticket(t, st, engine_error(sl.eng));
+    live.clear();
+  }
+  return st;
+}
+
+static void finish_batch(psl_server* sv, Slot& sl, std::vector<Ticket*>& live);
+
+// presolve one batch on a slot and copy its results out (lock not held)
+static void run_batch(psl_server* sv, Slot& sl, std::vector<Ticket*>& b) {
+  std::vector<Ticket*> live;
+  if (load_batch(sl, b, live) != PSL_OK || live.empty()) return;
   psl_stats S{};
-  if (st == PSL_OK) st = engine_run(sl.eng, &S);
+  psl_status st = engine_run(sl.eng, &S);
   if (st != PSL_OK) {
     for (Ticket* t : live) fail_ticket(t, st, engine_error(sl.eng));
     return;
   }
+  finish_batch(sv, sl, live);
+}
+
+// after a batch's run: its reduced problems into their heap blocks, its
+// records to the host (lock not held)
+static void finish_batch(psl_server* sv, Slot& sl, std::vector<Ticket*>& live) {
   // reduced problems into their blocks, records to the host
   int64_t nseg = 0, chunks = 0, total_rec = 0;
   const void* rec0 = nullptr;
@@ -448,7 +479,6 @@ extern "C" psl_status psl_server_create(const psl_server_config* c, const psl_se
   if (e.empty() && (c->max_batch_lps < 1 || c->max_batch_rows < 1 || c->max_batch_cols < 1 ||
                     c->max_batch_nnz < 1 || c->max_batch_nnz >= ((int64_t)1 << 30)))
     e = "batch limits must be positive (nnz below 2^30)";
-  if (e.empty() && !c->threaded && c->slots != 1) e = "a server without threads has one slot";
   if (!e.empty()) {
     g_server_error = e;
     return PSL_ERR_INVALID;
@@ -538,21 +568,59 @@ extern "C" psl_status psl_server_submit(psl_server* sv, const psl_lp* lp, uint64
   return PSL_OK;
 }
 
+// the batch on a stepped slot ended, or failed with st (lock not held)
+static void retire(psl_server* sv, Slot& sl, psl_status st) {
+  if (st != PSL_OK) {
+    for (Ticket* t : sl.live) fail_ticket(t, st, engine_error(sl.eng));
+  } else if (!sl.live.empty()) {
+    finish_batch(sv, sl, sl.live);
+  }
+  std::lock_guard<std::mutex> lk(sv->mu);
+  --sv->running;
+  publish(sv, sl, sl.batch);
+  sl.busy = false;
+  sl.batch.clear();
+  sl.live.clear();
+}
+
 extern "C" psl_status psl_server_step(psl_server* sv, int32_t* n_run) {
   if (!sv || !n_run) return PSL_ERR_INVALID;
   if (sv->cfg.threaded) return sfail(sv, PSL_ERR_STATE, "the server runs its own worker threads");
-  Slot& sl = *sv->slots[0];
-  std::vector<Ticket*> b;
-  {
-    std::lock_guard<std::mutex> lk(sv->mu);
-    b = take_batch(sv);
-    ++sv->running;
+  (void)hipSetDevice(sv->s.device);
+  // admit: every free slot takes the next batch from the queue head
+  for (auto& slp : sv->slots) {
+    Slot& sl = *slp;
+    if (sl.busy) continue;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sl.batch = take_batch(sv);
+      if (sl.batch.empty()) break;  // nothing waiting, or the head does not fit yet
+      ++sv->running;
+    }
+    sl.busy = true;
+    psl_status st = load_batch(sl, sl.batch, sl.live);
+    if (st == PSL_OK && !sl.live.empty()) st = engine_start(sl.eng);
+    if (st != PSL_OK || sl.live.empty()) retire(sv, sl, st);
   }
-  *n_run = (int32_t)b.size();
-  if (!b.empty()) run_batch(sv, sl, b);
-  std::lock_guard<std::mutex> lk(sv->mu);
-  --sv->running;
-  if (!b.empty()) publish(sv, sl, b);
+  // one unit (a round, a cycle's reduction pass or the compaction) of every
+  // resident batch: all launches first, so the slots' streams overlap
+  int32_t advanced = 0;
+  for (auto& slp : sv->slots) {
+    Slot& sl = *slp;
+    if (!sl.busy) continue;
+    advanced += (int32_t)sl.live.size();
+    psl_status st = engine_launch(sl.eng);
+    if (st != PSL_OK) retire(sv, sl, st);
+  }
+  // then the completions; a batch whose run ended is retired
+  for (auto& slp : sv->slots) {
+    Slot& sl = *slp;
+    if (!sl.busy) continue;
+    bool done = false;
+    psl_status st = engine_complete(sl.eng, &done);
+    if (st != PSL_OK || done) retire(sv, sl, st);
+  }
+  *n_run = advanced;
   return PSL_OK;
 }
 
@@ -685,13 +753,12 @@ extern "C" psl_status psl_server_drain(psl_server* sv) {
   if (!sv->cfg.threaded) {
     for (;;) {
       int32_t n = 0;
-      {
-        std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->queue.empty()) return PSL_OK;
-      }
       psl_status st = psl_server_step(sv, &n);
       if (st != PSL_OK) return st;
-      if (n == 0) return sfail(sv, PSL_ERR_CAPACITY, "the queue head does not fit the result heap");
+      if (n > 0) continue;
+      std::lock_guard<std::mutex> lk(sv->mu);
+      if (sv->queue.empty()) return PSL_OK;
+      return sfail(sv, PSL_ERR_CAPACITY, "the queue head does not fit the result heap");
     }
   }
   std::unique_lock<std::mutex> lk(sv->mu);

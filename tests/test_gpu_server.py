@@ -95,8 +95,10 @@ def test_server_manual_steps_and_invalid_member():
     ts = [sv.submit(lp) for lp in lps]
     with pytest.raises(psl.PslError):
         sv.info(ts[0])  # not done yet
-    n = sv.step()
-    assert n == len(lps)
+    steps = 0
+    while sv.step() > 0:  # one unit of the batch's run per step
+        steps += 1
+    assert steps >= 3  # round 0, at least one round, the compaction
     for i, (t, lp) in enumerate(zip(ts, lps)):
         info = sv.info(t)
         if i == 2:
@@ -104,6 +106,43 @@ def test_server_manual_steps_and_invalid_member():
             continue
         got, _ = got_of(sv, t)
         assert_same(got, O.presolve(lp), f"manual {i}")
+    assert sv.step() == 0
+    sv.close()
+
+
+def test_stepped_server_admits_between_rounds():
+    """A stepped server with three slots: LPs submitted while other batches
+    are between their rounds are admitted at the next step on a free slot and
+    run beside them; every ticket equals the oracle's presolve of its LP."""
+    lps = mix_lps()
+    sv = psl.Server(slots=3, threaded=0, **SMALL)
+    tickets, pending = [], list(range(len(lps)))
+    arrival = {}
+    rng = np.random.default_rng(4)
+    steps = 0
+    while True:
+        for _ in range(int(rng.integers(0, 3))):  # arrivals between steps
+            if pending:
+                i = pending.pop(0)
+                t = sv.submit(lps[i])
+                arrival[t] = time.perf_counter()
+                tickets.append((i, t))
+        n = sv.step()
+        steps += 1
+        assert steps < 10_000
+        if not pending and n == 0:
+            break
+    assert len(set(sv.poll())) == len(lps)
+    spans = []
+    for i, t in tickets:
+        got, info = got_of(sv, t)
+        assert_same(got, O.presolve(lps[i]), f"stepped ticket {i}")
+        start = arrival[t] + info["queue_ms"] * 1e-3
+        spans.append((info["slot"], start, arrival[t] + info["latency_ms"] * 1e-3))
+        sv.release(t)
+    assert len({sl for sl, _, _ in spans}) >= 2
+    # batches on different slots were resident at the same time
+    assert any(a[0] != b[0] and a[1] < b[2] and b[1] < a[2] for a in spans for b in spans)
     assert sv.step() == 0
     sv.close()
 
