@@ -103,6 +103,22 @@ def _member(i):
     return lpgen.batch_member(i)
 
 
+def _pool_warm(i):
+    from oracle import oracle as O  # noqa: F401 (loads the oracle in the worker)
+    return i
+
+
+def _member_generated(i):
+    _member(i)
+    return 0
+
+
+def _member_presolved(i):
+    from oracle import oracle as O
+    O.presolve(_member(i))
+    return 0
+
+
 def _serving_member(i):
     from paper_2609_16182_amd import lpgen
     return lpgen.serving_member(i)
@@ -281,9 +297,26 @@ def batch_leg(args, torch, psl):
         for lp in lps[:n_s]:
             O.presolve(lp)
         dt = time.perf_counter() - ts
-        cpu = {"value": round(n_s / dt, 1), "unit": "LPs/s", "cores": 1, "kind": "oracle",
+        one = {"value": round(n_s / dt, 1), "unit": "LPs/s", "cores": 1, "kind": "oracle",
                "sample": f"the first {n_s} LPs of the batch ({nnz_s} nnz, already generated), one after the "
                          f"other on one host core, {dt:.2f}s"}
+        # LP-parallel: a pool of processes over the first LPs, each task one
+        # LP generated then presolved; the generation alone is timed the same
+        # way and taken off
+        n_p = min(K, 1024)
+        with ProcessPoolExecutor(workers) as ex:
+            list(ex.map(_pool_warm, range(4 * workers), chunksize=1))  # workers started, oracle loaded
+            ts = time.perf_counter()
+            list(ex.map(_member_generated, range(n_p), chunksize=8))
+            t_gen = time.perf_counter() - ts
+            ts = time.perf_counter()
+            list(ex.map(_member_presolved, range(n_p), chunksize=8))
+            t_all = time.perf_counter() - ts
+        cpu = {"value": round(n_p / max(t_all - t_gen, 1e-9), 1), "unit": "LPs/s", "cores": workers,
+               "kind": "oracle",
+               "sample": f"the first {n_p} LPs of the batch, LP-parallel over {workers} processes (one task = "
+                         f"generate and presolve one LP, {t_all:.2f}s, less the same pool generating them, "
+                         f"{t_gen:.2f}s)", "one_core": one}
     return {
         "metric": "batched LPs/s", "lps": K, "nnz": total_nnz,
         "value": round(K / (batch_ms * 1e-3), 1), "unit": "LPs/s",
