@@ -199,6 +199,7 @@ struct psl_server {
   psl_server_config cfg{};
   psl_settings s{};
   std::mutex mu;
+  std::mutex step_mu;  // stepped server: one step at a time (the slots' state)
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Ticket>> tickets;
@@ -586,6 +587,7 @@ static void retire(psl_server* sv, Slot& sl, psl_status st) {
 extern "C" psl_status psl_server_step(psl_server* sv, int32_t* n_run) {
   if (!sv || !n_run) return PSL_ERR_INVALID;
   if (sv->cfg.threaded) return sfail(sv, PSL_ERR_STATE, "the server runs its own worker threads");
+  std::lock_guard<std::mutex> step_lock(sv->step_mu);
   (void)hipSetDevice(sv->s.device);
   // admit: every free slot takes the next batch from the queue head
   for (auto& slp : sv->slots) {
