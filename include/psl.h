@@ -550,7 +550,8 @@ psl_status psl_server_submit(psl_server *sv, const psl_lp *lp, uint64_t *ticket)
  * whose run ended are retired (their tickets done, reduced problems copied
  * to the result heap, records to the host). Nothing runs between steps.
  * *n_run = LPs resident during the step (0: the server is idle -- nothing
- * waiting, or the head does not fit yet). PSL_ERR_STATE if threaded. */
+ * waiting, or the head does not fit yet). Steps called from several threads
+ * run one after another. PSL_ERR_STATE if threaded. */
 psl_status psl_server_step(psl_server *sv, int32_t *n_run);
 
 /* Copy up to cap tickets completed since the last poll into tickets[], in
