@@ -409,7 +409,13 @@ __global__ void k_par_long_insert(Dev d, ParScratch P) {
 
 // rows of a key group other than its leader go to the verify list (a row
 // whose slot names another row as leader is in a group of two or more)
-__global__ void k_par_vlist(Dev d, ParScratch P) {
+// the rows to verify (not their group's leader) appended to P.vlist in any
+// order: one counter update per 1024 rows (every row of the 1% that are
+// non-leaders would otherwise leave most wavefronts updating one address)
+#define VLIST_BLOCK 1024
+__global__ void __launch_bounds__(VLIST_BLOCK) k_par_vlist(Dev d, ParScratch P) {
+  __shared__ int wcount[VLIST_BLOCK / PSL_WAVE];
+  __shared__ int gbase;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool pred = false;
   if (i < d.m) {
@@ -423,12 +429,20 @@ __global__ void k_par_vlist(Dev d, ParScratch P) {
     }
   }
   unsigned long long mask = __ballot(pred);
-  if (mask == 0) return;
-  int leader = __ffsll((long long)mask) - 1;
-  int base = 0;
-  if (lane_id() == leader) base = atomicAdd(&d.flags->vlist_count, (int)__popcll(mask));
-  base = __shfl(base, leader, PSL_WAVE);
-  if (pred) P.vlist[base + __popcll(mask & lanemask_lt())] = (int)i;
+  int w = threadIdx.x >> 6;
+  if (lane_id() == 0) wcount[w] = (int)__popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < VLIST_BLOCK / PSL_WAVE; ++k) {
+      int c = wcount[k];
+      wcount[k] = t;
+      t += c;
+    }
+    gbase = t ? atomicAdd(&d.flags->vlist_count, t) : 0;
+  }
+  __syncthreads();
+  if (pred) P.vlist[gbase + wcount[w] + __popcll(mask & lanemask_lt())] = (int)i;
 }
 
 // effective sides of row r mapped through lambda onto its leader's frame
@@ -672,7 +686,7 @@ void launch_par_hash(const Dev& d, const ParScratch& p, const SweepGrid& g, hipS
   if (total > 0) hipLaunchKernelGGL(k_par_hash, dim3(total), dim3(PSL_BLOCK), 0, s, d, p, g);
   if (d.nlong > 0)
     hipLaunchKernelGGL(k_par_long_insert, dim3((d.nlong + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);
-  if (d.m > 0) hipLaunchKernelGGL(k_par_vlist, dim3((d.m + PSL_BLOCK - 1) / PSL_BLOCK), dim3(PSL_BLOCK), 0, s, d, p);
+  if (d.m > 0) hipLaunchKernelGGL(k_par_vlist, dim3((d.m + VLIST_BLOCK - 1) / VLIST_BLOCK), dim3(VLIST_BLOCK), 0, s, d, p);
 }
 
 void launch_par_drop(const Dev& d, const ParScratch& p, hipStream_t s) {

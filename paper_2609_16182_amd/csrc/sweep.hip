@@ -1086,11 +1086,15 @@ __device__ __forceinline__ int emit_col(const Dev& d, int j, int round, Record* 
 // the counts of the indices before it (ballots inside the wavefront, the
 // wavefronts' totals through LDS). The indices with records are compacted per
 // wavefront and dealt out to its lanes, each writing its index's records at
-// that position. Also counts the removed rows (a row tile's records are its
-// removed rows) and (batches) marks the LPs that changed.
+// that position. Also sets the rows removed and (batches) marks the LPs that
+// changed.
 __global__ void __launch_bounds__(DEC_BLOCK) k_decide_emit(Dev d, const int32_t* tile_sum, const int32_t* tile_off,
                                                             int64_t row_tiles, int64_t base, int round) {
   int64_t tile = blockIdx.x;
+  // a row tile's records are its removed rows, so the rows removed are the
+  // records before the first column tile (the scanned tile sums)
+  if (tile == 0 && threadIdx.x == 0)
+    d.flags->rows_removed = row_tiles < (int64_t)gridDim.x ? tile_off[row_tiles] : d.flags->round_total;
   int tsum = tile_sum[tile];
   if (tsum == 0) return;  // a tile without records
   __shared__ int list[DEC_TILE], lpos[DEC_TILE];
@@ -1151,10 +1155,7 @@ __global__ void __launch_bounds__(DEC_BLOCK) k_decide_emit(Dev d, const int32_t*
     }
     if (d.K > 1) d.lpo[lp].total = 1;  // the LP changed this round
   }
-  if (rows) {
-    if (threadIdx.x == 0) atomicAdd(&d.flags->rows_removed, tsum);
-    return;
-  }
+  if (rows) return;
   // columns whose bound became finite: one atomic per workgroup
   int fpre, ftot_w;
   wave_small_scan(fin, fpre, ftot_w);
