@@ -147,6 +147,31 @@ def test_stepped_server_admits_between_rounds():
     sv.close()
 
 
+def test_stepped_server_drain_and_invalid_members():
+    """drain() steps a stepped server with two slots until every ticket is
+    done; an invalid LP fails its own ticket only, in whichever batch it
+    lands."""
+    lps = [lpgen.batch_member(30 + i, m=200 + 40 * i) for i in range(9)]
+    bad = dict(lpgen.tiny(5))
+    bad["val"] = np.array(bad["val"], np.float64).copy()
+    bad["val"][0] = 0.0  # a stored zero coefficient is rejected
+    lps.insert(4, bad)
+    sv = psl.Server(slots=2, threaded=0, **{**SMALL, "max_batch_lps": 3})
+    ts = [sv.submit(lp) for lp in lps]
+    sv.drain()
+    assert len(set(sv.poll())) == len(lps)
+    for i, (t, lp) in enumerate(zip(ts, lps)):
+        info = sv.info(t)
+        if i == 4:
+            assert info["status"] == psl.PSL_ERR_INVALID
+            continue
+        assert info["batch_lps"] <= 3
+        got, _ = got_of(sv, t)
+        assert_same(got, O.presolve(lp), f"drained {i}")
+    assert sv.step() == 0
+    sv.close()
+
+
 def test_server_admission_waits_for_memory():
     lps = [lpgen.batch_member(20 + i, m=4000) for i in range(8)]
     foot = max(psl.reduced_footprint(lp["m"], lp["n"], lpgen.nnz(lp)) for lp in lps)
