@@ -477,13 +477,6 @@ static psl_status read_flags(psl_presolver* p) {
   return PSL_OK;
 }
 
-// flags of a round, with the number of rows it removed
-static psl_status read_round(psl_presolver* p, int32_t* rows_removed) {
-  psl_status e = read_flags(p);
-  if (e != PSL_OK) return e;
-  *rows_removed = p->hflags->rows_removed;
-  return PSL_OK;
-}
 
 // workgroups per bin from the current bin offsets and chunk count
 static void set_grid(psl_presolver* p) {
