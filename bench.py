@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--serve-rates", default="50,200,1000,2000")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--serve-slots", type=int, default=4, help="batch engines of the continuous-batching server")
+    ap.add_argument("--serve-fifo-max-rate", type=float, default=float("inf"),
+                    help="skip the one-LP-per-launch server above this rate (its queue only grows there)")
     ap.add_argument("--only-serving", action="store_true", help="run the serving workload only")
     return ap.parse_args()
 
@@ -199,6 +201,9 @@ def serving_leg(args, torch, psl):
         for t in sv.poll():
             sv.release(t)
         for i, rate in enumerate(rates):
+            if kind != "batched" and rate > args.serve_fifo_max_rate:
+                out[kind].append({"rate": rate, "skipped": "above --serve-fifo-max-rate"})
+                continue
             r = _replay(psl, sv, pool, rate, args.serve_seconds, seed=100 + i)
             out[kind].append(r)
             print(f"[bench] serving {kind} rate {rate}: {r}", file=sys.stderr, flush=True)
