@@ -172,6 +172,36 @@ def test_stepped_server_drain_and_invalid_members():
     sv.close()
 
 
+def test_stepped_server_waits_for_memory():
+    """A stepped server whose result heap holds two reservations: the third LP
+    is not admitted while the first two results stay resident (drain reports
+    it), and is admitted at the next step once they are released."""
+    lps = [lpgen.batch_member(20 + i, m=4000) for i in range(3)]
+    foot = max(psl.reduced_footprint(lp["m"], lp["n"], lpgen.nnz(lp)) for lp in lps)
+    probe = psl.Server(slots=2, threaded=0, **SMALL)
+    arena = probe.memory()["arena_bytes"]
+    probe.close()
+    sv = psl.Server(slots=2, threaded=0, **{**SMALL, "hbm_budget_bytes": arena + int(2.5 * foot)})
+    ts = [sv.submit(lp) for lp in lps]
+    while sv.step() > 0:
+        pass
+    done = list(sv.poll())
+    assert sorted(done) == ts[:2]
+    for i in range(2):
+        got, _ = got_of(sv, ts[i])
+        assert_same(got, O.presolve(lps[i]), f"resident {i}")
+    with pytest.raises(psl.PslError) as e:
+        sv.drain()
+    assert e.value.status == psl.PSL_ERR_CAPACITY
+    sv.release(ts[0])
+    sv.release(ts[1])
+    sv.drain()
+    assert list(sv.poll()) == [ts[2]]
+    got, _ = got_of(sv, ts[2])
+    assert_same(got, O.presolve(lps[2]), "admitted after a release")
+    sv.close()
+
+
 def test_server_admission_waits_for_memory():
     lps = [lpgen.batch_member(20 + i, m=4000) for i in range(8)]
     foot = max(psl.reduced_footprint(lp["m"], lp["n"], lpgen.nnz(lp)) for lp in lps)
