@@ -672,7 +672,10 @@ class Batch:
 
 class Server:
     """Continuous-batching presolve server (psl_server_*). The arrays of a
-    submitted LP are kept alive here until its ticket is released."""
+    submitted LP are kept alive here until its ticket is released. With
+    threaded=0 nothing runs between calls of step(), each of which admits
+    waiting LPs into free slots and advances every resident batch by one
+    round (psl_server_step)."""
 
     def __init__(self, stream=None, **config):
         settings = {k: config.pop(k) for k in list(config) if k in {f for f, _ in psl_settings._fields_}}
